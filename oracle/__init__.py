@@ -1,0 +1,211 @@
+"""CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the device
+library: the C half (``oracle.c``) is compiled by gcc into ``liboracle.so``;
+the numpy half is written here from the definitions in the ConnectIt paper
+(arXiv 2008.03909).  Each function names the passage it follows.
+
+Pinning: every function here is checked by ``tests/test_oracle_pins.py``
+against closed forms, brute force, invariants and the paper's worked
+example, not against itself.  ``identify_frequent`` and the MLP reference
+are pinned by hand-computed fixtures and finite differences.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def build(verbose: bool = False) -> str:
+    src = os.path.join(_HERE, "oracle.c")
+    tmp = _SO + ".tmp"
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise RuntimeError(f"{_SO} is missing: run __graft_entry__.build() first")
+        lib = ctypes.CDLL(_SO)
+        i64 = ctypes.c_int64
+        lib.oracle_csr_build.argtypes = [i64, i64, _i32p, _i32p, ctypes.c_int, _i64p, _i32p]
+        lib.oracle_csr_build.restype = i64
+        lib.oracle_bfs_cc.argtypes = [i64, _i64p, _i32p, _i32p]
+        lib.oracle_bfs_cc.restype = i64
+        lib.oracle_uf_cc.argtypes = [i64, i64, _i32p, _i32p, _i32p]
+        lib.oracle_uf_cc.restype = i64
+        lib.oracle_closure_cc.argtypes = [i64, i64, _i32p, _i32p, _i32p]
+        lib.oracle_closure_cc.restype = i64
+        lib.oracle_uf_init.argtypes = [i64, _i32p]
+        lib.oracle_uf_insert.argtypes = [i64, _i32p, i64, _i32p, _i32p]
+        lib.oracle_uf_query.argtypes = [i64, _i32p, i64, _i32p, _i32p, _u8p]
+        lib.oracle_uf_labels.argtypes = [i64, _i32p, _i32p]
+        lib.oracle_uf_labels.restype = i64
+        lib.oracle_kout_sample.argtypes = [i64, _i64p, _i32p, ctypes.c_int32, ctypes.c_uint64, _i32p]
+        lib.oracle_kout_sample.restype = i64
+        lib.oracle_bfs_sample.argtypes = [i64, _i64p, _i32p, ctypes.c_int32, ctypes.c_uint64, _i32p]
+        lib.oracle_bfs_sample.restype = i64
+        _lib = lib
+    return _lib
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _p32(a):
+    return a.ctypes.data_as(_i32p)
+
+
+def _p64(a):
+    return a.ctypes.data_as(_i64p)
+
+
+# ---- adjacency ------------------------------------------------------------
+
+def csr_build(n: int, u, v, dedup: bool = True):
+    """CSR of the undirected pair list (Section 2, "Graph Notation and Formats").
+
+    Both orientations of every non-loop pair; rows ascending; with ``dedup``
+    one copy of each directed edge.  Returns (offsets int64[n+1], adj int32[m]).
+    """
+    u, v = _c(u, np.int32), _c(v, np.int32)
+    offsets = np.zeros(n + 1, np.int64)
+    adj = np.empty(max(2 * u.shape[0], 1), np.int32)
+    m = _load().oracle_csr_build(n, u.shape[0], _p32(u), _p32(v), int(dedup), _p64(offsets), _p32(adj))
+    return offsets, adj[:m].copy()
+
+
+# ---- connectivity labelling: label[v] = min id reachable from v -------------
+
+def bfs_cc(n: int, offsets, adj):
+    """Sequential BFS sweep over a CSR (Section 2 connectivity labelling)."""
+    offsets, adj = _c(offsets, np.int64), _c(adj, np.int32)
+    lab = np.empty(n, np.int32)
+    c = _load().oracle_bfs_cc(n, _p64(offsets), _p32(adj) if adj.size else _p32(np.zeros(1, np.int32)), _p32(lab))
+    return lab, int(c)
+
+
+def uf_cc(n: int, u, v):
+    """Sequential union-find over a pair list (larger root linked under smaller)."""
+    u, v = _c(u, np.int32), _c(v, np.int32)
+    lab = np.empty(n, np.int32)
+    c = _load().oracle_uf_cc(n, u.shape[0], _p32(u), _p32(v), _p32(lab))
+    return lab, int(c)
+
+
+def closure_cc(n: int, u, v):
+    """Warshall closure labelling for n <= 64."""
+    if n > 64:
+        raise ValueError("closure oracle is for n <= 64")
+    u, v = _c(u, np.int32), _c(v, np.int32)
+    lab = np.empty(max(n, 1), np.int32)
+    c = _load().oracle_closure_cc(n, u.shape[0], _p32(u), _p32(v), _p32(lab))
+    return lab[:n].copy(), int(c)
+
+
+def labels(g, method: str = "uf"):
+    """Canonical labels of an ``inputs.Graph`` via the chosen oracle."""
+    if method == "uf":
+        return uf_cc(g.n, g.u, g.v)
+    if method == "bfs":
+        off, adj = csr_build(g.n, g.u, g.v, dedup=False)
+        return bfs_cc(g.n, off, adj)
+    if method == "closure":
+        return closure_cc(g.n, g.u, g.v)
+    raise ValueError(method)
+
+
+# ---- batch-incremental connectivity (Appendix "ConnectIt: Streaming") ------
+
+class Incremental:
+    """Insert/IsConnected applied batch after batch in issue order."""
+
+    def __init__(self, n: int):
+        self.n = n
+        self.P = np.empty(n, np.int32)
+        _load().oracle_uf_init(n, _p32(self.P))
+
+    def insert(self, u, v):
+        u, v = _c(u, np.int32), _c(v, np.int32)
+        _load().oracle_uf_insert(self.n, _p32(self.P), u.shape[0], _p32(u), _p32(v))
+
+    def query(self, a, b):
+        a, b = _c(a, np.int32), _c(b, np.int32)
+        out = np.empty(max(a.shape[0], 1), np.uint8)
+        _load().oracle_uf_query(self.n, _p32(self.P), a.shape[0], _p32(a), _p32(b), out.ctypes.data_as(_u8p))
+        return out[: a.shape[0]].copy()
+
+    def labels(self):
+        lab = np.empty(self.n, np.int32)
+        c = _load().oracle_uf_labels(self.n, _p32(self.P), _p32(lab))
+        return lab, int(c)
+
+
+# ---- samplers with a deterministic partition -------------------------------
+
+def kout_sample(n: int, offsets, adj, k: int, seed: int):
+    """Partition produced by k-out sampling (first edge + k-1 seeded picks).
+
+    Section 3.2 "k-out Sampling" and the k-out sampling algorithm of the
+    appendix: union the picked edges, fully compress.  The result is the
+    connected components of the picked sub-graph, in canonical-min form."""
+    offsets, adj = _c(offsets, np.int64), _c(adj, np.int32)
+    lab = np.empty(n, np.int32)
+    c = _load().oracle_kout_sample(n, _p64(offsets), _p32(adj) if adj.size else _p32(np.zeros(1, np.int32)),
+                                   k, seed, _p32(lab))
+    return lab, int(c)
+
+
+def bfs_sample(n: int, offsets, adj, tries: int, seed: int):
+    """Partition produced by BFS sampling (Section 3.2 "Breadth-First Search
+    Sampling"): the first seeded source whose component holds more than 10%
+    of the vertices; that component relabelled to its minimum member."""
+    offsets, adj = _c(offsets, np.int64), _c(adj, np.int32)
+    lab = np.empty(n, np.int32)
+    t = _load().oracle_bfs_sample(n, _p64(offsets), _p32(adj) if adj.size else _p32(np.zeros(1, np.int32)),
+                                  tries, seed, _p32(lab))
+    return lab, int(t)
+
+
+def identify_frequent(labels_arr) -> int:
+    """Most frequent label (Algorithm 1, IdentifyFrequent); ties go to the
+    smallest label.  ``np.argmax`` returns the first maximum, i.e. the
+    smallest label among those with the highest count."""
+    lab = np.asarray(labels_arr)
+    if lab.size == 0:
+        return -1
+    counts = np.bincount(lab.astype(np.int64))
+    return int(np.argmax(counts))
+
+
+def partial_labelling_ok(sample_labels, true_labels) -> bool:
+    """Partial connectivity labelling (Section 2): equal sample labels imply
+    the same true component, i.e. every sample class sits inside one
+    component."""
+    s = np.asarray(sample_labels, np.int64)
+    t = np.asarray(true_labels, np.int64)
+    first = np.full(int(s.max()) + 1 if s.size else 1, -1, np.int64)
+    order = np.arange(s.shape[0])
+    # record, for each sample class, the true label of its first member
+    rev = order[::-1]
+    first[s[rev]] = t[rev]
+    return bool(np.all(first[s] == t))

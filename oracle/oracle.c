@@ -1,0 +1,246 @@
+/*
+ * CPU oracle for graph connectivity -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, sequential, obviously-correct C.  Only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg may load this library; the
+ * product path never does.  It shares no code with the device library.
+ *
+ * What it computes (ConnectIt, Dhulipala/Hong/Shun, arXiv 2008.03909):
+ *  - the connectivity labelling of Section 2 ("Graph Connectivity and
+ *    Related Problems"): labels equal iff connected.  The canonical form
+ *    used throughout is label[v] = the minimum vertex id reachable from v;
+ *  - two independent ways to reach it (BFS sweep; sequential union-find)
+ *    and a Warshall transitive closure for tiny graphs;
+ *  - adjacency (CSR) construction from an undirected pair list, as the
+ *    CSR format of Section 2 ("Graph Notation and Formats") describes it;
+ *  - the batch-incremental semantics of Section 3.4 / Appendix
+ *    "ConnectIt: Streaming": a query answered after batches B_1..B_t sees
+ *    the graph E_0 + B_1 + ... + B_t;
+ *  - the exact partitions produced by the two deterministic samplers
+ *    (k-out with the first edge plus k-1 seeded picks, Section 3.2 and the
+ *    k-out sampling algorithm of Appendix "Sampling Schemes"; BFS sampling
+ *    with up to c seeded sources and the 10% success rule), each reduced to
+ *    its definition: the connected components of the sampled sub-graph.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- splitmix64 in counter mode (Steele, Lea, Flood, OOPSLA 2014) -------
+ * Output i of the generator seeded with state s is fin(s + (i+1)*gamma).
+ * The method's random draws (k-out picks, BFS sources) are defined on this
+ * generator, so the oracle implements it from that definition. */
+static uint64_t sm_fin(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+static uint64_t sm_out(uint64_t state, uint64_t i) { return sm_fin(state + (i + 1) * 0x9E3779B97F4A7C15ULL); }
+
+/* ---- CSR construction ------------------------------------------------------
+ * Directed edge list = both orientations of every pair with u != v; rows
+ * sorted ascending; with dedup, repeated (u,v) keep one copy.  Returns m. */
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+int64_t oracle_csr_build(int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v, int dedup,
+                         int64_t* offsets, int32_t* adj) {
+  int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  for (int64_t i = 0; i < num_pairs; ++i) {
+    if (u[i] == v[i]) continue;
+    deg[u[i]]++;
+    deg[v[i]]++;
+  }
+  offsets[0] = 0;
+  for (int64_t x = 0; x < n; ++x) offsets[x + 1] = offsets[x] + deg[x];
+  int64_t* fill = deg; /* reuse as write cursor */
+  for (int64_t x = 0; x < n; ++x) fill[x] = offsets[x];
+  for (int64_t i = 0; i < num_pairs; ++i) {
+    if (u[i] == v[i]) continue;
+    adj[fill[u[i]]++] = v[i];
+    adj[fill[v[i]]++] = u[i];
+  }
+  for (int64_t x = 0; x < n; ++x)
+    qsort(adj + offsets[x], (size_t)(offsets[x + 1] - offsets[x]), sizeof(int32_t), cmp_i32);
+  if (dedup) {
+    int64_t w = 0;
+    for (int64_t x = 0; x < n; ++x) {
+      int64_t b = offsets[x], e = offsets[x + 1];
+      offsets[x] = w;
+      for (int64_t j = b; j < e; ++j)
+        if (j == b || adj[j] != adj[j - 1]) adj[w++] = adj[j];
+    }
+    offsets[n] = w;
+  }
+  free(deg);
+  return offsets[n];
+}
+
+/* ---- 1. BFS sweep ----------------------------------------------------------
+ * Start a BFS at v = 0, 1, ..., n-1 whenever v is still unlabelled; every
+ * vertex it reaches gets label v.  The first vertex of a component met by the
+ * sweep is its minimum, so the labels are canonical by construction.
+ * Returns the number of components. */
+int64_t oracle_bfs_cc(int64_t n, const int64_t* offsets, const int32_t* adj, int32_t* label) {
+  int32_t* queue = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  for (int64_t x = 0; x < n; ++x) label[x] = -1;
+  int64_t comps = 0;
+  for (int64_t s = 0; s < n; ++s) {
+    if (label[s] >= 0) continue;
+    ++comps;
+    int64_t head = 0, tail = 0;
+    label[s] = (int32_t)s;
+    queue[tail++] = (int32_t)s;
+    while (head < tail) {
+      int32_t x = queue[head++];
+      for (int64_t j = offsets[x]; j < offsets[x + 1]; ++j) {
+        int32_t y = adj[j];
+        if (label[y] < 0) {
+          label[y] = (int32_t)s;
+          queue[tail++] = y;
+        }
+      }
+    }
+  }
+  free(queue);
+  return comps;
+}
+
+/* ---- 2. sequential union-find ------------------------------------------
+ * Link the larger root under the smaller one; path halving in find.  Since
+ * every link points to a smaller id, each root is its tree's minimum. */
+static int32_t uf_find(int32_t* P, int32_t x) {
+  while (P[x] != x) {
+    P[x] = P[P[x]];
+    x = P[x];
+  }
+  return x;
+}
+static void uf_union(int32_t* P, int32_t a, int32_t b) {
+  int32_t ra = uf_find(P, a), rb = uf_find(P, b);
+  if (ra == rb) return;
+  if (ra < rb) P[rb] = ra;
+  else P[ra] = rb;
+}
+
+void oracle_uf_init(int64_t n, int32_t* P) {
+  for (int64_t x = 0; x < n; ++x) P[x] = (int32_t)x;
+}
+void oracle_uf_insert(int64_t n, int32_t* P, int64_t k, const int32_t* u, const int32_t* v) {
+  (void)n;
+  for (int64_t i = 0; i < k; ++i) uf_union(P, u[i], v[i]);
+}
+void oracle_uf_query(int64_t n, int32_t* P, int64_t q, const int32_t* a, const int32_t* b, uint8_t* out) {
+  (void)n;
+  for (int64_t i = 0; i < q; ++i) out[i] = (uint8_t)(uf_find(P, a[i]) == uf_find(P, b[i]));
+}
+int64_t oracle_uf_labels(int64_t n, int32_t* P, int32_t* label) {
+  int64_t comps = 0;
+  for (int64_t x = 0; x < n; ++x) {
+    label[x] = uf_find(P, (int32_t)x);
+    comps += label[x] == x;
+  }
+  return comps;
+}
+
+int64_t oracle_uf_cc(int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v, int32_t* label) {
+  int32_t* P = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  oracle_uf_init(n, P);
+  oracle_uf_insert(n, P, num_pairs, u, v);
+  int64_t comps = oracle_uf_labels(n, P, label);
+  free(P);
+  return comps;
+}
+
+/* ---- 3. Warshall transitive closure, n <= 64 ---------------------------
+ * R[i] = bitmask of vertices reachable from i (reflexive); label = lowest
+ * set bit.  Returns -1 if n > 64. */
+int64_t oracle_closure_cc(int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v, int32_t* label) {
+  if (n > 64) return -1;
+  uint64_t R[64];
+  for (int64_t i = 0; i < n; ++i) R[i] = 1ULL << i;
+  for (int64_t e = 0; e < num_pairs; ++e) {
+    R[u[e]] |= 1ULL << v[e];
+    R[v[e]] |= 1ULL << u[e];
+  }
+  for (int64_t k = 0; k < n; ++k)
+    for (int64_t i = 0; i < n; ++i)
+      if (R[i] >> k & 1ULL) R[i] |= R[k];
+  int64_t comps = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t lo = 0;
+    while (!(R[i] >> lo & 1ULL)) ++lo;
+    label[i] = lo;
+    comps += lo == i;
+  }
+  return comps;
+}
+
+/* ---- k-out sample partition --------------------------------------------
+ * The sampled sub-graph keeps, for every vertex v with deg(v) > 0, the edge
+ * to its first neighbour A[I[v]] and k-1 more edges A[I[v] + (r_j mod deg)],
+ * r_j = output (v*k + j) of splitmix64 seeded with key, j = 1..k-1,
+ * key = output 0x6b6f7574 of splitmix64 seeded with `seed`.  The sample's
+ * labelling is the connected components of that sub-graph (canonical min). */
+int64_t oracle_kout_sample(int64_t n, const int64_t* offsets, const int32_t* adj, int32_t k, uint64_t seed,
+                           int32_t* label) {
+  int32_t* P = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  oracle_uf_init(n, P);
+  const uint64_t key = sm_out(seed, 0x6b6f7574ULL);
+  for (int64_t x = 0; x < n; ++x) {
+    int64_t deg = offsets[x + 1] - offsets[x];
+    if (deg == 0) continue;
+    uf_union(P, (int32_t)x, adj[offsets[x]]);
+    for (int32_t j = 1; j < k; ++j) {
+      uint64_t r = sm_out(key, (uint64_t)x * (uint64_t)k + (uint64_t)j);
+      uf_union(P, (int32_t)x, adj[offsets[x] + (int64_t)(r % (uint64_t)deg)]);
+    }
+  }
+  int64_t comps = oracle_uf_labels(n, P, label);
+  free(P);
+  return comps;
+}
+
+/* ---- BFS sample partition ----------------------------------------------
+ * Try t = 0..tries-1: source s_t = output t of splitmix64 seeded with
+ * key = output 0x626673 of splitmix64 seeded with `seed`, reduced mod n.
+ * The BFS reaches exactly the component of s_t; if it holds more than n/10
+ * vertices (strictly: 10*size > n, in integers), the sample labels that component with its minimum
+ * member and every other vertex with itself, and the source index is
+ * returned.  If no try succeeds the labelling is the identity and -1 is
+ * returned. */
+int64_t oracle_bfs_sample(int64_t n, const int64_t* offsets, const int32_t* adj, int32_t tries, uint64_t seed,
+                          int32_t* label) {
+  const uint64_t key = sm_out(seed, 0x626673ULL);
+  int32_t* queue = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  uint8_t* seen = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  int64_t result = -1;
+  for (int64_t x = 0; x < n; ++x) label[x] = (int32_t)x;
+  for (int32_t t = 0; t < tries && n > 0; ++t) {
+    int32_t s = (int32_t)(sm_out(key, (uint64_t)t) % (uint64_t)n);
+    memset(seen, 0, (size_t)n);
+    int64_t head = 0, tail = 0;
+    int32_t mn = s;
+    seen[s] = 1;
+    queue[tail++] = s;
+    while (head < tail) {
+      int32_t x = queue[head++];
+      if (x < mn) mn = x;
+      for (int64_t j = offsets[x]; j < offsets[x + 1]; ++j)
+        if (!seen[adj[j]]) {
+          seen[adj[j]] = 1;
+          queue[tail++] = adj[j];
+        }
+    }
+    if (10 * tail > n) {
+      for (int64_t i = 0; i < tail; ++i) label[queue[i]] = mn;
+      result = t;
+      break;
+    }
+  }
+  free(queue);
+  free(seen);
+  return result;
+}

@@ -1,0 +1,319 @@
+"""Pins for the CPU oracle: closed forms, brute force, invariants, the paper's
+worked example and published counts -- never the oracle against a retyped
+copy of itself.  CPU only."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_03909_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _python_components(n, edges):
+    """Independent pure-Python DFS (small graphs only)."""
+    nbr = [[] for _ in range(n)]
+    for a, b in edges:
+        nbr[a].append(b)
+        nbr[b].append(a)
+    lab = [-1] * n
+    for s in range(n):
+        if lab[s] >= 0:
+            continue
+        stack = [s]
+        lab[s] = s
+        while stack:
+            x = stack.pop()
+            for y in nbr[x]:
+                if lab[y] < 0:
+                    lab[y] = s
+                    stack.append(y)
+    return np.array(lab, np.int32)
+
+
+def _all_three(g):
+    a, ca = oracle.labels(g, "uf")
+    b, cb = oracle.labels(g, "bfs")
+    assert np.array_equal(a, b) and ca == cb
+    return a, ca
+
+
+def _invariants(g, lab, comps):
+    idx = np.arange(g.n)
+    assert np.all(lab <= idx)                      # canonical labels are minima
+    assert np.all(lab[lab] == lab)                 # idempotent
+    assert comps == int(np.sum(lab == idx))        # count = number of roots
+    assert np.all(lab[g.u] == lab[g.v])            # every edge inside one class
+
+
+# ---- closed forms ------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 7, 1000])
+def test_empty_graph_is_n_singletons(n):
+    g = inputs.empty(n)
+    lab, c = _all_three(g)
+    assert c == n and np.array_equal(lab, np.arange(n))
+
+
+@pytest.mark.parametrize("n", [2, 3, 50, 4097])
+def test_path_any_order_is_one_component(n):
+    for g in (inputs.path(n), inputs.chain(n, seed=11),
+              inputs.path(n, np.arange(n)[::-1].copy())):
+        lab, c = _all_three(g)
+        assert c == 1 and np.all(lab == 0)
+        _invariants(g, lab, c)
+
+
+def test_disjoint_cliques_count_and_labels():
+    sizes = [1, 2, 3, 5, 8, 13]
+    g = inputs.disjoint_union([inputs.clique(s) for s in sizes])
+    lab, c = _all_three(g)
+    assert c == len(sizes)
+    starts = np.cumsum([0] + sizes[:-1])
+    expect = np.repeat(starts, sizes)
+    assert np.array_equal(lab, expect)
+
+
+@pytest.mark.parametrize("center", [0, 5, 99])
+def test_star_and_complete_graph(center):
+    g = inputs.star(100, center)
+    lab, c = _all_three(g)
+    assert c == 1 and np.all(lab == 0)
+    g = inputs.clique(40)
+    lab, c = _all_three(g)
+    assert c == 1 and np.all(lab == 0)
+
+
+def test_grid_percolation_extremes():
+    full = inputs.grid(3, 6, 1.0, seed=3)
+    assert full.num_pairs == 3 * 6 * 6 * 5
+    lab, c = _all_three(full)
+    assert c == 1
+    none = inputs.grid(3, 6, 0.0, seed=3)
+    lab, c = _all_three(none)
+    assert c == 6 ** 3 and np.array_equal(lab, np.arange(216))
+    full2 = inputs.grid(2, 9, 1.0, seed=1)
+    assert full2.num_pairs == 2 * 9 * 8
+    assert _all_three(full2)[1] == 1
+
+
+def test_disjoint_union_adds_component_counts():
+    parts = [inputs.er(300, 200, seed=s) for s in range(4)]
+    total = sum(oracle.labels(p)[1] for p in parts)
+    assert oracle.labels(inputs.disjoint_union(parts))[1] == total
+
+
+# ---- worked example from the paper ---------------------------------------------
+
+def _read_golden(name):
+    d = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, *vals = line.split()
+            d[k] = [int(x) for x in vals]
+    return d
+
+
+def test_rem_counterexample_graph_is_connected():
+    d = _read_golden("rem_counterexample.txt")
+    e = np.array(d["edges"], np.int32).reshape(-1, 2)
+    g = inputs.Graph(d["n"][0], e[:, 0], e[:, 1])
+    for method in ("uf", "bfs", "closure"):
+        lab, c = oracle.labels(g, method)
+        assert c == d["components"][0]
+        assert lab.tolist() == d["labels"]
+
+
+# ---- brute force ------------------------------------------------------------------
+
+# Number of connected labelled graphs on k vertices, OEIS A001187.
+CONNECTED_LABELLED = {1: 1, 2: 1, 3: 4, 4: 38, 5: 728, 6: 26704}
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_all_labelled_graphs_on_k_vertices(k):
+    """Every labelled graph on k vertices at once (disjoint union): the three
+    oracle algorithms agree and the number of connected ones is A001187(k)."""
+    g = inputs.all_graphs_on(k)
+    lab, c = _all_three(g)
+    _invariants(g, lab, c)
+    per = lab.reshape(-1, k) - (np.arange(g.n // k) * k)[:, None]
+    ncomp = (per == np.arange(k)[None, :]).sum(axis=1)
+    assert int(np.sum(ncomp == 1)) == CONNECTED_LABELLED[k]
+    # every sub-graph: labels equal the closure oracle on that sub-graph
+    if k <= 5:
+        iu, iv = np.triu_indices(k, k=1)
+        for gi in range(1 << iu.shape[0]):
+            sel = [(int(iu[b]), int(iv[b])) for b in range(iu.shape[0]) if gi >> b & 1]
+            su = np.array([a for a, _ in sel], np.int32)
+            sv = np.array([b for _, b in sel], np.int32)
+            cl, _ = oracle.closure_cc(k, su, sv)
+            assert np.array_equal(cl, per[gi])
+
+
+def test_random_small_graphs_match_closure_and_dfs():
+    rng = np.random.default_rng(5)
+    for trial in range(300):
+        n = int(rng.integers(1, 65))
+        m = int(rng.integers(0, 2 * n + 1))
+        u = rng.integers(0, n, m).astype(np.int32)
+        v = rng.integers(0, n, m).astype(np.int32)
+        g = inputs.Graph(n, u, v)
+        lab, c = _all_three(g)
+        cl, cc = oracle.closure_cc(n, u, v)
+        assert np.array_equal(lab, cl) and c == cc
+        assert np.array_equal(lab, _python_components(n, zip(u.tolist(), v.tolist())))
+
+
+def test_er_workload_invariants():
+    g = inputs.workload_er_2_16()
+    lab, c = _all_three(g)
+    _invariants(g, lab, c)
+    # average degree 16: one giant component; isolated vertices are rare
+    assert np.sum(lab == 0) > 0.99 * g.n
+
+
+# ---- CSR construction -------------------------------------------------------------
+
+@pytest.mark.parametrize("dedup", [False, True])
+def test_csr_build_matches_python(dedup):
+    rng = np.random.default_rng(7)
+    for trial in range(50):
+        n = int(rng.integers(1, 40))
+        m = int(rng.integers(0, 120))
+        u = rng.integers(0, n, m).astype(np.int32)
+        v = rng.integers(0, n, m).astype(np.int32)
+        off, adj = oracle.csr_build(n, u, v, dedup)
+        rows = [[] for _ in range(n)]
+        for a, b in zip(u.tolist(), v.tolist()):
+            if a != b:
+                rows[a].append(b)
+                rows[b].append(a)
+        rows = [sorted(set(r)) if dedup else sorted(r) for r in rows]
+        assert off[0] == 0 and off[-1] == adj.shape[0]
+        for x in range(n):
+            assert adj[off[x]:off[x + 1]].tolist() == rows[x]
+
+
+# ---- samplers ----------------------------------------------------------------------
+
+def test_kout_first_edge_only_closed_form():
+    """k = 1 keeps only v -> (smallest neighbour of v).  That functional graph
+    has only 2-cycles, so its component count is (#isolated vertices) +
+    (#mutual pairs u<v with min-nbr(u)=v and min-nbr(v)=u)."""
+    rng = np.random.default_rng(3)
+    for trial in range(30):
+        n = int(rng.integers(2, 300))
+        g = inputs.er(n, int(rng.integers(0, 3 * n)), seed=trial)
+        off, adj = oracle.csr_build(g.n, g.u, g.v, dedup=True)
+        lab, c = oracle.kout_sample(g.n, off, adj, 1, seed=9)
+        deg = np.diff(off)
+        first = np.where(deg > 0, adj[np.minimum(off[:-1], max(adj.shape[0] - 1, 0))] if adj.size else -1, -1)
+        iso = int(np.sum(deg == 0))
+        mutual = sum(1 for x in range(n) if first[x] > x and first[first[x]] == x)
+        assert c == iso + mutual
+
+
+def test_kout_sample_is_partial_labelling():
+    for seed in range(5):
+        g = inputs.er(2000, 1500, seed=seed)   # sparse: many components
+        off, adj = oracle.csr_build(g.n, g.u, g.v, dedup=True)
+        true, tc = oracle.labels(g)
+        for k in (1, 2, 3):
+            lab, c = oracle.kout_sample(g.n, off, adj, k, seed=seed)
+            assert oracle.partial_labelling_ok(lab, true)
+            assert c >= tc
+            assert np.all(lab <= np.arange(g.n)) and np.all(lab[lab] == lab)
+
+
+def test_kout_sample_star_and_clique_collapse():
+    for g in (inputs.star(500, 7), inputs.clique(30)):
+        off, adj = oracle.csr_build(g.n, g.u, g.v, dedup=True)
+        lab, c = oracle.kout_sample(g.n, off, adj, 2, seed=1)
+        assert c == 1 and np.all(lab == 0)
+
+
+def test_kout_dense_er_leaves_few_components():
+    """Holm et al. (k-out theorem, cited in Section 3.2): few inter-component
+    edges remain.  Loose statistical check on an average-degree-16 ER graph."""
+    g = inputs.workload_er_2_16()
+    off, adj = oracle.csr_build(g.n, g.u, g.v, dedup=False)
+    lab, c = oracle.kout_sample(g.n, off, adj, 2, seed=1)
+    L = oracle.identify_frequent(lab)
+    assert np.mean(lab == L) > 0.9
+
+
+def test_bfs_sample_finds_the_component_of_its_source():
+    g = inputs.disjoint_union([inputs.er(600, 3000, seed=1), inputs.er(400, 2000, seed=2)])
+    off, adj = oracle.csr_build(g.n, g.u, g.v, dedup=True)
+    true, _ = oracle.labels(g)
+    lab, t = oracle.bfs_sample(g.n, off, adj, 3, seed=4)
+    assert t == 0                                   # both halves exceed 10%
+    cls = lab != np.arange(g.n)
+    comp = true[cls][0]
+    # sampled class == one true component, labelled with its minimum
+    members = np.nonzero(true == comp)[0]
+    assert np.array_equal(np.nonzero(lab == members.min())[0], members)
+    assert oracle.partial_labelling_ok(lab, true)
+
+
+def test_bfs_sample_fails_on_tiny_components():
+    g = inputs.disjoint_union([inputs.clique(3) for _ in range(50)])    # each 2% of n
+    off, adj = oracle.csr_build(g.n, g.u, g.v, dedup=True)
+    lab, t = oracle.bfs_sample(g.n, off, adj, 3, seed=4)
+    assert t == -1 and np.array_equal(lab, np.arange(g.n))
+
+
+def test_bfs_sample_threshold_is_strict():
+    # component of exactly n/10 vertices never qualifies; n/10 + 1 does
+    for size, ok in ((10, False), (11, True)):
+        g = inputs.disjoint_union([inputs.path(size), inputs.empty(100 - size)])
+        off, adj = oracle.csr_build(g.n, g.u, g.v, dedup=True)
+        # every try hits either the path or an isolated vertex; try many seeds
+        hit = False
+        for seed in range(60):
+            lab, t = oracle.bfs_sample(g.n, off, adj, 1, seed=seed)
+            if t == 0:
+                hit = True
+                assert np.all(lab[:size] == 0)
+        assert hit == ok
+
+
+def test_identify_frequent_fixtures():
+    assert oracle.identify_frequent(np.array([3, 3, 1, 1, 2])) == 1       # tie -> smaller
+    assert oracle.identify_frequent(np.array([5])) == 5
+    assert oracle.identify_frequent(np.array([0, 1, 2, 3])) == 0
+    assert oracle.identify_frequent(np.array([9, 4, 9, 4, 9])) == 9
+
+
+# ---- batch-incremental semantics -------------------------------------------------
+
+def test_incremental_matches_closure_on_every_prefix():
+    rng = np.random.default_rng(11)
+    n = 48
+    inc = oracle.Incremental(n)
+    eu, ev = [], []
+    prev = None
+    for batch in range(20):
+        k = int(rng.integers(0, 6))
+        u = rng.integers(0, n, k).astype(np.int32)
+        v = rng.integers(0, n, k).astype(np.int32)
+        inc.insert(u, v)
+        eu += u.tolist()
+        ev += v.tolist()
+        a = rng.integers(0, n, 100).astype(np.int32)
+        b = rng.integers(0, n, 100).astype(np.int32)
+        got = inc.query(a, b)
+        cl, _ = oracle.closure_cc(n, np.array(eu, np.int32), np.array(ev, np.int32))
+        assert np.array_equal(got, (cl[a] == cl[b]).astype(np.uint8))
+        lab, _ = inc.labels()
+        assert np.array_equal(lab, cl)
+        if prev is not None:       # answers are monotone: once connected, always
+            assert np.all(cl[prev[0]] == cl[prev[1]])
+        prev = (a[got == 1], b[got == 1])
