@@ -1,0 +1,211 @@
+/*
+ * connectit_hip.h -- C ABI of the MI355X (gfx950) connectivity library.
+ *
+ * Implements the method of "ConnectIt: A Framework for Static and
+ * Incremental Parallel Graph Connectivity Algorithms" (Dhulipala, Hong,
+ * Shun; arXiv 2008.03909):
+ *   - static connectivity (Algorithm 1): init labels, a sampling step
+ *     (k-out / BFS / LDD, Section 3.2), IdentifyFrequent, and a finish step
+ *     that skips the most frequent sampled component (Section 3.3:
+ *     union-find variants, Shiloach-Vishkin, root-based Liu-Tarjan);
+ *   - batch-incremental connectivity (Section 3.4 and the appendix
+ *     "ConnectIt: Streaming"): Insert(u,v) and IsConnected(u,v) batches.
+ *
+ * Conventions for every call:
+ *   - Vertex ids are int32 in [0, n); n must be in [1, 2^31 - 1].
+ *   - Pointers named *_dev or documented as device pointers are device
+ *     memory owned by the caller (for example torch tensors); the library
+ *     never frees them.  Work is enqueued on `hip_stream` (a hipStream_t;
+ *     NULL = the null stream) and is asynchronous unless stated otherwise.
+ *   - Labels are canonical: labels_out[v] = the minimum vertex id of v's
+ *     connected component, so two runs (any variant) give identical arrays.
+ *   - Host-checkable problems (bad sizes, null pointers, an illegal variant,
+ *     a too-small workspace) return an error code at once and enqueue
+ *     nothing.  Problems only the device can see (an id outside [0, n),
+ *     an exceeded round cap) set a device error word; it is reported by the
+ *     next call that synchronises and by cc_ctx_sync_status().
+ *   - cc_last_error() returns a thread-local detail string for the last
+ *     failing call on that thread.
+ */
+#ifndef CONNECTIT_HIP_H
+#define CONNECTIT_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CC_OK = 0,
+  CC_EINVAL = -1,       /* bad argument or illegal variant combination */
+  CC_ENOMEM = -2,       /* workspace too small or device allocation failed */
+  CC_EDEVICE = -3,      /* HIP runtime error or device-detected bad input */
+  CC_ELIVELOCK = -4,    /* a round-based phase exceeded its round cap */
+  CC_EBUSY = -5,        /* serving loop: request refused by admission */
+  CC_EUNSUPPORTED = -6  /* option not built */
+} cc_status;
+
+/* Sampling methods, Section 3.2. */
+enum { CC_SAMPLE_NONE = 0, CC_SAMPLE_KOUT = 1, CC_SAMPLE_BFS = 2, CC_SAMPLE_LDD = 3 };
+/* k-out edge choice: hybrid = first edge + (k-1) uniform picks (the paper's
+ * default); afforest = first k edges; pure = k uniform picks. */
+enum { CC_KOUT_HYBRID = 0, CC_KOUT_AFFOREST = 1, CC_KOUT_PURE = 2 };
+/* Finish methods, Section 3.3. */
+enum { CC_FIN_UF_REM_CAS = 0, CC_FIN_UF_ASYNC = 1, CC_FIN_SV = 2, CC_FIN_LT = 3 };
+/* Find options (appendix "Find Algorithms"). */
+enum { CC_FIND_NAIVE = 0, CC_FIND_ATOMIC_SPLIT = 1, CC_FIND_ATOMIC_HALVE = 2, CC_FIND_COMPRESS = 3 };
+/* Splice options of Rem's algorithm (appendix "Splice Algorithms"). */
+enum { CC_SPLICE_SPLIT_ONE = 0, CC_SPLICE_HALVE_ONE = 1, CC_SPLICE_ATOMIC = 2 };
+/* Liu-Tarjan rule bits (appendix "Liu-Tarjan Algorithms").  Connect kind in
+ * the low two bits; the other bits add RootUp, FullShortcut (else one
+ * Shortcut step per round) and Alter.  Only the root-based (RootUp)
+ * combinations are accepted: CRSA, PRSA, PRS, CRFA, PRFA, PRF. */
+enum {
+  CC_LT_CONNECT = 0,
+  CC_LT_PARENT_CONNECT = 1,
+  CC_LT_ROOTUP = 4,
+  CC_LT_FULL_SHORTCUT = 8,
+  CC_LT_ALTER = 16
+};
+#define CC_LT_CRSA (CC_LT_CONNECT | CC_LT_ROOTUP | CC_LT_ALTER)
+#define CC_LT_PRSA (CC_LT_PARENT_CONNECT | CC_LT_ROOTUP | CC_LT_ALTER)
+#define CC_LT_PRS (CC_LT_PARENT_CONNECT | CC_LT_ROOTUP)
+#define CC_LT_CRFA (CC_LT_CONNECT | CC_LT_ROOTUP | CC_LT_FULL_SHORTCUT | CC_LT_ALTER)
+#define CC_LT_PRFA (CC_LT_PARENT_CONNECT | CC_LT_ROOTUP | CC_LT_FULL_SHORTCUT | CC_LT_ALTER)
+#define CC_LT_PRF (CC_LT_PARENT_CONNECT | CC_LT_ROOTUP | CC_LT_FULL_SHORTCUT)
+
+/* One sampling x finish combination (Algorithm 1's sample_opt/finish_opt).
+ *  - kout_k >= 1 edges per vertex (paper default 2);
+ *  - bfs_tries >= 1 BFS attempts (paper text: 3), success iff the reached
+ *    component holds more than n/10 vertices;
+ *  - ldd_beta in (0, 1) (paper default 0.2); ldd_permute must be 0 (the
+ *    paper's default ordering; vertex 0 wakes first);
+ *  - find/splice: for UF-Rem-CAS any splice with find in {NAIVE,
+ *    ATOMIC_SPLIT, ATOMIC_HALVE}; for UF-Async any find; FIND_COMPRESS with
+ *    Rem-CAS (which includes the SpliceAtomic + FindCompress combination of
+ *    the paper's counter-example) is rejected with CC_EINVAL;
+ *  - seed drives every random draw of the sampler (k-out picks, BFS
+ *    sources, LDD shifts); it changes speed, never labels. */
+typedef struct {
+  int32_t sample;
+  int32_t kout_k;
+  int32_t kout_mode;
+  int32_t bfs_tries;
+  float ldd_beta;
+  int32_t ldd_permute;
+  int32_t finish;
+  int32_t find;
+  int32_t splice;
+  uint32_t lt_rules;
+  uint64_t seed;
+} cc_variant;
+
+/* Per-call statistics of the last static run on a context (host copy). */
+typedef struct {
+  int64_t n, m;
+  int32_t lmax;              /* skipped sampled component, -1 if none */
+  int32_t sample_success;    /* BFS: index of the successful try, else -1; 1 for others */
+  int64_t lmax_size;         /* vertices carrying lmax after sampling */
+  int64_t candidates;        /* finish vertices (label != lmax and degree > 0) */
+  int64_t candidate_edges;   /* adjacency entries the finish visits */
+  int32_t sample_rounds;     /* BFS levels / LDD rounds (0 for k-out) */
+  int32_t finish_rounds;     /* SV / LT rounds (0 for union-find) */
+  int64_t num_components;
+} cc_stats;
+
+typedef struct cc_ctx cc_ctx;
+typedef struct cc_stream cc_stream;
+
+/* ---- context -------------------------------------------------------------
+ * A context binds a device and owns a few hundred bytes of device state
+ * (error word, statistics) allocated here.  Not thread-safe: use one context
+ * per host thread.  Returns CC_EDEVICE if the device cannot be used. */
+cc_status cc_ctx_create(int device, cc_ctx** out);
+void cc_ctx_destroy(cc_ctx* ctx);
+/* Synchronises the device and reports (then clears) the device error word. */
+cc_status cc_ctx_sync_status(cc_ctx* ctx);
+/* Copies the statistics of the last static call (synchronises its stream). */
+cc_status cc_last_stats(cc_ctx* ctx, cc_stats* out);
+/* When enabled, static calls record HIP events around each phase on the
+ * call's stream; cc_phase_times() synchronises and returns the accumulated
+ * milliseconds and launch counts per phase since the last reset.  Phase
+ * names are stable strings ("init", "sample", "compress_count", "frequent",
+ * "compact", "finish", "output", ...). */
+cc_status cc_ctx_set_timing(cc_ctx* ctx, int enable);
+int cc_phase_times(cc_ctx* ctx, int max_phases, const char** names, double* total_ms, int64_t* counts);
+void cc_phase_times_reset(cc_ctx* ctx);
+
+/* The paper's default: k-out (k = 2, hybrid) + UF-Rem-CAS + SplitAtomicOne
+ * + FindNaive, seed 0x5eed. */
+cc_status cc_default_variant(cc_variant* out);
+/* Validates a variant (same rules as the static calls). */
+cc_status cc_check_variant(const cc_variant* v);
+
+/* ---- static connectivity (Algorithm 1) ---------------------------------------
+ * Workspace bytes needed by cc_connectivity_csr for (n, m, variant). */
+cc_status cc_workspace_bytes(int64_t n, int64_t m, const cc_variant* v, size_t* bytes);
+
+/* labels_out[v] = min id of v's component, for the undirected graph given as
+ * a symmetric CSR: offsets (n+1 entries, int64 if offsets_are_64bit else
+ * int32; offsets[0] = 0, offsets[n] = m) and adj (m int32 ids).  The CSR
+ * must be symmetric (the skip of the frequent component relies on it);
+ * rows need not be sorted, but the k-out "first edge" is adj[offsets[v]].
+ * Self-loops and duplicates are allowed.  m must fit int32 offsets unless
+ * offsets_are_64bit.  workspace: device buffer of >= cc_workspace_bytes.
+ * num_components_dev (nullable): one int64 written on the device.
+ * Round-based variants (BFS, LDD, SV, LT) read a 4-byte flag per round and
+ * so synchronise hip_stream internally; k-out/none + union-find does not. */
+cc_status cc_connectivity_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                              const int32_t* adj, const cc_variant* v, void* workspace, size_t ws_bytes,
+                              int32_t* labels_out, int64_t* num_components_dev, void* hip_stream);
+
+/* Sampling step alone (for inspection/tests): writes the sampled partial
+ * labelling, each sampled class relabelled to its minimum member, and the
+ * frequent label chosen by IdentifyFrequent (or -1).  Same arguments as
+ * cc_connectivity_csr; synchronises hip_stream. */
+cc_status cc_sample_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                        const int32_t* adj, const cc_variant* v, void* workspace, size_t ws_bytes,
+                        int32_t* labels_out, int32_t* lmax_out_host, void* hip_stream);
+
+/* ---- ingest: undirected pair list -> symmetric CSR (Section 2 formats) -------
+ * Output: both orientations of every pair with u != v, rows sorted
+ * ascending, duplicates removed iff dedup != 0.  adj_out needs capacity
+ * 2*num_pairs; offsets_out gets n+1 entries (int64 if offsets_64bit).  The
+ * edge count m is written to *m_dev (device int64).  Ids outside [0, n) set
+ * the device error word and are dropped. */
+cc_status cc_csr_workspace_bytes(int64_t n, int64_t num_pairs, size_t* bytes);
+cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v, int dedup,
+                       void* workspace, size_t ws_bytes, void* offsets_out, int offsets_64bit, int32_t* adj_out,
+                       int64_t* m_dev, void* hip_stream);
+
+/* ---- batch-incremental connectivity (Section 3.4) -----------------------------
+ * A cc_stream owns an n x int32 parent array on the device (allocated by
+ * cc_stream_create, freed by cc_stream_destroy), starting from the empty
+ * graph.  Accepted finishes: UF-Async (any find) and UF-Rem-CAS (any
+ * splice, non-compress find).  On one cc_stream, a query batch reflects
+ * exactly the insert batches enqueued before it in stream order. */
+cc_status cc_stream_create(cc_ctx* ctx, int64_t n, const cc_variant* v, cc_stream** out);
+void cc_stream_destroy(cc_stream* s);
+/* Initialize(G): the static algorithm on a symmetric CSR, result kept as the
+ * stream's state.  workspace as for cc_connectivity_csr. */
+cc_status cc_stream_init_csr(cc_stream* s, int64_t m, const void* offsets, int offsets_are_64bit,
+                             const int32_t* adj, void* workspace, size_t ws_bytes, void* hip_stream);
+/* Insert(u[i], v[i]) for i < k (device arrays). */
+cc_status cc_insert_batch(cc_stream* s, int64_t k, const int32_t* u, const int32_t* v, void* hip_stream);
+/* out[i] = IsConnected(a[i], b[i]) as 0/1 bytes (device arrays). */
+cc_status cc_query_batch(cc_stream* s, int64_t q, const int32_t* a, const int32_t* b, uint8_t* out,
+                         void* hip_stream);
+/* Canonical labels of the current state (labels_out: n int32 device). */
+cc_status cc_stream_labels(cc_stream* s, int32_t* labels_out, int64_t* num_components_dev, void* hip_stream);
+/* Synchronises and reports (then clears) the stream's device error word. */
+cc_status cc_stream_sync_status(cc_stream* s);
+
+const char* cc_status_string(cc_status st);
+const char* cc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CONNECTIT_HIP_H */

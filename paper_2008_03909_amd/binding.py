@@ -1,0 +1,376 @@
+"""Thin Python binding of ``libconnectit_hip.so`` (C ABI: include/connectit_hip.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step runs in the library's kernels.  If the
+library is missing this module raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libconnectit_hip.so")
+
+CC_OK, CC_EINVAL, CC_ENOMEM, CC_EDEVICE, CC_ELIVELOCK, CC_EBUSY, CC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+SAMPLE_NONE, SAMPLE_KOUT, SAMPLE_BFS, SAMPLE_LDD = 0, 1, 2, 3
+KOUT_HYBRID, KOUT_AFFOREST, KOUT_PURE = 0, 1, 2
+FIN_UF_REM_CAS, FIN_UF_ASYNC, FIN_SV, FIN_LT = 0, 1, 2, 3
+FIND_NAIVE, FIND_ATOMIC_SPLIT, FIND_ATOMIC_HALVE, FIND_COMPRESS = 0, 1, 2, 3
+SPLICE_SPLIT_ONE, SPLICE_HALVE_ONE, SPLICE_ATOMIC = 0, 1, 2
+LT_CONNECT, LT_PARENT_CONNECT, LT_ROOTUP, LT_FULL_SHORTCUT, LT_ALTER = 0, 1, 4, 8, 16
+LT_CRSA = LT_CONNECT | LT_ROOTUP | LT_ALTER
+LT_PRSA = LT_PARENT_CONNECT | LT_ROOTUP | LT_ALTER
+LT_PRS = LT_PARENT_CONNECT | LT_ROOTUP
+LT_CRFA = LT_CONNECT | LT_ROOTUP | LT_FULL_SHORTCUT | LT_ALTER
+LT_PRFA = LT_PARENT_CONNECT | LT_ROOTUP | LT_FULL_SHORTCUT | LT_ALTER
+LT_PRF = LT_PARENT_CONNECT | LT_ROOTUP | LT_FULL_SHORTCUT
+LT_NAMES = {LT_CRSA: "CRSA", LT_PRSA: "PRSA", LT_PRS: "PRS", LT_CRFA: "CRFA", LT_PRFA: "PRFA", LT_PRF: "PRF"}
+
+
+class cc_variant(ctypes.Structure):
+    _fields_ = [
+        ("sample", ctypes.c_int32),
+        ("kout_k", ctypes.c_int32),
+        ("kout_mode", ctypes.c_int32),
+        ("bfs_tries", ctypes.c_int32),
+        ("ldd_beta", ctypes.c_float),
+        ("ldd_permute", ctypes.c_int32),
+        ("finish", ctypes.c_int32),
+        ("find", ctypes.c_int32),
+        ("splice", ctypes.c_int32),
+        ("lt_rules", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+    def copy(self, **kw) -> "cc_variant":
+        v = cc_variant()
+        ctypes.memmove(ctypes.byref(v), ctypes.byref(self), ctypes.sizeof(cc_variant))
+        for k, x in kw.items():
+            setattr(v, k, x)
+        return v
+
+    def name(self) -> str:
+        s = {0: "none", 1: "kout", 2: "bfs", 3: "ldd"}[self.sample]
+        if self.sample == SAMPLE_KOUT:
+            s += {0: "", 1: "-afforest", 2: "-pure"}[self.kout_mode] + f"(k={self.kout_k})"
+        if self.finish == FIN_UF_REM_CAS:
+            f = "rem-cas/" + ["split-one", "halve-one", "splice"][self.splice] + "/" + \
+                ["naive", "split", "halve"][self.find]
+        elif self.finish == FIN_UF_ASYNC:
+            f = "async/" + ["naive", "split", "halve", "compress"][self.find]
+        elif self.finish == FIN_SV:
+            f = "sv"
+        else:
+            f = "lt-" + LT_NAMES.get(self.lt_rules, str(self.lt_rules))
+        return f"{s}+{f}"
+
+    def __repr__(self):
+        return f"cc_variant({self.name()}, seed={self.seed})"
+
+
+class cc_stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("m", ctypes.c_int64),
+        ("lmax", ctypes.c_int32), ("sample_success", ctypes.c_int32),
+        ("lmax_size", ctypes.c_int64), ("candidates", ctypes.c_int64),
+        ("candidate_edges", ctypes.c_int64),
+        ("sample_rounds", ctypes.c_int32), ("finish_rounds", ctypes.c_int32),
+        ("num_components", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+
+
+def lib():
+    """The loaded library.  Raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError(f"{SO_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(SO_PATH)
+        sig = {
+            "cc_ctx_create": (_int, [_int, ctypes.POINTER(_vp)]),
+            "cc_ctx_destroy": (None, [_vp]),
+            "cc_ctx_sync_status": (_int, [_vp]),
+            "cc_last_stats": (_int, [_vp, ctypes.POINTER(cc_stats)]),
+            "cc_ctx_set_timing": (_int, [_vp, _int]),
+            "cc_phase_times": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
+            "cc_phase_times_reset": (None, [_vp]),
+            "cc_default_variant": (_int, [ctypes.POINTER(cc_variant)]),
+            "cc_check_variant": (_int, [ctypes.POINTER(cc_variant)]),
+            "cc_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_variant), ctypes.POINTER(ctypes.c_size_t)]),
+            "cc_connectivity_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
+                                           ctypes.c_size_t, _vp, _vp, _vp]),
+            "cc_sample_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
+                                     ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_int32), _vp]),
+            "cc_csr_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+            "cc_build_csr": (_int, [_vp, _i64, _i64, _vp, _vp, _int, _vp, ctypes.c_size_t, _vp, _int, _vp, _vp,
+                                    _vp]),
+            "cc_stream_create": (_int, [_vp, _i64, ctypes.POINTER(cc_variant), ctypes.POINTER(_vp)]),
+            "cc_stream_destroy": (None, [_vp]),
+            "cc_stream_init_csr": (_int, [_vp, _i64, _vp, _int, _vp, _vp, ctypes.c_size_t, _vp]),
+            "cc_insert_batch": (_int, [_vp, _i64, _vp, _vp, _vp]),
+            "cc_query_batch": (_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
+            "cc_stream_labels": (_int, [_vp, _vp, _vp, _vp]),
+            "cc_stream_sync_status": (_int, [_vp]),
+            "cc_status_string": (ctypes.c_char_p, [_int]),
+            "cc_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class CCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        L = lib()
+        msg = L.cc_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {L.cc_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str):
+    if status != CC_OK:
+        raise CCError(status, where)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(x, dtype, device):
+    if isinstance(x, torch.Tensor):
+        t = x.to(device=device, dtype=dtype)
+    else:
+        t = torch.as_tensor(x, dtype=dtype, device=device)
+    return t.contiguous()
+
+
+def default_variant(**kw) -> cc_variant:
+    v = cc_variant()
+    _check(lib().cc_default_variant(ctypes.byref(v)), "cc_default_variant")
+    for k, x in kw.items():
+        setattr(v, k, x)
+    return v
+
+
+def check_variant(v: cc_variant) -> int:
+    return lib().cc_check_variant(ctypes.byref(v))
+
+
+def workspace_bytes(n: int, m: int, v: cc_variant) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().cc_workspace_bytes(n, m, ctypes.byref(v), ctypes.byref(b)), "cc_workspace_bytes")
+    return int(b.value)
+
+
+class Context:
+    """Owns a cc_ctx (device scalars, timing events)."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.h = ctypes.c_void_p()
+        _check(lib().cc_ctx_create(device, ctypes.byref(self.h)), "cc_ctx_create")
+        self._ws = None
+
+    def close(self):
+        if self.h:
+            lib().cc_ctx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def torch_device(self):
+        return torch.device("cuda", self.device)
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        """A cached device byte buffer of at least nbytes."""
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.torch_device)
+        return self._ws
+
+    def sync_status(self):
+        _check(lib().cc_ctx_sync_status(self.h), "cc_ctx_sync_status")
+
+    def last_stats(self) -> dict:
+        s = cc_stats()
+        _check(lib().cc_last_stats(self.h, ctypes.byref(s)), "cc_last_stats")
+        return s.as_dict()
+
+    def set_timing(self, on: bool):
+        _check(lib().cc_ctx_set_timing(self.h, int(on)), "cc_ctx_set_timing")
+
+    def phase_times(self) -> dict:
+        k = lib().cc_phase_times(self.h, 0, None, None, None)
+        names = (ctypes.c_char_p * max(k, 1))()
+        ms = (ctypes.c_double * max(k, 1))()
+        cnt = (ctypes.c_int64 * max(k, 1))()
+        k = lib().cc_phase_times(self.h, k, names, ms, cnt)
+        return {names[i].decode(): (ms[i], cnt[i]) for i in range(k)}
+
+    def phase_times_reset(self):
+        lib().cc_phase_times_reset(self.h)
+
+
+class CSR:
+    """A device CSR: offsets (n+1, int32 or int64) and adj (m, int32)."""
+
+    def __init__(self, n: int, offsets: torch.Tensor, adj: torch.Tensor):
+        self.n = int(n)
+        self.offsets = offsets
+        self.adj = adj
+        self.m = int(adj.numel())
+
+    @property
+    def o64(self) -> int:
+        return int(self.offsets.dtype == torch.int64)
+
+
+def build_csr(ctx: Context, n: int, u, v, dedup: bool = True, offsets_64bit: bool | None = None,
+              stream=None) -> CSR:
+    """cc_build_csr: symmetric, row-sorted CSR of an undirected pair list."""
+    dev = ctx.torch_device
+    ut = _dev_tensor(u, torch.int32, dev)
+    vt = _dev_tensor(v, torch.int32, dev)
+    k = int(ut.numel())
+    if offsets_64bit is None:
+        offsets_64bit = 2 * k > 0x7FFFFFFF
+    wsb = ctypes.c_size_t()
+    _check(lib().cc_csr_workspace_bytes(n, k, ctypes.byref(wsb)), "cc_csr_workspace_bytes")
+    ws = torch.empty(max(int(wsb.value), 256), dtype=torch.uint8, device=dev)
+    offsets = torch.empty(n + 1, dtype=torch.int64 if offsets_64bit else torch.int32, device=dev)
+    adj = torch.empty(max(2 * k, 1), dtype=torch.int32, device=dev)
+    m_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib().cc_build_csr(ctx.h, n, k, _ptr(ut), _ptr(vt), int(dedup), _ptr(ws), ws.numel(), _ptr(offsets),
+                              int(offsets_64bit), _ptr(adj), _ptr(m_dev), _stream_handle(stream)),
+           "cc_build_csr")
+    m = int(m_dev.item())
+    del ws
+    return CSR(n, offsets, adj[:m])
+
+
+def connectivity_csr(ctx: Context, g: CSR, variant: cc_variant | None = None, labels: torch.Tensor | None = None,
+                     ncomp: torch.Tensor | None = None, stream=None):
+    """cc_connectivity_csr.  Returns (labels int32[n], num_components int64[1]) on the device."""
+    v = variant if variant is not None else default_variant()
+    dev = ctx.torch_device
+    if labels is None:
+        labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    if ncomp is None:
+        ncomp = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = ctx.workspace(workspace_bytes(g.n, g.m, v))
+    _check(lib().cc_connectivity_csr(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), ctypes.byref(v),
+                                     _ptr(ws), ws.numel(), _ptr(labels), _ptr(ncomp), _stream_handle(stream)),
+           "cc_connectivity_csr")
+    return labels, ncomp
+
+
+def sample_csr(ctx: Context, g: CSR, variant: cc_variant, stream=None):
+    """cc_sample_csr: the sampled partial labelling and the chosen frequent label."""
+    dev = ctx.torch_device
+    labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ws = ctx.workspace(workspace_bytes(g.n, g.m, variant))
+    lm = ctypes.c_int32(-2)
+    _check(lib().cc_sample_csr(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), ctypes.byref(variant),
+                               _ptr(ws), ws.numel(), _ptr(labels), ctypes.byref(lm), _stream_handle(stream)),
+           "cc_sample_csr")
+    return labels, int(lm.value)
+
+
+class Stream:
+    """cc_stream: device-resident batch-incremental connectivity state."""
+
+    def __init__(self, ctx: Context, n: int, variant: cc_variant | None = None):
+        self.ctx = ctx
+        self.n = n
+        self.h = ctypes.c_void_p()
+        vp = ctypes.byref(variant) if variant is not None else None
+        _check(lib().cc_stream_create(ctx.h, n, vp, ctypes.byref(self.h)), "cc_stream_create")
+
+    def close(self):
+        if self.h:
+            lib().cc_stream_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_csr(self, g: CSR, variant: cc_variant, stream=None):
+        ws = self.ctx.workspace(workspace_bytes(g.n, g.m, variant))
+        _check(lib().cc_stream_init_csr(self.h, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(ws), ws.numel(),
+                                        _stream_handle(stream)), "cc_stream_init_csr")
+
+    def insert(self, u: torch.Tensor, v: torch.Tensor, stream=None):
+        _check(lib().cc_insert_batch(self.h, int(u.numel()), _ptr(u), _ptr(v), _stream_handle(stream)),
+               "cc_insert_batch")
+
+    def query(self, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        if out is None:
+            out = torch.empty(int(a.numel()), dtype=torch.uint8, device=a.device)
+        _check(lib().cc_query_batch(self.h, int(a.numel()), _ptr(a), _ptr(b), _ptr(out), _stream_handle(stream)),
+               "cc_query_batch")
+        return out
+
+    def labels(self, stream=None):
+        dev = self.ctx.torch_device
+        lab = torch.empty(self.n, dtype=torch.int32, device=dev)
+        nc = torch.empty(1, dtype=torch.int64, device=dev)
+        _check(lib().cc_stream_labels(self.h, _ptr(lab), _ptr(nc), _stream_handle(stream)), "cc_stream_labels")
+        return lab, nc
+
+    def sync_status(self):
+        _check(lib().cc_stream_sync_status(self.h), "cc_stream_sync_status")
+
+
+# ---- the variant space ---------------------------------------------------------
+
+def all_finishes():
+    """The 20 finish methods: 9 Rem-CAS, 4 Async, SV, 6 root-based Liu-Tarjan."""
+    out = []
+    for sp in (SPLICE_SPLIT_ONE, SPLICE_HALVE_ONE, SPLICE_ATOMIC):
+        for fd in (FIND_NAIVE, FIND_ATOMIC_SPLIT, FIND_ATOMIC_HALVE):
+            out.append(dict(finish=FIN_UF_REM_CAS, splice=sp, find=fd))
+    for fd in (FIND_NAIVE, FIND_ATOMIC_SPLIT, FIND_ATOMIC_HALVE, FIND_COMPRESS):
+        out.append(dict(finish=FIN_UF_ASYNC, find=fd, splice=0))
+    out.append(dict(finish=FIN_SV, find=0, splice=0))
+    for r in (LT_CRSA, LT_PRSA, LT_PRS, LT_CRFA, LT_PRFA, LT_PRF):
+        out.append(dict(finish=FIN_LT, lt_rules=r, find=0, splice=0))
+    return out
+
+
+def all_variants(seed: int = 0x5EED):
+    """Every sampling x finish combination (4 x 20 = 80)."""
+    base = default_variant(seed=seed)
+    out = []
+    for s in (SAMPLE_NONE, SAMPLE_KOUT, SAMPLE_BFS, SAMPLE_LDD):
+        for f in all_finishes():
+            out.append(base.copy(sample=s, **f))
+    return out

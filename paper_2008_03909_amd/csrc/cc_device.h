@@ -1,0 +1,190 @@
+// Device-side building blocks for the connectivity kernels (gfx950, wave64).
+//
+// Parent arrays are int32 and are shared by every wave of a launch, so every
+// access that the algorithms treat as racy (the starred reads and CAS of the
+// union-find pseudocode in the ConnectIt appendix "Union Find Algorithms")
+// is an agent-scope atomic: relaxed loads compile to `global_load ... sc1`,
+// which cannot hit a stale line, and CAS / min are agent-scope RMWs.  The
+// invariant that every link points to a smaller id (P[x] <= x) keeps the
+// forest acyclic and makes each root its tree's minimum, which is what lets
+// the final labels be the canonical minimum-id labels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cc {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int32_t ld(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas(int32_t* p, int32_t expected, int32_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+}
+// writeMin; returns the previous value.
+__device__ __forceinline__ int32_t amin(int32_t* p, int32_t v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t aor(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long add64(long long* p, long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ldu(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- splitmix64 in counter mode (Steele, Lea, Flood, OOPSLA 2014) --------
+// Output i of the generator seeded with state s is fin(s + (i+1) * gamma).
+__host__ __device__ __forceinline__ uint64_t sm_fin(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ uint64_t sm_out(uint64_t state, uint64_t i) {
+  return sm_fin(state + (i + 1) * 0x9E3779B97F4A7C15ULL);
+}
+// Stream tags for the method's own random draws.
+constexpr uint64_t kTagKout = 0x6b6f7574ULL;  // "kout"
+constexpr uint64_t kTagBfs = 0x626673ULL;     // "bfs"
+constexpr uint64_t kTagLdd = 0x6c6464ULL;     // "ldd"
+
+// ---- find options (ConnectIt appendix, "Find Algorithms") ----------------
+enum FindKind { kFindNaive = 0, kFindSplit = 1, kFindHalve = 2, kFindCompress = 3 };
+enum SpliceKind { kSplitOne = 0, kHalveOne = 1, kSpliceAtomic = 2 };
+
+// FindNaive: follow parents to the root, no writes.
+__device__ __forceinline__ int32_t find_naive(int32_t* P, int32_t u) {
+  int32_t p = ld(P + u);
+  while (p != u) {
+    u = p;
+    p = ld(P + u);
+  }
+  return u;
+}
+
+// FindAtomicSplit: point each visited node at its grandparent, then step to
+// the old parent.  FindAtomicHalve: same CAS, then step to the node's
+// (possibly new) parent.  Both re-read v and w every iteration.
+template <int KIND>
+__device__ __forceinline__ int32_t find_split_halve(int32_t* P, int32_t u) {
+  while (true) {
+    int32_t v = ld(P + u);
+    int32_t w = ld(P + v);
+    if (v == w) return v;
+    cas(P + u, v, w);
+    u = (KIND == kFindSplit) ? v : ld(P + u);
+  }
+}
+
+// FindCompress: find the root, then point every node of the walked path
+// whose parent is still above the root directly at the root.
+__device__ __forceinline__ int32_t find_compress(int32_t* P, int32_t u) {
+  int32_t r = u;
+  int32_t p = ld(P + r);
+  if (p == r) return r;
+  while (p != r) {
+    r = p;
+    p = ld(P + r);
+  }
+  int32_t j = ld(P + u);
+  while (j > r) {
+    st(P + u, r);
+    u = j;
+    j = ld(P + u);
+  }
+  return r;
+}
+
+template <int FIND>
+__device__ __forceinline__ int32_t find(int32_t* P, int32_t u) {
+  if constexpr (FIND == kFindNaive) return find_naive(P, u);
+  else if constexpr (FIND == kFindCompress) return find_compress(P, u);
+  else return find_split_halve<FIND>(P, u);
+}
+
+// ---- UF-Async (Jayanti-Tarjan style; appendix "UF-Async") ----------------
+// Find both roots; CAS the larger root onto the smaller; retry on failure.
+template <int FIND>
+__device__ __forceinline__ void union_async(int32_t* P, int32_t u, int32_t v) {
+  while (true) {
+    int32_t pu = find<FIND>(P, u);
+    int32_t pv = find<FIND>(P, v);
+    if (pu == pv) return;
+    if (pu < pv) {
+      int32_t t = pu;
+      pu = pv;
+      pv = t;
+    }
+    if (ld(P + pu) == pu && cas(P + pu, pu, pv)) return;
+  }
+}
+
+// ---- UF-Rem-CAS (lock-free Rem; appendix "UF-Rem-CAS") --------------------
+// Walk both paths upward comparing parents; the side with the larger parent
+// moves.  If it is a root, CAS-hook it under the other side's parent;
+// otherwise take one splice step (SplitAtomicOne, HalveAtomicOne or
+// SpliceAtomic).  After a successful hook the non-naive compress options
+// re-run their find on both endpoints.  Returns true if this call linked.
+template <int SPLICE, int FIND>
+__device__ __forceinline__ bool union_rem(int32_t* P, int32_t u, int32_t v) {
+  int32_t ru = u, rv = v;
+  while (true) {
+    int32_t pu = ld(P + ru);
+    int32_t pv = ld(P + rv);
+    if (pu == pv) return false;
+    if (pu < pv) {
+      int32_t t = ru;
+      ru = rv;
+      rv = t;
+      t = pu;
+      pu = pv;
+      pv = t;
+    }
+    // now P[ru] = pu > pv = P[rv]
+    if (pu == ru) {
+      if (cas(P + ru, ru, pv)) {
+        if constexpr (FIND != kFindNaive) {
+          find<FIND>(P, u);
+          find<FIND>(P, v);
+        }
+        return true;
+      }
+      continue;  // lost the race: re-read both parents
+    }
+    if constexpr (SPLICE == kSpliceAtomic) {
+      // Splice: re-parent ru under rv's parent (smaller than ru's parent).
+      cas(P + ru, pu, pv);
+      ru = pu;
+    } else {
+      // One path-split / path-halve step at ru.
+      int32_t w = ld(P + pu);
+      if (pu != w) cas(P + ru, pu, w);
+      ru = (SPLICE == kSplitOne) ? pu : w;
+    }
+  }
+}
+
+// Union dispatch.  ALG 0 = Rem-CAS (SPLICE, FIND), 1 = Async (FIND).
+template <int ALG, int SPLICE, int FIND>
+__device__ __forceinline__ void unite(int32_t* P, int32_t u, int32_t v) {
+  if constexpr (ALG == 0) union_rem<SPLICE, FIND>(P, u, v);
+  else union_async<FIND>(P, u, v);
+}
+
+// ---- wave helpers -----------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+}  // namespace cc

@@ -1,0 +1,108 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "connectit_hip.h"
+
+namespace cc {
+
+// Device-resident per-context scalars.  Kernels update these; the host reads
+// them back only where a round loop needs a decision or on request.
+struct DevScalars {
+  uint32_t error;          // bit 0: id out of range; bit 1: round cap; bit 2: bad CSR
+  uint32_t changed;        // round-based finishes: set when a round changed a parent
+  unsigned long long lmax_key;  // (count << 32) | ~label, max-reduced by IdentifyFrequent
+  int32_t lmax;            // resolved frequent label (-1: none)
+  int32_t bfs_min;         // minimum vertex reached by the current BFS
+  int32_t bin_count[4];    // candidate bins: thread / wave / block / (unused)
+  long long cand_edges;    // adjacency entries owned by candidates
+  long long num_components;
+  long long lmax_size;
+  uint32_t qcount[2];      // frontier queue lengths (ping-pong)
+  long long frontier_edges;    // degree sum of the next frontier
+  long long reached;       // vertices reached by the current BFS
+  uint32_t flag2;          // spare flag for sub-rounds (full shortcut)
+  uint32_t pad[15];
+};
+
+enum : uint32_t { kErrBadId = 1u, kErrRoundCap = 2u, kErrBadCsr = 4u };
+
+struct PhaseRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+}  // namespace cc
+
+struct cc_ctx {
+  int device = 0;
+  cc::DevScalars* dev = nullptr;     // device copy
+  cc::DevScalars* host = nullptr;    // pinned host mirror
+  cc_stats last{};
+  // phase timing
+  int timing = 0;
+  std::vector<cc::PhaseRec> pending;        // events of calls not yet harvested
+  std::vector<hipEvent_t> event_pool;
+  std::vector<std::string> phase_names;
+  std::vector<double> phase_ms;
+  std::vector<int64_t> phase_cnt;
+};
+
+namespace cc {
+
+// thread-local error message
+void set_error(const char* fmt, ...);
+cc_status fail(cc_status st, const char* fmt, ...);
+
+#define CC_HIP(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess)                                                                \
+      return ::cc::fail(CC_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), \
+                        __FILE__, __LINE__);                                             \
+  } while (0)
+
+#define CC_LAUNCH_CHECK()                                                                          \
+  do {                                                                                             \
+    hipError_t _e = hipGetLastError();                                                             \
+    if (_e != hipSuccess)                                                                          \
+      return ::cc::fail(CC_EDEVICE, "kernel launch failed: %s (%s:%d)", hipGetErrorString(_e), __FILE__, \
+                        __LINE__);                                                                 \
+  } while (0)
+
+// Phase timing: records an event pair around a phase when ctx->timing is on.
+struct PhaseScope {
+  cc_ctx* ctx;
+  hipStream_t s;
+  const char* name;
+  hipEvent_t a = nullptr;
+  PhaseScope(cc_ctx* c, hipStream_t st, const char* nm);
+  ~PhaseScope();
+};
+
+inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline unsigned grid_for(int64_t work, int block, int64_t cap = (int64_t)1 << 20) {
+  int64_t g = div_up(work > 0 ? work : 1, block);
+  return (unsigned)(g < cap ? g : cap);
+}
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace layout of a static call.
+struct WsLayout {
+  size_t count = 0;       // n int32: IdentifyFrequent counts / SV prev / LT snapshot
+  size_t cand = 0;        // n int32: thread-bin candidates
+  size_t big = 0;         // n int32: wave-bin (front) and block-bin (back) candidates
+  size_t bits = 0;        // 3 bitmaps of n bits (BFS / LDD)
+  size_t queue = 0;       // 2 * n int32 frontier queues
+  size_t edges = 0;       // LT with Alter: 2 * m int32 (edge list)
+  size_t hist = 0;        // LDD start-round histogram
+  size_t total = 0;
+};
+WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v);
+cc_status check_variant(const cc_variant* v, bool for_stream);
+
+}  // namespace cc

@@ -1,0 +1,244 @@
+// Round-based finishes: Shiloach-Vishkin and the root-based Liu-Tarjan
+// variants (ConnectIt Section 3.3 "Other Min-Based Algorithms", appendix
+// "Shiloach-Vishkin" and "Liu-Tarjan Algorithms").
+//
+// Both keep the parent array min-based (a parent only ever decreases, so
+// P[x] <= x holds throughout), work over the edges of the candidate vertices
+// (the most frequent sampled component is skipped), and stop after the first
+// round that changes nothing.
+#include "cc_frontier.h"
+#include "cc_static.h"
+
+namespace cc {
+
+constexpr int kRoundCap = 100000;
+
+// ---- Shiloach-Vishkin ------------------------------------------------------
+// Hook: for an edge (u, v) with labels l < h, if h was a root at the start of
+// the round, writeMin(P[h], l).  Then FullShortcut: every vertex points at its
+// root, and the snapshot of roots is refreshed.
+struct SvHook {
+  int32_t* P;
+  const int32_t* prev;
+  __device__ __forceinline__ bool operator()(int32_t u, int32_t v) const {
+    const int32_t pu = ld(P + u), pv = ld(P + v);
+    if (pu == pv) return false;
+    const int32_t l = pu < pv ? pu : pv;
+    const int32_t h = pu < pv ? pv : pu;
+    if (prev[h] != h) return false;
+    amin(P + h, l);
+    return true;
+  }
+};
+
+// Pointer-jumps every vertex to its root; optionally writes the snapshot and
+// raises `flag` when a parent changed.
+__global__ void k_full_shortcut(int64_t n, int32_t* P, int32_t* snap, uint32_t* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool any = false;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+    const int64_t v = base + threadIdx.x;
+    if (v < n) {
+      const int32_t p = ld(P + v);
+      int32_t r = p;
+      if (p != (int32_t)v) {
+        r = find_naive(P, p);
+        if (r != p) {
+          st(P + v, r);
+          any = true;
+        }
+      }
+      if (snap) snap[v] = r;
+    }
+  }
+  if (flag) wave_flag(any, flag);
+}
+
+// One shortcut step: P[v] <- P[P[v]].
+__global__ void k_shortcut_one(int64_t n, int32_t* P, uint32_t* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool any = false;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+    const int64_t v = base + threadIdx.x;
+    if (v < n) {
+      const int32_t p = ld(P + v);
+      const int32_t pp = ld(P + p);
+      if (pp != p) {
+        amin(P + v, pp);
+        any = true;
+      }
+    }
+  }
+  wave_flag(any, flag);
+}
+
+__global__ void k_copy_i32(int64_t n, const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+static cc_status read_flag(StaticArgs& a, uint32_t* out) {
+  CC_HIP(hipMemcpyAsync(&a.ctx->host->changed, &a.ctx->dev->changed, 4, hipMemcpyDeviceToHost, a.s));
+  CC_HIP(hipStreamSynchronize(a.s));
+  *out = a.ctx->host->changed;
+  return CC_OK;
+}
+
+template <typename I>
+cc_status finish_sv(StaticArgs& a) {
+  DevScalars* sc = a.ctx->dev;
+  int32_t* prev = a.count;  // frequency counts are no longer needed
+  const unsigned g = grid_for(a.n, kFBlock, 4096);
+  // labels are fully compressed after sampling, so prev = P is a root snapshot
+  hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, prev, (uint32_t*)nullptr);
+  for (int round = 0;; ++round) {
+    if (round >= kRoundCap) return fail(CC_ELIVELOCK, "Shiloach-Vishkin exceeded %d rounds", kRoundCap);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->changed, 0u);
+    visit_candidates(a.s, a.n, a.cand, a.big, sc, (const I*)a.off, a.adj, SvHook{a.P, prev}, &sc->changed);
+    hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, prev, (uint32_t*)nullptr);
+    CC_LAUNCH_CHECK();
+    ++a.finish_rounds;
+    uint32_t changed = 0;
+    cc_status st = read_flag(a, &changed);
+    if (st != CC_OK) return st;
+    if (!changed) break;
+  }
+  return CC_OK;
+}
+
+// ---- Liu-Tarjan (root-based) ------------------------------------------------
+// update(x, c): with RootUp, only if x was a root when the round started
+// (Q[x] == x); the parent becomes min(P[x], c).
+__device__ __forceinline__ bool lt_update(int32_t* P, const int32_t* Q, int32_t x, int32_t c) {
+  if (Q[x] != x) return false;
+  if (c >= ld(P + x)) return false;
+  return c < amin(P + x, c);
+}
+
+// Connect: the endpoints are each other's candidates.  ParentConnect: the
+// endpoints' parents (from the round-start snapshot) are each other's
+// candidates.
+template <bool PARENT>
+struct LtConnect {
+  int32_t* P;
+  const int32_t* Q;
+  __device__ __forceinline__ bool operator()(int32_t v, int32_t w) const {
+    if (PARENT) {
+      const int32_t pv = Q[v], pw = Q[w];
+      if (pv == pw) return false;
+      const bool x = lt_update(P, Q, pv, pw);
+      const bool y = lt_update(P, Q, pw, pv);
+      return x || y;
+    }
+    if (v == w) return false;
+    const bool x = lt_update(P, Q, v, w);
+    const bool y = lt_update(P, Q, w, v);
+    return x || y;
+  }
+};
+
+// Copies the candidates' edges into an explicit list (needed by Alter).
+struct EmitEdge {
+  int32_t* eu;
+  int32_t* ev;
+  unsigned long long* cnt;
+  __device__ __forceinline__ bool operator()(int32_t u, int32_t w) const {
+    wave_append_pair(u != w, u, w, eu, ev, cnt);
+    return false;
+  }
+};
+
+template <bool PARENT>
+__global__ void k_lt_connect_list(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                                  const unsigned long long* cnt, LtConnect<PARENT> op, uint32_t* flag) {
+  const int64_t c = (int64_t)*cnt;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool any = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c; i += stride) {
+    const int32_t a = eu[i];
+    if (a < 0) continue;
+    any |= op(a, ev[i]);
+  }
+  wave_flag(any, flag);
+}
+
+// Alter: replace every live edge (v, w) by (P[v], P[w]); a self-loop dies.
+__global__ void k_lt_alter(int32_t* eu, int32_t* ev, const unsigned long long* cnt, const int32_t* P,
+                           uint32_t* flag) {
+  const int64_t c = (int64_t)*cnt;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool any = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c; i += stride) {
+    const int32_t a = eu[i];
+    if (a < 0) continue;
+    const int32_t b = ev[i];
+    const int32_t pa = ld(P + a), pb = ld(P + b);
+    if (pa == pb) {
+      eu[i] = -1;
+    } else if (pa != a || pb != b) {
+      eu[i] = pa;
+      ev[i] = pb;
+      any = true;
+    }
+  }
+  wave_flag(any, flag);
+}
+
+template <typename I, bool PARENT>
+static cc_status lt_rounds(StaticArgs& a) {
+  DevScalars* sc = a.ctx->dev;
+  const uint32_t rules = a.v->lt_rules;
+  const bool full = rules & CC_LT_FULL_SHORTCUT;
+  const bool alter = rules & CC_LT_ALTER;
+  int32_t* Q = a.count;
+  int32_t* eu = nullptr;
+  int32_t* ev = nullptr;
+  unsigned long long* ecnt = (unsigned long long*)&sc->frontier_edges;
+  const unsigned g = grid_for(a.n, kFBlock, 4096);
+  if (alter) {
+    eu = (int32_t*)(a.ws + a.L.edges);
+    ev = (int32_t*)(a.ws + a.L.edges + align256((size_t)a.m * 4));
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, (uint32_t*)ecnt, 0u);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, (uint32_t*)ecnt + 1, 0u);
+    visit_candidates(a.s, a.n, a.cand, a.big, sc, (const I*)a.off, a.adj, EmitEdge{eu, ev, ecnt},
+                     (uint32_t*)nullptr);
+  }
+  for (int round = 0;; ++round) {
+    if (round >= kRoundCap) return fail(CC_ELIVELOCK, "Liu-Tarjan exceeded %d rounds", kRoundCap);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->changed, 0u);
+    hipLaunchKernelGGL(k_copy_i32, dim3(g), dim3(kFBlock), 0, a.s, a.n, (const int32_t*)a.P, Q);
+    LtConnect<PARENT> op{a.P, Q};
+    if (alter) {
+      hipLaunchKernelGGL(k_lt_connect_list<PARENT>, dim3(grid_for(a.m, kFBlock, 8192)), dim3(kFBlock), 0, a.s,
+                         (const int32_t*)eu, (const int32_t*)ev, (const unsigned long long*)ecnt, op, &sc->changed);
+    } else {
+      visit_candidates(a.s, a.n, a.cand, a.big, sc, (const I*)a.off, a.adj, op, &sc->changed);
+    }
+    if (full) hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, (int32_t*)nullptr,
+                                 &sc->changed);
+    else hipLaunchKernelGGL(k_shortcut_one, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, &sc->changed);
+    if (alter)
+      hipLaunchKernelGGL(k_lt_alter, dim3(grid_for(a.m, kFBlock, 8192)), dim3(kFBlock), 0, a.s, eu, ev,
+                         (const unsigned long long*)ecnt, (const int32_t*)a.P, &sc->changed);
+    CC_LAUNCH_CHECK();
+    ++a.finish_rounds;
+    uint32_t changed = 0;
+    cc_status st = read_flag(a, &changed);
+    if (st != CC_OK) return st;
+    if (!changed) break;
+  }
+  return CC_OK;
+}
+
+template <typename I>
+cc_status finish_lt(StaticArgs& a) {
+  if ((a.v->lt_rules & 3u) == CC_LT_PARENT_CONNECT) return lt_rounds<I, true>(a);
+  return lt_rounds<I, false>(a);
+}
+
+template cc_status finish_sv<int32_t>(StaticArgs&);
+template cc_status finish_sv<int64_t>(StaticArgs&);
+template cc_status finish_lt<int32_t>(StaticArgs&);
+template cc_status finish_lt<int64_t>(StaticArgs&);
+
+}  // namespace cc

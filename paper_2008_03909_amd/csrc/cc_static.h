@@ -1,0 +1,35 @@
+// Shared host-side state of one static connectivity call.
+#pragma once
+#include "cc_internal.h"
+
+namespace cc {
+
+struct StaticArgs {
+  cc_ctx* ctx = nullptr;
+  hipStream_t s = nullptr;
+  int64_t n = 0, m = 0;
+  const void* off = nullptr;
+  bool o64 = false;
+  const int32_t* adj = nullptr;
+  const cc_variant* v = nullptr;
+  WsLayout L;
+  char* ws = nullptr;
+  int32_t* P = nullptr;      // parent array == caller's labels_out
+  int32_t* count = nullptr;  // n int32 scratch (frequency counts, snapshots)
+  int32_t* cand = nullptr;   // thread-bin candidates (also LDD min-member scratch)
+  int32_t* big = nullptr;    // wave-bin (front) / block-bin (back) candidates
+  int64_t* ncomp_user = nullptr;
+  int32_t sample_success = 1;
+  int32_t sample_rounds = 0;
+  int32_t finish_rounds = 0;
+};
+
+template <typename I> cc_status sample_bfs(StaticArgs& a);
+template <typename I> cc_status sample_ldd(StaticArgs& a);
+template <typename I> cc_status finish_sv(StaticArgs& a);
+template <typename I> cc_status finish_lt(StaticArgs& a);
+
+// Synchronous read of the context's device scalars into ctx->host.
+cc_status pull_scalars(StaticArgs& a);
+
+}  // namespace cc

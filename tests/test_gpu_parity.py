@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Inputs come from the seeded generators; expected values come only from the
+oracle.  Labels are canonical minimum ids, so the bar is bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2008_03909_amd import binding as b
+from paper_2008_03909_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = b.Context(0)
+    yield c
+    c.close()
+
+
+def _csr(ctx, g, dedup=True, o64=False):
+    return b.build_csr(ctx, g.n, g.u, g.v, dedup=dedup, offsets_64bit=o64)
+
+
+def _labels(ctx, g, variant, dedup=True, o64=False):
+    d = _csr(ctx, g, dedup, o64)
+    lab, nc = b.connectivity_csr(ctx, d, variant)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    return lab.cpu().numpy(), int(nc.item())
+
+
+def _suite():
+    """Small graphs that span several tiles and ragged tails, plus the edge cases."""
+    gs = [
+        inputs.empty(1),
+        inputs.empty(777),
+        inputs.path(2),
+        inputs.path(1000, np.arange(1000)[::-1].copy()),          # long find paths
+        inputs.chain(5000, seed=3),
+        inputs.star(3000, center=2999),
+        inputs.clique(70),
+        inputs.disjoint_union([inputs.clique(s) for s in (1, 2, 3, 5, 8, 13, 21)]),
+        inputs.er(4096, 3000, seed=5),                             # many small components
+        inputs.er(10_000, 80_000, seed=6),                         # giant component
+        inputs.rmat(12, 8 << 12, 0.57, 0.19, 0.19, seed=7),
+        inputs.grid(3, 20, 0.35, seed=8),
+        inputs.grid(2, 64, 0.55, seed=9),
+        inputs.relabel(inputs.grid(2, 40, 1.0, seed=1), inputs.permutation(1600, 4)),
+    ]
+    # a hub whose row is far longer than a block, plus isolated vertices
+    hub = np.zeros(20000, np.int32)
+    leaves = np.arange(1, 20001, dtype=np.int32)
+    gs.append(inputs.Graph(25000, hub, leaves, "hub20000"))
+    # self-loops and duplicates
+    u = np.array([0, 0, 1, 1, 2, 3, 3, 5], np.int32)
+    v = np.array([0, 1, 0, 1, 2, 4, 4, 5], np.int32)
+    gs.append(inputs.Graph(7, u, v, "loops+dups"))
+    return gs
+
+
+SUITE = _suite()
+
+
+# ---- ingest -------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dedup", [True, False])
+@pytest.mark.parametrize("o64", [False, True])
+def test_build_csr_matches_oracle(ctx, dedup, o64):
+    for g in SUITE + [inputs.workload_er_2_16()]:
+        d = _csr(ctx, g, dedup, o64)
+        off, adj = oracle.csr_build(g.n, g.u, g.v, dedup)
+        assert d.offsets.dtype == (torch.int64 if o64 else torch.int32)
+        assert np.array_equal(d.offsets.cpu().numpy().astype(np.int64), off), g
+        assert np.array_equal(d.adj.cpu().numpy(), adj), g
+
+
+def test_build_csr_flags_out_of_range_ids(ctx):
+    g = inputs.Graph(10, np.array([1, 2, 12], np.int32), np.array([2, 3, 4], np.int32))
+    d = _csr(ctx, g)
+    torch.cuda.synchronize()
+    with pytest.raises(b.CCError):
+        ctx.sync_status()
+    off, adj = oracle.csr_build(10, np.array([1, 2], np.int32), np.array([2, 3], np.int32), True)
+    assert np.array_equal(d.adj.cpu().numpy(), adj)
+
+
+# ---- default variant and the full variant space ----------------------------------
+
+def test_default_variant_er_workload(ctx):
+    g = inputs.workload_er_2_16()
+    want, wc = oracle.labels(g)
+    got, gc = _labels(ctx, g, b.default_variant(), dedup=False)
+    assert gc == wc
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("vi", range(80))
+def test_every_variant_on_the_suite(ctx, vi):
+    v = b.all_variants()[vi]
+    for g in SUITE:
+        want, wc = oracle.labels(g)
+        got, gc = _labels(ctx, g, v)
+        assert gc == wc, (v, g)
+        assert np.array_equal(got, want), (v, g)
+
+
+def test_every_variant_on_all_graphs_with_six_vertices(ctx):
+    g = inputs.all_graphs_on(6)
+    want, wc = oracle.labels(g)
+    d = _csr(ctx, g)
+    for v in b.all_variants():
+        lab, nc = b.connectivity_csr(ctx, d, v)
+        assert int(nc.item()) == wc, v
+        assert np.array_equal(lab.cpu().numpy(), want), v
+
+
+def test_rem_counterexample_graph_every_variant(ctx):
+    e = np.array([[0, 2], [1, 3], [2, 5], [3, 4], [4, 5]], np.int32)
+    g = inputs.Graph(6, e[:, 0], e[:, 1])
+    for v in b.all_variants():
+        got, gc = _labels(ctx, g, v)
+        assert gc == 1 and got.tolist() == [0] * 6, v
+    bad = b.default_variant(splice=b.SPLICE_ATOMIC, find=b.FIND_COMPRESS)
+    with pytest.raises(b.CCError) as ei:
+        _labels(ctx, g, bad)
+    assert ei.value.status == b.CC_EINVAL
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_seeds_change_nothing(ctx, seed):
+    g = inputs.rmat(14, 8 << 14, 0.57, 0.19, 0.19, seed=11)
+    want, _ = oracle.labels(g)
+    for s in (b.SAMPLE_KOUT, b.SAMPLE_BFS, b.SAMPLE_LDD):
+        v = b.default_variant(sample=s, seed=seed * 7919)
+        got, _ = _labels(ctx, g, v)
+        assert np.array_equal(got, want)
+
+
+# ---- samplers ------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_kout_sample_matches_oracle_partition(ctx, k):
+    for g in SUITE:
+        d = _csr(ctx, g)
+        v = b.default_variant(kout_k=k, seed=1234)
+        lab, lmax = b.sample_csr(ctx, d, v)
+        off, adj = oracle.csr_build(g.n, g.u, g.v, True)
+        want, _ = oracle.kout_sample(g.n, off, adj, k, 1234)
+        assert np.array_equal(lab.cpu().numpy(), want), g
+        # IdentifyFrequent over vertices with an edge, ties to the smaller label
+        deg = np.diff(off)
+        if np.any(deg > 0):
+            assert lmax == oracle.identify_frequent(want[deg > 0]), g
+
+
+def test_bfs_sample_matches_oracle_partition(ctx):
+    for g in SUITE + [inputs.disjoint_union([inputs.clique(3) for _ in range(50)])]:
+        d = _csr(ctx, g)
+        v = b.default_variant(sample=b.SAMPLE_BFS, seed=99)
+        lab, lmax = b.sample_csr(ctx, d, v)
+        off, adj = oracle.csr_build(g.n, g.u, g.v, True)
+        want, t = oracle.bfs_sample(g.n, off, adj, 3, 99)
+        assert np.array_equal(lab.cpu().numpy(), want), g
+        assert ctx.last_stats()["sample_success"] == t
+
+
+def test_ldd_sample_is_a_partial_labelling_of_stars(ctx):
+    for g in SUITE:
+        d = _csr(ctx, g)
+        v = b.default_variant(sample=b.SAMPLE_LDD, seed=5)
+        lab, lmax = b.sample_csr(ctx, d, v)
+        lab = lab.cpu().numpy()
+        true, _ = oracle.labels(g)
+        idx = np.arange(g.n)
+        assert oracle.partial_labelling_ok(lab, true), g
+        assert np.all(lab <= idx) and np.all(lab[lab] == lab), g      # stars rooted at the minimum
+        # every cluster is connected inside itself: its induced sub-graph has one component
+        keep = lab[g.u] == lab[g.v]
+        sub, _ = oracle.uf_cc(g.n, g.u[keep], g.v[keep])
+        assert np.array_equal(sub, lab), g
+
+
+# ---- incremental -----------------------------------------------------------------------
+
+def _stream_variants():
+    vs = [b.default_variant(finish=b.FIN_UF_ASYNC, find=f) for f in range(4)]
+    vs += [b.default_variant(finish=b.FIN_UF_REM_CAS, splice=s, find=0) for s in range(3)]
+    return vs
+
+
+@pytest.mark.parametrize("vi", range(7))
+def test_incremental_matches_oracle_on_every_prefix(ctx, vi):
+    v = _stream_variants()[vi]
+    n = 5000
+    st = b.Stream(ctx, n, v)
+    inc = oracle.Incremental(n)
+    rng = np.random.default_rng(vi)
+    dev = ctx.torch_device
+    for batch in range(12):
+        k = int(rng.integers(0, 1500))
+        u = rng.integers(0, n, k).astype(np.int32)
+        w = rng.integers(0, n, k).astype(np.int32)
+        st.insert(torch.from_numpy(u).to(dev), torch.from_numpy(w).to(dev))
+        inc.insert(u, w)
+        q = int(rng.integers(1, 3000))
+        a = rng.integers(0, n, q).astype(np.int32)
+        c = rng.integers(0, n, q).astype(np.int32)
+        got = st.query(torch.from_numpy(a).to(dev), torch.from_numpy(c).to(dev)).cpu().numpy()
+        assert np.array_equal(got, inc.query(a, c)), (v, batch)
+    lab, nc = st.labels()
+    want, wc = inc.labels()
+    assert np.array_equal(lab.cpu().numpy(), want) and int(nc.item()) == wc
+    st.sync_status()
+    st.close()
+
+
+def test_incremental_initialize_from_a_graph(ctx):
+    g = inputs.er(20000, 15000, seed=3)
+    d = _csr(ctx, g)
+    v = b.default_variant(finish=b.FIN_UF_ASYNC)
+    st = b.Stream(ctx, g.n, v)
+    st.init_csr(d, v)
+    inc = oracle.Incremental(g.n)
+    inc.insert(g.u, g.v)
+    rng = np.random.default_rng(1)
+    dev = ctx.torch_device
+    u = rng.integers(0, g.n, 4000).astype(np.int32)
+    w = rng.integers(0, g.n, 4000).astype(np.int32)
+    st.insert(torch.from_numpy(u).to(dev), torch.from_numpy(w).to(dev))
+    inc.insert(u, w)
+    lab, _ = st.labels()
+    assert np.array_equal(lab.cpu().numpy(), inc.labels()[0])
+    st.close()
+
+
+def test_incremental_batch_split_and_order_invariance(ctx):
+    g = inputs.rmat(13, 4 << 13, 0.57, 0.19, 0.19, seed=3)
+    dev = ctx.torch_device
+    want, _ = oracle.labels(g)
+    for split_seed in range(3):
+        st = b.Stream(ctx, g.n)
+        su, sv = inputs.shuffle_pairs(g.u, g.v, split_seed)
+        cuts = np.sort(np.random.default_rng(split_seed).integers(0, su.shape[0], 5))
+        for part in np.split(np.arange(su.shape[0]), cuts):
+            st.insert(torch.from_numpy(su[part]).to(dev), torch.from_numpy(sv[part]).to(dev))
+        lab, _ = st.labels()
+        assert np.array_equal(lab.cpu().numpy(), want)
+        st.close()
+
+
+def test_incremental_rejects_bad_ids(ctx):
+    st = b.Stream(ctx, 10)
+    dev = ctx.torch_device
+    st.insert(torch.tensor([1, 11], dtype=torch.int32, device=dev), torch.tensor([2, 3], dtype=torch.int32, device=dev))
+    torch.cuda.synchronize()
+    with pytest.raises(b.CCError):
+        st.sync_status()
+    st.close()
