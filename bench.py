@@ -1,0 +1,436 @@
+"""Benchmark: static connectivity throughput on one MI355X, plus incremental
+updates/s with p50/p99 batch latency.
+
+Default workload: R-MAT, n = 2^24, 8n tuples with (a,b,c,d) =
+(0.57,0.19,0.19,0.05), seed 2, symmetrised and deduplicated on the device
+(int32 CSR).  A step is one static connectivity call (init, k-out sampling,
+IdentifyFrequent, compaction, finish, output) on the device-resident CSR with
+the default variant (k-out k=2 hybrid + UF-Rem-CAS + SplitAtomicOne +
+FindNaive).  edges/s = m / step time, m = directed edges after dedup.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    from paper_2008_03909_amd import inputs
+
+    if name == "rmat24":
+        return inputs.workload_rmat(24, 8, seed=2), (
+            "rmat n=2^24 edge_factor=8 (a,b,c,d)=(0.57,0.19,0.19,0.05) seed=2, symmetrized, deduplicated, int32 CSR")
+    if name == "er16":
+        return inputs.workload_er_2_16(), (
+            "erdos-renyi n=2^16 pairs=2^19 seed=1, symmetrized, duplicates kept, int32 CSR")
+    if name == "grid3d":
+        return inputs.workload_grid3d(256, 0.35, seed=3), (
+            "3d grid 256^3 bond percolation p=0.35 seed=3, symmetrized, int32 CSR")
+    if name == "rmat27":
+        return inputs.workload_rmat(27, 8, seed=4), (
+            "rmat n=2^27 edge_factor=8 (a,b,c,d)=(0.57,0.19,0.19,0.05) seed=4, symmetrized, deduplicated, "
+            "int64 offsets")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def phase_alg_bytes(phase: str, n: int, m: int, o: int, n_nz: int, st: dict, k: int = 2) -> float:
+    """Algorithmic bytes of one launch of a phase of the default variant.
+
+    n_nz = vertices with at least one edge; n_f / m_f = candidate vertices /
+    their adjacency entries; every random 4-byte access counts 4 bytes."""
+    n_f, m_f, comps = st["candidates"], st["candidate_edges"], st["num_components"]
+    if phase == "init":
+        return 8.0 * n                                   # P and count writes
+    if phase == "sample":
+        return o * n + 16.0 * k * n_nz                   # row bounds; k picks; k unions (2 reads + CAS)
+    if phase == "compress_count":
+        return (4.0 + o) * n + 8.0 * n_nz                # P, degree; root read + count update
+    if phase == "frequent":
+        return 4.0 * n
+    if phase == "compact":
+        return (4.0 + o) * n + 4.0 * n_f
+    if phase == "finish":
+        return 2.0 * o * n_f + 12.0 * m_f                # row bounds; adjacency + 2 parent reads per edge
+    if phase == "output":
+        return 4.0 * n + 8.0 * (n - comps)               # P read; root read + write for non-roots
+    return 0.0
+
+
+def read_traffic(kernel: str, workload_name: str):
+    """HBM bytes per dispatch measured by rocprofv3 --pmc, if a summary for
+    this kernel and workload exists and was taken from the current sources."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload_name}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            a, b = line.split("=", 1)
+            kv[a.strip()] = b.strip()
+    src = kv.get("source")
+    if src:
+        h = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+        if h != kv.get("source_sha256_16"):
+            return None
+    try:
+        return float(kv["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(g, m: int):
+    """The CPU oracle (sequential union-find over the pair list) on the same
+    workload, one host core, median of 3 runs."""
+    import oracle
+
+    if not os.path.exists(oracle._SO):
+        oracle.build()
+    ts = []
+    for _ in range(3):
+        t = time.perf_counter()
+        oracle.uf_cc(g.n, g.u, g.v)
+        ts.append(time.perf_counter() - t)
+    t = statistics.median(ts)
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"full workload ({g.num_pairs} pairs), sequential union-find oracle, median of 3 runs "
+                      f"({t:.2f} s each); host {cpu}, {os.cpu_count()} logical cpus"}
+
+
+def incremental(ctx, g, seed: int = 5, max_pairs: int | None = None):
+    """Insert the workload's pairs (shuffled) in batches of log-uniform size in
+    [1e3, 1e7] interleaved with query batches of log-uniform size in
+    [1e3, 1e6]; per-batch latency from HIP events on the issuing stream."""
+    import numpy as np
+    import torch
+
+    from paper_2008_03909_amd import binding as b
+    from paper_2008_03909_amd import inputs
+
+    dev = ctx.torch_device
+    su, sv = inputs.shuffle_pairs(g.u, g.v, seed)
+    if max_pairs:
+        su, sv = su[:max_pairs], sv[:max_pairs]
+    du = torch.from_numpy(su).to(dev)
+    dv = torch.from_numpy(sv).to(dev)
+    qa, qb = inputs.query_pairs(g.n, 1_000_000, seed=6)
+    dqa = torch.from_numpy(qa).to(dev)
+    dqb = torch.from_numpy(qb).to(dev)
+    qout = torch.empty(1_000_000, dtype=torch.uint8, device=dev)
+    rng = np.random.default_rng(seed)
+    v = b.default_variant(finish=b.FIN_UF_ASYNC, find=b.FIND_NAIVE)
+    st = b.Stream(ctx, g.n, v)
+    s = torch.cuda.current_stream()
+    recs = []
+    pos = 0
+    total = du.numel()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while pos < total:
+        if rng.random() < 0.5:
+            k = min(inputs.log_uniform_int(1e3, 1e7, rng.random()), total - pos)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            st.insert(du[pos:pos + k], dv[pos:pos + k])
+            e1.record(s)
+            recs.append(("insert", k, e0, e1))
+            pos += k
+        else:
+            q = inputs.log_uniform_int(1e3, 1e6, rng.random())
+            off = int(rng.integers(0, 1_000_000 - q + 1))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            st.query(dqa[off:off + q], dqb[off:off + q], out=qout[:q])
+            e1.record(s)
+            recs.append(("query", q, e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st.sync_status()
+    st.close()
+    ins = [(k, a.elapsed_time(bb)) for kind, k, a, bb in recs if kind == "insert"]
+    qs = [(k, a.elapsed_time(bb)) for kind, k, a, bb in recs if kind == "query"]
+    lat = sorted(ms for _, ms in ins + qs)
+
+    def pct(xs, p):
+        xs = sorted(xs)
+        return xs[min(len(xs) - 1, int(round(p / 100.0 * (len(xs) - 1))))] if xs else None
+
+    ins_ms = sum(ms for _, ms in ins)
+    q_ms = sum(ms for _, ms in qs)
+    return {
+        "updates_per_s": sum(k for k, _ in ins) / (ins_ms / 1e3) if ins_ms else None,
+        "queries_per_s": sum(k for k, _ in qs) / (q_ms / 1e3) if q_ms else None,
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+        "insert_p50_ms": pct([ms for _, ms in ins], 50), "insert_p99_ms": pct([ms for _, ms in ins], 99),
+        "query_p50_ms": pct([ms for _, ms in qs], 50), "query_p99_ms": pct([ms for _, ms in qs], 99),
+        "batches": len(recs), "inserted_pairs": sum(k for k, _ in ins), "queried_pairs": sum(k for k, _ in qs),
+        "wall_s": wall,
+        "finish": "uf-async/naive",
+        "note": "undirected pair inserts (duplicates and self-loops included as no-op inserts); latency is "
+                "device time per batch from HIP events; batches run back to back on one stream",
+    }
+
+
+def _time_ms(fn, reps: int = 10) -> float:
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def calibration(ctx, csr, n: int, m: int, o: int):
+    """Roofline anchors on the same device: a 1 GiB stream copy, and the
+    paper's MapEdges / GatherEdges primitives on the workload's CSR."""
+    import torch
+
+    from paper_2008_03909_amd import binding as b
+
+    dev = ctx.torch_device
+    nb = 1 << 30
+    src = torch.empty(nb, dtype=torch.uint8, device=dev)
+    dst = torch.empty(nb, dtype=torch.uint8, device=dev)
+    t_copy = _time_ms(lambda: b.calib_copy(src, dst))
+    del src, dst
+    vals = torch.arange(n, dtype=torch.int32, device=dev)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    t_map = _time_ms(lambda: b.calib_edges(csr, None, out))
+    t_gather = _time_ms(lambda: b.calib_edges(csr, vals, out))
+    map_bytes = (o + 4) * n + 4 * m
+    gather_bytes = (o + 4) * n + 8 * m
+    return {
+        "copy_gbs": round(2 * nb / (t_copy / 1e3) / 1e9, 1),
+        "map_edges_ms": round(t_map, 4), "map_edges_gbs": round(map_bytes / (t_map / 1e3) / 1e9, 1),
+        "gather_edges_ms": round(t_gather, 4), "gather_edges_gbs": round(gather_bytes / (t_gather / 1e3) / 1e9, 1),
+        "gather_edges_edges_per_s": m / (t_gather / 1e3),
+    }
+
+
+def sweep(ctx, csr, g, workload_name: str, reps: int = 5, check: bool = True):
+    """Time every sampling x finish variant (median of `reps` after one warm-up)
+    and check every labelling against the CPU oracle.  Extra rows vary the
+    k-out edge choice and k under the default finish."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2008_03909_amd import binding as b
+
+    want = None
+    if check:
+        if not os.path.exists(oracle._SO):
+            oracle.build()
+        want, _ = oracle.uf_cc(g.n, g.u, g.v)
+    vs = b.all_variants()
+    base = b.default_variant()
+    extra = [base.copy(kout_mode=b.KOUT_AFFOREST), base.copy(kout_mode=b.KOUT_PURE),
+             base.copy(kout_k=1), base.copy(kout_k=3), base.copy(kout_mode=b.KOUT_AFFOREST, kout_k=1)]
+    rows = []
+    dev = ctx.torch_device
+    labels = torch.empty(csr.n, dtype=torch.int32, device=dev)
+    ncomp = torch.empty(1, dtype=torch.int64, device=dev)
+    for i, v in enumerate(vs + extra):
+        b.connectivity_csr(ctx, csr, v, labels=labels, ncomp=ncomp)
+        torch.cuda.synchronize()
+        ok = True
+        if want is not None:
+            ok = bool(np.array_equal(labels.cpu().numpy(), want))
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.connectivity_csr(ctx, csr, v, labels=labels, ncomp=ncomp)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        st = ctx.last_stats()
+        ms = statistics.median(ts)
+        rows.append({"variant": v.name(), "index": i if i < len(vs) else None, "ms": round(ms, 4),
+                     "edges_per_s": csr.m / (ms / 1e3), "labels_match_oracle": ok,
+                     "sample_rounds": st["sample_rounds"], "finish_rounds": st["finish_rounds"],
+                     "candidates": st["candidates"], "candidate_edges": st["candidate_edges"],
+                     "lmax_size": st["lmax_size"]})
+        log(f"  [{i:2d}] {v.name():40s} {ms:9.3f} ms  match={ok} rounds={st['sample_rounds']}/{st['finish_rounds']}")
+    ctx.sync_status()
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat24", choices=["rmat24", "er16", "grid3d", "rmat27"])
+    ap.add_argument("--variant", default="default", help="'default' or an index into the 80-variant list")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-incremental", action="store_true")
+    ap.add_argument("--phases", action="store_true", help="print per-phase times to stderr")
+    ap.add_argument("--sweep", default="", help="also time all 80 variants; write the rows to this JSON file")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
+              f"DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2008_03909_amd import binding as b
+
+    assert torch.cuda.is_available(), "no GPU"
+    t = time.perf_counter()
+    g, desc = workload(args.workload)
+    log(f"generated {g} in {time.perf_counter() - t:.1f}s")
+
+    ctx = b.Context(0)
+    dev = ctx.torch_device
+    du = torch.from_numpy(g.u).to(dev)
+    dv = torch.from_numpy(g.v).to(dev)
+    dedup = args.workload != "er16"
+    o64 = args.workload == "rmat27"
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    csr = b.build_csr(ctx, g.n, du, dv, dedup=dedup, offsets_64bit=o64)
+    e1.record()
+    torch.cuda.synchronize()
+    ingest_ms = e0.elapsed_time(e1)
+    del du, dv
+    n, m = csr.n, csr.m
+    o = 8 if o64 else 4
+    deg = (csr.offsets[1:] - csr.offsets[:-1])
+    n_nz = int((deg > 0).sum().item())
+    del deg
+    log(f"device CSR: n={n} m={m} nonisolated={n_nz} ingest {ingest_ms:.1f} ms")
+
+    if args.variant == "default":
+        v = b.default_variant()
+    else:
+        v = b.all_variants()[int(args.variant)]
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    ncomp = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = ctx.workspace(b.workspace_bytes(n, m, v))
+    for _ in range(args.warmup):
+        b.connectivity_csr(ctx, csr, v, labels=labels, ncomp=ncomp)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+
+    # timed region: K steps, phase events on the call's stream
+    ctx.set_timing(True)
+    ctx.phase_times_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.connectivity_csr(ctx, csr, v, labels=labels, ncomp=ncomp)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    ctx.sync_status()
+    phases = ctx.phase_times()
+    st = ctx.last_stats()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = m / (ms_step / 1e3)
+    log(f"static: {ms_step:.3f} ms/step, {value:.3e} edges/s, components={st['num_components']}")
+
+    alg_total = 0.0
+    ph_out = {}
+    for name, (ms, cnt) in phases.items():
+        avg = ms / max(cnt, 1)
+        ab = phase_alg_bytes(name, n, m, o, n_nz, st)
+        alg_total += ab * cnt / args.steps
+        ph_out[name] = {"avg_ms": round(avg, 4), "launches": cnt, "alg_bytes": ab,
+                        "alg_gbs": round(ab / (avg / 1e3) / 1e9, 1) if avg > 0 else None}
+    if args.phases:
+        for k_, x in ph_out.items():
+            log(f"  {k_:16s} {x}")
+    dom = max(ph_out, key=lambda k_: ph_out[k_]["avg_ms"])
+    dom_kernel = {"sample": "k_kout", "compress_count": "k_compress_count", "init": "k_init",
+                  "frequent": "k_argmax", "compact": "k_compact", "finish": "k_fin", "output": "k_output"}.get(dom, dom)
+    achieved = ph_out[dom]["alg_gbs"]
+    traffic = read_traffic(dom_kernel, args.workload)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                "traffic": traffic, "kernel": dom_kernel, "phase": dom,
+                "alg_bytes_per_launch": ph_out[dom]["alg_bytes"], "avg_launch_ms": ph_out[dom]["avg_ms"]}
+
+    out = {
+        "metric": "static CC edges/s + HBM GB/s; incremental updates/s with p50/p99 latency",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "m": m, "nonisolated": n_nz, "variant": v.name(),
+                   "num_components": st["num_components"], "parallelism": "single-gpu"},
+        "hbm_gbs_alg": round(alg_total / (ms_step / 1e3) / 1e9, 1),
+        "roofline": roofline,
+        "phases": ph_out,
+        "stats": st,
+        "ingest": {"ms": ingest_ms, "pairs": g.num_pairs, "pairs_per_s": g.num_pairs / (ingest_ms / 1e3)},
+    }
+    del ws
+    if args.sweep:
+        log("variant sweep ...")
+        rows = sweep(ctx, csr, g, args.workload)
+        with open(args.sweep, "w") as f:
+            json.dump({"workload": desc, "n": n, "m": m, "rows": rows}, f, indent=1)
+        best = min(rows[:80], key=lambda r: r["ms"])
+        out["sweep"] = {"variants": len(rows), "all_match_oracle": all(r["labels_match_oracle"] for r in rows),
+                        "best": best["variant"], "best_ms": best["ms"], "best_edges_per_s": best["edges_per_s"],
+                        "file": os.path.basename(args.sweep)}
+    out["calibration"] = calibration(ctx, csr, n, m, o)
+    log(f"calibration: {out['calibration']}")
+    if not args.no_incremental:
+        log("incremental stream ...")
+        out["incremental"] = incremental(ctx, g)
+        log(f"incremental: {out['incremental']['updates_per_s']:.3e} updates/s, "
+            f"p50 {out['incremental']['p50_ms']:.3f} ms, p99 {out['incremental']['p99_ms']:.3f} ms")
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(g, m)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3e} edges/s")
+    out["host"] = platform.node()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -174,7 +174,9 @@ cc_status cc_sample_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, 
  * ascending, duplicates removed iff dedup != 0.  adj_out needs capacity
  * 2*num_pairs; offsets_out gets n+1 entries (int64 if offsets_64bit).  The
  * edge count m is written to *m_dev (device int64).  Ids outside [0, n) set
- * the device error word and are dropped. */
+ * the device error word and are dropped.  The workspace (at least
+ * cc_csr_workspace_bytes) must be 256-byte aligned.  Synchronises hip_stream
+ * once (to size the sort). */
 cc_status cc_csr_workspace_bytes(int64_t n, int64_t num_pairs, size_t* bytes);
 cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v, int dedup,
                        void* workspace, size_t ws_bytes, void* offsets_out, int offsets_64bit, int32_t* adj_out,
@@ -201,6 +203,18 @@ cc_status cc_query_batch(cc_stream* s, int64_t q, const int32_t* a, const int32_
 cc_status cc_stream_labels(cc_stream* s, int32_t* labels_out, int64_t* num_components_dev, void* hip_stream);
 /* Synchronises and reports (then clears) the stream's device error word. */
 cc_status cc_stream_sync_status(cc_stream* s);
+
+/* ---- calibration (measurement aids) ------------------------------------------
+ * Roofline anchors for the kernels above; they compute nothing the method
+ * needs.  cc_calib_copy: dst = src for `bytes` bytes (both 16-byte aligned,
+ * bytes a multiple of 16) -- the attainable streaming bandwidth.
+ * cc_calib_edges: the paper's MapEdges (vals == NULL: out[v] = number of
+ * adjacency entries read for v) or GatherEdges (out[v] = sum over v's
+ * neighbours w of vals[w], int32 wrap-around), the practical lower bounds of
+ * the appendix "Comparison with MapEdges and GatherEdges".  out: n int32. */
+cc_status cc_calib_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+cc_status cc_calib_edges(int64_t n, const void* offsets, int offsets_are_64bit, const int32_t* adj,
+                         const int32_t* vals, int32_t* out, void* hip_stream);
 
 const char* cc_status_string(cc_status st);
 const char* cc_last_error(void);

@@ -124,6 +124,8 @@ def lib():
             "cc_query_batch": (_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
             "cc_stream_labels": (_int, [_vp, _vp, _vp, _vp]),
             "cc_stream_sync_status": (_int, [_vp]),
+            "cc_calib_copy": (_int, [_vp, _vp, ctypes.c_size_t, _vp]),
+            "cc_calib_edges": (_int, [_i64, _vp, _int, _vp, _vp, _vp, _vp]),
             "cc_status_string": (ctypes.c_char_p, [_int]),
             "cc_last_error": (ctypes.c_char_p, []),
         }
@@ -348,6 +350,22 @@ class Stream:
 
     def sync_status(self):
         _check(lib().cc_stream_sync_status(self.h), "cc_stream_sync_status")
+
+
+# ---- calibration -------------------------------------------------------------
+
+def calib_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    nbytes = min(src.numel() * src.element_size(), dst.numel() * dst.element_size())
+    _check(lib().cc_calib_copy(_ptr(src), _ptr(dst), nbytes - nbytes % 16, _stream_handle(stream)), "cc_calib_copy")
+
+
+def calib_edges(g: CSR, vals: torch.Tensor | None = None, out: torch.Tensor | None = None, stream=None):
+    """MapEdges (vals None) or GatherEdges over a device CSR; returns out (n int32)."""
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.int32, device=g.adj.device)
+    _check(lib().cc_calib_edges(g.n, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(vals), _ptr(out),
+                                _stream_handle(stream)), "cc_calib_edges")
+    return out
 
 
 # ---- the variant space ---------------------------------------------------------

@@ -25,36 +25,38 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per block
 constexpr int kWavesPerSortBlock = kSortThreads / kWave;
 
-__global__ void k_expand_pairs(int64_t n, int64_t num_pairs, const int32_t* __restrict__ u,
-                               const int32_t* __restrict__ v, unsigned long long* __restrict__ keys,
-                               unsigned long long* cnt, DevScalars* sc) {
+// Pair i writes keys 2i and 2i+1; a self-loop or a pair with an id outside
+// [0, n) writes two sentinel keys (all ones), which sort after every real key
+// because a real key never has all-ones digits in both halves (that would be
+// the self-loop (2^bits-1, 2^bits-1)).  The number of real keys is counted
+// with one atomic per block.
+constexpr unsigned long long kSentinel = ~0ull;
+
+__global__ void __launch_bounds__(256) k_expand_pairs(int64_t n, int64_t num_pairs, const int32_t* __restrict__ u,
+                                                      const int32_t* __restrict__ v,
+                                                      unsigned long long* __restrict__ keys, unsigned long long* cnt,
+                                                      DevScalars* sc) {
+  __shared__ unsigned long long red[256 / kWave];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool bad = false;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < num_pairs; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    bool take = false;
-    uint32_t a = 0, b = 0;
-    if (i < num_pairs) {
-      const int32_t x = u[i], y = v[i];
-      const bool ok = x >= 0 && y >= 0 && (int64_t)x < n && (int64_t)y < n;
-      bad |= !ok;
-      take = ok && x != y;
-      a = (uint32_t)x;
-      b = (uint32_t)y;
-    }
-    const uint64_t mask = __ballot(take);
-    if (!mask) continue;
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    unsigned long long pos = 0;
-    if (lane_id() == leader)
-      pos = __hip_atomic_fetch_add(cnt, 2ull * (unsigned long long)__popcll(mask), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    pos = __shfl(pos, leader, kWave);
-    if (take) {
-      const unsigned long long p = pos + 2ull * (unsigned long long)__popcll(mask & lanemask_lt());
-      keys[p] = ((unsigned long long)a << 32) | b;
-      keys[p + 1] = ((unsigned long long)b << 32) | a;
-    }
+  unsigned long long real = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < num_pairs; i += stride) {
+    const int32_t x = u[i], y = v[i];
+    const bool ok = x >= 0 && y >= 0 && (int64_t)x < n && (int64_t)y < n;
+    bad |= !ok;
+    const bool take = ok && x != y;
+    ulonglong2 kv;
+    kv.x = take ? (((unsigned long long)(uint32_t)x << 32) | (uint32_t)y) : kSentinel;
+    kv.y = take ? (((unsigned long long)(uint32_t)y << 32) | (uint32_t)x) : kSentinel;
+    *(ulonglong2*)(keys + 2 * i) = kv;
+    real += take ? 2ull : 0ull;
+  }
+  real = wave_sum(real);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = real;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256 / kWave; ++w) real += red[w];
+    if (real) __hip_atomic_fetch_add(cnt, real, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (__ballot(bad) && lane_id() == 0) atomicOr(&sc->error, kErrBadId);
 }
@@ -286,6 +288,7 @@ cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t*
   const CsrWs W = csr_ws(num_pairs);
   if (!workspace || ws_bytes < W.total)
     return fail(CC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, W.total);
+  if (((uintptr_t)workspace & 255u) != 0) return fail(CC_EINVAL, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)hip_stream;
   char* w = (char*)workspace;
   unsigned long long* keys = (unsigned long long*)(w + W.keys);
@@ -309,8 +312,9 @@ cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t*
   std::vector<int> shifts;
   for (int b = 0; b < bits; b += 8) shifts.push_back(b);
   for (int b = 0; b < bits; b += 8) shifts.push_back(32 + b);
-  const int64_t count = (int64_t)E;
-  const int64_t tiles = div_up(count > 0 ? count : 1, kSortTile);
+  const int64_t count = (int64_t)E;          // real keys; they sort ahead of the sentinels
+  const int64_t sorted = 2 * num_pairs;       // keys the radix passes move
+  const int64_t tiles = div_up(sorted > 0 ? sorted : 1, kSortTile);
   unsigned long long* src = keys;
   unsigned long long* dst = alt;
   if (count > 0) {
@@ -319,10 +323,10 @@ cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t*
       const int width = (bits - lowbit) < 8 ? (bits - lowbit) : 8;
       const uint32_t dmask = (1u << width) - 1u;
       hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)tiles), dim3(kSortThreads), 0, s,
-                         (const unsigned long long*)src, count, sh, dmask, hist, tiles);
+                         (const unsigned long long*)src, sorted, sh, dmask, hist, tiles);
       exclusive_scan(s, hist, 256 * tiles, sums);
       hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kSortThreads), 0, s,
-                         (const unsigned long long*)src, dst, count, sh, dmask, (const uint32_t*)hist, tiles);
+                         (const unsigned long long*)src, dst, sorted, sh, dmask, (const uint32_t*)hist, tiles);
       CC_LAUNCH_CHECK();
       unsigned long long* t = src;
       src = dst;

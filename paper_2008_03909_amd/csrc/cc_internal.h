@@ -100,6 +100,7 @@ struct WsLayout {
   size_t queue = 0;       // 2 * n int32 frontier queues
   size_t edges = 0;       // LT with Alter: 2 * m int32 (edge list)
   size_t hist = 0;        // LDD start-round histogram
+  size_t seg = 0;         // compaction: per-segment counts and edge sums
   size_t total = 0;
 };
 WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v);

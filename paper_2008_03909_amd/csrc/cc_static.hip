@@ -139,6 +139,8 @@ cc_status check_variant(const cc_variant* v, bool for_stream) {
   return CC_OK;
 }
 
+constexpr int kSegMaxHost = 8448;
+
 WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v) {
   WsLayout L;
   size_t off = 0;
@@ -152,6 +154,7 @@ WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v) {
   }
   if (v->sample == CC_SAMPLE_LDD) L.hist = off, off += align256(4096 * 4);
   if (v->finish == CC_FIN_LT && (v->lt_rules & CC_LT_ALTER)) L.edges = off, off += 2 * align256((size_t)m * 4);
+  L.seg = off, off += align256((size_t)kSegMaxHost * 12) + align256((size_t)kSegMaxHost * 8);
   L.total = off + 256;
   return L;
 }
@@ -161,40 +164,94 @@ WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v) {
 constexpr int kBlock = 256;
 constexpr int64_t kStreamGridCap = 4096;
 
-__global__ void k_init(int64_t n, int32_t* __restrict__ P, int32_t* __restrict__ count, DevScalars* sc,
-                       long long* ncomp_user) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ int64_t div_up_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__device__ __forceinline__ uint64_t lanemask_lt_dev() {
+  const int l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+
+__global__ void k_reset_scalars(DevScalars* sc, long long* ncomp_user) {
+  sc->changed = 0;
+  sc->lmax_key = 0ull;
+  sc->lmax = -1;
+  sc->bfs_min = 0x7fffffff;
+  for (int b = 0; b < 4; ++b) sc->bin_count[b] = 0;
+  sc->cand_edges = 0;
+  sc->num_components = 0;
+  sc->lmax_size = 0;
+  sc->qcount[0] = sc->qcount[1] = 0;
+  sc->frontier_edges = 0;
+  sc->reached = 0;
+  sc->flag2 = 0;
+  if (ncomp_user) *ncomp_user = 0;
+}
+
+// P[v] = v and count[v] = 0, four vertices per lane with 16-byte stores.
+__global__ void k_init(int64_t n, int32_t* __restrict__ P, int32_t* __restrict__ count, int aligned) {
+  const int64_t groups = div_up_dev(n, 4);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (i == 0) {
-    sc->changed = 0;
-    sc->lmax_key = 0ull;
-    sc->lmax = -1;
-    sc->bfs_min = 0x7fffffff;
-    for (int b = 0; b < 4; ++b) sc->bin_count[b] = 0;
-    sc->cand_edges = 0;
-    sc->num_components = 0;
-    sc->lmax_size = 0;
-    sc->qcount[0] = sc->qcount[1] = 0;
-    sc->frontier_edges = 0;
-    sc->reached = 0;
-    sc->flag2 = 0;
-    if (ncomp_user) *ncomp_user = 0;
-  }
-  for (; i < n; i += stride) {
-    P[i] = (int32_t)i;
-    if (count) count[i] = 0;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups; g += stride) {
+    const int64_t v0 = 4 * g;
+    if (aligned && v0 + 3 < n) {
+      *(int4*)(P + v0) = make_int4((int)v0, (int)v0 + 1, (int)v0 + 2, (int)v0 + 3);
+      if (count) *(int4*)(count + v0) = make_int4(0, 0, 0, 0);
+    } else {
+      for (int j = 0; j < 4; ++j)
+        if (v0 + j < n) {
+          P[v0 + j] = (int32_t)(v0 + j);
+          if (count) count[v0 + j] = 0;
+        }
+    }
   }
 }
 
+// Loads off[v0 .. v0+4] (five entries) as int64.
+__device__ __forceinline__ void load_off5(const int32_t* off, int64_t v0, bool vec, int64_t n, int64_t o[5]) {
+  if (vec) {
+    const int4 a = *(const int4*)(off + v0);
+    o[0] = a.x, o[1] = a.y, o[2] = a.z, o[3] = a.w;
+    o[4] = off[v0 + 4];
+  } else {
+    for (int j = 0; j < 5; ++j) o[j] = (v0 + j <= n) ? (int64_t)off[v0 + j] : 0;
+  }
+}
+__device__ __forceinline__ void load_off5(const int64_t* off, int64_t v0, bool vec, int64_t n, int64_t o[5]) {
+  if (vec) {
+    const longlong2 a = *(const longlong2*)(off + v0);
+    const longlong2 b = *(const longlong2*)(off + v0 + 2);
+    o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
+    o[4] = off[v0 + 4];
+  } else {
+    for (int j = 0; j < 5; ++j) o[j] = (v0 + j <= n) ? (int64_t)off[v0 + j] : 0;
+  }
+}
+__device__ __forceinline__ void load4(const int32_t* p, int64_t v0, bool vec, int64_t n, int32_t x[4]) {
+  if (vec) {
+    const int4 a = *(const int4*)(p + v0);
+    x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w;
+  } else {
+    for (int j = 0; j < 4; ++j) x[j] = (v0 + j < n) ? p[v0 + j] : 0;
+  }
+}
+
+// k-out sampling: for every vertex with an edge, unite it with its first
+// neighbour (hybrid, afforest) or a seeded pick (pure), then with k-1 more
+// picks, using UF-Rem-CAS with SplitAtomicOne.  All picked neighbours of a
+// vertex are loaded before its first union so their latencies overlap.
 template <typename I>
-__global__ void k_kout(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ adj, int32_t* P, int k,
-                       int mode, uint64_t key) {
+__global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ adj,
+                                                 int32_t* P, int k, int mode, uint64_t key) {
+  constexpr int kMaxPreload = 4;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
     const int64_t b = (int64_t)off[v];
     const int64_t deg = (int64_t)off[v + 1] - b;
     if (deg <= 0) continue;
-    for (int j = 0; j < k; ++j) {
+    int32_t w[kMaxPreload];
+    const int kk = k < kMaxPreload ? k : kMaxPreload;
+    int got = 0;
+    for (int j = 0; j < kk; ++j) {
       int64_t idx;
       if (mode == CC_KOUT_AFFOREST) {
         if (j >= deg) break;
@@ -204,49 +261,88 @@ __global__ void k_kout(int64_t n, const I* __restrict__ off, const int32_t* __re
       } else {
         idx = (int64_t)(sm_out(key, (uint64_t)v * (uint64_t)k + (uint64_t)j) % (uint64_t)deg);
       }
+      w[j] = adj[b + idx];
+      got = j + 1;
+    }
+    for (int j = 0; j < got; ++j) union_rem<kSplitOne, kFindNaive>(P, (int32_t)v, w[j]);
+    for (int j = kMaxPreload; j < k; ++j) {
+      int64_t idx;
+      if (mode == CC_KOUT_AFFOREST) {
+        if (j >= deg) break;
+        idx = j;
+      } else {
+        idx = (int64_t)(sm_out(key, (uint64_t)v * (uint64_t)k + (uint64_t)j) % (uint64_t)deg);
+      }
       union_rem<kSplitOne, kFindNaive>(P, (int32_t)v, adj[b + idx]);
     }
   }
 }
 
 // Full compression fused with the IdentifyFrequent histogram.  Only vertices
-// with at least one edge are counted (an isolated vertex is its own class and
-// can never be the most frequent one unless every class is a singleton, in
-// which case skipping nothing is equivalent).  Equal labels inside a wave are
-// aggregated into one atomic.
+// with at least one edge are counted (an isolated vertex is a class of its
+// own and cannot be the unique most frequent one; if every class is a
+// singleton, skipping nothing is equivalent).  Counting is aggregated twice:
+// lanes of a wave with the leader's label add once, and the block keeps the
+// count of one "hot" label (the first leader label it meets) in LDS, so the
+// giant component costs one global atomic per block.
 template <typename I>
-__global__ void k_compress_count(int64_t n, const I* __restrict__ off, int32_t* P, int32_t* __restrict__ count) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__global__ void __launch_bounds__(kBlock) k_compress_count(int64_t n, const I* __restrict__ off, int32_t* P,
+                                                           int32_t* __restrict__ count, int aligned) {
+  __shared__ int32_t hot;
+  __shared__ int32_t hot_cnt;
+  if (threadIdx.x == 0) {
+    hot = -1;
+    hot_cnt = 0;
+  }
+  __syncthreads();
   const int lane = lane_id();
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
-    const int64_t v = base + threadIdx.x;
-    const bool act = v < n;
-    int32_t r = 0;
-    bool c = false;
+  const int64_t groups = div_up_dev(n, 4);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t gbase = blockIdx.x * (int64_t)blockDim.x; gbase < groups; gbase += stride) {
+    const int64_t g = gbase + threadIdx.x;
+    const int64_t v0 = 4 * g;
+    int32_t p[4] = {0, 0, 0, 0};
+    int64_t o[5] = {0, 0, 0, 0, 0};
+    const bool act = g < groups;
+    const bool vec = aligned && v0 + 3 < n;
     if (act) {
-      int32_t p = ld(P + v);
-      r = p;
-      if (p != (int32_t)v) {
-        r = find_naive(P, p);
-        if (r != p) st(P + v, r);
+      load4(P, v0, vec, n, p);
+      if (count) load_off5(off, v0, vec, n, o);
+    }
+    int32_t r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      r[j] = p[j];
+      if (act && v0 + j < n && p[j] != (int32_t)(v0 + j)) {
+        r[j] = find_naive(P, p[j]);
+        if (r[j] != p[j]) st(P + v0 + j, r[j]);
       }
-      c = (int64_t)off[v + 1] > (int64_t)off[v];
     }
     if (!count) continue;
-    uint64_t mact = __ballot(c);
-    if (mact == 0) continue;
-    const int leader = __ffsll((unsigned long long)mact) - 1;
-    const int32_t lead = __shfl(r, leader, kWave);
-    const uint64_t same = __ballot(c && r == lead);
-    if (c) {
-      if (r == lead) {
-        if (lane == leader)
-          __hip_atomic_fetch_add(count + lead, (int32_t)__popcll(same), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        __hip_atomic_fetch_add(count + r, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool c = act && v0 + j < n && o[j + 1] > o[j];
+      const uint64_t mact = __ballot(c);
+      if (mact == 0) continue;
+      const int leader = __ffsll((unsigned long long)mact) - 1;
+      const int32_t lead = __shfl(r[j], leader, kWave);
+      const uint64_t same = __ballot(c && r[j] == lead);
+      if (lane == leader) {
+        int32_t h = hot;
+        if (h == -1) {
+          atomicCAS(&hot, -1, lead);
+          h = hot;
+        }
+        if (h == lead) atomicAdd(&hot_cnt, (int32_t)__popcll(same));
+        else __hip_atomic_fetch_add(count + lead, (int32_t)__popcll(same), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+      if (c && r[j] != lead) __hip_atomic_fetch_add(count + r[j], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+  if (!count) return;
+  __syncthreads();
+  if (threadIdx.x == 0 && hot_cnt > 0)
+    __hip_atomic_fetch_add(count + hot, hot_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
@@ -258,16 +354,22 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
 }
 
 // IdentifyFrequent: max over (count << 32 | ~label); ties go to the smaller label.
-__global__ void k_argmax(int64_t n, const int32_t* __restrict__ count, DevScalars* sc) {
+__global__ void __launch_bounds__(kBlock) k_argmax(int64_t n, const int32_t* __restrict__ count, DevScalars* sc,
+                                                   int aligned) {
   __shared__ unsigned long long red[kBlock / kWave];
   unsigned long long best = 0;
+  const int64_t groups = div_up_dev(n, 4);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
-    int32_t c = count[v];
-    if (c > 0) {
-      unsigned long long key = ((unsigned long long)(uint32_t)c << 32) | (uint32_t)(~(uint32_t)v);
-      best = key > best ? key : best;
-    }
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups; g += stride) {
+    const int64_t v0 = 4 * g;
+    int32_t c[4];
+    load4(count, v0, aligned && v0 + 3 < n, n, c);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (c[j] > 0 && v0 + j < n) {
+        const unsigned long long key = ((unsigned long long)(uint32_t)c[j] << 32) | (uint32_t)(~(uint32_t)(v0 + j));
+        best = key > best ? key : best;
+      }
   }
   best = wave_max_u64(best);
   if (lane_id() == 0) red[threadIdx.x / kWave] = best;
@@ -288,45 +390,146 @@ __global__ void k_resolve_lmax(DevScalars* sc, int use) {
   sc->lmax_size = use ? (long long)(key >> 32) : 0;
 }
 
-// Candidate compaction with degree binning.
+// Candidate compaction with degree binning, in three launches and without
+// contended atomics.  Wave w owns the vertex range [w*S, min((w+1)*S, n)) and
+// the same range of the scratch array: thread-bin candidates (degree <=
+// thr_wave) fill it from the front, larger ones from the back (block-bin ones, degree >
+// thr_block, stored as ~v).  A one-block scan turns the per-wave counts into
+// list offsets, and a gather copies every segment into the final lists:
+// cand (thread bin), big front (wave bin), big back (block bin).  The lists
+// are in a fixed order, so the finish sees the same work every run.
+constexpr int kSegMax = 8448;  // upper bound on the number of segments
+
 template <typename I>
-__global__ void k_compact(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ P, DevScalars* sc,
-                          int32_t* __restrict__ cand, int32_t* __restrict__ big, int thr_wave, int thr_block) {
+__global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, const I* __restrict__ off,
+                                                        const int32_t* __restrict__ P, const DevScalars* sc,
+                                                        int32_t* __restrict__ scratch, int32_t* __restrict__ segcnt,
+                                                        long long* __restrict__ segedges, int thr_wave,
+                                                        int thr_block, int aligned) {
   const int32_t L = sc->lmax;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int lane = lane_id();
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  long long edges = 0;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
-    const int64_t v = base + threadIdx.x;
-    int64_t deg = 0;
-    bool isc = false;
-    if (v < n) {
-      deg = (int64_t)off[v + 1] - (int64_t)off[v];
-      isc = deg > 0 && P[v] != L;
-    }
-    const int bin = deg <= thr_wave ? 0 : (deg <= thr_block ? 1 : 2);
-    if (isc) edges += deg;
+  const uint64_t lt = lanemask_lt_dev();
+  const int64_t nseg = div_up_dev(n, S);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; w < nseg; w += waves) {
+    const int64_t lo = w * S;
+    const int64_t hi = (lo + S < n) ? lo + S : n;
+    int32_t c0 = 0, cb = 0, c2 = 0;
+    long long edges = 0;
+    for (int64_t base = lo; base < hi; base += 4 * kWave) {
+      const int64_t v0 = base + 4 * lane;
+      const bool act = v0 < hi;
+      const bool vec = aligned && v0 + 3 < hi;
+      int32_t p[4] = {0, 0, 0, 0};
+      int64_t o[5] = {0, 0, 0, 0, 0};
+      if (act) {
+        load4(P, v0, vec, n, p);
+        load_off5(off, v0, vec, n, o);
+      }
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const uint64_t mask = __ballot(isc && bin == b);
-      if (!mask) continue;
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      int32_t basepos = 0;
-      if (lane == leader)
-        basepos = __hip_atomic_fetch_add(&sc->bin_count[b], (int32_t)__popcll(mask), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-      basepos = __shfl(basepos, leader, kWave);
-      if (isc && bin == b) {
-        const int32_t pos = basepos + (int32_t)__popcll(mask & lt_mask);
-        if (b == 0) cand[pos] = (int32_t)v;
-        else if (b == 1) big[pos] = (int32_t)v;
-        else big[n - 1 - pos] = (int32_t)v;
+      for (int j = 0; j < 4; ++j) {
+        const bool inb = act && v0 + j < hi;
+        const int64_t deg = inb ? o[j + 1] - o[j] : 0;
+        const bool isc = inb && deg > 0 && p[j] != L;
+        if (isc) edges += deg;
+        const bool small = isc && deg <= thr_wave;
+        const bool large = isc && deg > thr_wave;
+        const bool huge = large && deg > thr_block;
+        const uint64_t ms = __ballot(small);
+        const uint64_t ml = __ballot(large);
+        if (small) scratch[lo + c0 + __popcll(ms & lt)] = (int32_t)(v0 + j);
+        if (large) scratch[hi - 1 - (cb + __popcll(ml & lt))] = huge ? ~(int32_t)(v0 + j) : (int32_t)(v0 + j);
+        c0 += __popcll(ms);
+        cb += __popcll(ml);
+        c2 += __popcll(__ballot(huge));
       }
     }
+    edges = wave_sum(edges);
+    if (lane == 0) {
+      segcnt[3 * w + 0] = c0;
+      segcnt[3 * w + 1] = cb - c2;
+      segcnt[3 * w + 2] = c2;
+      segedges[w] = edges;
+    }
   }
-  edges = wave_sum(edges);
-  if (lane == 0 && edges) add64(&sc->cand_edges, edges);
+}
+
+// One block: exclusive scan of the per-segment counts (three bins), totals
+// into the context scalars.
+__global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* segcnt, const long long* segedges,
+                                                       DevScalars* sc) {
+  __shared__ int32_t part[3][1024];
+  __shared__ long long epart[1024];
+  const int t = threadIdx.x;
+  const int64_t per = div_up_dev(nseg, 1024);
+  const int64_t lo = t * per, hi = (lo + per < nseg) ? lo + per : nseg;
+  int32_t s0 = 0, s1 = 0, s2 = 0;
+  long long e = 0;
+  for (int64_t i = lo; i < hi; ++i) {
+    s0 += segcnt[3 * i];
+    s1 += segcnt[3 * i + 1];
+    s2 += segcnt[3 * i + 2];
+    e += segedges[i];
+  }
+  part[0][t] = s0, part[1][t] = s1, part[2][t] = s2;
+  epart[t] = e;
+  __syncthreads();
+  if (t < 3) {  // serial exclusive scan of 1024 partials per bin
+    int32_t run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int32_t x = part[t][i];
+      part[t][i] = run;
+      run += x;
+    }
+    sc->bin_count[t] = run;
+  } else if (t == 3) {
+    long long tot = 0;
+    for (int i = 0; i < 1024; ++i) tot += epart[i];
+    sc->cand_edges = tot;
+  }
+  __syncthreads();
+  int32_t r0 = part[0][t], r1 = part[1][t], r2 = part[2][t];
+  for (int64_t i = lo; i < hi; ++i) {
+    const int32_t x0 = segcnt[3 * i], x1 = segcnt[3 * i + 1], x2 = segcnt[3 * i + 2];
+    segcnt[3 * i] = r0, segcnt[3 * i + 1] = r1, segcnt[3 * i + 2] = r2;
+    r0 += x0, r1 += x1, r2 += x2;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_compact_gather(int64_t n, int64_t S, const int32_t* __restrict__ scratch,
+                                                           const int32_t* __restrict__ segoff,
+                                                           const int32_t* __restrict__ segcnt_unused,
+                                                           int32_t* __restrict__ cand, int32_t* __restrict__ big,
+                                                           const DevScalars* sc) {
+  (void)segcnt_unused;
+  const int lane = lane_id();
+  const uint64_t lt = lanemask_lt_dev();
+  const int64_t nseg = div_up_dev(n, S);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int32_t tot0 = sc->bin_count[0], tot1 = sc->bin_count[1], tot2 = sc->bin_count[2];
+  for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; w < nseg; w += waves) {
+    const int64_t lo = w * S;
+    const int64_t hi = (lo + S < n) ? lo + S : n;
+    const int32_t o0 = segoff[3 * w], o1 = segoff[3 * w + 1], o2 = segoff[3 * w + 2];
+    // segment counts = next segment's offset (or the total) minus this one's
+    const int32_t e0 = (w + 1 < nseg) ? segoff[3 * (w + 1)] : tot0;
+    const int32_t e1 = (w + 1 < nseg) ? segoff[3 * (w + 1) + 1] : tot1;
+    const int32_t e2 = (w + 1 < nseg) ? segoff[3 * (w + 1) + 2] : tot2;
+    const int32_t c0 = e0 - o0, cb = (e1 - o1) + (e2 - o2);
+    for (int32_t i = lane; i < c0; i += kWave) cand[o0 + i] = scratch[lo + i];
+    int32_t r1 = o1, r2 = o2;
+    for (int32_t i0 = 0; i0 < cb; i0 += kWave) {
+      const int32_t i = i0 + lane;
+      const int32_t x = (i < cb) ? scratch[hi - 1 - i] : 0;
+      const bool b1 = i < cb && x >= 0;
+      const bool b2 = i < cb && x < 0;
+      const uint64_t m1 = __ballot(b1), m2 = __ballot(b2);
+      if (b1) big[r1 + __popcll(m1 & lt)] = x;
+      if (b2) big[n - 1 - (r2 + __popcll(m2 & lt))] = ~x;
+      r1 += __popcll(m1);
+      r2 += __popcll(m2);
+    }
+  }
 }
 
 // Union-find finish: thread / wave / block per candidate.
@@ -368,18 +571,27 @@ __global__ void k_fin_block(int64_t n, const int32_t* __restrict__ big, const De
 
 // Final compression and component count: label = root (the component's
 // minimum, since every link points to a smaller id).
-__global__ void k_output(int64_t n, int32_t* P, DevScalars* sc, long long* ncomp_user) {
+__global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, DevScalars* sc, long long* ncomp_user,
+                                                   int aligned) {
   __shared__ long long red[kBlock / kWave];
   long long roots = 0;
+  const int64_t groups = div_up_dev(n, 4);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
-    const int32_t p = ld(P + v);
-    if (p == (int32_t)v) {
-      ++roots;
-      continue;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups; g += stride) {
+    const int64_t v0 = 4 * g;
+    int32_t p[4];
+    load4(P, v0, aligned && v0 + 3 < n, n, p);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t v = v0 + j;
+      if (v >= n) continue;
+      if (p[j] == (int32_t)v) {
+        ++roots;
+        continue;
+      }
+      const int32_t r = find_naive(P, p[j]);
+      if (r != p[j]) st(P + v, r);
     }
-    const int32_t r = find_naive(P, p);
-    if (r != p) st(P + v, r);
   }
   roots = wave_sum(roots);
   if (lane_id() == 0) red[threadIdx.x / kWave] = roots;
@@ -431,17 +643,24 @@ static cc_status uf_finish_dispatch(StaticArgs& a) {
   return fail(CC_EINVAL, "no such union-find variant");
 }
 
+static inline bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+// Every array the streaming kernels read four-at-a-time is 16-byte aligned.
+static inline int vec_ok(const StaticArgs& a) { return al16(a.P) && al16(a.off) && al16(a.count); }
+static inline unsigned grid4(int64_t n) { return grid_for(div_up(n, 4), kBlock, 2048); }
+
 template <typename I>
 cc_status compress_count_frequent(StaticArgs& a, bool use_lmax) {
-  const unsigned g = grid_for(a.n, kBlock, kStreamGridCap);
+  const int vec = vec_ok(a);
   {
     PhaseScope ps(a.ctx, a.s, "compress_count");
-    hipLaunchKernelGGL(k_compress_count<I>, dim3(g), dim3(kBlock), 0, a.s, a.n, (const I*)a.off, a.P,
-                       use_lmax ? a.count : (int32_t*)nullptr);
+    hipLaunchKernelGGL(k_compress_count<I>, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, (const I*)a.off, a.P,
+                       use_lmax ? a.count : (int32_t*)nullptr, vec);
   }
   {
     PhaseScope ps(a.ctx, a.s, "frequent");
-    if (use_lmax) hipLaunchKernelGGL(k_argmax, dim3(g), dim3(kBlock), 0, a.s, a.n, (const int32_t*)a.count, a.ctx->dev);
+    if (use_lmax)
+      hipLaunchKernelGGL(k_argmax, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, (const int32_t*)a.count, a.ctx->dev,
+                         vec);
     hipLaunchKernelGGL(k_resolve_lmax, dim3(1), dim3(1), 0, a.s, a.ctx->dev, use_lmax ? 1 : 0);
   }
   CC_LAUNCH_CHECK();
@@ -495,17 +714,29 @@ template <typename I>
 static cc_status run_static(StaticArgs& a, bool sample_only) {
   {
     PhaseScope ps(a.ctx, a.s, "init");
-    hipLaunchKernelGGL(k_init, dim3(grid_for(a.n, kBlock, kStreamGridCap)), dim3(kBlock), 0, a.s, a.n, a.P,
-                       a.v->sample == CC_SAMPLE_NONE ? (int32_t*)nullptr : a.count, a.ctx->dev,
-                       (long long*)a.ncomp_user);
+    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, a.s, a.ctx->dev, (long long*)a.ncomp_user);
+    hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P,
+                       a.v->sample == CC_SAMPLE_NONE ? (int32_t*)nullptr : a.count, vec_ok(a));
     CC_LAUNCH_CHECK();
   }
   cc_status st = run_sample<I>(a);
   if (st != CC_OK || sample_only) return st;
   {
     PhaseScope ps(a.ctx, a.s, "compact");
-    hipLaunchKernelGGL(k_compact<I>, dim3(grid_for(a.n, kBlock, kStreamGridCap)), dim3(kBlock), 0, a.s, a.n,
-                       (const I*)a.off, (const int32_t*)a.P, a.ctx->dev, a.cand, a.big, kThrWave, kThrBlock);
+    // segment size: a multiple of 256 vertices, at most ~8192 segments
+    int64_t S = div_up(div_up(a.n, 8192), 256) * 256;
+    const int64_t nseg = div_up(a.n, S);
+    int32_t* segcnt = (int32_t*)(a.ws + a.L.seg);
+    long long* segedges = (long long*)(a.ws + a.L.seg + align256((size_t)kSegMax * 12));
+    const unsigned gw = grid_for(nseg * kWave, kBlock, 2048);
+    hipLaunchKernelGGL(k_compact_seg<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
+                       (const int32_t*)a.P, (const DevScalars*)a.ctx->dev, a.count, segcnt, segedges, kThrWave,
+                       kThrBlock, vec_ok(a));
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, a.s, nseg, segcnt, (const long long*)segedges,
+                       a.ctx->dev);
+    hipLaunchKernelGGL(k_compact_gather, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const int32_t*)a.count,
+                       (const int32_t*)segcnt, (const int32_t*)nullptr, a.cand, a.big,
+                       (const DevScalars*)a.ctx->dev);
     CC_LAUNCH_CHECK();
   }
   a.finish_rounds = 0;
@@ -518,8 +749,8 @@ static cc_status run_static(StaticArgs& a, bool sample_only) {
   if (st != CC_OK) return st;
   {
     PhaseScope ps(a.ctx, a.s, "output");
-    hipLaunchKernelGGL(k_output, dim3(grid_for(a.n, kBlock, kStreamGridCap)), dim3(kBlock), 0, a.s, a.n, a.P,
-                       a.ctx->dev, (long long*)a.ncomp_user);
+    hipLaunchKernelGGL(k_output, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P, a.ctx->dev,
+                       (long long*)a.ncomp_user, vec_ok(a));
     CC_LAUNCH_CHECK();
   }
   return CC_OK;

@@ -259,3 +259,26 @@ def test_incremental_rejects_bad_ids(ctx):
     with pytest.raises(b.CCError):
         st.sync_status()
     st.close()
+
+
+# ---- calibration kernels ------------------------------------------------------------
+
+def test_map_and_gather_edges(ctx):
+    for g in SUITE + [inputs.rmat(14, 8 << 14, 0.57, 0.19, 0.19, seed=2)]:
+        d = _csr(ctx, g)
+        off, adj = oracle.csr_build(g.n, g.u, g.v, True)
+        deg = np.diff(off).astype(np.int64)
+        got = b.calib_edges(d).cpu().numpy()
+        assert np.array_equal(got, deg.astype(np.int32)), g
+        vals = (np.arange(g.n, dtype=np.int64) * 7 + 3) % 1000
+        gv = b.calib_edges(d, torch.from_numpy(vals.astype(np.int32)).to(ctx.torch_device)).cpu().numpy()
+        want = np.zeros(g.n, np.int64)
+        np.add.at(want, np.repeat(np.arange(g.n), deg), vals[adj])
+        assert np.array_equal(gv, want.astype(np.int32)), g
+
+
+def test_calib_copy(ctx):
+    src = torch.randint(0, 255, (1 << 20,), dtype=torch.uint8, device=ctx.torch_device)
+    dst = torch.zeros_like(src)
+    b.calib_copy(src, dst)
+    assert torch.equal(src, dst)
