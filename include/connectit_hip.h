@@ -211,10 +211,12 @@ cc_status cc_stream_sync_status(cc_stream* s);
  * cc_calib_edges: the paper's MapEdges (vals == NULL: out[v] = number of
  * adjacency entries read for v) or GatherEdges (out[v] = sum over v's
  * neighbours w of vals[w], int32 wrap-around), the practical lower bounds of
- * the appendix "Comparison with MapEdges and GatherEdges".  out: n int32. */
+ * the appendix "Comparison with MapEdges and GatherEdges".  out: n int32;
+ * workspace: device bytes >= cc_calib_workspace_bytes(m). */
 cc_status cc_calib_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
-cc_status cc_calib_edges(int64_t n, const void* offsets, int offsets_are_64bit, const int32_t* adj,
-                         const int32_t* vals, int32_t* out, void* hip_stream);
+cc_status cc_calib_workspace_bytes(int64_t m, size_t* bytes);
+cc_status cc_calib_edges(int64_t n, int64_t m, const void* offsets, int offsets_are_64bit, const int32_t* adj,
+                         const int32_t* vals, int32_t* out, void* workspace, size_t ws_bytes, void* hip_stream);
 
 const char* cc_status_string(cc_status st);
 const char* cc_last_error(void);

@@ -125,7 +125,8 @@ def lib():
             "cc_stream_labels": (_int, [_vp, _vp, _vp, _vp]),
             "cc_stream_sync_status": (_int, [_vp]),
             "cc_calib_copy": (_int, [_vp, _vp, ctypes.c_size_t, _vp]),
-            "cc_calib_edges": (_int, [_i64, _vp, _int, _vp, _vp, _vp, _vp]),
+            "cc_calib_workspace_bytes": (_int, [_i64, ctypes.POINTER(ctypes.c_size_t)]),
+            "cc_calib_edges": (_int, [_i64, _i64, _vp, _int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
             "cc_status_string": (ctypes.c_char_p, [_int]),
             "cc_last_error": (ctypes.c_char_p, []),
         }
@@ -363,8 +364,11 @@ def calib_edges(g: CSR, vals: torch.Tensor | None = None, out: torch.Tensor | No
     """MapEdges (vals None) or GatherEdges over a device CSR; returns out (n int32)."""
     if out is None:
         out = torch.empty(g.n, dtype=torch.int32, device=g.adj.device)
-    _check(lib().cc_calib_edges(g.n, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(vals), _ptr(out),
-                                _stream_handle(stream)), "cc_calib_edges")
+    wsb = ctypes.c_size_t()
+    _check(lib().cc_calib_workspace_bytes(g.m, ctypes.byref(wsb)), "cc_calib_workspace_bytes")
+    ws = torch.empty(int(wsb.value), dtype=torch.uint8, device=g.adj.device)
+    _check(lib().cc_calib_edges(g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(vals), _ptr(out), _ptr(ws),
+                                ws.numel(), _stream_handle(stream)), "cc_calib_edges")
     return out
 
 

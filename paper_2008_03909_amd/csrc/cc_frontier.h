@@ -17,10 +17,12 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // Plain read of a bitmap bit (used where a stale 0 only costs an atomic).
 __device__ __forceinline__ bool bit_get(const uint32_t* bm, int64_t x) { return (bm[x >> 5] >> (x & 31)) & 1u; }
 
-// Atomically set bit x; true iff this call set it.
+// Atomically set bit x; true iff this call set it.  Bits only ever go from
+// 0 to 1, so a plain (possibly stale) read that already shows the bit is
+// conclusive and saves the atomic; a stale 0 falls through to it.
 __device__ __forceinline__ bool bit_claim(uint32_t* bm, int64_t x) {
   const uint32_t b = 1u << (x & 31);
-  if (ldu(bm + (x >> 5)) & b) return false;
+  if (bm[x >> 5] & b) return false;
   return !(aor(bm + (x >> 5), b) & b);
 }
 
@@ -60,8 +62,126 @@ __device__ __forceinline__ void wave_flag(bool any, uint32_t* flag) {
     __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Degree bins of the candidate lists and of frontier vertices.
+constexpr int kThrWave = 32;      // degree <= 32: one thread per vertex
+constexpr int kThrBlock = 256;    // <= 256: one wave; <= kThrGrid: one block
+constexpr int kThrGrid = 4096;    // larger: the whole grid, edge-balanced
+constexpr int kHeavyFrontier = 256;  // frontier rows above this go to the grid kernel
+
+// Capacity of a heavy list: vertices whose degree exceeds kHeavyFrontier.
+inline size_t heavy_cap(int64_t m) { return (size_t)(m / kHeavyFrontier) + 2; }
+
+// Exclusive prefix of the degrees of a vertex list whose length lives on the
+// device: hp[i] = sum of deg(list[j]) for j < i, hp[count] = total.  Three
+// launches: per-tile sums, one-block scan of the tile sums, tile scans.  The
+// grid is sized for the list's capacity; surplus blocks exit at once.
+constexpr int kHpTile = 1024;
+
+__device__ __forceinline__ long long block_excl_scan_ll(long long x, long long* total) {
+  __shared__ long long wsum[1024 / kWave];
+  const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  long long inc = x;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const long long y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  long long before = 0, all = 0;
+  for (int q = 0; q < nw; ++q) {
+    if (q < w) before += wsum[q];
+    all += wsum[q];
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - x;
+}
+
+template <typename I>
+__device__ __forceinline__ long long list_deg(const int32_t* list, int64_t i, int64_t c, const I* off) {
+  if (i >= c) return 0;
+  const int32_t u = list[i];
+  return (long long)off[u + 1] - (long long)off[u];
+}
+
+template <typename I>
+__global__ void __launch_bounds__(kHpTile) k_hp_tiles(const int32_t* __restrict__ list, const int32_t* count_ptr,
+                                                      const I* __restrict__ off, long long* __restrict__ tsum) {
+  const int64_t c = *count_ptr;
+  const int64_t i = blockIdx.x * (int64_t)kHpTile + threadIdx.x;
+  if ((int64_t)blockIdx.x * kHpTile >= c) return;
+  long long total;
+  block_excl_scan_ll(list_deg(list, i, c, off), &total);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = total;
+}
+
+static __global__ void __launch_bounds__(kHpTile) k_hp_top(const int32_t* count_ptr, long long* tsum) {
+  const int64_t c = *count_ptr;
+  const int64_t tiles = (c + kHpTile - 1) / kHpTile;
+  long long carry = 0;
+  for (int64_t base = 0; base < tiles; base += kHpTile) {
+    const int64_t i = base + threadIdx.x;
+    const long long x = i < tiles ? tsum[i] : 0;
+    long long total;
+    const long long ex = block_excl_scan_ll(x, &total);
+    if (i < tiles) tsum[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) tsum[tiles] = carry;  // grand total after the tile offsets
+}
+
+template <typename I>
+__global__ void __launch_bounds__(kHpTile) k_hp_down(const int32_t* __restrict__ list, const int32_t* count_ptr,
+                                                     const I* __restrict__ off, const long long* __restrict__ tsum,
+                                                     long long* __restrict__ hp) {
+  const int64_t c = *count_ptr;
+  if ((int64_t)blockIdx.x * kHpTile >= c) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) hp[0] = 0;
+    return;
+  }
+  const int64_t i = blockIdx.x * (int64_t)kHpTile + threadIdx.x;
+  long long total;
+  const long long ex = block_excl_scan_ll(list_deg(list, i, c, off), &total);
+  if (i < c) hp[i] = tsum[blockIdx.x] + ex;
+  if (i == c - 1) hp[c] = tsum[(c + kHpTile - 1) / kHpTile];
+}
+
+// Launches the three prefix kernels for a list of capacity `cap` (tsum holds
+// cap / kHpTile + 2 entries).
+template <typename I>
+inline void heavy_prefix(hipStream_t s, const int32_t* list, const int32_t* count_ptr, int64_t cap, const I* off,
+                         long long* tsum, long long* hp) {
+  const unsigned tiles = (unsigned)((cap + kHpTile - 1) / kHpTile);
+  hipLaunchKernelGGL(k_hp_tiles<I>, dim3(tiles ? tiles : 1), dim3(kHpTile), 0, s, list, count_ptr, off, tsum);
+  hipLaunchKernelGGL(k_hp_top, dim3(1), dim3(kHpTile), 0, s, count_ptr, tsum);
+  hipLaunchKernelGGL(k_hp_down<I>, dim3(tiles ? tiles : 1), dim3(kHpTile), 0, s, list, count_ptr, off,
+                     (const long long*)tsum, hp);
+}
+
+// Largest i in [0, c) with hp[i] <= e (hp ascending, hp[0] = 0 <= e).
+__device__ __forceinline__ int64_t heavy_owner(const long long* hp, int64_t c, long long e) {
+  int64_t lo = 0, hi = c - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (hp[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Owner of edge e for a wave that covers the tile [e0, e0 + 64): one binary
+// search for the tile start (the same for every lane), then each lane steps
+// forward; heavy rows are longer than a tile, so that is at most one step.
+__device__ __forceinline__ int64_t heavy_owner_tile(const long long* hp, int64_t c, long long e0, long long e) {
+  int64_t i = heavy_owner(hp, c, e0);
+  while (i + 1 < c && hp[i + 1] <= e) ++i;
+  return i;
+}
+
 // Edge visitors over the degree-binned candidate lists written by the
-// compaction kernel: op(u, w) for every candidate u and every w in row(u).
+// compaction: op(u, w) for every candidate u and every w in row(u).  Thread
+// bin: cand front; wave bin: big front; block bin: big back; grid bin: the
+// heavy list, whose edges are spread evenly over the whole grid.
 template <class Op, typename I>
 __global__ void k_visit_thread(const int32_t* __restrict__ cand, const DevScalars* sc, const I* __restrict__ off,
                                const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
@@ -105,13 +225,48 @@ __global__ void k_visit_block(int64_t n, const int32_t* __restrict__ big, const 
 }
 
 template <class Op, typename I>
-inline void visit_candidates(hipStream_t s, int64_t n, const int32_t* cand, const int32_t* big,
-                             const DevScalars* sc, const I* off, const int32_t* adj, Op op, uint32_t* flag) {
-  hipLaunchKernelGGL((k_visit_thread<Op, I>), dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, s, cand, sc, off,
-                     adj, op, flag);
-  hipLaunchKernelGGL((k_visit_wave<Op, I>), dim3(grid_for(n * kWave, kFBlock, 2048)), dim3(kFBlock), 0, s, big, sc,
+__global__ void k_visit_heavy(const int32_t* __restrict__ hlist, const int32_t* count_ptr,
+                              const long long* __restrict__ hp, const I* __restrict__ off,
+                              const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+  const int64_t c = *count_ptr;
+  bool any = false;
+  if (c > 0) {
+    const long long T = hp[c];  // written by heavy_prefix
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
+      const long long e0 = base + (threadIdx.x / kWave) * kWave;
+      const long long e = base + threadIdx.x;
+      if (e0 >= T) continue;
+      if (e < T) {
+        const int64_t i = heavy_owner_tile(hp, c, e0, e);
+        const int32_t u = hlist[i];
+        any |= op(u, adj[(int64_t)off[u] + (e - hp[i])]);
+      }
+    }
+  }
+  if (flag) wave_flag(any, flag);
+}
+
+// Candidate lists of one static call.
+struct CandLists {
+  int64_t n;
+  const int32_t* cand;    // thread bin
+  const int32_t* big;     // wave bin (front), block bin (back)
+  const int32_t* heavy;   // grid bin
+  const long long* hp;    // degree prefix of the grid bin
+  const DevScalars* sc;
+};
+
+template <class Op, typename I>
+inline void visit_candidates(hipStream_t s, const CandLists& L, const I* off, const int32_t* adj, Op op,
+                             uint32_t* flag) {
+  hipLaunchKernelGGL((k_visit_thread<Op, I>), dim3(grid_for(L.n, kFBlock, 4096)), dim3(kFBlock), 0, s, L.cand, L.sc,
                      off, adj, op, flag);
-  hipLaunchKernelGGL((k_visit_block<Op, I>), dim3(1024), dim3(kFBlock), 0, s, n, big, sc, off, adj, op, flag);
+  hipLaunchKernelGGL((k_visit_wave<Op, I>), dim3(grid_for(L.n * kWave, kFBlock, 2048)), dim3(kFBlock), 0, s, L.big,
+                     L.sc, off, adj, op, flag);
+  hipLaunchKernelGGL((k_visit_block<Op, I>), dim3(1024), dim3(kFBlock), 0, s, L.n, L.big, L.sc, off, adj, op, flag);
+  hipLaunchKernelGGL((k_visit_heavy<Op, I>), dim3(2048), dim3(kFBlock), 0, s, L.heavy, &L.sc->bin_count[3], L.hp,
+                     off, adj, op, flag);
 }
 
 static __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }

@@ -26,7 +26,8 @@ struct DevScalars {
   long long frontier_edges;    // degree sum of the next frontier
   long long reached;       // vertices reached by the current BFS
   uint32_t flag2;          // spare flag for sub-rounds (full shortcut)
-  uint32_t pad[15];
+  int32_t hcount;          // heavy frontier vertices deferred to the grid kernel
+  uint32_t pad[14];
 };
 
 enum : uint32_t { kErrBadId = 1u, kErrRoundCap = 2u, kErrBadCsr = 4u };
@@ -101,6 +102,7 @@ struct WsLayout {
   size_t edges = 0;       // LT with Alter: 2 * m int32 (edge list)
   size_t hist = 0;        // LDD start-round histogram
   size_t seg = 0;         // compaction: per-segment counts and edge sums
+  size_t heavy = 0;       // grid-bin vertex list and its degree prefix
   size_t total = 0;
 };
 WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v);

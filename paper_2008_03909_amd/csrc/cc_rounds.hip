@@ -26,7 +26,8 @@ struct SvHook {
     const int32_t l = pu < pv ? pu : pv;
     const int32_t h = pu < pv ? pv : pu;
     if (prev[h] != h) return false;
-    amin(P + h, l);
+    // P[h] only decreases: skip the atomic when another edge already did better
+    if (ld(P + h) > l) amin(P + h, l);
     return true;
   }
 };
@@ -94,7 +95,7 @@ cc_status finish_sv(StaticArgs& a) {
   for (int round = 0;; ++round) {
     if (round >= kRoundCap) return fail(CC_ELIVELOCK, "Shiloach-Vishkin exceeded %d rounds", kRoundCap);
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->changed, 0u);
-    visit_candidates(a.s, a.n, a.cand, a.big, sc, (const I*)a.off, a.adj, SvHook{a.P, prev}, &sc->changed);
+    visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, SvHook{a.P, prev}, &sc->changed);
     hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, prev, (uint32_t*)nullptr);
     CC_LAUNCH_CHECK();
     ++a.finish_rounds;
@@ -200,8 +201,7 @@ static cc_status lt_rounds(StaticArgs& a) {
     ev = (int32_t*)(a.ws + a.L.edges + align256((size_t)a.m * 4));
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, (uint32_t*)ecnt, 0u);
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, (uint32_t*)ecnt + 1, 0u);
-    visit_candidates(a.s, a.n, a.cand, a.big, sc, (const I*)a.off, a.adj, EmitEdge{eu, ev, ecnt},
-                     (uint32_t*)nullptr);
+    visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, EmitEdge{eu, ev, ecnt}, (uint32_t*)nullptr);
   }
   for (int round = 0;; ++round) {
     if (round >= kRoundCap) return fail(CC_ELIVELOCK, "Liu-Tarjan exceeded %d rounds", kRoundCap);
@@ -212,7 +212,7 @@ static cc_status lt_rounds(StaticArgs& a) {
       hipLaunchKernelGGL(k_lt_connect_list<PARENT>, dim3(grid_for(a.m, kFBlock, 8192)), dim3(kFBlock), 0, a.s,
                          (const int32_t*)eu, (const int32_t*)ev, (const unsigned long long*)ecnt, op, &sc->changed);
     } else {
-      visit_candidates(a.s, a.n, a.cand, a.big, sc, (const I*)a.off, a.adj, op, &sc->changed);
+      visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, op, &sc->changed);
     }
     if (full) hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, (int32_t*)nullptr,
                                  &sc->changed);

@@ -50,6 +50,7 @@ __global__ void k_bfs_level_reset(uint32_t* fn, int64_t words, DevScalars* sc, i
   if (i == 0) {
     sc->qcount[nxt] = 0;
     sc->frontier_edges = 0;
+    sc->hcount = 0;
   }
   for (; i < words; i += stride) fn[i] = 0u;
 }
@@ -58,18 +59,23 @@ __global__ void k_bfs_level_reset(uint32_t* fn, int64_t words, DevScalars* sc, i
 // wave are walked by the whole wave (lanes take consecutive entries).
 template <typename I>
 __global__ void k_bfs_td(const int32_t* __restrict__ qin, const uint32_t* cnt_in, int32_t* qout, uint32_t* cnt_out,
-                         const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn) {
+                         const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
+                         int32_t* heavy, int32_t* hcount) {
   const int64_t cnt = *cnt_in;
   const int lane = lane_id();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < cnt; base += stride) {
     const int64_t idx = base + threadIdx.x;
     int64_t b = 0, e = 0;
+    int32_t u = 0;
     if (idx < cnt) {
-      const int32_t u = qin[idx];
+      u = qin[idx];
       b = (int64_t)off[u];
       e = (int64_t)off[u + 1];
     }
+    const bool heavy_row = (e - b) > kHeavyFrontier;
+    wave_append(heavy_row, u, heavy, (uint32_t*)hcount);
+    if (heavy_row) e = b;  // the grid kernel walks this row
     const bool big = (e - b) > kWave;
     uint64_t bm = __ballot(big);
     while (bm) {
@@ -122,6 +128,60 @@ __global__ void k_bfs_bu(int64_t n, const I* __restrict__ off, const int32_t* __
     }
     wave_append(found, (int32_t)v, qout, cnt_out);
   }
+}
+
+// Rows of heavy frontier vertices, spread evenly over the whole grid.
+template <typename I>
+__global__ void k_bfs_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount, const long long* __restrict__ hp,
+                            const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
+                            int32_t* qout, uint32_t* cnt_out) {
+  const int64_t c = *hcount;
+  if (c == 0) return;
+  const long long T = hp[c];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
+    const long long e = base + threadIdx.x;
+    bool got = false;
+    int32_t w = 0;
+    const long long e0 = base + (threadIdx.x / kWave) * kWave;
+    if (e < T) {
+      const int64_t i = heavy_owner_tile(hp, c, e0, e);
+      const int32_t u = heavy[i];
+      w = adj[(int64_t)off[u] + (e - hp[i])];
+      got = bit_claim(vis, w);
+      if (got) aor(fn + (w >> 5), 1u << (w & 31));
+    }
+    wave_append(got, w, qout, cnt_out);
+  }
+}
+
+template <typename I>
+__global__ void k_ldd_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount, const long long* __restrict__ hp,
+                            const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis, int32_t* P,
+                            int32_t* qout, uint32_t* cnt_out) {
+  const int64_t c = *hcount;
+  if (c == 0) return;
+  const long long T = hp[c];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
+    const long long e = base + threadIdx.x;
+    bool got = false;
+    int32_t w = 0;
+    const long long e0 = base + (threadIdx.x / kWave) * kWave;
+    if (e < T) {
+      const int64_t i = heavy_owner_tile(hp, c, e0, e);
+      const int32_t u = heavy[i];
+      w = adj[(int64_t)off[u] + (e - hp[i])];
+      got = bit_claim(vis, w);
+      if (got) P[w] = P[u];
+    }
+    wave_append(got, w, qout, cnt_out);
+  }
+}
+
+__global__ void k_round_reset(DevScalars* sc, int nxt) {
+  sc->qcount[nxt] = 0;
+  sc->hcount = 0;
 }
 
 template <typename I>
@@ -200,7 +260,11 @@ cc_status sample_bfs(StaticArgs& a) {
                          sc, nxt);
       if (top_down) {
         hipLaunchKernelGGL(k_bfs_td<I>, dim3(grid_for(nf, kFBlock, 8192)), dim3(kFBlock), 0, a.s, q[cur],
-                           &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, fn);
+                           &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, fn, a.heavy, &sc->hcount);
+        heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&sc->hcount, a.hcap, off, a.tsum, a.hp);
+        hipLaunchKernelGGL(k_bfs_heavy<I>, dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
+                           (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, fn, q[nxt],
+                           &sc->qcount[nxt]);
       } else {
         hipLaunchKernelGGL(k_bfs_bu<I>, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, off, a.adj, vis,
                            fc, fn, q[nxt], &sc->qcount[nxt]);
@@ -293,20 +357,23 @@ __global__ void k_ldd_wake(int64_t lo, int64_t hi, uint32_t* vis, int32_t* P, in
 template <typename I>
 __global__ void k_ldd_expand(const int32_t* __restrict__ qin, const uint32_t* cnt_in, int32_t* qout,
                              uint32_t* cnt_out, const I* __restrict__ off, const int32_t* __restrict__ adj,
-                             uint32_t* vis, int32_t* P) {
+                             uint32_t* vis, int32_t* P, int32_t* heavy, int32_t* hcount) {
   const int64_t cnt = *cnt_in;
   const int lane = lane_id();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < cnt; base += stride) {
     const int64_t idx = base + threadIdx.x;
     int64_t b = 0, e = 0;
-    int32_t c = 0;
+    int32_t c = 0, u = 0;
     if (idx < cnt) {
-      const int32_t u = qin[idx];
+      u = qin[idx];
       b = (int64_t)off[u];
       e = (int64_t)off[u + 1];
       c = P[u];
     }
+    const bool heavy_row = (e - b) > kHeavyFrontier;
+    wave_append(heavy_row, u, heavy, (uint32_t*)hcount);
+    if (heavy_row) e = b;  // the grid kernel walks this row
     const bool big = (e - b) > kWave;
     uint64_t bm = __ballot(big);
     while (bm) {
@@ -389,9 +456,13 @@ cc_status sample_ldd(StaticArgs& a) {
                          q[cur], &sc->qcount[cur]);
     lo = hi;
     const int nxt = cur ^ 1;
-    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->qcount[nxt], 0u);
+    hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, a.s, sc, nxt);
     hipLaunchKernelGGL(k_ldd_expand<I>, dim3(grid_for(n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, q[cur],
-                       &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, a.P);
+                       &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, a.P, a.heavy, &sc->hcount);
+    heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&sc->hcount, a.hcap, off, a.tsum, a.hp);
+    hipLaunchKernelGGL(k_ldd_heavy<I>, dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
+                       (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, a.P, q[nxt],
+                       &sc->qcount[nxt]);
     CC_LAUNCH_CHECK();
     cur = nxt;
     ++a.sample_rounds;

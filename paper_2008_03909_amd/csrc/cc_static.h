@@ -1,5 +1,6 @@
 // Shared host-side state of one static connectivity call.
 #pragma once
+#include "cc_frontier.h"
 #include "cc_internal.h"
 
 namespace cc {
@@ -18,10 +19,15 @@ struct StaticArgs {
   int32_t* count = nullptr;  // n int32 scratch (frequency counts, snapshots)
   int32_t* cand = nullptr;   // thread-bin candidates (also LDD min-member scratch)
   int32_t* big = nullptr;    // wave-bin (front) / block-bin (back) candidates
+  int32_t* heavy = nullptr;  // grid-bin candidates / heavy frontier vertices
+  long long* hp = nullptr;   // degree prefix of `heavy`
+  long long* tsum = nullptr; // tile sums of that prefix
+  int64_t hcap = 0;          // capacity of `heavy`
   int64_t* ncomp_user = nullptr;
   int32_t sample_success = 1;
   int32_t sample_rounds = 0;
   int32_t finish_rounds = 0;
+  CandLists lists() const { return CandLists{n, cand, big, heavy, hp, ctx->dev}; }
 };
 
 template <typename I> cc_status sample_bfs(StaticArgs& a);

@@ -21,6 +21,7 @@
 #include <cstring>
 
 #include "cc_device.h"
+#include "cc_frontier.h"
 #include "cc_internal.h"
 #include "cc_static.h"
 
@@ -154,7 +155,11 @@ WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v) {
   }
   if (v->sample == CC_SAMPLE_LDD) L.hist = off, off += align256(4096 * 4);
   if (v->finish == CC_FIN_LT && (v->lt_rules & CC_LT_ALTER)) L.edges = off, off += 2 * align256((size_t)m * 4);
-  L.seg = off, off += align256((size_t)kSegMaxHost * 12) + align256((size_t)kSegMaxHost * 8);
+  L.seg = off, off += align256((size_t)kSegMaxHost * 16) + align256((size_t)kSegMaxHost * 8);
+  {
+    const size_t hcap = heavy_cap(m);  // vertices with degree above the frontier threshold
+    L.heavy = off, off += align256(hcap * 4) + align256((hcap + 1) * 8) + align256((hcap / kHpTile + 3) * 8);
+  }
   L.total = off + 256;
   return L;
 }
@@ -282,17 +287,20 @@ __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict_
 // with at least one edge are counted (an isolated vertex is a class of its
 // own and cannot be the unique most frequent one; if every class is a
 // singleton, skipping nothing is equivalent).  Counting is aggregated twice:
-// lanes of a wave with the leader's label add once, and the block keeps the
-// count of one "hot" label (the first leader label it meets) in LDS, so the
-// giant component costs one global atomic per block.
+// each wave peels its lanes into runs of equal labels (one add per run), and
+// the block keeps the counts of up to kHotSlots labels in an LDS table
+// (direct-mapped by label), so a few giant classes cost one global atomic
+// per block each instead of one per vertex.
+constexpr int kHotSlots = 32;
+
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_compress_count(int64_t n, const I* __restrict__ off, int32_t* P,
                                                            int32_t* __restrict__ count, int aligned) {
-  __shared__ int32_t hot;
-  __shared__ int32_t hot_cnt;
-  if (threadIdx.x == 0) {
-    hot = -1;
-    hot_cnt = 0;
+  __shared__ int32_t hot_label[kHotSlots];
+  __shared__ int32_t hot_cnt[kHotSlots];
+  if (threadIdx.x < kHotSlots) {
+    hot_label[threadIdx.x] = -1;
+    hot_cnt[threadIdx.x] = 0;
   }
   __syncthreads();
   const int lane = lane_id();
@@ -321,28 +329,33 @@ __global__ void __launch_bounds__(kBlock) k_compress_count(int64_t n, const I* _
     if (!count) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const bool c = act && v0 + j < n && o[j + 1] > o[j];
-      const uint64_t mact = __ballot(c);
-      if (mact == 0) continue;
-      const int leader = __ffsll((unsigned long long)mact) - 1;
-      const int32_t lead = __shfl(r[j], leader, kWave);
-      const uint64_t same = __ballot(c && r[j] == lead);
-      if (lane == leader) {
-        int32_t h = hot;
-        if (h == -1) {
-          atomicCAS(&hot, -1, lead);
-          h = hot;
+      bool c = act && v0 + j < n && o[j + 1] > o[j];
+      uint64_t mact = __ballot(c);
+      while (mact) {
+        const int leader = __ffsll((unsigned long long)mact) - 1;
+        const int32_t lead = __shfl(r[j], leader, kWave);
+        const uint64_t same = __ballot(c && r[j] == lead);
+        if (lane == leader) {
+          const int32_t add = (int32_t)__popcll(same);
+          const int slot = (int)((uint32_t)lead % kHotSlots);
+          int32_t h = hot_label[slot];
+          if (h == -1) {
+            atomicCAS(&hot_label[slot], -1, lead);
+            h = hot_label[slot];
+          }
+          if (h == lead) atomicAdd(&hot_cnt[slot], add);
+          else __hip_atomic_fetch_add(count + lead, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (h == lead) atomicAdd(&hot_cnt, (int32_t)__popcll(same));
-        else __hip_atomic_fetch_add(count + lead, (int32_t)__popcll(same), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (r[j] == lead) c = false;
+        mact &= ~same;
       }
-      if (c && r[j] != lead) __hip_atomic_fetch_add(count + r[j], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   if (!count) return;
   __syncthreads();
-  if (threadIdx.x == 0 && hot_cnt > 0)
-    __hip_atomic_fetch_add(count + hot, hot_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < kHotSlots && hot_cnt[threadIdx.x] > 0)
+    __hip_atomic_fetch_add(count + hot_label[threadIdx.x], hot_cnt[threadIdx.x], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
@@ -393,19 +406,19 @@ __global__ void k_resolve_lmax(DevScalars* sc, int use) {
 // Candidate compaction with degree binning, in three launches and without
 // contended atomics.  Wave w owns the vertex range [w*S, min((w+1)*S, n)) and
 // the same range of the scratch array: thread-bin candidates (degree <=
-// thr_wave) fill it from the front, larger ones from the back (block-bin ones, degree >
-// thr_block, stored as ~v).  A one-block scan turns the per-wave counts into
-// list offsets, and a gather copies every segment into the final lists:
-// cand (thread bin), big front (wave bin), big back (block bin).  The lists
-// are in a fixed order, so the finish sees the same work every run.
+// kThrWave) fill it from the front, all others from the back.  A one-block
+// scan turns the per-wave counts of the four bins into list offsets, and a
+// gather copies every segment into the final lists (thread bin: cand; wave
+// bin: big front; block bin: big back; grid bin: heavy), classifying the
+// back entries by degree.  The lists come out in a fixed order, so the finish
+// does the same work every run.
 constexpr int kSegMax = 8448;  // upper bound on the number of segments
 
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, const I* __restrict__ off,
                                                         const int32_t* __restrict__ P, const DevScalars* sc,
                                                         int32_t* __restrict__ scratch, int32_t* __restrict__ segcnt,
-                                                        long long* __restrict__ segedges, int thr_wave,
-                                                        int thr_block, int aligned) {
+                                                        long long* __restrict__ segedges, int aligned) {
   const int32_t L = sc->lmax;
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt_dev();
@@ -414,7 +427,7 @@ __global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, co
   for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; w < nseg; w += waves) {
     const int64_t lo = w * S;
     const int64_t hi = (lo + S < n) ? lo + S : n;
-    int32_t c0 = 0, cb = 0, c2 = 0;
+    int32_t c0 = 0, cb = 0, c2 = 0, c3 = 0;
     long long edges = 0;
     for (int64_t base = lo; base < hi; base += 4 * kWave) {
       const int64_t v0 = base + 4 * lane;
@@ -432,49 +445,48 @@ __global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, co
         const int64_t deg = inb ? o[j + 1] - o[j] : 0;
         const bool isc = inb && deg > 0 && p[j] != L;
         if (isc) edges += deg;
-        const bool small = isc && deg <= thr_wave;
-        const bool large = isc && deg > thr_wave;
-        const bool huge = large && deg > thr_block;
+        const bool small = isc && deg <= kThrWave;
+        const bool large = isc && deg > kThrWave;
         const uint64_t ms = __ballot(small);
         const uint64_t ml = __ballot(large);
         if (small) scratch[lo + c0 + __popcll(ms & lt)] = (int32_t)(v0 + j);
-        if (large) scratch[hi - 1 - (cb + __popcll(ml & lt))] = huge ? ~(int32_t)(v0 + j) : (int32_t)(v0 + j);
+        if (large) scratch[hi - 1 - (cb + __popcll(ml & lt))] = (int32_t)(v0 + j);
         c0 += __popcll(ms);
         cb += __popcll(ml);
-        c2 += __popcll(__ballot(huge));
+        c2 += __popcll(__ballot(large && deg > kThrBlock && deg <= kThrGrid));
+        c3 += __popcll(__ballot(large && deg > kThrGrid));
       }
     }
     edges = wave_sum(edges);
     if (lane == 0) {
-      segcnt[3 * w + 0] = c0;
-      segcnt[3 * w + 1] = cb - c2;
-      segcnt[3 * w + 2] = c2;
+      segcnt[4 * w + 0] = c0;
+      segcnt[4 * w + 1] = cb - c2 - c3;
+      segcnt[4 * w + 2] = c2;
+      segcnt[4 * w + 3] = c3;
       segedges[w] = edges;
     }
   }
 }
 
-// One block: exclusive scan of the per-segment counts (three bins), totals
+// One block: exclusive scan of the per-segment counts (four bins), totals
 // into the context scalars.
 __global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* segcnt, const long long* segedges,
                                                        DevScalars* sc) {
-  __shared__ int32_t part[3][1024];
+  __shared__ int32_t part[4][1024];
   __shared__ long long epart[1024];
   const int t = threadIdx.x;
   const int64_t per = div_up_dev(nseg, 1024);
   const int64_t lo = t * per, hi = (lo + per < nseg) ? lo + per : nseg;
-  int32_t s0 = 0, s1 = 0, s2 = 0;
+  int32_t s[4] = {0, 0, 0, 0};
   long long e = 0;
   for (int64_t i = lo; i < hi; ++i) {
-    s0 += segcnt[3 * i];
-    s1 += segcnt[3 * i + 1];
-    s2 += segcnt[3 * i + 2];
+    for (int q = 0; q < 4; ++q) s[q] += segcnt[4 * i + q];
     e += segedges[i];
   }
-  part[0][t] = s0, part[1][t] = s1, part[2][t] = s2;
+  for (int q = 0; q < 4; ++q) part[q][t] = s[q];
   epart[t] = e;
   __syncthreads();
-  if (t < 3) {  // serial exclusive scan of 1024 partials per bin
+  if (t < 4) {  // serial exclusive scan of the 1024 partials of one bin
     int32_t run = 0;
     for (int i = 0; i < 1024; ++i) {
       const int32_t x = part[t][i];
@@ -482,92 +494,76 @@ __global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* se
       run += x;
     }
     sc->bin_count[t] = run;
-  } else if (t == 3) {
+  } else if (t == 4) {
     long long tot = 0;
     for (int i = 0; i < 1024; ++i) tot += epart[i];
     sc->cand_edges = tot;
   }
   __syncthreads();
-  int32_t r0 = part[0][t], r1 = part[1][t], r2 = part[2][t];
-  for (int64_t i = lo; i < hi; ++i) {
-    const int32_t x0 = segcnt[3 * i], x1 = segcnt[3 * i + 1], x2 = segcnt[3 * i + 2];
-    segcnt[3 * i] = r0, segcnt[3 * i + 1] = r1, segcnt[3 * i + 2] = r2;
-    r0 += x0, r1 += x1, r2 += x2;
-  }
+  int32_t r[4];
+  for (int q = 0; q < 4; ++q) r[q] = part[q][t];
+  for (int64_t i = lo; i < hi; ++i)
+    for (int q = 0; q < 4; ++q) {
+      const int32_t x = segcnt[4 * i + q];
+      segcnt[4 * i + q] = r[q];
+      r[q] += x;
+    }
 }
 
-__global__ void __launch_bounds__(kBlock) k_compact_gather(int64_t n, int64_t S, const int32_t* __restrict__ scratch,
+template <typename I>
+__global__ void __launch_bounds__(kBlock) k_compact_gather(int64_t n, int64_t S, const I* __restrict__ off,
+                                                           const int32_t* __restrict__ scratch,
                                                            const int32_t* __restrict__ segoff,
-                                                           const int32_t* __restrict__ segcnt_unused,
                                                            int32_t* __restrict__ cand, int32_t* __restrict__ big,
-                                                           const DevScalars* sc) {
-  (void)segcnt_unused;
+                                                           int32_t* __restrict__ heavy, const DevScalars* sc) {
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt_dev();
   const int64_t nseg = div_up_dev(n, S);
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  const int32_t tot0 = sc->bin_count[0], tot1 = sc->bin_count[1], tot2 = sc->bin_count[2];
+  int32_t tot[4];
+  for (int q = 0; q < 4; ++q) tot[q] = sc->bin_count[q];
   for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; w < nseg; w += waves) {
     const int64_t lo = w * S;
     const int64_t hi = (lo + S < n) ? lo + S : n;
-    const int32_t o0 = segoff[3 * w], o1 = segoff[3 * w + 1], o2 = segoff[3 * w + 2];
-    // segment counts = next segment's offset (or the total) minus this one's
-    const int32_t e0 = (w + 1 < nseg) ? segoff[3 * (w + 1)] : tot0;
-    const int32_t e1 = (w + 1 < nseg) ? segoff[3 * (w + 1) + 1] : tot1;
-    const int32_t e2 = (w + 1 < nseg) ? segoff[3 * (w + 1) + 2] : tot2;
-    const int32_t c0 = e0 - o0, cb = (e1 - o1) + (e2 - o2);
-    for (int32_t i = lane; i < c0; i += kWave) cand[o0 + i] = scratch[lo + i];
-    int32_t r1 = o1, r2 = o2;
+    int32_t o[4], c[4];
+    for (int q = 0; q < 4; ++q) {
+      o[q] = segoff[4 * w + q];
+      c[q] = ((w + 1 < nseg) ? segoff[4 * (w + 1) + q] : tot[q]) - o[q];
+    }
+    for (int32_t i = lane; i < c[0]; i += kWave) cand[o[0] + i] = scratch[lo + i];
+    const int32_t cb = c[1] + c[2] + c[3];
+    int32_t r1 = o[1], r2 = o[2], r3 = o[3];
     for (int32_t i0 = 0; i0 < cb; i0 += kWave) {
       const int32_t i = i0 + lane;
-      const int32_t x = (i < cb) ? scratch[hi - 1 - i] : 0;
-      const bool b1 = i < cb && x >= 0;
-      const bool b2 = i < cb && x < 0;
-      const uint64_t m1 = __ballot(b1), m2 = __ballot(b2);
+      int32_t x = 0;
+      int64_t deg = 0;
+      if (i < cb) {
+        x = scratch[hi - 1 - i];
+        deg = (int64_t)off[x + 1] - (int64_t)off[x];
+      }
+      const bool b1 = i < cb && deg <= kThrBlock;
+      const bool b2 = i < cb && deg > kThrBlock && deg <= kThrGrid;
+      const bool b3 = i < cb && deg > kThrGrid;
+      const uint64_t m1 = __ballot(b1), m2 = __ballot(b2), m3 = __ballot(b3);
       if (b1) big[r1 + __popcll(m1 & lt)] = x;
-      if (b2) big[n - 1 - (r2 + __popcll(m2 & lt))] = ~x;
+      if (b2) big[n - 1 - (r2 + __popcll(m2 & lt))] = x;
+      if (b3) heavy[r3 + __popcll(m3 & lt)] = x;
       r1 += __popcll(m1);
       r2 += __popcll(m2);
+      r3 += __popcll(m3);
     }
   }
 }
 
-// Union-find finish: thread / wave / block per candidate.
-template <int ALG, int SPLICE, int FIND, typename I>
-__global__ void k_fin_thread(const int32_t* __restrict__ cand, const DevScalars* sc, const I* __restrict__ off,
-                             const int32_t* __restrict__ adj, int32_t* P) {
-  const int64_t cnt = sc->bin_count[0];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
-    const int32_t u = cand[i];
-    const int64_t e = (int64_t)off[u + 1];
-    for (int64_t j = (int64_t)off[u]; j < e; ++j) unite<ALG, SPLICE, FIND>(P, u, adj[j]);
+// Union-find finish operator: Union(u, w) with the variant's rules.
+template <int ALG, int SPLICE, int FIND>
+struct UnionOp {
+  int32_t* P;
+  __device__ __forceinline__ bool operator()(int32_t u, int32_t w) const {
+    unite<ALG, SPLICE, FIND>(P, u, w);
+    return false;
   }
-}
-
-template <int ALG, int SPLICE, int FIND, typename I>
-__global__ void k_fin_wave(const int32_t* __restrict__ big, const DevScalars* sc, const I* __restrict__ off,
-                           const int32_t* __restrict__ adj, int32_t* P) {
-  const int64_t cnt = sc->bin_count[1];
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  const int lane = lane_id();
-  for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < cnt; i += waves) {
-    const int32_t u = big[i];
-    const int64_t e = (int64_t)off[u + 1];
-    for (int64_t j = (int64_t)off[u] + lane; j < e; j += kWave) unite<ALG, SPLICE, FIND>(P, u, adj[j]);
-  }
-}
-
-template <int ALG, int SPLICE, int FIND, typename I>
-__global__ void k_fin_block(int64_t n, const int32_t* __restrict__ big, const DevScalars* sc,
-                            const I* __restrict__ off, const int32_t* __restrict__ adj, int32_t* P) {
-  const int64_t cnt = sc->bin_count[2];
-  for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-    const int32_t u = big[n - 1 - i];
-    const int64_t e = (int64_t)off[u + 1];
-    for (int64_t j = (int64_t)off[u] + threadIdx.x; j < e; j += blockDim.x) unite<ALG, SPLICE, FIND>(P, u, adj[j]);
-  }
-}
+};
 
 // Final compression and component count: label = root (the component's
 // minimum, since every link points to a smaller id).
@@ -608,20 +604,9 @@ __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, DevSca
 // ---------------------------------------------------------------------------
 // host orchestration
 
-constexpr int kThrWave = 32;     // degree <= 32: one thread per candidate
-constexpr int kThrBlock = 8192;  // degree <= 8192: one wave; larger: one block
-
 template <int ALG, int SPLICE, int FIND, typename I>
 static cc_status launch_uf_finish(StaticArgs& a) {
-  const I* off = (const I*)a.off;
-  const unsigned gt = grid_for(a.n, kBlock, kStreamGridCap);
-  hipLaunchKernelGGL((k_fin_thread<ALG, SPLICE, FIND, I>), dim3(gt), dim3(kBlock), 0, a.s, a.cand, a.ctx->dev, off,
-                     a.adj, a.P);
-  const unsigned gw = grid_for(a.n * kWave, kBlock, 2048);
-  hipLaunchKernelGGL((k_fin_wave<ALG, SPLICE, FIND, I>), dim3(gw), dim3(kBlock), 0, a.s, a.big, a.ctx->dev, off,
-                     a.adj, a.P);
-  hipLaunchKernelGGL((k_fin_block<ALG, SPLICE, FIND, I>), dim3(1024), dim3(kBlock), 0, a.s, a.n, a.big, a.ctx->dev,
-                     off, a.adj, a.P);
+  visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, UnionOp<ALG, SPLICE, FIND>{a.P}, (uint32_t*)nullptr);
   CC_LAUNCH_CHECK();
   return CC_OK;
 }
@@ -727,16 +712,17 @@ static cc_status run_static(StaticArgs& a, bool sample_only) {
     int64_t S = div_up(div_up(a.n, 8192), 256) * 256;
     const int64_t nseg = div_up(a.n, S);
     int32_t* segcnt = (int32_t*)(a.ws + a.L.seg);
-    long long* segedges = (long long*)(a.ws + a.L.seg + align256((size_t)kSegMax * 12));
+    long long* segedges = (long long*)(a.ws + a.L.seg + align256((size_t)kSegMax * 16));
     const unsigned gw = grid_for(nseg * kWave, kBlock, 2048);
     hipLaunchKernelGGL(k_compact_seg<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
-                       (const int32_t*)a.P, (const DevScalars*)a.ctx->dev, a.count, segcnt, segedges, kThrWave,
-                       kThrBlock, vec_ok(a));
+                       (const int32_t*)a.P, (const DevScalars*)a.ctx->dev, a.count, segcnt, segedges, vec_ok(a));
     hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, a.s, nseg, segcnt, (const long long*)segedges,
                        a.ctx->dev);
-    hipLaunchKernelGGL(k_compact_gather, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const int32_t*)a.count,
-                       (const int32_t*)segcnt, (const int32_t*)nullptr, a.cand, a.big,
+    hipLaunchKernelGGL(k_compact_gather<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
+                       (const int32_t*)a.count, (const int32_t*)segcnt, a.cand, a.big, a.heavy,
                        (const DevScalars*)a.ctx->dev);
+    heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&a.ctx->dev->bin_count[3], a.hcap, (const I*)a.off, a.tsum,
+                    a.hp);
     CC_LAUNCH_CHECK();
   }
   a.finish_rounds = 0;
@@ -784,6 +770,10 @@ static cc_status setup_args(StaticArgs& a, cc_ctx* ctx, int64_t n, int64_t m, co
   a.count = (int32_t*)(w + L.count);
   a.cand = (int32_t*)(w + L.cand);
   a.big = (int32_t*)(w + L.big);
+  a.heavy = (int32_t*)(w + L.heavy);
+  a.hp = (long long*)(w + L.heavy + align256(heavy_cap(m) * 4));
+  a.tsum = (long long*)(w + L.heavy + align256(heavy_cap(m) * 4) + align256((heavy_cap(m) + 1) * 8));
+  a.hcap = (int64_t)heavy_cap(m);
   a.ncomp_user = ncomp;
   return CC_OK;
 }

@@ -54,6 +54,13 @@ def _suite():
     hub = np.zeros(20000, np.int32)
     leaves = np.arange(1, 20001, dtype=np.int32)
     gs.append(inputs.Graph(25000, hub, leaves, "hub20000"))
+    # two hubs above the grid-bin threshold joined through a path, plus a star of 5000
+    h1 = np.full(40000, 7, np.int32)
+    l1 = np.arange(100, 40100, dtype=np.int32)
+    h2 = np.full(36000, 90000, np.int32)
+    l2 = np.arange(40100, 76100, dtype=np.int32)
+    gs.append(inputs.Graph(100000, np.concatenate([h1, h2, [40099]]).astype(np.int32),
+                           np.concatenate([l1, l2, [40100]]).astype(np.int32), "two-heavy-hubs"))
     # self-loops and duplicates
     u = np.array([0, 0, 1, 1, 2, 3, 3, 5], np.int32)
     v = np.array([0, 1, 0, 1, 2, 4, 4, 5], np.int32)
