@@ -197,6 +197,75 @@ def incremental(ctx, g, seed: int = 5, max_pairs: int | None = None):
     }
 
 
+def serving(ctx, g, capacity_pairs_per_s: float | None = None, loads=(0.0, 0.5, 0.9), requests: int = 300,
+            seed: int = 5):
+    """Poisson arrivals through the serving loop (continuous batching): insert
+    requests of log-uniform size in [1e3, 1e7] pairs (the workload's pairs,
+    shuffled) and query requests in [1e3, 1e6] random pairs, 50/50, at an
+    offered load given as a fraction of a capacity (pairs/s).  Payloads live
+    in pinned host memory and cross PCIe inside the measured latency.  Load
+    0.0 means every request arrives at once (closed loop); its throughput is
+    the capacity the other loads are scaled to."""
+    import numpy as np
+
+    from paper_2008_03909_amd import binding as b
+    from paper_2008_03909_amd import inputs
+
+    su, sv = inputs.shuffle_pairs(g.u, g.v, seed)
+    res = []
+    for li, load in enumerate(loads):
+        rng = np.random.default_rng(seed + li)
+        types, starts, lens, A, B = [], [], [], [], []
+        pe, pos = 0, 0
+        for i in range(requests):
+            t = int(rng.random() < 0.5)
+            if t == 0 and pe < su.size:
+                k = min(inputs.log_uniform_int(1e3, 1e7, rng.random()), su.size - pe)
+                A.append(su[pe:pe + k])
+                B.append(sv[pe:pe + k])
+                pe += k
+            else:
+                t = 1
+                k = inputs.log_uniform_int(1e3, 1e6, rng.random())
+                qa, qb = inputs.query_pairs(g.n, k, seed=seed * 7919 + 31 * li + i)
+                A.append(qa)
+                B.append(qb)
+            types.append(t)
+            starts.append(pos)
+            lens.append(k)
+            pos += k
+        lens_a = np.array(lens, np.float64)
+        if load <= 0.0:
+            arrivals = np.zeros(len(types))
+        else:
+            rate = load * capacity_pairs_per_s / lens_a.mean()      # requests per second
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, len(types)))
+        # request payloads and answers in pinned host memory (zero-copy DMA)
+        import torch
+        pa = torch.from_numpy(np.concatenate(A).astype(np.int32)).pin_memory()
+        pb = torch.from_numpy(np.concatenate(B).astype(np.int32)).pin_memory()
+        po = torch.zeros(pa.numel(), dtype=torch.uint8).pin_memory()
+        srv = b.Server(ctx, g.n, budget_bytes=2 << 30, num_streams=4, max_inflight=64)
+        t0 = time.perf_counter()
+        _, lat = srv.run_trace(np.array(types), arrivals, np.array(starts), np.array(lens),
+                               pa.numpy(), pb.numpy(), po.numpy())
+        wall = time.perf_counter() - t0
+        srv.close()
+        ty = np.array(types)
+        ins_pairs = float(lens_a[ty == 0].sum())
+        if load <= 0.0:
+            capacity_pairs_per_s = float(lens_a.sum()) / wall
+        res.append({
+            "offered_load": load, "requests": len(types), "inserted_pairs": int(ins_pairs),
+            "queried_pairs": int(lens_a[ty == 1].sum()), "wall_s": round(wall, 4),
+            "updates_per_s": ins_pairs / wall, "pairs_per_s": float(lens_a.sum()) / wall,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "insert_p50_ms": float(np.percentile(lat[ty == 0], 50) * 1e3) if np.any(ty == 0) else None,
+            "query_p50_ms": float(np.percentile(lat[ty == 1], 50) * 1e3) if np.any(ty == 1) else None,
+        })
+    return res
+
+
 def _time_ms(fn, reps: int = 10) -> float:
     import torch
 
@@ -423,6 +492,11 @@ def main():
         out["incremental"] = incremental(ctx, g)
         log(f"incremental: {out['incremental']['updates_per_s']:.3e} updates/s, "
             f"p50 {out['incremental']['p50_ms']:.3f} ms, p99 {out['incremental']['p99_ms']:.3f} ms")
+        log("serving loop (Poisson arrivals) ...")
+        out["serving"] = serving(ctx, g)
+        for r in out["serving"]:
+            log(f"serving load {r['offered_load']}: {r['pairs_per_s']:.3e} pairs/s, p50 {r['p50_ms']:.3f} ms, "
+                f"p99 {r['p99_ms']:.3f} ms")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, m)

@@ -204,6 +204,46 @@ cc_status cc_stream_labels(cc_stream* s, int32_t* labels_out, int64_t* num_compo
 /* Synchronises and reports (then clears) the stream's device error word. */
 cc_status cc_stream_sync_status(cc_stream* s);
 
+/* ---- serving loop (continuous batching over one stream state) -----------------
+ * A cc_server owns a cc_stream (created from v; NULL = UF-Async + FindNaive),
+ * a device request pool of budget_bytes, num_streams HIP streams (1..16) and
+ * at most max_inflight requests on the device.  Requests are admitted in arrival order when their bytes
+ * (8 per pair, plus 1 per query pair) fit in the pool; consecutive requests
+ * of one type run concurrently, and a change between inserts and queries is
+ * ordered by a barrier event, so every query answers against exactly the
+ * inserts that arrived before it (the batch-incremental semantics of the
+ * streaming appendix, arrival order = batch order).  Single host thread.
+ * Zero copy: the server DMAs from the caller's host arrays and writes query
+ * answers (0/1 bytes) straight into out, so every array must stay valid and
+ * unmodified until its request completes (pinned memory, e.g. hipHostMalloc,
+ * makes the transfers asynchronous).  A request larger than the
+ * budget returns CC_EBUSY.  Times are seconds on the server's steady clock
+ * (cc_server_clock); arrival < 0 means "now". */
+typedef struct cc_server cc_server;
+cc_status cc_server_create(cc_ctx* ctx, int64_t n, const cc_variant* v, int64_t budget_bytes, int num_streams,
+                           int max_inflight, cc_server** out);
+void cc_server_destroy(cc_server* s);
+double cc_server_clock(cc_server* s);
+cc_status cc_server_submit_insert(cc_server* s, int64_t k, const int32_t* u_host, const int32_t* v_host,
+                                  double arrival, int64_t* id);
+cc_status cc_server_submit_query(cc_server* s, int64_t q, const int32_t* a_host, const int32_t* b_host,
+                                 uint8_t* out_host, double arrival, int64_t* id);
+/* Retires finished requests and admits pending ones; wait_all != 0 blocks
+ * until every submitted request has completed. */
+cc_status cc_server_poll(cc_server* s, int wait_all);
+/* Replays a trace in real time: request i (type 0 insert / 1 query) arrives
+ * arrival_s[i] seconds after the call and carries pairs [start[i],
+ * start[i]+len[i]) of a/b (host arrays); query answers go to out at the same
+ * positions; latency_s[i] = completion - arrival.  Returns after all finish. */
+cc_status cc_server_run_trace(cc_server* s, int64_t count, const int32_t* type, const double* arrival_s,
+                              const int64_t* start, const int64_t* len, const int32_t* a, const int32_t* b,
+                              uint8_t* out, double* latency_s);
+cc_status cc_server_request_info(cc_server* s, int64_t id, int* done, double* latency_s);
+/* Labels of the state after every submitted request (waits for all). */
+cc_status cc_server_labels(cc_server* s, int32_t* labels_out, int64_t* num_components_dev, void* hip_stream);
+/* Bytes of the device pool currently held by admitted requests. */
+int64_t cc_server_pool_used(cc_server* s);
+
 /* ---- calibration (measurement aids) ------------------------------------------
  * Roofline anchors for the kernels above; they compute nothing the method
  * needs.  cc_calib_copy: dst = src for `bytes` bytes (both 16-byte aligned,

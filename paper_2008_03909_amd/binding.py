@@ -124,6 +124,16 @@ def lib():
             "cc_query_batch": (_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
             "cc_stream_labels": (_int, [_vp, _vp, _vp, _vp]),
             "cc_stream_sync_status": (_int, [_vp]),
+            "cc_server_create": (_int, [_vp, _i64, ctypes.POINTER(cc_variant), _i64, _int, _int, ctypes.POINTER(_vp)]),
+            "cc_server_destroy": (None, [_vp]),
+            "cc_server_clock": (ctypes.c_double, [_vp]),
+            "cc_server_submit_insert": (_int, [_vp, _i64, _vp, _vp, ctypes.c_double, ctypes.POINTER(_i64)]),
+            "cc_server_submit_query": (_int, [_vp, _i64, _vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(_i64)]),
+            "cc_server_poll": (_int, [_vp, _int]),
+            "cc_server_run_trace": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "cc_server_request_info": (_int, [_vp, _i64, ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]),
+            "cc_server_labels": (_int, [_vp, _vp, _vp, _vp]),
+            "cc_server_pool_used": (_i64, [_vp]),
             "cc_calib_copy": (_int, [_vp, _vp, ctypes.c_size_t, _vp]),
             "cc_calib_workspace_bytes": (_int, [_i64, ctypes.POINTER(ctypes.c_size_t)]),
             "cc_calib_edges": (_int, [_i64, _i64, _vp, _int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -351,6 +361,100 @@ class Stream:
 
     def sync_status(self):
         _check(lib().cc_stream_sync_status(self.h), "cc_stream_sync_status")
+
+
+# ---- serving loop --------------------------------------------------------------
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else ctypes.c_void_p(0)
+
+
+class Server:
+    """cc_server: continuous batching of insert/query requests (host arrays)."""
+
+    def __init__(self, ctx: Context, n: int, variant: cc_variant | None = None, budget_bytes: int = 1 << 30,
+                 num_streams: int = 4, max_inflight: int = 64):
+        self.ctx = ctx
+        self.n = n
+        self.h = ctypes.c_void_p()
+        vp = ctypes.byref(variant) if variant is not None else None
+        _check(lib().cc_server_create(ctx.h, n, vp, budget_bytes, num_streams, max_inflight, ctypes.byref(self.h)),
+               "cc_server_create")
+        self._keep = []
+
+    def close(self):
+        if self.h:
+            lib().cc_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clock(self) -> float:
+        return lib().cc_server_clock(self.h)
+
+    def insert(self, u, v, arrival: float = -1.0) -> int:
+        import numpy as np
+        u = np.ascontiguousarray(u, np.int32)
+        v = np.ascontiguousarray(v, np.int32)
+        self._keep += [u, v]          # the server reads them until the request completes
+        rid = ctypes.c_int64()
+        _check(lib().cc_server_submit_insert(self.h, u.size, _np_ptr(u), _np_ptr(v), arrival, ctypes.byref(rid)),
+               "cc_server_submit_insert")
+        return rid.value
+
+    def query(self, a, b, arrival: float = -1.0):
+        """Returns (request id, output array filled when the request completes)."""
+        import numpy as np
+        a = np.ascontiguousarray(a, np.int32)
+        b = np.ascontiguousarray(b, np.int32)
+        out = np.zeros(a.size, np.uint8)
+        self._keep += [a, b, out]
+        rid = ctypes.c_int64()
+        _check(lib().cc_server_submit_query(self.h, a.size, _np_ptr(a), _np_ptr(b), _np_ptr(out), arrival,
+                                            ctypes.byref(rid)), "cc_server_submit_query")
+        return rid.value, out
+
+    def poll(self, wait_all: bool = False):
+        _check(lib().cc_server_poll(self.h, int(wait_all)), "cc_server_poll")
+
+    def info(self, rid: int):
+        done = ctypes.c_int()
+        lat = ctypes.c_double()
+        _check(lib().cc_server_request_info(self.h, rid, ctypes.byref(done), ctypes.byref(lat)),
+               "cc_server_request_info")
+        return bool(done.value), lat.value
+
+    def run_trace(self, types, arrivals, starts, lens, a, b, out=None):
+        """Real-time replay; returns (query answers aligned with a/b, latencies).
+        a, b and out may be pinned (e.g. numpy views of pinned torch tensors)."""
+        import numpy as np
+        types = np.ascontiguousarray(types, np.int32)
+        arrivals = np.ascontiguousarray(arrivals, np.float64)
+        starts = np.ascontiguousarray(starts, np.int64)
+        lens = np.ascontiguousarray(lens, np.int64)
+        a = np.ascontiguousarray(a, np.int32)
+        b = np.ascontiguousarray(b, np.int32)
+        if out is None:
+            out = np.zeros(a.size, np.uint8)
+        lat = np.zeros(types.size, np.float64)
+        _check(lib().cc_server_run_trace(self.h, types.size, _np_ptr(types), _np_ptr(arrivals), _np_ptr(starts),
+                                         _np_ptr(lens), _np_ptr(a), _np_ptr(b), _np_ptr(out), _np_ptr(lat)),
+               "cc_server_run_trace")
+        return out, lat
+
+    def labels(self):
+        dev = self.ctx.torch_device
+        lab = torch.empty(self.n, dtype=torch.int32, device=dev)
+        nc = torch.empty(1, dtype=torch.int64, device=dev)
+        _check(lib().cc_server_labels(self.h, _ptr(lab), _ptr(nc), _stream_handle()), "cc_server_labels")
+        return lab, nc
+
+    def pool_used(self) -> int:
+        return int(lib().cc_server_pool_used(self.h))
 
 
 # ---- calibration -------------------------------------------------------------
