@@ -134,6 +134,11 @@ cc_status cc_last_stats(cc_ctx* ctx, cc_stats* out);
  * names are stable strings ("init", "sample", "compress_count", "frequent",
  * "compact", "finish", "output", ...). */
 cc_status cc_ctx_set_timing(cc_ctx* ctx, int enable);
+/* Caps the rounds of every round-based phase (BFS levels per try, SV and LT
+ * rounds) at `limit` (0 = only the built-in caps); a call that reaches it
+ * returns CC_ELIVELOCK, its labels undefined.  A measurement aid for timing
+ * many variants without waiting on hopeless ones. */
+cc_status cc_ctx_set_round_limit(cc_ctx* ctx, int32_t limit);
 int cc_phase_times(cc_ctx* ctx, int max_phases, const char** names, double* total_ms, int64_t* counts);
 void cc_phase_times_reset(cc_ctx* ctx);
 
@@ -243,6 +248,52 @@ cc_status cc_server_request_info(cc_server* s, int64_t id, int* done, double* la
 cc_status cc_server_labels(cc_server* s, int32_t* labels_out, int64_t* num_components_dev, void* hip_stream);
 /* Bytes of the device pool currently held by admitted requests. */
 int64_t cc_server_pool_used(cc_server* s);
+
+/* ---- learned variant selector ---------------------------------------------------
+ * Not part of the paper's method: it only chooses among its variants, so it
+ * changes speed, never labels.  Model: 16 features -> 64 -> 64 -> K (ReLU),
+ * parameters packed as BF16 [W1 16x64 | b1 64 | W2 64x64 | b2 64 | W3 64xK |
+ * b3 K] (row-major, input index first), inputs and hidden activations
+ * rounded to BF16, FP32 accumulation, FP32 outputs (predicted log-time of
+ * each arm relative to the best).  1 <= K <= 128.  All arrays are device
+ * memory unless named *_host. */
+int64_t cc_mlp_param_count(int32_t num_arms);
+/* Y[B x K] = MLP(X[B x 16]); cache (nullable, B x 256 floats) keeps the
+ * hidden pre-/post-activations for cc_mlp_backward. */
+cc_status cc_mlp_forward(const uint16_t* params, int32_t K, int32_t B, const float* X, float* Y, float* cache,
+                         void* hip_stream);
+/* grads (FP32, parameter packing) = d/dparams of mean((Y - T)^2) over the
+ * B x K entries, BF16 rounding treated as identity; scratch: 4*B*64 floats;
+ * loss (nullable, device float) receives the loss. */
+cc_status cc_mlp_backward(const uint16_t* params, int32_t K, int32_t B, const float* X, const float* cache,
+                          const float* Y, const float* T, float* grads, float* scratch, float* loss,
+                          void* hip_stream);
+/* One Adam step (step >= 1) on FP32 master weights; params gets their BF16 copy. */
+cc_status cc_mlp_adam(float* master, uint16_t* params, const float* grads, float* m1, float* m2, int64_t count,
+                      float lr, float beta1, float beta2, float eps, int32_t step, void* hip_stream);
+/* dst = BF16(src), round to nearest even. */
+cc_status cc_mlp_pack_bf16(const float* src, uint16_t* dst, int64_t count, void* hip_stream);
+/* The 16 features of a symmetric CSR (documented in the selector source):
+ * degree statistics, k-out sample statistics (the sample is left in
+ * labels_scratch, n int32) and a BFS probe capped at 8 levels.
+ * workspace as for cc_connectivity_csr with the default variant.
+ * Synchronises hip_stream. */
+cc_status cc_graph_features(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                            const int32_t* adj, void* workspace, size_t ws_bytes, int32_t* labels_scratch,
+                            float* features_host, void* hip_stream);
+/* Static connectivity with the arm the model predicts fastest: features,
+ * normalisation x = (f - norm_host[0:16]) / norm_host[16:32], forward pass,
+ * argmin over the K arms (host array of variants), then the chosen arm -- an
+ * arm that samples like the default k-out continues from the features'
+ * sample.  params_dev NULL runs the default variant.  chosen_host (nullable)
+ * gets the arm index (-1 for the default); features_host (nullable) gets the
+ * 16 features.  workspace: at least the largest cc_workspace_bytes over the
+ * arms and the default. */
+cc_status cc_connectivity_auto(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                               const int32_t* adj, const uint16_t* params_dev, int32_t K, const cc_variant* arms,
+                               const float* norm_host, void* workspace, size_t ws_bytes, int32_t* labels_out,
+                               int64_t* num_components_dev, int32_t* chosen_host, float* features_host,
+                               void* hip_stream);
 
 /* ---- calibration (measurement aids) ------------------------------------------
  * Roofline anchors for the kernels above; they compute nothing the method

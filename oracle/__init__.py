@@ -63,6 +63,10 @@ def _load():
         lib.oracle_kout_sample.restype = i64
         lib.oracle_bfs_sample.argtypes = [i64, _i64p, _i32p, ctypes.c_int32, ctypes.c_uint64, _i32p]
         lib.oracle_bfs_sample.restype = i64
+        lib.oracle_splitmix_out.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.oracle_splitmix_out.restype = ctypes.c_uint64
+        lib.oracle_bfs_levels.argtypes = [i64, _i64p, _i32p, ctypes.c_int32, ctypes.c_int32, _i32p]
+        lib.oracle_bfs_levels.restype = i64
         _lib = lib
     return _lib
 
@@ -184,6 +188,32 @@ def bfs_sample(n: int, offsets, adj, tries: int, seed: int):
     t = _load().oracle_bfs_sample(n, _p64(offsets), _p32(adj) if adj.size else _p32(np.zeros(1, np.int32)),
                                   tries, seed, _p32(lab))
     return lab, int(t)
+
+
+def splitmix_out(state: int, i: int) -> int:
+    """Output i of splitmix64 seeded with `state` (counter mode)."""
+    return int(_load().oracle_splitmix_out(state, i))
+
+
+def bfs_levels(n: int, offsets, adj, source: int, cap: int):
+    """BFS from source for at most cap levels: (reached, levels expanded)."""
+    offsets, adj = _c(offsets, np.int64), _c(adj, np.int32)
+    lv = np.zeros(1, np.int32)
+    r = _load().oracle_bfs_levels(n, _p64(offsets), _p32(adj) if adj.size else _p32(np.zeros(1, np.int32)),
+                                  source, cap, _p32(lv))
+    return int(r), int(lv[0])
+
+
+def degree_features(offsets):
+    """The selector's degree features (indices 0-8, 14, 15) from the definition."""
+    d = np.diff(np.asarray(offsets, np.int64)).astype(np.float64)
+    n, m = d.size, d.sum()
+    mean = d.mean()
+    sd = d.std()
+    skew = float(np.mean((d - mean) ** 3) / sd ** 3) if sd > 0 else 0.0
+    return {0: np.log2(n), 1: np.log2(m + 1), 2: m / n, 3: sd / mean if mean > 0 else 0.0,
+            4: d.max() / mean if mean > 0 else 0.0, 5: np.mean(d == 0), 6: np.mean(d == 1), 7: np.mean(d <= 2),
+            8: skew, 14: float(m / n < 3), 15: np.log2(d.max() + 1)}
 
 
 def identify_frequent(labels_arr) -> int:

@@ -244,3 +244,36 @@ int64_t oracle_bfs_sample(int64_t n, const int64_t* offsets, const int32_t* adj,
   free(seen);
   return result;
 }
+
+/* splitmix64 output i of the generator seeded with `state` (exported so the
+ * tests can derive the same seeded choices as the device does). */
+uint64_t oracle_splitmix_out(uint64_t state, uint64_t i) { return sm_out(state, i); }
+
+/* BFS from `source` for at most `cap` levels (cap <= 0: no limit); returns
+ * the number of vertices reached and writes the number of levels expanded
+ * (a level counts if its frontier was non-empty when expanded). */
+int64_t oracle_bfs_levels(int64_t n, const int64_t* offsets, const int32_t* adj, int32_t source, int32_t cap,
+                          int32_t* levels_out) {
+  int32_t* dist = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t* queue = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  for (int64_t x = 0; x < n; ++x) dist[x] = -1;
+  int64_t head = 0, tail = 0;
+  dist[source] = 0;
+  queue[tail++] = source;
+  int32_t levels = 0;
+  while (head < tail) {
+    int32_t x = queue[head];
+    if (cap > 0 && dist[x] >= cap) break;
+    if (dist[x] + 1 > levels) levels = dist[x] + 1;
+    ++head;
+    for (int64_t j = offsets[x]; j < offsets[x + 1]; ++j)
+      if (dist[adj[j]] < 0) {
+        dist[adj[j]] = dist[x] + 1;
+        queue[tail++] = adj[j];
+      }
+  }
+  free(dist);
+  free(queue);
+  *levels_out = levels;
+  return tail;
+}

@@ -104,6 +104,7 @@ def lib():
             "cc_ctx_sync_status": (_int, [_vp]),
             "cc_last_stats": (_int, [_vp, ctypes.POINTER(cc_stats)]),
             "cc_ctx_set_timing": (_int, [_vp, _int]),
+            "cc_ctx_set_round_limit": (_int, [_vp, ctypes.c_int32]),
             "cc_phase_times": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
             "cc_phase_times_reset": (None, [_vp]),
@@ -134,6 +135,18 @@ def lib():
             "cc_server_request_info": (_int, [_vp, _i64, ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]),
             "cc_server_labels": (_int, [_vp, _vp, _vp, _vp]),
             "cc_server_pool_used": (_i64, [_vp]),
+            "cc_mlp_param_count": (_i64, [ctypes.c_int32]),
+            "cc_mlp_forward": (_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp]),
+            "cc_mlp_backward": (_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "cc_mlp_adam": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_int32, _vp]),
+            "cc_mlp_pack_bf16": (_int, [_vp, _vp, _i64, _vp]),
+            "cc_graph_features": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, ctypes.c_size_t, _vp,
+                                         ctypes.POINTER(ctypes.c_float), _vp]),
+            "cc_connectivity_auto": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, ctypes.c_int32,
+                                            ctypes.POINTER(cc_variant), ctypes.POINTER(ctypes.c_float), _vp,
+                                            ctypes.c_size_t, _vp, _vp, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_float), _vp]),
             "cc_calib_copy": (_int, [_vp, _vp, ctypes.c_size_t, _vp]),
             "cc_calib_workspace_bytes": (_int, [_i64, ctypes.POINTER(ctypes.c_size_t)]),
             "cc_calib_edges": (_int, [_i64, _i64, _vp, _int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -237,6 +250,9 @@ class Context:
 
     def set_timing(self, on: bool):
         _check(lib().cc_ctx_set_timing(self.h, int(on)), "cc_ctx_set_timing")
+
+    def set_round_limit(self, limit: int):
+        _check(lib().cc_ctx_set_round_limit(self.h, int(limit)), "cc_ctx_set_round_limit")
 
     def phase_times(self) -> dict:
         k = lib().cc_phase_times(self.h, 0, None, None, None)
@@ -455,6 +471,82 @@ class Server:
 
     def pool_used(self) -> int:
         return int(lib().cc_server_pool_used(self.h))
+
+
+# ---- selector ---------------------------------------------------------------------
+
+def mlp_param_count(K: int) -> int:
+    return int(lib().cc_mlp_param_count(K))
+
+
+def mlp_forward(params_bf16: torch.Tensor, K: int, X: torch.Tensor, cache: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """params_bf16: int16/uint16-typed device tensor of BF16 bit patterns; X: [B,16] float32."""
+    B = int(X.shape[0])
+    Y = torch.empty(B, K, dtype=torch.float32, device=X.device)
+    _check(lib().cc_mlp_forward(_ptr(params_bf16), K, B, _ptr(X), _ptr(Y), _ptr(cache), _stream_handle(stream)),
+           "cc_mlp_forward")
+    return Y
+
+
+def mlp_backward(params_bf16, K, X, cache, Y, T, stream=None):
+    B = int(X.shape[0])
+    dev = X.device
+    grads = torch.empty(mlp_param_count(K), dtype=torch.float32, device=dev)
+    scratch = torch.empty(4 * B * 64, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    _check(lib().cc_mlp_backward(_ptr(params_bf16), K, B, _ptr(X), _ptr(cache), _ptr(Y), _ptr(T), _ptr(grads),
+                                 _ptr(scratch), _ptr(loss), _stream_handle(stream)), "cc_mlp_backward")
+    return grads, loss
+
+
+def mlp_adam(master, params_bf16, grads, m1, m2, lr, beta1, beta2, eps, step, stream=None):
+    _check(lib().cc_mlp_adam(_ptr(master), _ptr(params_bf16), _ptr(grads), _ptr(m1), _ptr(m2), master.numel(), lr,
+                             beta1, beta2, eps, step, _stream_handle(stream)), "cc_mlp_adam")
+
+
+def mlp_pack_bf16(src: torch.Tensor, dst: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if dst is None:
+        dst = torch.empty(src.numel(), dtype=torch.int16, device=src.device)
+    _check(lib().cc_mlp_pack_bf16(_ptr(src), _ptr(dst), src.numel(), _stream_handle(stream)), "cc_mlp_pack_bf16")
+    return dst
+
+
+def graph_features(ctx: Context, g: CSR, labels_scratch: torch.Tensor | None = None, stream=None):
+    """The 16 selector features; also returns the k-out sample labels."""
+    dev = ctx.torch_device
+    if labels_scratch is None:
+        labels_scratch = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ws = ctx.workspace(workspace_bytes(g.n, g.m, default_variant()))
+    f = (ctypes.c_float * 16)()
+    _check(lib().cc_graph_features(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(ws), ws.numel(),
+                                   _ptr(labels_scratch), f, _stream_handle(stream)), "cc_graph_features")
+    return [float(x) for x in f], labels_scratch
+
+
+def connectivity_auto(ctx: Context, g: CSR, params_bf16: torch.Tensor | None, arms, norm, labels=None, ncomp=None,
+                      stream=None):
+    """cc_connectivity_auto: returns (labels, ncomp, chosen arm index, features)."""
+    dev = ctx.torch_device
+    if labels is None:
+        labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    if ncomp is None:
+        ncomp = torch.empty(1, dtype=torch.int64, device=dev)
+    K = len(arms) if arms is not None else 0
+    need = workspace_bytes(g.n, g.m, default_variant())
+    arr = None
+    if arms is not None:
+        arr = (cc_variant * K)(*arms)
+        for a in arms:
+            need = max(need, workspace_bytes(g.n, g.m, a))
+    nrm = (ctypes.c_float * 32)(*[float(x) for x in norm]) if norm is not None else None
+    ws = ctx.workspace(need)
+    chosen = ctypes.c_int32(-2)
+    f = (ctypes.c_float * 16)()
+    _check(lib().cc_connectivity_auto(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(params_bf16), K,
+                                      arr, nrm, _ptr(ws), ws.numel(), _ptr(labels), _ptr(ncomp),
+                                      ctypes.byref(chosen), f, _stream_handle(stream)), "cc_connectivity_auto")
+    return labels, ncomp, chosen.value, [float(x) for x in f]
 
 
 # ---- calibration -------------------------------------------------------------

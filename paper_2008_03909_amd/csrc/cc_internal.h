@@ -44,6 +44,7 @@ struct cc_ctx {
   cc::DevScalars* dev = nullptr;     // device copy
   cc::DevScalars* host = nullptr;    // pinned host mirror
   cc_stats last{};
+  int round_limit = 0;  // 0: the built-in caps only
   // phase timing
   int timing = 0;
   std::vector<cc::PhaseRec> pending;        // events of calls not yet harvested
@@ -103,6 +104,7 @@ struct WsLayout {
   size_t hist = 0;        // LDD start-round histogram
   size_t seg = 0;         // compaction: per-segment counts and edge sums
   size_t heavy = 0;       // grid-bin vertex list and its degree prefix
+  size_t mlp = 0;         // selector: one feature row and its scores
   size_t total = 0;
 };
 WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v);

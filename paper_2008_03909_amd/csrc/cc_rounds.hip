@@ -94,6 +94,8 @@ cc_status finish_sv(StaticArgs& a) {
   hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, prev, (uint32_t*)nullptr);
   for (int round = 0;; ++round) {
     if (round >= kRoundCap) return fail(CC_ELIVELOCK, "Shiloach-Vishkin exceeded %d rounds", kRoundCap);
+    if (a.ctx->round_limit > 0 && round >= a.ctx->round_limit)
+      return fail(CC_ELIVELOCK, "Shiloach-Vishkin reached the context's round limit (%d)", a.ctx->round_limit);
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->changed, 0u);
     visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, SvHook{a.P, prev}, &sc->changed);
     hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, prev, (uint32_t*)nullptr);
@@ -205,6 +207,8 @@ static cc_status lt_rounds(StaticArgs& a) {
   }
   for (int round = 0;; ++round) {
     if (round >= kRoundCap) return fail(CC_ELIVELOCK, "Liu-Tarjan exceeded %d rounds", kRoundCap);
+    if (a.ctx->round_limit > 0 && round >= a.ctx->round_limit)
+      return fail(CC_ELIVELOCK, "Liu-Tarjan reached the context's round limit (%d)", a.ctx->round_limit);
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->changed, 0u);
     hipLaunchKernelGGL(k_copy_i32, dim3(g), dim3(kFBlock), 0, a.s, a.n, (const int32_t*)a.P, Q);
     LtConnect<PARENT> op{a.P, Q};

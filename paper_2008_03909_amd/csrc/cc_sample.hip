@@ -223,8 +223,9 @@ __global__ void k_label_reached(int64_t n, const uint32_t* __restrict__ vis, con
     if (bit_get(vis, v)) P[v] = mn;
 }
 
+// One direction-optimizing BFS from `source` into the visited bitmap.
 template <typename I>
-cc_status sample_bfs(StaticArgs& a) {
+cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reached_out, int32_t* levels_out) {
   const int64_t n = a.n, m = a.m;
   const int64_t words = (n + 31) / 32;
   const size_t bw = align256((size_t)words * 4);
@@ -234,56 +235,75 @@ cc_status sample_bfs(StaticArgs& a) {
   int32_t* q[2] = {(int32_t*)(a.ws + a.L.queue), (int32_t*)(a.ws + a.L.queue + align256((size_t)n * 4))};
   const I* off = (const I*)a.off;
   DevScalars* sc = a.ctx->dev;
-  const uint64_t key = sm_out(a.v->seed, kTagBfs);
   const double alpha = 15.0, beta = 18.0;  // Beamer's direction-switch constants
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(3 * bw / 4, kFBlock, 4096)), dim3(kFBlock), 0, a.s, vis,
+                     (int64_t)(3 * bw / 4), 0u);
+  hipLaunchKernelGGL(k_bfs_start<I>, dim3(1), dim3(1), 0, a.s, source, off, vis, fa, q[0], sc);
+  CC_LAUNCH_CHECK();
+  cc_status st = pull_scalars(a);
+  if (st != CC_OK) return st;
+  int64_t nf = 1, mf = a.ctx->host->frontier_edges, seen_edges = mf, reached = 1;
+  bool top_down = true;
+  int cur = 0;
+  int32_t levels = 0;
+  uint32_t* fc = fa;
+  uint32_t* fn = fb;
+  for (int level = 0; nf > 0 && (level_cap <= 0 || level < level_cap); ++level) {
+    if (level > n + 1) return fail(CC_ELIVELOCK, "BFS exceeded n levels");
+    if (a.ctx->round_limit > 0 && level >= a.ctx->round_limit)
+      return fail(CC_ELIVELOCK, "BFS reached the context's round limit (%d)", a.ctx->round_limit);
+    if (top_down && (double)mf > (double)(m - seen_edges + mf) / alpha) top_down = false;
+    else if (!top_down && (double)nf < (double)n / beta) top_down = true;
+    const int nxt = cur ^ 1;
+    hipLaunchKernelGGL(k_bfs_level_reset, dim3(grid_for(words, kFBlock, 4096)), dim3(kFBlock), 0, a.s, fn, words,
+                       sc, nxt);
+    if (top_down) {
+      hipLaunchKernelGGL(k_bfs_td<I>, dim3(grid_for(nf, kFBlock, 8192)), dim3(kFBlock), 0, a.s, q[cur],
+                         &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, fn, a.heavy, &sc->hcount);
+      heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&sc->hcount, a.hcap, off, a.tsum, a.hp);
+      hipLaunchKernelGGL(k_bfs_heavy<I>, dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
+                         (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, fn, q[nxt],
+                         &sc->qcount[nxt]);
+    } else {
+      hipLaunchKernelGGL(k_bfs_bu<I>, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, off, a.adj, vis,
+                         fc, fn, q[nxt], &sc->qcount[nxt]);
+    }
+    hipLaunchKernelGGL(k_sum_degrees<I>, dim3(grid_for(n, kFBlock, 1024)), dim3(kFBlock), 0, a.s, q[nxt],
+                       &sc->qcount[nxt], off, sc);
+    CC_LAUNCH_CHECK();
+    st = pull_scalars(a);
+    if (st != CC_OK) return st;
+    nf = a.ctx->host->qcount[nxt];
+    mf = a.ctx->host->frontier_edges;
+    seen_edges += mf;
+    reached += nf;
+    uint32_t* t2 = fc;
+    fc = fn;
+    fn = t2;
+    cur = nxt;
+    ++levels;
+  }
+  *reached_out = reached;
+  *levels_out = levels;
+  return CC_OK;
+}
+
+template <typename I>
+cc_status sample_bfs(StaticArgs& a) {
+  const int64_t n = a.n;
+  const int64_t words = (n + 31) / 32;
+  uint32_t* vis = (uint32_t*)(a.ws + a.L.bits);
+  DevScalars* sc = a.ctx->dev;
+  const uint64_t key = sm_out(a.v->seed, kTagBfs);
   a.sample_success = -1;
   a.sample_rounds = 0;
   for (int t = 0; t < a.v->bfs_tries; ++t) {
     const int32_t s = (int32_t)(sm_out(key, (uint64_t)t) % (uint64_t)n);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(3 * bw / 4, kFBlock, 4096)), dim3(kFBlock), 0, a.s, vis,
-                       (int64_t)(3 * bw / 4), 0u);
-    hipLaunchKernelGGL(k_bfs_start<I>, dim3(1), dim3(1), 0, a.s, s, off, vis, fa, q[0], sc);
-    CC_LAUNCH_CHECK();
-    cc_status st = pull_scalars(a);
+    int64_t reached = 0;
+    int32_t levels = 0;
+    cc_status st = bfs_probe<I>(a, s, 0, &reached, &levels);
     if (st != CC_OK) return st;
-    int64_t nf = 1, mf = a.ctx->host->frontier_edges, seen_edges = mf, reached = 1;
-    bool top_down = true;
-    int cur = 0;
-    uint32_t* fc = fa;
-    uint32_t* fn = fb;
-    for (int level = 0; nf > 0; ++level) {
-      if (level > n + 1) return fail(CC_ELIVELOCK, "BFS exceeded n levels");
-      if (top_down && (double)mf > (double)(m - seen_edges + mf) / alpha) top_down = false;
-      else if (!top_down && (double)nf < (double)n / beta) top_down = true;
-      const int nxt = cur ^ 1;
-      hipLaunchKernelGGL(k_bfs_level_reset, dim3(grid_for(words, kFBlock, 4096)), dim3(kFBlock), 0, a.s, fn, words,
-                         sc, nxt);
-      if (top_down) {
-        hipLaunchKernelGGL(k_bfs_td<I>, dim3(grid_for(nf, kFBlock, 8192)), dim3(kFBlock), 0, a.s, q[cur],
-                           &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, fn, a.heavy, &sc->hcount);
-        heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&sc->hcount, a.hcap, off, a.tsum, a.hp);
-        hipLaunchKernelGGL(k_bfs_heavy<I>, dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
-                           (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, fn, q[nxt],
-                           &sc->qcount[nxt]);
-      } else {
-        hipLaunchKernelGGL(k_bfs_bu<I>, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, off, a.adj, vis,
-                           fc, fn, q[nxt], &sc->qcount[nxt]);
-      }
-      hipLaunchKernelGGL(k_sum_degrees<I>, dim3(grid_for(n, kFBlock, 1024)), dim3(kFBlock), 0, a.s, q[nxt],
-                         &sc->qcount[nxt], off, sc);
-      CC_LAUNCH_CHECK();
-      st = pull_scalars(a);
-      if (st != CC_OK) return st;
-      nf = a.ctx->host->qcount[nxt];
-      mf = a.ctx->host->frontier_edges;
-      seen_edges += mf;
-      reached += nf;
-      uint32_t* t2 = fc;
-      fc = fn;
-      fn = t2;
-      cur = nxt;
-      ++a.sample_rounds;
-    }
+    a.sample_rounds += levels;
     if (10 * reached > n) {
       hipLaunchKernelGGL(k_bitmap_min, dim3(grid_for(words, kFBlock, 1024)), dim3(kFBlock), 0, a.s, vis, words, sc);
       hipLaunchKernelGGL(k_label_reached, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n,
@@ -477,6 +497,8 @@ cc_status sample_ldd(StaticArgs& a) {
   return CC_OK;
 }
 
+template cc_status bfs_probe<int32_t>(StaticArgs&, int32_t, int, int64_t*, int32_t*);
+template cc_status bfs_probe<int64_t>(StaticArgs&, int32_t, int, int64_t*, int32_t*);
 template cc_status sample_bfs<int32_t>(StaticArgs&);
 template cc_status sample_bfs<int64_t>(StaticArgs&);
 template cc_status sample_ldd<int32_t>(StaticArgs&);

@@ -38,4 +38,16 @@ template <typename I> cc_status finish_lt(StaticArgs& a);
 // Synchronous read of the context's device scalars into ctx->host.
 cc_status pull_scalars(StaticArgs& a);
 
+// Argument checks and workspace carving shared by every static entry point.
+cc_status setup_args(StaticArgs& a, cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int o64,
+                     const int32_t* adj, const cc_variant* v, void* ws, size_t ws_bytes, int32_t* labels,
+                     int64_t* ncomp, void* stream);
+// Init + sampling + IdentifyFrequent only / the rest of Algorithm 1 after it.
+cc_status static_sample_only(StaticArgs& a);
+cc_status static_from_sample(StaticArgs& a);
+// BFS from `source` for at most `level_cap` levels (<= 0: no cap) over the
+// workspace bitmaps; reports vertices reached and levels expanded.
+template <typename I> cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reached,
+                                          int32_t* levels);
+
 }  // namespace cc

@@ -149,11 +149,11 @@ WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v) {
   L.count = off, off += n4;
   L.cand = off, off += n4;
   L.big = off, off += n4;
-  if (v->sample == CC_SAMPLE_BFS || v->sample == CC_SAMPLE_LDD) {
-    L.bits = off, off += 3 * align256((size_t)((n + 31) / 32) * 4);
-    L.queue = off, off += 2 * n4;
-  }
-  if (v->sample == CC_SAMPLE_LDD) L.hist = off, off += align256(4096 * 4);
+  // frontier state for BFS / LDD sampling and the selector's BFS probe
+  L.bits = off, off += 3 * align256((size_t)((n + 31) / 32) * 4);
+  L.queue = off, off += 2 * n4;
+  L.hist = off, off += align256(4096 * 4);
+  L.mlp = off, off += 65536;   // selector: feature partials, label stats, one MLP row
   if (v->finish == CC_FIN_LT && (v->lt_rules & CC_LT_ALTER)) L.edges = off, off += 2 * align256((size_t)m * 4);
   L.seg = off, off += align256((size_t)kSegMaxHost * 16) + align256((size_t)kSegMaxHost * 8);
   {
@@ -696,6 +696,9 @@ static cc_status run_sample(StaticArgs& a) {
 }
 
 template <typename I>
+static cc_status run_tail(StaticArgs& a);
+
+template <typename I>
 static cc_status run_static(StaticArgs& a, bool sample_only) {
   {
     PhaseScope ps(a.ctx, a.s, "init");
@@ -706,6 +709,14 @@ static cc_status run_static(StaticArgs& a, bool sample_only) {
   }
   cc_status st = run_sample<I>(a);
   if (st != CC_OK || sample_only) return st;
+  return run_tail<I>(a);
+}
+
+// Compaction, finish and output, on a parent array that already holds a
+// sampled labelling with its frequent label resolved in the context scalars.
+template <typename I>
+static cc_status run_tail(StaticArgs& a) {
+  cc_status st = CC_OK;
   {
     PhaseScope ps(a.ctx, a.s, "compact");
     // segment size: a multiple of 256 vertices, at most ~8192 segments
@@ -742,7 +753,12 @@ static cc_status run_static(StaticArgs& a, bool sample_only) {
   return CC_OK;
 }
 
-static cc_status setup_args(StaticArgs& a, cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int o64,
+cc_status static_sample_only(StaticArgs& a) {
+  return a.o64 ? run_static<int64_t>(a, true) : run_static<int32_t>(a, true);
+}
+cc_status static_from_sample(StaticArgs& a) { return a.o64 ? run_tail<int64_t>(a) : run_tail<int32_t>(a); }
+
+cc_status setup_args(StaticArgs& a, cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int o64,
                             const int32_t* adj, const cc_variant* v, void* ws, size_t ws_bytes, int32_t* labels,
                             int64_t* ncomp, void* stream) {
   if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
@@ -854,6 +870,12 @@ cc_status cc_last_stats(cc_ctx* ctx, cc_stats* out) {
   s.candidate_edges = ctx->host->cand_edges;
   s.num_components = ctx->host->num_components;
   *out = s;
+  return CC_OK;
+}
+
+cc_status cc_ctx_set_round_limit(cc_ctx* ctx, int32_t limit) {
+  if (!ctx || limit < 0) return fail(CC_EINVAL, "bad argument");
+  ctx->round_limit = limit;
   return CC_OK;
 }
 
