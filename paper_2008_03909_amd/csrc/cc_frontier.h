@@ -55,6 +55,40 @@ __device__ __forceinline__ void wave_append_pair(bool take, int32_t a, int32_t b
   }
 }
 
+// Wave-private output buffer in LDS: appends cost LDS writes; the global
+// queue counter is bumped once per flush (at most kWaveQCap entries).  Every
+// call must be made by all 64 lanes of the wave together (uniform control
+// flow), since `cnt` is a wave-uniform register.
+constexpr int kWaveQCap = 512;
+
+struct WaveQ {
+  int32_t* buf;  // this wave's kWaveQCap-entry LDS slice
+  int cnt;
+};
+
+__device__ __forceinline__ void wq_flush(WaveQ& q, int32_t* gq, uint32_t* gcnt) {
+  if (q.cnt == 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint32_t base = 0;
+  if (lane_id() == 0)
+    base = __hip_atomic_fetch_add(gcnt, (uint32_t)q.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  base = __shfl(base, 0, kWave);
+  for (int i = lane_id(); i < q.cnt; i += kWave) gq[base + i] = q.buf[i];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  q.cnt = 0;
+}
+
+__device__ __forceinline__ void wq_push(WaveQ& q, bool take, int32_t val, int32_t* gq, uint32_t* gcnt) {
+  const uint64_t m = __ballot(take);
+  if (take) q.buf[q.cnt + __popcll(m & lanemask_lt())] = val;
+  q.cnt += __popcll(m);
+  if (q.cnt > kWaveQCap - kWave) wq_flush(q, gq, gcnt);
+}
+
 // Sets *flag = 1 once per wave if any active lane saw a change.
 __device__ __forceinline__ void wave_flag(bool any, uint32_t* flag) {
   const uint64_t mask = __ballot(any);

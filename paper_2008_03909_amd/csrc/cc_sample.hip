@@ -55,61 +55,91 @@ __global__ void k_bfs_level_reset(uint32_t* fn, int64_t words, DevScalars* sc, i
   for (; i < words; i += stride) fn[i] = 0u;
 }
 
-// Top-down step: frontier queue -> claimed neighbours.  Rows longer than a
-// wave are walked by the whole wave (lanes take consecutive entries).
-template <typename I>
-__global__ void k_bfs_td(const int32_t* __restrict__ qin, const uint32_t* cnt_in, int32_t* qout, uint32_t* cnt_out,
-                         const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
-                         int32_t* heavy, int32_t* hcount) {
-  const int64_t cnt = *cnt_in;
+// Frontier expansion (BFS top-down step, LDD cluster growth), load-balanced
+// within each wave: a wave takes 64 frontier vertices, concatenates their
+// rows (exclusive scan of the degrees across lanes) and walks the joint edge
+// list 64 edges at a time; each lane finds the row of its edge by a binary
+// search over the 64 row starts in LDS.  Rows above kHeavyFrontier are
+// deferred to the grid kernel.  Claimed vertices go through a wave-private
+// LDS buffer, so the output queue's counter is bumped once per flush.
+template <bool LDD, typename I>
+__global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ qin, const uint32_t* cnt_in,
+                                                    int32_t* qout, uint32_t* cnt_out, const I* __restrict__ off,
+                                                    const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
+                                                    int32_t* P, int32_t* heavy, int32_t* hcount) {
+  constexpr int W = kFBlock / kWave;
+  __shared__ int32_t qbuf[W][kWaveQCap];
+  __shared__ int32_t tpre[W][kWave + 1];
+  __shared__ int64_t tbeg[W][kWave];
+  __shared__ int32_t tlab[W][kWave];
+  const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < cnt; base += stride) {
-    const int64_t idx = base + threadIdx.x;
-    int64_t b = 0, e = 0;
+  WaveQ q{qbuf[wv], 0};
+  const int64_t cnt = *cnt_in;
+  const int64_t tiles = (cnt + kWave - 1) / kWave;
+  const int64_t waves = (int64_t)gridDim.x * W;
+  for (int64_t tile = blockIdx.x * (int64_t)W + wv; tile < tiles; tile += waves) {
+    const int64_t idx = tile * kWave + lane;
     int32_t u = 0;
+    int64_t b = 0, d = 0;
     if (idx < cnt) {
       u = qin[idx];
       b = (int64_t)off[u];
-      e = (int64_t)off[u + 1];
+      d = (int64_t)off[u + 1] - b;
     }
-    const bool heavy_row = (e - b) > kHeavyFrontier;
-    wave_append(heavy_row, u, heavy, (uint32_t*)hcount);
-    if (heavy_row) e = b;  // the grid kernel walks this row
-    const bool big = (e - b) > kWave;
-    uint64_t bm = __ballot(big);
-    while (bm) {
-      const int l = __ffsll((unsigned long long)bm) - 1;
-      bm &= bm - 1;
-      const int64_t bb = __shfl(b, l, kWave), eb = __shfl(e, l, kWave);
-      for (int64_t j0 = bb; j0 < eb; j0 += kWave) {
-        const int64_t j = j0 + lane;
-        bool got = false;
-        int32_t w = 0;
-        if (j < eb) {
-          w = adj[j];
-          got = bit_claim(vis, w);
-          if (got) aor(fn + (w >> 5), 1u << (w & 31));
+    const bool heavy_row = d > kHeavyFrontier;
+    wave_append(heavy_row, u, heavy, (uint32_t*)hcount);  // rare: one atomic per wave with a heavy row
+    if (heavy_row) d = 0;
+    // exclusive scan of the row lengths across the wave
+    int32_t inc = (int32_t)d;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int32_t y = __shfl_up(inc, o, kWave);
+      if (lane >= o) inc += y;
+    }
+    const int32_t total = __shfl(inc, kWave - 1, kWave);
+    tpre[wv][lane] = inc - (int32_t)d;
+    if (lane == kWave - 1) tpre[wv][kWave] = total;
+    tbeg[wv][lane] = b;
+    if (LDD) tlab[wv][lane] = (idx < cnt) ? P[u] : 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int32_t e0 = 0; e0 < total; e0 += kWave) {
+      const int32_t e = e0 + lane;
+      bool got = false;
+      int32_t w = 0;
+      if (e < total) {
+        int lo = 0, hi = kWave - 1;  // last row whose start <= e
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (tpre[wv][mid] <= e) lo = mid;
+          else hi = mid - 1;
         }
-        wave_append(got, w, qout, cnt_out);
+        w = adj[tbeg[wv][lo] + (e - tpre[wv][lo])];
+        got = bit_claim(vis, w);
+        if (got) {
+          if (LDD) P[w] = tlab[wv][lo];
+          else aor(fn + (w >> 5), 1u << (w & 31));
+        }
       }
+      wq_push(q, got, w, qout, cnt_out);
     }
-    if (!big) {
-      for (int64_t j = b; j < e; ++j) {
-        const int32_t w = adj[j];
-        const bool got = bit_claim(vis, w);
-        if (got) aor(fn + (w >> 5), 1u << (w & 31));
-        wave_append(got, w, qout, cnt_out);
-      }
-    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  wq_flush(q, qout, cnt_out);
 }
 
 // Bottom-up step: every unvisited vertex looks for a neighbour in the
 // current frontier bitmap and stops at the first one.
 template <typename I>
-__global__ void k_bfs_bu(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis,
-                         const uint32_t* __restrict__ fc, uint32_t* fn, int32_t* qout, uint32_t* cnt_out) {
+__global__ void __launch_bounds__(kFBlock) k_bfs_bu(int64_t n, const I* __restrict__ off,
+                                                    const int32_t* __restrict__ adj, uint32_t* vis,
+                                                    const uint32_t* __restrict__ fc, uint32_t* fn, int32_t* qout,
+                                                    uint32_t* cnt_out) {
+  __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
+  WaveQ q{qbuf[threadIdx.x / kWave], 0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
     const int64_t v = base + threadIdx.x;
@@ -126,57 +156,42 @@ __global__ void k_bfs_bu(int64_t n, const I* __restrict__ off, const int32_t* __
       aor(vis + (v >> 5), 1u << (v & 31));
       aor(fn + (v >> 5), 1u << (v & 31));
     }
-    wave_append(found, (int32_t)v, qout, cnt_out);
+    wq_push(q, found, (int32_t)v, qout, cnt_out);
   }
+  wq_flush(q, qout, cnt_out);
 }
 
 // Rows of heavy frontier vertices, spread evenly over the whole grid.
-template <typename I>
-__global__ void k_bfs_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount, const long long* __restrict__ hp,
-                            const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
-                            int32_t* qout, uint32_t* cnt_out) {
+template <bool LDD, typename I>
+__global__ void __launch_bounds__(kFBlock) k_expand_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount,
+                                                          const long long* __restrict__ hp, const I* __restrict__ off,
+                                                          const int32_t* __restrict__ adj, uint32_t* vis,
+                                                          uint32_t* fn, int32_t* P, int32_t* qout,
+                                                          uint32_t* cnt_out) {
+  __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
+  WaveQ q{qbuf[threadIdx.x / kWave], 0};
   const int64_t c = *hcount;
   if (c == 0) return;
   const long long T = hp[c];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
     const long long e = base + threadIdx.x;
+    const long long e0 = base + (threadIdx.x / kWave) * kWave;
     bool got = false;
     int32_t w = 0;
-    const long long e0 = base + (threadIdx.x / kWave) * kWave;
     if (e < T) {
       const int64_t i = heavy_owner_tile(hp, c, e0, e);
       const int32_t u = heavy[i];
       w = adj[(int64_t)off[u] + (e - hp[i])];
       got = bit_claim(vis, w);
-      if (got) aor(fn + (w >> 5), 1u << (w & 31));
+      if (got) {
+        if (LDD) P[w] = P[u];
+        else aor(fn + (w >> 5), 1u << (w & 31));
+      }
     }
-    wave_append(got, w, qout, cnt_out);
+    wq_push(q, got, w, qout, cnt_out);
   }
-}
-
-template <typename I>
-__global__ void k_ldd_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount, const long long* __restrict__ hp,
-                            const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis, int32_t* P,
-                            int32_t* qout, uint32_t* cnt_out) {
-  const int64_t c = *hcount;
-  if (c == 0) return;
-  const long long T = hp[c];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
-    const long long e = base + threadIdx.x;
-    bool got = false;
-    int32_t w = 0;
-    const long long e0 = base + (threadIdx.x / kWave) * kWave;
-    if (e < T) {
-      const int64_t i = heavy_owner_tile(hp, c, e0, e);
-      const int32_t u = heavy[i];
-      w = adj[(int64_t)off[u] + (e - hp[i])];
-      got = bit_claim(vis, w);
-      if (got) P[w] = P[u];
-    }
-    wave_append(got, w, qout, cnt_out);
-  }
+  wq_flush(q, qout, cnt_out);
 }
 
 __global__ void k_round_reset(DevScalars* sc, int nxt) {
@@ -258,12 +273,13 @@ cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reach
     hipLaunchKernelGGL(k_bfs_level_reset, dim3(grid_for(words, kFBlock, 4096)), dim3(kFBlock), 0, a.s, fn, words,
                        sc, nxt);
     if (top_down) {
-      hipLaunchKernelGGL(k_bfs_td<I>, dim3(grid_for(nf, kFBlock, 8192)), dim3(kFBlock), 0, a.s, q[cur],
-                         &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, fn, a.heavy, &sc->hcount);
+      hipLaunchKernelGGL((k_expand<false, I>), dim3(grid_for(nf * kWave / kWave, kFBlock, 2048)), dim3(kFBlock), 0,
+                         a.s, q[cur], &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, fn,
+                         (int32_t*)nullptr, a.heavy, &sc->hcount);
       heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&sc->hcount, a.hcap, off, a.tsum, a.hp);
-      hipLaunchKernelGGL(k_bfs_heavy<I>, dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
-                         (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, fn, q[nxt],
-                         &sc->qcount[nxt]);
+      hipLaunchKernelGGL((k_expand_heavy<false, I>), dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
+                         (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, fn,
+                         (int32_t*)nullptr, q[nxt], &sc->qcount[nxt]);
     } else {
       hipLaunchKernelGGL(k_bfs_bu<I>, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, off, a.adj, vis,
                          fc, fn, q[nxt], &sc->qcount[nxt]);
@@ -360,7 +376,10 @@ __global__ void k_ldd_hist(int64_t n, uint64_t key, float beta, const DevScalars
 }
 
 // Vertices [lo, hi) wake: the unvisited ones become cluster centres.
-__global__ void k_ldd_wake(int64_t lo, int64_t hi, uint32_t* vis, int32_t* P, int32_t* q, uint32_t* cnt) {
+__global__ void __launch_bounds__(kFBlock) k_ldd_wake(int64_t lo, int64_t hi, uint32_t* vis, int32_t* P, int32_t* q,
+                                                      uint32_t* cnt) {
+  __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
+  WaveQ wq{qbuf[threadIdx.x / kWave], 0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = lo + blockIdx.x * (int64_t)blockDim.x; base < hi; base += stride) {
     const int64_t v = base + threadIdx.x;
@@ -369,59 +388,9 @@ __global__ void k_ldd_wake(int64_t lo, int64_t hi, uint32_t* vis, int32_t* P, in
       got = bit_claim(vis, v);
       if (got) P[v] = (int32_t)v;
     }
-    wave_append(got, (int32_t)v, q, cnt);
+    wq_push(wq, got, (int32_t)v, q, cnt);
   }
-}
-
-// One hop of every cluster: claim unvisited neighbours for the claimer's cluster.
-template <typename I>
-__global__ void k_ldd_expand(const int32_t* __restrict__ qin, const uint32_t* cnt_in, int32_t* qout,
-                             uint32_t* cnt_out, const I* __restrict__ off, const int32_t* __restrict__ adj,
-                             uint32_t* vis, int32_t* P, int32_t* heavy, int32_t* hcount) {
-  const int64_t cnt = *cnt_in;
-  const int lane = lane_id();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < cnt; base += stride) {
-    const int64_t idx = base + threadIdx.x;
-    int64_t b = 0, e = 0;
-    int32_t c = 0, u = 0;
-    if (idx < cnt) {
-      u = qin[idx];
-      b = (int64_t)off[u];
-      e = (int64_t)off[u + 1];
-      c = P[u];
-    }
-    const bool heavy_row = (e - b) > kHeavyFrontier;
-    wave_append(heavy_row, u, heavy, (uint32_t*)hcount);
-    if (heavy_row) e = b;  // the grid kernel walks this row
-    const bool big = (e - b) > kWave;
-    uint64_t bm = __ballot(big);
-    while (bm) {
-      const int l = __ffsll((unsigned long long)bm) - 1;
-      bm &= bm - 1;
-      const int64_t bb = __shfl(b, l, kWave), eb = __shfl(e, l, kWave);
-      const int32_t cb = __shfl(c, l, kWave);
-      for (int64_t j0 = bb; j0 < eb; j0 += kWave) {
-        const int64_t j = j0 + lane;
-        bool got = false;
-        int32_t w = 0;
-        if (j < eb) {
-          w = adj[j];
-          got = bit_claim(vis, w);
-          if (got) P[w] = cb;
-        }
-        wave_append(got, w, qout, cnt_out);
-      }
-    }
-    if (!big) {
-      for (int64_t j = b; j < e; ++j) {
-        const int32_t w = adj[j];
-        const bool got = bit_claim(vis, w);
-        if (got) P[w] = c;
-        wave_append(got, w, qout, cnt_out);
-      }
-    }
-  }
+  wq_flush(wq, q, cnt);
 }
 
 __global__ void k_min_member(int64_t n, const int32_t* __restrict__ P, int32_t* mn) {
@@ -477,12 +446,13 @@ cc_status sample_ldd(StaticArgs& a) {
     lo = hi;
     const int nxt = cur ^ 1;
     hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, a.s, sc, nxt);
-    hipLaunchKernelGGL(k_ldd_expand<I>, dim3(grid_for(n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, q[cur],
-                       &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, a.P, a.heavy, &sc->hcount);
+    hipLaunchKernelGGL((k_expand<true, I>), dim3(grid_for(n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, q[cur],
+                       &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, (uint32_t*)nullptr, a.P,
+                       a.heavy, &sc->hcount);
     heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&sc->hcount, a.hcap, off, a.tsum, a.hp);
-    hipLaunchKernelGGL(k_ldd_heavy<I>, dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
-                       (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, a.P, q[nxt],
-                       &sc->qcount[nxt]);
+    hipLaunchKernelGGL((k_expand_heavy<true, I>), dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
+                       (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, (uint32_t*)nullptr,
+                       a.P, q[nxt], &sc->qcount[nxt]);
     CC_LAUNCH_CHECK();
     cur = nxt;
     ++a.sample_rounds;
