@@ -73,11 +73,44 @@ def phase_alg_bytes(phase: str, n: int, m: int, o: int, n_nz: int, st: dict, k: 
     return 0.0
 
 
-def read_traffic(kernel: str, workload_name: str):
-    """HBM bytes per dispatch measured by rocprofv3 --pmc, if a summary for
-    this kernel and workload exists and was taken from the current sources."""
-    import hashlib
+CSRC = os.path.join(ROOT, "paper_2008_03909_amd", "csrc")
 
+
+def kernel_digest(kernel: str):
+    """Digest of a kernel's source: its definition (from the template line
+    before ``__global__`` to the closing brace) plus the shared device
+    header.  A profile taken from other source text is stale."""
+    import glob
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    found = False
+    for path in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        text = open(path).read()
+        m = re.search(r"__global__[^;{]*?\b" + re.escape(kernel) + r"\s*\(", text)
+        if not m:
+            continue
+        a = text.rfind("\n\n", 0, m.start()) + 2
+        depth, i = 0, text.index("{", m.end())
+        for j in range(i, len(text)):
+            depth += {"{": 1, "}": -1}.get(text[j], 0)
+            if depth == 0:
+                break
+        h.update(text[a:j + 1].encode())
+        found = True
+        break
+    if not found:
+        return None
+    h.update(open(os.path.join(CSRC, "cc_device.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload_name: str):
+    """HBM bytes per dispatch of `kernel` from a committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a plain
+    copy kernel of known size gives), or None if there is none or it was
+    taken from other kernel source."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload_name}.txt")
     if not os.path.exists(path):
         return None
@@ -86,11 +119,8 @@ def read_traffic(kernel: str, workload_name: str):
         if "=" in line and not line.startswith("#"):
             a, b = line.split("=", 1)
             kv[a.strip()] = b.strip()
-    src = kv.get("source")
-    if src:
-        h = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
-        if h != kv.get("source_sha256_16"):
-            return None
+    if kv.get("kernel_digest") != kernel_digest(kernel):
+        return None
     try:
         return float(kv["hbm_bytes_per_dispatch"])
     except (KeyError, ValueError):
