@@ -174,6 +174,20 @@ cc_status cc_sample_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, 
                         const int32_t* adj, const cc_variant* v, void* workspace, size_t ws_bytes,
                         int32_t* labels_out, int32_t* lmax_out_host, void* hip_stream);
 
+/* labels_out[v] = min id of v's component for an undirected pair list
+ * (u[i], v[i]), i < num_pairs, device int32 arrays (Section 2's edge-list
+ * format; self-loops and duplicates allowed, ids must be in [0, n)).  The
+ * pairs are first turned into a symmetric deduplicated CSR (as
+ * cc_build_csr, int64 offsets when 2*num_pairs >= 2^31) that lives in the
+ * workspace, then labelled as by cc_connectivity_csr with variant var.
+ * workspace: device buffer of >= cc_coo_workspace_bytes (any alignment).
+ * Synchronises hip_stream twice (the sort's size and the edge count).
+ * Ids outside [0, n) set the device error word and are dropped. */
+cc_status cc_coo_workspace_bytes(int64_t n, int64_t num_pairs, const cc_variant* v, size_t* bytes);
+cc_status cc_connectivity_coo(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v,
+                              const cc_variant* var, void* workspace, size_t ws_bytes, int32_t* labels_out,
+                              int64_t* num_components_dev, void* hip_stream);
+
 /* ---- ingest: undirected pair list -> symmetric CSR (Section 2 formats) -------
  * Output: both orientations of every pair with u != v, rows sorted
  * ascending, duplicates removed iff dedup != 0.  adj_out needs capacity
@@ -273,22 +287,35 @@ cc_status cc_mlp_adam(float* master, uint16_t* params, const float* grads, float
                       float lr, float beta1, float beta2, float eps, int32_t step, void* hip_stream);
 /* dst = BF16(src), round to nearest even. */
 cc_status cc_mlp_pack_bf16(const float* src, uint16_t* dst, int64_t count, void* hip_stream);
-/* The 16 features of a symmetric CSR (documented in the selector source):
- * degree statistics, k-out sample statistics (the sample is left in
- * labels_scratch, n int32) and a BFS probe capped at 8 levels.
- * workspace as for cc_connectivity_csr with the default variant.
- * Synchronises hip_stream. */
+/* The 16 features of a symmetric CSR: degree statistics (log2 n,
+ * log2(m+1), m/n, coefficient of variation, max/mean, fractions of degree 0,
+ * 1 and <= 2, skewness, [m/n < 3], log2(max degree + 1)); statistics of
+ * 4096 seeded vertex draws (fraction whose first neighbour id is smaller,
+ * mean log-distance to it, mean log-degree of it); and a BFS from a seeded
+ * source that expands whole levels within 8 levels and 4096 scanned
+ * adjacency entries (levels expanded, fraction of vertices reached).  The
+ * exact definitions are in the selector source.  workspace as for
+ * cc_connectivity_csr with the default variant.  Synchronises hip_stream. */
 cc_status cc_graph_features(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
-                            const int32_t* adj, void* workspace, size_t ws_bytes, int32_t* labels_scratch,
-                            float* features_host, void* hip_stream);
-/* Static connectivity with the arm the model predicts fastest: features,
- * normalisation x = (f - norm_host[0:16]) / norm_host[16:32], forward pass,
- * argmin over the K arms (host array of variants), then the chosen arm -- an
- * arm that samples like the default k-out continues from the features'
- * sample.  params_dev NULL runs the default variant.  chosen_host (nullable)
- * gets the arm index (-1 for the default); features_host (nullable) gets the
- * 16 features.  workspace: at least the largest cc_workspace_bytes over the
- * arms and the default. */
+                            const int32_t* adj, void* workspace, size_t ws_bytes, float* features_host,
+                            void* hip_stream);
+/* The arm the model predicts fastest, without running it: features,
+ * normalisation and forward pass as in cc_connectivity_auto, then
+ * out_host = arms[argmin].  params_dev NULL gives the default variant
+ * (chosen -1).  workspace as for cc_connectivity_auto.  Synchronises
+ * hip_stream once. */
+cc_status cc_select_variant(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                            const int32_t* adj, const uint16_t* params_dev, int32_t K, const cc_variant* arms,
+                            const float* norm_host, void* workspace, size_t ws_bytes, cc_variant* out_host,
+                            int32_t* chosen_host, float* features_host, void* hip_stream);
+/* Static connectivity with the arm the model predicts fastest: the 16
+ * features, x = (f - norm_host[0:16]) / norm_host[16:32], the forward pass
+ * and the argmin over the K arms (host array of variants) all run on the
+ * device and are read back with one synchronisation, then the chosen arm
+ * runs as cc_connectivity_csr.  params_dev NULL runs the default variant.
+ * chosen_host (nullable) gets the arm index (-1 for the default);
+ * features_host (nullable) gets the 16 features.  workspace: at least the
+ * largest cc_workspace_bytes over the arms and the default. */
 cc_status cc_connectivity_auto(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
                                const int32_t* adj, const uint16_t* params_dev, int32_t K, const cc_variant* arms,
                                const float* norm_host, void* workspace, size_t ws_bytes, int32_t* labels_out,

@@ -67,6 +67,8 @@ def _load():
         lib.oracle_splitmix_out.restype = ctypes.c_uint64
         lib.oracle_bfs_levels.argtypes = [i64, _i64p, _i32p, ctypes.c_int32, ctypes.c_int32, _i32p]
         lib.oracle_bfs_levels.restype = i64
+        lib.oracle_bfs_budget.argtypes = [i64, _i64p, _i32p, ctypes.c_int32, ctypes.c_int32, i64, _i32p]
+        lib.oracle_bfs_budget.restype = i64
         _lib = lib
     return _lib
 
@@ -202,6 +204,49 @@ def bfs_levels(n: int, offsets, adj, source: int, cap: int):
     r = _load().oracle_bfs_levels(n, _p64(offsets), _p32(adj) if adj.size else _p32(np.zeros(1, np.int32)),
                                   source, cap, _p32(lv))
     return int(r), int(lv[0])
+
+
+def bfs_budget(n: int, offsets, adj, source: int, cap: int, edge_budget: int):
+    """BFS that expands whole levels while the scanned adjacency entries stay
+    within edge_budget and at most cap levels: (reached, levels)."""
+    offsets, adj = _c(offsets, np.int64), _c(adj, np.int32)
+    lv = np.zeros(1, np.int32)
+    r = _load().oracle_bfs_budget(n, _p64(offsets), _p32(adj) if adj.size else _p32(np.zeros(1, np.int32)),
+                                  source, cap, edge_budget, _p32(lv))
+    return int(r), int(lv[0])
+
+
+FEATURE_TAG = 0x66656174       # "feat": stream of the selector's draws
+FEATURE_SAMPLES = 4096
+PROBE_LEVELS = 8
+PROBE_EDGES = 4096
+
+
+def sampled_features(n: int, offsets, adj, seed: int):
+    """The selector's sampled features, from their definitions (FP64):
+    vertices v_i = splitmix(key, i) mod n for i < 4096 with key =
+    splitmix(seed, "feat"); over the drawn vertices that have an edge, with
+    f = the first entry of v's row: 9 = mean [f < v], 10 = mean
+    log2(1 + |v - f|) / log2(n + 1), 11 = mean log2(1 + deg f); then a
+    whole-level BFS from splitmix(key, 4096) mod n within 8 levels and 4096
+    scanned entries: 12 = levels, 13 = reached / n."""
+    off = np.asarray(offsets, np.int64)
+    a = np.asarray(adj)
+    key = splitmix_out(seed, FEATURE_TAG)
+    cnt = down = loc = hub = 0.0
+    for i in range(FEATURE_SAMPLES):
+        v = splitmix_out(key, i) % n
+        if off[v + 1] > off[v]:
+            f = int(a[off[v]])
+            cnt += 1
+            down += f < v
+            loc += np.log2(1.0 + abs(v - f)) / np.log2(n + 1.0)
+            hub += np.log2(1.0 + float(off[f + 1] - off[f]))
+    src = splitmix_out(key, FEATURE_SAMPLES) % n
+    reached, levels = bfs_budget(n, off, a, src, PROBE_LEVELS, PROBE_EDGES)
+    out = {9: down / cnt if cnt else 0.0, 10: loc / cnt if cnt else 0.0, 11: hub / cnt if cnt else 0.0,
+           12: float(levels), 13: reached / n}
+    return out
 
 
 def degree_features(offsets):

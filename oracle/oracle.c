@@ -277,3 +277,46 @@ int64_t oracle_bfs_levels(int64_t n, const int64_t* offsets, const int32_t* adj,
   *levels_out = levels;
   return tail;
 }
+
+/* Breadth-first search from `source` that expands whole levels only: before
+ * a level is expanded, the degrees of its frontier are summed, and the
+ * search stops if expanding it would take the number of scanned adjacency
+ * entries above edge_budget, or when `cap` levels have been expanded or the
+ * frontier is empty.  Returns the number of vertices discovered by the
+ * expanded levels (the source included) and writes that number of levels.
+ * Which vertices a level discovers does not depend on the scan order, so
+ * both results are unique. */
+int64_t oracle_bfs_budget(int64_t n, const int64_t* offsets, const int32_t* adj, int32_t source, int32_t cap,
+                          int64_t edge_budget, int32_t* levels_out) {
+  uint8_t* seen = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+  int32_t* cur = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t* nxt = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int64_t nc = 1, reached = 1, scanned = 0;
+  int32_t levels = 0;
+  cur[0] = source;
+  seen[source] = 1;
+  while (nc > 0 && levels < cap) {
+    int64_t fe = 0;
+    for (int64_t i = 0; i < nc; ++i) fe += offsets[cur[i] + 1] - offsets[cur[i]];
+    if (scanned + fe > edge_budget) break;
+    int64_t nn = 0;
+    for (int64_t i = 0; i < nc; ++i)
+      for (int64_t j = offsets[cur[i]]; j < offsets[cur[i] + 1]; ++j)
+        if (!seen[adj[j]]) {
+          seen[adj[j]] = 1;
+          nxt[nn++] = adj[j];
+        }
+    scanned += fe;
+    ++levels;
+    reached += nn;
+    int32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+    nc = nn;
+  }
+  free(seen);
+  free(cur);
+  free(nxt);
+  *levels_out = levels;
+  return reached;
+}

@@ -115,6 +115,10 @@ def lib():
                                            ctypes.c_size_t, _vp, _vp, _vp]),
             "cc_sample_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
                                      ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_int32), _vp]),
+            "cc_coo_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_variant),
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+            "cc_connectivity_coo": (_int, [_vp, _i64, _i64, _vp, _vp, ctypes.POINTER(cc_variant), _vp,
+                                           ctypes.c_size_t, _vp, _vp, _vp]),
             "cc_csr_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
             "cc_build_csr": (_int, [_vp, _i64, _i64, _vp, _vp, _int, _vp, ctypes.c_size_t, _vp, _int, _vp, _vp,
                                     _vp]),
@@ -141,12 +145,16 @@ def lib():
             "cc_mlp_adam": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_float, ctypes.c_int32, _vp]),
             "cc_mlp_pack_bf16": (_int, [_vp, _vp, _i64, _vp]),
-            "cc_graph_features": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, ctypes.c_size_t, _vp,
+            "cc_graph_features": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, ctypes.c_size_t,
                                          ctypes.POINTER(ctypes.c_float), _vp]),
             "cc_connectivity_auto": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, ctypes.c_int32,
                                             ctypes.POINTER(cc_variant), ctypes.POINTER(ctypes.c_float), _vp,
                                             ctypes.c_size_t, _vp, _vp, ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_float), _vp]),
+            "cc_select_variant": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, ctypes.c_int32,
+                                         ctypes.POINTER(cc_variant), ctypes.POINTER(ctypes.c_float), _vp,
+                                         ctypes.c_size_t, ctypes.POINTER(cc_variant),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float), _vp]),
             "cc_calib_copy": (_int, [_vp, _vp, ctypes.c_size_t, _vp]),
             "cc_calib_workspace_bytes": (_int, [_i64, ctypes.POINTER(ctypes.c_size_t)]),
             "cc_calib_edges": (_int, [_i64, _i64, _vp, _int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -316,6 +324,28 @@ def connectivity_csr(ctx: Context, g: CSR, variant: cc_variant | None = None, la
     _check(lib().cc_connectivity_csr(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), ctypes.byref(v),
                                      _ptr(ws), ws.numel(), _ptr(labels), _ptr(ncomp), _stream_handle(stream)),
            "cc_connectivity_csr")
+    return labels, ncomp
+
+
+def connectivity_coo(ctx: Context, n: int, u, v, variant: cc_variant | None = None,
+                     labels: torch.Tensor | None = None, ncomp: torch.Tensor | None = None, stream=None):
+    """cc_connectivity_coo on an undirected pair list (device or host int32
+    arrays; host arrays are copied to the device first).  Returns (labels,
+    num_components int64[1]) on the device."""
+    var = variant if variant is not None else default_variant()
+    dev = ctx.torch_device
+    ut = _dev_tensor(u, torch.int32, dev)
+    vt = _dev_tensor(v, torch.int32, dev)
+    k = int(ut.numel())
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+    if ncomp is None:
+        ncomp = torch.empty(1, dtype=torch.int64, device=dev)
+    wsb = ctypes.c_size_t()
+    _check(lib().cc_coo_workspace_bytes(n, k, ctypes.byref(var), ctypes.byref(wsb)), "cc_coo_workspace_bytes")
+    ws = ctx.workspace(int(wsb.value))
+    _check(lib().cc_connectivity_coo(ctx.h, n, k, _ptr(ut), _ptr(vt), ctypes.byref(var), _ptr(ws), ws.numel(),
+                                     _ptr(labels), _ptr(ncomp), _stream_handle(stream)), "cc_connectivity_coo")
     return labels, ncomp
 
 
@@ -512,16 +542,62 @@ def mlp_pack_bf16(src: torch.Tensor, dst: torch.Tensor | None = None, stream=Non
     return dst
 
 
-def graph_features(ctx: Context, g: CSR, labels_scratch: torch.Tensor | None = None, stream=None):
-    """The 16 selector features; also returns the k-out sample labels."""
-    dev = ctx.torch_device
-    if labels_scratch is None:
-        labels_scratch = torch.empty(g.n, dtype=torch.int32, device=dev)
+def graph_features(ctx: Context, g: CSR, stream=None):
+    """The 16 selector features (host list of floats)."""
     ws = ctx.workspace(workspace_bytes(g.n, g.m, default_variant()))
     f = (ctypes.c_float * 16)()
-    _check(lib().cc_graph_features(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(ws), ws.numel(),
-                                   _ptr(labels_scratch), f, _stream_handle(stream)), "cc_graph_features")
-    return [float(x) for x in f], labels_scratch
+    _check(lib().cc_graph_features(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(ws), ws.numel(), f,
+                                   _stream_handle(stream)), "cc_graph_features")
+    return [float(x) for x in f]
+
+
+class Selector:
+    """A trained model bound to its arms: the ctypes arrays are built once so
+    that a call costs one C call (features, forward pass and argmin on the
+    device, then the chosen arm)."""
+
+    def __init__(self, ctx: Context, params_bf16: torch.Tensor | None, arms, norm):
+        self.ctx = ctx
+        self.params = params_bf16
+        self.arms = list(arms) if arms is not None else []
+        self.K = len(self.arms) if params_bf16 is not None else 0
+        self._arr = (cc_variant * max(self.K, 1))(*self.arms[:self.K]) if self.K else None
+        self._norm = (ctypes.c_float * 32)(*[float(x) for x in norm]) if norm is not None else None
+        self._need = {}
+        self._feat = (ctypes.c_float * 16)()
+        self._chosen = ctypes.c_int32(-2)
+
+    def _ws(self, g: CSR):
+        key = (g.n, g.m)
+        if key not in self._need:
+            need = workspace_bytes(g.n, g.m, default_variant())
+            for a in self.arms[:self.K]:
+                need = max(need, workspace_bytes(g.n, g.m, a))
+            self._need[key] = need
+        return self.ctx.workspace(self._need[key])
+
+    def connectivity(self, g: CSR, labels: torch.Tensor, ncomp: torch.Tensor, stream=None):
+        """cc_connectivity_auto: returns the chosen arm index (-1 = default)."""
+        ws = self._ws(g)
+        _check(lib().cc_connectivity_auto(self.ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj),
+                                          _ptr(self.params), self.K, self._arr, self._norm, _ptr(ws), ws.numel(),
+                                          _ptr(labels), _ptr(ncomp), ctypes.byref(self._chosen), self._feat,
+                                          _stream_handle(stream)), "cc_connectivity_auto")
+        return self._chosen.value
+
+    def features(self):
+        """Features of the last call."""
+        return [float(x) for x in self._feat]
+
+    def select(self, g: CSR, stream=None):
+        """cc_select_variant: (variant, arm index or -1, features) without running it."""
+        ws = self._ws(g)
+        out = cc_variant()
+        _check(lib().cc_select_variant(self.ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj),
+                                       _ptr(self.params), self.K, self._arr, self._norm, _ptr(ws), ws.numel(),
+                                       ctypes.byref(out), ctypes.byref(self._chosen), self._feat,
+                                       _stream_handle(stream)), "cc_select_variant")
+        return out, self._chosen.value, self.features()
 
 
 def connectivity_auto(ctx: Context, g: CSR, params_bf16: torch.Tensor | None, arms, norm, labels=None, ncomp=None,
@@ -532,21 +608,14 @@ def connectivity_auto(ctx: Context, g: CSR, params_bf16: torch.Tensor | None, ar
         labels = torch.empty(g.n, dtype=torch.int32, device=dev)
     if ncomp is None:
         ncomp = torch.empty(1, dtype=torch.int64, device=dev)
-    K = len(arms) if arms is not None else 0
-    need = workspace_bytes(g.n, g.m, default_variant())
-    arr = None
-    if arms is not None:
-        arr = (cc_variant * K)(*arms)
-        for a in arms:
-            need = max(need, workspace_bytes(g.n, g.m, a))
-    nrm = (ctypes.c_float * 32)(*[float(x) for x in norm]) if norm is not None else None
-    ws = ctx.workspace(need)
-    chosen = ctypes.c_int32(-2)
-    f = (ctypes.c_float * 16)()
-    _check(lib().cc_connectivity_auto(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(params_bf16), K,
-                                      arr, nrm, _ptr(ws), ws.numel(), _ptr(labels), _ptr(ncomp),
-                                      ctypes.byref(chosen), f, _stream_handle(stream)), "cc_connectivity_auto")
-    return labels, ncomp, chosen.value, [float(x) for x in f]
+    sel = Selector(ctx, params_bf16, arms, norm)
+    chosen = sel.connectivity(g, labels, ncomp, stream)
+    return labels, ncomp, chosen, sel.features()
+
+
+def select_variant(ctx: Context, g: CSR, params_bf16: torch.Tensor | None, arms, norm, stream=None):
+    """cc_select_variant: (chosen variant, arm index or -1, features) without running it."""
+    return Selector(ctx, params_bf16, arms, norm).select(g, stream)
 
 
 # ---- calibration -------------------------------------------------------------

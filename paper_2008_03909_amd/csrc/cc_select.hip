@@ -8,14 +8,18 @@
 // to finish).  It changes speed only: every arm returns the same canonical
 // labels.
 //
-// Features (16 FP32, host-computed from device reductions):
+// Features (16 FP32), computed on the device in three launches and read back
+// with the model's choice in one copy:
 //   0 log2 n          1 log2(m+1)         2 m/n               3 degree CV
 //   4 max/mean deg    5 frac deg 0        6 frac deg 1        7 frac deg <= 2
-//   8 degree skew     9 k-out L_max frac  10 k-out comps / n  11 k-out inter-component edge frac (16384 sampled edges)
-//   12 BFS levels (<= 8) from a seeded source   13 BFS coverage at the cap
-//   14 [m/n < 3]      15 log2(max deg + 1)
-// The k-out sample (k = 2 hybrid, the default variant's) is left in the
-// caller's label buffer, so an arm with that sampler continues from it.
+//   8 degree skew     14 [m/n < 3]        15 log2(max deg + 1)
+// and, over 4096 seeded vertex draws v (those with an edge; f = the first
+// entry of v's row):
+//   9 mean [f < v]    10 mean log2(1 + |v - f|) / log2(n + 1)
+//   11 mean log2(1 + deg f)
+// and a BFS from a seeded source that expands whole levels while at most
+// 4096 adjacency entries are scanned and at most 8 levels:
+//   12 levels expanded     13 vertices reached / n
 //
 // MLP: parameters packed as BF16 [W1 16x64 | b1 64 | W2 64x64 | b2 64 |
 // W3 64xK | b3 K] (row-major, input index first).  Inputs and hidden
@@ -66,23 +70,20 @@ __device__ __forceinline__ MlpView mlp_view(const uint16_t* p, int K) {
   return v;
 }
 
-// One block per row.  cache (nullable): per row [z1 64 | a1 64 | z2 64 | a2 64].
-__global__ void __launch_bounds__(kH) k_mlp_forward(const uint16_t* __restrict__ params, int K, int B,
-                                                    const float* __restrict__ X, float* __restrict__ Y,
-                                                    float* __restrict__ cache) {
-  __shared__ float x[kIn], a1[kH], a2[kH];
-  const int r = blockIdx.x, t = threadIdx.x;
-  if (r >= B) return;
-  const MlpView P = mlp_view(params, K);
-  if (t < kIn) x[t] = bf16_round(X[(int64_t)r * kIn + t]);
+// One row of the forward pass by a block of kH threads: xin (FP32, kIn
+// values) -> Y (K values).  cache (nullable): [z1 64 | a1 64 | z2 64 | a2 64].
+__device__ __forceinline__ void mlp_forward_row(const MlpView& P, int K, const float* xin, float* x, float* a1,
+                                                float* a2, float* Y, float* cache) {
+  const int t = threadIdx.x;
+  if (t < kIn) x[t] = bf16_round(xin[t]);
   __syncthreads();
   float z = bf16_to_f32(P.b1[t]);
   for (int i = 0; i < kIn; ++i) z += x[i] * bf16_to_f32(P.W1[i * kH + t]);
   const float h1 = bf16_round(z > 0.f ? z : 0.f);
   a1[t] = h1;
   if (cache) {
-    cache[(int64_t)r * 4 * kH + t] = z;
-    cache[(int64_t)r * 4 * kH + kH + t] = h1;
+    cache[t] = z;
+    cache[kH + t] = h1;
   }
   __syncthreads();
   z = bf16_to_f32(P.b2[t]);
@@ -90,15 +91,26 @@ __global__ void __launch_bounds__(kH) k_mlp_forward(const uint16_t* __restrict__
   const float h2 = bf16_round(z > 0.f ? z : 0.f);
   a2[t] = h2;
   if (cache) {
-    cache[(int64_t)r * 4 * kH + 2 * kH + t] = z;
-    cache[(int64_t)r * 4 * kH + 3 * kH + t] = h2;
+    cache[2 * kH + t] = z;
+    cache[3 * kH + t] = h2;
   }
   __syncthreads();
   for (int j = t; j < K; j += kH) {
     float y = bf16_to_f32(P.b3[j]);
     for (int i = 0; i < kH; ++i) y += a2[i] * bf16_to_f32(P.W3[i * K + j]);
-    Y[(int64_t)r * K + j] = y;
+    Y[j] = y;
   }
+}
+
+// One block per row.
+__global__ void __launch_bounds__(kH) k_mlp_forward(const uint16_t* __restrict__ params, int K, int B,
+                                                    const float* __restrict__ X, float* __restrict__ Y,
+                                                    float* __restrict__ cache) {
+  __shared__ float x[kIn], a1[kH], a2[kH];
+  const int r = blockIdx.x;
+  if (r >= B) return;
+  mlp_forward_row(mlp_view(params, K), K, X + (int64_t)r * kIn, x, a1, a2, Y + (int64_t)r * K,
+                  cache ? cache + (int64_t)r * 4 * kH : nullptr);
 }
 
 // Gradients of the mean squared error L = mean_{r,j} (Y - T)^2 with respect
@@ -212,150 +224,270 @@ __global__ void k_f32_to_bf16(const float* __restrict__ src, uint16_t* __restric
 
 // ---- feature kernels ----------------------------------------------------------
 
-// Per-block partials: [sum d, sum d^2, sum d^3, max d, #d==0, #d==1, #d<=2, 0].
-template <typename I>
-__global__ void __launch_bounds__(256) k_deg_stats(int64_t n, const I* __restrict__ off, double* __restrict__ part) {
-  __shared__ double red[8][256 / kWave];
-  double s1 = 0, s2 = 0, s3 = 0, mx = 0, c0 = 0, c1 = 0, c2 = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
-    const double d = (double)((int64_t)off[v + 1] - (int64_t)off[v]);
-    s1 += d;
-    s2 += d * d;
-    s3 += d * d * d;
-    mx = d > mx ? d : mx;
-    c0 += d == 0.0;
-    c1 += d == 1.0;
-    c2 += d <= 2.0;
-  }
-  double vals[7] = {s1, s2, s3, mx, c0, c1, c2};
-  for (int q = 0; q < 7; ++q) {
-    double x = vals[q];
-    for (int o = 32; o > 0; o >>= 1) {
-      const double y = __shfl_xor(x, o, kWave);
-      x = (q == 3) ? (y > x ? y : x) : x + y;
-    }
-    if (lane_id() == 0) red[q][threadIdx.x / kWave] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < 7) {
-    const int q = threadIdx.x;
-    double x = red[q][0];
-    for (int w = 1; w < 256 / kWave; ++w) x = (q == 3) ? (red[q][w] > x ? red[q][w] : x) : x + red[q][w];
-    part[(int64_t)blockIdx.x * 8 + q] = x;
-  }
-}
+constexpr int kFeatBlocks = 512;
+constexpr int kFeatSamples = 4096;
+constexpr int kProbeLevels = 8;
+constexpr int kProbeEdges = 4096;
+constexpr int kProbeSlots = 8192;     // LDS hash of discovered vertices: load <= 1/2
+constexpr int kPart = 12;             // doubles per block of partial sums
+constexpr uint64_t kTagFeat = 0x66656174ULL;  // "feat"
 
-// Sampled-labelling statistics: [#roots, #label == lmax, #sampled edges with
-// different endpoint labels, #sampled edges].
+// Selector area of the workspace (64 KB): partials, probe result, feature
+// vector and choice, normalisation, scores.
+constexpr size_t kSelPart = 0;
+constexpr size_t kSelProbe = kSelPart + (size_t)kFeatBlocks * kPart * 8;
+constexpr size_t kSelOut = kSelProbe + 64;     // 16 floats + chosen (int32)
+constexpr size_t kSelNorm = kSelOut + 128;     // 32 floats
+constexpr size_t kSelY = kSelNorm + 128;       // K <= 128 floats
+static_assert(kSelY + kMaxArms * 4 <= 65536, "selector area");
+
+__device__ __forceinline__ double max_d(double a, double b) { return b > a ? b : a; }
+
+// Per-block partials: [sum d, sum d^2, sum d^3, max d, #d==0, #d==1, #d<=2,
+// #draws with an edge, #(f < v), sum locality, sum log2(1 + deg f), 0].
 template <typename I>
-__global__ void __launch_bounds__(256) k_label_stats(int64_t n, int64_t m, const I* __restrict__ off,
-                                                     const int32_t* __restrict__ adj,
-                                                     const int32_t* __restrict__ P, const DevScalars* sc,
-                                                     uint64_t key, int nsamples,
-                                                     unsigned long long* __restrict__ out) {
-  const int32_t L = sc->lmax;
-  unsigned long long roots = 0, inl = 0, diff = 0, samp = 0;
+__global__ void __launch_bounds__(256) k_feat_pass(int64_t n, const I* __restrict__ off,
+                                                   const int32_t* __restrict__ adj, uint64_t key,
+                                                   double* __restrict__ part) {
+  __shared__ double red[kPart][256 / kWave];
+  double q[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t v = gid; v < n; v += stride) {
-    const int32_t p = P[v];
-    roots += p == (int32_t)v;
-    inl += p == L;
+    const double d = (double)((int64_t)off[v + 1] - (int64_t)off[v]);
+    q[0] += d;
+    q[1] += d * d;
+    q[2] += d * d * d;
+    q[3] = max_d(q[3], d);
+    q[4] += d == 0.0;
+    q[5] += d == 1.0;
+    q[6] += d <= 2.0;
   }
-  if (m > 0)
-    for (int64_t i = gid; i < nsamples; i += stride) {
-      const int64_t e = (int64_t)(sm_out(key, (uint64_t)i) % (uint64_t)m);
-      int64_t lo = 0, hi = n - 1;  // owner: largest v with off[v] <= e
+  const double ln = log2((double)n + 1.0);
+  for (int64_t i = gid; i < kFeatSamples; i += stride) {
+    const int64_t v = (int64_t)(sm_out(key, (uint64_t)i) % (uint64_t)n);
+    const int64_t b = (int64_t)off[v];
+    if ((int64_t)off[v + 1] == b) continue;
+    const int64_t f = adj[b];
+    q[7] += 1.0;
+    q[8] += f < v;
+    q[9] += log2(1.0 + (double)(v > f ? v - f : f - v)) / ln;
+    q[10] += log2(1.0 + (double)((int64_t)off[f + 1] - (int64_t)off[f]));
+  }
+  for (int k = 0; k < kPart; ++k) {
+    double x = q[k];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double y = __shfl_xor(x, o, kWave);
+      x = (k == 3) ? max_d(x, y) : x + y;
+    }
+    if (lane_id() == 0) red[k][threadIdx.x / kWave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPart) {
+    const int k = threadIdx.x;
+    double x = red[k][0];
+    for (int w = 1; w < 256 / kWave; ++w) x = (k == 3) ? max_d(x, red[k][w]) : x + red[k][w];
+    part[(int64_t)blockIdx.x * kPart + k] = x;
+  }
+}
+
+// Whole-level BFS within an edge budget, in one block.  Discovered vertices
+// live in an LDS hash table; the two frontier queues (capacity n each) are
+// in the workspace.  Before a level is expanded the block sums its
+// frontier's degrees and stops if the budget would be exceeded, so which
+// vertices are reached does not depend on scheduling.  out: [levels, reached].
+constexpr int kProbeThreads = 256;
+template <typename I>
+__global__ void __launch_bounds__(kProbeThreads) k_feat_probe(const I* __restrict__ off,
+                                                              const int32_t* __restrict__ adj, int32_t src,
+                                                              int32_t* __restrict__ qa, int32_t* __restrict__ qb,
+                                                              int64_t* __restrict__ out) {
+  __shared__ int32_t slots[kProbeSlots];
+  __shared__ int32_t pre[kProbeEdges + 2];   // frontier degree prefix (frontier <= kProbeEdges + 1)
+  __shared__ long long tsum[kProbeThreads];
+  __shared__ long long total;
+  __shared__ int32_t nnext;
+  const int t = threadIdx.x;
+  for (int i = t; i < kProbeSlots; i += kProbeThreads) slots[i] = -1;
+  __syncthreads();
+  auto insert = [&](int32_t w) -> bool {
+    uint32_t h = ((uint32_t)w * 2654435761u) & (kProbeSlots - 1);
+    while (true) {
+      const int32_t prev = atomicCAS(&slots[h], -1, w);
+      if (prev == -1) return true;
+      if (prev == w) return false;
+      h = (h + 1) & (kProbeSlots - 1);
+    }
+  };
+  if (t == 0) {
+    insert(src);
+    qa[0] = src;
+  }
+  int32_t* cur = qa;
+  int32_t* nxt = qb;
+  int64_t f = 1, reached = 1, scanned = 0;
+  int levels = 0;
+  __syncthreads();
+  while (f > 0 && levels < kProbeLevels) {
+    // frontier degrees: each thread sums a contiguous chunk, the chunk sums
+    // are scanned, and (only if the level fits the budget) each thread
+    // writes the int32 prefix of its chunk
+    const int64_t chunk = (f + kProbeThreads - 1) / kProbeThreads;
+    const int64_t i0 = t * chunk < f ? t * chunk : f;
+    const int64_t i1 = i0 + chunk < f ? i0 + chunk : f;
+    long long s = 0;
+    for (int64_t i = i0; i < i1; ++i) s += (long long)((int64_t)off[cur[i] + 1] - (int64_t)off[cur[i]]);
+    tsum[t] = s;
+    __syncthreads();
+    if (t == 0) {
+      long long acc = 0;
+      for (int i = 0; i < kProbeThreads; ++i) {
+        const long long x = tsum[i];
+        tsum[i] = acc;
+        acc += x;
+      }
+      total = acc;
+      nnext = 0;
+    }
+    __syncthreads();
+    const long long fe = total;
+    if (scanned + fe > kProbeEdges) break;
+    {
+      int32_t acc = (int32_t)tsum[t];
+      for (int64_t i = i0; i < i1; ++i) {
+        pre[i] = acc;
+        acc += (int32_t)((int64_t)off[cur[i] + 1] - (int64_t)off[cur[i]]);
+      }
+      if (t == 0) pre[f] = (int32_t)fe;
+    }
+    __syncthreads();
+    for (int32_t e = t; e < (int32_t)fe; e += kProbeThreads) {
+      int64_t lo = 0, hi = f - 1;   // owner: largest i with pre[i] <= e
       while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
-        if ((int64_t)off[mid] <= e) lo = mid;
+        if (pre[mid] <= e) lo = mid;
         else hi = mid - 1;
       }
-      diff += P[lo] != P[adj[e]];
-      ++samp;
+      const int32_t x = cur[lo];
+      const int32_t w = adj[(int64_t)off[x] + (e - pre[lo])];
+      if (insert(w)) nxt[atomicAdd(&nnext, 1)] = w;
     }
-  roots = wave_sum(roots);
-  inl = wave_sum(inl);
-  diff = wave_sum(diff);
-  samp = wave_sum(samp);
-  if (lane_id() == 0) {
-    if (roots) atomicAdd(out + 0, roots);
-    if (inl) atomicAdd(out + 1, inl);
-    if (diff) atomicAdd(out + 2, diff);
-    if (samp) atomicAdd(out + 3, samp);
+    __syncthreads();
+    scanned += fe;
+    ++levels;
+    f = nnext;
+    reached += f;
+    int32_t* tq = cur;
+    cur = nxt;
+    nxt = tq;
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = levels;
+    out[1] = reached;
   }
 }
 
-__global__ void k_zero_u64(unsigned long long* p, int count) {
-  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0ull;
+// Reduces the partials into the 16 features (written to out[0..15]); with a
+// model, normalises them, runs the forward pass and writes the argmin arm
+// (smallest index on ties) to out[16] as an int32, else -1.
+__global__ void __launch_bounds__(kH) k_feat_finish(int64_t n, int64_t m, const double* __restrict__ part,
+                                                    int nblocks, const int64_t* __restrict__ probe,
+                                                    const uint16_t* __restrict__ params, int K,
+                                                    const float* __restrict__ norm, float* __restrict__ out,
+                                                    float* __restrict__ Y) {
+  __shared__ double red[kPart][kH];
+  __shared__ float feat[kIn], x[kIn], a1[kH], a2[kH];
+  const int t = threadIdx.x;
+  double q[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = t; b < nblocks; b += kH)
+    for (int k = 0; k < kPart; ++k) q[k] = (k == 3) ? max_d(q[k], part[(int64_t)b * kPart + k]) : q[k] + part[(int64_t)b * kPart + k];
+  for (int k = 0; k < kPart; ++k) red[k][t] = q[k];
+  __syncthreads();
+  if (t == 0) {
+    for (int k = 0; k < kPart; ++k) {
+      double s = red[k][0];
+      for (int i = 1; i < kH; ++i) s = (k == 3) ? max_d(s, red[k][i]) : s + red[k][i];
+      q[k] = s;
+    }
+    const double dn = (double)n, dm = (double)m;
+    const double mean = q[0] / dn;
+    const double var = q[1] / dn - mean * mean > 0 ? q[1] / dn - mean * mean : 0.0;
+    const double sd = sqrt(var);
+    const double skew = sd > 0 ? (q[2] / dn - 3 * mean * var - mean * mean * mean) / (sd * sd * sd) : 0.0;
+    const double cnt = q[7];
+    feat[0] = (float)log2(dn);
+    feat[1] = (float)log2(dm + 1.0);
+    feat[2] = (float)(dm / dn);
+    feat[3] = (float)(mean > 0 ? sd / mean : 0.0);
+    feat[4] = (float)(mean > 0 ? q[3] / mean : 0.0);
+    feat[5] = (float)(q[4] / dn);
+    feat[6] = (float)(q[5] / dn);
+    feat[7] = (float)(q[6] / dn);
+    feat[8] = (float)(skew > 1e6 ? 1e6 : skew);
+    feat[9] = (float)(cnt > 0 ? q[8] / cnt : 0.0);
+    feat[10] = (float)(cnt > 0 ? q[9] / cnt : 0.0);
+    feat[11] = (float)(cnt > 0 ? q[10] / cnt : 0.0);
+    feat[12] = (float)probe[0];
+    feat[13] = (float)((double)probe[1] / dn);
+    feat[14] = (float)(dm / dn < 3.0 ? 1.0 : 0.0);
+    feat[15] = (float)log2(q[3] + 1.0);
+    for (int i = 0; i < kIn; ++i) out[i] = feat[i];
+  }
+  __syncthreads();
+  if (!params) {
+    if (t == 0) ((int32_t*)out)[kIn] = -1;
+    return;
+  }
+  __shared__ float xin[kIn];
+  if (t < kIn) xin[t] = (feat[t] - norm[t]) / (norm[kIn + t] > 0.f ? norm[kIn + t] : 1.f);
+  __syncthreads();
+  mlp_forward_row(mlp_view(params, K), K, xin, x, a1, a2, Y, nullptr);
+  __syncthreads();
+  if (t == 0) {
+    int c = 0;
+    for (int j = 1; j < K; ++j)
+      if (Y[j] < Y[c]) c = j;
+    ((int32_t*)out)[kIn] = c;
+  }
 }
 
-constexpr int kFeatBlocks = 512;
-constexpr int kIcSamples = 16384;
-constexpr int kBfsFeatureCap = 8;
-constexpr uint64_t kTagFeat = 0x66656174ULL;  // "feat"
-
+// Features and, with a model, the chosen arm; one host synchronisation.
 template <typename I>
-static cc_status features_impl(StaticArgs& a, float* feat) {
-  // degree moments: kFeatBlocks * 8 doubles at the start of the selector area
-  double* part = (double*)(a.ws + a.L.mlp);
-  hipLaunchKernelGGL(k_deg_stats<I>, dim3(kFeatBlocks), dim3(256), 0, a.s, a.n, (const I*)a.off, part);
+static cc_status features_impl(StaticArgs& a, const uint16_t* params, int K, const float* norm_host, float* feat,
+                               int* chosen) {
+  char* sel = a.ws + a.L.mlp;
+  double* part = (double*)(sel + kSelPart);
+  int64_t* probe = (int64_t*)(sel + kSelProbe);
+  float* out = (float*)(sel + kSelOut);
+  float* norm = (float*)(sel + kSelNorm);
+  float* Y = (float*)(sel + kSelY);
+  const uint64_t key = sm_out(a.v->seed, kTagFeat);
+  const unsigned nb = grid_for(a.n, 256, kFeatBlocks);
+  hipLaunchKernelGGL(k_feat_pass<I>, dim3(nb), dim3(256), 0, a.s, a.n, (const I*)a.off, a.adj, key, part);
+  const int32_t src = (int32_t)(sm_out(key, (uint64_t)kFeatSamples) % (uint64_t)a.n);
+  int32_t* qa = (int32_t*)(a.ws + a.L.queue);
+  int32_t* qb = (int32_t*)(a.ws + a.L.queue + align256((size_t)a.n * 4));
+  hipLaunchKernelGGL(k_feat_probe<I>, dim3(1), dim3(kProbeThreads), 0, a.s, (const I*)a.off, a.adj, src, qa, qb,
+                     probe);
+  if (params) CC_HIP(hipMemcpyAsync(norm, norm_host, 2 * kIn * sizeof(float), hipMemcpyHostToDevice, a.s));
+  hipLaunchKernelGGL(k_feat_finish, dim3(1), dim3(kH), 0, a.s, a.n, a.m, (const double*)part, (int)nb,
+                     (const int64_t*)probe, params, K, (const float*)norm, out, Y);
   CC_LAUNCH_CHECK();
-  std::vector<double> hp(kFeatBlocks * 8);
-  CC_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, a.s));
-  // k-out sample into the caller's label buffer
-  cc_status st = static_sample_only(a);
-  if (st != CC_OK) return st;
-  unsigned long long* ls = (unsigned long long*)(a.ws + a.L.mlp + kFeatBlocks * 8 * sizeof(double));
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, a.s, ls, 4);
-  hipLaunchKernelGGL(k_label_stats<I>, dim3(kFeatBlocks), dim3(256), 0, a.s, a.n, a.m, (const I*)a.off, a.adj,
-                     (const int32_t*)a.P, (const DevScalars*)a.ctx->dev, sm_out(a.v->seed, kTagFeat), kIcSamples,
-                     ls);
-  CC_LAUNCH_CHECK();
-  unsigned long long lsh[4];
-  CC_HIP(hipMemcpyAsync(lsh, ls, sizeof(lsh), hipMemcpyDeviceToHost, a.s));
+  float h[kIn + 1];
+  CC_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, a.s));
   CC_HIP(hipStreamSynchronize(a.s));
-  // capped BFS from a seeded source (the labels in P are left untouched)
-  int64_t reached = 0;
-  int32_t levels = 0;
-  const int32_t src = (int32_t)(sm_out(sm_out(a.v->seed, kTagFeat), 1) % (uint64_t)a.n);
-  st = bfs_probe<I>(a, src, kBfsFeatureCap, &reached, &levels);
-  if (st != CC_OK) return st;
-  double s1 = 0, s2 = 0, s3 = 0, mx = 0, c0 = 0, c1 = 0, c2 = 0;
-  for (int b = 0; b < kFeatBlocks; ++b) {
-    const double* p = &hp[b * 8];
-    s1 += p[0], s2 += p[1], s3 += p[2], mx = p[3] > mx ? p[3] : mx, c0 += p[4], c1 += p[5], c2 += p[6];
-  }
-  const double n = (double)a.n, m = (double)a.m;
-  const double mean = s1 / n;
-  const double var = s2 / n - mean * mean > 0 ? s2 / n - mean * mean : 0.0;
-  const double sd = std::sqrt(var);
-  const double skew = sd > 0 ? (s3 / n - 3 * mean * var - mean * mean * mean) / (sd * sd * sd) : 0.0;
-  const double lmax_size = (double)a.ctx->host->lmax_size;
-  feat[0] = (float)std::log2(n);
-  feat[1] = (float)std::log2(m + 1.0);
-  feat[2] = (float)(m / n);
-  feat[3] = (float)(mean > 0 ? sd / mean : 0.0);
-  feat[4] = (float)(mean > 0 ? mx / mean : 0.0);
-  feat[5] = (float)(c0 / n);
-  feat[6] = (float)(c1 / n);
-  feat[7] = (float)(c2 / n);
-  feat[8] = (float)(skew > 1e6 ? 1e6 : skew);
-  feat[9] = (float)(lmax_size / n);
-  feat[10] = (float)((double)lsh[0] / n);
-  feat[11] = (float)(lsh[3] ? (double)lsh[2] / (double)lsh[3] : 0.0);
-  feat[12] = (float)levels;
-  feat[13] = (float)((double)reached / n);
-  feat[14] = (float)(m / n < 3.0 ? 1.0 : 0.0);
-  feat[15] = (float)std::log2(mx + 1.0);
+  memcpy(feat, h, kIn * sizeof(float));
+  int32_t c;
+  memcpy(&c, &h[kIn], sizeof(c));
+  *chosen = c;
   return CC_OK;
 }
 
-static cc_status features(StaticArgs& a, float* feat) {
-  // The sample step resolves lmax into ctx->dev; read it for feature 9.
-  cc_status st = a.o64 ? features_impl<int64_t>(a, feat) : features_impl<int32_t>(a, feat);
-  return st;
+static cc_status features(StaticArgs& a, const uint16_t* params, int K, const float* norm_host, float* feat,
+                          int* chosen) {
+  return a.o64 ? features_impl<int64_t>(a, params, K, norm_host, feat, chosen)
+               : features_impl<int32_t>(a, params, K, norm_host, feat, chosen);
 }
 
 }  // namespace cc
@@ -408,17 +540,77 @@ cc_status cc_mlp_pack_bf16(const float* src, uint16_t* dst, int64_t count, void*
 }
 
 cc_status cc_graph_features(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
-                            const int32_t* adj, void* workspace, size_t ws_bytes, int32_t* labels_scratch,
-                            float* features_host, void* hip_stream) {
+                            const int32_t* adj, void* workspace, size_t ws_bytes, float* features_host,
+                            void* hip_stream) {
   if (!features_host) return fail(CC_EINVAL, "features_host is NULL");
   cc_variant v;
   cc_default_variant(&v);
   StaticArgs a;
-  cc_status st = setup_args(a, ctx, n, m, offsets, offsets_are_64bit, adj, &v, workspace, ws_bytes, labels_scratch,
-                            nullptr, hip_stream);
+  // the features never touch the label array: any non-null pointer will do
+  cc_status st = setup_args(a, ctx, n, m, offsets, offsets_are_64bit, adj, &v, workspace, ws_bytes,
+                            (int32_t*)workspace, nullptr, hip_stream);
   if (st != CC_OK) return st;
-  st = features(a, features_host);
-  return st;
+  int chosen;
+  return features(a, nullptr, 0, nullptr, features_host, &chosen);
+}
+
+}  // extern "C"
+
+static cc_status check_selector_args(int64_t n, int64_t m, const uint16_t* params_dev, int32_t K,
+                                     const cc_variant* arms, const float* norm_host, const cc_variant* def,
+                                     size_t ws_bytes, const void* workspace) {
+  if (params_dev && (K < 1 || K > kMaxArms || !arms || !norm_host)) return fail(CC_EINVAL, "bad selector arguments");
+  if (params_dev)
+    for (int j = 0; j < K; ++j) {
+      cc_status s2 = check_variant(&arms[j], false);
+      if (s2 != CC_OK) return s2;
+    }
+  // the workspace must serve every arm
+  size_t need = ws_layout(n, m, def).total;
+  if (params_dev)
+    for (int j = 0; j < K; ++j) need = std::max(need, ws_layout(n, m, &arms[j]).total);
+  if (!workspace || ws_bytes < need)
+    return fail(CC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+  return CC_OK;
+}
+
+// Features, then (with a model) the arm of smallest predicted log-time;
+// without a model the default variant and chosen = -1.
+static cc_status select_arm(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int o64, const int32_t* adj,
+                            const uint16_t* params_dev, int32_t K, const cc_variant* arms, const float* norm_host,
+                            void* workspace, size_t ws_bytes, void* hip_stream, float* feat, int* chosen,
+                            cc_variant* use) {
+  cc_variant def;
+  cc_default_variant(&def);
+  cc_status st = check_selector_args(n, m, params_dev, K, arms, norm_host, &def, ws_bytes, workspace);
+  if (st != CC_OK) return st;
+  StaticArgs a;
+  st = setup_args(a, ctx, n, m, offsets, o64, adj, &def, workspace, ws_bytes, (int32_t*)workspace, nullptr,
+                  hip_stream);
+  if (st != CC_OK) return st;
+  st = features(a, params_dev, params_dev ? K : 0, norm_host, feat, chosen);
+  if (st != CC_OK) return st;
+  if (!params_dev) *chosen = -1;
+  if (*chosen < -1 || *chosen >= K) return fail(CC_EDEVICE, "selector returned arm %d of %d", *chosen, K);
+  *use = *chosen < 0 ? def : arms[*chosen];
+  return CC_OK;
+}
+
+extern "C" {
+
+cc_status cc_select_variant(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                            const int32_t* adj, const uint16_t* params_dev, int32_t K, const cc_variant* arms,
+                            const float* norm_host, void* workspace, size_t ws_bytes, cc_variant* out_host,
+                            int32_t* chosen_host, float* features_host, void* hip_stream) {
+  if (!out_host) return fail(CC_EINVAL, "out_host is NULL");
+  float feat[kIn];
+  int chosen;
+  cc_status st = select_arm(ctx, n, m, offsets, offsets_are_64bit, adj, params_dev, K, arms, norm_host, workspace,
+                            ws_bytes, hip_stream, feat, &chosen, out_host);
+  if (st != CC_OK) return st;
+  if (chosen_host) *chosen_host = chosen;
+  if (features_host) memcpy(features_host, feat, sizeof(feat));
+  return CC_OK;
 }
 
 cc_status cc_connectivity_auto(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
@@ -426,57 +618,16 @@ cc_status cc_connectivity_auto(cc_ctx* ctx, int64_t n, int64_t m, const void* of
                                const float* norm_host, void* workspace, size_t ws_bytes, int32_t* labels_out,
                                int64_t* num_components_dev, int32_t* chosen_host, float* features_host,
                                void* hip_stream) {
-  if (params_dev && (K < 1 || K > kMaxArms || !arms || !norm_host)) return fail(CC_EINVAL, "bad selector arguments");
-  cc_variant def;
-  cc_default_variant(&def);
-  if (params_dev)
-    for (int j = 0; j < K; ++j) {
-      cc_status s2 = check_variant(&arms[j], false);
-      if (s2 != CC_OK) return s2;
-    }
-  // workspace must serve every arm
-  size_t need = ws_layout(n, m, &def).total;
-  if (params_dev)
-    for (int j = 0; j < K; ++j) need = std::max(need, ws_layout(n, m, &arms[j]).total);
-  if (!workspace || ws_bytes < need) return fail(CC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required",
-                                                 ws_bytes, need);
-  StaticArgs a;
-  cc_status st = setup_args(a, ctx, n, m, offsets, offsets_are_64bit, adj, &def, workspace, ws_bytes, labels_out,
-                            num_components_dev, hip_stream);
-  if (st != CC_OK) return st;
+  if (!labels_out) return fail(CC_EINVAL, "labels_out is NULL");
   float feat[kIn];
-  st = features(a, feat);
+  int chosen;
+  cc_variant use;
+  cc_status st = select_arm(ctx, n, m, offsets, offsets_are_64bit, adj, params_dev, K, arms, norm_host, workspace,
+                            ws_bytes, hip_stream, feat, &chosen, &use);
   if (st != CC_OK) return st;
   if (features_host) memcpy(features_host, feat, sizeof(feat));
-  int chosen = -1;
-  const cc_variant* use = &def;
-  if (params_dev) {
-    float x[kIn];
-    for (int i = 0; i < kIn; ++i) x[i] = (feat[i] - norm_host[i]) / (norm_host[kIn + i] > 0 ? norm_host[kIn + i] : 1.f);
-    float* dx = (float*)(a.ws + a.L.mlp + kFeatBlocks * 8 * sizeof(double) + 256);
-    float* dy = dx + 64;  // K <= 128 scores
-    CC_HIP(hipMemcpyAsync(dx, x, sizeof(x), hipMemcpyHostToDevice, a.s));
-    hipLaunchKernelGGL(k_mlp_forward, dim3(1), dim3(kH), 0, a.s, params_dev, K, 1, (const float*)dx, dy,
-                       (float*)nullptr);
-    CC_LAUNCH_CHECK();
-    std::vector<float> y(K);
-    CC_HIP(hipMemcpyAsync(y.data(), dy, K * sizeof(float), hipMemcpyDeviceToHost, a.s));
-    CC_HIP(hipStreamSynchronize(a.s));
-    chosen = 0;
-    for (int j = 1; j < K; ++j)
-      if (y[j] < y[chosen]) chosen = j;
-    use = &arms[chosen];
-  }
   if (chosen_host) *chosen_host = chosen;
-  // An arm with the features' own sampler continues from that sample.
-  const bool same_sample = use->sample == CC_SAMPLE_KOUT && use->kout_k == def.kout_k &&
-                           use->kout_mode == def.kout_mode && use->seed == def.seed;
-  if (same_sample) {
-    a.v = use;
-    st = static_from_sample(a);
-    return st;
-  }
-  return cc_connectivity_csr(ctx, n, m, offsets, offsets_are_64bit, adj, use, workspace, ws_bytes, labels_out,
+  return cc_connectivity_csr(ctx, n, m, offsets, offsets_are_64bit, adj, &use, workspace, ws_bytes, labels_out,
                              num_components_dev, hip_stream);
 }
 

@@ -16,6 +16,7 @@
 //
 // P is the caller's labels_out buffer: the parent array lives there for the
 // whole call, so the final compression writes the answer in place.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -960,6 +961,65 @@ cc_status cc_sample_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, 
   lm = ctx->host->lmax;
   if (lmax_out_host) *lmax_out_host = lm;
   return CC_OK;
+}
+
+// Pair-list entry: a symmetric deduplicated CSR is built in the front of the
+// workspace (offsets, adjacency, edge count), then the CSR path runs on the
+// rest, which also serves as the build's scratch (the two never overlap in
+// time on one stream).
+struct CooLayout {
+  int o64 = 0;
+  size_t off = 0, adj = 0, mdev = 0, rest = 0, rest_bytes = 0, total = 0;
+};
+
+static cc_status coo_layout(int64_t n, int64_t num_pairs, const cc_variant* v, CooLayout* L) {
+  if (n < 1 || n > 0x7fffffffLL || num_pairs < 0) return fail(CC_EINVAL, "bad n or num_pairs");
+  cc_status st = check_variant(v, false);
+  if (st != CC_OK) return st;
+  size_t build = 0;
+  st = cc_csr_workspace_bytes(n, num_pairs, &build);
+  if (st != CC_OK) return st;
+  const int64_t mmax = 2 * num_pairs;
+  L->o64 = mmax > 0x7fffffffLL;
+  size_t o = 0;
+  L->off = o, o += align256((size_t)(n + 1) * (L->o64 ? 8 : 4));
+  L->adj = o, o += align256((size_t)(mmax > 0 ? mmax : 1) * 4);
+  L->mdev = o, o += 256;
+  L->rest = o;
+  L->rest_bytes = std::max(build, ws_layout(n, mmax, v).total);
+  L->total = o + L->rest_bytes + 256;  // + alignment of the caller's base
+  return CC_OK;
+}
+
+cc_status cc_coo_workspace_bytes(int64_t n, int64_t num_pairs, const cc_variant* v, size_t* bytes) {
+  if (!bytes) return fail(CC_EINVAL, "bytes is NULL");
+  CooLayout L;
+  cc_status st = coo_layout(n, num_pairs, v, &L);
+  if (st != CC_OK) return st;
+  *bytes = L.total;
+  return CC_OK;
+}
+
+cc_status cc_connectivity_coo(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v,
+                              const cc_variant* var, void* workspace, size_t ws_bytes, int32_t* labels_out,
+                              int64_t* num_components_dev, void* hip_stream) {
+  if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+  CooLayout L;
+  cc_status st = coo_layout(n, num_pairs, var, &L);
+  if (st != CC_OK) return st;
+  if (!workspace || ws_bytes < L.total)
+    return fail(CC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, L.total);
+  if (num_pairs > 0 && (!u || !v)) return fail(CC_EINVAL, "null pair arrays");
+  char* w = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+  hipStream_t s = (hipStream_t)hip_stream;
+  st = cc_build_csr(ctx, n, num_pairs, u, v, 1, w + L.rest, L.rest_bytes, w + L.off, L.o64, (int32_t*)(w + L.adj),
+                    (int64_t*)(w + L.mdev), hip_stream);
+  if (st != CC_OK) return st;
+  int64_t m = 0;
+  CC_HIP(hipMemcpyAsync(&m, w + L.mdev, sizeof(m), hipMemcpyDeviceToHost, s));
+  CC_HIP(hipStreamSynchronize(s));
+  return cc_connectivity_csr(ctx, n, m, w + L.off, L.o64, (const int32_t*)(w + L.adj), var, w + L.rest,
+                             L.rest_bytes, labels_out, num_components_dev, hip_stream);
 }
 
 const char* cc_status_string(cc_status st) {

@@ -9,9 +9,11 @@ Corpus: synthetic graphs whose family and size follow from a seed -- ER
 b = c, edge factor 8), percolated 2D grids (p in [0.45, 1]) and 3D grids
 (p in [0.2, 1]), stars, chains in random id order, and disjoint unions of
 2-8 of these; n log-uniform in [2^lo, 2^hi].  Graphs with seed % 10 == 0
-are held out.  Each graph records its 16 features and the time of every
-arm (median of up to 3 runs; arms that reach the round limit are censored
-at their elapsed time).  Targets are log(t_arm) - log(min_arm t).
+are held out.  Each graph records its 16 features (degree statistics,
+sampled first-neighbour statistics, a budgeted BFS probe; computed on the
+device) and the time of every arm (median of up to 3 runs; arms that reach
+the round limit are censored at their elapsed time).  Targets are
+log(t_arm) - log(min_arm t).
 """
 from __future__ import annotations
 
@@ -122,7 +124,7 @@ def time_arm(ctx, csr, v, labels, ncomp, reps=3, slow_ms=20.0):
 def measure(ctx, g, arm_list, reps=3):
     dev = ctx.torch_device
     csr = b.build_csr(ctx, g.n, g.u, g.v, dedup=True)
-    feats, _ = b.graph_features(ctx, csr)
+    feats = b.graph_features(ctx, csr)
     labels = torch.empty(csr.n, dtype=torch.int32, device=dev)
     ncomp = torch.empty(1, dtype=torch.int64, device=dev)
     times, cens = [], []
@@ -236,9 +238,9 @@ def evaluate(ctx, params, norm, seeds, lo=12, hi=22, reps=3, log=None):
     default and the decision-tree rules; labels of the selector are checked
     against the default's."""
     arm_list = arms()
-    K = len(arm_list)
     dev = ctx.torch_device
     rows = []
+    sel = b.Selector(ctx, params, arm_list, norm)
     ctx.set_round_limit(2000)
     for i, s in enumerate(seeds):
         fam, g = corpus_graph(s, lo, hi)
@@ -246,12 +248,12 @@ def evaluate(ctx, params, norm, seeds, lo=12, hi=22, reps=3, log=None):
         best = int(np.argmin(times))
         labels = torch.empty(csr.n, dtype=torch.int32, device=dev)
         ncomp = torch.empty(1, dtype=torch.int64, device=dev)
-        # end-to-end selector time (median of reps)
+        # end-to-end selector time (median of reps): features, model and arm
         ts, chosen = [], -1
         for _ in range(reps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            lab, nc, chosen, _ = b.connectivity_auto(ctx, csr, params, arm_list, norm, labels=labels, ncomp=ncomp)
+            chosen = sel.connectivity(csr, labels, ncomp)
             e1.record()
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1))

@@ -97,3 +97,19 @@ def test_size_errors():
     assert L.cc_workspace_bytes(10, -1, ctypes.byref(v), ctypes.byref(sz)) == b.CC_EINVAL
     assert L.cc_csr_workspace_bytes(10, 1 << 32, ctypes.byref(sz)) == b.CC_EINVAL
     assert L.cc_status_string(b.CC_ELIVELOCK) == b"CC_ELIVELOCK"
+
+
+def test_pair_list_workspace_sizing():
+    v = b.default_variant()
+    sz = ctypes.c_size_t()
+    L = b.lib()
+    assert L.cc_coo_workspace_bytes(1000, 5000, ctypes.byref(v), ctypes.byref(sz)) == b.CC_OK
+    small = sz.value
+    # at least the CSR (offsets + 2 * pairs adjacency) and the static workspace
+    assert small >= 1001 * 4 + 10000 * 4 + b.workspace_bytes(1000, 10000, v)
+    assert L.cc_coo_workspace_bytes(1000, 50000, ctypes.byref(v), ctypes.byref(sz)) == b.CC_OK
+    assert sz.value > small
+    assert L.cc_coo_workspace_bytes(0, 10, ctypes.byref(v), ctypes.byref(sz)) == b.CC_EINVAL
+    assert L.cc_coo_workspace_bytes(10, -1, ctypes.byref(v), ctypes.byref(sz)) == b.CC_EINVAL
+    bad = v.copy(find=b.FIND_COMPRESS)
+    assert L.cc_coo_workspace_bytes(10, 10, ctypes.byref(bad), ctypes.byref(sz)) == b.CC_EINVAL

@@ -1,0 +1,68 @@
+"""Full-size workloads, built and launched the way bench.py times them:
+R-MAT 2^24 (deduplicated int32 CSR), the 256^3 bond-percolated grid, and
+R-MAT 2^27 with int64 offsets.  Labels and component counts are compared
+element by element with the oracle's sequential union-find over the same
+pair list."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2008_03909_amd import binding as b
+from paper_2008_03909_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = b.Context(0)
+    yield c
+    c.close()
+
+
+def _note(msg):
+    print(f"[fullsize] {msg}", file=sys.stderr, flush=True)
+
+
+def _check(ctx, g, variants, dedup=True, o64=False):
+    want, wc = oracle.uf_cc(g.n, g.u, g.v)
+    dev = ctx.torch_device
+    d = b.build_csr(ctx, g.n, torch.from_numpy(g.u).to(dev), torch.from_numpy(g.v).to(dev), dedup=dedup,
+                    offsets_64bit=o64)
+    labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ncomp = torch.empty(1, dtype=torch.int64, device=dev)
+    for v in variants:
+        _note(f"{g} {v.name()}")
+        b.connectivity_csr(ctx, d, v, labels=labels, ncomp=ncomp)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        assert int(ncomp.item()) == wc, v.name()
+        assert np.array_equal(labels.cpu().numpy(), want), v.name()
+    return d
+
+
+def _spread():
+    vs = b.all_variants()
+    return [b.default_variant()] + [vs[i] for i in (0, 13, 24, 39, 44, 58, 66, 79)]
+
+
+def test_rmat_2_24(ctx):
+    g = inputs.workload_rmat(24, 8, seed=2)
+    d = _check(ctx, g, _spread())
+    assert d.m == 263_432_958
+
+
+def test_grid_256_cubed(ctx):
+    g = inputs.workload_grid3d(256, 0.35, seed=3)
+    _check(ctx, g, _spread())
+
+
+@pytest.mark.slow
+def test_rmat_2_27_int64_offsets(ctx):
+    g = inputs.workload_rmat(27, 8, seed=4)
+    vs = b.all_variants()
+    d = _check(ctx, g, [b.default_variant(), vs[44], vs[79]], o64=True)
+    assert d.offsets.dtype == torch.int64

@@ -104,6 +104,20 @@ def test_default_variant_er_workload(ctx):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("vi", [0, 4, 9, 23, 41, 63, 79])
+def test_pair_list_entry_matches_oracle(ctx, vi):
+    """cc_connectivity_coo (CSR built inside the workspace) on the suite,
+    including an empty pair list, self-loops and duplicates."""
+    v = b.all_variants()[vi]
+    for g in SUITE + [inputs.workload_er_2_16(), inputs.Graph(9, np.zeros(0, np.int32), np.zeros(0, np.int32))]:
+        want, wc = oracle.labels(g)
+        lab, nc = b.connectivity_coo(ctx, g.n, g.u, g.v, v)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        assert int(nc.item()) == wc, (v, g)
+        assert np.array_equal(lab.cpu().numpy(), want), (v, g)
+
+
 @pytest.mark.parametrize("vi", range(80))
 def test_every_variant_on_the_suite(ctx, vi):
     v = b.all_variants()[vi]

@@ -317,3 +317,67 @@ def test_incremental_matches_closure_on_every_prefix():
         if prev is not None:       # answers are monotone: once connected, always
             assert np.all(cl[prev[0]] == cl[prev[1]])
         prev = (a[got == 1], b[got == 1])
+
+
+# ---- selector features from their definitions -----------------------------------
+
+def test_bfs_budget_on_a_path_closed_form():
+    """Path 0-1-...-(n-1) from 0: expanding k levels scans 1 + 2(k-1)
+    entries (the source has one neighbour, inner vertices two), so a budget
+    of 6 allows 3 levels and 4 vertices; without limits the search expands
+    eccentricity + 1 = n levels."""
+    g = inputs.path(50)
+    off, adj = oracle.csr_build(g.n, g.u, g.v)
+    assert oracle.bfs_budget(50, off, adj, 0, 8, 6) == (4, 3)
+    assert oracle.bfs_budget(50, off, adj, 0, 8, 10**9) == (9, 8)
+    assert oracle.bfs_budget(50, off, adj, 0, 1000, 10**9) == (50, 50)
+    assert oracle.bfs_budget(50, off, adj, 25, 3, 10**9) == (7, 3)
+
+
+def test_bfs_budget_star_and_isolated():
+    g = inputs.star(101, 0)           # centre 0, leaves 1..100
+    off, adj = oracle.csr_build(g.n, g.u, g.v)
+    assert oracle.bfs_budget(101, off, adj, 7, 8, 50) == (2, 1)     # the centre's row exceeds the budget
+    # centre row fits: leaf -> centre -> all leaves -> leaves scan back (nothing new)
+    assert oracle.bfs_budget(101, off, adj, 7, 8, 1 + 100 + 99) == (101, 3)
+    e = inputs.empty(5)
+    off, adj = oracle.csr_build(e.n, e.u, e.v)
+    assert oracle.bfs_budget(5, off, adj, 3, 8, 4096) == (1, 1)
+
+
+def test_bfs_budget_without_limits_agrees_with_plain_bfs():
+    """Two separate searches: with no budget and a large cap, reached is the
+    size of the source's component and levels its eccentricity + 1."""
+    for seed in range(5):
+        g = inputs.er(400, 300 + 60 * seed, seed=seed)
+        off, adj = oracle.csr_build(g.n, g.u, g.v)
+        lab, _ = oracle.bfs_cc(g.n, off, adj)
+        for src in (0, 17, 399):
+            r, lv = oracle.bfs_budget(g.n, off, adj, src, 10**6, 10**12)
+            r2, lv2 = oracle.bfs_levels(g.n, off, adj, src, 0)
+            assert r == int(np.sum(lab == lab[src])) == r2
+            assert lv == lv2
+
+
+def test_sampled_features_closed_forms():
+    # path: every first neighbour is at distance 1 -> locality 1/log2(n+1);
+    # the first neighbour is smaller for every v but 0
+    n = 5000
+    g = inputs.path(n)
+    off, adj = oracle.csr_build(g.n, g.u, g.v)
+    f = oracle.sampled_features(n, off, adj, 0x5eed)
+    assert abs(f[10] - 1.0 / np.log2(n + 1)) < 1e-12
+    key = oracle.splitmix_out(0x5eed, oracle.FEATURE_TAG)
+    zeros = sum(oracle.splitmix_out(key, i) % n == 0 for i in range(oracle.FEATURE_SAMPLES))
+    assert abs(f[9] - (1 - zeros / oracle.FEATURE_SAMPLES)) < 1e-12
+    # complete graph: every first neighbour has degree n-1
+    k = inputs.clique(40)
+    off, adj = oracle.csr_build(k.n, k.u, k.v)
+    f = oracle.sampled_features(40, off, adj, 3)
+    assert abs(f[11] - np.log2(40)) < 1e-12
+    assert f[12] == 2 and f[13] == 1.0          # 39 + 39*39 entries fit 4096: 2 levels reach everything
+    # no edges: the sampled means are 0, the probe expands its isolated source
+    e = inputs.empty(100)
+    off, adj = oracle.csr_build(e.n, e.u, e.v)
+    f = oracle.sampled_features(100, off, adj, 1)
+    assert (f[9], f[10], f[11], f[12], f[13]) == (0.0, 0.0, 0.0, 1.0, 0.01)
