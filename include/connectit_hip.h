@@ -292,7 +292,7 @@ cc_status cc_mlp_pack_bf16(const float* src, uint16_t* dst, int64_t count, void*
  * 1 and <= 2, skewness, [m/n < 3], log2(max degree + 1)); statistics of
  * 4096 seeded vertex draws (fraction whose first neighbour id is smaller,
  * mean log-distance to it, mean log-degree of it); and a BFS from a seeded
- * source that expands whole levels within 8 levels and 4096 scanned
+ * source that expands whole levels within 4 levels and 1024 scanned
  * adjacency entries (levels expanded, fraction of vertices reached).  The
  * exact definitions are in the selector source.  workspace as for
  * cc_connectivity_csr with the default variant.  Synchronises hip_stream. */

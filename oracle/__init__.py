@@ -218,8 +218,8 @@ def bfs_budget(n: int, offsets, adj, source: int, cap: int, edge_budget: int):
 
 FEATURE_TAG = 0x66656174       # "feat": stream of the selector's draws
 FEATURE_SAMPLES = 4096
-PROBE_LEVELS = 8
-PROBE_EDGES = 4096
+PROBE_LEVELS = 4
+PROBE_EDGES = 1024
 
 
 def sampled_features(n: int, offsets, adj, seed: int):
@@ -228,7 +228,7 @@ def sampled_features(n: int, offsets, adj, seed: int):
     splitmix(seed, "feat"); over the drawn vertices that have an edge, with
     f = the first entry of v's row: 9 = mean [f < v], 10 = mean
     log2(1 + |v - f|) / log2(n + 1), 11 = mean log2(1 + deg f); then a
-    whole-level BFS from splitmix(key, 4096) mod n within 8 levels and 4096
+    whole-level BFS from splitmix(key, 4096) mod n within 4 levels and 1024
     scanned entries: 12 = levels, 13 = reached / n."""
     off = np.asarray(offsets, np.int64)
     a = np.asarray(adj)

@@ -183,7 +183,15 @@ def _check(status: int, where: str):
 
 
 def _ptr(t: torch.Tensor | None):
-    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+    """Device address of a tensor (NULL for None).  Host tensors are refused:
+    the library dereferences these addresses in kernels."""
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _stream_handle(stream=None):
@@ -387,13 +395,27 @@ class Stream:
         _check(lib().cc_stream_init_csr(self.h, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(ws), ws.numel(),
                                         _stream_handle(stream)), "cc_stream_init_csr")
 
-    def insert(self, u: torch.Tensor, v: torch.Tensor, stream=None):
+    def insert(self, u, v, stream=None):
+        """Insert(u[i], v[i]); host arrays are copied to the device first."""
+        dev = self.ctx.torch_device
+        u = _dev_tensor(u, torch.int32, dev)
+        v = _dev_tensor(v, torch.int32, dev)
+        if u.numel() != v.numel():
+            raise ValueError("u and v differ in length")
         _check(lib().cc_insert_batch(self.h, int(u.numel()), _ptr(u), _ptr(v), _stream_handle(stream)),
                "cc_insert_batch")
 
-    def query(self, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    def query(self, a, b, out: torch.Tensor | None = None, stream=None):
+        """IsConnected(a[i], b[i]) as a device uint8 tensor."""
+        dev = self.ctx.torch_device
+        a = _dev_tensor(a, torch.int32, dev)
+        b = _dev_tensor(b, torch.int32, dev)
+        if a.numel() != b.numel():
+            raise ValueError("a and b differ in length")
         if out is None:
-            out = torch.empty(int(a.numel()), dtype=torch.uint8, device=a.device)
+            out = torch.empty(int(a.numel()), dtype=torch.uint8, device=dev)
+        elif out.dtype != torch.uint8 or out.numel() < a.numel():
+            raise ValueError("out must be a uint8 tensor with one byte per pair")
         _check(lib().cc_query_batch(self.h, int(a.numel()), _ptr(a), _ptr(b), _ptr(out), _stream_handle(stream)),
                "cc_query_batch")
         return out

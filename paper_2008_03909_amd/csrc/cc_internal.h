@@ -24,10 +24,14 @@ struct DevScalars {
   long long lmax_size;
   uint32_t qcount[2];      // frontier queue lengths (ping-pong)
   long long frontier_edges;    // degree sum of the next frontier
-  long long reached;       // vertices reached by the current BFS
+  uint32_t bfs_mode;       // BFS level direction: 0 top-down, 1 bottom-up, 2 finished
+  int32_t bfs_level;       // BFS levels expanded
+  long long reached;       // vertices reached by the current BFS (follows bfs_mode/bfs_level: read together)
+  long long seen_edges;    // BFS: degree sum of every frontier so far
+  unsigned long long heavy_count;  // vertices with degree above the frontier threshold
   uint32_t flag2;          // spare flag for sub-rounds (full shortcut)
   int32_t hcount;          // heavy frontier vertices deferred to the grid kernel
-  uint32_t pad[14];
+  uint32_t pad[14];        // pad[0]: LDD minimum draw; pad[1]: selector block ticket
 };
 
 enum : uint32_t { kErrBadId = 1u, kErrRoundCap = 2u, kErrBadCsr = 4u };
@@ -43,6 +47,8 @@ struct cc_ctx {
   int device = 0;
   cc::DevScalars* dev = nullptr;     // device copy
   cc::DevScalars* host = nullptr;    // pinned host mirror
+  float* sel_host = nullptr;         // pinned: selector features + choice
+  unsigned char* ring_host = nullptr;  // pinned: BFS progress snapshots (2 x 16 bytes)
   cc_stats last{};
   int round_limit = 0;  // 0: the built-in caps only
   // phase timing

@@ -32,27 +32,303 @@ cc_status pull_scalars(StaticArgs& a) {
 }
 
 // ---- BFS --------------------------------------------------------------------
+//
+// The levels run without host synchronisation: a level is a prologue kernel
+// (one block decides the direction from device counters and resets them;
+// every block clears the next frontier bitmap), one expansion kernel that
+// runs the top-down or the bottom-up step as the prologue decided (or
+// nothing once the search is finished), and, for graphs with vertices above
+// kHeavyFrontier, the degree prefix and grid expansion of heavy frontier
+// rows.  The host enqueues levels in growing batches and, after each batch,
+// a 16-byte snapshot copy into pinned memory; it waits on the previous
+// batch's snapshot while the current batch runs, and stops once a snapshot
+// says the search finished (the levels queued after it do nothing).
+
+enum : uint32_t { kBfsTopDown = 0, kBfsBottomUp = 1, kBfsDone = 2 };
+constexpr int kBfsParts = 2048;        // per-block degree sums of the next frontier
+constexpr int kBfsStepBlocks = 1024;   // fpart[0, 1024): step; [1024, 2048): heavy rows
+constexpr double kBeamerAlpha = 15.0, kBeamerBeta = 18.0;   // direction-switch constants (Beamer et al.)
 
 template <typename I>
 __global__ void k_bfs_start(int32_t s, const I* off, uint32_t* vis, uint32_t* fc, int32_t* q0, DevScalars* sc) {
   vis[s >> 5] |= 1u << (s & 31);
   fc[s >> 5] |= 1u << (s & 31);
   q0[0] = s;
+  const long long d = (long long)off[s + 1] - (long long)off[s];
   sc->qcount[0] = 1;
   sc->qcount[1] = 0;
-  sc->frontier_edges = (long long)off[s + 1] - (long long)off[s];
+  sc->frontier_edges = d;
+  sc->seen_edges = d;
+  sc->bfs_mode = kBfsTopDown;
+  sc->bfs_level = 0;
+  sc->reached = 1;
+  sc->hcount = 0;
 }
 
-// Prepares the next level: clears the next-frontier bitmap and its counter.
-__global__ void k_bfs_level_reset(uint32_t* fn, int64_t words, DevScalars* sc, int nxt) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i == 0) {
-    sc->qcount[nxt] = 0;
-    sc->frontier_edges = 0;
-    sc->hcount = 0;
+__device__ __forceinline__ long long block_sum_ll(long long x, long long* red) {
+  x = wave_sum(x);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = x;
+  __syncthreads();
+  long long s = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) s += red[w];
+  return s;
+}
+
+// Level prologue.  Block 0: degree sum of the frontier just produced (from
+// the per-block partials of the previous level), reached += its size,
+// direction for the coming level, counters of the next frontier reset.
+// Every block: clears the next frontier bitmap.
+__global__ void __launch_bounds__(kFBlock) k_bfs_begin(int64_t words, uint32_t* fn, DevScalars* sc, int cur,
+                                                       const long long* __restrict__ fpart, int64_t n, int64_t m,
+                                                       int level_cap) {
+  __shared__ long long red[kFBlock / kWave];
+  if (blockIdx.x == 0) {
+    long long s = 0;
+    for (int i = threadIdx.x; i < kBfsParts; i += kFBlock) s += fpart[i];
+    s = block_sum_ll(s, red);
+    if (threadIdx.x == 0 && sc->bfs_mode != kBfsDone) {
+      const int64_t nf = sc->qcount[cur];
+      long long mf = sc->frontier_edges;
+      if (sc->bfs_level > 0) {   // the frontier was produced by the previous level
+        mf = s;
+        sc->reached += nf;
+        sc->seen_edges += mf;
+        sc->frontier_edges = mf;
+      }
+      uint32_t mode = sc->bfs_mode;
+      if (nf == 0 || (level_cap > 0 && sc->bfs_level >= level_cap)) {
+        mode = kBfsDone;
+      } else if (mode == kBfsTopDown && (double)mf > (double)(m - sc->seen_edges + mf) / kBeamerAlpha) {
+        mode = kBfsBottomUp;
+      } else if (mode == kBfsBottomUp && (double)nf < (double)n / kBeamerBeta) {
+        mode = kBfsTopDown;
+      }
+      sc->bfs_mode = mode;
+      sc->qcount[cur ^ 1] = 0;
+      sc->hcount = 0;
+      if (mode != kBfsDone) sc->bfs_level += 1;
+    }
   }
-  for (; i < words; i += stride) fn[i] = 0u;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += stride) fn[i] = 0u;
+}
+
+// One BFS level.  Top-down: the wave-balanced expansion of the frontier
+// queue (rows above kHeavyFrontier deferred); claimed vertices are appended
+// to the next queue and marked in the next bitmap.  Bottom-up: each
+// unvisited vertex looks for a neighbour in the current bitmap; lanes map to
+// consecutive vertices, so the 32 bits of a bitmap word belong to one wave,
+// which writes the word itself (no atomics).  Both write the degree sum of
+// the vertices they add to fpart[blockIdx].
+template <typename I>
+__global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __restrict__ off,
+                                                      const int32_t* __restrict__ adj, uint32_t* vis,
+                                                      const uint32_t* __restrict__ fc, uint32_t* fn,
+                                                      const int32_t* __restrict__ qin, const uint32_t* cnt_in,
+                                                      int32_t* qout, uint32_t* cnt_out, int32_t* heavy,
+                                                      int32_t* hcount, const DevScalars* sc,
+                                                      long long* __restrict__ fpart) {
+  constexpr int W = kFBlock / kWave;
+  __shared__ int32_t qbuf[W][kWaveQCap];
+  __shared__ int32_t tpre[W][kWave + 1];
+  __shared__ int64_t tbeg[W][kWave];
+  __shared__ long long red[W];
+  const uint32_t mode = sc->bfs_mode;
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  WaveQ q{qbuf[wv], 0};
+  long long added = 0;
+  if (mode == kBfsTopDown) {
+    const int64_t cnt = *cnt_in;
+    const int64_t tiles = (cnt + kWave - 1) / kWave;
+    const int64_t waves = (int64_t)gridDim.x * W;
+    for (int64_t tile = blockIdx.x * (int64_t)W + wv; tile < tiles; tile += waves) {
+      const int64_t idx = tile * kWave + lane;
+      int32_t u = 0;
+      int64_t b = 0, d = 0;
+      if (idx < cnt) {
+        u = qin[idx];
+        b = (int64_t)off[u];
+        d = (int64_t)off[u + 1] - b;
+      }
+      const bool heavy_row = d > kHeavyFrontier;
+      wave_append(heavy_row, u, heavy, (uint32_t*)hcount);
+      if (heavy_row) d = 0;
+      int32_t inc = (int32_t)d;
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += y;
+      }
+      const int32_t total = __shfl(inc, kWave - 1, kWave);
+      tpre[wv][lane] = inc - (int32_t)d;
+      if (lane == kWave - 1) tpre[wv][kWave] = total;
+      tbeg[wv][lane] = b;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int32_t e0 = 0; e0 < total; e0 += kWave) {
+        const int32_t e = e0 + lane;
+        bool got = false;
+        int32_t w = 0;
+        if (e < total) {
+          int lo = 0, hi = kWave - 1;  // last row whose start <= e
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tpre[wv][mid] <= e) lo = mid;
+            else hi = mid - 1;
+          }
+          w = adj[tbeg[wv][lo] + (e - tpre[wv][lo])];
+          got = bit_claim(vis, w);
+          if (got) {
+            aor(fn + (w >> 5), 1u << (w & 31));
+            added += (long long)off[w + 1] - (long long)off[w];
+          }
+        }
+        wq_push(q, got, w, qout, cnt_out);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  } else if (mode == kBfsBottomUp) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+      const int64_t v = base + threadIdx.x;
+      bool found = false;
+      if (v < n && !bit_get(vis, v)) {
+        const int64_t e = (int64_t)off[v + 1];
+        const int64_t b = (int64_t)off[v];
+        for (int64_t j = b; j < e; ++j)
+          if (bit_get(fc, adj[j])) {
+            found = true;
+            break;
+          }
+        if (found) added += e - b;
+      }
+      // base is a multiple of 256, so lanes 0-31 and 32-63 each cover one
+      // whole bitmap word; its owner lane writes it
+      const uint64_t bits = __ballot(found);
+      if ((lane & 31) == 0 && v < n) {
+        const uint32_t wbits = (uint32_t)(bits >> (lane & 32));
+        if (wbits) {
+          vis[v >> 5] |= wbits;
+          fn[v >> 5] = wbits;
+        }
+      }
+      wq_push(q, found, (int32_t)v, qout, cnt_out);
+    }
+  }
+  wq_flush(q, qout, cnt_out);
+  added = wave_sum(added);
+  if (lane == 0) red[wv] = added;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long s = 0;
+    for (int w = 0; w < W; ++w) s += red[w];
+    fpart[blockIdx.x] = s;
+  }
+}
+
+// Heavy frontier rows (top-down levels only), spread evenly over the grid;
+// degree sums of the added vertices to fpart[kBfsStepBlocks + blockIdx].
+template <typename I>
+__global__ void __launch_bounds__(kFBlock) k_bfs_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount,
+                                                       const long long* __restrict__ hp, const I* __restrict__ off,
+                                                       const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
+                                                       int32_t* qout, uint32_t* cnt_out, const DevScalars* sc,
+                                                       long long* __restrict__ fpart) {
+  __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
+  __shared__ long long red[kFBlock / kWave];
+  WaveQ q{qbuf[threadIdx.x / kWave], 0};
+  const int64_t c = sc->bfs_mode == kBfsTopDown ? (int64_t)*hcount : 0;
+  long long added = 0;
+  if (c > 0) {
+    const long long T = hp[c];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
+      const long long e = base + threadIdx.x;
+      const long long e0 = base + (threadIdx.x / kWave) * kWave;
+      bool got = false;
+      int32_t w = 0;
+      if (e < T) {
+        const int64_t i = heavy_owner_tile(hp, c, e0, e);
+        const int32_t u = heavy[i];
+        w = adj[(int64_t)off[u] + (e - hp[i])];
+        got = bit_claim(vis, w);
+        if (got) {
+          aor(fn + (w >> 5), 1u << (w & 31));
+          added += (long long)off[w + 1] - (long long)off[w];
+        }
+      }
+      wq_push(q, got, w, qout, cnt_out);
+    }
+    wq_flush(q, qout, cnt_out);
+  }
+  added = wave_sum(added);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = added;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long s = 0;
+    for (int w = 0; w < kFBlock / kWave; ++w) s += red[w];
+    fpart[kBfsStepBlocks + blockIdx.x] = s;
+  }
+}
+
+// One-block exclusive degree prefix of a device-counted list (any length;
+// meant for short lists): hp[i] for i < c, hp[c] = total.
+template <typename I>
+__global__ void __launch_bounds__(kHpTile) k_hp_single(const int32_t* __restrict__ list, const int32_t* count_ptr,
+                                                       const I* __restrict__ off, long long* __restrict__ hp) {
+  const int64_t c = *count_ptr;
+  long long carry = 0;
+  for (int64_t base = 0; base < c; base += kHpTile) {
+    const int64_t i = base + threadIdx.x;
+    long long total;
+    const long long ex = block_excl_scan_ll(list_deg(list, i, c, off), &total);
+    if (i < c) hp[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) hp[c] = carry;
+}
+
+template <typename I>
+__global__ void __launch_bounds__(kFBlock) k_count_heavy(int64_t n, const I* __restrict__ off,
+                                                         unsigned long long* out) {
+  __shared__ long long red[kFBlock / kWave];
+  long long c = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride)
+    c += ((int64_t)off[v + 1] - (int64_t)off[v]) > kHeavyFrontier;
+  c = block_sum_ll(c, red);
+  if (threadIdx.x == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+__global__ void k_zero_u64_one(unsigned long long* p) { *p = 0ull; }
+
+template <typename I>
+cc_status count_heavy(StaticArgs& a) {
+  if (a.heavy_vertices >= 0) return CC_OK;
+  unsigned long long* d = &a.ctx->dev->heavy_count;
+  hipLaunchKernelGGL(k_zero_u64_one, dim3(1), dim3(1), 0, a.s, d);
+  hipLaunchKernelGGL(k_count_heavy<I>, dim3(grid_for(a.n, kFBlock, 256)), dim3(kFBlock), 0, a.s, a.n,
+                     (const I*)a.off, d);
+  CC_LAUNCH_CHECK();
+  unsigned long long h = 0;
+  CC_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, a.s));
+  CC_HIP(hipStreamSynchronize(a.s));
+  a.heavy_vertices = (int64_t)h;
+  return CC_OK;
+}
+
+constexpr int64_t kHpSingleMax = 65536;   // heavy lists up to this length use the one-block prefix
+
+template <typename I>
+void list_prefix(StaticArgs& a, const int32_t* list, const int32_t* count_ptr) {
+  if (a.heavy_vertices >= 0 && a.heavy_vertices <= kHpSingleMax)
+    hipLaunchKernelGGL(k_hp_single<I>, dim3(1), dim3(kHpTile), 0, a.s, list, count_ptr, (const I*)a.off, a.hp);
+  else
+    heavy_prefix<I>(a.s, list, count_ptr, a.hcap, (const I*)a.off, a.tsum, a.hp);
 }
 
 // Frontier expansion (BFS top-down step, LDD cluster growth), load-balanced
@@ -131,36 +407,6 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
   wq_flush(q, qout, cnt_out);
 }
 
-// Bottom-up step: every unvisited vertex looks for a neighbour in the
-// current frontier bitmap and stops at the first one.
-template <typename I>
-__global__ void __launch_bounds__(kFBlock) k_bfs_bu(int64_t n, const I* __restrict__ off,
-                                                    const int32_t* __restrict__ adj, uint32_t* vis,
-                                                    const uint32_t* __restrict__ fc, uint32_t* fn, int32_t* qout,
-                                                    uint32_t* cnt_out) {
-  __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
-  WaveQ q{qbuf[threadIdx.x / kWave], 0};
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
-    const int64_t v = base + threadIdx.x;
-    bool found = false;
-    if (v < n && !bit_get(vis, v)) {
-      const int64_t e = (int64_t)off[v + 1];
-      for (int64_t j = (int64_t)off[v]; j < e; ++j)
-        if (bit_get(fc, adj[j])) {
-          found = true;
-          break;
-        }
-    }
-    if (found) {
-      aor(vis + (v >> 5), 1u << (v & 31));
-      aor(fn + (v >> 5), 1u << (v & 31));
-    }
-    wq_push(q, found, (int32_t)v, qout, cnt_out);
-  }
-  wq_flush(q, qout, cnt_out);
-}
-
 // Rows of heavy frontier vertices, spread evenly over the whole grid.
 template <bool LDD, typename I>
 __global__ void __launch_bounds__(kFBlock) k_expand_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount,
@@ -199,22 +445,11 @@ __global__ void k_round_reset(DevScalars* sc, int nxt) {
   sc->hcount = 0;
 }
 
-template <typename I>
-__global__ void k_sum_degrees(const int32_t* __restrict__ q, const uint32_t* cnt, const I* __restrict__ off,
-                              DevScalars* sc) {
-  const int64_t c = *cnt;
-  long long s = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c; i += stride) {
-    const int32_t u = q[i];
-    s += (long long)off[u + 1] - (long long)off[u];
-  }
-  s = wave_sum(s);
-  if (lane_id() == 0 && s) add64(&sc->frontier_edges, s);
-}
-
-// Minimum reached vertex = lowest set bit of the visited bitmap.
-__global__ void k_bitmap_min(const uint32_t* __restrict__ vis, int64_t words, DevScalars* sc) {
+// Minimum reached vertex = lowest set bit of the visited bitmap (one atomic
+// per block; the grid is kept small).
+__global__ void __launch_bounds__(kFBlock) k_bitmap_min(const uint32_t* __restrict__ vis, int64_t words,
+                                                        DevScalars* sc) {
+  __shared__ int32_t red[kFBlock / kWave];
   int32_t best = 0x7fffffff;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += stride) {
@@ -228,7 +463,12 @@ __global__ void k_bitmap_min(const uint32_t* __restrict__ vis, int64_t words, De
     const int32_t y = __shfl_xor(best, o, kWave);
     best = y < best ? y : best;
   }
-  if (lane_id() == 0 && best != 0x7fffffff) atomicMin(&sc->bfs_min, best);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kFBlock / kWave; ++w) best = red[w] < best ? red[w] : best;
+    if (best != 0x7fffffff) atomicMin(&sc->bfs_min, best);
+  }
 }
 
 __global__ void k_label_reached(int64_t n, const uint32_t* __restrict__ vis, const DevScalars* sc, int32_t* P) {
@@ -238,7 +478,7 @@ __global__ void k_label_reached(int64_t n, const uint32_t* __restrict__ vis, con
     if (bit_get(vis, v)) P[v] = mn;
 }
 
-// One direction-optimizing BFS from `source` into the visited bitmap.
+// One BFS from `source` (every level device-driven, see above).
 template <typename I>
 cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reached_out, int32_t* levels_out) {
   const int64_t n = a.n, m = a.m;
@@ -248,59 +488,89 @@ cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reach
   uint32_t* fa = (uint32_t*)(a.ws + a.L.bits + bw);
   uint32_t* fb = (uint32_t*)(a.ws + a.L.bits + 2 * bw);
   int32_t* q[2] = {(int32_t*)(a.ws + a.L.queue), (int32_t*)(a.ws + a.L.queue + align256((size_t)n * 4))};
+  long long* fpart = (long long*)(a.ws + a.L.hist);   // kBfsParts entries (the LDD histogram area)
   const I* off = (const I*)a.off;
   DevScalars* sc = a.ctx->dev;
-  const double alpha = 15.0, beta = 18.0;  // Beamer's direction-switch constants
+  cc_status st = count_heavy<I>(a);
+  if (st != CC_OK) return st;
+  const bool heavy = a.heavy_vertices > 0;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(3 * bw / 4, kFBlock, 4096)), dim3(kFBlock), 0, a.s, vis,
                      (int64_t)(3 * bw / 4), 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(kFBlock), 0, a.s, (uint32_t*)fpart, (int64_t)kBfsParts * 2, 0u);
   hipLaunchKernelGGL(k_bfs_start<I>, dim3(1), dim3(1), 0, a.s, source, off, vis, fa, q[0], sc);
   CC_LAUNCH_CHECK();
-  cc_status st = pull_scalars(a);
-  if (st != CC_OK) return st;
-  int64_t nf = 1, mf = a.ctx->host->frontier_edges, seen_edges = mf, reached = 1;
-  bool top_down = true;
-  int cur = 0;
-  int32_t levels = 0;
+  const unsigned gb = grid_for(words, kFBlock, 1024);
+  const unsigned gs = grid_for(n, kFBlock, kBfsStepBlocks);
+  const unsigned gh = kBfsParts - kBfsStepBlocks;
   uint32_t* fc = fa;
   uint32_t* fn = fb;
-  for (int level = 0; nf > 0 && (level_cap <= 0 || level < level_cap); ++level) {
-    if (level > n + 1) return fail(CC_ELIVELOCK, "BFS exceeded n levels");
-    if (a.ctx->round_limit > 0 && level >= a.ctx->round_limit)
-      return fail(CC_ELIVELOCK, "BFS reached the context's round limit (%d)", a.ctx->round_limit);
-    if (top_down && (double)mf > (double)(m - seen_edges + mf) / alpha) top_down = false;
-    else if (!top_down && (double)nf < (double)n / beta) top_down = true;
-    const int nxt = cur ^ 1;
-    hipLaunchKernelGGL(k_bfs_level_reset, dim3(grid_for(words, kFBlock, 4096)), dim3(kFBlock), 0, a.s, fn, words,
-                       sc, nxt);
-    if (top_down) {
-      hipLaunchKernelGGL((k_expand<false, I>), dim3(grid_for(nf * kWave / kWave, kFBlock, 2048)), dim3(kFBlock), 0,
-                         a.s, q[cur], &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, fn,
-                         (int32_t*)nullptr, a.heavy, &sc->hcount);
-      heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&sc->hcount, a.hcap, off, a.tsum, a.hp);
-      hipLaunchKernelGGL((k_expand_heavy<false, I>), dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
-                         (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, fn,
-                         (int32_t*)nullptr, q[nxt], &sc->qcount[nxt]);
-    } else {
-      hipLaunchKernelGGL(k_bfs_bu<I>, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, off, a.adj, vis,
-                         fc, fn, q[nxt], &sc->qcount[nxt]);
+  int cur = 0;
+  int64_t launched = 0;
+  int batch = 2;
+  int slot = 0;
+  bool have_prev = false;
+  hipEvent_t ev[2];
+  CC_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  CC_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct Snap {
+    uint32_t mode;
+    int32_t level;
+    long long reached;
+  };
+  Snap* ring = (Snap*)a.ctx->ring_host;
+  Snap fin{kBfsTopDown, 0, 1};
+  cc_status result = CC_OK;
+  while (true) {
+    for (int j = 0; j < batch; ++j) {
+      hipLaunchKernelGGL(k_bfs_begin, dim3(gb), dim3(kFBlock), 0, a.s, words, fn, sc, cur, (const long long*)fpart, n,
+                         m, level_cap);
+      hipLaunchKernelGGL(k_bfs_step<I>, dim3(gs), dim3(kFBlock), 0, a.s, n, off, a.adj, vis, (const uint32_t*)fc, fn,
+                         (const int32_t*)q[cur], &sc->qcount[cur], q[cur ^ 1], &sc->qcount[cur ^ 1], a.heavy,
+                         &sc->hcount, (const DevScalars*)sc, fpart);
+      if (heavy) {
+        list_prefix<I>(a, a.heavy, (const int32_t*)&sc->hcount);
+        hipLaunchKernelGGL(k_bfs_heavy<I>, dim3(gh), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
+                           (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, fn, q[cur ^ 1],
+                           &sc->qcount[cur ^ 1], (const DevScalars*)sc, fpart);
+      }
+      uint32_t* t2 = fc;
+      fc = fn;
+      fn = t2;
+      cur ^= 1;
+      ++launched;
     }
-    hipLaunchKernelGGL(k_sum_degrees<I>, dim3(grid_for(n, kFBlock, 1024)), dim3(kFBlock), 0, a.s, q[nxt],
-                       &sc->qcount[nxt], off, sc);
     CC_LAUNCH_CHECK();
-    st = pull_scalars(a);
-    if (st != CC_OK) return st;
-    nf = a.ctx->host->qcount[nxt];
-    mf = a.ctx->host->frontier_edges;
-    seen_edges += mf;
-    reached += nf;
-    uint32_t* t2 = fc;
-    fc = fn;
-    fn = t2;
-    cur = nxt;
-    ++levels;
+    CC_HIP(hipMemcpyAsync(&ring[slot], &sc->bfs_mode, sizeof(Snap), hipMemcpyDeviceToHost, a.s));
+    CC_HIP(hipEventRecord(ev[slot], a.s));
+    if (have_prev) {
+      CC_HIP(hipEventSynchronize(ev[slot ^ 1]));
+      const Snap sn = ring[slot ^ 1];
+      if (sn.mode == kBfsDone) {
+        fin = sn;
+        break;
+      }
+      if (a.ctx->round_limit > 0 && sn.level >= a.ctx->round_limit) {
+        result = fail(CC_ELIVELOCK, "BFS reached the context's round limit (%d)", a.ctx->round_limit);
+        break;
+      }
+      // a search expands at most n levels; the host runs at most two
+      // batches (<= 64 levels) ahead of the snapshot it reads
+      if (sn.level > n + 1 || launched > n + 2 + 2 * 32) {
+        result = fail(CC_ELIVELOCK, "BFS exceeded n levels");
+        break;
+      }
+    }
+    have_prev = true;
+    slot ^= 1;
+    batch = batch < 32 ? 2 * batch : 32;
   }
-  *reached_out = reached;
-  *levels_out = levels;
+  // the batch queued after the finishing snapshot does nothing; wait for it
+  CC_HIP(hipStreamSynchronize(a.s));
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  if (result != CC_OK) return result;
+  *reached_out = fin.reached;
+  *levels_out = fin.level;
   return CC_OK;
 }
 
@@ -321,7 +591,7 @@ cc_status sample_bfs(StaticArgs& a) {
     if (st != CC_OK) return st;
     a.sample_rounds += levels;
     if (10 * reached > n) {
-      hipLaunchKernelGGL(k_bitmap_min, dim3(grid_for(words, kFBlock, 1024)), dim3(kFBlock), 0, a.s, vis, words, sc);
+      hipLaunchKernelGGL(k_bitmap_min, dim3(grid_for(words, kFBlock, 256)), dim3(kFBlock), 0, a.s, vis, words, sc);
       hipLaunchKernelGGL(k_label_reached, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n,
                          (const uint32_t*)vis, (const DevScalars*)sc, a.P);
       CC_LAUNCH_CHECK();
@@ -340,8 +610,12 @@ __device__ __forceinline__ float ldd_delta(uint32_t u24, float beta) {
   return -logf(((float)u24 + 0.5f) * (1.0f / 16777216.0f)) / beta;
 }
 
-// Minimum draw (largest shift) and min-member scratch init.
-__global__ void k_ldd_prep(int64_t n, uint64_t key, int32_t* mn, DevScalars* sc) {
+// Minimum draw (largest shift) and min-member scratch init; one atomic per
+// block (the grid is kept small).
+constexpr int kLddGrid = 256;
+
+__global__ void __launch_bounds__(kFBlock) k_ldd_prep(int64_t n, uint64_t key, int32_t* mn, DevScalars* sc) {
+  __shared__ uint32_t red[kFBlock / kWave];
   uint32_t best = 0xffffffffu;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
@@ -353,11 +627,17 @@ __global__ void k_ldd_prep(int64_t n, uint64_t key, int32_t* mn, DevScalars* sc)
     const uint32_t y = __shfl_xor(best, o, kWave);
     best = y < best ? y : best;
   }
-  if (lane_id() == 0) atomicMin(&sc->pad[0], best);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kFBlock / kWave; ++w) best = red[w] < best ? red[w] : best;
+    atomicMin(&sc->pad[0], best);
+  }
 }
 
 constexpr int kLddMaxRounds = 4096;
 
+// Start-round histogram: per-block LDS counts, added once per block.
 __global__ void k_ldd_hist(int64_t n, uint64_t key, float beta, const DevScalars* sc, uint32_t* hist) {
   __shared__ uint32_t h[kLddMaxRounds];
   for (int i = threadIdx.x; i < kLddMaxRounds; i += blockDim.x) h[i] = 0;
@@ -375,29 +655,56 @@ __global__ void k_ldd_hist(int64_t n, uint64_t key, float beta, const DevScalars
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-// Vertices [lo, hi) wake: the unvisited ones become cluster centres.
+// Vertices [lo, hi) wake: the unvisited ones become cluster centres.  Lanes
+// map to consecutive vertices from a 32-aligned start, so each half-wave
+// owns one bitmap word and writes it without atomics.  Block 0 also resets
+// the counters of the round's output queue (queue `nxt`) and the heavy list.
 __global__ void __launch_bounds__(kFBlock) k_ldd_wake(int64_t lo, int64_t hi, uint32_t* vis, int32_t* P, int32_t* q,
-                                                      uint32_t* cnt) {
+                                                      uint32_t* cnt, DevScalars* sc, int nxt) {
   __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
   WaveQ wq{qbuf[threadIdx.x / kWave], 0};
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->qcount[nxt] = 0;
+    sc->hcount = 0;
+  }
+  const int lane = lane_id();
+  const int64_t lo32 = lo & ~(int64_t)31;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = lo + blockIdx.x * (int64_t)blockDim.x; base < hi; base += stride) {
+  for (int64_t base = lo32 + blockIdx.x * (int64_t)blockDim.x; base < hi; base += stride) {
     const int64_t v = base + threadIdx.x;
-    bool got = false;
-    if (v < hi) {
-      got = bit_claim(vis, v);
-      if (got) P[v] = (int32_t)v;
+    const bool got = v >= lo && v < hi && !bit_get(vis, v);
+    if (got) P[v] = (int32_t)v;
+    const uint64_t bits = __ballot(got);
+    if ((lane & 31) == 0) {
+      const uint32_t wbits = (uint32_t)(bits >> (lane & 32));
+      if (wbits) vis[v >> 5] |= wbits;
     }
     wq_push(wq, got, (int32_t)v, q, cnt);
   }
   wq_flush(wq, q, cnt);
 }
 
-__global__ void k_min_member(int64_t n, const int32_t* __restrict__ P, int32_t* mn) {
+// Minimum member of every cluster: runs of equal cluster labels in a wave
+// are peeled and take one atomic each (after a plain read shows it helps).
+__global__ void __launch_bounds__(kFBlock) k_min_member(int64_t n, const int32_t* __restrict__ P, int32_t* mn) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
-    const int32_t c = P[v];
-    if ((int32_t)v < ld(mn + c)) amin(mn + c, (int32_t)v);
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+    const int64_t v = base + threadIdx.x;
+    const bool act = v < n;
+    const int32_t c = act ? P[v] : 0;
+    uint64_t mact = __ballot(act);
+    while (mact) {
+      const int leader = __ffsll((unsigned long long)mact) - 1;
+      const int32_t lead = __shfl(c, leader, kWave);
+      const bool mine = act && c == lead;
+      int32_t x = mine ? (int32_t)v : 0x7fffffff;
+      for (int o = 32; o > 0; o >>= 1) {
+        const int32_t y = __shfl_xor(x, o, kWave);
+        x = y < x ? y : x;
+      }
+      if (lane_id() == leader && x < ld(mn + lead)) amin(mn + lead, x);
+      mact &= ~__ballot(mine);
+    }
   }
 }
 
@@ -419,11 +726,14 @@ cc_status sample_ldd(StaticArgs& a) {
   const uint64_t key = sm_out(a.v->seed, kTagLdd);
   const float beta = a.v->ldd_beta;
 
+  cc_status st = count_heavy<I>(a);
+  if (st != CC_OK) return st;
+  const bool heavy = a.heavy_vertices > 0;
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->pad[0], 0xffffffffu);
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words, kFBlock, 4096)), dim3(kFBlock), 0, a.s, vis, words, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(kFBlock), 0, a.s, hist, (int64_t)kLddMaxRounds, 0u);
-  hipLaunchKernelGGL(k_ldd_prep, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, key, mn, sc);
-  hipLaunchKernelGGL(k_ldd_hist, dim3(grid_for(n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, n, key, beta,
+  hipLaunchKernelGGL(k_ldd_prep, dim3(grid_for(n, kFBlock, kLddGrid)), dim3(kFBlock), 0, a.s, n, key, mn, sc);
+  hipLaunchKernelGGL(k_ldd_hist, dim3(grid_for(n, kFBlock, kLddGrid)), dim3(kFBlock), 0, a.s, n, key, beta,
                      (const DevScalars*)sc, hist);
   CC_LAUNCH_CHECK();
   std::vector<uint32_t> h(kLddMaxRounds);
@@ -432,7 +742,7 @@ cc_status sample_ldd(StaticArgs& a) {
   int last = 0;
   for (int r = 0; r < kLddMaxRounds; ++r)
     if (h[r]) last = r;
-  // reset both queue counters
+  // both queue counters start at zero; each wake resets the other one
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->qcount[0], 0u);
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->qcount[1], 0u);
   int64_t lo = 0, S = 0;
@@ -440,19 +750,19 @@ cc_status sample_ldd(StaticArgs& a) {
   for (int r = 0; r <= last; ++r) {
     S += h[r];
     const int64_t hi = (r == last) ? n : S;
-    if (hi > lo)
-      hipLaunchKernelGGL(k_ldd_wake, dim3(grid_for(hi - lo, kFBlock, 4096)), dim3(kFBlock), 0, a.s, lo, hi, vis, a.P,
-                         q[cur], &sc->qcount[cur]);
-    lo = hi;
     const int nxt = cur ^ 1;
-    hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, a.s, sc, nxt);
+    hipLaunchKernelGGL(k_ldd_wake, dim3(grid_for(hi > lo ? hi - (lo & ~(int64_t)31) : 1, kFBlock, 4096)),
+                       dim3(kFBlock), 0, a.s, lo, hi, vis, a.P, q[cur], &sc->qcount[cur], sc, nxt);
+    lo = hi > lo ? hi : lo;
     hipLaunchKernelGGL((k_expand<true, I>), dim3(grid_for(n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, q[cur],
                        &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, (uint32_t*)nullptr, a.P,
                        a.heavy, &sc->hcount);
-    heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&sc->hcount, a.hcap, off, a.tsum, a.hp);
-    hipLaunchKernelGGL((k_expand_heavy<true, I>), dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
-                       (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, (uint32_t*)nullptr,
-                       a.P, q[nxt], &sc->qcount[nxt]);
+    if (heavy) {
+      list_prefix<I>(a, a.heavy, (const int32_t*)&sc->hcount);
+      hipLaunchKernelGGL((k_expand_heavy<true, I>), dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
+                         (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, (uint32_t*)nullptr,
+                         a.P, q[nxt], &sc->qcount[nxt]);
+    }
     CC_LAUNCH_CHECK();
     cur = nxt;
     ++a.sample_rounds;

@@ -18,7 +18,7 @@
 //   9 mean [f < v]    10 mean log2(1 + |v - f|) / log2(n + 1)
 //   11 mean log2(1 + deg f)
 // and a BFS from a seeded source that expands whole levels while at most
-// 4096 adjacency entries are scanned and at most 8 levels:
+// 1024 adjacency entries are scanned and at most 4 levels:
 //   12 levels expanded     13 vertices reached / n
 //
 // MLP: parameters packed as BF16 [W1 16x64 | b1 64 | W2 64x64 | b2 64 |
@@ -70,32 +70,37 @@ __device__ __forceinline__ MlpView mlp_view(const uint16_t* p, int K) {
   return v;
 }
 
-// One row of the forward pass by a block of kH threads: xin (FP32, kIn
-// values) -> Y (K values).  cache (nullable): [z1 64 | a1 64 | z2 64 | a2 64].
+// One row of the forward pass by a block of at least kH threads (thread t
+// computes hidden unit t): xin (FP32, kIn values) -> Y (K values).  cache
+// (nullable): [z1 64 | a1 64 | z2 64 | a2 64].
 __device__ __forceinline__ void mlp_forward_row(const MlpView& P, int K, const float* xin, float* x, float* a1,
                                                 float* a2, float* Y, float* cache) {
   const int t = threadIdx.x;
   if (t < kIn) x[t] = bf16_round(xin[t]);
   __syncthreads();
-  float z = bf16_to_f32(P.b1[t]);
-  for (int i = 0; i < kIn; ++i) z += x[i] * bf16_to_f32(P.W1[i * kH + t]);
-  const float h1 = bf16_round(z > 0.f ? z : 0.f);
-  a1[t] = h1;
-  if (cache) {
-    cache[t] = z;
-    cache[kH + t] = h1;
+  if (t < kH) {
+    float z = bf16_to_f32(P.b1[t]);
+    for (int i = 0; i < kIn; ++i) z += x[i] * bf16_to_f32(P.W1[i * kH + t]);
+    const float h1 = bf16_round(z > 0.f ? z : 0.f);
+    a1[t] = h1;
+    if (cache) {
+      cache[t] = z;
+      cache[kH + t] = h1;
+    }
   }
   __syncthreads();
-  z = bf16_to_f32(P.b2[t]);
-  for (int i = 0; i < kH; ++i) z += a1[i] * bf16_to_f32(P.W2[i * kH + t]);
-  const float h2 = bf16_round(z > 0.f ? z : 0.f);
-  a2[t] = h2;
-  if (cache) {
-    cache[2 * kH + t] = z;
-    cache[3 * kH + t] = h2;
+  if (t < kH) {
+    float z = bf16_to_f32(P.b2[t]);
+    for (int i = 0; i < kH; ++i) z += a1[i] * bf16_to_f32(P.W2[i * kH + t]);
+    const float h2 = bf16_round(z > 0.f ? z : 0.f);
+    a2[t] = h2;
+    if (cache) {
+      cache[2 * kH + t] = z;
+      cache[3 * kH + t] = h2;
+    }
   }
   __syncthreads();
-  for (int j = t; j < K; j += kH) {
+  for (int j = t; j < K; j += blockDim.x) {
     float y = bf16_to_f32(P.b3[j]);
     for (int i = 0; i < kH; ++i) y += a2[i] * bf16_to_f32(P.W3[i * K + j]);
     Y[j] = y;
@@ -223,45 +228,67 @@ __global__ void k_f32_to_bf16(const float* __restrict__ src, uint16_t* __restric
 }
 
 // ---- feature kernels ----------------------------------------------------------
+//
+// One launch computes everything: blocks [0, nb) sweep the degrees and the
+// vertex draws into per-block partials, block nb runs the budgeted BFS, and
+// the last block to finish (a ticket counter) reduces the partials, forms
+// the 16 features, normalises them, runs the forward pass and picks the
+// arm.  The host then copies 17 words to pinned memory and synchronises once.
 
-constexpr int kFeatBlocks = 512;
+constexpr int kFeatBlocks = 2048;
+constexpr int kFeatThreads = 256;
 constexpr int kFeatSamples = 4096;
-constexpr int kProbeLevels = 8;
-constexpr int kProbeEdges = 4096;
-constexpr int kProbeSlots = 8192;     // LDS hash of discovered vertices: load <= 1/2
+constexpr int kProbeLevels = 4;
+constexpr int kProbeEdges = 1024;
+constexpr int kProbeSlots = 2048;     // LDS hash of discovered vertices: load <= 1/2
+constexpr int kProbeCap = kProbeEdges + 1;   // frontier capacity (a level discovers <= kProbeEdges)
 constexpr int kPart = 12;             // doubles per block of partial sums
 constexpr uint64_t kTagFeat = 0x66656174ULL;  // "feat"
 
-// Selector area of the workspace (64 KB): partials, probe result, feature
-// vector and choice, normalisation, scores.
-constexpr size_t kSelPart = 0;
-constexpr size_t kSelProbe = kSelPart + (size_t)kFeatBlocks * kPart * 8;
+// Selector area of the workspace: probe result and output; the per-block
+// partials (at most n/1024 + 1 blocks of 96 bytes) use the n-int count area.
+constexpr size_t kSelProbe = 0;
 constexpr size_t kSelOut = kSelProbe + 64;     // 16 floats + chosen (int32)
-constexpr size_t kSelNorm = kSelOut + 128;     // 32 floats
-constexpr size_t kSelY = kSelNorm + 128;       // K <= 128 floats
-static_assert(kSelY + kMaxArms * 4 <= 65536, "selector area");
+
+// Dynamic roles share one LDS buffer.
+constexpr size_t kProbeSmem = 2 * (size_t)kProbeCap * 8 + (size_t)kProbeSlots * 4 + 4 * (size_t)kProbeCap * 4 +
+                               (size_t)(kProbeCap + 1) * 4 + 64;
+constexpr size_t kFinishSmem = (size_t)kPart * kFeatThreads * 8 + (3 * kIn + 2 * kH + kMaxArms) * 4 + 16;
+constexpr size_t kFeatSmem = kProbeSmem > kFinishSmem ? kProbeSmem : kFinishSmem;
+
+struct NormArg {
+  float v[2 * kIn];   // mean[16], sd[16]
+};
 
 __device__ __forceinline__ double max_d(double a, double b) { return b > a ? b : a; }
+__device__ __forceinline__ double combine(int k, double a, double b) { return k == 3 ? max_d(a, b) : a + b; }
 
-// Per-block partials: [sum d, sum d^2, sum d^3, max d, #d==0, #d==1, #d<=2,
-// #draws with an edge, #(f < v), sum locality, sum log2(1 + deg f), 0].
+// Partials of one pass block: [sum d, sum d^2, sum d^3, max d, #d==0,
+// #d==1, #d<=2, #draws with an edge, #(f < v), sum locality,
+// sum log2(1 + deg f), 0].
 template <typename I>
-__global__ void __launch_bounds__(256) k_feat_pass(int64_t n, const I* __restrict__ off,
-                                                   const int32_t* __restrict__ adj, uint64_t key,
-                                                   double* __restrict__ part) {
-  __shared__ double red[kPart][256 / kWave];
+__device__ void feat_pass(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ adj, uint64_t key,
+                          int nb, double* __restrict__ part, double* red) {
   double q[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (int64_t v = gid; v < n; v += stride) {
-    const double d = (double)((int64_t)off[v + 1] - (int64_t)off[v]);
-    q[0] += d;
-    q[1] += d * d;
-    q[2] += d * d * d;
-    q[3] = max_d(q[3], d);
-    q[4] += d == 0.0;
-    q[5] += d == 1.0;
-    q[6] += d <= 2.0;
+  const int64_t stride = (int64_t)nb * kFeatThreads;
+  const int64_t gid = blockIdx.x * (int64_t)kFeatThreads + threadIdx.x;
+  // four vertices per lane: five row bounds loaded together
+  for (int64_t v0 = 4 * gid; v0 < n; v0 += 4 * stride) {
+    int64_t o[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) o[j] = v0 + j <= n ? (int64_t)off[v0 + j] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (v0 + j >= n) break;
+      const double d = (double)(o[j + 1] - o[j]);
+      q[0] += d;
+      q[1] += d * d;
+      q[2] += d * d * d;
+      q[3] = max_d(q[3], d);
+      q[4] += d == 0.0;
+      q[5] += d == 1.0;
+      q[6] += d <= 2.0;
+    }
   }
   const double ln = log2((double)n + 1.0);
   for (int64_t i = gid; i < kFeatSamples; i += stride) {
@@ -274,41 +301,61 @@ __global__ void __launch_bounds__(256) k_feat_pass(int64_t n, const I* __restric
     q[9] += log2(1.0 + (double)(v > f ? v - f : f - v)) / ln;
     q[10] += log2(1.0 + (double)((int64_t)off[f + 1] - (int64_t)off[f]));
   }
+  constexpr int kW = kFeatThreads / kWave;
   for (int k = 0; k < kPart; ++k) {
     double x = q[k];
-    for (int o = 32; o > 0; o >>= 1) {
-      const double y = __shfl_xor(x, o, kWave);
-      x = (k == 3) ? max_d(x, y) : x + y;
-    }
-    if (lane_id() == 0) red[k][threadIdx.x / kWave] = x;
+    for (int o = 32; o > 0; o >>= 1) x = combine(k, x, __shfl_xor(x, o, kWave));
+    if (lane_id() == 0) red[k * kW + threadIdx.x / kWave] = x;
   }
   __syncthreads();
   if (threadIdx.x < kPart) {
     const int k = threadIdx.x;
-    double x = red[k][0];
-    for (int w = 1; w < 256 / kWave; ++w) x = (k == 3) ? max_d(x, red[k][w]) : x + red[k][w];
+    double x = red[k * kW];
+    for (int w = 1; w < kW; ++w) x = combine(k, x, red[k * kW + w]);
     part[(int64_t)blockIdx.x * kPart + k] = x;
   }
 }
 
-// Whole-level BFS within an edge budget, in one block.  Discovered vertices
-// live in an LDS hash table; the two frontier queues (capacity n each) are
-// in the workspace.  Before a level is expanded the block sums its
-// frontier's degrees and stops if the budget would be exceeded, so which
-// vertices are reached does not depend on scheduling.  out: [levels, reached].
-constexpr int kProbeThreads = 256;
+// Whole-level BFS within an edge budget, entirely in LDS: a hash table of
+// discovered vertices and two frontier queues holding each vertex's row
+// start and degree (loaded once, when the vertex is discovered).  Before a
+// level is expanded its frontier's degrees are summed and the search stops
+// if the budget would be exceeded, so which vertices are reached does not
+// depend on scheduling.  out: [levels, reached].
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T* wtot, T* total) {
+  constexpr int kW = kFeatThreads / kWave;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  T inc = x;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const T y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) wtot[w] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+  for (int i = 0; i < kW; ++i) {
+    if (i < w) before += wtot[i];
+    all += wtot[i];
+  }
+  if (threadIdx.x == 0) *total = all;
+  __syncthreads();
+  return before + inc - x;
+}
+
 template <typename I>
-__global__ void __launch_bounds__(kProbeThreads) k_feat_probe(const I* __restrict__ off,
-                                                              const int32_t* __restrict__ adj, int32_t src,
-                                                              int32_t* __restrict__ qa, int32_t* __restrict__ qb,
-                                                              int64_t* __restrict__ out) {
-  __shared__ int32_t slots[kProbeSlots];
-  __shared__ int32_t pre[kProbeEdges + 2];   // frontier degree prefix (frontier <= kProbeEdges + 1)
-  __shared__ long long tsum[kProbeThreads];
-  __shared__ long long total;
-  __shared__ int32_t nnext;
+__device__ void feat_probe(const I* __restrict__ off, const int32_t* __restrict__ adj, int32_t src,
+                           int64_t* __restrict__ out, unsigned char* smem) {
+  int64_t* qst = (int64_t*)smem;                           // [2][kProbeCap] row starts
+  int32_t* slots = (int32_t*)(qst + 2 * kProbeCap);        // hash of discovered vertices
+  int32_t* qid = slots + kProbeSlots;                      // [2][kProbeCap] vertex ids
+  int32_t* qdg = qid + 2 * kProbeCap;                      // [2][kProbeCap] degrees (clamped)
+  int32_t* pre = qdg + 2 * kProbeCap;                      // [kProbeCap + 1] frontier degree prefix
+  long long* wtot = (long long*)(((uintptr_t)(pre + kProbeCap + 1) + 7) & ~(uintptr_t)7);
+  long long* total = wtot + kFeatThreads / kWave;
+  int32_t* nnext = (int32_t*)(total + 1);
   const int t = threadIdx.x;
-  for (int i = t; i < kProbeSlots; i += kProbeThreads) slots[i] = -1;
+  for (int i = t; i < kProbeSlots; i += kFeatThreads) slots[i] = -1;
   __syncthreads();
   auto insert = [&](int32_t w) -> bool {
     uint32_t h = ((uint32_t)w * 2654435761u) & (kProbeSlots - 1);
@@ -319,67 +366,60 @@ __global__ void __launch_bounds__(kProbeThreads) k_feat_probe(const I* __restric
       h = (h + 1) & (kProbeSlots - 1);
     }
   };
+  auto push = [&](int q, int32_t pos, int32_t w) {
+    const int64_t b = (int64_t)off[w], d = (int64_t)off[w + 1] - b;
+    qid[q * kProbeCap + pos] = w;
+    qst[q * kProbeCap + pos] = b;
+    qdg[q * kProbeCap + pos] = (int32_t)(d < kProbeEdges + 1 ? d : kProbeEdges + 1);
+  };
   if (t == 0) {
     insert(src);
-    qa[0] = src;
+    push(0, 0, src);
   }
-  int32_t* cur = qa;
-  int32_t* nxt = qb;
-  int64_t f = 1, reached = 1, scanned = 0;
+  int cur = 0;
+  int32_t f = 1;
+  int64_t reached = 1, scanned = 0;
   int levels = 0;
   __syncthreads();
   while (f > 0 && levels < kProbeLevels) {
-    // frontier degrees: each thread sums a contiguous chunk, the chunk sums
-    // are scanned, and (only if the level fits the budget) each thread
-    // writes the int32 prefix of its chunk
-    const int64_t chunk = (f + kProbeThreads - 1) / kProbeThreads;
-    const int64_t i0 = t * chunk < f ? t * chunk : f;
-    const int64_t i1 = i0 + chunk < f ? i0 + chunk : f;
-    long long s = 0;
-    for (int64_t i = i0; i < i1; ++i) s += (long long)((int64_t)off[cur[i] + 1] - (int64_t)off[cur[i]]);
-    tsum[t] = s;
-    __syncthreads();
-    if (t == 0) {
-      long long acc = 0;
-      for (int i = 0; i < kProbeThreads; ++i) {
-        const long long x = tsum[i];
-        tsum[i] = acc;
-        acc += x;
-      }
-      total = acc;
-      nnext = 0;
-    }
-    __syncthreads();
-    const long long fe = total;
+    // contiguous chunk of the frontier per thread; scan of the chunk sums
+    const int32_t chunk = (f + kFeatThreads - 1) / kFeatThreads;
+    const int32_t i0 = t * chunk < f ? t * chunk : f;
+    const int32_t i1 = i0 + chunk < f ? i0 + chunk : f;
+    long long sum = 0;
+    for (int32_t i = i0; i < i1; ++i) sum += qdg[cur * kProbeCap + i];
+    const long long before = block_excl_scan<long long>(sum, wtot, total);
+    const long long fe = *total;
     if (scanned + fe > kProbeEdges) break;
     {
-      int32_t acc = (int32_t)tsum[t];
-      for (int64_t i = i0; i < i1; ++i) {
+      int32_t acc = (int32_t)before;
+      for (int32_t i = i0; i < i1; ++i) {
         pre[i] = acc;
-        acc += (int32_t)((int64_t)off[cur[i] + 1] - (int64_t)off[cur[i]]);
+        acc += qdg[cur * kProbeCap + i];
       }
-      if (t == 0) pre[f] = (int32_t)fe;
+      if (t == 0) {
+        pre[f] = (int32_t)fe;
+        *nnext = 0;
+      }
     }
     __syncthreads();
-    for (int32_t e = t; e < (int32_t)fe; e += kProbeThreads) {
-      int64_t lo = 0, hi = f - 1;   // owner: largest i with pre[i] <= e
+    const int nq = cur ^ 1;
+    for (int32_t e = t; e < (int32_t)fe; e += kFeatThreads) {
+      int32_t lo = 0, hi = f - 1;   // owner: largest i with pre[i] <= e
       while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
+        const int32_t mid = (lo + hi + 1) >> 1;
         if (pre[mid] <= e) lo = mid;
         else hi = mid - 1;
       }
-      const int32_t x = cur[lo];
-      const int32_t w = adj[(int64_t)off[x] + (e - pre[lo])];
-      if (insert(w)) nxt[atomicAdd(&nnext, 1)] = w;
+      const int32_t w = adj[qst[cur * kProbeCap + lo] + (e - pre[lo])];
+      if (insert(w)) push(nq, atomicAdd(nnext, 1), w);
     }
     __syncthreads();
     scanned += fe;
     ++levels;
-    f = nnext;
+    f = *nnext;
     reached += f;
-    int32_t* tq = cur;
-    cur = nxt;
-    nxt = tq;
+    cur = nq;
     __syncthreads();
   }
   if (t == 0) {
@@ -388,50 +428,67 @@ __global__ void __launch_bounds__(kProbeThreads) k_feat_probe(const I* __restric
   }
 }
 
-// Reduces the partials into the 16 features (written to out[0..15]); with a
-// model, normalises them, runs the forward pass and writes the argmin arm
-// (smallest index on ties) to out[16] as an int32, else -1.
-__global__ void __launch_bounds__(kH) k_feat_finish(int64_t n, int64_t m, const double* __restrict__ part,
-                                                    int nblocks, const int64_t* __restrict__ probe,
-                                                    const uint16_t* __restrict__ params, int K,
-                                                    const float* __restrict__ norm, float* __restrict__ out,
-                                                    float* __restrict__ Y) {
-  __shared__ double red[kPart][kH];
-  __shared__ float feat[kIn], x[kIn], a1[kH], a2[kH];
+__device__ __forceinline__ double load_f64_agent(const double* p) {
+  const unsigned long long u =
+      __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double d;
+  memcpy(&d, &u, 8);
+  return d;
+}
+
+// Reduces the partials into the 16 features (out[0..15]); with a model,
+// normalises them, runs the forward pass and writes the argmin arm (smallest
+// index on ties) to out[16] as an int32, else -1.
+__device__ void feat_finish(int64_t n, int64_t m, const double* part, int nb, const int64_t* probe,
+                            const uint16_t* __restrict__ params, int K, const NormArg& norm, float* __restrict__ out,
+                            unsigned char* smem) {
+  double* red = (double*)smem;                        // [kPart][kFeatThreads]
+  float* feat = (float*)(red + kPart * kFeatThreads);
+  float* xin = feat + kIn;
+  float* x = xin + kIn;
+  float* a1 = x + kIn;
+  float* a2 = a1 + kH;
+  float* Y = a2 + kH;
   const int t = threadIdx.x;
   double q[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int b = t; b < nblocks; b += kH)
-    for (int k = 0; k < kPart; ++k) q[k] = (k == 3) ? max_d(q[k], part[(int64_t)b * kPart + k]) : q[k] + part[(int64_t)b * kPart + k];
-  for (int k = 0; k < kPart; ++k) red[k][t] = q[k];
+  for (int b = t; b < nb; b += kFeatThreads)
+    for (int k = 0; k < kPart; ++k) q[k] = combine(k, q[k], load_f64_agent(part + (int64_t)b * kPart + k));
+  for (int k = 0; k < kPart; ++k) red[k * kFeatThreads + t] = q[k];
   __syncthreads();
+  for (int h = kFeatThreads / 2; h > 0; h >>= 1) {
+    if (t < h)
+      for (int k = 0; k < kPart; ++k)
+        red[k * kFeatThreads + t] = combine(k, red[k * kFeatThreads + t], red[k * kFeatThreads + t + h]);
+    __syncthreads();
+  }
   if (t == 0) {
-    for (int k = 0; k < kPart; ++k) {
-      double s = red[k][0];
-      for (int i = 1; i < kH; ++i) s = (k == 3) ? max_d(s, red[k][i]) : s + red[k][i];
-      q[k] = s;
-    }
+    double r[kPart];
+    for (int k = 0; k < kPart; ++k) r[k] = red[k * kFeatThreads];
+    const long long levels = __hip_atomic_load((const long long*)probe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long reached =
+        __hip_atomic_load((const long long*)probe + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double dn = (double)n, dm = (double)m;
-    const double mean = q[0] / dn;
-    const double var = q[1] / dn - mean * mean > 0 ? q[1] / dn - mean * mean : 0.0;
+    const double mean = r[0] / dn;
+    const double var = r[1] / dn - mean * mean > 0 ? r[1] / dn - mean * mean : 0.0;
     const double sd = sqrt(var);
-    const double skew = sd > 0 ? (q[2] / dn - 3 * mean * var - mean * mean * mean) / (sd * sd * sd) : 0.0;
-    const double cnt = q[7];
+    const double skew = sd > 0 ? (r[2] / dn - 3 * mean * var - mean * mean * mean) / (sd * sd * sd) : 0.0;
+    const double cnt = r[7];
     feat[0] = (float)log2(dn);
     feat[1] = (float)log2(dm + 1.0);
     feat[2] = (float)(dm / dn);
     feat[3] = (float)(mean > 0 ? sd / mean : 0.0);
-    feat[4] = (float)(mean > 0 ? q[3] / mean : 0.0);
-    feat[5] = (float)(q[4] / dn);
-    feat[6] = (float)(q[5] / dn);
-    feat[7] = (float)(q[6] / dn);
+    feat[4] = (float)(mean > 0 ? r[3] / mean : 0.0);
+    feat[5] = (float)(r[4] / dn);
+    feat[6] = (float)(r[5] / dn);
+    feat[7] = (float)(r[6] / dn);
     feat[8] = (float)(skew > 1e6 ? 1e6 : skew);
-    feat[9] = (float)(cnt > 0 ? q[8] / cnt : 0.0);
-    feat[10] = (float)(cnt > 0 ? q[9] / cnt : 0.0);
-    feat[11] = (float)(cnt > 0 ? q[10] / cnt : 0.0);
-    feat[12] = (float)probe[0];
-    feat[13] = (float)((double)probe[1] / dn);
+    feat[9] = (float)(cnt > 0 ? r[8] / cnt : 0.0);
+    feat[10] = (float)(cnt > 0 ? r[9] / cnt : 0.0);
+    feat[11] = (float)(cnt > 0 ? r[10] / cnt : 0.0);
+    feat[12] = (float)levels;
+    feat[13] = (float)((double)reached / dn);
     feat[14] = (float)(dm / dn < 3.0 ? 1.0 : 0.0);
-    feat[15] = (float)log2(q[3] + 1.0);
+    feat[15] = (float)log2(r[3] + 1.0);
     for (int i = 0; i < kIn; ++i) out[i] = feat[i];
   }
   __syncthreads();
@@ -439,8 +496,7 @@ __global__ void __launch_bounds__(kH) k_feat_finish(int64_t n, int64_t m, const 
     if (t == 0) ((int32_t*)out)[kIn] = -1;
     return;
   }
-  __shared__ float xin[kIn];
-  if (t < kIn) xin[t] = (feat[t] - norm[t]) / (norm[kIn + t] > 0.f ? norm[kIn + t] : 1.f);
+  if (t < kIn) xin[t] = (feat[t] - norm.v[t]) / (norm.v[kIn + t] > 0.f ? norm.v[kIn + t] : 1.f);
   __syncthreads();
   mlp_forward_row(mlp_view(params, K), K, xin, x, a1, a2, Y, nullptr);
   __syncthreads();
@@ -452,30 +508,47 @@ __global__ void __launch_bounds__(kH) k_feat_finish(int64_t n, int64_t m, const 
   }
 }
 
+template <typename I>
+__global__ void __launch_bounds__(kFeatThreads) k_features(int64_t n, int64_t m, const I* __restrict__ off,
+                                                           const int32_t* __restrict__ adj, uint64_t key,
+                                                           int32_t src, double* part,
+                                                           int64_t* probe, int nb, uint32_t* ticket,
+                                                           const uint16_t* __restrict__ params, int K, NormArg norm,
+                                                           float* __restrict__ out) {
+  __shared__ __align__(16) unsigned char smem[kFeatSmem];
+  __shared__ int last;
+  if (blockIdx.x < (unsigned)nb) feat_pass<I>(n, off, adj, key, nb, part, (double*)smem);
+  else feat_probe<I>(off, adj, src, probe, smem);
+  // publish this block's results, then take a ticket; the last block finishes
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)nb;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  feat_finish(n, m, part, nb, probe, params, K, norm, out, smem);
+  if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Features and, with a model, the chosen arm; one host synchronisation.
 template <typename I>
 static cc_status features_impl(StaticArgs& a, const uint16_t* params, int K, const float* norm_host, float* feat,
                                int* chosen) {
   char* sel = a.ws + a.L.mlp;
-  double* part = (double*)(sel + kSelPart);
+  double* part = (double*)(a.ws + a.L.count);
   int64_t* probe = (int64_t*)(sel + kSelProbe);
   float* out = (float*)(sel + kSelOut);
-  float* norm = (float*)(sel + kSelNorm);
-  float* Y = (float*)(sel + kSelY);
   const uint64_t key = sm_out(a.v->seed, kTagFeat);
-  const unsigned nb = grid_for(a.n, 256, kFeatBlocks);
-  hipLaunchKernelGGL(k_feat_pass<I>, dim3(nb), dim3(256), 0, a.s, a.n, (const I*)a.off, a.adj, key, part);
+  const int nb = (int)grid_for(div_up(a.n, 4), kFeatThreads, kFeatBlocks);
   const int32_t src = (int32_t)(sm_out(key, (uint64_t)kFeatSamples) % (uint64_t)a.n);
-  int32_t* qa = (int32_t*)(a.ws + a.L.queue);
-  int32_t* qb = (int32_t*)(a.ws + a.L.queue + align256((size_t)a.n * 4));
-  hipLaunchKernelGGL(k_feat_probe<I>, dim3(1), dim3(kProbeThreads), 0, a.s, (const I*)a.off, a.adj, src, qa, qb,
-                     probe);
-  if (params) CC_HIP(hipMemcpyAsync(norm, norm_host, 2 * kIn * sizeof(float), hipMemcpyHostToDevice, a.s));
-  hipLaunchKernelGGL(k_feat_finish, dim3(1), dim3(kH), 0, a.s, a.n, a.m, (const double*)part, (int)nb,
-                     (const int64_t*)probe, params, K, (const float*)norm, out, Y);
+  NormArg na;
+  for (int i = 0; i < 2 * kIn; ++i) na.v[i] = params ? norm_host[i] : 0.f;
+  hipLaunchKernelGGL(k_features<I>, dim3(nb + 1), dim3(kFeatThreads), 0, a.s, a.n, a.m, (const I*)a.off, a.adj, key,
+                     src, part, probe, nb, &a.ctx->dev->pad[1], params, K, na, out);
   CC_LAUNCH_CHECK();
-  float h[kIn + 1];
-  CC_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, a.s));
+  float* h = a.ctx->sel_host;
+  CC_HIP(hipMemcpyAsync(h, out, (kIn + 1) * sizeof(float), hipMemcpyDeviceToHost, a.s));
   CC_HIP(hipStreamSynchronize(a.s));
   memcpy(feat, h, kIn * sizeof(float));
   int32_t c;

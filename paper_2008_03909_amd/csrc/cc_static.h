@@ -23,6 +23,7 @@ struct StaticArgs {
   long long* hp = nullptr;   // degree prefix of `heavy`
   long long* tsum = nullptr; // tile sums of that prefix
   int64_t hcap = 0;          // capacity of `heavy`
+  int64_t heavy_vertices = -1;  // vertices with degree > kHeavyFrontier (-1: not counted yet)
   int64_t* ncomp_user = nullptr;
   int32_t sample_success = 1;
   int32_t sample_rounds = 0;
@@ -42,12 +43,14 @@ cc_status pull_scalars(StaticArgs& a);
 cc_status setup_args(StaticArgs& a, cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int o64,
                      const int32_t* adj, const cc_variant* v, void* ws, size_t ws_bytes, int32_t* labels,
                      int64_t* ncomp, void* stream);
-// Init + sampling + IdentifyFrequent only / the rest of Algorithm 1 after it.
-cc_status static_sample_only(StaticArgs& a);
-cc_status static_from_sample(StaticArgs& a);
 // BFS from `source` for at most `level_cap` levels (<= 0: no cap) over the
 // workspace bitmaps; reports vertices reached and levels expanded.
 template <typename I> cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reached,
                                           int32_t* levels);
+// Number of vertices with degree > kHeavyFrontier (cached in a).
+template <typename I> cc_status count_heavy(StaticArgs& a);
+// Degree prefix of a device-counted vertex list: one block when the list is
+// known to be short, else the three-launch version.
+template <typename I> void list_prefix(StaticArgs& a, const int32_t* list, const int32_t* count_ptr);
 
 }  // namespace cc

@@ -296,7 +296,8 @@ constexpr int kHotSlots = 32;
 
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_compress_count(int64_t n, const I* __restrict__ off, int32_t* P,
-                                                           int32_t* __restrict__ count, int aligned) {
+                                                           int32_t* __restrict__ count, int2* __restrict__ hotpart,
+                                                           int aligned) {
   __shared__ int32_t hot_label[kHotSlots];
   __shared__ int32_t hot_cnt[kHotSlots];
   if (threadIdx.x < kHotSlots) {
@@ -354,9 +355,41 @@ __global__ void __launch_bounds__(kBlock) k_compress_count(int64_t n, const I* _
   }
   if (!count) return;
   __syncthreads();
-  if (threadIdx.x < kHotSlots && hot_cnt[threadIdx.x] > 0)
-    __hip_atomic_fetch_add(count + hot_label[threadIdx.x], hot_cnt[threadIdx.x], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+  // Entries counted more than once in this block go to the block's own
+  // slots of hotpart and a merge kernel adds them, so a class spread over
+  // every block costs no address one atomic per block; single counts (small
+  // classes, each touching few blocks) are added directly.
+  if (threadIdx.x < kHotSlots) {
+    const int32_t c = hot_cnt[threadIdx.x], lab = hot_label[threadIdx.x];
+    const bool keep = c > 1;
+    if (c == 1) __hip_atomic_fetch_add(count + lab, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    hotpart[(int64_t)blockIdx.x * kHotSlots + threadIdx.x] = make_int2(keep ? lab : -1, keep ? c : 0);
+  }
+}
+
+// Adds the blocks' hot-table entries into count: block (s, c) walks slot s
+// of blocks [256c, 256c + 256); a wave peels runs of equal labels and adds
+// each run once.
+__global__ void __launch_bounds__(kBlock) k_hot_merge(int nblocks, const int2* __restrict__ hotpart,
+                                                      int32_t* __restrict__ count) {
+  const int s = blockIdx.x % kHotSlots;
+  {
+    const int b = (blockIdx.x / kHotSlots) * kBlock + threadIdx.x;
+    int2 e = make_int2(-1, 0);
+    if (b < nblocks) e = hotpart[(int64_t)b * kHotSlots + s];
+    bool c = e.x >= 0;
+    uint64_t mact = __ballot(c);
+    while (mact) {
+      const int leader = __ffsll((unsigned long long)mact) - 1;
+      const int32_t lead = __shfl(e.x, leader, kWave);
+      const bool mine = c && e.x == lead;
+      int32_t add = mine ? e.y : 0;
+      for (int o = 32; o > 0; o >>= 1) add += __shfl_xor(add, o, kWave);
+      if (lane_id() == leader) __hip_atomic_fetch_add(count + lead, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      mact &= ~__ballot(mine);
+      if (mine) c = false;
+    }
+  }
 }
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
@@ -367,9 +400,11 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
   return x;
 }
 
-// IdentifyFrequent: max over (count << 32 | ~label); ties go to the smaller label.
-__global__ void __launch_bounds__(kBlock) k_argmax(int64_t n, const int32_t* __restrict__ count, DevScalars* sc,
-                                                   int aligned) {
+// IdentifyFrequent: max over (count << 32 | ~label); ties go to the smaller
+// label.  Each block writes its maximum to part[blockIdx]; one block
+// reduces them (no address takes an atomic per block).
+__global__ void __launch_bounds__(kBlock) k_argmax(int64_t n, const int32_t* __restrict__ count,
+                                                   unsigned long long* __restrict__ part, int aligned) {
   __shared__ unsigned long long red[kBlock / kWave];
   unsigned long long best = 0;
   const int64_t groups = div_up_dev(n, 4);
@@ -390,7 +425,7 @@ __global__ void __launch_bounds__(kBlock) k_argmax(int64_t n, const int32_t* __r
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kBlock / kWave; ++w) best = red[w] > best ? red[w] : best;
-    if (best) atomicMax(&sc->lmax_key, best);
+    part[blockIdx.x] = best;
   }
 }
 
@@ -398,10 +433,22 @@ __device__ __forceinline__ int32_t lmax_of(unsigned long long key) {
   return key ? (int32_t)(~(uint32_t)(key & 0xffffffffull)) : -1;
 }
 
-__global__ void k_resolve_lmax(DevScalars* sc, int use) {
-  unsigned long long key = sc->lmax_key;
-  sc->lmax = use ? lmax_of(key) : -1;
-  sc->lmax_size = use ? (long long)(key >> 32) : 0;
+// Reduces nparts block maxima (nparts 0: no frequent label) and publishes
+// lmax and its class size.
+__global__ void __launch_bounds__(kBlock) k_resolve_lmax(DevScalars* sc, const unsigned long long* __restrict__ part,
+                                                         int nparts) {
+  __shared__ unsigned long long red[kBlock / kWave];
+  unsigned long long best = 0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) best = part[i] > best ? part[i] : best;
+  best = wave_max_u64(best);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) best = red[w] > best ? red[w] : best;
+    sc->lmax_key = best;
+    sc->lmax = lmax_of(best);
+    sc->lmax_size = (long long)(best >> 32);
+  }
 }
 
 // Candidate compaction with degree binning, in three launches and without
@@ -470,39 +517,58 @@ __global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, co
 }
 
 // One block: exclusive scan of the per-segment counts (four bins), totals
-// into the context scalars.
+// into the context scalars.  Each thread sums a run of segments; the runs
+// are scanned with wave shuffles and a second-level scan of the 16 wave
+// totals.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+  const int lane = lane_id();
+  for (int o = 1; o < kWave; o <<= 1) {
+    const T y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
 __global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* segcnt, const long long* segedges,
                                                        DevScalars* sc) {
-  __shared__ int32_t part[4][1024];
-  __shared__ long long epart[1024];
-  const int t = threadIdx.x;
+  constexpr int kWaves = 1024 / kWave;
+  __shared__ int32_t wtot[4][kWaves];
+  __shared__ long long etot[kWaves];
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
   const int64_t per = div_up_dev(nseg, 1024);
-  const int64_t lo = t * per, hi = (lo + per < nseg) ? lo + per : nseg;
+  const int64_t lo = t * per < nseg ? t * per : nseg;
+  const int64_t hi = (lo + per < nseg) ? lo + per : nseg;
   int32_t s[4] = {0, 0, 0, 0};
   long long e = 0;
   for (int64_t i = lo; i < hi; ++i) {
     for (int q = 0; q < 4; ++q) s[q] += segcnt[4 * i + q];
     e += segedges[i];
   }
-  for (int q = 0; q < 4; ++q) part[q][t] = s[q];
-  epart[t] = e;
+  int32_t inc[4];
+  for (int q = 0; q < 4; ++q) {
+    inc[q] = wave_incl_scan(s[q]);
+    if (lane == kWave - 1) wtot[q][w] = inc[q];
+  }
+  const long long einc = wave_incl_scan(e);
+  if (lane == kWave - 1) etot[w] = einc;
   __syncthreads();
-  if (t < 4) {  // serial exclusive scan of the 1024 partials of one bin
+  if (t < 4) {  // exclusive scan of the 16 wave totals of bin t
     int32_t run = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const int32_t x = part[t][i];
-      part[t][i] = run;
+    for (int i = 0; i < kWaves; ++i) {
+      const int32_t x = wtot[t][i];
+      wtot[t][i] = run;
       run += x;
     }
     sc->bin_count[t] = run;
   } else if (t == 4) {
     long long tot = 0;
-    for (int i = 0; i < 1024; ++i) tot += epart[i];
+    for (int i = 0; i < kWaves; ++i) tot += etot[i];
     sc->cand_edges = tot;
   }
   __syncthreads();
   int32_t r[4];
-  for (int q = 0; q < 4; ++q) r[q] = part[q][t];
+  for (int q = 0; q < 4; ++q) r[q] = wtot[q][w] + inc[q] - s[q];
   for (int64_t i = lo; i < hi; ++i)
     for (int q = 0; q < 4; ++q) {
       const int32_t x = segcnt[4 * i + q];
@@ -639,15 +705,25 @@ cc_status compress_count_frequent(StaticArgs& a, bool use_lmax) {
   const int vec = vec_ok(a);
   {
     PhaseScope ps(a.ctx, a.s, "compress_count");
-    hipLaunchKernelGGL(k_compress_count<I>, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, (const I*)a.off, a.P,
-                       use_lmax ? a.count : (int32_t*)nullptr, vec);
+    // per-block hot-table entries: kHotSlots int2 per block, in the
+    // candidate array (unused until compaction; large enough for any n)
+    int2* hotpart = (int2*)a.cand;
+    const unsigned nb = grid4(a.n);
+    hipLaunchKernelGGL(k_compress_count<I>, dim3(nb), dim3(kBlock), 0, a.s, a.n, (const I*)a.off, a.P,
+                       use_lmax ? a.count : (int32_t*)nullptr, hotpart, vec);
+    if (use_lmax)
+      hipLaunchKernelGGL(k_hot_merge, dim3(kHotSlots * div_up(nb, kBlock)), dim3(kBlock), 0, a.s, (int)nb,
+                         (const int2*)hotpart, a.count);
   }
   {
     PhaseScope ps(a.ctx, a.s, "frequent");
+    // block maxima in the compaction area (unused until compaction)
+    unsigned long long* part = (unsigned long long*)(a.ws + a.L.seg);
+    const unsigned nb = grid4(a.n);
     if (use_lmax)
-      hipLaunchKernelGGL(k_argmax, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, (const int32_t*)a.count, a.ctx->dev,
-                         vec);
-    hipLaunchKernelGGL(k_resolve_lmax, dim3(1), dim3(1), 0, a.s, a.ctx->dev, use_lmax ? 1 : 0);
+      hipLaunchKernelGGL(k_argmax, dim3(nb), dim3(kBlock), 0, a.s, a.n, (const int32_t*)a.count, part, vec);
+    hipLaunchKernelGGL(k_resolve_lmax, dim3(1), dim3(kBlock), 0, a.s, a.ctx->dev, (const unsigned long long*)part,
+                       use_lmax ? (int)nb : 0);
   }
   CC_LAUNCH_CHECK();
   return CC_OK;
@@ -754,10 +830,6 @@ static cc_status run_tail(StaticArgs& a) {
   return CC_OK;
 }
 
-cc_status static_sample_only(StaticArgs& a) {
-  return a.o64 ? run_static<int64_t>(a, true) : run_static<int32_t>(a, true);
-}
-cc_status static_from_sample(StaticArgs& a) { return a.o64 ? run_tail<int64_t>(a) : run_tail<int32_t>(a); }
 
 cc_status setup_args(StaticArgs& a, cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int o64,
                             const int32_t* adj, const cc_variant* v, void* ws, size_t ws_bytes, int32_t* labels,
@@ -820,8 +892,12 @@ cc_status cc_ctx_create(int device, cc_ctx** out) {
   cc_ctx* c = new cc_ctx();
   c->device = device;
   if (hipMalloc((void**)&c->dev, sizeof(DevScalars)) != hipSuccess ||
-      hipHostMalloc((void**)&c->host, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->host, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->sel_host, 256, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->ring_host, 256, hipHostMallocDefault) != hipSuccess) {
     if (c->dev) hipFree(c->dev);
+    if (c->host) hipHostFree(c->host);
+    if (c->sel_host) hipHostFree(c->sel_host);
     delete c;
     return fail(CC_ENOMEM, "cannot allocate context state");
   }
@@ -843,6 +919,8 @@ void cc_ctx_destroy(cc_ctx* ctx) {
   for (auto e : ctx->event_pool) hipEventDestroy(e);
   if (ctx->dev) hipFree(ctx->dev);
   if (ctx->host) hipHostFree(ctx->host);
+  if (ctx->sel_host) hipHostFree(ctx->sel_host);
+  if (ctx->ring_host) hipHostFree(ctx->ring_host);
   delete ctx;
 }
 

@@ -375,7 +375,7 @@ def test_sampled_features_closed_forms():
     off, adj = oracle.csr_build(k.n, k.u, k.v)
     f = oracle.sampled_features(40, off, adj, 3)
     assert abs(f[11] - np.log2(40)) < 1e-12
-    assert f[12] == 2 and f[13] == 1.0          # 39 + 39*39 entries fit 4096: 2 levels reach everything
+    assert f[12] == 1 and f[13] == 1.0          # one level reaches everything; 39 + 39*39 > 1024 stops the next
     # no edges: the sampled means are 0, the probe expands its isolated source
     e = inputs.empty(100)
     off, adj = oracle.csr_build(e.n, e.u, e.v)

@@ -1,0 +1,53 @@
+"""What the trained selector gains over the method without it, on the CPU
+from committed data: the network trained on the GPU
+(paper_2008_03909_amd/selector_data/model.npz) is applied by the oracle's
+MLP forward pass to the recorded features of the 200 held-out corpus graphs
+(seed % 10 == 0); the recorded time of each selected arm is compared with
+the per-graph best arm, the fixed default (k-out + UF-Rem-CAS /
+SplitAtomicOne / FindNaive) and the paper's text rules."""
+import glob
+import os
+
+import numpy as np
+
+from oracle import mlp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DATA = os.path.join(ROOT, "paper_2008_03909_amd", "selector_data")
+DEFAULT_ARM = 4
+
+
+def _corpus():
+    zs = [np.load(p, allow_pickle=False) for p in sorted(glob.glob(os.path.join(DATA, "corpus_*.npz")))]
+    assert zs, "no committed corpus"
+    return {k: np.concatenate([z[k] for z in zs]) for k in ("seeds", "features", "times")}
+
+
+def _picks(features):
+    z = np.load(os.path.join(DATA, "model.npz"), allow_pickle=False)
+    K, norm = int(z["K"]), z["norm"].astype(np.float64)
+    sd = np.where(norm[16:] > 0, norm[16:], 1.0)
+    x = (features.astype(np.float32) - norm[:16].astype(np.float32)) / sd.astype(np.float32)
+    y, _ = mlp.forward(mlp.bf16_round(z["master"]), x.astype(np.float64), K)
+    return y.argmin(1)
+
+
+def test_corpus_shape():
+    C = _corpus()
+    assert C["seeds"].size == 2000 and np.unique(C["seeds"]).size == 2000
+    assert np.sum(C["seeds"] % 10 == 0) == 200
+    assert C["times"].shape == (2000, 16) and np.all(C["times"] > 0)
+
+
+def test_trained_selector_against_best_default_and_rules():
+    C = _corpus()
+    held = C["seeds"] % 10 == 0
+    t = C["times"][held]
+    pick = _picks(C["features"][held])
+    sel = t[np.arange(t.shape[0]), pick].mean()
+    best = t.min(1).mean()
+    default = t[:, DEFAULT_ARM].mean()
+    rules = t[np.arange(t.shape[0]), np.where(C["features"][held][:, 14] > 0.5, 0, DEFAULT_ARM)].mean()
+    assert sel <= 1.10 * best, (sel, best)
+    assert sel < 0.9 * default, (sel, default)
+    assert sel < rules, (sel, rules)
