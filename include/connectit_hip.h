@@ -291,11 +291,12 @@ cc_status cc_mlp_pack_bf16(const float* src, uint16_t* dst, int64_t count, void*
  * log2(m+1), m/n, coefficient of variation, max/mean, fractions of degree 0,
  * 1 and <= 2, skewness, [m/n < 3], log2(max degree + 1)); statistics of
  * 4096 seeded vertex draws (fraction whose first neighbour id is smaller,
- * mean log-distance to it, mean log-degree of it); and a BFS from a seeded
- * source that expands whole levels within 4 levels and 1024 scanned
- * adjacency entries (levels expanded, fraction of vertices reached).  The
- * exact definitions are in the selector source.  workspace as for
- * cc_connectivity_csr with the default variant.  Synchronises hip_stream. */
+ * mean log-distance to it, mean log-degree of it); and 16 BFS probes from
+ * seeded sources, each expanding whole levels within 4 levels and 1024
+ * scanned adjacency entries (mean levels expanded, mean fraction of
+ * vertices reached).  The exact definitions are in the selector source.
+ * workspace as for cc_connectivity_csr with the default variant.
+ * Synchronises hip_stream. */
 cc_status cc_graph_features(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
                             const int32_t* adj, void* workspace, size_t ws_bytes, float* features_host,
                             void* hip_stream);

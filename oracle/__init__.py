@@ -220,6 +220,7 @@ FEATURE_TAG = 0x66656174       # "feat": stream of the selector's draws
 FEATURE_SAMPLES = 4096
 PROBE_LEVELS = 4
 PROBE_EDGES = 1024
+PROBES = 16
 
 
 def sampled_features(n: int, offsets, adj, seed: int):
@@ -227,9 +228,9 @@ def sampled_features(n: int, offsets, adj, seed: int):
     vertices v_i = splitmix(key, i) mod n for i < 4096 with key =
     splitmix(seed, "feat"); over the drawn vertices that have an edge, with
     f = the first entry of v's row: 9 = mean [f < v], 10 = mean
-    log2(1 + |v - f|) / log2(n + 1), 11 = mean log2(1 + deg f); then a
-    whole-level BFS from splitmix(key, 4096) mod n within 4 levels and 1024
-    scanned entries: 12 = levels, 13 = reached / n."""
+    log2(1 + |v - f|) / log2(n + 1), 11 = mean log2(1 + deg f); then
+    whole-level BFSs from splitmix(key, 4096 + p) mod n, p < 16, each within
+    4 levels and 1024 scanned entries: 12 = mean levels, 13 = mean reached / n."""
     off = np.asarray(offsets, np.int64)
     a = np.asarray(adj)
     key = splitmix_out(seed, FEATURE_TAG)
@@ -242,10 +243,14 @@ def sampled_features(n: int, offsets, adj, seed: int):
             down += f < v
             loc += np.log2(1.0 + abs(v - f)) / np.log2(n + 1.0)
             hub += np.log2(1.0 + float(off[f + 1] - off[f]))
-    src = splitmix_out(key, FEATURE_SAMPLES) % n
-    reached, levels = bfs_budget(n, off, a, src, PROBE_LEVELS, PROBE_EDGES)
+    lv = rc = 0.0
+    for p in range(PROBES):
+        src = splitmix_out(key, FEATURE_SAMPLES + p) % n
+        reached, levels = bfs_budget(n, off, a, src, PROBE_LEVELS, PROBE_EDGES)
+        lv += levels
+        rc += reached
     out = {9: down / cnt if cnt else 0.0, 10: loc / cnt if cnt else 0.0, 11: hub / cnt if cnt else 0.0,
-           12: float(levels), 13: reached / n}
+           12: lv / PROBES, 13: rc / PROBES / n}
     return out
 
 

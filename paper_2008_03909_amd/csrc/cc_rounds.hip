@@ -141,15 +141,91 @@ struct LtConnect {
 };
 
 // Copies the candidates' edges into an explicit list (needed by Alter).
-struct EmitEdge {
-  int32_t* eu;
-  int32_t* ev;
-  unsigned long long* cnt;
-  __device__ __forceinline__ bool operator()(int32_t u, int32_t w) const {
-    wave_append_pair(u != w, u, w, eu, ev, cnt);
-    return false;
+// The grid bin's edges take positions [0, hp[c3]) directly (their degree
+// prefix exists); the other bins follow: a wave takes 64 candidates, scans
+// their degrees and reserves the whole tile's range with one atomic.  A
+// self-loop leaves a dead entry (eu = -1).
+__global__ void k_lt_emit_base(const long long* hp, const DevScalars* sc, unsigned long long* cnt) {
+  *cnt = (unsigned long long)hp[sc->bin_count[3]];
+}
+
+template <typename I>
+__global__ void __launch_bounds__(kFBlock) k_lt_emit_heavy(const int32_t* __restrict__ heavy, const DevScalars* sc,
+                                                           const long long* __restrict__ hp, const I* __restrict__ off,
+                                                           const int32_t* __restrict__ adj, int32_t* eu, int32_t* ev) {
+  const int64_t c = sc->bin_count[3];
+  if (c == 0) return;
+  const long long T = hp[c];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
+    const long long e = base + threadIdx.x;
+    const long long e0 = base + (threadIdx.x / kWave) * kWave;
+    if (e < T) {
+      const int64_t i = heavy_owner_tile(hp, c, e0, e);
+      const int32_t u = heavy[i];
+      const int32_t w = adj[(int64_t)off[u] + (e - hp[i])];
+      eu[e] = u == w ? -1 : u;
+      ev[e] = w;
+    }
   }
-};
+}
+
+template <typename I>
+__global__ void __launch_bounds__(kFBlock) k_lt_emit(int64_t n, const int32_t* __restrict__ cand,
+                                                     const int32_t* __restrict__ big, const DevScalars* sc,
+                                                     const I* __restrict__ off, const int32_t* __restrict__ adj,
+                                                     int32_t* eu, int32_t* ev, unsigned long long* cnt) {
+  constexpr int W = kFBlock / kWave;
+  __shared__ int32_t tpre[W][kWave + 1];
+  __shared__ int64_t tbeg[W][kWave];
+  __shared__ int32_t tu[W][kWave];
+  const int wv = threadIdx.x / kWave, lane = lane_id();
+  const int64_t c0 = sc->bin_count[0], c1 = sc->bin_count[1], c2 = sc->bin_count[2];
+  const int64_t total_c = c0 + c1 + c2;
+  const int64_t tiles = (total_c + kWave - 1) / kWave;
+  const int64_t waves = (int64_t)gridDim.x * W;
+  for (int64_t tile = blockIdx.x * (int64_t)W + wv; tile < tiles; tile += waves) {
+    const int64_t i = tile * kWave + lane;
+    int32_t u = 0;
+    int64_t b = 0, d = 0;
+    if (i < total_c) {
+      u = i < c0 ? cand[i] : (i < c0 + c1 ? big[i - c0] : big[n - 1 - (i - c0 - c1)]);
+      b = (int64_t)off[u];
+      d = (int64_t)off[u + 1] - b;   // <= kThrGrid in these bins
+    }
+    int32_t inc = (int32_t)d;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int32_t y = __shfl_up(inc, o, kWave);
+      if (lane >= o) inc += y;
+    }
+    const int32_t total = __shfl(inc, kWave - 1, kWave);
+    tpre[wv][lane] = inc - (int32_t)d;
+    tbeg[wv][lane] = b;
+    tu[wv][lane] = u;
+    unsigned long long base = 0;
+    if (lane == 0 && total > 0)
+      base = __hip_atomic_fetch_add(cnt, (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    base = __shfl(base, 0, kWave);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int32_t e = lane; e < total; e += kWave) {
+      int lo = 0, hi = kWave - 1;   // last row whose start <= e
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tpre[wv][mid] <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      const int32_t uu = tu[wv][lo];
+      const int32_t w = adj[tbeg[wv][lo] + (e - tpre[wv][lo])];
+      eu[base + e] = uu == w ? -1 : uu;
+      ev[base + e] = w;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
 
 template <bool PARENT>
 __global__ void k_lt_connect_list(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
@@ -201,9 +277,12 @@ static cc_status lt_rounds(StaticArgs& a) {
   if (alter) {
     eu = (int32_t*)(a.ws + a.L.edges);
     ev = (int32_t*)(a.ws + a.L.edges + align256((size_t)a.m * 4));
-    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, (uint32_t*)ecnt, 0u);
-    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, (uint32_t*)ecnt + 1, 0u);
-    visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, EmitEdge{eu, ev, ecnt}, (uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_lt_emit_base, dim3(1), dim3(1), 0, a.s, (const long long*)a.hp, (const DevScalars*)sc, ecnt);
+    hipLaunchKernelGGL(k_lt_emit_heavy<I>, dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
+                       (const DevScalars*)sc, (const long long*)a.hp, (const I*)a.off, a.adj, eu, ev);
+    hipLaunchKernelGGL(k_lt_emit<I>, dim3(grid_for(a.n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, a.n,
+                       (const int32_t*)a.cand, (const int32_t*)a.big, (const DevScalars*)sc, (const I*)a.off, a.adj,
+                       eu, ev, ecnt);
   }
   for (int round = 0;; ++round) {
     if (round >= kRoundCap) return fail(CC_ELIVELOCK, "Liu-Tarjan exceeded %d rounds", kRoundCap);

@@ -44,7 +44,9 @@ cc_status pull_scalars(StaticArgs& a) {
 // batch's snapshot while the current batch runs, and stops once a snapshot
 // says the search finished (the levels queued after it do nothing).
 
-enum : uint32_t { kBfsTopDown = 0, kBfsBottomUp = 1, kBfsDone = 2 };
+enum : uint32_t { kBfsTopDown = 0, kBfsBottomUp = 1, kBfsDone = 2, kBfsSmall = 3 };
+constexpr int kSmallEdges = 4096;      // single-block levels while a frontier scans at most this many entries
+constexpr int kSmallLevels = 2048;     // at most this many single-block levels per launch
 constexpr int kBfsParts = 2048;        // per-block degree sums of the next frontier
 constexpr int kBfsStepBlocks = 1024;   // fpart[0, 1024): step; [1024, 2048): heavy rows
 constexpr double kBeamerAlpha = 15.0, kBeamerBeta = 18.0;   // direction-switch constants (Beamer et al.)
@@ -103,7 +105,11 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_begin(int64_t words, uint32_t* 
         mode = kBfsBottomUp;
       } else if (mode == kBfsBottomUp && (double)nf < (double)n / kBeamerBeta) {
         mode = kBfsTopDown;
+      } else if (mode == kBfsSmall) {
+        mode = kBfsTopDown;
       }
+      // a frontier this small is expanded level after level by one block
+      if (mode == kBfsTopDown && mf <= kSmallEdges && (level_cap <= 0)) mode = kBfsSmall;
       sc->bfs_mode = mode;
       sc->qcount[cur ^ 1] = 0;
       sc->hcount = 0;
@@ -112,6 +118,97 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_begin(int64_t words, uint32_t* 
   }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += stride) fn[i] = 0u;
+}
+
+// Small frontiers (degree sum <= kSmallEdges): one block expands level after
+// level, with the frontier's degree prefix in LDS and __syncthreads between
+// levels, while the frontier stays that small (at most kSmallLevels levels).
+// Queues alternate between qin and qout; the last frontier produced (not yet
+// expanded) is left in qout with its bits in fn, as if one level had run,
+// and the levels, reached vertices and scanned edges of the internal levels
+// are added to the device counters.  Returns that frontier's degree sum.
+template <typename I>
+__device__ long long bfs_small_levels(const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis,
+                                      uint32_t* fn, const int32_t* qin0, uint32_t f0, int32_t* qout0,
+                                      uint32_t* cnt_out, DevScalars* sc) {
+  __shared__ int32_t spre[kSmallEdges + 2];
+  __shared__ long long stsum[kFBlock];
+  __shared__ long long stotal;
+  __shared__ int32_t snn;
+  const int t = threadIdx.x;
+  int32_t* qa = const_cast<int32_t*>(qin0);
+  int32_t* qb = qout0;
+  int64_t f = f0;
+  int levels = 0;
+  long long reached_add = 0, seen_add = 0, fe = 0;
+  while (true) {
+    // degree sum of the current frontier (contiguous chunk per thread)
+    const int64_t chunk = (f + kFBlock - 1) / kFBlock;
+    const int64_t i0 = t * chunk < f ? t * chunk : f;
+    const int64_t i1 = i0 + chunk < f ? i0 + chunk : f;
+    long long sum = 0;
+    for (int64_t i = i0; i < i1; ++i) sum += (long long)off[qa[i] + 1] - (long long)off[qa[i]];
+    stsum[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+      long long acc = 0;
+      for (int i = 0; i < kFBlock; ++i) {
+        const long long x = stsum[i];
+        stsum[i] = acc;
+        acc += x;
+      }
+      stotal = acc;
+      snn = 0;
+    }
+    __syncthreads();
+    fe = stotal;
+    if (f == 0 || (levels > 0 && (fe > kSmallEdges || levels >= kSmallLevels))) break;
+    if (levels > 0) {            // an internally produced frontier about to be expanded
+      reached_add += f;
+      seen_add += fe;
+    }
+    {
+      int32_t acc = (int32_t)stsum[t];
+      for (int64_t i = i0; i < i1; ++i) {
+        spre[i] = acc;
+        acc += (int32_t)((long long)off[qa[i] + 1] - (long long)off[qa[i]]);
+      }
+      if (t == 0) spre[f] = (int32_t)fe;
+    }
+    __syncthreads();
+    for (int32_t e = t; e < (int32_t)fe; e += kFBlock) {
+      int64_t lo = 0, hi = f - 1;   // owner: largest i with spre[i] <= e
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (spre[mid] <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      const int32_t x = qa[lo];
+      const int32_t w = adj[(int64_t)off[x] + (e - spre[lo])];
+      if (bit_claim(vis, w)) qb[atomicAdd(&snn, 1)] = w;
+    }
+    __syncthreads();
+    f = snn;
+    ++levels;
+    int32_t* tq = qa;
+    qa = qb;
+    qb = tq;
+    __syncthreads();
+  }
+  // the current frontier (qa, f entries) is the output
+  if (qa != qout0)
+    for (int64_t i = t; i < f; i += kFBlock) qout0[i] = qa[i];
+  for (int64_t i = t; i < f; i += kFBlock) {
+    const int32_t w = qa[i];
+    aor(fn + (w >> 5), 1u << (w & 31));
+  }
+  if (t == 0) {
+    *cnt_out = (uint32_t)f;
+    sc->bfs_level += levels - 1;
+    sc->reached += reached_add;
+    sc->seen_edges += seen_add;
+  }
+  return t == 0 ? fe : 0;
 }
 
 // One BFS level.  Top-down: the wave-balanced expansion of the frontier
@@ -127,7 +224,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
                                                       const uint32_t* __restrict__ fc, uint32_t* fn,
                                                       const int32_t* __restrict__ qin, const uint32_t* cnt_in,
                                                       int32_t* qout, uint32_t* cnt_out, int32_t* heavy,
-                                                      int32_t* hcount, const DevScalars* sc,
+                                                      int32_t* hcount, DevScalars* sc,
                                                       long long* __restrict__ fpart) {
   constexpr int W = kFBlock / kWave;
   __shared__ int32_t qbuf[W][kWaveQCap];
@@ -139,7 +236,9 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
   const int lane = lane_id();
   WaveQ q{qbuf[wv], 0};
   long long added = 0;
-  if (mode == kBfsTopDown) {
+  if (mode == kBfsSmall) {
+    if (blockIdx.x == 0) added = bfs_small_levels<I>(off, adj, vis, fn, qin, *cnt_in, qout, cnt_out, sc);
+  } else if (mode == kBfsTopDown) {
     const int64_t cnt = *cnt_in;
     const int64_t tiles = (cnt + kWave - 1) / kWave;
     const int64_t waves = (int64_t)gridDim.x * W;
@@ -311,7 +410,7 @@ cc_status count_heavy(StaticArgs& a) {
   if (a.heavy_vertices >= 0) return CC_OK;
   unsigned long long* d = &a.ctx->dev->heavy_count;
   hipLaunchKernelGGL(k_zero_u64_one, dim3(1), dim3(1), 0, a.s, d);
-  hipLaunchKernelGGL(k_count_heavy<I>, dim3(grid_for(a.n, kFBlock, 256)), dim3(kFBlock), 0, a.s, a.n,
+  hipLaunchKernelGGL(k_count_heavy<I>, dim3(grid_for(a.n, kFBlock, 1024)), dim3(kFBlock), 0, a.s, a.n,
                      (const I*)a.off, d);
   CC_LAUNCH_CHECK();
   unsigned long long h = 0;
@@ -526,7 +625,7 @@ cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reach
                          m, level_cap);
       hipLaunchKernelGGL(k_bfs_step<I>, dim3(gs), dim3(kFBlock), 0, a.s, n, off, a.adj, vis, (const uint32_t*)fc, fn,
                          (const int32_t*)q[cur], &sc->qcount[cur], q[cur ^ 1], &sc->qcount[cur ^ 1], a.heavy,
-                         &sc->hcount, (const DevScalars*)sc, fpart);
+                         &sc->hcount, sc, fpart);
       if (heavy) {
         list_prefix<I>(a, a.heavy, (const int32_t*)&sc->hcount);
         hipLaunchKernelGGL(k_bfs_heavy<I>, dim3(gh), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
@@ -684,33 +783,28 @@ __global__ void __launch_bounds__(kFBlock) k_ldd_wake(int64_t lo, int64_t hi, ui
   wq_flush(wq, q, cnt);
 }
 
-// Minimum member of every cluster: runs of equal cluster labels in a wave
-// are peeled and take one atomic each (after a plain read shows it helps).
-__global__ void __launch_bounds__(kFBlock) k_min_member(int64_t n, const int32_t* __restrict__ P, int32_t* mn) {
+// Minimum member of every cluster.  mn[c] starts at c, so only members with
+// a smaller id than their centre can lower it (after a plain read shows they
+// would); clusters whose minimum moved are marked in `moved`, so the relabel
+// reads mn only for those.
+__global__ void __launch_bounds__(kFBlock) k_min_member(int64_t n, const int32_t* __restrict__ P, int32_t* mn,
+                                                        uint32_t* moved) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
-    const int64_t v = base + threadIdx.x;
-    const bool act = v < n;
-    const int32_t c = act ? P[v] : 0;
-    uint64_t mact = __ballot(act);
-    while (mact) {
-      const int leader = __ffsll((unsigned long long)mact) - 1;
-      const int32_t lead = __shfl(c, leader, kWave);
-      const bool mine = act && c == lead;
-      int32_t x = mine ? (int32_t)v : 0x7fffffff;
-      for (int o = 32; o > 0; o >>= 1) {
-        const int32_t y = __shfl_xor(x, o, kWave);
-        x = y < x ? y : x;
-      }
-      if (lane_id() == leader && x < ld(mn + lead)) amin(mn + lead, x);
-      mact &= ~__ballot(mine);
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int32_t c = P[v];
+    if ((int32_t)v < c && (int32_t)v < ld(mn + c)) {
+      amin(mn + c, (int32_t)v);
+      if (!bit_get(moved, c)) aor(moved + (c >> 5), 1u << (c & 31));
     }
   }
 }
 
-__global__ void k_relabel(int64_t n, int32_t* P, const int32_t* __restrict__ mn) {
+__global__ void k_relabel(int64_t n, int32_t* P, const int32_t* __restrict__ mn, const uint32_t* __restrict__ moved) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) P[v] = mn[P[v]];
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int32_t c = P[v];
+    if (bit_get(moved, c)) P[v] = mn[c];
+  }
 }
 
 template <typename I>
@@ -769,10 +863,12 @@ cc_status sample_ldd(StaticArgs& a) {
   }
   // After the last wake every vertex is visited; the last expansion claimed
   // nothing new.  Relabel each cluster to its minimum member.
+  uint32_t* moved = (uint32_t*)(a.ws + a.L.bits + align256((size_t)words * 4));   // second bitmap
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words, kFBlock, 4096)), dim3(kFBlock), 0, a.s, moved, words, 0u);
   hipLaunchKernelGGL(k_min_member, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, (const int32_t*)a.P,
-                     mn);
+                     mn, moved);
   hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, a.P,
-                     (const int32_t*)mn);
+                     (const int32_t*)mn, (const uint32_t*)moved);
   CC_LAUNCH_CHECK();
   return CC_OK;
 }

@@ -17,9 +17,9 @@
 // entry of v's row):
 //   9 mean [f < v]    10 mean log2(1 + |v - f|) / log2(n + 1)
 //   11 mean log2(1 + deg f)
-// and a BFS from a seeded source that expands whole levels while at most
-// 1024 adjacency entries are scanned and at most 4 levels:
-//   12 levels expanded     13 vertices reached / n
+// and 16 BFS probes from seeded sources, each expanding whole levels while
+// at most 1024 adjacency entries are scanned and at most 4 levels:
+//   12 mean levels expanded     13 mean vertices reached / n
 //
 // MLP: parameters packed as BF16 [W1 16x64 | b1 64 | W2 64x64 | b2 64 |
 // W3 64xK | b3 K] (row-major, input index first).  Inputs and hidden
@@ -242,13 +242,14 @@ constexpr int kProbeLevels = 4;
 constexpr int kProbeEdges = 1024;
 constexpr int kProbeSlots = 2048;     // LDS hash of discovered vertices: load <= 1/2
 constexpr int kProbeCap = kProbeEdges + 1;   // frontier capacity (a level discovers <= kProbeEdges)
+constexpr int kProbes = 16;           // independent probes from seeded sources, one block each
 constexpr int kPart = 12;             // doubles per block of partial sums
 constexpr uint64_t kTagFeat = 0x66656174ULL;  // "feat"
 
-// Selector area of the workspace: probe result and output; the per-block
+// Selector area of the workspace: probe results and output; the per-block
 // partials (at most n/1024 + 1 blocks of 96 bytes) use the n-int count area.
-constexpr size_t kSelProbe = 0;
-constexpr size_t kSelOut = kSelProbe + 64;     // 16 floats + chosen (int32)
+constexpr size_t kSelProbe = 0;                // kProbes x [levels, reached]
+constexpr size_t kSelOut = kSelProbe + kProbes * 16;   // 16 floats + chosen (int32)
 
 // Dynamic roles share one LDS buffer.
 constexpr size_t kProbeSmem = 2 * (size_t)kProbeCap * 8 + (size_t)kProbeSlots * 4 + 4 * (size_t)kProbeCap * 4 +
@@ -464,9 +465,14 @@ __device__ void feat_finish(int64_t n, int64_t m, const double* part, int nb, co
   if (t == 0) {
     double r[kPart];
     for (int k = 0; k < kPart; ++k) r[k] = red[k * kFeatThreads];
-    const long long levels = __hip_atomic_load((const long long*)probe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const long long reached =
-        __hip_atomic_load((const long long*)probe + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double levels = 0, reached = 0;
+    for (int p = 0; p < kProbes; ++p) {
+      levels += (double)__hip_atomic_load((const long long*)probe + 2 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      reached +=
+          (double)__hip_atomic_load((const long long*)probe + 2 * p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    levels /= kProbes;
+    reached /= kProbes;
     const double dn = (double)n, dm = (double)m;
     const double mean = r[0] / dn;
     const double var = r[1] / dn - mean * mean > 0 ? r[1] / dn - mean * mean : 0.0;
@@ -486,7 +492,7 @@ __device__ void feat_finish(int64_t n, int64_t m, const double* part, int nb, co
     feat[10] = (float)(cnt > 0 ? r[9] / cnt : 0.0);
     feat[11] = (float)(cnt > 0 ? r[10] / cnt : 0.0);
     feat[12] = (float)levels;
-    feat[13] = (float)((double)reached / dn);
+    feat[13] = (float)(reached / dn);
     feat[14] = (float)(dm / dn < 3.0 ? 1.0 : 0.0);
     feat[15] = (float)log2(r[3] + 1.0);
     for (int i = 0; i < kIn; ++i) out[i] = feat[i];
@@ -511,19 +517,24 @@ __device__ void feat_finish(int64_t n, int64_t m, const double* part, int nb, co
 template <typename I>
 __global__ void __launch_bounds__(kFeatThreads) k_features(int64_t n, int64_t m, const I* __restrict__ off,
                                                            const int32_t* __restrict__ adj, uint64_t key,
-                                                           int32_t src, double* part,
+                                                           double* part,
                                                            int64_t* probe, int nb, uint32_t* ticket,
                                                            const uint16_t* __restrict__ params, int K, NormArg norm,
                                                            float* __restrict__ out) {
   __shared__ __align__(16) unsigned char smem[kFeatSmem];
   __shared__ int last;
-  if (blockIdx.x < (unsigned)nb) feat_pass<I>(n, off, adj, key, nb, part, (double*)smem);
-  else feat_probe<I>(off, adj, src, probe, smem);
+  if (blockIdx.x < (unsigned)nb) {
+    feat_pass<I>(n, off, adj, key, nb, part, (double*)smem);
+  } else {
+    const int p = (int)blockIdx.x - nb;
+    const int32_t src = (int32_t)(sm_out(key, (uint64_t)(kFeatSamples + p)) % (uint64_t)n);
+    feat_probe<I>(off, adj, src, probe + 2 * p, smem);
+  }
   // publish this block's results, then take a ticket; the last block finishes
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0)
-    last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)nb;
+    last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)(nb + kProbes - 1);
   __syncthreads();
   if (!last) return;
   __threadfence();
@@ -541,11 +552,10 @@ static cc_status features_impl(StaticArgs& a, const uint16_t* params, int K, con
   float* out = (float*)(sel + kSelOut);
   const uint64_t key = sm_out(a.v->seed, kTagFeat);
   const int nb = (int)grid_for(div_up(a.n, 4), kFeatThreads, kFeatBlocks);
-  const int32_t src = (int32_t)(sm_out(key, (uint64_t)kFeatSamples) % (uint64_t)a.n);
   NormArg na;
   for (int i = 0; i < 2 * kIn; ++i) na.v[i] = params ? norm_host[i] : 0.f;
-  hipLaunchKernelGGL(k_features<I>, dim3(nb + 1), dim3(kFeatThreads), 0, a.s, a.n, a.m, (const I*)a.off, a.adj, key,
-                     src, part, probe, nb, &a.ctx->dev->pad[1], params, K, na, out);
+  hipLaunchKernelGGL(k_features<I>, dim3(nb + kProbes), dim3(kFeatThreads), 0, a.s, a.n, a.m, (const I*)a.off, a.adj,
+                     key, part, probe, nb, &a.ctx->dev->pad[1], params, K, na, out);
   CC_LAUNCH_CHECK();
   float* h = a.ctx->sel_host;
   CC_HIP(hipMemcpyAsync(h, out, (kIn + 1) * sizeof(float), hipMemcpyDeviceToHost, a.s));
