@@ -586,6 +586,7 @@ class Selector:
         self._arr = (cc_variant * max(self.K, 1))(*self.arms[:self.K]) if self.K else None
         self._norm = (ctypes.c_float * 32)(*[float(x) for x in norm]) if norm is not None else None
         self._need = {}
+        self._args = {}
         self._feat = (ctypes.c_float * 16)()
         self._chosen = ctypes.c_int32(-2)
 
@@ -599,12 +600,21 @@ class Selector:
         return self.ctx.workspace(self._need[key])
 
     def connectivity(self, g: CSR, labels: torch.Tensor, ncomp: torch.Tensor, stream=None):
-        """cc_connectivity_auto: returns the chosen arm index (-1 = default)."""
-        ws = self._ws(g)
-        _check(lib().cc_connectivity_auto(self.ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj),
-                                          _ptr(self.params), self.K, self._arr, self._norm, _ptr(ws), ws.numel(),
-                                          _ptr(labels), _ptr(ncomp), ctypes.byref(self._chosen), self._feat,
-                                          _stream_handle(stream)), "cc_connectivity_auto")
+        """cc_connectivity_auto: returns the chosen arm index (-1 = default).
+        The marshalled arguments are cached per (graph, outputs, stream), so
+        a repeated call costs one C call."""
+        hs = _stream_handle(stream)
+        key = (id(g), g.offsets.data_ptr(), g.adj.data_ptr(), labels.data_ptr(), ncomp.data_ptr(), hs.value)
+        args = self._args.get(key)
+        if args is None:
+            ws = self._ws(g)
+            if labels.numel() < g.n or ncomp.numel() < 1:
+                raise ValueError("labels needs n entries and ncomp one")
+            args = (self.ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(self.params), self.K, self._arr,
+                    self._norm, _ptr(ws), ws.numel(), _ptr(labels), _ptr(ncomp), ctypes.byref(self._chosen),
+                    self._feat, hs, (g, labels, ncomp, ws))
+            self._args = {key: args}    # keep one entry: the tensors it references stay alive
+        _check(lib().cc_connectivity_auto(*args[:-1]), "cc_connectivity_auto")
         return self._chosen.value
 
     def features(self):

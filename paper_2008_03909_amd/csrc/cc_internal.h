@@ -31,7 +31,7 @@ struct DevScalars {
   unsigned long long heavy_count;  // vertices with degree above the frontier threshold
   uint32_t flag2;          // spare flag for sub-rounds (full shortcut)
   int32_t hcount;          // heavy frontier vertices deferred to the grid kernel
-  uint32_t pad[14];        // pad[0]: LDD minimum draw; pad[1]: selector block ticket
+  uint32_t pad[14];        // pad[0]: LDD minimum draw
 };
 
 enum : uint32_t { kErrBadId = 1u, kErrRoundCap = 2u, kErrBadCsr = 4u };
@@ -47,7 +47,9 @@ struct cc_ctx {
   int device = 0;
   cc::DevScalars* dev = nullptr;     // device copy
   cc::DevScalars* host = nullptr;    // pinned host mirror
-  float* sel_host = nullptr;         // pinned: selector features + choice
+  float* sel_host = nullptr;         // pinned, coherent: selector features + choice
+  float* sel_dev = nullptr;          // the same memory as the device addresses it
+  uint32_t sel_seq = 0;              // sequence number of the last selector call
   unsigned char* ring_host = nullptr;  // pinned: BFS progress snapshots (2 x 16 bytes)
   cc_stats last{};
   int round_limit = 0;  // 0: the built-in caps only

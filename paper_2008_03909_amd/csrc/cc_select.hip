@@ -27,6 +27,7 @@
 // outputs are FP32 predicted log-time ratios; ReLU between layers.  The
 // backward pass treats the BF16 rounding as identity (straight-through) and
 // the ReLU derivative at 0 as 0.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -229,13 +230,14 @@ __global__ void k_f32_to_bf16(const float* __restrict__ src, uint16_t* __restric
 
 // ---- feature kernels ----------------------------------------------------------
 //
-// One launch computes everything: blocks [0, nb) sweep the degrees and the
-// vertex draws into per-block partials, block nb runs the budgeted BFS, and
-// the last block to finish (a ticket counter) reduces the partials, forms
-// the 16 features, normalises them, runs the forward pass and picks the
-// arm.  The host then copies 17 words to pinned memory and synchronises once.
+// Two launches compute everything: in the first, blocks [0, nb) sweep the
+// degrees and the vertex draws into per-block partials and blocks nb ..
+// nb + kProbes - 1 run one budgeted BFS each; the second (one block)
+// reduces the partials, forms the 16 features, normalises them, runs the
+// forward pass, picks the arm and writes the 17 words straight into the
+// context's pinned host buffer; the host synchronises once.
 
-constexpr int kFeatBlocks = 2048;
+constexpr int kFeatBlocks = 1024;      // pass blocks: the last block reads their partials four per thread
 constexpr int kFeatThreads = 256;
 constexpr int kFeatSamples = 4096;
 constexpr int kProbeLevels = 4;
@@ -246,16 +248,15 @@ constexpr int kProbes = 16;           // independent probes from seeded sources,
 constexpr int kPart = 12;             // doubles per block of partial sums
 constexpr uint64_t kTagFeat = 0x66656174ULL;  // "feat"
 
-// Selector area of the workspace: probe results and output; the per-block
+// Selector area of the workspace: probe results; the per-block
 // partials (at most n/1024 + 1 blocks of 96 bytes) use the n-int count area.
 constexpr size_t kSelProbe = 0;                // kProbes x [levels, reached]
-constexpr size_t kSelOut = kSelProbe + kProbes * 16;   // 16 floats + chosen (int32)
 
 // Dynamic roles share one LDS buffer.
 constexpr size_t kProbeSmem = 2 * (size_t)kProbeCap * 8 + (size_t)kProbeSlots * 4 + 4 * (size_t)kProbeCap * 4 +
                                (size_t)(kProbeCap + 1) * 4 + 64;
 constexpr size_t kFinishSmem = (size_t)kPart * kFeatThreads * 8 + (3 * kIn + 2 * kH + kMaxArms) * 4 + 16;
-constexpr size_t kFeatSmem = kProbeSmem > kFinishSmem ? kProbeSmem : kFinishSmem;
+constexpr size_t kFeatSmem = kProbeSmem;
 
 struct NormArg {
   float v[2 * kIn];   // mean[16], sd[16]
@@ -429,15 +430,7 @@ __device__ void feat_probe(const I* __restrict__ off, const int32_t* __restrict_
   }
 }
 
-__device__ __forceinline__ double load_f64_agent(const double* p) {
-  const unsigned long long u =
-      __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  double d;
-  memcpy(&d, &u, 8);
-  return d;
-}
-
-// Reduces the partials into the 16 features (out[0..15]); with a model,
+// Reduces the partials into the 16 features (out[0..15]).  With a model,
 // normalises them, runs the forward pass and writes the argmin arm (smallest
 // index on ties) to out[16] as an int32, else -1.
 __device__ void feat_finish(int64_t n, int64_t m, const double* part, int nb, const int64_t* probe,
@@ -452,8 +445,20 @@ __device__ void feat_finish(int64_t n, int64_t m, const double* part, int nb, co
   float* Y = a2 + kH;
   const int t = threadIdx.x;
   double q[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int b = t; b < nb; b += kFeatThreads)
-    for (int k = 0; k < kPart; ++k) q[k] = combine(k, q[k], load_f64_agent(part + (int64_t)b * kPart + k));
+  static_assert(kFeatBlocks <= 4 * kFeatThreads, "four partial rows per thread");
+  {
+    double x[4][kPart];   // every load in flight before any is used
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int b = t + j * kFeatThreads;
+#pragma unroll
+      for (int k = 0; k < kPart; ++k) x[j][k] = b < nb ? part[(int64_t)b * kPart + k] : 0.0;   // 0 is neutral for sums and maxima of counts
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < kPart; ++k) q[k] = combine(k, q[k], x[j][k]);
+  }
   for (int k = 0; k < kPart; ++k) red[k * kFeatThreads + t] = q[k];
   __syncthreads();
   for (int h = kFeatThreads / 2; h > 0; h >>= 1) {
@@ -467,9 +472,8 @@ __device__ void feat_finish(int64_t n, int64_t m, const double* part, int nb, co
     for (int k = 0; k < kPart; ++k) r[k] = red[k * kFeatThreads];
     double levels = 0, reached = 0;
     for (int p = 0; p < kProbes; ++p) {
-      levels += (double)__hip_atomic_load((const long long*)probe + 2 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      reached +=
-          (double)__hip_atomic_load((const long long*)probe + 2 * p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      levels += (double)probe[2 * p];
+      reached += (double)probe[2 * p + 1];
     }
     levels /= kProbes;
     reached /= kProbes;
@@ -515,14 +519,10 @@ __device__ void feat_finish(int64_t n, int64_t m, const double* part, int nb, co
 }
 
 template <typename I>
-__global__ void __launch_bounds__(kFeatThreads) k_features(int64_t n, int64_t m, const I* __restrict__ off,
+__global__ void __launch_bounds__(kFeatThreads) k_features(int64_t n, const I* __restrict__ off,
                                                            const int32_t* __restrict__ adj, uint64_t key,
-                                                           double* part,
-                                                           int64_t* probe, int nb, uint32_t* ticket,
-                                                           const uint16_t* __restrict__ params, int K, NormArg norm,
-                                                           float* __restrict__ out) {
+                                                           double* part, int64_t* probe, int nb) {
   __shared__ __align__(16) unsigned char smem[kFeatSmem];
-  __shared__ int last;
   if (blockIdx.x < (unsigned)nb) {
     feat_pass<I>(n, off, adj, key, nb, part, (double*)smem);
   } else {
@@ -530,16 +530,33 @@ __global__ void __launch_bounds__(kFeatThreads) k_features(int64_t n, int64_t m,
     const int32_t src = (int32_t)(sm_out(key, (uint64_t)(kFeatSamples + p)) % (uint64_t)n);
     feat_probe<I>(off, adj, src, probe + 2 * p, smem);
   }
-  // publish this block's results, then take a ticket; the last block finishes
-  __threadfence();
+}
+
+// One block: the model's parameters are first staged in LDS (coalesced), so
+// the forward pass reads no global memory.
+constexpr int kMaxParams = kIn * kH + kH + kH * kH + kH + kH * kMaxArms + kMaxArms;
+
+__global__ void __launch_bounds__(kFeatThreads) k_feat_final(int64_t n, int64_t m, const double* part, int nb,
+                                                             const int64_t* probe, const uint16_t* __restrict__ params,
+                                                             int K, NormArg norm, float* __restrict__ out,
+                                                             uint32_t seq) {
+  __shared__ __align__(16) unsigned char smem[kFinishSmem];
+  __shared__ __align__(16) uint16_t lparams[kMaxParams];
+  const uint16_t* pp = nullptr;
+  if (params) {
+    const int64_t cnt = mlp_param_count(K);
+    for (int64_t i = threadIdx.x; i < cnt; i += kFeatThreads) lparams[i] = params[i];
+    pp = lparams;
+  }
   __syncthreads();
-  if (threadIdx.x == 0)
-    last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)(nb + kProbes - 1);
+  feat_finish(n, m, part, nb, probe, pp, K, norm, out, smem);
+  // publish: the 17 result words, then (system scope) the call's sequence
+  // number, which the host polls
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  feat_finish(n, m, part, nb, probe, params, K, norm, out, smem);
-  if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    __hip_atomic_store((uint32_t*)out + kIn + 1, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // Features and, with a model, the chosen arm; one host synchronisation.
@@ -549,17 +566,31 @@ static cc_status features_impl(StaticArgs& a, const uint16_t* params, int K, con
   char* sel = a.ws + a.L.mlp;
   double* part = (double*)(a.ws + a.L.count);
   int64_t* probe = (int64_t*)(sel + kSelProbe);
-  float* out = (float*)(sel + kSelOut);
   const uint64_t key = sm_out(a.v->seed, kTagFeat);
   const int nb = (int)grid_for(div_up(a.n, 4), kFeatThreads, kFeatBlocks);
   NormArg na;
   for (int i = 0; i < 2 * kIn; ++i) na.v[i] = params ? norm_host[i] : 0.f;
-  hipLaunchKernelGGL(k_features<I>, dim3(nb + kProbes), dim3(kFeatThreads), 0, a.s, a.n, a.m, (const I*)a.off, a.adj,
-                     key, part, probe, nb, &a.ctx->dev->pad[1], params, K, na, out);
+  hipLaunchKernelGGL(k_features<I>, dim3(nb + kProbes), dim3(kFeatThreads), 0, a.s, a.n, (const I*)a.off, a.adj, key,
+                     part, probe, nb);
+  const uint32_t seq = ++a.ctx->sel_seq;
+  hipLaunchKernelGGL(k_feat_final, dim3(1), dim3(kFeatThreads), 0, a.s, a.n, a.m, (const double*)part, nb,
+                     (const int64_t*)probe, params, K, na, a.ctx->sel_dev, seq);
   CC_LAUNCH_CHECK();
+  // The final kernel writes straight into pinned host memory and then the
+  // sequence number: poll for it (it arrives microseconds before a stream
+  // synchronisation would return); after 50 ms fall back to synchronising,
+  // which also reports a failed launch.
   float* h = a.ctx->sel_host;
-  CC_HIP(hipMemcpyAsync(h, out, (kIn + 1) * sizeof(float), hipMemcpyDeviceToHost, a.s));
-  CC_HIP(hipStreamSynchronize(a.s));
+  volatile uint32_t* flag = (volatile uint32_t*)h + kIn + 1;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 0; __atomic_load_n(flag, __ATOMIC_ACQUIRE) != seq; ++spin) {
+    if ((spin & 1023u) == 0 &&
+        std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
+      CC_HIP(hipStreamSynchronize(a.s));
+      if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) != seq) return fail(CC_EDEVICE, "selector kernel did not report");
+      break;
+    }
+  }
   memcpy(feat, h, kIn * sizeof(float));
   int32_t c;
   memcpy(&c, &h[kIn], sizeof(c));

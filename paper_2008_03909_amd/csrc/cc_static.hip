@@ -893,7 +893,8 @@ cc_status cc_ctx_create(int device, cc_ctx** out) {
   c->device = device;
   if (hipMalloc((void**)&c->dev, sizeof(DevScalars)) != hipSuccess ||
       hipHostMalloc((void**)&c->host, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->sel_host, 256, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->sel_host, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->sel_dev, c->sel_host, 0) != hipSuccess ||
       hipHostMalloc((void**)&c->ring_host, 256, hipHostMallocDefault) != hipSuccess) {
     if (c->dev) hipFree(c->dev);
     if (c->host) hipHostFree(c->host);
