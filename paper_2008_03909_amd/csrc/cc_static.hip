@@ -320,12 +320,23 @@ __global__ void __launch_bounds__(kBlock) k_compress_count(int64_t n, const I* _
       if (count) load_off5(off, v0, vec, n, o);
     }
     int32_t r[4];
+    bool moved = false;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       r[j] = p[j];
       if (act && v0 + j < n && p[j] != (int32_t)(v0 + j)) {
         r[j] = find_naive(P, p[j]);
-        if (r[j] != p[j]) st(P + v0 + j, r[j]);
+        moved |= r[j] != p[j];
+      }
+    }
+    // one 16-byte store for the lane's four slots (whole lines when most
+    // lanes change, as after k-out on meshes); each slot is owned by this lane
+    if (moved) {
+      if (vec) {
+        *(int4*)(P + v0) = make_int4(r[0], r[1], r[2], r[3]);
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (act && v0 + j < n && r[j] != p[j]) st(P + v0 + j, r[j]);
       }
     }
     if (!count) continue;
@@ -634,7 +645,7 @@ struct UnionOp {
 
 // Final compression and component count: label = root (the component's
 // minimum, since every link points to a smaller id).
-__global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, DevScalars* sc, long long* ncomp_user,
+__global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, long long* __restrict__ part,
                                                    int aligned) {
   __shared__ long long red[kBlock / kWave];
   long long roots = 0;
@@ -642,18 +653,29 @@ __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, DevSca
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups; g += stride) {
     const int64_t v0 = 4 * g;
-    int32_t p[4];
-    load4(P, v0, aligned && v0 + 3 < n, n, p);
+    const bool vec = aligned && v0 + 3 < n;
+    int32_t p[4], r[4];
+    load4(P, v0, vec, n, p);
+    bool moved = false;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t v = v0 + j;
+      r[j] = p[j];
       if (v >= n) continue;
       if (p[j] == (int32_t)v) {
         ++roots;
         continue;
       }
-      const int32_t r = find_naive(P, p[j]);
-      if (r != p[j]) st(P + v, r);
+      r[j] = find_naive(P, p[j]);
+      moved |= r[j] != p[j];
+    }
+    if (moved) {
+      if (vec) {
+        *(int4*)(P + v0) = make_int4(r[0], r[1], r[2], r[3]);
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (v0 + j < n && r[j] != p[j]) st(P + v0 + j, r[j]);
+      }
     }
   }
   roots = wave_sum(roots);
@@ -661,10 +683,23 @@ __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, DevSca
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kBlock / kWave; ++w) roots += red[w];
-    if (roots) {
-      add64(&sc->num_components, roots);
-      if (ncomp_user) add64(ncomp_user, roots);
-    }
+    part[blockIdx.x] = roots;
+  }
+}
+
+// Component count from the per-block root counts (one block).
+__global__ void __launch_bounds__(kBlock) k_output_sum(const long long* __restrict__ part, int nparts,
+                                                       DevScalars* sc, long long* ncomp_user) {
+  __shared__ long long red[kBlock / kWave];
+  long long s = 0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) s += part[i];
+  s = wave_sum(s);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) s += red[w];
+    sc->num_components = s;
+    if (ncomp_user) *ncomp_user = s;
   }
 }
 
@@ -823,8 +858,12 @@ static cc_status run_tail(StaticArgs& a) {
   if (st != CC_OK) return st;
   {
     PhaseScope ps(a.ctx, a.s, "output");
-    hipLaunchKernelGGL(k_output, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P, a.ctx->dev,
-                       (long long*)a.ncomp_user, vec_ok(a));
+    // per-block root counts in the compaction area (free once the finish ran)
+    long long* part = (long long*)(a.ws + a.L.seg);
+    const unsigned nb = grid4(a.n);
+    hipLaunchKernelGGL(k_output, dim3(nb), dim3(kBlock), 0, a.s, a.n, a.P, part, vec_ok(a));
+    hipLaunchKernelGGL(k_output_sum, dim3(1), dim3(kBlock), 0, a.s, (const long long*)part, (int)nb, a.ctx->dev,
+                       (long long*)a.ncomp_user);
     CC_LAUNCH_CHECK();
   }
   return CC_OK;
