@@ -756,10 +756,14 @@ __global__ void k_ldd_hist(int64_t n, uint64_t key, float beta, const DevScalars
 
 // Vertices [lo, hi) wake: the unvisited ones become cluster centres.  Lanes
 // map to consecutive vertices from a 32-aligned start, so each half-wave
-// owns one bitmap word and writes it without atomics.  Block 0 also resets
-// the counters of the round's output queue (queue `nxt`) and the heavy list.
-__global__ void __launch_bounds__(kFBlock) k_ldd_wake(int64_t lo, int64_t hi, uint32_t* vis, int32_t* P, int32_t* q,
-                                                      uint32_t* cnt, DevScalars* sc, int nxt) {
+// owns one bitmap word and writes it without atomics.  Only centres with an
+// edge join the frontier (an isolated centre has nothing to expand).  Block
+// 0 also resets the counters of the round's output queue (queue `nxt`) and
+// the heavy list.
+template <typename I>
+__global__ void __launch_bounds__(kFBlock) k_ldd_wake(int64_t lo, int64_t hi, const I* __restrict__ off,
+                                                      uint32_t* vis, int32_t* P, int32_t* q, uint32_t* cnt,
+                                                      DevScalars* sc, int nxt) {
   __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
   WaveQ wq{qbuf[threadIdx.x / kWave], 0};
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -778,7 +782,8 @@ __global__ void __launch_bounds__(kFBlock) k_ldd_wake(int64_t lo, int64_t hi, ui
       const uint32_t wbits = (uint32_t)(bits >> (lane & 32));
       if (wbits) vis[v >> 5] |= wbits;
     }
-    wq_push(wq, got, (int32_t)v, q, cnt);
+    const bool push = got && (int64_t)off[v + 1] > (int64_t)off[v];
+    wq_push(wq, push, (int32_t)v, q, cnt);
   }
   wq_flush(wq, q, cnt);
 }
@@ -845,8 +850,8 @@ cc_status sample_ldd(StaticArgs& a) {
     S += h[r];
     const int64_t hi = (r == last) ? n : S;
     const int nxt = cur ^ 1;
-    hipLaunchKernelGGL(k_ldd_wake, dim3(grid_for(hi > lo ? hi - (lo & ~(int64_t)31) : 1, kFBlock, 4096)),
-                       dim3(kFBlock), 0, a.s, lo, hi, vis, a.P, q[cur], &sc->qcount[cur], sc, nxt);
+    hipLaunchKernelGGL(k_ldd_wake<I>, dim3(grid_for(hi > lo ? hi - (lo & ~(int64_t)31) : 1, kFBlock, 4096)),
+                       dim3(kFBlock), 0, a.s, lo, hi, off, vis, a.P, q[cur], &sc->qcount[cur], sc, nxt);
     lo = hi > lo ? hi : lo;
     hipLaunchKernelGGL((k_expand<true, I>), dim3(grid_for(n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, q[cur],
                        &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, (uint32_t*)nullptr, a.P,
