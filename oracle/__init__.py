@@ -69,6 +69,8 @@ def _load():
         lib.oracle_bfs_levels.restype = i64
         lib.oracle_bfs_budget.argtypes = [i64, _i64p, _i32p, ctypes.c_int32, ctypes.c_int32, i64, _i32p]
         lib.oracle_bfs_budget.restype = i64
+        lib.oracle_forest_check.argtypes = [i64, _i64p, _i32p, _i32p, i64, _i32p, _i32p]
+        lib.oracle_forest_check.restype = i64
         _lib = lib
     return _lib
 
@@ -164,6 +166,24 @@ class Incremental:
         lab = np.empty(self.n, np.int32)
         c = _load().oracle_uf_labels(self.n, _p32(self.P), _p32(lab))
         return lab, int(c)
+
+
+# ---- spanning forest (Section 2; appendix "ConnectIt: Spanning Forest") -----
+
+FOREST_OK, FOREST_BAD_ID, FOREST_NOT_AN_EDGE, FOREST_CYCLE, FOREST_WRONG_SPAN = 0, 1, 2, 3, 4
+
+
+def forest_check(g, fu, fv) -> int:
+    """0 iff the edges (fu[i], fv[i]) form a spanning forest of the graph
+    ``g`` (an ``inputs.Graph``): every edge is an edge of g, none closes a
+    cycle, and they connect exactly what g connects.  A spanning forest is
+    not unique, so this checks the definition instead of comparing edges."""
+    off, adj = csr_build(g.n, g.u, g.v, dedup=True)
+    lab, _ = uf_cc(g.n, g.u, g.v)
+    fu, fv = _c(fu, np.int32), _c(fv, np.int32)
+    z = np.zeros(1, np.int32)
+    return int(_load().oracle_forest_check(g.n, _p64(off), _p32(adj) if adj.size else _p32(z), _p32(lab), fu.shape[0],
+                                           _p32(fu) if fu.size else _p32(z), _p32(fv) if fv.size else _p32(z)))
 
 
 # ---- samplers with a deterministic partition -------------------------------

@@ -320,3 +320,55 @@ int64_t oracle_bfs_budget(int64_t n, const int64_t* offsets, const int32_t* adj,
   *levels_out = levels;
   return reached;
 }
+
+/* ---- spanning forest check (Section 2's definition of a spanning forest) --
+ * A set F of k edges is a spanning forest of G iff every edge of F is an
+ * edge of G, no edge of F closes a cycle (a sequential union-find over F
+ * links two different trees at every edge), and F connects exactly what G
+ * connects (the labels of the union-find over F equal label_g, G's
+ * canonical labels).  Membership is a binary search in the row of u of the
+ * CSR (rows sorted ascending).  Returns 0 if F is a spanning forest, else a
+ * code naming the first failed condition: 1 an id out of range, 2 an edge
+ * not in G, 3 a cycle, 4 different connectivity. */
+int64_t oracle_forest_check(int64_t n, const int64_t* offsets, const int32_t* adj, const int32_t* label_g, int64_t k,
+                            const int32_t* fu, const int32_t* fv) {
+  int64_t code = 0;
+  int32_t* P = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t* lab = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  oracle_uf_init(n, P);
+  for (int64_t i = 0; i < k && !code; ++i) {
+    const int32_t a = fu[i], b = fv[i];
+    if (a < 0 || b < 0 || a >= n || b >= n) {
+      code = 1;
+      break;
+    }
+    int64_t lo = offsets[a], hi = offsets[a + 1];
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (adj[mid] < b) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo >= offsets[a + 1] || adj[lo] != b) {
+      code = 2;
+      break;
+    }
+    const int32_t ra = uf_find(P, a), rb = uf_find(P, b);
+    if (ra == rb) {
+      code = 3;
+      break;
+    }
+    if (ra < rb) P[rb] = ra;
+    else P[ra] = rb;
+  }
+  if (!code) {
+    oracle_uf_labels(n, P, lab);
+    for (int64_t x = 0; x < n; ++x)
+      if (lab[x] != label_g[x]) {
+        code = 4;
+        break;
+      }
+  }
+  free(P);
+  free(lab);
+  return code;
+}

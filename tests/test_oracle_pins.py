@@ -381,3 +381,56 @@ def test_sampled_features_closed_forms():
     off, adj = oracle.csr_build(e.n, e.u, e.v)
     f = oracle.sampled_features(100, off, adj, 1)
     assert (f[9], f[10], f[11], f[12], f[13]) == (0.0, 0.0, 0.0, 1.0, 0.01)
+
+
+# ---- spanning forest checker: planted mistakes must be caught --------------------
+
+def test_forest_check_accepts_trees_and_rejects_planted_mistakes():
+    g = inputs.disjoint_union([inputs.path(6), inputs.clique(4), inputs.empty(3)])   # 13 vertices, 5 components
+    # a valid forest: the path's 5 edges and a star inside the clique
+    fu = np.array([0, 1, 2, 3, 4, 6, 6, 6], np.int32)
+    fv = np.array([1, 2, 3, 4, 5, 7, 8, 9], np.int32)
+    assert oracle.forest_check(g, fu, fv) == oracle.FOREST_OK
+    assert oracle.forest_check(g, fv, fu) == oracle.FOREST_OK            # orientation does not matter
+    # dropping an edge leaves the path split
+    assert oracle.forest_check(g, fu[1:], fv[1:]) == oracle.FOREST_WRONG_SPAN
+    # an extra clique edge closes a cycle
+    assert oracle.forest_check(g, np.append(fu, 7), np.append(fv, 8)) == oracle.FOREST_CYCLE
+    # a pair that is not an edge (0 and 2 are not adjacent on the path)
+    bad_u = fu.copy(); bad_u[1] = 0
+    assert oracle.forest_check(g, bad_u, fv) == oracle.FOREST_NOT_AN_EDGE
+    # an id outside [0, n)
+    assert oracle.forest_check(g, np.append(fu, 13), np.append(fv, 0)) == oracle.FOREST_BAD_ID
+    # the empty graph's forest is empty
+    e = inputs.empty(5)
+    assert oracle.forest_check(e, np.zeros(0, np.int32), np.zeros(0, np.int32)) == oracle.FOREST_OK
+
+
+def test_forest_check_on_random_graphs_against_bfs_trees():
+    """BFS parent edges (computed here in plain Python) form a spanning forest;
+    swapping one tree edge for a non-tree edge of the same component keeps it
+    one, while duplicating a tree edge does not."""
+    import collections
+    for seed in range(4):
+        g = inputs.er(300, 350 + 50 * seed, seed=seed)
+        off, adj = oracle.csr_build(g.n, g.u, g.v)
+        seen = np.zeros(g.n, bool)
+        fu, fv = [], []
+        for s in range(g.n):
+            if seen[s]:
+                continue
+            seen[s] = True
+            dq = collections.deque([s])
+            while dq:
+                x = dq.popleft()
+                for y in adj[off[x]:off[x + 1]]:
+                    if not seen[y]:
+                        seen[y] = True
+                        fu.append(x)
+                        fv.append(int(y))
+                        dq.append(y)
+        fu, fv = np.array(fu, np.int32), np.array(fv, np.int32)
+        _, c = oracle.labels(g)
+        assert fu.size == g.n - c
+        assert oracle.forest_check(g, fu, fv) == oracle.FOREST_OK
+        assert oracle.forest_check(g, np.append(fu, fu[0]), np.append(fv, fv[0])) == oracle.FOREST_CYCLE
