@@ -395,6 +395,7 @@ def main():
     ap.add_argument("--variant", default="default", help="'default' or an index into the 80-variant list")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-incremental", action="store_true")
+    ap.add_argument("--no-forest", action="store_true", help="skip the spanning-forest timing")
     ap.add_argument("--phases", action="store_true", help="print per-phase times to stderr")
     ap.add_argument("--sweep", default="", help="also time all 80 variants; write the rows to this JSON file")
     args = ap.parse_args()
@@ -506,6 +507,19 @@ def main():
         "ingest": {"ms": ingest_ms, "pairs": g.num_pairs, "pairs_per_s": g.num_pairs / (ingest_ms / 1e3)},
     }
     del ws
+    if not args.no_forest:
+        # spanning forest with the default variant on the same CSR (outside the timed region above)
+        for _ in range(2):
+            b.spanning_forest_csr(ctx, csr, v)
+        torch.cuda.synchronize()
+        t0f = time.perf_counter()
+        for _ in range(args.steps):
+            _, _, _, ne = b.spanning_forest_csr(ctx, csr, v)
+        torch.cuda.synchronize()
+        ms_f = (time.perf_counter() - t0f) * 1e3 / args.steps
+        out["spanning_forest"] = {"ms": ms_f, "edges_per_s": m / (ms_f / 1e3),
+                                  "forest_edges": int(ne.item()), "vs_connectivity": ms_f / ms_step}
+        log(f"spanning forest: {ms_f:.3f} ms ({ms_f / ms_step:.2f}x connectivity), {int(ne.item())} edges")
     if args.sweep:
         log("variant sweep ...")
         rows = sweep(ctx, csr, g, args.workload)

@@ -188,6 +188,25 @@ cc_status cc_connectivity_coo(cc_ctx* ctx, int64_t n, int64_t num_pairs, const i
                               const cc_variant* var, void* workspace, size_t ws_bytes, int32_t* labels_out,
                               int64_t* num_components_dev, void* hip_stream);
 
+/* ---- spanning forest (appendix "ConnectIt: Spanning Forest") --------------------
+ * One tree per connected component: edges_u[i], edges_v[i] for
+ * i < *num_edges_dev (= n - number of components) are adjacency entries
+ * (u, v) of the CSR that together span every component without a cycle.
+ * labels_out receives the labels exactly as cc_connectivity_csr would.
+ * Every sampler is accepted; BFS and LDD contribute their tree edges, k-out
+ * the edges that hooked a union-find root.  The finish must be root-based
+ * with CAS hooks: UF-Async (any find) or UF-Rem-CAS with SplitAtomicOne or
+ * HalveAtomicOne; SpliceAtomic (which moves non-roots between trees), SV and
+ * LT return CC_EUNSUPPORTED.  Which spanning forest comes out depends on the
+ * order of concurrent hooks; every one is valid.  edges_u / edges_v: device
+ * int32 arrays of at least n entries; num_edges_dev: one device int64.
+ * workspace: device buffer of >= cc_forest_workspace_bytes. */
+cc_status cc_forest_workspace_bytes(int64_t n, int64_t m, const cc_variant* v, size_t* bytes);
+cc_status cc_spanning_forest_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                                 const int32_t* adj, const cc_variant* v, void* workspace, size_t ws_bytes,
+                                 int32_t* labels_out, int32_t* edges_u, int32_t* edges_v, int64_t* num_edges_dev,
+                                 void* hip_stream);
+
 /* ---- ingest: undirected pair list -> symmetric CSR (Section 2 formats) -------
  * Output: both orientations of every pair with u != v, rows sorted
  * ascending, duplicates removed iff dedup != 0.  adj_out needs capacity

@@ -180,9 +180,17 @@ def forest_check(g, fu, fv) -> int:
     not unique, so this checks the definition instead of comparing edges."""
     off, adj = csr_build(g.n, g.u, g.v, dedup=True)
     lab, _ = uf_cc(g.n, g.u, g.v)
+    return forest_check_csr(g.n, off, adj, lab, fu, fv)
+
+
+def forest_check_csr(n: int, offsets, adj, labels_g, fu, fv) -> int:
+    """forest_check against a prepared CSR (rows sorted, deduplicated) and the
+    graph's canonical labels."""
+    off, adj = _c(offsets, np.int64), _c(adj, np.int32)
+    lab = _c(labels_g, np.int32)
     fu, fv = _c(fu, np.int32), _c(fv, np.int32)
     z = np.zeros(1, np.int32)
-    return int(_load().oracle_forest_check(g.n, _p64(off), _p32(adj) if adj.size else _p32(z), _p32(lab), fu.shape[0],
+    return int(_load().oracle_forest_check(n, _p64(off), _p32(adj) if adj.size else _p32(z), _p32(lab), fu.shape[0],
                                            _p32(fu) if fu.size else _p32(z), _p32(fv) if fv.size else _p32(z)))
 
 

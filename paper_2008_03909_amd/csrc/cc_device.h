@@ -111,18 +111,19 @@ __device__ __forceinline__ int32_t find(int32_t* P, int32_t u) {
 
 // ---- UF-Async (Jayanti-Tarjan style; appendix "UF-Async") ----------------
 // Find both roots; CAS the larger root onto the smaller; retry on failure.
+// Returns the root this call hooked, or -1 if u and v were already joined.
 template <int FIND>
-__device__ __forceinline__ void union_async(int32_t* P, int32_t u, int32_t v) {
+__device__ __forceinline__ int32_t union_async(int32_t* P, int32_t u, int32_t v) {
   while (true) {
     int32_t pu = find<FIND>(P, u);
     int32_t pv = find<FIND>(P, v);
-    if (pu == pv) return;
+    if (pu == pv) return -1;
     if (pu < pv) {
       int32_t t = pu;
       pu = pv;
       pv = t;
     }
-    if (ld(P + pu) == pu && cas(P + pu, pu, pv)) return;
+    if (ld(P + pu) == pu && cas(P + pu, pu, pv)) return pu;
   }
 }
 
@@ -131,14 +132,15 @@ __device__ __forceinline__ void union_async(int32_t* P, int32_t u, int32_t v) {
 // moves.  If it is a root, CAS-hook it under the other side's parent;
 // otherwise take one splice step (SplitAtomicOne, HalveAtomicOne or
 // SpliceAtomic).  After a successful hook the non-naive compress options
-// re-run their find on both endpoints.  Returns true if this call linked.
+// re-run their find on both endpoints.  Returns the root this call hooked
+// (the spanning-forest slot of edge (u, v)), or -1 if it linked nothing.
 template <int SPLICE, int FIND>
-__device__ __forceinline__ bool union_rem(int32_t* P, int32_t u, int32_t v) {
+__device__ __forceinline__ int32_t union_rem(int32_t* P, int32_t u, int32_t v) {
   int32_t ru = u, rv = v;
   while (true) {
     int32_t pu = ld(P + ru);
     int32_t pv = ld(P + rv);
-    if (pu == pv) return false;
+    if (pu == pv) return -1;
     if (pu < pv) {
       int32_t t = ru;
       ru = rv;
@@ -154,7 +156,7 @@ __device__ __forceinline__ bool union_rem(int32_t* P, int32_t u, int32_t v) {
           find<FIND>(P, u);
           find<FIND>(P, v);
         }
-        return true;
+        return ru;
       }
       continue;  // lost the race: re-read both parents
     }
@@ -172,10 +174,17 @@ __device__ __forceinline__ bool union_rem(int32_t* P, int32_t u, int32_t v) {
 }
 
 // Union dispatch.  ALG 0 = Rem-CAS (SPLICE, FIND), 1 = Async (FIND).
+// Returns the hooked root or -1.
 template <int ALG, int SPLICE, int FIND>
-__device__ __forceinline__ void unite(int32_t* P, int32_t u, int32_t v) {
-  if constexpr (ALG == 0) union_rem<SPLICE, FIND>(P, u, v);
-  else union_async<FIND>(P, u, v);
+__device__ __forceinline__ int32_t unite(int32_t* P, int32_t u, int32_t v) {
+  if constexpr (ALG == 0) return union_rem<SPLICE, FIND>(P, u, v);
+  else return union_async<FIND>(P, u, v);
+}
+
+// Spanning forest: the edge that hooked root r is stored at slot r (each
+// root is hooked at most once, so no slot is written twice).
+__device__ __forceinline__ void forest_record(int2* hook, int32_t r, int32_t u, int32_t v) {
+  if (hook && r >= 0) hook[r] = make_int2(u, v);
 }
 
 // ---- wave helpers -----------------------------------------------------------

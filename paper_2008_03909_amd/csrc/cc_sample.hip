@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_begin(int64_t words, uint32_t* 
 template <typename I>
 __device__ long long bfs_small_levels(const I* __restrict__ off, const int32_t* __restrict__ adj, uint32_t* vis,
                                       uint32_t* fn, const int32_t* qin0, uint32_t f0, int32_t* qout0,
-                                      uint32_t* cnt_out, DevScalars* sc) {
+                                      uint32_t* cnt_out, DevScalars* sc, int2* tree) {
   __shared__ int32_t spre[kSmallEdges + 2];
   __shared__ long long stsum[kFBlock];
   __shared__ long long stotal;
@@ -185,7 +185,10 @@ __device__ long long bfs_small_levels(const I* __restrict__ off, const int32_t* 
       }
       const int32_t x = qa[lo];
       const int32_t w = adj[(int64_t)off[x] + (e - spre[lo])];
-      if (bit_claim(vis, w)) qb[atomicAdd(&snn, 1)] = w;
+      if (bit_claim(vis, w)) {
+        qb[atomicAdd(&snn, 1)] = w;
+        if (tree) tree[w] = make_int2(x, w);
+      }
     }
     __syncthreads();
     f = snn;
@@ -225,11 +228,12 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
                                                       const int32_t* __restrict__ qin, const uint32_t* cnt_in,
                                                       int32_t* qout, uint32_t* cnt_out, int32_t* heavy,
                                                       int32_t* hcount, DevScalars* sc,
-                                                      long long* __restrict__ fpart) {
+                                                      long long* __restrict__ fpart, int2* tree) {
   constexpr int W = kFBlock / kWave;
   __shared__ int32_t qbuf[W][kWaveQCap];
   __shared__ int32_t tpre[W][kWave + 1];
   __shared__ int64_t tbeg[W][kWave];
+  __shared__ int32_t tu[W][kWave];
   __shared__ long long red[W];
   const uint32_t mode = sc->bfs_mode;
   const int wv = threadIdx.x / kWave;
@@ -237,7 +241,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
   WaveQ q{qbuf[wv], 0};
   long long added = 0;
   if (mode == kBfsSmall) {
-    if (blockIdx.x == 0) added = bfs_small_levels<I>(off, adj, vis, fn, qin, *cnt_in, qout, cnt_out, sc);
+    if (blockIdx.x == 0) added = bfs_small_levels<I>(off, adj, vis, fn, qin, *cnt_in, qout, cnt_out, sc, tree);
   } else if (mode == kBfsTopDown) {
     const int64_t cnt = *cnt_in;
     const int64_t tiles = (cnt + kWave - 1) / kWave;
@@ -263,6 +267,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
       tpre[wv][lane] = inc - (int32_t)d;
       if (lane == kWave - 1) tpre[wv][kWave] = total;
       tbeg[wv][lane] = b;
+      tu[wv][lane] = u;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -282,6 +287,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
           if (got) {
             aor(fn + (w >> 5), 1u << (w & 31));
             added += (long long)off[w + 1] - (long long)off[w];
+            if (tree) tree[w] = make_int2(tu[wv][lo], w);
           }
         }
         wq_push(q, got, w, qout, cnt_out);
@@ -298,11 +304,14 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
       if (v < n && !bit_get(vis, v)) {
         const int64_t e = (int64_t)off[v + 1];
         const int64_t b = (int64_t)off[v];
-        for (int64_t j = b; j < e; ++j)
-          if (bit_get(fc, adj[j])) {
+        for (int64_t j = b; j < e; ++j) {
+          const int32_t x = adj[j];
+          if (bit_get(fc, x)) {
             found = true;
+            if (tree) tree[v] = make_int2(x, (int32_t)v);
             break;
           }
+        }
         if (found) added += e - b;
       }
       // base is a multiple of 256, so lanes 0-31 and 32-63 each cover one
@@ -336,7 +345,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_heavy(const int32_t* __restrict
                                                        const long long* __restrict__ hp, const I* __restrict__ off,
                                                        const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
                                                        int32_t* qout, uint32_t* cnt_out, const DevScalars* sc,
-                                                       long long* __restrict__ fpart) {
+                                                       long long* __restrict__ fpart, int2* tree) {
   __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
   __shared__ long long red[kFBlock / kWave];
   WaveQ q{qbuf[threadIdx.x / kWave], 0};
@@ -358,6 +367,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_heavy(const int32_t* __restrict
         if (got) {
           aor(fn + (w >> 5), 1u << (w & 31));
           added += (long long)off[w + 1] - (long long)off[w];
+          if (tree) tree[w] = make_int2(u, w);
         }
       }
       wq_push(q, got, w, qout, cnt_out);
@@ -441,12 +451,13 @@ template <bool LDD, typename I>
 __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ qin, const uint32_t* cnt_in,
                                                     int32_t* qout, uint32_t* cnt_out, const I* __restrict__ off,
                                                     const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
-                                                    int32_t* P, int32_t* heavy, int32_t* hcount) {
+                                                    int32_t* P, int32_t* heavy, int32_t* hcount, int2* tree) {
   constexpr int W = kFBlock / kWave;
   __shared__ int32_t qbuf[W][kWaveQCap];
   __shared__ int32_t tpre[W][kWave + 1];
   __shared__ int64_t tbeg[W][kWave];
   __shared__ int32_t tlab[W][kWave];
+  __shared__ int32_t tu[W][kWave];
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   WaveQ q{qbuf[wv], 0};
@@ -475,6 +486,7 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
     tpre[wv][lane] = inc - (int32_t)d;
     if (lane == kWave - 1) tpre[wv][kWave] = total;
     tbeg[wv][lane] = b;
+    tu[wv][lane] = u;
     if (LDD) tlab[wv][lane] = (idx < cnt) ? P[u] : 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -495,6 +507,7 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
         if (got) {
           if (LDD) P[w] = tlab[wv][lo];
           else aor(fn + (w >> 5), 1u << (w & 31));
+          if (tree) tree[w] = make_int2(tu[wv][lo], w);
         }
       }
       wq_push(q, got, w, qout, cnt_out);
@@ -512,7 +525,7 @@ __global__ void __launch_bounds__(kFBlock) k_expand_heavy(const int32_t* __restr
                                                           const long long* __restrict__ hp, const I* __restrict__ off,
                                                           const int32_t* __restrict__ adj, uint32_t* vis,
                                                           uint32_t* fn, int32_t* P, int32_t* qout,
-                                                          uint32_t* cnt_out) {
+                                                          uint32_t* cnt_out, int2* tree) {
   __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
   WaveQ q{qbuf[threadIdx.x / kWave], 0};
   const int64_t c = *hcount;
@@ -532,6 +545,7 @@ __global__ void __launch_bounds__(kFBlock) k_expand_heavy(const int32_t* __restr
       if (got) {
         if (LDD) P[w] = P[u];
         else aor(fn + (w >> 5), 1u << (w & 31));
+        if (tree) tree[w] = make_int2(u, w);
       }
     }
     wq_push(q, got, w, qout, cnt_out);
@@ -625,12 +639,12 @@ cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reach
                          m, level_cap);
       hipLaunchKernelGGL(k_bfs_step<I>, dim3(gs), dim3(kFBlock), 0, a.s, n, off, a.adj, vis, (const uint32_t*)fc, fn,
                          (const int32_t*)q[cur], &sc->qcount[cur], q[cur ^ 1], &sc->qcount[cur ^ 1], a.heavy,
-                         &sc->hcount, sc, fpart);
+                         &sc->hcount, sc, fpart, a.tree_e);
       if (heavy) {
         list_prefix<I>(a, a.heavy, (const int32_t*)&sc->hcount);
         hipLaunchKernelGGL(k_bfs_heavy<I>, dim3(gh), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
                            (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, fn, q[cur ^ 1],
-                           &sc->qcount[cur ^ 1], (const DevScalars*)sc, fpart);
+                           &sc->qcount[cur ^ 1], (const DevScalars*)sc, fpart, a.tree_e);
       }
       uint32_t* t2 = fc;
       fc = fn;
@@ -689,6 +703,9 @@ cc_status sample_bfs(StaticArgs& a) {
     cc_status st = bfs_probe<I>(a, s, 0, &reached, &levels);
     if (st != CC_OK) return st;
     a.sample_rounds += levels;
+    if (10 * reached <= n && a.tree_e)   // a failed try's tree edges are not a sample
+      hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 * n, kFBlock, 4096)), dim3(kFBlock), 0, a.s,
+                         (uint32_t*)a.tree_e, 2 * n, 0xffffffffu);
     if (10 * reached > n) {
       hipLaunchKernelGGL(k_bitmap_min, dim3(grid_for(words, kFBlock, 256)), dim3(kFBlock), 0, a.s, vis, words, sc);
       hipLaunchKernelGGL(k_label_reached, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n,
@@ -855,12 +872,12 @@ cc_status sample_ldd(StaticArgs& a) {
     lo = hi > lo ? hi : lo;
     hipLaunchKernelGGL((k_expand<true, I>), dim3(grid_for(n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, q[cur],
                        &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, (uint32_t*)nullptr, a.P,
-                       a.heavy, &sc->hcount);
+                       a.heavy, &sc->hcount, a.tree_e);
     if (heavy) {
       list_prefix<I>(a, a.heavy, (const int32_t*)&sc->hcount);
       hipLaunchKernelGGL((k_expand_heavy<true, I>), dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
                          (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, (uint32_t*)nullptr,
-                         a.P, q[nxt], &sc->qcount[nxt]);
+                         a.P, q[nxt], &sc->qcount[nxt], a.tree_e);
     }
     CC_LAUNCH_CHECK();
     cur = nxt;

@@ -24,6 +24,8 @@ struct StaticArgs {
   long long* tsum = nullptr; // tile sums of that prefix
   int64_t hcap = 0;          // capacity of `heavy`
   int64_t heavy_vertices = -1;  // vertices with degree > kHeavyFrontier (-1: not counted yet)
+  int2* tree_e = nullptr;    // spanning forest: BFS/LDD tree edge per claimed vertex (nullable)
+  int2* hook_e = nullptr;    // spanning forest: union-find edge per hooked root (nullable)
   int64_t* ncomp_user = nullptr;
   int32_t sample_success = 1;
   int32_t sample_rounds = 0;
@@ -36,6 +38,8 @@ template <typename I> cc_status sample_ldd(StaticArgs& a);
 template <typename I> cc_status finish_sv(StaticArgs& a);
 template <typename I> cc_status finish_lt(StaticArgs& a);
 
+// The whole static algorithm on prepared arguments (statistics recorded).
+cc_status static_run(StaticArgs& a);
 // Synchronous read of the context's device scalars into ctx->host.
 cc_status pull_scalars(StaticArgs& a);
 

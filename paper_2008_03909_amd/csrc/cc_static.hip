@@ -247,7 +247,7 @@ __device__ __forceinline__ void load4(const int32_t* p, int64_t v0, bool vec, in
 // vertex are loaded before its first union so their latencies overlap.
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ adj,
-                                                 int32_t* P, int k, int mode, uint64_t key) {
+                                                 int32_t* P, int k, int mode, uint64_t key, int2* hook) {
   constexpr int kMaxPreload = 4;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict_
       w[j] = adj[b + idx];
       got = j + 1;
     }
-    for (int j = 0; j < got; ++j) union_rem<kSplitOne, kFindNaive>(P, (int32_t)v, w[j]);
+    for (int j = 0; j < got; ++j) forest_record(hook, union_rem<kSplitOne, kFindNaive>(P, (int32_t)v, w[j]), (int32_t)v, w[j]);
     for (int j = kMaxPreload; j < k; ++j) {
       int64_t idx;
       if (mode == CC_KOUT_AFFOREST) {
@@ -279,7 +279,8 @@ __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict_
       } else {
         idx = (int64_t)(sm_out(key, (uint64_t)v * (uint64_t)k + (uint64_t)j) % (uint64_t)deg);
       }
-      union_rem<kSplitOne, kFindNaive>(P, (int32_t)v, adj[b + idx]);
+      const int32_t w2 = adj[b + idx];
+      forest_record(hook, union_rem<kSplitOne, kFindNaive>(P, (int32_t)v, w2), (int32_t)v, w2);
     }
   }
 }
@@ -637,8 +638,9 @@ __global__ void __launch_bounds__(kBlock) k_compact_gather(int64_t n, int64_t S,
 template <int ALG, int SPLICE, int FIND>
 struct UnionOp {
   int32_t* P;
+  int2* hook;   // spanning forest: edge per hooked root (nullable)
   __device__ __forceinline__ bool operator()(int32_t u, int32_t w) const {
-    unite<ALG, SPLICE, FIND>(P, u, w);
+    forest_record(hook, unite<ALG, SPLICE, FIND>(P, u, w), u, w);
     return false;
   }
 };
@@ -708,7 +710,8 @@ __global__ void __launch_bounds__(kBlock) k_output_sum(const long long* __restri
 
 template <int ALG, int SPLICE, int FIND, typename I>
 static cc_status launch_uf_finish(StaticArgs& a) {
-  visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, UnionOp<ALG, SPLICE, FIND>{a.P}, (uint32_t*)nullptr);
+  visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, UnionOp<ALG, SPLICE, FIND>{a.P, a.hook_e},
+                   (uint32_t*)nullptr);
   CC_LAUNCH_CHECK();
   return CC_OK;
 }
@@ -778,7 +781,7 @@ static cc_status run_sample(StaticArgs& a) {
       PhaseScope ps(a.ctx, a.s, "sample");
       const uint64_t key = sm_out(v->seed, kTagKout);
       hipLaunchKernelGGL(k_kout<I>, dim3(grid_for(a.n, kBlock, kStreamGridCap)), dim3(kBlock), 0, a.s, a.n,
-                         (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key);
+                         (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key, a.hook_e);
       CC_LAUNCH_CHECK();
       use_lmax = true;
       break;
@@ -869,6 +872,14 @@ static cc_status run_tail(StaticArgs& a) {
   return CC_OK;
 }
 
+
+static void record_stats_host(StaticArgs& a);
+
+cc_status static_run(StaticArgs& a) {
+  cc_status st = a.o64 ? run_static<int64_t>(a, false) : run_static<int32_t>(a, false);
+  record_stats_host(a);
+  return st;
+}
 
 cc_status setup_args(StaticArgs& a, cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int o64,
                             const int32_t* adj, const cc_variant* v, void* ws, size_t ws_bytes, int32_t* labels,
