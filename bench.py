@@ -507,7 +507,8 @@ def main():
         "ingest": {"ms": ingest_ms, "pairs": g.num_pairs, "pairs_per_s": g.num_pairs / (ingest_ms / 1e3)},
     }
     del ws
-    if not args.no_forest:
+    forest_ok = v.finish == b.FIN_UF_ASYNC or (v.finish == b.FIN_UF_REM_CAS and v.splice != b.SPLICE_ATOMIC)
+    if not args.no_forest and forest_ok:
         # spanning forest with the default variant on the same CSR (outside the timed region above)
         for _ in range(2):
             b.spanning_forest_csr(ctx, csr, v)
