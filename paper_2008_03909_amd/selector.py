@@ -33,8 +33,10 @@ FAMILIES = ("er", "rmat", "grid2d", "grid3d", "star", "chain", "union")
 
 
 def arms():
-    """The K = 16 arms: {none, k-out, BFS, LDD} x {Rem-CAS/SplitAtomicOne,
-    Rem-CAS/SpliceAtomic, Async/FindAtomicSplit, Shiloach-Vishkin}."""
+    """The K = 20 arms: {none, k-out, BFS, LDD} x {Rem-CAS/SplitAtomicOne,
+    Rem-CAS/SpliceAtomic, Async/FindAtomicSplit, Shiloach-Vishkin}, then four
+    k-out edge choices with Rem-CAS/SplitAtomicOne: hybrid k = 1, afforest
+    k = 1 and k = 2, hybrid k = 3."""
     base = b.default_variant()
     fins = [dict(finish=b.FIN_UF_REM_CAS, splice=b.SPLICE_SPLIT_ONE, find=b.FIND_NAIVE),
             dict(finish=b.FIN_UF_REM_CAS, splice=b.SPLICE_ATOMIC, find=b.FIND_NAIVE),
@@ -44,6 +46,8 @@ def arms():
     for s in (b.SAMPLE_NONE, b.SAMPLE_KOUT, b.SAMPLE_BFS, b.SAMPLE_LDD):
         for f in fins:
             out.append(base.copy(sample=s, **f))
+    for k, mode in ((1, b.KOUT_HYBRID), (1, b.KOUT_AFFOREST), (2, b.KOUT_AFFOREST), (3, b.KOUT_HYBRID)):
+        out.append(base.copy(kout_k=k, kout_mode=mode))
     return out
 
 

@@ -36,7 +36,7 @@ def test_corpus_shape():
     C = _corpus()
     assert C["seeds"].size == 2000 and np.unique(C["seeds"]).size == 2000
     assert np.sum(C["seeds"] % 10 == 0) == 200
-    assert C["times"].shape == (2000, 16) and np.all(C["times"] > 0)
+    assert C["times"].shape[0] == 2000 and C["times"].shape[1] >= 16 and np.all(C["times"] > 0)
 
 
 def test_trained_selector_against_best_default_and_rules():
