@@ -605,6 +605,9 @@ class Selector:
         self.params = params_bf16
         self.arms = list(arms) if arms is not None else []
         self.K = len(self.arms) if params_bf16 is not None else 0
+        if params_bf16 is not None and params_bf16.numel() != mlp_param_count(self.K):
+            raise ValueError(f"the model has {params_bf16.numel()} parameters; {len(self.arms)} arms need "
+                             f"{mlp_param_count(self.K)}")
         self._arr = (cc_variant * max(self.K, 1))(*self.arms[:self.K]) if self.K else None
         self._norm = (ctypes.c_float * 32)(*[float(x) for x in norm]) if norm is not None else None
         self._need = {}
