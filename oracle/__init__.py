@@ -71,6 +71,8 @@ def _load():
         lib.oracle_bfs_budget.restype = i64
         lib.oracle_forest_check.argtypes = [i64, _i64p, _i32p, _i32p, i64, _i32p, _i32p]
         lib.oracle_forest_check.restype = i64
+        lib.oracle_msf_weight.argtypes = [i64, i64, _i32p, _i32p, ctypes.POINTER(ctypes.c_double), _i64p]
+        lib.oracle_msf_weight.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -192,6 +194,20 @@ def forest_check_csr(n: int, offsets, adj, labels_g, fu, fv) -> int:
     z = np.zeros(1, np.int32)
     return int(_load().oracle_forest_check(n, _p64(off), _p32(adj) if adj.size else _p32(z), _p32(lab), fu.shape[0],
                                            _p32(fu) if fu.size else _p32(z), _p32(fv) if fv.size else _p32(z)))
+
+
+def msf_weight(n: int, u, v, w):
+    """Exact minimum spanning forest weight (Kruskal) of an undirected
+    weighted pair list, and its edge count.  The reference for the
+    approximate MSF of Section 5.1: a (1 + eps) approximation must weigh at
+    most (1 + eps) times this."""
+    u, v = _c(u, np.int32), _c(v, np.int32)
+    w = _c(w, np.float64)
+    k = np.zeros(1, np.int64)
+    z32, z64 = np.zeros(1, np.int32), np.zeros(1, np.float64)
+    total = _load().oracle_msf_weight(n, u.shape[0], _p32(u) if u.size else _p32(z32), _p32(v) if v.size else _p32(z32),
+                                      (w if w.size else z64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _p64(k))
+    return float(total), int(k[0])
 
 
 # ---- samplers with a deterministic partition -------------------------------

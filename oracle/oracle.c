@@ -372,3 +372,40 @@ int64_t oracle_forest_check(int64_t n, const int64_t* offsets, const int32_t* ad
   free(lab);
   return code;
 }
+
+/* ---- minimum spanning forest weight (Kruskal) ---------------------------
+ * Exact MSF weight of an undirected weighted pair list: pairs sorted by
+ * weight (ties by index), each pair kept iff it joins two different trees
+ * of a sequential union-find.  Self-loops never join anything. */
+static const double* g_msf_w;
+static int cmp_by_weight(const void* a, const void* b) {
+  const int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  const double wx = g_msf_w[x], wy = g_msf_w[y];
+  if (wx < wy) return -1;
+  if (wx > wy) return 1;
+  return x < y ? -1 : (x > y);
+}
+double oracle_msf_weight(int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v, const double* w,
+                         int64_t* num_edges) {
+  int64_t* idx = (int64_t*)malloc((size_t)(num_pairs > 0 ? num_pairs : 1) * sizeof(int64_t));
+  int32_t* P = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  for (int64_t i = 0; i < num_pairs; ++i) idx[i] = i;
+  g_msf_w = w;
+  qsort(idx, (size_t)num_pairs, sizeof(int64_t), cmp_by_weight);
+  oracle_uf_init(n, P);
+  double total = 0.0;
+  int64_t k = 0;
+  for (int64_t t = 0; t < num_pairs; ++t) {
+    const int64_t i = idx[t];
+    const int32_t ra = uf_find(P, u[i]), rb = uf_find(P, v[i]);
+    if (ra == rb) continue;
+    if (ra < rb) P[rb] = ra;
+    else P[ra] = rb;
+    total += w[i];
+    ++k;
+  }
+  free(idx);
+  free(P);
+  if (num_edges) *num_edges = k;
+  return total;
+}

@@ -52,6 +52,8 @@ def _load():
         lib.gen_orient_drop_loops.restype = ctypes.c_int64
         lib.gen_splitmix_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
         lib.gen_splitmix_draw.restype = ctypes.c_uint64
+        lib.gen_pair_weights.argtypes = [ctypes.c_int64, ctypes.c_int64, _i32p, _i32p, ctypes.c_double,
+                                         ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)]
         _lib = lib
     return _lib
 
@@ -224,3 +226,17 @@ def workload_grid3d(side: int = 256, p: float = 0.35, seed: int = 3) -> Graph:
 
 def log_uniform_int(lo: float, hi: float, u: float) -> int:
     return int(math.floor(10 ** (math.log10(lo) + u * (math.log10(hi) - math.log10(lo)))))
+
+
+def pair_weights(n: int, a, b, seed: int, mean: float = 1.0) -> np.ndarray:
+    """Float32 weight of each undirected pair (a[i], b[i]): exponential with
+    the given mean, a function of the unordered pair (so both orientations
+    and repeated copies agree).  Also gives the weight of every adjacency
+    entry of a CSR: pass the row ids and the adjacency."""
+    a = np.ascontiguousarray(a, np.int32)
+    b = np.ascontiguousarray(b, np.int32)
+    w = np.empty(a.shape[0], np.float32)
+    if a.size:
+        _load().gen_pair_weights(n, a.shape[0], _p(a), _p(b), float(mean), seed,
+                                 w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    return w

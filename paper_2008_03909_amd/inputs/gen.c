@@ -180,3 +180,22 @@ int64_t gen_orient_drop_loops(int64_t count, int32_t* u, int32_t* v) {
   }
   return out;
 }
+
+/* Symmetric edge weights: the weight of the undirected pair {a, b} is
+ * mean * (-ln U), U uniform in (0, 1) from the top 53 bits of draw
+ * min(a,b) * n + max(a,b) of the weight stream -- an exponential law, the
+ * same for both orientations and for every copy of the pair.  Written as
+ * float (the weighted CSR's element type). */
+#include <math.h>
+void gen_pair_weights(int64_t n, int64_t count, const int32_t* a, const int32_t* b, double mean, uint64_t seed,
+                      float* w) {
+  const uint64_t key = stream_key(seed, 7);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t x = a[i] < b[i] ? a[i] : b[i];
+    const int64_t y = a[i] < b[i] ? b[i] : a[i];
+    const uint64_t r = draw(key, (uint64_t)x * (uint64_t)n + (uint64_t)y);
+    const double u = ((double)(r >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    w[i] = (float)(-mean * log(u));
+  }
+}

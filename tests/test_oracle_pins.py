@@ -434,3 +434,52 @@ def test_forest_check_on_random_graphs_against_bfs_trees():
         assert fu.size == g.n - c
         assert oracle.forest_check(g, fu, fv) == oracle.FOREST_OK
         assert oracle.forest_check(g, np.append(fu, fu[0]), np.append(fv, fv[0])) == oracle.FOREST_CYCLE
+
+
+# ---- exact MSF weight (Kruskal) ------------------------------------------------
+
+def test_msf_weight_closed_forms():
+    # a tree is its own MSF; a cycle drops its heaviest edge; unit weights give n - c
+    rng = np.random.default_rng(3)
+    g = inputs.path(40)
+    w = rng.uniform(0.5, 2.0, g.num_pairs)
+    assert abs(oracle.msf_weight(g.n, g.u, g.v, w)[0] - w.sum()) < 1e-9
+    n = 30
+    cu = np.arange(n, dtype=np.int32)
+    cv = ((cu + 1) % n).astype(np.int32)
+    cw = rng.uniform(1, 5, n)
+    tot, k = oracle.msf_weight(n, cu, cv, cw)
+    assert k == n - 1 and abs(tot - (cw.sum() - cw.max())) < 1e-9
+    e = inputs.er(500, 700, seed=9)
+    _, c = oracle.labels(e)
+    tot, k = oracle.msf_weight(e.n, e.u, e.v, np.ones(e.num_pairs))
+    assert k == e.n - c and tot == e.n - c
+
+
+def test_msf_weight_against_brute_force():
+    """Minimum over every spanning tree of small complete graphs."""
+    rng = np.random.default_rng(5)
+    for n in (3, 4, 5, 6):
+        pairs = [(a, b) for a in range(n) for b in range(a + 1, n)]
+        for _ in range(3):
+            w = rng.exponential(1.0, len(pairs))
+            best = np.inf
+            for sub in itertools.combinations(range(len(pairs)), n - 1):
+                P = list(range(n))
+
+                def f(x):
+                    while P[x] != x:
+                        x = P[x]
+                    return x
+                ok = True
+                for i in sub:
+                    ra, rb = f(pairs[i][0]), f(pairs[i][1])
+                    if ra == rb:
+                        ok = False
+                        break
+                    P[max(ra, rb)] = min(ra, rb)
+                if ok:
+                    best = min(best, sum(w[i] for i in sub))
+            u = np.array([p[0] for p in pairs], np.int32)
+            v = np.array([p[1] for p in pairs], np.int32)
+            assert abs(oracle.msf_weight(n, u, v, w)[0] - best) < 1e-9
