@@ -31,7 +31,7 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 def build(verbose: bool = False) -> str:
     src = os.path.join(_HERE, "oracle.c")
     tmp = _SO + ".tmp"
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src]
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -73,6 +73,9 @@ def _load():
         lib.oracle_forest_check.restype = i64
         lib.oracle_msf_weight.argtypes = [i64, i64, _i32p, _i32p, ctypes.POINTER(ctypes.c_double), _i64p]
         lib.oracle_msf_weight.restype = ctypes.c_double
+        lib.oracle_amsf_buckets.argtypes = [i64, i64, _i32p, _i32p, ctypes.POINTER(ctypes.c_float),
+                                            ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _i64p]
+        lib.oracle_amsf_buckets.restype = ctypes.c_int32
         _lib = lib
     return _lib
 
@@ -208,6 +211,33 @@ def msf_weight(n: int, u, v, w):
     total = _load().oracle_msf_weight(n, u.shape[0], _p32(u) if u.size else _p32(z32), _p32(v) if v.size else _p32(z32),
                                       (w if w.size else z64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _p64(k))
     return float(total), int(k[0])
+
+
+def amsf_buckets(n: int, u, v, w, eps: float, max_buckets: int = 4096):
+    """Bucket boundaries of the approximate MSF of Section 5.1 and the
+    number of forest edges each bucket contributes.
+
+    Boundaries: t_0 = the smallest weight, t_{i+1} = t_i * (1 + eps) in
+    double, rounded down to float; an edge lies in the largest bucket i with
+    t_i <= w.  Processing the buckets in order (a spanning forest per bucket
+    over the earlier buckets' components) is Kruskal's algorithm on weights
+    rounded down to t_i, so the per-bucket edge counts are the same for every
+    forest the method can return.  Returns (thresholds float32 of nb + 1
+    entries, counts int64 of nb entries).  Raises ValueError on a weight
+    that is not finite and > 0 or when more than max_buckets are needed."""
+    u, v = _c(u, np.int32), _c(v, np.int32)
+    w = _c(w, np.float32)
+    t = np.zeros(max_buckets + 1, np.float32)
+    cnt = np.zeros(max(max_buckets, 1), np.int64)
+    if u.size == 0:
+        return t[:1][:0], cnt[:0]
+    nb = _load().oracle_amsf_buckets(n, u.shape[0], _p32(u), _p32(v), w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                     float(eps), max_buckets, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _p64(cnt))
+    if nb == -2:
+        raise ValueError("weights must be finite and > 0")
+    if nb < 0:
+        raise ValueError(f"more than {max_buckets} buckets")
+    return t[: nb + 1].copy(), cnt[:nb].copy()
 
 
 # ---- samplers with a deterministic partition -------------------------------

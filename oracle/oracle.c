@@ -23,6 +23,7 @@
  *    its definition: the connected components of the sampled sub-graph.
  */
 #include <stdint.h>
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -408,4 +409,74 @@ double oracle_msf_weight(int64_t n, int64_t num_pairs, const int32_t* u, const i
   free(P);
   if (num_edges) *num_edges = k;
   return total;
+}
+
+/* Approximate MSF buckets (Section 5.1).  The bucket boundaries are
+ * t_0 = W_min and t_{i+1} = t_i * (1 + eps), each product taken in double
+ * and rounded down to float, so that no bucket [t_i, t_{i+1}) spans more
+ * than a factor 1 + eps; an edge of weight w is in the largest i with
+ * t_i <= w.  Taking the buckets in increasing order and adding a spanning
+ * forest of each bucket over the components of the earlier ones is Kruskal's
+ * algorithm on the weights rounded down to their bucket's boundary, so the
+ * number of forest edges that fall in each bucket is the same for every
+ * such forest: those counts are returned.  Returns the number of buckets
+ * (at most max_buckets; -1 if more would be needed, -2 for a weight that is
+ * not finite and > 0); thresholds gets nb + 1 boundaries. */
+static float round_down_float(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = nextafterf(f, -INFINITY);
+  return f;
+}
+static const int32_t* g_bucket_of;
+static int cmp_by_bucket(const void* a, const void* b) {
+  const int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  const int32_t bx = g_bucket_of[x], by = g_bucket_of[y];
+  if (bx != by) return bx < by ? -1 : 1;
+  return x < y ? -1 : (x > y);
+}
+int32_t oracle_amsf_buckets(int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v, const float* w,
+                            double eps, int32_t max_buckets, float* thresholds, int64_t* counts) {
+  if (num_pairs == 0) return 0;
+  float wmin = INFINITY, wmax = 0.0f;
+  for (int64_t i = 0; i < num_pairs; ++i) {
+    if (!(w[i] > 0.0f) || isinf(w[i])) return -2;
+    if (w[i] < wmin) wmin = w[i];
+    if (w[i] > wmax) wmax = w[i];
+  }
+  int32_t nb = 0;
+  thresholds[0] = wmin;
+  while (thresholds[nb] <= wmax) {
+    if (nb == max_buckets) return -1;
+    thresholds[nb + 1] = round_down_float((double)thresholds[nb] * (1.0 + eps));
+    ++nb;
+  }
+  int32_t* bucket = (int32_t*)malloc((size_t)num_pairs * sizeof(int32_t));
+  for (int64_t i = 0; i < num_pairs; ++i) {
+    int32_t lo = 0, hi = nb - 1; /* largest b with thresholds[b] <= w */
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) / 2;
+      if (thresholds[mid] <= w[i]) lo = mid;
+      else hi = mid - 1;
+    }
+    bucket[i] = lo;
+  }
+  int64_t* idx = (int64_t*)malloc((size_t)num_pairs * sizeof(int64_t));
+  int32_t* P = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  for (int64_t i = 0; i < num_pairs; ++i) idx[i] = i;
+  g_bucket_of = bucket;
+  qsort(idx, (size_t)num_pairs, sizeof(int64_t), cmp_by_bucket);
+  oracle_uf_init(n, P);
+  for (int32_t b = 0; b < nb; ++b) counts[b] = 0;
+  for (int64_t t = 0; t < num_pairs; ++t) {
+    const int64_t i = idx[t];
+    const int32_t ra = uf_find(P, u[i]), rb = uf_find(P, v[i]);
+    if (ra == rb) continue;
+    if (ra < rb) P[rb] = ra;
+    else P[ra] = rb;
+    ++counts[bucket[i]];
+  }
+  free(bucket);
+  free(idx);
+  free(P);
+  return nb;
 }

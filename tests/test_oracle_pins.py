@@ -483,3 +483,91 @@ def test_msf_weight_against_brute_force():
             u = np.array([p[0] for p in pairs], np.int32)
             v = np.array([p[1] for p in pairs], np.int32)
             assert abs(oracle.msf_weight(n, u, v, w)[0] - best) < 1e-9
+
+
+# ---- approximate MSF buckets (Section 5.1) -----------------------------------
+
+def _spanning_forests(n, pairs):
+    """Every spanning forest of a small multigraph, as index tuples."""
+    P = list(range(n))
+
+    def f(x):
+        while P[x] != x:
+            x = P[x]
+        return x
+    comps = n
+    for a, b in pairs:
+        ra, rb = f(a), f(b)
+        if ra != rb:
+            P[max(ra, rb)] = min(ra, rb)
+            comps -= 1
+    k = n - comps
+    out = []
+    for sub in itertools.combinations(range(len(pairs)), k):
+        P = list(range(n))
+        ok = True
+        for i in sub:
+            ra, rb = f(pairs[i][0]), f(pairs[i][1])
+            if ra == rb:
+                ok = False
+                break
+            P[max(ra, rb)] = min(ra, rb)
+        if ok:
+            out.append(sub)
+    return out
+
+
+def test_amsf_thresholds_closed_forms():
+    """Boundaries t_0 = W_min, t_{i+1} = t_i (1 + eps) rounded down to
+    float: exact for eps = 0.25 from 1.0, and one float below 1.1 for
+    eps = 0.1 (round-to-nearest would give 1.1f itself)."""
+    u = np.array([0, 1, 2, 3], np.int32)
+    v = np.array([1, 2, 3, 4], np.int32)
+    w = np.array([1.0, 1.25, 1.5625, 2.0], np.float32)
+    t, cnt = oracle.amsf_buckets(5, u, v, w, 0.25)
+    assert t.tolist() == [1.0, 1.25, 1.5625, 1.953125, 2.44140625]
+    assert cnt.tolist() == [1, 1, 1, 1]  # a path: every edge is a forest edge
+    below = np.nextafter(np.float32(1.1), np.float32(0))
+    w = np.array([1.0, below, np.float32(1.1), np.nextafter(below, np.float32(0))], np.float32)
+    t, cnt = oracle.amsf_buckets(5, u, v, w, 0.1)
+    assert t[1] == below
+    assert cnt.tolist() == [2, 2]  # 1.0 and the float under t_1 in bucket 0; t_1 and 1.1f in bucket 1
+    # every weight equal: one bucket holding n - c forest edges
+    t, cnt = oracle.amsf_buckets(6, np.array([0, 1, 0, 3], np.int32), np.array([1, 2, 2, 4], np.int32),
+                                 np.full(4, 3.0, np.float32), 0.25)
+    assert len(t) == 2 and cnt.tolist() == [3]
+    # a ratio under 1 + eps: one bucket
+    t, cnt = oracle.amsf_buckets(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32),
+                                 np.array([1.0, 1.2], np.float32), 0.25)
+    assert cnt.tolist() == [2]
+    with pytest.raises(ValueError):
+        oracle.amsf_buckets(3, np.array([0], np.int32), np.array([1], np.int32), np.array([0.0], np.float32), 0.25)
+    with pytest.raises(ValueError):
+        oracle.amsf_buckets(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32),
+                            np.array([1.0, 1e30], np.float32), 0.25, max_buckets=16)
+
+
+def test_amsf_counts_against_brute_force():
+    """On small multigraphs, every spanning forest of minimum rounded weight
+    (each weight rounded down to its bucket's boundary) has exactly the
+    oracle's per-bucket counts, and the bucketed forests weigh at most
+    (1 + eps) times the exact minimum."""
+    rng = np.random.default_rng(11)
+    for trial in range(30):
+        n = int(rng.integers(3, 7))
+        k = int(rng.integers(n - 1, n + 4))
+        pairs = [tuple(int(x) for x in rng.choice(n, 2, replace=False)) for _ in range(k)]
+        eps = float(rng.choice([0.1, 0.25, 1.0]))
+        w = rng.exponential(1.0, k).astype(np.float32)
+        u = np.array([p[0] for p in pairs], np.int32)
+        v = np.array([p[1] for p in pairs], np.int32)
+        t, cnt = oracle.amsf_buckets(n, u, v, w, eps)
+        b = np.searchsorted(t, w, side="right") - 1
+        rounded = t[b].astype(np.float64)
+        forests = _spanning_forests(n, pairs)
+        best = min(sum(rounded[i] for i in f) for f in forests)
+        exact, _ = oracle.msf_weight(n, u, v, w.astype(np.float64))
+        for f in forests:
+            if sum(rounded[i] for i in f) <= best * (1 + 1e-12):
+                assert np.bincount(b[list(f)], minlength=len(cnt)).tolist() == cnt.tolist(), trial
+                assert sum(float(w[i]) for i in f) <= (1 + eps) * exact * (1 + 1e-9), trial
