@@ -386,6 +386,49 @@ def sweep(ctx, csr, g, workload_name: str, reps: int = 5, check: bool = True):
     return rows
 
 
+def amsf_leg(ctx, csr, n: int, m: int, ms_conn: float, steps: int) -> dict:
+    """Approximate MSF (Section 5.1) on the same CSR with exponential weights
+    of mean 1 (the paper's weighting), eps = 0.25.  Timed outside the main
+    region; per-phase times from the call's own events."""
+    import numpy as np
+    import torch
+
+    from paper_2008_03909_amd import binding as b
+    from paper_2008_03909_amd import inputs
+
+    t = time.perf_counter()
+    off_h = csr.offsets.cpu().numpy()
+    adj_h = csr.adj.cpu().numpy()
+    rows = np.repeat(np.arange(n, dtype=np.int32), np.diff(off_h))
+    w = inputs.pair_weights(n, rows, adj_h, seed=77, mean=1.0)
+    del rows, adj_h, off_h
+    wt = torch.from_numpy(w).to(ctx.torch_device)
+    del w
+    log(f"amsf weights in {time.perf_counter() - t:.1f}s")
+    opt = b.amsf_options()
+    for _ in range(2):
+        b.amsf_csr(ctx, csr, wt, opt)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.phase_times_reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, _, _, _, ne, tw = b.amsf_csr(ctx, csr, wt, opt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ctx.set_timing(False)
+    ph = {k: round(v[0] / steps, 4) for k, v in ctx.phase_times().items()}
+    st = ctx.last_stats()
+    res = {"ms": ms, "edges_per_s": m / (ms / 1e3), "epsilon": float(opt.epsilon),
+           "light_fraction": float(opt.light_fraction), "forest_edges": int(ne.item()),
+           "weight": float(tw.item()), "light_buckets": st["sample_rounds"], "rounds": st["finish_rounds"],
+           "vs_connectivity": ms / ms_conn, "phase_ms_per_call": ph}
+    log(f"amsf: {ms:.3f} ms ({ms / ms_conn:.2f}x connectivity), {res['forest_edges']} edges, "
+        f"light buckets {res['light_buckets']}, rounds {res['rounds']}, phases {ph}")
+    del wt
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -396,6 +439,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-incremental", action="store_true")
     ap.add_argument("--no-forest", action="store_true", help="skip the spanning-forest timing")
+    ap.add_argument("--no-amsf", action="store_true", help="skip the approximate-MSF timing")
     ap.add_argument("--phases", action="store_true", help="print per-phase times to stderr")
     ap.add_argument("--sweep", default="", help="also time all 80 variants; write the rows to this JSON file")
     args = ap.parse_args()
@@ -521,6 +565,8 @@ def main():
         out["spanning_forest"] = {"ms": ms_f, "edges_per_s": m / (ms_f / 1e3),
                                   "forest_edges": int(ne.item()), "vs_connectivity": ms_f / ms_step}
         log(f"spanning forest: {ms_f:.3f} ms ({ms_f / ms_step:.2f}x connectivity), {int(ne.item())} edges")
+    if not args.no_amsf:
+        out["amsf"] = amsf_leg(ctx, csr, n, m, ms_step, args.steps)
     if args.sweep:
         log("variant sweep ...")
         rows = sweep(ctx, csr, g, args.workload)

@@ -207,6 +207,48 @@ cc_status cc_spanning_forest_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* 
                                  int32_t* labels_out, int32_t* edges_u, int32_t* edges_v, int64_t* num_edges_dev,
                                  void* hip_stream);
 
+/* ---- approximate minimum spanning forest (Section 5.1, AMSF) -------------------
+ * weights[j] > 0 is the weight of adjacency entry j of the symmetric CSR
+ * (device float array of m entries); both orientations of an edge must carry
+ * the same weight.  With W_min the smallest weight, the edges are bucketed
+ * by thresholds t_0 = W_min, t_{i+1} = t_i * (1 + epsilon) computed in
+ * double and rounded down to float (so every bucket [t_i, t_{i+1}) spans a
+ * ratio of at most 1 + epsilon), and buckets are taken in increasing order:
+ * each adds a spanning forest of its edges over the components of the
+ * buckets before it.  The result is a spanning forest whose weight is at
+ * most (1 + epsilon) times the minimum; the number of its edges in each
+ * bucket is the same for every such forest.
+ *
+ * The first buckets, holding about light_fraction of the entries (estimated
+ * from a sample of the weights), are extracted once into a bucket-sorted
+ * edge list; every later bucket is a round over the rows of the vertices
+ * outside the largest component of the labelling so far (the paper's
+ * sampled no-filter variant, AMSF-NF-S).  light_fraction = 0 runs every
+ * bucket that way.  Union-find is UF-Rem-CAS with SplitAtomicOne and
+ * FindNaive, as in the paper's experiments.
+ *
+ * Outputs: edges_u / edges_v / edges_w (device, at least n entries each;
+ * edges_w nullable) receive *num_edges_dev (device int64) forest edges;
+ * labels_out receives the canonical component labels (min id);
+ * weight_dev (nullable, device double) the forest's total weight.
+ * Errors: epsilon outside [2^-20, 2^20], light_fraction outside [0, 1] or
+ * bucket counts above 4096 (the weight range spans more than
+ * (1 + epsilon)^4096) return CC_EINVAL; a weight that is not finite and > 0
+ * returns CC_EINVAL after the first pass.  The call synchronises hip_stream
+ * twice (the weight range, then the bucket histogram).
+ * workspace: device buffer of >= cc_amsf_workspace_bytes. */
+typedef struct {
+  float epsilon;         /* bucket ratio - 1 (the paper's experiments: 0.25) */
+  float light_fraction;  /* share of entries handled from the bucket-sorted list */
+  uint64_t seed;         /* weight sample used to pick the light buckets */
+} cc_amsf_options;
+cc_status cc_amsf_default_options(cc_amsf_options* out);
+cc_status cc_amsf_workspace_bytes(int64_t n, int64_t m, const cc_amsf_options* opt, size_t* bytes);
+cc_status cc_amsf_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                      const int32_t* adj, const float* weights, const cc_amsf_options* opt, void* workspace,
+                      size_t ws_bytes, int32_t* labels_out, int32_t* edges_u, int32_t* edges_v, float* edges_w,
+                      int64_t* num_edges_dev, double* weight_dev, void* hip_stream);
+
 /* ---- ingest: undirected pair list -> symmetric CSR (Section 2 formats) -------
  * Output: both orientations of every pair with u != v, rows sorted
  * ascending, duplicates removed iff dedup != 0.  adj_out needs capacity

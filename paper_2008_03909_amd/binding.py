@@ -71,6 +71,10 @@ class cc_variant(ctypes.Structure):
         return f"cc_variant({self.name()}, seed={self.seed})"
 
 
+class cc_amsf_options(ctypes.Structure):
+    _fields_ = [("epsilon", ctypes.c_float), ("light_fraction", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
 class cc_stats(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int64), ("m", ctypes.c_int64),
@@ -123,6 +127,11 @@ def lib():
                                                  ctypes.POINTER(ctypes.c_size_t)]),
             "cc_spanning_forest_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
                                               ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]),
+            "cc_amsf_default_options": (_int, [ctypes.POINTER(cc_amsf_options)]),
+            "cc_amsf_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_amsf_options),
+                                               ctypes.POINTER(ctypes.c_size_t)]),
+            "cc_amsf_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, ctypes.POINTER(cc_amsf_options), _vp,
+                                   ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "cc_csr_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
             "cc_build_csr": (_int, [_vp, _i64, _i64, _vp, _vp, _int, _vp, ctypes.c_size_t, _vp, _int, _vp, _vp,
                                     _vp]),
@@ -377,6 +386,45 @@ def spanning_forest_csr(ctx: Context, g: CSR, variant: cc_variant | None = None,
                                         _ptr(ws), ws.numel(), _ptr(labels), _ptr(eu), _ptr(ev), _ptr(ne),
                                         _stream_handle(stream)), "cc_spanning_forest_csr")
     return labels, eu, ev, ne
+
+
+def amsf_options(epsilon: float | None = None, light_fraction: float | None = None,
+                 seed: int | None = None) -> cc_amsf_options:
+    """cc_amsf_default_options with the given fields replaced."""
+    o = cc_amsf_options()
+    _check(lib().cc_amsf_default_options(ctypes.byref(o)), "cc_amsf_default_options")
+    if epsilon is not None:
+        o.epsilon = epsilon
+    if light_fraction is not None:
+        o.light_fraction = light_fraction
+    if seed is not None:
+        o.seed = seed
+    return o
+
+
+def amsf_csr(ctx: Context, g: CSR, weights, options: cc_amsf_options | None = None, stream=None):
+    """cc_amsf_csr (Section 5.1).  weights: device float32 tensor of g.m
+    entries, one per adjacency entry.  Returns (labels int32[n], edges_u,
+    edges_v, edges_w, num_edges int64[1], weight float64[1]); the first
+    num_edges entries of edges_u/v/w are the forest."""
+    o = options if options is not None else amsf_options()
+    dev = ctx.torch_device
+    labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    eu = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    ev = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    ew = torch.empty(max(g.n, 1), dtype=torch.float32, device=dev)
+    ne = torch.zeros(1, dtype=torch.int64, device=dev)
+    tw = torch.zeros(1, dtype=torch.float64, device=dev)
+    if weights.dtype != torch.float32 or weights.numel() != g.m:
+        raise ValueError(f"weights must be float32 with {g.m} entries")
+    wsb = ctypes.c_size_t()
+    _check(lib().cc_amsf_workspace_bytes(g.n, g.m, ctypes.byref(o), ctypes.byref(wsb)), "cc_amsf_workspace_bytes")
+    ws = ctx.workspace(int(wsb.value))
+    wp = _ptr(weights) if g.m > 0 else None
+    _check(lib().cc_amsf_csr(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), wp, ctypes.byref(o), _ptr(ws),
+                             ws.numel(), _ptr(labels), _ptr(eu), _ptr(ev), _ptr(ew), _ptr(ne), _ptr(tw),
+                             _stream_handle(stream)), "cc_amsf_csr")
+    return labels, eu, ev, ew, ne, tw
 
 
 def sample_csr(ctx: Context, g: CSR, variant: cc_variant, stream=None):

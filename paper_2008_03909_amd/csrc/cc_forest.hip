@@ -21,6 +21,13 @@ namespace cc {
 
 constexpr int kForestTile = 4096;   // entries of the (tree_e ++ hook_e) array per block
 
+// Slot i of the concatenation (tree_e ++ hook_e), or of hook_e alone when
+// there is no tree array.
+__device__ __forceinline__ int2 forest_slot(const int2* tree, const int2* hook, int64_t n, int64_t i) {
+  if (!tree) return hook[i];
+  return i < n ? tree[i] : hook[i - n];
+}
+
 __global__ void __launch_bounds__(kFBlock) k_forest_count(int64_t len, const int2* __restrict__ tree,
                                                           const int2* __restrict__ hook, int64_t n,
                                                           int32_t* __restrict__ cnt) {
@@ -28,7 +35,7 @@ __global__ void __launch_bounds__(kFBlock) k_forest_count(int64_t len, const int
   const int64_t base = (int64_t)blockIdx.x * kForestTile;
   int32_t c = 0;
   for (int64_t i = base + threadIdx.x; i < base + kForestTile && i < len; i += kFBlock) {
-    const int2 e = i < n ? tree[i] : hook[i - n];
+    const int2 e = forest_slot(tree, hook, n, i);
     c += e.x >= 0;
   }
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
@@ -69,9 +76,11 @@ __global__ void __launch_bounds__(1024) k_forest_scan(int64_t tiles, int32_t* cn
 }
 
 __global__ void __launch_bounds__(kFBlock) k_forest_write(int64_t len, const int2* __restrict__ tree,
-                                                          const int2* __restrict__ hook, int64_t n,
+                                                          const int2* __restrict__ hook,
+                                                          const float* __restrict__ hook_w, int64_t n,
                                                           const int32_t* __restrict__ base_of,
-                                                          int32_t* __restrict__ out_u, int32_t* __restrict__ out_v) {
+                                                          int32_t* __restrict__ out_u, int32_t* __restrict__ out_v,
+                                                          float* __restrict__ out_w) {
   __shared__ int32_t wcnt[kFBlock / kWave];
   const int lane = lane_id(), w = threadIdx.x / kWave;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -80,7 +89,7 @@ __global__ void __launch_bounds__(kFBlock) k_forest_write(int64_t len, const int
   for (int64_t i0 = base; i0 < base + kForestTile && i0 < len; i0 += kFBlock) {
     const int64_t i = i0 + threadIdx.x;
     int2 e = make_int2(-1, -1);
-    if (i < base + kForestTile && i < len) e = i < n ? tree[i] : hook[i - n];
+    if (i < base + kForestTile && i < len) e = forest_slot(tree, hook, n, i);
     const bool keep = e.x >= 0;
     const uint64_t m = __ballot(keep);
     if (lane == 0) wcnt[w] = __popcll(m);
@@ -94,15 +103,30 @@ __global__ void __launch_bounds__(kFBlock) k_forest_write(int64_t len, const int
       const int32_t p = pos + before + __popcll(m & lt);
       out_u[p] = e.x;
       out_v[p] = e.y;
+      if (out_w) out_w[p] = hook_w[tree ? i - n : i];
     }
     pos += all;
     __syncthreads();
   }
 }
 
+int64_t forest_tiles(int64_t len) { return (len + kForestTile - 1) / kForestTile; }
+
+cc_status forest_filter(hipStream_t s, int64_t n, const int2* tree, const int2* hook, const float* hook_w,
+                        int32_t* cnt, int32_t* out_u, int32_t* out_v, float* out_w, int64_t* num_edges) {
+  const int64_t len = tree ? 2 * n : n;
+  const int64_t tiles = forest_tiles(len);
+  hipLaunchKernelGGL(k_forest_count, dim3((unsigned)tiles), dim3(kFBlock), 0, s, len, tree, hook, n, cnt);
+  hipLaunchKernelGGL(k_forest_scan, dim3(1), dim3(1024), 0, s, tiles, cnt, (long long*)num_edges);
+  hipLaunchKernelGGL(k_forest_write, dim3((unsigned)tiles), dim3(kFBlock), 0, s, len, tree, hook,
+                     (hook_w && out_w) ? hook_w : (const float*)nullptr, n, (const int32_t*)cnt, out_u, out_v,
+                     (hook_w && out_w) ? out_w : (float*)nullptr);
+  CC_LAUNCH_CHECK();
+  return CC_OK;
+}
+
 static size_t forest_extra(int64_t n) {
-  const int64_t tiles = (2 * n + kForestTile - 1) / kForestTile;
-  return 2 * align256((size_t)n * 8) + align256((size_t)tiles * 4);
+  return 2 * align256((size_t)n * 8) + align256((size_t)forest_tiles(2 * n) * 4);
 }
 
 }  // namespace cc
@@ -152,15 +176,7 @@ cc_status cc_spanning_forest_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* 
   CC_LAUNCH_CHECK();
   st = static_run(a);
   if (st != CC_OK) return st;
-  const int64_t len = 2 * n;
-  const int64_t tiles = (len + kForestTile - 1) / kForestTile;
-  hipLaunchKernelGGL(k_forest_count, dim3((unsigned)tiles), dim3(kFBlock), 0, a.s, len, (const int2*)a.tree_e,
-                     (const int2*)a.hook_e, n, cnt);
-  hipLaunchKernelGGL(k_forest_scan, dim3(1), dim3(1024), 0, a.s, tiles, cnt, (long long*)num_edges_dev);
-  hipLaunchKernelGGL(k_forest_write, dim3((unsigned)tiles), dim3(kFBlock), 0, a.s, len, (const int2*)a.tree_e,
-                     (const int2*)a.hook_e, n, (const int32_t*)cnt, edges_u, edges_v);
-  CC_LAUNCH_CHECK();
-  return CC_OK;
+  return forest_filter(a.s, n, a.tree_e, a.hook_e, nullptr, cnt, edges_u, edges_v, nullptr, num_edges_dev);
 }
 
 }  // extern "C"

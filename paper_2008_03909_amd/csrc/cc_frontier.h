@@ -213,7 +213,8 @@ __device__ __forceinline__ int64_t heavy_owner_tile(const long long* hp, int64_t
 }
 
 // Edge visitors over the degree-binned candidate lists written by the
-// compaction: op(u, w) for every candidate u and every w in row(u).  Thread
+// compaction: op(u, w, j) for every candidate u and every entry j of row(u),
+// w = adj[j].  Thread
 // bin: cand front; wave bin: big front; block bin: big back; grid bin: the
 // heavy list, whose edges are spread evenly over the whole grid.
 template <class Op, typename I>
@@ -225,7 +226,7 @@ __global__ void k_visit_thread(const int32_t* __restrict__ cand, const DevScalar
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
     const int32_t u = cand[i];
     const int64_t e = (int64_t)off[u + 1];
-    for (int64_t j = (int64_t)off[u]; j < e; ++j) any |= op(u, adj[j]);
+    for (int64_t j = (int64_t)off[u]; j < e; ++j) any |= op(u, adj[j], j);
   }
   if (flag) wave_flag(any, flag);
 }
@@ -240,7 +241,7 @@ __global__ void k_visit_wave(const int32_t* __restrict__ big, const DevScalars* 
   for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < cnt; i += waves) {
     const int32_t u = big[i];
     const int64_t e = (int64_t)off[u + 1];
-    for (int64_t j = (int64_t)off[u] + lane; j < e; j += kWave) any |= op(u, adj[j]);
+    for (int64_t j = (int64_t)off[u] + lane; j < e; j += kWave) any |= op(u, adj[j], j);
   }
   if (flag) wave_flag(any, flag);
 }
@@ -253,7 +254,7 @@ __global__ void k_visit_block(int64_t n, const int32_t* __restrict__ big, const 
   for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
     const int32_t u = big[n - 1 - i];
     const int64_t e = (int64_t)off[u + 1];
-    for (int64_t j = (int64_t)off[u] + threadIdx.x; j < e; j += blockDim.x) any |= op(u, adj[j]);
+    for (int64_t j = (int64_t)off[u] + threadIdx.x; j < e; j += blockDim.x) any |= op(u, adj[j], j);
   }
   if (flag) wave_flag(any, flag);
 }
@@ -274,7 +275,8 @@ __global__ void k_visit_heavy(const int32_t* __restrict__ hlist, const int32_t* 
       if (e < T) {
         const int64_t i = heavy_owner_tile(hp, c, e0, e);
         const int32_t u = hlist[i];
-        any |= op(u, adj[(int64_t)off[u] + (e - hp[i])]);
+        const int64_t j = (int64_t)off[u] + (e - hp[i]);
+        any |= op(u, adj[j], j);
       }
     }
   }

@@ -51,6 +51,7 @@ struct cc_ctx {
   float* sel_dev = nullptr;          // the same memory as the device addresses it
   uint32_t sel_seq = 0;              // sequence number of the last selector call
   unsigned char* ring_host = nullptr;  // pinned: BFS progress snapshots (2 x 16 bytes)
+  void* amsf_host = nullptr;         // pinned: bucket histogram of the last AMSF call (allocated on first use)
   cc_stats last{};
   int round_limit = 0;  // 0: the built-in caps only
   // phase timing

@@ -20,7 +20,7 @@ constexpr int kRoundCap = 100000;
 struct SvHook {
   int32_t* P;
   const int32_t* prev;
-  __device__ __forceinline__ bool operator()(int32_t u, int32_t v) const {
+  __device__ __forceinline__ bool operator()(int32_t u, int32_t v, int64_t) const {
     const int32_t pu = ld(P + u), pv = ld(P + v);
     if (pu == pv) return false;
     const int32_t l = pu < pv ? pu : pv;
@@ -125,7 +125,7 @@ template <bool PARENT>
 struct LtConnect {
   int32_t* P;
   const int32_t* Q;
-  __device__ __forceinline__ bool operator()(int32_t v, int32_t w) const {
+  __device__ __forceinline__ bool operator()(int32_t v, int32_t w, int64_t) const {
     if (PARENT) {
       const int32_t pv = Q[v], pw = Q[w];
       if (pv == pw) return false;
@@ -236,7 +236,7 @@ __global__ void k_lt_connect_list(const int32_t* __restrict__ eu, const int32_t*
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c; i += stride) {
     const int32_t a = eu[i];
     if (a < 0) continue;
-    any |= op(a, ev[i]);
+    any |= op(a, ev[i], i);
   }
   wave_flag(any, flag);
 }

@@ -40,6 +40,18 @@ template <typename I> cc_status finish_lt(StaticArgs& a);
 
 // The whole static algorithm on prepared arguments (statistics recorded).
 cc_status static_run(StaticArgs& a);
+// Recompresses the labels, resolves the frequent label (exact counts) and
+// builds the degree-binned candidate lists of the vertices outside it.
+template <typename I> cc_status prepare_candidates(StaticArgs& a);
+// Final compression to canonical labels and the component count.
+cc_status output_labels(StaticArgs& a);
+// Writes the recorded forest edges (tree_e when given, then hook_e) densely
+// to out_u/out_v (and the hook weights to out_w when both are given);
+// *num_edges (device) receives the count.  `cnt` holds forest_tiles(len)
+// int32.
+cc_status forest_filter(hipStream_t s, int64_t n, const int2* tree, const int2* hook, const float* hook_w,
+                        int32_t* cnt, int32_t* out_u, int32_t* out_v, float* out_w, int64_t* num_edges);
+int64_t forest_tiles(int64_t len);
 // Synchronous read of the context's device scalars into ctx->host.
 cc_status pull_scalars(StaticArgs& a);
 

@@ -639,7 +639,7 @@ template <int ALG, int SPLICE, int FIND>
 struct UnionOp {
   int32_t* P;
   int2* hook;   // spanning forest: edge per hooked root (nullable)
-  __device__ __forceinline__ bool operator()(int32_t u, int32_t w) const {
+  __device__ __forceinline__ bool operator()(int32_t u, int32_t w, int64_t) const {
     forest_record(hook, unite<ALG, SPLICE, FIND>(P, u, w), u, w);
     return false;
   }
@@ -827,30 +827,58 @@ static cc_status run_static(StaticArgs& a, bool sample_only) {
   return run_tail<I>(a);
 }
 
+// Candidate lists of the vertices outside the frequent label (resolved in
+// the context scalars), binned by degree.
+template <typename I>
+cc_status compact_candidates(StaticArgs& a) {
+  PhaseScope ps(a.ctx, a.s, "compact");
+  // segment size: a multiple of 256 vertices, at most ~8192 segments
+  int64_t S = div_up(div_up(a.n, 8192), 256) * 256;
+  const int64_t nseg = div_up(a.n, S);
+  int32_t* segcnt = (int32_t*)(a.ws + a.L.seg);
+  long long* segedges = (long long*)(a.ws + a.L.seg + align256((size_t)kSegMax * 16));
+  const unsigned gw = grid_for(nseg * kWave, kBlock, 2048);
+  hipLaunchKernelGGL(k_compact_seg<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
+                     (const int32_t*)a.P, (const DevScalars*)a.ctx->dev, a.count, segcnt, segedges, vec_ok(a));
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, a.s, nseg, segcnt, (const long long*)segedges,
+                     a.ctx->dev);
+  hipLaunchKernelGGL(k_compact_gather<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
+                     (const int32_t*)a.count, (const int32_t*)segcnt, a.cand, a.big, a.heavy,
+                     (const DevScalars*)a.ctx->dev);
+  heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&a.ctx->dev->bin_count[3], a.hcap, (const I*)a.off, a.tsum, a.hp);
+  CC_LAUNCH_CHECK();
+  return CC_OK;
+}
+
+template <typename I>
+cc_status prepare_candidates(StaticArgs& a) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(a.n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, (uint32_t*)a.count,
+                     a.n, 0u);
+  cc_status st = compress_count_frequent<I>(a, true);
+  if (st != CC_OK) return st;
+  return compact_candidates<I>(a);
+}
+template cc_status prepare_candidates<int32_t>(StaticArgs&);
+template cc_status prepare_candidates<int64_t>(StaticArgs&);
+
+cc_status output_labels(StaticArgs& a) {
+  PhaseScope ps(a.ctx, a.s, "output");
+  // per-block root counts in the compaction area (free once the finish ran)
+  long long* part = (long long*)(a.ws + a.L.seg);
+  const unsigned nb = grid4(a.n);
+  hipLaunchKernelGGL(k_output, dim3(nb), dim3(kBlock), 0, a.s, a.n, a.P, part, vec_ok(a));
+  hipLaunchKernelGGL(k_output_sum, dim3(1), dim3(kBlock), 0, a.s, (const long long*)part, (int)nb, a.ctx->dev,
+                     (long long*)a.ncomp_user);
+  CC_LAUNCH_CHECK();
+  return CC_OK;
+}
+
 // Compaction, finish and output, on a parent array that already holds a
 // sampled labelling with its frequent label resolved in the context scalars.
 template <typename I>
 static cc_status run_tail(StaticArgs& a) {
-  cc_status st = CC_OK;
-  {
-    PhaseScope ps(a.ctx, a.s, "compact");
-    // segment size: a multiple of 256 vertices, at most ~8192 segments
-    int64_t S = div_up(div_up(a.n, 8192), 256) * 256;
-    const int64_t nseg = div_up(a.n, S);
-    int32_t* segcnt = (int32_t*)(a.ws + a.L.seg);
-    long long* segedges = (long long*)(a.ws + a.L.seg + align256((size_t)kSegMax * 16));
-    const unsigned gw = grid_for(nseg * kWave, kBlock, 2048);
-    hipLaunchKernelGGL(k_compact_seg<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
-                       (const int32_t*)a.P, (const DevScalars*)a.ctx->dev, a.count, segcnt, segedges, vec_ok(a));
-    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, a.s, nseg, segcnt, (const long long*)segedges,
-                       a.ctx->dev);
-    hipLaunchKernelGGL(k_compact_gather<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
-                       (const int32_t*)a.count, (const int32_t*)segcnt, a.cand, a.big, a.heavy,
-                       (const DevScalars*)a.ctx->dev);
-    heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&a.ctx->dev->bin_count[3], a.hcap, (const I*)a.off, a.tsum,
-                    a.hp);
-    CC_LAUNCH_CHECK();
-  }
+  cc_status st = compact_candidates<I>(a);
+  if (st != CC_OK) return st;
   a.finish_rounds = 0;
   {
     PhaseScope ps(a.ctx, a.s, "finish");
@@ -859,17 +887,7 @@ static cc_status run_tail(StaticArgs& a) {
     else st = uf_finish_dispatch<I>(a);
   }
   if (st != CC_OK) return st;
-  {
-    PhaseScope ps(a.ctx, a.s, "output");
-    // per-block root counts in the compaction area (free once the finish ran)
-    long long* part = (long long*)(a.ws + a.L.seg);
-    const unsigned nb = grid4(a.n);
-    hipLaunchKernelGGL(k_output, dim3(nb), dim3(kBlock), 0, a.s, a.n, a.P, part, vec_ok(a));
-    hipLaunchKernelGGL(k_output_sum, dim3(1), dim3(kBlock), 0, a.s, (const long long*)part, (int)nb, a.ctx->dev,
-                       (long long*)a.ncomp_user);
-    CC_LAUNCH_CHECK();
-  }
-  return CC_OK;
+  return output_labels(a);
 }
 
 
@@ -972,6 +990,7 @@ void cc_ctx_destroy(cc_ctx* ctx) {
   if (ctx->host) hipHostFree(ctx->host);
   if (ctx->sel_host) hipHostFree(ctx->sel_host);
   if (ctx->ring_host) hipHostFree(ctx->ring_host);
+  if (ctx->amsf_host) hipHostFree(ctx->amsf_host);
   delete ctx;
 }
 
