@@ -235,11 +235,12 @@ cc_status cc_spanning_forest_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* 
  * bucket counts above 4096 (the weight range spans more than
  * (1 + epsilon)^4096) return CC_EINVAL; a weight that is not finite and > 0
  * returns CC_EINVAL after the first pass.  The call synchronises hip_stream
- * twice (the weight range, then the bucket histogram).
+ * twice (after the light buckets are counted, and after the candidate lists
+ * of the later rounds are built).
  * workspace: device buffer of >= cc_amsf_workspace_bytes. */
 typedef struct {
   float epsilon;         /* bucket ratio - 1 (the paper's experiments: 0.25) */
-  float light_fraction;  /* share of entries handled from the bucket-sorted list */
+  float light_fraction;  /* share of entries handled from the bucket-sorted list (default 0.4) */
   uint64_t seed;         /* weight sample used to pick the light buckets */
 } cc_amsf_options;
 cc_status cc_amsf_default_options(cc_amsf_options* out);

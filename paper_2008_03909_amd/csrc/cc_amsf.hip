@@ -43,11 +43,10 @@ constexpr int kAmsfMaxBuckets = 4096;   // bucket table size (LDS)
 constexpr int kAmsfLightMax = 1024;     // light buckets at most
 constexpr int kAmsfTile = 4096;         // adjacency entries per tile of the two passes
 constexpr int kAmsfThreads = 512;       // block of the two passes
-constexpr int kAmsfWindow = 4096;       // row offsets of one tile kept in LDS
-constexpr int kAmsfPassGrid = 768;      // blocks of the two passes (3 per CU)
+constexpr int kAmsfPassGrid = 768;      // blocks of the two passes (3 per CU; at most 2048)
 constexpr int kAmsfRangeGrid = 1024;    // blocks of the weight-range pass
 constexpr int kAmsfSamples = 16384;     // weights sampled to pick the light buckets
-constexpr int kAmsfSeqMax = 16384;      // buckets this small share a single-block launch
+constexpr int kAmsfSeqMax = 2048;       // buckets this small share a single-block launch
 constexpr int kAmsfSeqThreads = 1024;
 constexpr uint64_t kTagAmsf = 0x616d7366ULL;  // "amsf"
 
@@ -66,8 +65,9 @@ static_assert(sizeof(AmsfScalars) == 256, "AmsfScalars is one 256-byte block");
 // Device block copied to the host in one transfer after the first pass.
 struct AmsfHostBlock {
   AmsfScalars sc;
-  long long lstart[kAmsfLightMax + 1];      // start of each light bucket in the sorted list, then the total
-  unsigned long long hist[kAmsfMaxBuckets];  // entries per bucket (both orientations)
+  long long lstart[kAmsfLightMax + 1];  // start of each light bucket in the sorted list, then the total
+  long long rowsum[kAmsfLightMax];      // light entries (u < v) per bucket
+  uint32_t shist[kAmsfMaxBuckets];      // sampled entries per bucket (kAmsfSamples in all)
 };
 
 // ---- weight range --------------------------------------------------------
@@ -97,12 +97,20 @@ __global__ void __launch_bounds__(kFBlock) k_amsf_range(int64_t m, const float* 
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (aligned) {
     const int64_t q = m / 4;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q; i += stride) {
-      const float4 x = ((const float4*)w)[i];
-      range_add(x.x, lo, hi, bad);
-      range_add(x.y, lo, hi, bad);
-      range_add(x.z, lo, hi, bad);
-      range_add(x.w, lo, hi, bad);
+    // four 16-byte loads in flight per thread
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q; i += 4 * stride) {
+      float4 x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        x[k] = i + k * stride < q ? ((const float4*)w)[i + k * stride] : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (i + k * stride >= q) continue;
+        range_add(x[k].x, lo, hi, bad);
+        range_add(x[k].y, lo, hi, bad);
+        range_add(x[k].z, lo, hi, bad);
+        range_add(x[k].w, lo, hi, bad);
+      }
     }
     for (int64_t i = 4 * q + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride)
       range_add(w[i], lo, hi, bad);
@@ -147,10 +155,11 @@ __device__ __forceinline__ int bucket_of(float x, const float* t, int nb, float 
 __global__ void __launch_bounds__(1024) k_amsf_setup(const RangePart* __restrict__ part, int nparts, double eps,
                                                      float light_fraction, uint64_t key, int64_t m,
                                                      const float* __restrict__ w, float* __restrict__ thr,
-                                                     AmsfScalars* as) {
+                                                     AmsfScalars* as, uint32_t* __restrict__ shist) {
   __shared__ float slo[1024 / kWave], shi[1024 / kWave];
   __shared__ uint32_t sbad[1024 / kWave];
   __shared__ uint32_t hist[kAmsfMaxBuckets];
+  __shared__ float ts[kAmsfMaxBuckets + 1];
   __shared__ int32_t s_nb;
   float lo = INFINITY, hi = 0.0f;
   uint32_t bad = 0;
@@ -204,17 +213,21 @@ __global__ void __launch_bounds__(1024) k_amsf_setup(const RangePart* __restrict
   }
   __syncthreads();
   const int nb = s_nb;
-  if (nb == 0 || light_fraction <= 0.0f) {
+  if (nb == 0) {
     if (threadIdx.x == 0) as->b0 = 0;
     return;
   }
   const float l2 = as->log2_wmin, ilr = as->inv_log2_ratio;
+  for (int i = threadIdx.x; i <= nb; i += blockDim.x) ts[i] = thr[i];
+  __syncthreads();
   for (int i = threadIdx.x; i < kAmsfSamples; i += blockDim.x) {
     const int64_t j = (int64_t)(sm_out(key, (uint64_t)i) % (uint64_t)m);
-    atomicAdd(&hist[bucket_of(w[j], thr, nb, l2, ilr)], 1u);
+    atomicAdd(&hist[bucket_of(w[j], ts, nb, l2, ilr)], 1u);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) shist[i] = hist[i];
+  if (threadIdx.x == 0 && light_fraction <= 0.0f) as->b0 = 0;
+  if (threadIdx.x == 0 && light_fraction > 0.0f) {
     const double budget = (double)light_fraction * kAmsfSamples;
     int32_t b0 = 0;
     uint32_t below = 0;  // samples in buckets < b0
@@ -236,12 +249,50 @@ __global__ void __launch_bounds__(kFBlock) k_amsf_tile_rows(int64_t n, const I* 
   }
 }
 
-// Pass A (SCATTER false): per-bucket entry counts into hist (both
-// orientations) and, for light buckets, the entries with u < v per block
-// into lpart[b * gridDim.x + block].  Pass B (SCATTER true): the same tiles
-// in the same order; each light entry with u < v goes to the sorted list at
-// its block's scanned offset for its bucket.  b0_arg < 0: read b0 from the
+// The light entries of the CSR, in two identical passes.  A block takes one
+// tile of kAmsfTile entries at a time; each thread owns kAmsfPer consecutive
+// entries.  Row ids come from the tile's row starts: every row r that begins
+// inside the tile marks its first position with r (atomicMax, so that of
+// several rows starting at one position the last, the non-empty one, wins),
+// and a block-wide running maximum carries the row to every entry; empty
+// rows cost nothing more.  The next tile's entries are loaded while the
+// current one is processed.
+//
+// Pass A (SCATTER false): per block, the light entries (weight below t[b0])
+// (u, v) with u < v of each light bucket into lpart[b * gridDim.x + block].
+// Pass B (SCATTER true): the same entries in the same blocks; each goes to
+// the sorted list at lstart[b] + lpart[b][block] (lpart scanned along each
+// bucket) plus its place inside the block.  b0_arg < 0: read b0 from the
 // device scalars.
+constexpr int kAmsfPer = kAmsfTile / kAmsfThreads;  // 8 entries per thread and tile
+static_assert(kAmsfPer == 8, "two 16-byte loads per thread");
+
+// A thread's kAmsfPer weights and neighbours of one tile (+inf weight past
+// the end of the adjacency).
+struct PassChunk {
+  float x[kAmsfPer];
+  int32_t v[kAmsfPer];
+};
+
+__device__ __forceinline__ void load_chunk(PassChunk& c, int64_t c0, int64_t E1, const float* w, const int32_t* adj,
+                                           int aligned) {
+  if (aligned && c0 + kAmsfPer <= E1) {
+    const float4 a0 = *(const float4*)(w + c0), a1 = *(const float4*)(w + c0 + 4);
+    const int4 b0 = *(const int4*)(adj + c0), b1 = *(const int4*)(adj + c0 + 4);
+    c.x[0] = a0.x, c.x[1] = a0.y, c.x[2] = a0.z, c.x[3] = a0.w;
+    c.x[4] = a1.x, c.x[5] = a1.y, c.x[6] = a1.z, c.x[7] = a1.w;
+    c.v[0] = b0.x, c.v[1] = b0.y, c.v[2] = b0.z, c.v[3] = b0.w;
+    c.v[4] = b1.x, c.v[5] = b1.y, c.v[6] = b1.z, c.v[7] = b1.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < kAmsfPer; ++i) {
+      const bool in = c0 + i < E1;
+      c.x[i] = in ? w[c0 + i] : INFINITY;
+      c.v[i] = in ? adj[c0 + i] : 0;
+    }
+  }
+}
+
 template <typename I, bool SCATTER>
 __global__ void __launch_bounds__(kAmsfThreads) k_amsf_pass(int64_t n, int64_t m, const I* __restrict__ off,
                                                             const int32_t* __restrict__ adj,
@@ -249,110 +300,143 @@ __global__ void __launch_bounds__(kAmsfThreads) k_amsf_pass(int64_t n, int64_t m
                                                             const float* __restrict__ thr, const AmsfScalars* as,
                                                             const int32_t* __restrict__ tile_row, int64_t ntiles,
                                                             int32_t b0_arg, long long* __restrict__ lpart,
-                                                            unsigned long long* __restrict__ hist,
-                                                            int2* __restrict__ luv, float* __restrict__ lw) {
-  __shared__ float t[kAmsfMaxBuckets + 1];
-  __shared__ int32_t win[kAmsfWindow];
-  __shared__ uint32_t hcnt[SCATTER ? 1 : kAmsfMaxBuckets];
+                                                            const long long* __restrict__ lstart,
+                                                            int2* __restrict__ luv, float* __restrict__ lw,
+                                                            int aligned) {
+  __shared__ float t[kAmsfLightMax + 1];
+  __shared__ int32_t starts[kAmsfTile];
   __shared__ int32_t lcnt[kAmsfLightMax];
+  __shared__ int32_t wmax[kAmsfThreads / kWave];
   const int nb = as->nb;
-  if (nb == 0) return;
-  const int b0 = b0_arg >= 0 ? b0_arg : as->b0;
+  const int b0 = nb == 0 ? 0 : (b0_arg >= 0 ? b0_arg : as->b0);
+  if (b0 == 0) return;
   const float l2 = as->log2_wmin, ilr = as->inv_log2_ratio;
-  for (int i = threadIdx.x; i <= nb; i += blockDim.x) t[i] = thr[i];
-  if (!SCATTER)
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) hcnt[i] = 0;
+  for (int i = threadIdx.x; i <= b0; i += blockDim.x) t[i] = thr[i];
   for (int i = threadIdx.x; i < b0; i += blockDim.x) lcnt[i] = 0;
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  int64_t k = blockIdx.x;
+  PassChunk cur, nxt;
+  int32_t r0 = 0, r1 = 0, nr0 = 0, nr1 = 0;
+  if (k < ntiles) {
+    const int64_t E0 = k * kAmsfTile, E1 = (E0 + kAmsfTile < m) ? E0 + kAmsfTile : m;
+    r0 = tile_row[k];
+    r1 = (k + 1 < ntiles) ? tile_row[k + 1] : (int32_t)(n - 1);
+    load_chunk(cur, E0 + (int64_t)kAmsfPer * threadIdx.x, E1, w, adj, aligned);
+  }
   __syncthreads();
-  for (int64_t k = blockIdx.x; k < ntiles; k += gridDim.x) {
+  const float tb0 = t[b0];
+  for (; k < ntiles; k += gridDim.x) {
     const int64_t E0 = k * kAmsfTile;
     const int64_t E1 = (E0 + kAmsfTile < m) ? E0 + kAmsfTile : m;
-    const int32_t r0 = tile_row[k];
-    const int32_t r1 = (k + 1 < ntiles) ? tile_row[k + 1] : (int32_t)(n - 1);
-    const int64_t wl = (int64_t)r1 - r0 + 2;  // offsets of rows r0 .. r1 + 1
-    const bool inwin = wl <= kAmsfWindow;
-    if (b0 > 0 && inwin)
-      for (int64_t i = threadIdx.x; i < wl; i += blockDim.x) {
-        const int64_t o = (int64_t)off[r0 + i] - E0;
-        win[i] = o < 0 ? 0 : (o > kAmsfTile + 1 ? kAmsfTile + 1 : (int32_t)o);
-      }
+    for (int i = threadIdx.x; i < kAmsfTile; i += blockDim.x) starts[i] = -1;
+    const int64_t kn = k + gridDim.x;
+    if (kn < ntiles) {
+      const int64_t F0 = kn * kAmsfTile, F1 = (F0 + kAmsfTile < m) ? F0 + kAmsfTile : m;
+      nr0 = tile_row[kn];
+      nr1 = (kn + 1 < ntiles) ? tile_row[kn + 1] : (int32_t)(n - 1);
+      load_chunk(nxt, F0 + (int64_t)kAmsfPer * threadIdx.x, F1, w, adj, aligned);
+    }
     __syncthreads();
-    for (int64_t e = E0 + threadIdx.x; e < E1; e += blockDim.x) {
-      const float x = w[e];
-      const int b = bucket_of(x, t, nb, l2, ilr);
-      if (!SCATTER) atomicAdd(&hcnt[b], 1u);
-      if (b < b0) {
-        const int32_t v = adj[e];
-        // owner row: the largest r in [r0, r1] whose row starts at or before e
-        int32_t u;
-        if (inwin) {
-          const int32_t rel = (int32_t)(e - E0);
-          int32_t lo = 0, hi = (int32_t)wl - 2;
-          while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (win[mid] <= rel) lo = mid;
-            else hi = mid - 1;
-          }
-          u = r0 + lo;
-        } else {
-          int32_t lo = r0, hi = r1;
-          while (lo < hi) {
-            const int32_t mid = (int32_t)(((int64_t)lo + hi + 1) >> 1);
-            if ((int64_t)off[mid] <= e) lo = mid;
-            else hi = mid - 1;
-          }
-          u = lo;
-        }
-        if (u < v) {
-          const int32_t q = atomicAdd(&lcnt[b], 1);
-          if (SCATTER) {
-            const long long p = lpart[(int64_t)b * gridDim.x + blockIdx.x] + q;
-            luv[p] = make_int2(u, v);
-            lw[p] = x;
-          }
+    if (threadIdx.x == 0) atomicMax(&starts[0], r0);
+    for (int64_t r = (int64_t)r0 + 1 + threadIdx.x; r <= r1; r += blockDim.x) {
+      const int64_t o = (int64_t)off[r];
+      if (o < E1) atomicMax(&starts[o - E0], (int32_t)r);
+    }
+    __syncthreads();
+    // running maximum over the tile: thread-local over its kAmsfPer
+    // positions, then an exclusive maximum over the threads before it
+    int32_t row[kAmsfPer];
+    int32_t run = -1;
+#pragma unroll
+    for (int i = 0; i < kAmsfPer; ++i) {
+      const int32_t sv = starts[kAmsfPer * threadIdx.x + i];
+      run = sv > run ? sv : run;
+      row[i] = run;
+    }
+    int32_t inc = run;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int32_t y = __shfl_up(inc, o, kWave);
+      if (lane >= o) inc = y > inc ? y : inc;
+    }
+    if (lane == kWave - 1) wmax[wv] = inc;
+    int32_t carry = __shfl_up(inc, 1, kWave);
+    if (lane == 0) carry = -1;
+    __syncthreads();
+    for (int q = 0; q < wv; ++q) carry = wmax[q] > carry ? wmax[q] : carry;
+    const int64_t c0 = E0 + (int64_t)kAmsfPer * threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < kAmsfPer; ++i) {
+      const int32_t u = row[i] > carry ? row[i] : carry;
+      if (c0 + i < E1 && cur.x[i] < tb0 && u < cur.v[i]) {
+        const int b = bucket_of(cur.x[i], t, b0, l2, ilr);
+        const int32_t q = atomicAdd(&lcnt[b], 1);
+        if (SCATTER) {
+          const long long p = lstart[b] + lpart[(int64_t)b * gridDim.x + blockIdx.x] + q;
+          luv[p] = make_int2(u, cur.v[i]);
+          lw[p] = cur.x[i];
         }
       }
     }
     __syncthreads();
+    cur = nxt;
+    r0 = nr0;
+    r1 = nr1;
   }
-  if (!SCATTER) {
-    for (int i = threadIdx.x; i < nb; i += blockDim.x)
-      if (hcnt[i]) atomicAdd(hist + i, (unsigned long long)hcnt[i]);
+  if (!SCATTER)
     for (int i = threadIdx.x; i < b0; i += blockDim.x) lpart[(int64_t)i * gridDim.x + blockIdx.x] = lcnt[i];
-  }
 }
 
-// One block: exclusive scan of lpart in bucket-major order (b0 * G counts),
-// in place; lstart[b] = first position of bucket b, lstart[b0] = total.
-__global__ void __launch_bounds__(1024) k_amsf_light_scan(long long* lpart, int G, const AmsfScalars* as,
-                                                          long long* __restrict__ lstart) {
+// Block b < b0: exclusive scan of bucket b's per-block counts (G <= 2048,
+// two consecutive counts per thread) in place, the bucket's total to
+// rowsum[b].
+__global__ void __launch_bounds__(1024) k_amsf_row_scan(long long* lpart, int G, const AmsfScalars* as,
+                                                        long long* __restrict__ rowsum) {
   __shared__ long long wsum[1024 / kWave];
-  const int b0 = as->nb > 0 ? as->b0 : 0;
-  const int64_t L = (int64_t)b0 * G;
+  const int b = blockIdx.x;
+  if (as->nb == 0 || b >= as->b0) return;
   const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
-  const int64_t per = (L + 1023) / 1024;
-  const int64_t lo = t * per < L ? t * per : L;
-  const int64_t hi = lo + per < L ? lo + per : L;
-  long long s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += lpart[i];
-  long long inc = s;
+  long long* row = lpart + (int64_t)b * G;
+  const long long x0 = 2 * t < G ? row[2 * t] : 0;
+  const long long x1 = 2 * t + 1 < G ? row[2 * t + 1] : 0;
+  const long long x = x0 + x1;
+  long long inc = x;
   for (int o = 1; o < kWave; o <<= 1) {
     const long long y = __shfl_up(inc, o, kWave);
     if (lane >= o) inc += y;
   }
   if (lane == kWave - 1) wsum[wv] = inc;
   __syncthreads();
-  long long run = inc - s, total = 0;
+  long long before = 0, total = 0;
   for (int q = 0; q < 1024 / kWave; ++q) {
-    if (q < wv) run += wsum[q];
+    if (q < wv) before += wsum[q];
     total += wsum[q];
   }
-  for (int64_t i = lo; i < hi; ++i) {
-    const long long x = lpart[i];
-    lpart[i] = run;
-    if (i % G == 0) lstart[i / G] = run;
-    run += x;
+  const long long ex = before + inc - x;
+  if (2 * t < G) row[2 * t] = ex;
+  if (2 * t + 1 < G) row[2 * t + 1] = ex + x0;
+  if (t == 0) rowsum[b] = total;
+}
+
+// One block: lstart[b] = sum of rowsum[b'] for b' < b, lstart[b0] = total.
+__global__ void __launch_bounds__(1024) k_amsf_lstart(const AmsfScalars* as, const long long* __restrict__ rowsum,
+                                                      long long* __restrict__ lstart) {
+  __shared__ long long wsum[1024 / kWave];
+  const int b0 = as->nb > 0 ? as->b0 : 0;
+  const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
+  const long long x = t < b0 ? rowsum[t] : 0;
+  long long inc = x;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const long long y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
   }
+  if (lane == kWave - 1) wsum[wv] = inc;
+  __syncthreads();
+  long long before = 0, total = 0;
+  for (int q = 0; q < 1024 / kWave; ++q) {
+    if (q < wv) before += wsum[q];
+    total += wsum[q];
+  }
+  if (t < b0) lstart[t] = before + inc - x;
   if (t == 0) lstart[b0] = total;
 }
 
@@ -413,6 +497,109 @@ struct AmsfRoundOp {
   }
 };
 
+// One round over the low-degree candidates (degree <= kThrWave, one thread
+// each), fused with the largest-component test: a candidate whose root is
+// now the root of L_max is dropped (its edges to other components are seen
+// from their other endpoints); the others visit their entries of bucket b
+// and stay on the list for the next round.  Each block takes kAmsfRoundTile
+// consecutive list entries and appends its survivors with one atomic.  The
+// list lengths rotate through three counters: round r reads cnt[r % 3],
+// appends to cnt[(r + 1) % 3] and clears cnt[(r + 2) % 3] for round r + 1.
+constexpr int kAmsfRoundThreads = 1024;
+constexpr int kAmsfRoundPer = 4;
+constexpr int kAmsfRoundTile = kAmsfRoundThreads * kAmsfRoundPer;
+
+template <typename I>
+__global__ void __launch_bounds__(kAmsfRoundThreads) k_amsf_round(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                                  uint32_t* cnt, int r, const I* __restrict__ off,
+                                                                  const int32_t* __restrict__ adj,
+                                                                  const float* __restrict__ w,
+                                                                  const float* __restrict__ thr, int b, int32_t* P,
+                                                                  int32_t L, int2* hook, float* hookw) {
+  __shared__ int32_t wsum[kAmsfRoundThreads / kWave];
+  __shared__ uint32_t s_base;
+  const uint32_t c = cnt[r % 3];
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[(r + 2) % 3] = 0u;
+  const int64_t base = (int64_t)blockIdx.x * kAmsfRoundTile;
+  if (base >= (int64_t)c) return;
+  const float lo = thr[b], hi = thr[b + 1];
+  __shared__ int32_t s_lroot;
+  if (threadIdx.x == 0) s_lroot = find_naive(P, L);
+  // the loads of a thread's kAmsfRoundPer candidates are issued stage by
+  // stage, so that their latencies overlap
+  int32_t u[kAmsfRoundPer], p[kAmsfRoundPer], pp[kAmsfRoundPer];
+#pragma unroll
+  for (int q = 0; q < kAmsfRoundPer; ++q) {
+    const int64_t i = base + q * kAmsfRoundThreads + threadIdx.x;
+    u[q] = i < (int64_t)c ? in[i] : -1;
+  }
+#pragma unroll
+  for (int q = 0; q < kAmsfRoundPer; ++q) p[q] = u[q] >= 0 ? ld(P + u[q]) : -1;
+#pragma unroll
+  for (int q = 0; q < kAmsfRoundPer; ++q) pp[q] = (u[q] >= 0 && p[q] != u[q]) ? ld(P + p[q]) : p[q];
+  __syncthreads();
+  const int32_t lroot = s_lroot;
+  int32_t keep[kAmsfRoundPer];
+  int64_t rs[kAmsfRoundPer], re[kAmsfRoundPer];
+  int nk = 0;
+#pragma unroll
+  for (int q = 0; q < kAmsfRoundPer; ++q) {
+    keep[q] = -1;
+    rs[q] = re[q] = 0;
+    if (u[q] < 0) continue;
+    int32_t ru = p[q];
+    if (p[q] != u[q]) {
+      ru = pp[q] == p[q] ? p[q] : find_naive(P, pp[q]);
+      if (ru != p[q]) st(P + u[q], ru);  // shortcut, as the compress step would
+    }
+    if (ru == lroot) continue;
+    keep[q] = u[q];
+    ++nk;
+  }
+#pragma unroll
+  for (int q = 0; q < kAmsfRoundPer; ++q)
+    if (keep[q] >= 0) {
+      rs[q] = (int64_t)off[keep[q]];
+      re[q] = (int64_t)off[keep[q] + 1];
+    }
+#pragma unroll
+  for (int q = 0; q < kAmsfRoundPer; ++q)
+    for (int64_t j = rs[q]; j < re[q]; ++j) {
+      const float x = w[j];
+      if (x >= lo && x < hi) amsf_unite(P, keep[q], adj[j], x, hook, hookw);
+    }
+  // block-wide exclusive scan of the survivors, one atomic per block
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  int32_t inc = nk;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) wsum[wv] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int q = 0; q < kAmsfRoundThreads / kWave; ++q) {
+      const int32_t x = wsum[q];
+      wsum[q] = (int32_t)tot;
+      tot += (uint32_t)x;
+    }
+    s_base = tot ? atomicAdd(cnt + (r + 1) % 3, tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t pos = s_base + (uint32_t)wsum[wv] + (uint32_t)(inc - nk);
+#pragma unroll
+  for (int q = 0; q < kAmsfRoundPer; ++q)
+    if (keep[q] >= 0) out[pos++] = keep[q];
+}
+
+// Round counters: the thread-bin candidate count into cnt[0], the others 0.
+__global__ void k_amsf_round_init(const DevScalars* sc, uint32_t* cnt) {
+  cnt[0] = (uint32_t)sc->bin_count[0];
+  cnt[1] = 0u;
+  cnt[2] = 0u;
+}
+
 // ---- total weight --------------------------------------------------------------
 
 __global__ void __launch_bounds__(kFBlock) k_amsf_weight(const float* __restrict__ ew, const long long* num_edges,
@@ -445,7 +632,7 @@ __global__ void __launch_bounds__(kFBlock) k_amsf_weight_sum(const double* __res
   }
 }
 
-constexpr int kAmsfWeightGrid = 256;
+constexpr int kAmsfWeightGrid = 1024;
 
 // ---- host ------------------------------------------------------------------------
 
@@ -516,30 +703,31 @@ static cc_status amsf_run(StaticArgs& a, const AmsfLayout& L, const float* w, co
   float* lw = (float*)(ws + L.lw);
   const int64_t n = a.n, m = a.m;
   const unsigned G = (unsigned)std::min<int64_t>(std::max<int64_t>(L.ntiles, 1), kAmsfPassGrid);
+  const int aligned = (((uintptr_t)w | (uintptr_t)a.adj) & 15u) == 0;
   {
     PhaseScope ps(a.ctx, a.s, "init");
     hipLaunchKernelGGL(k_amsf_iota, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, a.P);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 * n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, (uint32_t*)a.hook_e,
                        2 * n, 0xffffffffu);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(kAmsfMaxBuckets * 2, kFBlock, 64)), dim3(kFBlock), 0, a.s,
-                       (uint32_t*)hb->hist, (int64_t)kAmsfMaxBuckets * 2, 0u);
     CC_LAUNCH_CHECK();
   }
   {
     PhaseScope ps(a.ctx, a.s, "amsf_buckets");
     RangePart* part = (RangePart*)(ws + L.range);
-    const int aligned = ((uintptr_t)w & 15u) == 0;
     const unsigned gr = grid_for(std::max<int64_t>(div_up(m, 4), 1), kFBlock, kAmsfRangeGrid);
-    hipLaunchKernelGGL(k_amsf_range, dim3(gr), dim3(kFBlock), 0, a.s, m, w, aligned, part);
+    hipLaunchKernelGGL(k_amsf_range, dim3(gr), dim3(kFBlock), 0, a.s, m, w, (int)(((uintptr_t)w & 15u) == 0), part);
     hipLaunchKernelGGL(k_amsf_setup, dim3(1), dim3(1024), 0, a.s, (const RangePart*)part, (int)gr,
-                       (double)opt->epsilon, opt->light_fraction, sm_out(opt->seed, kTagAmsf), m, w, thr, as);
+                       (double)opt->epsilon, opt->light_fraction, sm_out(opt->seed, kTagAmsf), m, w, thr, as,
+                       hb->shist);
     hipLaunchKernelGGL(k_amsf_tile_rows<I>, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n,
                        (const I*)a.off, tile_row);
     hipLaunchKernelGGL((k_amsf_pass<I, false>), dim3(G), dim3(kAmsfThreads), 0, a.s, n, m, (const I*)a.off, a.adj,
                        w, (const float*)thr, (const AmsfScalars*)as, (const int32_t*)tile_row, L.ntiles, -1, lpart,
-                       hb->hist, (int2*)nullptr, (float*)nullptr);
-    hipLaunchKernelGGL(k_amsf_light_scan, dim3(1), dim3(1024), 0, a.s, lpart, (int)G, (const AmsfScalars*)as,
-                       hb->lstart);
+                       (const long long*)nullptr, (int2*)nullptr, (float*)nullptr, aligned);
+    hipLaunchKernelGGL(k_amsf_row_scan, dim3(kAmsfLightMax), dim3(1024), 0, a.s, lpart, (int)G,
+                       (const AmsfScalars*)as, hb->rowsum);
+    hipLaunchKernelGGL(k_amsf_lstart, dim3(1), dim3(1024), 0, a.s, (const AmsfScalars*)as,
+                       (const long long*)hb->rowsum, hb->lstart);
     CC_LAUNCH_CHECK();
     CC_HIP(hipMemcpyAsync(hb_host, hb, sizeof(AmsfHostBlock), hipMemcpyDeviceToHost, a.s));
     CC_HIP(hipStreamSynchronize(a.s));
@@ -559,7 +747,7 @@ static cc_status amsf_run(StaticArgs& a, const AmsfLayout& L, const float* w, co
     if (b0 > 0) {
       hipLaunchKernelGGL((k_amsf_pass<I, true>), dim3(G), dim3(kAmsfThreads), 0, a.s, n, m, (const I*)a.off, a.adj,
                          w, (const float*)thr, (const AmsfScalars*)as, (const int32_t*)tile_row, L.ntiles, b0, lpart,
-                         (unsigned long long*)nullptr, luv, lw);
+                         (const long long*)hb->lstart, luv, lw, aligned);
       int b = 0;
       while (b < b0) {
         const long long c = hb_host->lstart[b + 1] - hb_host->lstart[b];
@@ -582,20 +770,37 @@ static cc_status amsf_run(StaticArgs& a, const AmsfLayout& L, const float* w, co
   a.finish_rounds = 0;
   if (b0 < nb) {
     PhaseScope ps(a.ctx, a.s, "amsf_rounds");
-    const long long refresh = std::max<long long>(m / 32, 1);
-    long long since = refresh;  // build the candidate lists before the first round
+    // Candidate lists of the vertices outside L_max, built once; the
+    // low-degree list then shrinks round by round as its vertices join
+    // L_max, the short lists of higher-degree vertices are kept as built.
+    cc_status st = prepare_candidates<I>(a);
+    if (st != CC_OK) return st;
+    CC_HIP(hipMemcpyAsync(a.ctx->host, a.ctx->dev, sizeof(DevScalars), hipMemcpyDeviceToHost, a.s));
+    CC_HIP(hipStreamSynchronize(a.s));
+    const DevScalars hsc = *a.ctx->host;
+    uint32_t* rcnt = &as->pad[0];
+    hipLaunchKernelGGL(k_amsf_round_init, dim3(1), dim3(1), 0, a.s, (const DevScalars*)a.ctx->dev, rcnt);
+    const CandLists cl = a.lists();
+    const I* offI = (const I*)a.off;
+    int32_t* lists[2] = {a.cand, a.count};
+    const unsigned gthr = (unsigned)std::max<int64_t>(div_up(hsc.bin_count[0], kAmsfRoundTile), 1);
     for (int b = b0; b < nb; ++b) {
-      const long long c = (long long)hb_host->hist[b];
-      if (c == 0) continue;
-      if (since >= refresh) {
-        cc_status st = prepare_candidates<I>(a);
-        if (st != CC_OK) return st;
-        since = 0;
-      }
-      visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj,
-                       AmsfRoundOp{a.P, w, (const float*)thr, b, a.hook_e, hookw}, (uint32_t*)nullptr);
+      const int r = b - b0;
+      const AmsfRoundOp op{a.P, w, (const float*)thr, b, a.hook_e, hookw};
+      if (hsc.bin_count[0] > 0)
+        hipLaunchKernelGGL(k_amsf_round<I>, dim3(gthr), dim3(kAmsfRoundThreads), 0, a.s,
+                           (const int32_t*)lists[r & 1], lists[(r + 1) & 1], rcnt, r, offI, a.adj, w,
+                           (const float*)thr, b, a.P, hsc.lmax, a.hook_e, hookw);
+      if (hsc.bin_count[1] > 0)
+        hipLaunchKernelGGL((k_visit_wave<AmsfRoundOp, I>), dim3(grid_for((int64_t)hsc.bin_count[1] * kWave, kFBlock, 2048)),
+                           dim3(kFBlock), 0, a.s, cl.big, cl.sc, offI, a.adj, op, (uint32_t*)nullptr);
+      if (hsc.bin_count[2] > 0)
+        hipLaunchKernelGGL((k_visit_block<AmsfRoundOp, I>), dim3(1024), dim3(kFBlock), 0, a.s, cl.n, cl.big, cl.sc,
+                           offI, a.adj, op, (uint32_t*)nullptr);
+      if (hsc.bin_count[3] > 0)
+        hipLaunchKernelGGL((k_visit_heavy<AmsfRoundOp, I>), dim3(2048), dim3(kFBlock), 0, a.s, cl.heavy,
+                           &cl.sc->bin_count[3], cl.hp, offI, a.adj, op, (uint32_t*)nullptr);
       CC_LAUNCH_CHECK();
-      since += c;
       ++a.finish_rounds;
     }
   }
@@ -624,7 +829,7 @@ extern "C" {
 cc_status cc_amsf_default_options(cc_amsf_options* out) {
   if (!out) return fail(CC_EINVAL, "out is NULL");
   out->epsilon = 0.25f;
-  out->light_fraction = 0.125f;
+  out->light_fraction = 0.4f;
   out->seed = 0x5eedULL;
   return CC_OK;
 }

@@ -134,12 +134,16 @@ __device__ __forceinline__ int32_t union_async(int32_t* P, int32_t u, int32_t v)
 // SpliceAtomic).  After a successful hook the non-naive compress options
 // re-run their find on both endpoints.  Returns the root this call hooked
 // (the spanning-forest slot of edge (u, v)), or -1 if it linked nothing.
+// union_rem_from takes the parents of u and v already read by the caller
+// (so that a caller can overlap those loads across several edges).
 template <int SPLICE, int FIND>
-__device__ __forceinline__ int32_t union_rem(int32_t* P, int32_t u, int32_t v) {
+__device__ __forceinline__ int32_t union_rem_from(int32_t* P, int32_t u, int32_t v, int32_t pu0, int32_t pv0) {
   int32_t ru = u, rv = v;
+  bool first = true;
   while (true) {
-    int32_t pu = ld(P + ru);
-    int32_t pv = ld(P + rv);
+    int32_t pu = first ? pu0 : ld(P + ru);
+    int32_t pv = first ? pv0 : ld(P + rv);
+    first = false;
     if (pu == pv) return -1;
     if (pu < pv) {
       int32_t t = ru;
@@ -171,6 +175,11 @@ __device__ __forceinline__ int32_t union_rem(int32_t* P, int32_t u, int32_t v) {
       ru = (SPLICE == kSplitOne) ? pu : w;
     }
   }
+}
+
+template <int SPLICE, int FIND>
+__device__ __forceinline__ int32_t union_rem(int32_t* P, int32_t u, int32_t v) {
+  return union_rem_from<SPLICE, FIND>(P, u, v, ld(P + u), ld(P + v));
 }
 
 // Union dispatch.  ALG 0 = Rem-CAS (SPLICE, FIND), 1 = Async (FIND).

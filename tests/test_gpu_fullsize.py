@@ -66,3 +66,39 @@ def test_rmat_2_27_int64_offsets(ctx):
     vs = b.all_variants()
     d = _check(ctx, g, [b.default_variant(), vs[44], vs[79]], o64=True)
     assert d.offsets.dtype == torch.int64
+
+
+def test_amsf_rmat_2_24(ctx):
+    """Approximate MSF (Section 5.1) on R-MAT 2^24 with exponential weights of
+    mean 1, eps = 0.25: labels equal the oracle's, the forest is valid, every
+    returned weight is its edge's weight, and the per-bucket forest edge
+    counts equal the oracle's bucketed Kruskal (which makes the forest a
+    minimum one for the rounded weights, hence within 1 + eps of the
+    minimum).  The oracle works from the generator's pair list."""
+    g = inputs.workload_rmat(24, 8, seed=2)
+    dev = ctx.torch_device
+    d = b.build_csr(ctx, g.n, torch.from_numpy(g.u).to(dev), torch.from_numpy(g.v).to(dev))
+    off_d = d.offsets.cpu().numpy()
+    rows_d = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(off_d))
+    wt = torch.from_numpy(inputs.pair_weights(g.n, rows_d, d.adj.cpu().numpy(), seed=77)).to(dev)
+    del rows_d, off_d
+    keep = g.u != g.v
+    pu, pv = g.u[keep], g.v[keep]
+    pw = inputs.pair_weights(g.n, pu, pv, seed=77)
+    _note("oracle: labels, csr, buckets")
+    want, wc = oracle.uf_cc(g.n, g.u, g.v)
+    off, adj = oracle.csr_build(g.n, g.u, g.v, True)
+    t, cnt = oracle.amsf_buckets(g.n, pu, pv, pw, 0.25)
+    for lf in (b.amsf_options().light_fraction, 0.0):
+        _note(f"amsf rmat24 light_fraction={lf}")
+        lab, eu, ev, ew, ne, tw = b.amsf_csr(ctx, d, wt, b.amsf_options(epsilon=0.25, light_fraction=lf))
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        k = int(ne.item())
+        fu, fv, fw = eu[:k].cpu().numpy(), ev[:k].cpu().numpy(), ew[:k].cpu().numpy()
+        assert np.array_equal(lab.cpu().numpy(), want) and k == g.n - wc, lf
+        assert oracle.forest_check_csr(g.n, off, adj, want, fu, fv) == oracle.FOREST_OK, lf
+        assert np.array_equal(fw, inputs.pair_weights(g.n, fu, fv, seed=77)), lf
+        fb = np.searchsorted(t, fw, side="right") - 1
+        assert np.array_equal(np.bincount(fb, minlength=len(cnt)), cnt), lf
+        assert abs(float(tw.item()) - float(np.sum(fw, dtype=np.float64))) < 1e-6 * float(tw.item())
