@@ -263,12 +263,19 @@ cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t*
                        void* workspace, size_t ws_bytes, void* offsets_out, int offsets_64bit, int32_t* adj_out,
                        int64_t* m_dev, void* hip_stream);
 
-/* ---- batch-incremental connectivity (Section 3.4) -----------------------------
+/* ---- batch-incremental connectivity (Section 3.4 "Streaming") ---------------
  * A cc_stream owns an n x int32 parent array on the device (allocated by
  * cc_stream_create, freed by cc_stream_destroy), starting from the empty
- * graph.  Accepted finishes: UF-Async (any find) and UF-Rem-CAS (any
- * splice, non-compress find).  On one cc_stream, a query batch reflects
- * exactly the insert batches enqueued before it in stream order. */
+ * graph.  Every finish is accepted; it decides the streaming type (Section
+ * 3.4): type 1 = UF-Async (any find) and UF-Rem-CAS with SplitAtomicOne or
+ * HalveAtomicOne (inserts and queries may run concurrently); type 2 = SV
+ * and the root-based LT variants (inserts in synchronous rounds over the
+ * batch; these streams also own an n x int32 snapshot and an edge list
+ * that grows, with hipMalloc, to the largest batch seen); type 3 =
+ * UF-Rem-CAS with SpliceAtomic (phase-concurrent).  NULL v: UF-Async with
+ * FindNaive.  On one cc_stream, every batch reflects exactly the batches
+ * enqueued before it in stream order.  Type-2 inserts synchronise
+ * hip_stream once per round. */
 cc_status cc_stream_create(cc_ctx* ctx, int64_t n, const cc_variant* v, cc_stream** out);
 void cc_stream_destroy(cc_stream* s);
 /* Initialize(G): the static algorithm on a symmetric CSR, result kept as the
@@ -280,6 +287,19 @@ cc_status cc_insert_batch(cc_stream* s, int64_t k, const int32_t* u, const int32
 /* out[i] = IsConnected(a[i], b[i]) as 0/1 bytes (device arrays). */
 cc_status cc_query_batch(cc_stream* s, int64_t q, const int32_t* a, const int32_t* b, uint8_t* out,
                          void* hip_stream);
+/* One mixed batch (the streaming appendix's ProcessBatch): for i < k,
+ * kind[i] == 0 is Insert(u[i], v[i]) and any other kind is IsConnected(u[i],
+ * v[i]), answered in out[i] (0/1; 0 for inserts); all device arrays.  The
+ * answers are linearizable with respect to the batch's inserts: a query
+ * answers 1 if its endpoints were connected before the batch and 0 if they
+ * are not connected after it.  Type 1 runs inserts and queries together in
+ * one kernel (queries are Jayanti-Tarjan SameSet); types 2 and 3 run the
+ * inserts first, then the queries.  Ids outside [0, n) set the error word
+ * and the operation is skipped (answer 0). */
+cc_status cc_process_batch(cc_stream* s, int64_t k, const uint8_t* kind, const int32_t* u, const int32_t* v,
+                           uint8_t* out, void* hip_stream);
+/* The stream's type (1, 2 or 3 as above; 0 for NULL). */
+int32_t cc_stream_type(const cc_stream* s);
 /* Canonical labels of the current state (labels_out: n int32 device). */
 cc_status cc_stream_labels(cc_stream* s, int32_t* labels_out, int64_t* num_components_dev, void* hip_stream);
 /* Synchronises and reports (then clears) the stream's device error word. */

@@ -141,6 +141,8 @@ def lib():
             "cc_insert_batch": (_int, [_vp, _i64, _vp, _vp, _vp]),
             "cc_query_batch": (_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
             "cc_stream_labels": (_int, [_vp, _vp, _vp, _vp]),
+            "cc_process_batch": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+            "cc_stream_type": (ctypes.c_int32, [_vp]),
             "cc_stream_sync_status": (_int, [_vp]),
             "cc_server_create": (_int, [_vp, _i64, ctypes.POINTER(cc_variant), _i64, _int, _int, ctypes.POINTER(_vp)]),
             "cc_server_destroy": (None, [_vp]),
@@ -489,6 +491,29 @@ class Stream:
         _check(lib().cc_query_batch(self.h, int(a.numel()), _ptr(a), _ptr(b), _ptr(out), _stream_handle(stream)),
                "cc_query_batch")
         return out
+
+    def process(self, kind, u, v, out: torch.Tensor | None = None, stream=None):
+        """cc_process_batch: one mixed batch; kind[i] == 0 inserts (u[i], v[i]),
+        any other kind asks IsConnected(u[i], v[i]).  Returns the device
+        uint8 answers (0 for inserts)."""
+        dev = self.ctx.torch_device
+        kd = _dev_tensor(kind, torch.uint8, dev)
+        u = _dev_tensor(u, torch.int32, dev)
+        v = _dev_tensor(v, torch.int32, dev)
+        if not (kd.numel() == u.numel() == v.numel()):
+            raise ValueError("kind, u and v differ in length")
+        if out is None:
+            out = torch.empty(int(u.numel()), dtype=torch.uint8, device=dev)
+        elif out.dtype != torch.uint8 or out.numel() < u.numel():
+            raise ValueError("out must be a uint8 tensor with one byte per operation")
+        _check(lib().cc_process_batch(self.h, int(u.numel()), _ptr(kd), _ptr(u), _ptr(v), _ptr(out),
+                                      _stream_handle(stream)), "cc_process_batch")
+        return out
+
+    @property
+    def type(self) -> int:
+        """Streaming type of the finish: 1, 2 or 3 (Section 3.4)."""
+        return int(lib().cc_stream_type(self.h))
 
     def labels(self, stream=None):
         dev = self.ctx.torch_device

@@ -227,9 +227,9 @@ __global__ void __launch_bounds__(kFBlock) k_lt_emit(int64_t n, const int32_t* _
   }
 }
 
-template <bool PARENT>
-__global__ void k_lt_connect_list(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
-                                  const unsigned long long* cnt, LtConnect<PARENT> op, uint32_t* flag) {
+template <class Op>
+__global__ void k_edge_list(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                            const unsigned long long* cnt, Op op, uint32_t* flag) {
   const int64_t c = (int64_t)*cnt;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool any = false;
@@ -292,7 +292,7 @@ static cc_status lt_rounds(StaticArgs& a) {
     hipLaunchKernelGGL(k_copy_i32, dim3(g), dim3(kFBlock), 0, a.s, a.n, (const int32_t*)a.P, Q);
     LtConnect<PARENT> op{a.P, Q};
     if (alter) {
-      hipLaunchKernelGGL(k_lt_connect_list<PARENT>, dim3(grid_for(a.m, kFBlock, 8192)), dim3(kFBlock), 0, a.s,
+      hipLaunchKernelGGL(k_edge_list<LtConnect<PARENT>>, dim3(grid_for(a.m, kFBlock, 8192)), dim3(kFBlock), 0, a.s,
                          (const int32_t*)eu, (const int32_t*)ev, (const unsigned long long*)ecnt, op, &sc->changed);
     } else {
       visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, op, &sc->changed);
@@ -309,6 +309,55 @@ static cc_status lt_rounds(StaticArgs& a) {
     cc_status st = read_flag(a, &changed);
     if (st != CC_OK) return st;
     if (!changed) break;
+  }
+  return CC_OK;
+}
+
+// Rounds of SV or a root-based LT variant over an explicit edge list
+// (eu[i] < 0: dead entry; *ecnt entries on the device, at most cap): the
+// batch-insert step of a stream whose finish is SV or LT (the paper's
+// type-2 streaming algorithms, which must process insertions in batches).
+// P is the stream's min-based forest; Q is n int32 of scratch for the
+// round snapshot.  Alter rewrites eu/ev.  Synchronises s once per round.
+cc_status edge_list_rounds(cc_ctx* ctx, hipStream_t s, const cc_variant& v, int64_t n, int32_t* P, int32_t* Q,
+                           int32_t* eu, int32_t* ev, const unsigned long long* ecnt, int64_t cap, int32_t* rounds) {
+  DevScalars* sc = ctx->dev;
+  const unsigned g = grid_for(n, kFBlock, 4096);
+  const unsigned ge = grid_for(cap, kFBlock, 8192);
+  const bool sv = v.finish == CC_FIN_SV;
+  const bool parent = (v.lt_rules & 3u) == CC_LT_PARENT_CONNECT;
+  const bool full = v.lt_rules & CC_LT_FULL_SHORTCUT;
+  const bool alter = v.lt_rules & CC_LT_ALTER;
+  *rounds = 0;
+  // SV hooks only roots of the round-start snapshot: start from a flat forest
+  if (sv) hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, s, n, P, Q, (uint32_t*)nullptr);
+  for (int round = 0;; ++round) {
+    if (round >= kRoundCap) return fail(CC_ELIVELOCK, "batch rounds exceeded %d", kRoundCap);
+    if (ctx->round_limit > 0 && round >= ctx->round_limit)
+      return fail(CC_ELIVELOCK, "batch rounds reached the context's round limit (%d)", ctx->round_limit);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, &sc->changed, 0u);
+    if (sv) {
+      hipLaunchKernelGGL(k_edge_list<SvHook>, dim3(ge), dim3(kFBlock), 0, s, (const int32_t*)eu, (const int32_t*)ev,
+                         ecnt, SvHook{P, Q}, &sc->changed);
+      hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, s, n, P, Q, (uint32_t*)nullptr);
+    } else {
+      hipLaunchKernelGGL(k_copy_i32, dim3(g), dim3(kFBlock), 0, s, n, (const int32_t*)P, Q);
+      if (parent)
+        hipLaunchKernelGGL(k_edge_list<LtConnect<true>>, dim3(ge), dim3(kFBlock), 0, s, (const int32_t*)eu,
+                           (const int32_t*)ev, ecnt, LtConnect<true>{P, Q}, &sc->changed);
+      else
+        hipLaunchKernelGGL(k_edge_list<LtConnect<false>>, dim3(ge), dim3(kFBlock), 0, s, (const int32_t*)eu,
+                           (const int32_t*)ev, ecnt, LtConnect<false>{P, Q}, &sc->changed);
+      if (full) hipLaunchKernelGGL(k_full_shortcut, dim3(g), dim3(kFBlock), 0, s, n, P, (int32_t*)nullptr, &sc->changed);
+      else hipLaunchKernelGGL(k_shortcut_one, dim3(g), dim3(kFBlock), 0, s, n, P, &sc->changed);
+      if (alter)
+        hipLaunchKernelGGL(k_lt_alter, dim3(ge), dim3(kFBlock), 0, s, eu, ev, ecnt, (const int32_t*)P, &sc->changed);
+    }
+    CC_LAUNCH_CHECK();
+    ++*rounds;
+    CC_HIP(hipMemcpyAsync(&ctx->host->changed, &sc->changed, 4, hipMemcpyDeviceToHost, s));
+    CC_HIP(hipStreamSynchronize(s));
+    if (!ctx->host->changed) break;
   }
   return CC_OK;
 }

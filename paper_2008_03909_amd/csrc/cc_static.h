@@ -52,6 +52,10 @@ cc_status output_labels(StaticArgs& a);
 cc_status forest_filter(hipStream_t s, int64_t n, const int2* tree, const int2* hook, const float* hook_w,
                         int32_t* cnt, int32_t* out_u, int32_t* out_v, float* out_w, int64_t* num_edges);
 int64_t forest_tiles(int64_t len);
+// SV / root-based LT rounds over an explicit edge list until nothing changes
+// (stream batch inserts with a round-based finish).
+cc_status edge_list_rounds(cc_ctx* ctx, hipStream_t s, const cc_variant& v, int64_t n, int32_t* P, int32_t* Q,
+                           int32_t* eu, int32_t* ev, const unsigned long long* ecnt, int64_t cap, int32_t* rounds);
 // Synchronous read of the context's device scalars into ctx->host.
 cc_status pull_scalars(StaticArgs& a);
 

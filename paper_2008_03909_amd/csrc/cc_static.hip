@@ -124,10 +124,8 @@ cc_status check_variant(const cc_variant* v, bool for_stream) {
       if (v->find < CC_FIND_NAIVE || v->find > CC_FIND_COMPRESS) return fail(CC_EINVAL, "bad find");
       break;
     case CC_FIN_SV:
-      if (for_stream) return fail(CC_EUNSUPPORTED, "streams use union-find finishes");
       break;
     case CC_FIN_LT: {
-      if (for_stream) return fail(CC_EUNSUPPORTED, "streams use union-find finishes");
       uint32_t r = v->lt_rules;
       const uint32_t ok[] = {CC_LT_CRSA, CC_LT_PRSA, CC_LT_PRS, CC_LT_CRFA, CC_LT_PRFA, CC_LT_PRF};
       bool found = false;

@@ -1,13 +1,23 @@
-// Batch-incremental connectivity (ConnectIt Section 3.4; appendix
-// "ConnectIt: Streaming").
+// Batch-incremental connectivity (ConnectIt Section 3.4 "Streaming";
+// appendix "ConnectIt: Streaming").
 //
-// The stream keeps a device-resident parent array.  insert_batch applies
-// Union(u, v) for every pair of the batch concurrently; query_batch answers
-// IsConnected(a, b) as find(a) == find(b).  Calls on one stream are ordered by
-// the HIP stream they are enqueued on, so a query batch sees exactly the
-// insert batches enqueued before it -- the batch-incremental correctness of
-// the paper for all union-find types, including Rem's algorithm with the
-// splice rule, whose inserts and finds must not overlap (phase-concurrent).
+// The stream keeps a device-resident parent array.  The finish decides how
+// a batch runs, after the paper's three types of streaming algorithms:
+//  * type 1 -- UF-Async (any find) and UF-Rem-CAS with SplitAtomicOne or
+//    HalveAtomicOne: unions and finds are linearizable together, so a mixed
+//    batch (cc_process_batch) runs its inserts and queries concurrently in
+//    one kernel; a query is Jayanti and Tarjan's SameSet (find both roots;
+//    equal: connected; else, if the first root is still a root, not
+//    connected, linearized when the second find returned; else retry);
+//  * type 2 -- Shiloach-Vishkin and the root-based Liu-Tarjan variants:
+//    inserts are processed as a batch, in synchronous rounds over the
+//    batch's edges until nothing changes, then the queries run;
+//  * type 3 -- UF-Rem-CAS with SpliceAtomic: phase-concurrent, the batch's
+//    inserts run concurrently, then (after a barrier) its queries.
+// insert_batch / query_batch are the pure batches.  Calls on one stream are
+// ordered by the HIP stream they are enqueued on, so a batch sees exactly
+// the batches enqueued before it.
+#include <algorithm>
 #include <cstring>
 
 #include "cc_device.h"
@@ -18,8 +28,16 @@ struct cc_stream {
   cc_ctx* ctx = nullptr;
   int64_t n = 0;
   cc_variant v{};
+  int type = 1;                       // streaming type (1, 2 or 3) of the finish
   int32_t* P = nullptr;
   uint32_t* err = nullptr;
+  // type 2 only: round snapshot and the batch's edge list (grown on demand)
+  int32_t* Q = nullptr;
+  int32_t* eu = nullptr;
+  int32_t* ev = nullptr;
+  unsigned long long* ecnt = nullptr;
+  int64_t ecap = 0;
+  int32_t last_rounds = 0;
 };
 
 namespace cc {
@@ -62,6 +80,68 @@ __global__ void k_stream_query(int64_t q, const int32_t* __restrict__ a, const i
   if (bad) atomicOr(err, kErrBadId);
 }
 
+// Jayanti-Tarjan SameSet: linearizable against concurrent unions that link
+// roots only.  If ra is still a root after rb was found, ra and rb were
+// both roots when rb was found, so x and y were apart at that moment.
+template <int FIND>
+__device__ __forceinline__ bool same_set(int32_t* P, int32_t x, int32_t y) {
+  if (x == y) return true;
+  while (true) {
+    const int32_t ra = find<FIND>(P, x);
+    const int32_t rb = find<FIND>(P, y);
+    if (ra == rb) return true;
+    if (ld(P + ra) == ra) return false;
+  }
+}
+
+// A mixed batch.  kind[i] == 0: Insert(u[i], v[i]); otherwise
+// IsConnected(u[i], v[i]) -> out[i] (out[i] = 0 for inserts).  PHASE -1:
+// both kinds in one pass (type 1); 0: inserts only; 1: queries only.
+template <int ALG, int SPLICE, int FIND, int PHASE>
+__global__ void k_stream_mixed(int64_t k, const uint8_t* __restrict__ kind, const int32_t* __restrict__ u,
+                               const int32_t* __restrict__ v, uint8_t* __restrict__ out, int32_t* P, int64_t n,
+                               uint32_t* err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += stride) {
+    const bool query = kind[i] != 0;
+    if ((PHASE == 0 && query) || (PHASE == 1 && !query)) continue;
+    const int32_t a = u[i], b = v[i];
+    if (a < 0 || b < 0 || (int64_t)a >= n || (int64_t)b >= n) {
+      bad = true;  // each operation is handled in exactly one phase
+      out[i] = 0;
+      continue;
+    }
+    if (query) {
+      out[i] = same_set<FIND>(P, a, b) ? 1 : 0;
+    } else {
+      out[i] = 0;
+      if (a != b) unite<ALG, SPLICE, FIND>(P, a, b);
+    }
+  }
+  if (bad) atomicOr(err, kErrBadId);
+}
+
+// Inserts of a batch as an edge list for the round-based finishes: entry i
+// is (u[i], v[i]) if it is a valid insert with u != v, else dead (-1).
+__global__ void k_stream_edges(int64_t k, const uint8_t* __restrict__ kind, const int32_t* __restrict__ u,
+                               const int32_t* __restrict__ v, int32_t* __restrict__ eu, int32_t* __restrict__ ev,
+                               unsigned long long* ecnt, int64_t n, uint32_t* err, uint8_t* out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ecnt = (unsigned long long)k;
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += stride) {
+    const bool query = kind && kind[i] != 0;
+    const int32_t a = u[i], b = v[i];
+    const bool valid = a >= 0 && b >= 0 && (int64_t)a < n && (int64_t)b < n;
+    if (!query && !valid) bad = true;
+    eu[i] = (!query && valid && a != b) ? a : -1;
+    ev[i] = b;
+    if (out && !query) out[i] = 0;
+  }
+  if (bad) atomicOr(err, kErrBadId);
+}
+
 __global__ void k_stream_labels(int64_t n, int32_t* P, int32_t* labels, long long* ncomp) {
   __shared__ long long red[256 / kWave];
   long long roots = 0;
@@ -88,6 +168,58 @@ static void launch_insert(cc_stream* s, int64_t k, const int32_t* u, const int32
                      s->P, s->n, s->err);
 }
 
+template <int ALG, int SPLICE, int FIND, int PHASE>
+static void launch_mixed(cc_stream* s, int64_t k, const uint8_t* kind, const int32_t* u, const int32_t* v,
+                         uint8_t* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_stream_mixed<ALG, SPLICE, FIND, PHASE>), dim3(grid_for(k, 256, 8192)), dim3(256), 0, st, k,
+                     kind, u, v, out, s->P, s->n, s->err);
+}
+
+// Dispatch of a mixed batch over the union-find variants (types 1 and 3).
+template <int PHASE>
+static void mixed_uf(cc_stream* s, int64_t k, const uint8_t* kind, const int32_t* u, const int32_t* v, uint8_t* out,
+                     hipStream_t st) {
+  const cc_variant& x = s->v;
+  if (x.finish == CC_FIN_UF_ASYNC) {
+    if (x.find == 0) launch_mixed<1, 0, 0, PHASE>(s, k, kind, u, v, out, st);
+    else if (x.find == 1) launch_mixed<1, 0, 1, PHASE>(s, k, kind, u, v, out, st);
+    else if (x.find == 2) launch_mixed<1, 0, 2, PHASE>(s, k, kind, u, v, out, st);
+    else launch_mixed<1, 0, 3, PHASE>(s, k, kind, u, v, out, st);
+    return;
+  }
+#define REM(SPL, FND) \
+  if (x.splice == SPL && x.find == FND) return launch_mixed<0, SPL, FND, PHASE>(s, k, kind, u, v, out, st);
+  REM(0, 0) REM(0, 1) REM(0, 2) REM(1, 0) REM(1, 1) REM(1, 2) REM(2, 0) REM(2, 1) REM(2, 2)
+#undef REM
+}
+
+static int stream_type(const cc_variant& v) {
+  if (v.finish == CC_FIN_SV || v.finish == CC_FIN_LT) return 2;
+  if (v.finish == CC_FIN_UF_REM_CAS && v.splice == CC_SPLICE_ATOMIC) return 3;
+  return 1;
+}
+
+// Type 2: the batch's inserts as an edge list, then rounds until no change.
+static cc_status round_inserts(cc_stream* s, int64_t k, const uint8_t* kind, const int32_t* u, const int32_t* v,
+                               uint8_t* out, hipStream_t st) {
+  if (k > s->ecap) {
+    const int64_t cap = std::max<int64_t>(k, 2 * s->ecap);
+    CC_HIP(hipStreamSynchronize(st));
+    if (s->eu) CC_HIP(hipFree(s->eu));
+    if (s->ev) CC_HIP(hipFree(s->ev));
+    s->eu = s->ev = nullptr;
+    s->ecap = 0;
+    if (hipMalloc((void**)&s->eu, (size_t)cap * 4) != hipSuccess ||
+        hipMalloc((void**)&s->ev, (size_t)cap * 4) != hipSuccess)
+      return fail(CC_ENOMEM, "cannot allocate the edge list of a %lld-pair batch", (long long)k);
+    s->ecap = cap;
+  }
+  hipLaunchKernelGGL(k_stream_edges, dim3(grid_for(k, 256, 8192)), dim3(256), 0, st, k, kind, u, v, s->eu, s->ev,
+                     s->ecnt, s->n, s->err, out);
+  CC_LAUNCH_CHECK();
+  return edge_list_rounds(s->ctx, st, s->v, s->n, s->P, s->Q, s->eu, s->ev, s->ecnt, k, &s->last_rounds);
+}
+
 }  // namespace cc
 
 using namespace cc;
@@ -112,17 +244,22 @@ cc_status cc_stream_create(cc_ctx* ctx, int64_t n, const cc_variant* v, cc_strea
   s->ctx = ctx;
   s->n = n;
   s->v = *v;
-  if (hipMalloc((void**)&s->P, (size_t)n * 4) != hipSuccess || hipMalloc((void**)&s->err, 256) != hipSuccess) {
+  s->type = stream_type(*v);
+  bool ok = hipMalloc((void**)&s->P, (size_t)n * 4) == hipSuccess && hipMalloc((void**)&s->err, 256) == hipSuccess;
+  if (ok && s->type == 2)
+    ok = hipMalloc((void**)&s->Q, (size_t)n * 4) == hipSuccess &&
+         hipMalloc((void**)&s->ecnt, 256) == hipSuccess;
+  if (!ok) {
     if (s->P) hipFree(s->P);
+    if (s->err) hipFree(s->err);
+    if (s->Q) hipFree(s->Q);
     delete s;
     return fail(CC_ENOMEM, "cannot allocate the stream state (%lld vertices)", (long long)n);
   }
   hipLaunchKernelGGL(k_stream_init, dim3(grid_for(n, 256, 4096)), dim3(256), 0, (hipStream_t)0, n, s->P);
   hipMemset(s->err, 0, 256);
   if (hipDeviceSynchronize() != hipSuccess) {
-    hipFree(s->P);
-    hipFree(s->err);
-    delete s;
+    cc_stream_destroy(s);
     return fail(CC_EDEVICE, "stream initialisation failed");
   }
   *out = s;
@@ -132,8 +269,8 @@ cc_status cc_stream_create(cc_ctx* ctx, int64_t n, const cc_variant* v, cc_strea
 void cc_stream_destroy(cc_stream* s) {
   if (!s) return;
   hipDeviceSynchronize();
-  hipFree(s->P);
-  hipFree(s->err);
+  for (void* p : {(void*)s->P, (void*)s->err, (void*)s->Q, (void*)s->eu, (void*)s->ev, (void*)s->ecnt})
+    if (p) hipFree(p);
   delete s;
 }
 
@@ -150,6 +287,7 @@ cc_status cc_insert_batch(cc_stream* s, int64_t k, const int32_t* u, const int32
   if (k == 0) return CC_OK;
   if (!u || !v) return fail(CC_EINVAL, "NULL pair array");
   hipStream_t st = (hipStream_t)hip_stream;
+  if (s->type == 2) return round_inserts(s, k, nullptr, u, v, nullptr, st);
   const cc_variant& x = s->v;
   if (x.finish == CC_FIN_UF_ASYNC) {
     if (x.find == 0) launch_insert<1, 0, 0>(s, k, u, v, st);
@@ -194,6 +332,31 @@ cc_status cc_query_batch(cc_stream* s, int64_t q, const int32_t* a, const int32_
   CC_LAUNCH_CHECK();
   return CC_OK;
 }
+
+cc_status cc_process_batch(cc_stream* s, int64_t k, const uint8_t* kind, const int32_t* u, const int32_t* v,
+                           uint8_t* out, void* hip_stream) {
+  if (!s) return fail(CC_EINVAL, "stream is NULL");
+  if (k < 0) return fail(CC_EINVAL, "k < 0");
+  if (k == 0) return CC_OK;
+  if (!kind || !u || !v || !out) return fail(CC_EINVAL, "NULL array");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (s->type == 1) {
+    mixed_uf<-1>(s, k, kind, u, v, out, st);
+  } else if (s->type == 3) {
+    mixed_uf<0>(s, k, kind, u, v, out, st);
+    mixed_uf<1>(s, k, kind, u, v, out, st);
+  } else {
+    cc_status r = round_inserts(s, k, kind, u, v, out, st);
+    if (r != CC_OK) return r;
+    // queries after the rounds: P is a min-based forest, naive finds
+    hipLaunchKernelGGL((k_stream_mixed<1, 0, 0, 1>), dim3(grid_for(k, 256, 8192)), dim3(256), 0, st, k, kind, u, v,
+                       out, s->P, s->n, s->err);
+  }
+  CC_LAUNCH_CHECK();
+  return CC_OK;
+}
+
+int32_t cc_stream_type(const cc_stream* s) { return s ? s->type : 0; }
 
 cc_status cc_stream_labels(cc_stream* s, int32_t* labels_out, int64_t* num_components_dev, void* hip_stream) {
   if (!s || !labels_out) return fail(CC_EINVAL, "NULL argument");

@@ -209,10 +209,13 @@ def test_ldd_sample_is_a_partial_labelling_of_stars(ctx):
 def _stream_variants():
     vs = [b.default_variant(finish=b.FIN_UF_ASYNC, find=f) for f in range(4)]
     vs += [b.default_variant(finish=b.FIN_UF_REM_CAS, splice=s, find=0) for s in range(3)]
+    # type-2 streams: inserts in rounds (Shiloach-Vishkin, root-based Liu-Tarjan)
+    vs += [b.default_variant(finish=b.FIN_SV)]
+    vs += [b.default_variant(finish=b.FIN_LT, lt_rules=r) for r in sorted(b.LT_NAMES)]
     return vs
 
 
-@pytest.mark.parametrize("vi", range(7))
+@pytest.mark.parametrize("vi", range(14))
 def test_incremental_matches_oracle_on_every_prefix(ctx, vi):
     v = _stream_variants()[vi]
     n = 5000
