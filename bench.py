@@ -227,6 +227,62 @@ def incremental(ctx, g, seed: int = 5, max_pairs: int | None = None):
     }
 
 
+def mixed(ctx, g, seed: int = 7, total_ops: int = 20_000_000):
+    """Mixed batches (cc_process_batch): the workload's pairs, shuffled, as
+    inserts, interleaved 50/50 with uniform random queries, in batches of
+    log-uniform size in [1e3, 1e7] operations; device time per batch.  One
+    type-1 stream (inserts and queries in one kernel) and one type-3 stream
+    (Rem-CAS with SpliceAtomic: inserts, then queries)."""
+    import numpy as np
+    import torch
+
+    from paper_2008_03909_amd import binding as b
+    from paper_2008_03909_amd import inputs
+
+    dev = ctx.torch_device
+    rng = np.random.default_rng(seed)
+    su, sv = inputs.shuffle_pairs(g.u, g.v, seed)
+    half = min(total_ops // 2, su.shape[0])
+    qa, qb = inputs.query_pairs(g.n, half, seed=seed + 1)
+    kind = np.concatenate([np.zeros(half, np.uint8), np.ones(half, np.uint8)])
+    u = np.concatenate([su[:half], qa])
+    w = np.concatenate([sv[:half], qb])
+    perm = rng.permutation(2 * half)
+    dk = torch.from_numpy(kind[perm]).to(dev)
+    du = torch.from_numpy(u[perm]).to(dev)
+    dw = torch.from_numpy(w[perm]).to(dev)
+    out = torch.empty(2 * half, dtype=torch.uint8, device=dev)
+    sizes = []
+    pos = 0
+    while pos < 2 * half:
+        k = min(inputs.log_uniform_int(1e3, 1e7, rng.random()), 2 * half - pos)
+        sizes.append((pos, k))
+        pos += k
+    res = {}
+    for name, v in (("type1_uf_async", b.default_variant(finish=b.FIN_UF_ASYNC, find=b.FIND_NAIVE)),
+                    ("type3_rem_splice", b.default_variant(splice=b.SPLICE_ATOMIC))):
+        st = b.Stream(ctx, g.n, v)
+        s = torch.cuda.current_stream()
+        recs = []
+        torch.cuda.synchronize()
+        for p0, k in sizes:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            st.process(dk[p0:p0 + k], du[p0:p0 + k], dw[p0:p0 + k], out=out[p0:p0 + k])
+            e1.record(s)
+            recs.append((k, e0, e1))
+        torch.cuda.synchronize()
+        st.sync_status()
+        st.close()
+        ms = sorted(a.elapsed_time(bb) for _, a, bb in recs)
+        tot = sum(ms)
+        res[name] = {"ops_per_s": 2 * half / (tot / 1e3), "p50_ms": ms[len(ms) // 2],
+                     "p99_ms": ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))], "batches": len(ms)}
+    res["ops"] = 2 * half
+    res["note"] = "half inserts (workload pairs), half uniform queries, shuffled together; device time per batch"
+    return res
+
+
 def serving(ctx, g, capacity_pairs_per_s: float | None = None, loads=(0.0, 0.5, 0.9), requests: int = 300,
             seed: int = 5):
     """Poisson arrivals through the serving loop (continuous batching): insert
@@ -581,6 +637,9 @@ def main():
     if not args.no_incremental:
         log("incremental stream ...")
         out["incremental"] = incremental(ctx, g)
+        log("mixed batches ...")
+        out["mixed_batches"] = mixed(ctx, g)
+        log(f"mixed: {out['mixed_batches']}")
         log(f"incremental: {out['incremental']['updates_per_s']:.3e} updates/s, "
             f"p50 {out['incremental']['p50_ms']:.3f} ms, p99 {out['incremental']['p99_ms']:.3f} ms")
         log("serving loop (Poisson arrivals) ...")
