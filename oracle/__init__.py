@@ -76,6 +76,9 @@ def _load():
         lib.oracle_amsf_buckets.argtypes = [i64, i64, _i32p, _i32p, ctypes.POINTER(ctypes.c_float),
                                             ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _i64p]
         lib.oracle_amsf_buckets.restype = ctypes.c_int32
+        lib.oracle_kout_sample_mode.argtypes = [i64, _i64p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                                _i32p]
+        lib.oracle_kout_sample_mode.restype = i64
         _lib = lib
     return _lib
 
@@ -242,16 +245,19 @@ def amsf_buckets(n: int, u, v, w, eps: float, max_buckets: int = 4096):
 
 # ---- samplers with a deterministic partition -------------------------------
 
-def kout_sample(n: int, offsets, adj, k: int, seed: int):
-    """Partition produced by k-out sampling (first edge + k-1 seeded picks).
+def kout_sample(n: int, offsets, adj, k: int, seed: int, mode: int = 0):
+    """Partition produced by k-out sampling.
 
-    Section 3.2 "k-out Sampling" and the k-out sampling algorithm of the
-    appendix: union the picked edges, fully compress.  The result is the
-    connected components of the picked sub-graph, in canonical-min form."""
+    Section 3.2 "k-out Sampling" and the appendix's sampling schemes: mode 0
+    hybrid (first edge + k-1 seeded picks), 1 afforest (first k edges), 2
+    pure (k seeded picks), 3 maxdeg (the largest-degree neighbour, the first
+    on ties, + k-1 seeded picks); union the picked edges, fully compress.
+    The result is the connected components of the picked sub-graph, in
+    canonical-min form."""
     offsets, adj = _c(offsets, np.int64), _c(adj, np.int32)
     lab = np.empty(n, np.int32)
-    c = _load().oracle_kout_sample(n, _p64(offsets), _p32(adj) if adj.size else _p32(np.zeros(1, np.int32)),
-                                   k, seed, _p32(lab))
+    c = _load().oracle_kout_sample_mode(n, _p64(offsets), _p32(adj) if adj.size else _p32(np.zeros(1, np.int32)),
+                                        k, mode, seed, _p32(lab))
     return lab, int(c)
 
 

@@ -185,23 +185,47 @@ int64_t oracle_closure_cc(int64_t n, int64_t num_pairs, const int32_t* u, const 
  * r_j = output (v*k + j) of splitmix64 seeded with key, j = 1..k-1,
  * key = output 0x6b6f7574 of splitmix64 seeded with `seed`.  The sample's
  * labelling is the connected components of that sub-graph (canonical min). */
-int64_t oracle_kout_sample(int64_t n, const int64_t* offsets, const int32_t* adj, int32_t k, uint64_t seed,
-                           int32_t* label) {
+/* k-out edge choices (Section 3.2; appendix "Sampling Schemes"): mode 0
+ * hybrid (the first edge, then k-1 picks), 1 afforest (the first k edges),
+ * 2 pure (k picks), 3 maxdeg (the neighbour of largest degree, the first
+ * such in row order, then k-1 picks).  Pick j of x is entry
+ * draw(key, x*k + j) mod deg of x's row. */
+int64_t oracle_kout_sample_mode(int64_t n, const int64_t* offsets, const int32_t* adj, int32_t k, int32_t mode,
+                                uint64_t seed, int32_t* label) {
   int32_t* P = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
   oracle_uf_init(n, P);
   const uint64_t key = sm_out(seed, 0x6b6f7574ULL);
   for (int64_t x = 0; x < n; ++x) {
-    int64_t deg = offsets[x + 1] - offsets[x];
+    const int64_t b = offsets[x];
+    const int64_t deg = offsets[x + 1] - b;
     if (deg == 0) continue;
-    uf_union(P, (int32_t)x, adj[offsets[x]]);
-    for (int32_t j = 1; j < k; ++j) {
-      uint64_t r = sm_out(key, (uint64_t)x * (uint64_t)k + (uint64_t)j);
-      uf_union(P, (int32_t)x, adj[offsets[x] + (int64_t)(r % (uint64_t)deg)]);
+    for (int32_t j = 0; j < k; ++j) {
+      int64_t idx;
+      if (mode == 1) {
+        if (j >= deg) break;
+        idx = j;
+      } else if (mode == 0 && j == 0) {
+        idx = 0;
+      } else if (mode == 3 && j == 0) {
+        idx = 0;
+        for (int64_t t = 1; t < deg; ++t) {
+          const int32_t y = adj[b + t], z = adj[b + idx];
+          if (offsets[y + 1] - offsets[y] > offsets[z + 1] - offsets[z]) idx = t;
+        }
+      } else {
+        idx = (int64_t)(sm_out(key, (uint64_t)x * (uint64_t)k + (uint64_t)j) % (uint64_t)deg);
+      }
+      uf_union(P, (int32_t)x, adj[b + idx]);
     }
   }
   int64_t comps = oracle_uf_labels(n, P, label);
   free(P);
   return comps;
+}
+
+int64_t oracle_kout_sample(int64_t n, const int64_t* offsets, const int32_t* adj, int32_t k, uint64_t seed,
+                           int32_t* label) {
+  return oracle_kout_sample_mode(n, offsets, adj, k, 0, seed, label);
 }
 
 /* ---- BFS sample partition ----------------------------------------------

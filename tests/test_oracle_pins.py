@@ -571,3 +571,51 @@ def test_amsf_counts_against_brute_force():
             if sum(rounded[i] for i in f) <= best * (1 + 1e-12):
                 assert np.bincount(b[list(f)], minlength=len(cnt)).tolist() == cnt.tolist(), trial
                 assert sum(float(w[i]) for i in f) <= (1 + eps) * exact * (1 + 1e-9), trial
+
+
+# ---- k-out edge choices (appendix "Sampling Schemes") -------------------------
+
+def _csr_from_rows(rows):
+    off = np.zeros(len(rows) + 1, np.int64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    adj = np.array([x for r in rows for x in r], np.int32)
+    return off, adj
+
+
+def test_kout_maxdeg_closed_form():
+    """Two hubs (2, 3) with two leaves each, joined through the path 2-0-1-3.
+    With k = 1, max-degree picks send 0 to hub 2 and 1 to hub 3 and the edge
+    0-1 is never picked: two components.  The first-edge (hybrid) rule picks
+    0-1 and joins everything; afforest k = 1 is hybrid k = 1."""
+    rows = [[1, 2], [0, 3], [0, 4, 5], [1, 6, 7], [2], [2], [3], [3]]
+    off, adj = _csr_from_rows(rows)
+    lab, c = oracle.kout_sample(8, off, adj, 1, seed=3, mode=3)
+    assert c == 2 and lab.tolist() == [0, 1, 0, 1, 0, 0, 1, 1]
+    for mode in (0, 1):
+        lab, c = oracle.kout_sample(8, off, adj, 1, seed=3, mode=mode)
+        assert c == 1 and np.all(lab == 0)
+
+
+def test_kout_maxdeg_ties_take_the_first():
+    """Vertex 0's neighbours 1 and 2 both have degree 2; 1 and 2 each lead to
+    a hub of degree 3 with two leaves.  With k = 1, 0 picks 1 (the first of
+    the tie), so the components are {0, 1, 3, 5, 6} and {2, 4, 7, 8};
+    taking the last of a tie would give {1, 3, 5, 6} and {0, 2, 4, 7, 8}."""
+    rows = [[1, 2], [0, 3], [0, 4], [1, 5, 6], [2, 7, 8], [3], [3], [4], [4]]
+    off, adj = _csr_from_rows(rows)
+    lab, c = oracle.kout_sample(9, off, adj, 1, seed=3, mode=3)
+    assert c == 2 and lab.tolist() == [0, 0, 2, 0, 2, 0, 0, 2, 2]
+
+
+def test_kout_pure_and_afforest_are_partial_labellings():
+    for seed in range(3):
+        g = inputs.er(3000, 2500, seed=seed)
+        off, adj = oracle.csr_build(g.n, g.u, g.v, dedup=True)
+        true, tc = oracle.labels(g)
+        for mode in (1, 2, 3):
+            for k in (1, 2):
+                lab, c = oracle.kout_sample(g.n, off, adj, k, seed=seed, mode=mode)
+                assert oracle.partial_labelling_ok(lab, true) and c >= tc
+        # afforest with k >= every degree picks every edge: the exact labelling
+        lab, c = oracle.kout_sample(g.n, off, adj, int(np.diff(off).max()) + 1, seed=seed, mode=1)
+        assert np.array_equal(lab, true)
