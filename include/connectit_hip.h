@@ -51,9 +51,22 @@ typedef enum {
 enum { CC_SAMPLE_NONE = 0, CC_SAMPLE_KOUT = 1, CC_SAMPLE_BFS = 2, CC_SAMPLE_LDD = 3 };
 /* k-out edge choice: hybrid = first edge + (k-1) uniform picks (the paper's
  * default); afforest = first k edges; pure = k uniform picks. */
-enum { CC_KOUT_HYBRID = 0, CC_KOUT_AFFOREST = 1, CC_KOUT_PURE = 2 };
-/* Finish methods, Section 3.3. */
-enum { CC_FIN_UF_REM_CAS = 0, CC_FIN_UF_ASYNC = 1, CC_FIN_SV = 2, CC_FIN_LT = 3 };
+enum { CC_KOUT_HYBRID = 0, CC_KOUT_AFFOREST = 1, CC_KOUT_PURE = 2, CC_KOUT_MAXDEG = 3 };
+/* maxdeg (appendix "Sampling Schemes", max-degree sampling): pick 0 is the
+ * neighbour of largest degree (the first such in row order), then k-1
+ * uniform picks as for hybrid. */
+/* Finish methods, Section 3.3.  UF-Early and UF-Hooks are the UF-Async
+ * relatives of Section 3.3 (any find); LP is label propagation (appendix
+ * "Label Propagation"), run as rounds over every candidate edge. */
+enum {
+  CC_FIN_UF_REM_CAS = 0,
+  CC_FIN_UF_ASYNC = 1,
+  CC_FIN_SV = 2,
+  CC_FIN_LT = 3,
+  CC_FIN_UF_EARLY = 4,
+  CC_FIN_UF_HOOKS = 5,
+  CC_FIN_LP = 6
+};
 /* Find options (appendix "Find Algorithms"). */
 enum { CC_FIND_NAIVE = 0, CC_FIND_ATOMIC_SPLIT = 1, CC_FIND_ATOMIC_HALVE = 2, CC_FIND_COMPRESS = 3 };
 /* Splice options of Rem's algorithm (appendix "Splice Algorithms"). */

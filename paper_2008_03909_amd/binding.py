@@ -16,8 +16,9 @@ SO_PATH = os.path.join(_HERE, "libconnectit_hip.so")
 
 CC_OK, CC_EINVAL, CC_ENOMEM, CC_EDEVICE, CC_ELIVELOCK, CC_EBUSY, CC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SAMPLE_NONE, SAMPLE_KOUT, SAMPLE_BFS, SAMPLE_LDD = 0, 1, 2, 3
-KOUT_HYBRID, KOUT_AFFOREST, KOUT_PURE = 0, 1, 2
+KOUT_HYBRID, KOUT_AFFOREST, KOUT_PURE, KOUT_MAXDEG = 0, 1, 2, 3
 FIN_UF_REM_CAS, FIN_UF_ASYNC, FIN_SV, FIN_LT = 0, 1, 2, 3
+FIN_UF_EARLY, FIN_UF_HOOKS, FIN_LP = 4, 5, 6
 FIND_NAIVE, FIND_ATOMIC_SPLIT, FIND_ATOMIC_HALVE, FIND_COMPRESS = 0, 1, 2, 3
 SPLICE_SPLIT_ONE, SPLICE_HALVE_ONE, SPLICE_ATOMIC = 0, 1, 2
 LT_CONNECT, LT_PARENT_CONNECT, LT_ROOTUP, LT_FULL_SHORTCUT, LT_ALTER = 0, 1, 4, 8, 16
@@ -55,12 +56,15 @@ class cc_variant(ctypes.Structure):
     def name(self) -> str:
         s = {0: "none", 1: "kout", 2: "bfs", 3: "ldd"}[self.sample]
         if self.sample == SAMPLE_KOUT:
-            s += {0: "", 1: "-afforest", 2: "-pure"}[self.kout_mode] + f"(k={self.kout_k})"
+            s += {0: "", 1: "-afforest", 2: "-pure", 3: "-maxdeg"}[self.kout_mode] + f"(k={self.kout_k})"
         if self.finish == FIN_UF_REM_CAS:
             f = "rem-cas/" + ["split-one", "halve-one", "splice"][self.splice] + "/" + \
                 ["naive", "split", "halve"][self.find]
-        elif self.finish == FIN_UF_ASYNC:
-            f = "async/" + ["naive", "split", "halve", "compress"][self.find]
+        elif self.finish in (FIN_UF_ASYNC, FIN_UF_EARLY, FIN_UF_HOOKS):
+            f = {FIN_UF_ASYNC: "async/", FIN_UF_EARLY: "early/", FIN_UF_HOOKS: "hooks/"}[self.finish] + \
+                ["naive", "split", "halve", "compress"][self.find]
+        elif self.finish == FIN_LP:
+            f = "lp"
         elif self.finish == FIN_SV:
             f = "sv"
         else:
@@ -783,11 +787,28 @@ def all_finishes():
     return out
 
 
-def all_variants(seed: int = 0x5EED):
-    """Every sampling x finish combination (4 x 20 = 80)."""
+def extra_finishes():
+    """The 9 further finishes of Section 3.3 and the appendix: UF-Early and
+    UF-Hooks with each find, and label propagation."""
+    out = []
+    for fin in (FIN_UF_EARLY, FIN_UF_HOOKS):
+        for fd in (FIND_NAIVE, FIND_ATOMIC_SPLIT, FIND_ATOMIC_HALVE, FIND_COMPRESS):
+            out.append(dict(finish=fin, find=fd, splice=0))
+    out.append(dict(finish=FIN_LP, find=0, splice=0))
+    return out
+
+
+def all_variants(seed: int = 0x5EED, extended: bool = False):
+    """Every sampling x finish combination: the 80 of the main table
+    (4 samplers x 20 finishes); with extended=True 36 more follow them (the
+    4 samplers x extra_finishes()), so indices below 80 never change."""
     base = default_variant(seed=seed)
     out = []
     for s in (SAMPLE_NONE, SAMPLE_KOUT, SAMPLE_BFS, SAMPLE_LDD):
         for f in all_finishes():
             out.append(base.copy(sample=s, **f))
+    if extended:
+        for s in (SAMPLE_NONE, SAMPLE_KOUT, SAMPLE_BFS, SAMPLE_LDD):
+            for f in extra_finishes():
+                out.append(base.copy(sample=s, **f))
     return out

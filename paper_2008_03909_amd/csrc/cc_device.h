@@ -182,12 +182,82 @@ __device__ __forceinline__ int32_t union_rem(int32_t* P, int32_t u, int32_t v) {
   return union_rem_from<SPLICE, FIND>(P, u, v, ld(P + u), ld(P + v));
 }
 
-// Union dispatch.  ALG 0 = Rem-CAS (SPLICE, FIND), 1 = Async (FIND).
+// ---- UF-Early (Section 3.3, the variants of UF-Async) ----------------------
+// Walk both paths together: the larger of the two current nodes moves up;
+// once it is a root it is hooked (CAS) under the other node, which is
+// smaller and, since every tree's root is its minimum, in another tree.
+// Equal nodes: already joined.  With a compress find, both endpoints are
+// found again after a hook.  Returns the hooked root or -1.
+template <int FIND>
+__device__ __forceinline__ int32_t union_early(int32_t* P, int32_t u, int32_t v) {
+  int32_t x = u, y = v;
+  while (true) {
+    if (x == y) return -1;
+    if (x < y) {
+      const int32_t t = x;
+      x = y;
+      y = t;
+    }
+    const int32_t px = ld(P + x);
+    if (px == x) {
+      if (cas(P + x, x, y)) {
+        if constexpr (FIND != kFindNaive) {
+          find<FIND>(P, u);
+          find<FIND>(P, v);
+        }
+        return x;
+      }
+      continue;  // lost the race: read x's new parent
+    }
+    x = px;
+  }
+}
+
+// ---- UF-Hooks ------------------------------------------------------------------
+// As UF-Async, but the CAS that claims a root goes to an auxiliary array H
+// (H[r] = -1 while r is unclaimed); the winner then writes P[r] with a plain
+// store that no other thread contends for.  A root is hooked from the
+// moment its claim succeeds, so finds follow H[r] from a claimed root
+// whose P[r] is not written yet: no thread ever waits for another's store
+// (a lane spinning on a store that its own wave's exiting lane has yet to
+// issue would never see it).
+template <int FIND>
+__device__ __forceinline__ int32_t find_hooks(int32_t* P, const int32_t* H, int32_t u) {
+  while (true) {
+    const int32_t r = find<FIND>(P, u);
+    const int32_t h = ld(H + r);
+    if (h < 0) return r;
+    u = h;
+  }
+}
+
+template <int FIND>
+__device__ __forceinline__ int32_t union_hooks(int32_t* P, int32_t* H, int32_t u, int32_t v) {
+  while (true) {
+    int32_t pu = find_hooks<FIND>(P, H, u);
+    int32_t pv = find_hooks<FIND>(P, H, v);
+    if (pu == pv) return -1;
+    if (pu < pv) {
+      const int32_t t = pu;
+      pu = pv;
+      pv = t;
+    }
+    if (cas(H + pu, -1, pv)) {
+      st(P + pu, pv);
+      return pu;
+    }
+  }
+}
+
+// Union dispatch.  ALG 0 = Rem-CAS (SPLICE, FIND), 1 = Async (FIND),
+// 2 = Early (FIND), 3 = Hooks (FIND; H is its claim array, else unused).
 // Returns the hooked root or -1.
 template <int ALG, int SPLICE, int FIND>
-__device__ __forceinline__ int32_t unite(int32_t* P, int32_t u, int32_t v) {
+__device__ __forceinline__ int32_t unite(int32_t* P, int32_t u, int32_t v, int32_t* H = nullptr) {
   if constexpr (ALG == 0) return union_rem<SPLICE, FIND>(P, u, v);
-  else return union_async<FIND>(P, u, v);
+  else if constexpr (ALG == 1) return union_async<FIND>(P, u, v);
+  else if constexpr (ALG == 2) return union_early<FIND>(P, u, v);
+  else return union_hooks<FIND>(P, H, u, v);
 }
 
 // Spanning forest: the edge that hooked root r is stored at slot r (each

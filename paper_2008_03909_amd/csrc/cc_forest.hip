@@ -10,11 +10,11 @@
 // can be a claimed child and later a hooked root.  Each slot is written at
 // most once, there are n - c recorded edges in all, and they span every
 // component without a cycle.  Only root-based finishes that hook with a CAS
-// are supported: UF-Async, and UF-Rem-CAS with SplitAtomicOne or
-// HalveAtomicOne (those only shorten paths inside a tree).  SpliceAtomic
+// are supported: UF-Async, UF-Early, UF-Hooks, and UF-Rem-CAS with
+// SplitAtomicOne or HalveAtomicOne (those only shorten paths inside a tree).  SpliceAtomic
 // re-parents a non-root into the other tree, a link no recorded edge
 // stands for; SV and LT hook with writeMin, which does not identify the
-// winning edge.
+// winning edge, and label propagation keeps no tree at all.
 #include "cc_static.h"
 
 namespace cc {
@@ -149,8 +149,9 @@ cc_status cc_spanning_forest_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* 
                                  int32_t* labels_out, int32_t* edges_u, int32_t* edges_v, int64_t* num_edges_dev,
                                  void* hip_stream) {
   if (!v) return fail(CC_EINVAL, "variant is NULL");
-  if (v->finish != CC_FIN_UF_REM_CAS && v->finish != CC_FIN_UF_ASYNC)
-    return fail(CC_EUNSUPPORTED, "spanning forest needs a union-find finish (Rem-CAS or Async)");
+  if (v->finish != CC_FIN_UF_REM_CAS && v->finish != CC_FIN_UF_ASYNC && v->finish != CC_FIN_UF_EARLY &&
+      v->finish != CC_FIN_UF_HOOKS)
+    return fail(CC_EUNSUPPORTED, "spanning forest needs a union-find finish (Rem-CAS, Async, Early or Hooks)");
   if (v->finish == CC_FIN_UF_REM_CAS && v->splice == CC_SPLICE_ATOMIC)
     return fail(CC_EUNSUPPORTED, "spanning forest: SpliceAtomic moves non-roots between trees without a hook");
   if (!edges_u || !edges_v || !num_edges_dev) return fail(CC_EINVAL, "NULL forest output");

@@ -368,9 +368,98 @@ cc_status finish_lt(StaticArgs& a) {
   return lt_rounds<I, false>(a);
 }
 
+// ---- label propagation (appendix "Label Propagation") ---------------------
+// Labels are the parent array read as labels.  The frequent sampled class
+// is first relabelled to -1, below every id, so its vertices never change
+// and their label spreads to every vertex connected to them (the paper's
+// way of composing label propagation with sampling).  A round applies every
+// candidate edge both ways with writeMin; rounds repeat until nothing
+// changes.  Then the -1 class takes its smallest member as its label; every
+// other class already carries its minimum (the sampled labels are class
+// minima), so the result is the canonical labelling and a star forest.
+struct LpOp {
+  int32_t* P;
+  __device__ __forceinline__ bool operator()(int32_t u, int32_t w, int64_t) const {
+    const int32_t a = ld(P + u), c = ld(P + w);
+    if (a < c) return amin(P + w, a) > a;
+    if (c < a) return amin(P + u, c) > c;
+    return false;
+  }
+};
+
+__global__ void k_lp_mark(int64_t n, int32_t* P, const DevScalars* sc) {
+  const int32_t L = sc->lmax;
+  if (L < 0) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride)
+    if (P[v] == L) P[v] = -1;
+}
+
+// Per-block minimum vertex id labelled -1 (n when none).
+__global__ void __launch_bounds__(kFBlock) k_lp_min(int64_t n, const int32_t* __restrict__ P,
+                                                    int32_t* __restrict__ part) {
+  __shared__ int32_t red[kFBlock / kWave];
+  int32_t m = (int32_t)(n < 0x7fffffff ? n : 0x7fffffff);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride)
+    if (P[v] == -1 && (int32_t)v < m) m = (int32_t)v;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int32_t y = __shfl_xor(m, o, kWave);
+    m = y < m ? y : m;
+  }
+  if (lane_id() == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kFBlock / kWave; ++i) m = red[i] < m ? red[i] : m;
+    part[blockIdx.x] = m;
+  }
+}
+
+__global__ void k_lp_fix(int64_t n, int32_t* P, const int32_t* __restrict__ part, int nparts) {
+  __shared__ int32_t s_min;
+  if (threadIdx.x == 0) {
+    int32_t m = 0x7fffffff;
+    for (int i = 0; i < nparts; ++i) m = part[i] < m ? part[i] : m;
+    s_min = m;
+  }
+  __syncthreads();
+  const int32_t m = s_min;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride)
+    if (P[v] == -1) P[v] = m;
+}
+
+template <typename I>
+cc_status finish_lp(StaticArgs& a) {
+  DevScalars* sc = a.ctx->dev;
+  const unsigned g = grid_for(a.n, kFBlock, 4096);
+  hipLaunchKernelGGL(k_lp_mark, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, (const DevScalars*)sc);
+  for (int round = 0;; ++round) {
+    if (round >= kRoundCap) return fail(CC_ELIVELOCK, "label propagation exceeded %d rounds", kRoundCap);
+    if (a.ctx->round_limit > 0 && round >= a.ctx->round_limit)
+      return fail(CC_ELIVELOCK, "label propagation reached the context's round limit (%d)", a.ctx->round_limit);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->changed, 0u);
+    visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, LpOp{a.P}, &sc->changed);
+    CC_LAUNCH_CHECK();
+    ++a.finish_rounds;
+    uint32_t changed = 0;
+    cc_status st = read_flag(a, &changed);
+    if (st != CC_OK) return st;
+    if (!changed) break;
+  }
+  // per-block minima in the count array (free after the compaction)
+  const unsigned gm = grid_for(a.n, kFBlock, 1024);
+  hipLaunchKernelGGL(k_lp_min, dim3(gm), dim3(kFBlock), 0, a.s, a.n, (const int32_t*)a.P, a.count);
+  hipLaunchKernelGGL(k_lp_fix, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, (const int32_t*)a.count, (int)gm);
+  CC_LAUNCH_CHECK();
+  return CC_OK;
+}
+
 template cc_status finish_sv<int32_t>(StaticArgs&);
 template cc_status finish_sv<int64_t>(StaticArgs&);
 template cc_status finish_lt<int32_t>(StaticArgs&);
 template cc_status finish_lt<int64_t>(StaticArgs&);
+template cc_status finish_lp<int32_t>(StaticArgs&);
+template cc_status finish_lp<int64_t>(StaticArgs&);
 
 }  // namespace cc

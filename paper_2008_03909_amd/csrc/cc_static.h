@@ -37,6 +37,7 @@ template <typename I> cc_status sample_bfs(StaticArgs& a);
 template <typename I> cc_status sample_ldd(StaticArgs& a);
 template <typename I> cc_status finish_sv(StaticArgs& a);
 template <typename I> cc_status finish_lt(StaticArgs& a);
+template <typename I> cc_status finish_lp(StaticArgs& a);
 
 // The whole static algorithm on prepared arguments (statistics recorded).
 cc_status static_run(StaticArgs& a);

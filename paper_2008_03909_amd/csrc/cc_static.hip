@@ -103,7 +103,7 @@ cc_status check_variant(const cc_variant* v, bool for_stream) {
   if (v->sample < CC_SAMPLE_NONE || v->sample > CC_SAMPLE_LDD) return fail(CC_EINVAL, "bad sample %d", v->sample);
   if (v->sample == CC_SAMPLE_KOUT) {
     if (v->kout_k < 1 || v->kout_k > 64) return fail(CC_EINVAL, "kout_k must be in [1, 64]");
-    if (v->kout_mode < CC_KOUT_HYBRID || v->kout_mode > CC_KOUT_PURE) return fail(CC_EINVAL, "bad kout_mode");
+    if (v->kout_mode < CC_KOUT_HYBRID || v->kout_mode > CC_KOUT_MAXDEG) return fail(CC_EINVAL, "bad kout_mode");
   }
   if (v->sample == CC_SAMPLE_BFS && (v->bfs_tries < 1 || v->bfs_tries > 64))
     return fail(CC_EINVAL, "bfs_tries must be in [1, 64]");
@@ -121,7 +121,12 @@ cc_status check_variant(const cc_variant* v, bool for_stream) {
       if (v->find < CC_FIND_NAIVE || v->find > CC_FIND_ATOMIC_HALVE) return fail(CC_EINVAL, "bad find");
       break;
     case CC_FIN_UF_ASYNC:
+    case CC_FIN_UF_EARLY:
+    case CC_FIN_UF_HOOKS:
       if (v->find < CC_FIND_NAIVE || v->find > CC_FIND_COMPRESS) return fail(CC_EINVAL, "bad find");
+      break;
+    case CC_FIN_LP:
+      if (for_stream) return fail(CC_EUNSUPPORTED, "label propagation is not a streaming algorithm");
       break;
     case CC_FIN_SV:
       break;
@@ -262,6 +267,18 @@ __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict_
         idx = j;
       } else if (mode == CC_KOUT_HYBRID && j == 0) {
         idx = 0;
+      } else if (mode == CC_KOUT_MAXDEG && j == 0) {
+        // the neighbour of largest degree, the first one on ties
+        idx = 0;
+        int64_t best = -1;
+        for (int64_t t = 0; t < deg; ++t) {
+          const int32_t x = adj[b + t];
+          const int64_t dx = (int64_t)off[x + 1] - (int64_t)off[x];
+          if (dx > best) {
+            best = dx;
+            idx = t;
+          }
+        }
       } else {
         idx = (int64_t)(sm_out(key, (uint64_t)v * (uint64_t)k + (uint64_t)j) % (uint64_t)deg);
       }
@@ -637,8 +654,9 @@ template <int ALG, int SPLICE, int FIND>
 struct UnionOp {
   int32_t* P;
   int2* hook;   // spanning forest: edge per hooked root (nullable)
+  int32_t* H;   // UF-Hooks: claim array (else unused)
   __device__ __forceinline__ bool operator()(int32_t u, int32_t w, int64_t) const {
-    forest_record(hook, unite<ALG, SPLICE, FIND>(P, u, w), u, w);
+    forest_record(hook, unite<ALG, SPLICE, FIND>(P, u, w, H), u, w);
     return false;
   }
 };
@@ -708,7 +726,13 @@ __global__ void __launch_bounds__(kBlock) k_output_sum(const long long* __restri
 
 template <int ALG, int SPLICE, int FIND, typename I>
 static cc_status launch_uf_finish(StaticArgs& a) {
-  visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, UnionOp<ALG, SPLICE, FIND>{a.P, a.hook_e},
+  int32_t* H = nullptr;
+  if (ALG == 3) {  // UF-Hooks: claims in the count array (free once the compaction ran)
+    H = a.count;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(a.n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, (uint32_t*)H, a.n,
+                       0xffffffffu);
+  }
+  visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, UnionOp<ALG, SPLICE, FIND>{a.P, a.hook_e, H},
                    (uint32_t*)nullptr);
   CC_LAUNCH_CHECK();
   return CC_OK;
@@ -723,10 +747,19 @@ static cc_status uf_finish_dispatch(StaticArgs& a) {
     REM(0, 0) REM(0, 1) REM(0, 2) REM(1, 0) REM(1, 1) REM(1, 2) REM(2, 0) REM(2, 1) REM(2, 2)
 #undef REM
   } else {
-    if (v->find == 0) return launch_uf_finish<1, 0, 0, I>(a);
-    if (v->find == 1) return launch_uf_finish<1, 0, 1, I>(a);
-    if (v->find == 2) return launch_uf_finish<1, 0, 2, I>(a);
-    if (v->find == 3) return launch_uf_finish<1, 0, 3, I>(a);
+#define FINDS(ALG)                                                        \
+  if (v->find == 0) return launch_uf_finish<ALG, 0, 0, I>(a);             \
+  if (v->find == 1) return launch_uf_finish<ALG, 0, 1, I>(a);             \
+  if (v->find == 2) return launch_uf_finish<ALG, 0, 2, I>(a);             \
+  if (v->find == 3) return launch_uf_finish<ALG, 0, 3, I>(a);
+    if (v->finish == CC_FIN_UF_ASYNC) {
+      FINDS(1)
+    } else if (v->finish == CC_FIN_UF_EARLY) {
+      FINDS(2)
+    } else if (v->finish == CC_FIN_UF_HOOKS) {
+      FINDS(3)
+    }
+#undef FINDS
   }
   return fail(CC_EINVAL, "no such union-find variant");
 }
@@ -882,6 +915,7 @@ static cc_status run_tail(StaticArgs& a) {
     PhaseScope ps(a.ctx, a.s, "finish");
     if (a.v->finish == CC_FIN_SV) st = finish_sv<I>(a);
     else if (a.v->finish == CC_FIN_LT) st = finish_lt<I>(a);
+    else if (a.v->finish == CC_FIN_LP) st = finish_lp<I>(a);
     else st = uf_finish_dispatch<I>(a);
   }
   if (st != CC_OK) return st;

@@ -3,8 +3,8 @@
 //
 // The stream keeps a device-resident parent array.  The finish decides how
 // a batch runs, after the paper's three types of streaming algorithms:
-//  * type 1 -- UF-Async (any find) and UF-Rem-CAS with SplitAtomicOne or
-//    HalveAtomicOne: unions and finds are linearizable together, so a mixed
+//  * type 1 -- UF-Async, UF-Early, UF-Hooks (any find) and UF-Rem-CAS with
+//    SplitAtomicOne or HalveAtomicOne: unions and finds are linearizable together, so a mixed
 //    batch (cc_process_batch) runs its inserts and queries concurrently in
 //    one kernel; a query is Jayanti and Tarjan's SameSet (find both roots;
 //    equal: connected; else, if the first root is still a root, not
@@ -31,6 +31,7 @@ struct cc_stream {
   int type = 1;                       // streaming type (1, 2 or 3) of the finish
   int32_t* P = nullptr;
   uint32_t* err = nullptr;
+  int32_t* H = nullptr;               // UF-Hooks only: the claim array (-1 = unclaimed)
   // type 2 only: round snapshot and the batch's edge list (grown on demand)
   int32_t* Q = nullptr;
   int32_t* eu = nullptr;
@@ -49,7 +50,7 @@ __global__ void k_stream_init(int64_t n, int32_t* P) {
 
 template <int ALG, int SPLICE, int FIND>
 __global__ void k_stream_insert(int64_t k, const int32_t* __restrict__ u, const int32_t* __restrict__ v,
-                                int32_t* P, int64_t n, uint32_t* err) {
+                                int32_t* P, int32_t* H, int64_t n, uint32_t* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool bad = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += stride) {
@@ -58,7 +59,7 @@ __global__ void k_stream_insert(int64_t k, const int32_t* __restrict__ u, const 
       bad = true;
       continue;
     }
-    if (a != b) unite<ALG, SPLICE, FIND>(P, a, b);
+    if (a != b) unite<ALG, SPLICE, FIND>(P, a, b, H);
   }
   if (bad) atomicOr(err, kErrBadId);
 }
@@ -83,14 +84,16 @@ __global__ void k_stream_query(int64_t q, const int32_t* __restrict__ a, const i
 // Jayanti-Tarjan SameSet: linearizable against concurrent unions that link
 // roots only.  If ra is still a root after rb was found, ra and rb were
 // both roots when rb was found, so x and y were apart at that moment.
+// For UF-Hooks (H non-null) a root is one that is unclaimed in H, and the
+// finds follow claims (a claim is the union's linearization point).
 template <int FIND>
-__device__ __forceinline__ bool same_set(int32_t* P, int32_t x, int32_t y) {
+__device__ __forceinline__ bool same_set(int32_t* P, const int32_t* H, int32_t x, int32_t y) {
   if (x == y) return true;
   while (true) {
-    const int32_t ra = find<FIND>(P, x);
-    const int32_t rb = find<FIND>(P, y);
+    const int32_t ra = H ? find_hooks<FIND>(P, H, x) : find<FIND>(P, x);
+    const int32_t rb = H ? find_hooks<FIND>(P, H, y) : find<FIND>(P, y);
     if (ra == rb) return true;
-    if (ld(P + ra) == ra) return false;
+    if (H ? ld(H + ra) < 0 : ld(P + ra) == ra) return false;
   }
 }
 
@@ -99,8 +102,8 @@ __device__ __forceinline__ bool same_set(int32_t* P, int32_t x, int32_t y) {
 // both kinds in one pass (type 1); 0: inserts only; 1: queries only.
 template <int ALG, int SPLICE, int FIND, int PHASE>
 __global__ void k_stream_mixed(int64_t k, const uint8_t* __restrict__ kind, const int32_t* __restrict__ u,
-                               const int32_t* __restrict__ v, uint8_t* __restrict__ out, int32_t* P, int64_t n,
-                               uint32_t* err) {
+                               const int32_t* __restrict__ v, uint8_t* __restrict__ out, int32_t* P, int32_t* H,
+                               int64_t n, uint32_t* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool bad = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += stride) {
@@ -113,10 +116,10 @@ __global__ void k_stream_mixed(int64_t k, const uint8_t* __restrict__ kind, cons
       continue;
     }
     if (query) {
-      out[i] = same_set<FIND>(P, a, b) ? 1 : 0;
+      out[i] = same_set<FIND>(P, ALG == 3 ? H : nullptr, a, b) ? 1 : 0;
     } else {
       out[i] = 0;
-      if (a != b) unite<ALG, SPLICE, FIND>(P, a, b);
+      if (a != b) unite<ALG, SPLICE, FIND>(P, a, b, H);
     }
   }
   if (bad) atomicOr(err, kErrBadId);
@@ -165,14 +168,14 @@ __global__ void k_zero_i64(long long* p) { *p = 0; }
 template <int ALG, int SPLICE, int FIND>
 static void launch_insert(cc_stream* s, int64_t k, const int32_t* u, const int32_t* v, hipStream_t st) {
   hipLaunchKernelGGL((k_stream_insert<ALG, SPLICE, FIND>), dim3(grid_for(k, 256, 8192)), dim3(256), 0, st, k, u, v,
-                     s->P, s->n, s->err);
+                     s->P, s->H, s->n, s->err);
 }
 
 template <int ALG, int SPLICE, int FIND, int PHASE>
 static void launch_mixed(cc_stream* s, int64_t k, const uint8_t* kind, const int32_t* u, const int32_t* v,
                          uint8_t* out, hipStream_t st) {
   hipLaunchKernelGGL((k_stream_mixed<ALG, SPLICE, FIND, PHASE>), dim3(grid_for(k, 256, 8192)), dim3(256), 0, st, k,
-                     kind, u, v, out, s->P, s->n, s->err);
+                     kind, u, v, out, s->P, s->H, s->n, s->err);
 }
 
 // Dispatch of a mixed batch over the union-find variants (types 1 and 3).
@@ -180,13 +183,18 @@ template <int PHASE>
 static void mixed_uf(cc_stream* s, int64_t k, const uint8_t* kind, const int32_t* u, const int32_t* v, uint8_t* out,
                      hipStream_t st) {
   const cc_variant& x = s->v;
-  if (x.finish == CC_FIN_UF_ASYNC) {
-    if (x.find == 0) launch_mixed<1, 0, 0, PHASE>(s, k, kind, u, v, out, st);
-    else if (x.find == 1) launch_mixed<1, 0, 1, PHASE>(s, k, kind, u, v, out, st);
-    else if (x.find == 2) launch_mixed<1, 0, 2, PHASE>(s, k, kind, u, v, out, st);
-    else launch_mixed<1, 0, 3, PHASE>(s, k, kind, u, v, out, st);
-    return;
+#define FINDS(ALG)                                                       \
+  {                                                                      \
+    if (x.find == 0) launch_mixed<ALG, 0, 0, PHASE>(s, k, kind, u, v, out, st);      \
+    else if (x.find == 1) launch_mixed<ALG, 0, 1, PHASE>(s, k, kind, u, v, out, st); \
+    else if (x.find == 2) launch_mixed<ALG, 0, 2, PHASE>(s, k, kind, u, v, out, st); \
+    else launch_mixed<ALG, 0, 3, PHASE>(s, k, kind, u, v, out, st);                 \
+    return;                                                              \
   }
+  if (x.finish == CC_FIN_UF_ASYNC) FINDS(1)
+  if (x.finish == CC_FIN_UF_EARLY) FINDS(2)
+  if (x.finish == CC_FIN_UF_HOOKS) FINDS(3)
+#undef FINDS
 #define REM(SPL, FND) \
   if (x.splice == SPL && x.find == FND) return launch_mixed<0, SPL, FND, PHASE>(s, k, kind, u, v, out, st);
   REM(0, 0) REM(0, 1) REM(0, 2) REM(1, 0) REM(1, 1) REM(1, 2) REM(2, 0) REM(2, 1) REM(2, 2)
@@ -249,10 +257,13 @@ cc_status cc_stream_create(cc_ctx* ctx, int64_t n, const cc_variant* v, cc_strea
   if (ok && s->type == 2)
     ok = hipMalloc((void**)&s->Q, (size_t)n * 4) == hipSuccess &&
          hipMalloc((void**)&s->ecnt, 256) == hipSuccess;
+  if (ok && v->finish == CC_FIN_UF_HOOKS) {
+    ok = hipMalloc((void**)&s->H, (size_t)n * 4) == hipSuccess;
+    if (ok) hipMemset(s->H, 0xff, (size_t)n * 4);
+  }
   if (!ok) {
-    if (s->P) hipFree(s->P);
-    if (s->err) hipFree(s->err);
-    if (s->Q) hipFree(s->Q);
+    for (void* p : {(void*)s->P, (void*)s->err, (void*)s->H, (void*)s->Q, (void*)s->ecnt})
+      if (p) hipFree(p);
     delete s;
     return fail(CC_ENOMEM, "cannot allocate the stream state (%lld vertices)", (long long)n);
   }
@@ -269,7 +280,7 @@ cc_status cc_stream_create(cc_ctx* ctx, int64_t n, const cc_variant* v, cc_strea
 void cc_stream_destroy(cc_stream* s) {
   if (!s) return;
   hipDeviceSynchronize();
-  for (void* p : {(void*)s->P, (void*)s->err, (void*)s->Q, (void*)s->eu, (void*)s->ev, (void*)s->ecnt})
+  for (void* p : {(void*)s->P, (void*)s->err, (void*)s->H, (void*)s->Q, (void*)s->eu, (void*)s->ev, (void*)s->ecnt})
     if (p) hipFree(p);
   delete s;
 }
@@ -289,12 +300,18 @@ cc_status cc_insert_batch(cc_stream* s, int64_t k, const int32_t* u, const int32
   hipStream_t st = (hipStream_t)hip_stream;
   if (s->type == 2) return round_inserts(s, k, nullptr, u, v, nullptr, st);
   const cc_variant& x = s->v;
-  if (x.finish == CC_FIN_UF_ASYNC) {
-    if (x.find == 0) launch_insert<1, 0, 0>(s, k, u, v, st);
-    else if (x.find == 1) launch_insert<1, 0, 1>(s, k, u, v, st);
-    else if (x.find == 2) launch_insert<1, 0, 2>(s, k, u, v, st);
-    else launch_insert<1, 0, 3>(s, k, u, v, st);
-  } else {
+#define FINDS(ALG)                                        \
+  {                                                       \
+    if (x.find == 0) launch_insert<ALG, 0, 0>(s, k, u, v, st);      \
+    else if (x.find == 1) launch_insert<ALG, 0, 1>(s, k, u, v, st); \
+    else if (x.find == 2) launch_insert<ALG, 0, 2>(s, k, u, v, st); \
+    else launch_insert<ALG, 0, 3>(s, k, u, v, st);                 \
+  }
+  if (x.finish == CC_FIN_UF_ASYNC) FINDS(1)
+  else if (x.finish == CC_FIN_UF_EARLY) FINDS(2)
+  else if (x.finish == CC_FIN_UF_HOOKS) FINDS(3)
+#undef FINDS
+  else {
 #define REM(SPL, FND) \
   else if (x.splice == SPL && x.find == FND) launch_insert<0, SPL, FND>(s, k, u, v, st);
     if (false) {
@@ -350,7 +367,7 @@ cc_status cc_process_batch(cc_stream* s, int64_t k, const uint8_t* kind, const i
     if (r != CC_OK) return r;
     // queries after the rounds: P is a min-based forest, naive finds
     hipLaunchKernelGGL((k_stream_mixed<1, 0, 0, 1>), dim3(grid_for(k, 256, 8192)), dim3(256), 0, st, k, kind, u, v,
-                       out, s->P, s->n, s->err);
+                       out, s->P, (int32_t*)nullptr, s->n, s->err);
   }
   CC_LAUNCH_CHECK();
   return CC_OK;

@@ -48,6 +48,18 @@ def test_eighty_variants_are_accepted():
         assert b.check_variant(v) == b.CC_OK, v
 
 
+def test_extended_variants_are_accepted():
+    """UF-Early / UF-Hooks (any find) and label propagation, under every
+    sampler, follow the 80 main variants; k-out's max-degree edge choice."""
+    vs = b.all_variants(extended=True)
+    assert len(vs) == 116 and [v.name() for v in vs[:80]] == [v.name() for v in b.all_variants()]
+    assert len({v.name() for v in vs}) == 116
+    for v in vs:
+        assert b.check_variant(v) == b.CC_OK, v
+    assert b.check_variant(b.default_variant(kout_mode=b.KOUT_MAXDEG)) == b.CC_OK
+    assert b.check_variant(b.default_variant(kout_mode=4)) == b.CC_EINVAL
+
+
 def test_rem_with_find_compress_is_rejected():
     """The paper's counter-example combination (Rem + splice + FindCompress) and
     FindCompress with Rem in general are refused."""

@@ -24,7 +24,7 @@ def ctx():
 
 
 def _uf_variants():
-    return [v for v in b.all_variants() if v.finish == b.FIN_UF_ASYNC
+    return [v for v in b.all_variants(extended=True) if v.finish in (b.FIN_UF_ASYNC, b.FIN_UF_EARLY, b.FIN_UF_HOOKS)
             or (v.finish == b.FIN_UF_REM_CAS and v.splice != b.SPLICE_ATOMIC)]
 
 
@@ -41,7 +41,7 @@ def _check(ctx, g, v):
     assert code == oracle.FOREST_OK, (v.name(), g, code)
 
 
-@pytest.mark.parametrize("vi", range(40))
+@pytest.mark.parametrize("vi", range(72))
 def test_forest_every_union_find_variant_on_the_suite(ctx, vi):
     v = _uf_variants()[vi]
     for g in SUITE:
@@ -75,7 +75,7 @@ def test_forest_rejects_unsupported_finishes(ctx):
     g = inputs.er(100, 300, seed=1)
     d = b.build_csr(ctx, g.n, g.u, g.v)
     for v in (b.default_variant(finish=b.FIN_SV), b.default_variant(finish=b.FIN_LT, lt_rules=b.LT_PRF),
-              b.default_variant(splice=b.SPLICE_ATOMIC)):
+              b.default_variant(splice=b.SPLICE_ATOMIC), b.default_variant(finish=b.FIN_LP)):
         with pytest.raises(b.CCError) as e:
             b.spanning_forest_csr(ctx, d, v)
         assert e.value.status == b.CC_EUNSUPPORTED

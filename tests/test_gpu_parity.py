@@ -118,9 +118,11 @@ def test_pair_list_entry_matches_oracle(ctx, vi):
         assert np.array_equal(lab.cpu().numpy(), want), (v, g)
 
 
-@pytest.mark.parametrize("vi", range(80))
+@pytest.mark.parametrize("vi", range(116))
 def test_every_variant_on_the_suite(ctx, vi):
-    v = b.all_variants()[vi]
+    """The 80 main variants and the 36 with the further finishes (UF-Early,
+    UF-Hooks, label propagation)."""
+    v = b.all_variants(extended=True)[vi]
     for g in SUITE:
         want, wc = oracle.labels(g)
         got, gc = _labels(ctx, g, v)
@@ -132,7 +134,7 @@ def test_every_variant_on_all_graphs_with_six_vertices(ctx):
     g = inputs.all_graphs_on(6)
     want, wc = oracle.labels(g)
     d = _csr(ctx, g)
-    for v in b.all_variants():
+    for v in b.all_variants(extended=True):
         lab, nc = b.connectivity_csr(ctx, d, v)
         assert int(nc.item()) == wc, v
         assert np.array_equal(lab.cpu().numpy(), want), v
@@ -141,7 +143,7 @@ def test_every_variant_on_all_graphs_with_six_vertices(ctx):
 def test_rem_counterexample_graph_every_variant(ctx):
     e = np.array([[0, 2], [1, 3], [2, 5], [3, 4], [4, 5]], np.int32)
     g = inputs.Graph(6, e[:, 0], e[:, 1])
-    for v in b.all_variants():
+    for v in b.all_variants(extended=True):
         got, gc = _labels(ctx, g, v)
         assert gc == 1 and got.tolist() == [0] * 6, v
     bad = b.default_variant(splice=b.SPLICE_ATOMIC, find=b.FIND_COMPRESS)
@@ -162,14 +164,16 @@ def test_seeds_change_nothing(ctx, seed):
 
 # ---- samplers ------------------------------------------------------------------------
 
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_kout_sample_matches_oracle_partition(ctx, k):
+def test_kout_sample_matches_oracle_partition(ctx, k, mode):
+    """Every edge choice (hybrid, afforest, pure, max-degree)."""
     for g in SUITE:
         d = _csr(ctx, g)
-        v = b.default_variant(kout_k=k, seed=1234)
+        v = b.default_variant(kout_k=k, kout_mode=mode, seed=1234)
         lab, lmax = b.sample_csr(ctx, d, v)
         off, adj = oracle.csr_build(g.n, g.u, g.v, True)
-        want, _ = oracle.kout_sample(g.n, off, adj, k, 1234)
+        want, _ = oracle.kout_sample(g.n, off, adj, k, 1234, mode=mode)
         assert np.array_equal(lab.cpu().numpy(), want), g
         # IdentifyFrequent over vertices with an edge, ties to the smaller label
         deg = np.diff(off)
@@ -209,13 +213,14 @@ def test_ldd_sample_is_a_partial_labelling_of_stars(ctx):
 def _stream_variants():
     vs = [b.default_variant(finish=b.FIN_UF_ASYNC, find=f) for f in range(4)]
     vs += [b.default_variant(finish=b.FIN_UF_REM_CAS, splice=s, find=0) for s in range(3)]
+    vs += [b.default_variant(finish=b.FIN_UF_EARLY, find=3), b.default_variant(finish=b.FIN_UF_HOOKS, find=1)]
     # type-2 streams: inserts in rounds (Shiloach-Vishkin, root-based Liu-Tarjan)
     vs += [b.default_variant(finish=b.FIN_SV)]
     vs += [b.default_variant(finish=b.FIN_LT, lt_rules=r) for r in sorted(b.LT_NAMES)]
     return vs
 
 
-@pytest.mark.parametrize("vi", range(14))
+@pytest.mark.parametrize("vi", range(16))
 def test_incremental_matches_oracle_on_every_prefix(ctx, vi):
     v = _stream_variants()[vi]
     n = 5000

@@ -25,7 +25,8 @@ def ctx():
 
 
 def _variants():
-    vs = [b.default_variant(finish=b.FIN_UF_ASYNC, find=f) for f in range(4)]
+    vs = [b.default_variant(finish=fin, find=f) for fin in (b.FIN_UF_ASYNC, b.FIN_UF_EARLY, b.FIN_UF_HOOKS)
+          for f in range(4)]
     vs += [b.default_variant(finish=b.FIN_UF_REM_CAS, splice=s, find=f) for s in range(3) for f in range(3)]
     vs += [b.default_variant(finish=b.FIN_SV)]
     vs += [b.default_variant(finish=b.FIN_LT, lt_rules=r) for r in sorted(b.LT_NAMES)]
@@ -100,7 +101,7 @@ def test_mixed_batches_are_linearizable(ctx, vi):
 def test_mixed_batch_edge_cases(ctx):
     dev = ctx.torch_device
     for v in (b.default_variant(finish=b.FIN_UF_ASYNC), b.default_variant(finish=b.FIN_SV),
-              b.default_variant(splice=b.SPLICE_ATOMIC)):
+              b.default_variant(splice=b.SPLICE_ATOMIC), b.default_variant(finish=b.FIN_UF_HOOKS)):
         st = b.Stream(ctx, 10, v)
         # empty batch, self-loops, a query on one vertex, repeated pairs
         st.process(torch.zeros(0, dtype=torch.uint8, device=dev), torch.zeros(0, dtype=torch.int32, device=dev),
@@ -144,3 +145,8 @@ def test_type2_stream_initialize_then_batches(ctx):
         lab, _ = st.labels()
         assert np.array_equal(lab.cpu().numpy(), inc.labels()[0])
         st.close()
+
+
+def test_label_propagation_is_not_a_stream(ctx):
+    with pytest.raises(b.CCError):
+        b.Stream(ctx, 10, b.default_variant(finish=b.FIN_LP))
