@@ -248,9 +248,79 @@ __device__ __forceinline__ void load4(const int32_t* p, int64_t v0, bool vec, in
 // neighbour (hybrid, afforest) or a seeded pick (pure), then with k-1 more
 // picks, using UF-Rem-CAS with SplitAtomicOne.  All picked neighbours of a
 // vertex are loaded before its first union so their latencies overlap.
+// Max-degree edge choice, before the unions: pick0[v] = row position of v's
+// neighbour of largest degree (the first on ties).  Rows of at most
+// kMaxdegLane entries are scanned by one lane; longer rows are listed and a
+// wave per row scans them with a wave-wide maximum.
+constexpr int kMaxdegLane = 64;
+
+__device__ __forceinline__ unsigned long long maxdeg_key(int64_t deg, int64_t t) {
+  // larger degree first, then smaller position
+  return ((unsigned long long)deg << 32) | (unsigned long long)(0xffffffffu - (uint32_t)t);
+}
+
+template <typename I>
+__global__ void __launch_bounds__(kBlock) k_maxdeg_short(int64_t n, const I* __restrict__ off,
+                                                         const int32_t* __restrict__ adj, int32_t* __restrict__ pick0,
+                                                         int32_t* __restrict__ longrows, int32_t* nlong) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+    const int64_t v = base + threadIdx.x;
+    int64_t b = 0, deg = 0;
+    if (v < n) {
+      b = (int64_t)off[v];
+      deg = (int64_t)off[v + 1] - b;
+    }
+    const bool lng = deg > kMaxdegLane;
+    const uint64_t m = __ballot(lng);
+    if (m) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      int32_t pos = 0;
+      if (lane_id() == leader) pos = atomicAdd(nlong, (int32_t)__popcll(m));
+      pos = __shfl(pos, leader, kWave);
+      if (lng) longrows[pos + __popcll(m & lanemask_lt_dev())] = (int32_t)v;
+    }
+    if (v >= n || deg <= 0 || lng) continue;
+    unsigned long long best = 0;
+    for (int64_t t = 0; t < deg; ++t) {
+      const int32_t x = adj[b + t];
+      const unsigned long long key = maxdeg_key((int64_t)off[x + 1] - (int64_t)off[x], t);
+      best = key > best ? key : best;
+    }
+    pick0[v] = (int32_t)(0xffffffffu - (uint32_t)(best & 0xffffffffull));
+  }
+}
+
+template <typename I>
+__global__ void __launch_bounds__(kBlock) k_maxdeg_long(const I* __restrict__ off, const int32_t* __restrict__ adj,
+                                                        const int32_t* __restrict__ longrows, const int32_t* nlong,
+                                                        int32_t* __restrict__ pick0) {
+  const int64_t c = *nlong;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < c; i += waves) {
+    const int32_t v = longrows[i];
+    const int64_t b = (int64_t)off[v];
+    const int64_t deg = (int64_t)off[v + 1] - b;
+    unsigned long long best = 0;
+    for (int64_t t = lane_id(); t < deg; t += kWave) {
+      const int32_t x = adj[b + t];
+      const unsigned long long key = maxdeg_key((int64_t)off[x + 1] - (int64_t)off[x], t);
+      best = key > best ? key : best;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long y = __shfl_xor(best, o, kWave);
+      best = y > best ? y : best;
+    }
+    if (lane_id() == 0) pick0[v] = (int32_t)(0xffffffffu - (uint32_t)(best & 0xffffffffull));
+  }
+}
+
+__global__ void k_zero_one_i32(int32_t* p) { *p = 0; }
+
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ adj,
-                                                 int32_t* P, int k, int mode, uint64_t key, int2* hook) {
+                                                 int32_t* P, int k, int mode, uint64_t key, int2* hook,
+                                                 const int32_t* __restrict__ pick0) {
   constexpr int kMaxPreload = 4;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
@@ -268,17 +338,7 @@ __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict_
       } else if (mode == CC_KOUT_HYBRID && j == 0) {
         idx = 0;
       } else if (mode == CC_KOUT_MAXDEG && j == 0) {
-        // the neighbour of largest degree, the first one on ties
-        idx = 0;
-        int64_t best = -1;
-        for (int64_t t = 0; t < deg; ++t) {
-          const int32_t x = adj[b + t];
-          const int64_t dx = (int64_t)off[x + 1] - (int64_t)off[x];
-          if (dx > best) {
-            best = dx;
-            idx = t;
-          }
-        }
+        idx = pick0[v];  // the neighbour of largest degree, the first one on ties
       } else {
         idx = (int64_t)(sm_out(key, (uint64_t)v * (uint64_t)k + (uint64_t)j) % (uint64_t)deg);
       }
@@ -811,8 +871,21 @@ static cc_status run_sample(StaticArgs& a) {
     case CC_SAMPLE_KOUT: {
       PhaseScope ps(a.ctx, a.s, "sample");
       const uint64_t key = sm_out(v->seed, kTagKout);
+      int32_t* pick0 = nullptr;
+      if (v->kout_mode == CC_KOUT_MAXDEG) {
+        // pick positions in the candidate array, the long rows in the
+        // big array, their count in a spare scalar (all free until the
+        // compaction)
+        pick0 = a.cand;
+        int32_t* nlong = &a.ctx->dev->hcount;
+        hipLaunchKernelGGL(k_zero_one_i32, dim3(1), dim3(1), 0, a.s, nlong);
+        hipLaunchKernelGGL(k_maxdeg_short<I>, dim3(grid_for(a.n, kBlock, kStreamGridCap)), dim3(kBlock), 0, a.s, a.n,
+                           (const I*)a.off, a.adj, pick0, a.big, nlong);
+        hipLaunchKernelGGL(k_maxdeg_long<I>, dim3(2048), dim3(kBlock), 0, a.s, (const I*)a.off, a.adj,
+                           (const int32_t*)a.big, (const int32_t*)nlong, pick0);
+      }
       hipLaunchKernelGGL(k_kout<I>, dim3(grid_for(a.n, kBlock, kStreamGridCap)), dim3(kBlock), 0, a.s, a.n,
-                         (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key, a.hook_e);
+                         (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key, a.hook_e, (const int32_t*)pick0);
       CC_LAUNCH_CHECK();
       use_lmax = true;
       break;
