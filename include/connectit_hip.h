@@ -408,7 +408,10 @@ cc_status cc_select_variant(cc_ctx* ctx, int64_t n, int64_t m, const void* offse
  * features, x = (f - norm_host[0:16]) / norm_host[16:32], the forward pass
  * and the argmin over the K arms (host array of variants) all run on the
  * device and are read back with one synchronisation, then the chosen arm
- * runs as cc_connectivity_csr.  params_dev NULL runs the default variant.
+ * runs as cc_connectivity_csr.  Algorithm 1's init (labels_out = identity,
+ * counts cleared), the same for every arm, is enqueued before the host
+ * waits, so it runs during the wait.  params_dev NULL runs the default
+ * variant.
  * chosen_host (nullable) gets the arm index (-1 for the default);
  * features_host (nullable) gets the 16 features.  workspace: at least the
  * largest cc_workspace_bytes over the arms and the default. */

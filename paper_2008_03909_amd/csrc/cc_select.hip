@@ -560,9 +560,11 @@ __global__ void __launch_bounds__(kFeatThreads) k_feat_final(int64_t n, int64_t 
 }
 
 // Features and, with a model, the chosen arm; one host synchronisation.
+// `pre` (nullable) is enqueued after the selector's kernels and before the
+// host waits for their answer, so that its device work overlaps the wait.
 template <typename I>
 static cc_status features_impl(StaticArgs& a, const uint16_t* params, int K, const float* norm_host, float* feat,
-                               int* chosen) {
+                               int* chosen, StaticArgs* pre) {
   char* sel = a.ws + a.L.mlp;
   double* part = (double*)(a.ws + a.L.count);
   int64_t* probe = (int64_t*)(sel + kSelProbe);
@@ -576,6 +578,10 @@ static cc_status features_impl(StaticArgs& a, const uint16_t* params, int K, con
   hipLaunchKernelGGL(k_feat_final, dim3(1), dim3(kFeatThreads), 0, a.s, a.n, a.m, (const double*)part, nb,
                      (const int64_t*)probe, params, K, na, a.ctx->sel_dev, seq);
   CC_LAUNCH_CHECK();
+  if (pre) {
+    cc_status st = static_init(*pre);
+    if (st != CC_OK) return st;
+  }
   // The final kernel writes straight into pinned host memory and then the
   // sequence number: poll for it (it arrives microseconds before a stream
   // synchronisation would return); after 50 ms fall back to synchronising,
@@ -599,9 +605,9 @@ static cc_status features_impl(StaticArgs& a, const uint16_t* params, int K, con
 }
 
 static cc_status features(StaticArgs& a, const uint16_t* params, int K, const float* norm_host, float* feat,
-                          int* chosen) {
-  return a.o64 ? features_impl<int64_t>(a, params, K, norm_host, feat, chosen)
-               : features_impl<int32_t>(a, params, K, norm_host, feat, chosen);
+                          int* chosen, StaticArgs* pre = nullptr) {
+  return a.o64 ? features_impl<int64_t>(a, params, K, norm_host, feat, chosen, pre)
+               : features_impl<int32_t>(a, params, K, norm_host, feat, chosen, pre);
 }
 
 }  // namespace cc
@@ -693,7 +699,7 @@ static cc_status check_selector_args(int64_t n, int64_t m, const uint16_t* param
 static cc_status select_arm(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int o64, const int32_t* adj,
                             const uint16_t* params_dev, int32_t K, const cc_variant* arms, const float* norm_host,
                             void* workspace, size_t ws_bytes, void* hip_stream, float* feat, int* chosen,
-                            cc_variant* use) {
+                            cc_variant* use, StaticArgs* pre = nullptr) {
   cc_variant def;
   cc_default_variant(&def);
   cc_status st = check_selector_args(n, m, params_dev, K, arms, norm_host, &def, ws_bytes, workspace);
@@ -702,7 +708,7 @@ static cc_status select_arm(cc_ctx* ctx, int64_t n, int64_t m, const void* offse
   st = setup_args(a, ctx, n, m, offsets, o64, adj, &def, workspace, ws_bytes, (int32_t*)workspace, nullptr,
                   hip_stream);
   if (st != CC_OK) return st;
-  st = features(a, params_dev, params_dev ? K : 0, norm_host, feat, chosen);
+  st = features(a, params_dev, params_dev ? K : 0, norm_host, feat, chosen, pre);
   if (st != CC_OK) return st;
   if (!params_dev) *chosen = -1;
   if (*chosen < -1 || *chosen >= K) return fail(CC_EDEVICE, "selector returned arm %d of %d", *chosen, K);
@@ -735,14 +741,26 @@ cc_status cc_connectivity_auto(cc_ctx* ctx, int64_t n, int64_t m, const void* of
   if (!labels_out) return fail(CC_EINVAL, "labels_out is NULL");
   float feat[kIn];
   int chosen;
-  cc_variant use;
-  cc_status st = select_arm(ctx, n, m, offsets, offsets_are_64bit, adj, params_dev, K, arms, norm_host, workspace,
-                            ws_bytes, hip_stream, feat, &chosen, &use);
+  cc_variant use, def;
+  cc_default_variant(&def);
+  // Algorithm 1's init is the same for every arm: it is enqueued behind the
+  // selector's kernels and runs while the host waits for the choice.  (The
+  // count array sits at the start of every variant's workspace layout.)
+  StaticArgs pre;
+  cc_status st = setup_args(pre, ctx, n, m, offsets, offsets_are_64bit, adj, &def, workspace, ws_bytes, labels_out,
+                            num_components_dev, hip_stream);
+  if (st != CC_OK) return st;
+  st = select_arm(ctx, n, m, offsets, offsets_are_64bit, adj, params_dev, K, arms, norm_host, workspace, ws_bytes,
+                  hip_stream, feat, &chosen, &use, &pre);
   if (st != CC_OK) return st;
   if (features_host) memcpy(features_host, feat, sizeof(feat));
   if (chosen_host) *chosen_host = chosen;
-  return cc_connectivity_csr(ctx, n, m, offsets, offsets_are_64bit, adj, &use, workspace, ws_bytes, labels_out,
-                             num_components_dev, hip_stream);
+  StaticArgs a;
+  st = setup_args(a, ctx, n, m, offsets, offsets_are_64bit, adj, &use, workspace, ws_bytes, labels_out,
+                  num_components_dev, hip_stream);
+  if (st != CC_OK) return st;
+  a.skip_init = true;
+  return static_run(a);
 }
 
 }  // extern "C"

@@ -27,6 +27,7 @@ struct StaticArgs {
   int2* tree_e = nullptr;    // spanning forest: BFS/LDD tree edge per claimed vertex (nullable)
   int2* hook_e = nullptr;    // spanning forest: union-find edge per hooked root (nullable)
   int64_t* ncomp_user = nullptr;
+  bool skip_init = false;    // init (P = identity, counts and scalars cleared) already enqueued
   int32_t sample_success = 1;
   int32_t sample_rounds = 0;
   int32_t finish_rounds = 0;
@@ -39,6 +40,9 @@ template <typename I> cc_status finish_sv(StaticArgs& a);
 template <typename I> cc_status finish_lt(StaticArgs& a);
 template <typename I> cc_status finish_lp(StaticArgs& a);
 
+// Algorithm 1's init on prepared arguments: scalars reset, P = identity,
+// frequency counts cleared (the same for every variant).
+cc_status static_init(StaticArgs& a);
 // The whole static algorithm on prepared arguments (statistics recorded).
 cc_status static_run(StaticArgs& a);
 // Recompresses the labels, resolves the frequent label (exact counts) and

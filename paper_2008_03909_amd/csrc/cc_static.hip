@@ -919,7 +919,7 @@ static cc_status run_tail(StaticArgs& a);
 
 template <typename I>
 static cc_status run_static(StaticArgs& a, bool sample_only) {
-  {
+  if (!a.skip_init) {
     PhaseScope ps(a.ctx, a.s, "init");
     hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, a.s, a.ctx->dev, (long long*)a.ncomp_user);
     hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P,
@@ -997,6 +997,14 @@ static cc_status run_tail(StaticArgs& a) {
 
 
 static void record_stats_host(StaticArgs& a);
+
+cc_status static_init(StaticArgs& a) {
+  PhaseScope ps(a.ctx, a.s, "init");
+  hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, a.s, a.ctx->dev, (long long*)a.ncomp_user);
+  hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P, a.count, vec_ok(a));
+  CC_LAUNCH_CHECK();
+  return CC_OK;
+}
 
 cc_status static_run(StaticArgs& a) {
   cc_status st = a.o64 ? run_static<int64_t>(a, false) : run_static<int32_t>(a, false);
