@@ -33,10 +33,12 @@ FAMILIES = ("er", "rmat", "grid2d", "grid3d", "star", "chain", "union")
 
 
 def arms():
-    """The K = 20 arms: {none, k-out, BFS, LDD} x {Rem-CAS/SplitAtomicOne,
+    """The K = 24 arms: {none, k-out, BFS, LDD} x {Rem-CAS/SplitAtomicOne,
     Rem-CAS/SpliceAtomic, Async/FindAtomicSplit, Shiloach-Vishkin}, then four
     k-out edge choices with Rem-CAS/SplitAtomicOne: hybrid k = 1, afforest
-    k = 1 and k = 2, hybrid k = 3."""
+    k = 1 and k = 2, hybrid k = 3; then k-out with the further finishes
+    UF-Early/FindNaive, UF-Hooks/FindAtomicSplit and label propagation, and
+    the max-degree edge choice with Rem-CAS/SplitAtomicOne."""
     base = b.default_variant()
     fins = [dict(finish=b.FIN_UF_REM_CAS, splice=b.SPLICE_SPLIT_ONE, find=b.FIND_NAIVE),
             dict(finish=b.FIN_UF_REM_CAS, splice=b.SPLICE_ATOMIC, find=b.FIND_NAIVE),
@@ -48,6 +50,10 @@ def arms():
             out.append(base.copy(sample=s, **f))
     for k, mode in ((1, b.KOUT_HYBRID), (1, b.KOUT_AFFOREST), (2, b.KOUT_AFFOREST), (3, b.KOUT_HYBRID)):
         out.append(base.copy(kout_k=k, kout_mode=mode))
+    out.append(base.copy(finish=b.FIN_UF_EARLY, find=b.FIND_NAIVE, splice=0))
+    out.append(base.copy(finish=b.FIN_UF_HOOKS, find=b.FIND_ATOMIC_SPLIT, splice=0))
+    out.append(base.copy(finish=b.FIN_LP, find=0, splice=0))
+    out.append(base.copy(kout_mode=b.KOUT_MAXDEG))
     return out
 
 
