@@ -72,12 +72,15 @@ enum { CC_FIND_NAIVE = 0, CC_FIND_ATOMIC_SPLIT = 1, CC_FIND_ATOMIC_HALVE = 2, CC
 /* Splice options of Rem's algorithm (appendix "Splice Algorithms"). */
 enum { CC_SPLICE_SPLIT_ONE = 0, CC_SPLICE_HALVE_ONE = 1, CC_SPLICE_ATOMIC = 2 };
 /* Liu-Tarjan rule bits (appendix "Liu-Tarjan Algorithms").  Connect kind in
- * the low two bits; the other bits add RootUp, FullShortcut (else one
- * Shortcut step per round) and Alter.  Only the root-based (RootUp)
- * combinations are accepted: CRSA, PRSA, PRS, CRFA, PRFA, PRF. */
+ * the low two bits (Connect, ParentConnect, ExtendedConnect); the other bits
+ * add RootUp, FullShortcut (else one Shortcut step per round) and Alter.
+ * The appendix's 16 combinations are accepted: the root-based CRSA, PRSA,
+ * PRS, CRFA, PRFA, PRF, and the non-root-based CUSA, PUSA, PUS, EUSA, EUS,
+ * CUFA, PUFA, PUF, EUFA, EUF (not as stream finishes). */
 enum {
   CC_LT_CONNECT = 0,
   CC_LT_PARENT_CONNECT = 1,
+  CC_LT_EXTENDED_CONNECT = 2,
   CC_LT_ROOTUP = 4,
   CC_LT_FULL_SHORTCUT = 8,
   CC_LT_ALTER = 16
@@ -88,6 +91,16 @@ enum {
 #define CC_LT_CRFA (CC_LT_CONNECT | CC_LT_ROOTUP | CC_LT_FULL_SHORTCUT | CC_LT_ALTER)
 #define CC_LT_PRFA (CC_LT_PARENT_CONNECT | CC_LT_ROOTUP | CC_LT_FULL_SHORTCUT | CC_LT_ALTER)
 #define CC_LT_PRF (CC_LT_PARENT_CONNECT | CC_LT_ROOTUP | CC_LT_FULL_SHORTCUT)
+#define CC_LT_CUSA (CC_LT_CONNECT | CC_LT_ALTER)
+#define CC_LT_PUSA (CC_LT_PARENT_CONNECT | CC_LT_ALTER)
+#define CC_LT_PUS (CC_LT_PARENT_CONNECT)
+#define CC_LT_EUSA (CC_LT_EXTENDED_CONNECT | CC_LT_ALTER)
+#define CC_LT_EUS (CC_LT_EXTENDED_CONNECT)
+#define CC_LT_CUFA (CC_LT_CONNECT | CC_LT_FULL_SHORTCUT | CC_LT_ALTER)
+#define CC_LT_PUFA (CC_LT_PARENT_CONNECT | CC_LT_FULL_SHORTCUT | CC_LT_ALTER)
+#define CC_LT_PUF (CC_LT_PARENT_CONNECT | CC_LT_FULL_SHORTCUT)
+#define CC_LT_EUFA (CC_LT_EXTENDED_CONNECT | CC_LT_FULL_SHORTCUT | CC_LT_ALTER)
+#define CC_LT_EUF (CC_LT_EXTENDED_CONNECT | CC_LT_FULL_SHORTCUT)
 
 /* One sampling x finish combination (Algorithm 1's sample_opt/finish_opt).
  *  - kout_k >= 1 edges per vertex (paper default 2);

@@ -21,7 +21,7 @@ FIN_UF_REM_CAS, FIN_UF_ASYNC, FIN_SV, FIN_LT = 0, 1, 2, 3
 FIN_UF_EARLY, FIN_UF_HOOKS, FIN_LP = 4, 5, 6
 FIND_NAIVE, FIND_ATOMIC_SPLIT, FIND_ATOMIC_HALVE, FIND_COMPRESS = 0, 1, 2, 3
 SPLICE_SPLIT_ONE, SPLICE_HALVE_ONE, SPLICE_ATOMIC = 0, 1, 2
-LT_CONNECT, LT_PARENT_CONNECT, LT_ROOTUP, LT_FULL_SHORTCUT, LT_ALTER = 0, 1, 4, 8, 16
+LT_CONNECT, LT_PARENT_CONNECT, LT_EXTENDED_CONNECT, LT_ROOTUP, LT_FULL_SHORTCUT, LT_ALTER = 0, 1, 2, 4, 8, 16
 LT_CRSA = LT_CONNECT | LT_ROOTUP | LT_ALTER
 LT_PRSA = LT_PARENT_CONNECT | LT_ROOTUP | LT_ALTER
 LT_PRS = LT_PARENT_CONNECT | LT_ROOTUP
@@ -29,6 +29,15 @@ LT_CRFA = LT_CONNECT | LT_ROOTUP | LT_FULL_SHORTCUT | LT_ALTER
 LT_PRFA = LT_PARENT_CONNECT | LT_ROOTUP | LT_FULL_SHORTCUT | LT_ALTER
 LT_PRF = LT_PARENT_CONNECT | LT_ROOTUP | LT_FULL_SHORTCUT
 LT_NAMES = {LT_CRSA: "CRSA", LT_PRSA: "PRSA", LT_PRS: "PRS", LT_CRFA: "CRFA", LT_PRFA: "PRFA", LT_PRF: "PRF"}
+# the non-root-based variants (appendix "Liu-Tarjan Algorithms")
+LT_NONROOT = {
+    "CUSA": LT_CONNECT | LT_ALTER, "PUSA": LT_PARENT_CONNECT | LT_ALTER, "PUS": LT_PARENT_CONNECT,
+    "EUSA": LT_EXTENDED_CONNECT | LT_ALTER, "EUS": LT_EXTENDED_CONNECT,
+    "CUFA": LT_CONNECT | LT_FULL_SHORTCUT | LT_ALTER, "PUFA": LT_PARENT_CONNECT | LT_FULL_SHORTCUT | LT_ALTER,
+    "PUF": LT_PARENT_CONNECT | LT_FULL_SHORTCUT, "EUFA": LT_EXTENDED_CONNECT | LT_FULL_SHORTCUT | LT_ALTER,
+    "EUF": LT_EXTENDED_CONNECT | LT_FULL_SHORTCUT,
+}
+LT_NAMES.update({r: name for name, r in LT_NONROOT.items()})
 
 
 class cc_variant(ctypes.Structure):
@@ -788,19 +797,22 @@ def all_finishes():
 
 
 def extra_finishes():
-    """The 9 further finishes of Section 3.3 and the appendix: UF-Early and
-    UF-Hooks with each find, and label propagation."""
+    """The 19 further finishes of Section 3.3 and the appendix: UF-Early and
+    UF-Hooks with each find, label propagation, and the 10 non-root-based
+    Liu-Tarjan variants."""
     out = []
     for fin in (FIN_UF_EARLY, FIN_UF_HOOKS):
         for fd in (FIND_NAIVE, FIND_ATOMIC_SPLIT, FIND_ATOMIC_HALVE, FIND_COMPRESS):
             out.append(dict(finish=fin, find=fd, splice=0))
     out.append(dict(finish=FIN_LP, find=0, splice=0))
+    for r in LT_NONROOT.values():
+        out.append(dict(finish=FIN_LT, lt_rules=r, find=0, splice=0))
     return out
 
 
 def all_variants(seed: int = 0x5EED, extended: bool = False):
     """Every sampling x finish combination: the 80 of the main table
-    (4 samplers x 20 finishes); with extended=True 36 more follow them (the
+    (4 samplers x 20 finishes); with extended=True 76 more follow them (the
     4 samplers x extra_finishes()), so indices below 80 never change."""
     base = default_variant(seed=seed)
     out = []

@@ -362,12 +362,6 @@ cc_status edge_list_rounds(cc_ctx* ctx, hipStream_t s, const cc_variant& v, int6
   return CC_OK;
 }
 
-template <typename I>
-cc_status finish_lt(StaticArgs& a) {
-  if ((a.v->lt_rules & 3u) == CC_LT_PARENT_CONNECT) return lt_rounds<I, true>(a);
-  return lt_rounds<I, false>(a);
-}
-
 // ---- label propagation (appendix "Label Propagation") ---------------------
 // Labels are the parent array read as labels.  The frequent sampled class
 // is first relabelled to -1, below every id, so its vertices never change
@@ -453,6 +447,190 @@ cc_status finish_lp(StaticArgs& a) {
   hipLaunchKernelGGL(k_lp_fix, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, (const int32_t*)a.count, (int)gm);
   CC_LAUNCH_CHECK();
   return CC_OK;
+}
+
+// ---- Liu-Tarjan, non-root-based variants ------------------------------------
+// Any vertex may take a smaller candidate as its parent, so a non-root can
+// move between trees and the method is not monotone; it is composed with
+// sampling as label propagation is (appendix "Correctness for Other
+// Min-Based Methods"): the frequent sampled class is relabelled to a
+// virtual vertex -1, below every id, which never changes and whose own
+// parent is itself.  Edges in the Alter list may then have -1 as an
+// endpoint, so a dead entry is marked with kDead instead.
+constexpr int32_t kDead = (int32_t)0x80000000;
+
+__device__ __forceinline__ int32_t vsnap(const int32_t* Q, int32_t x) { return x < 0 ? -1 : Q[x]; }
+
+// update(x, c) without RootUp: the parent of any real vertex becomes
+// min(P[x], c).
+__device__ __forceinline__ bool lt_update_any(int32_t* P, int32_t x, int32_t c) {
+  if (x < 0) return false;
+  if (c >= ld(P + x)) return false;
+  return c < amin(P + x, c);
+}
+
+// CONN 0 Connect (the endpoints are each other's candidates), 1
+// ParentConnect (the endpoints' round-start parents, for those parents),
+// 2 ExtendedConnect (the round-start parents, for both the endpoints and
+// their parents).
+template <int CONN>
+struct LtConnectAny {
+  int32_t* P;
+  const int32_t* Q;
+  __device__ __forceinline__ bool operator()(int32_t v, int32_t w, int64_t) const {
+    if (CONN == 0) {
+      if (v == w) return false;
+      const bool x = lt_update_any(P, v, w);
+      const bool y = lt_update_any(P, w, v);
+      return x || y;
+    }
+    const int32_t pv = vsnap(Q, v), pw = vsnap(Q, w);
+    if (pv == pw) return false;
+    bool ch = lt_update_any(P, pv, pw);
+    ch |= lt_update_any(P, pw, pv);
+    if (CONN == 2) {
+      ch |= lt_update_any(P, v, pw);
+      ch |= lt_update_any(P, w, pv);
+    }
+    return ch;
+  }
+};
+
+template <class Op>
+__global__ void k_edge_list_v(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                              const unsigned long long* cnt, Op op, uint32_t* flag) {
+  const int64_t c = (int64_t)*cnt;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool any = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c; i += stride) {
+    const int32_t a = eu[i];
+    if (a == kDead) continue;
+    any |= op(a, ev[i], i);
+  }
+  wave_flag(any, flag);
+}
+
+// Emitted self-loops (-1) become kDead before -1 means the virtual vertex.
+__global__ void k_mark_dead(int32_t* eu, const unsigned long long* cnt) {
+  const int64_t c = (int64_t)*cnt;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c; i += stride)
+    if (eu[i] == -1) eu[i] = kDead;
+}
+
+__global__ void k_lt_alter_v(int32_t* eu, int32_t* ev, const unsigned long long* cnt, const int32_t* P,
+                             uint32_t* flag) {
+  const int64_t c = (int64_t)*cnt;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool any = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < c; i += stride) {
+    const int32_t a = eu[i];
+    if (a == kDead) continue;
+    const int32_t b = ev[i];
+    const int32_t pa = a < 0 ? -1 : ld(P + a), pb = b < 0 ? -1 : ld(P + b);
+    if (pa == pb) {
+      eu[i] = kDead;
+    } else if (pa != a || pb != b) {
+      eu[i] = pa;
+      ev[i] = pb;
+      any = true;
+    }
+  }
+  wave_flag(any, flag);
+}
+
+// Shortcut with the virtual vertex: one step P[v] = P[P[v]], or the full
+// walk to the root (a real root or -1).  Parents only decrease.
+__global__ void k_shortcut_v(int64_t n, int32_t* P, int full, uint32_t* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool any = false;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int32_t p = ld(P + v);
+    if (p < 0 || p == (int32_t)v) continue;
+    int32_t r = ld(P + p);
+    if (full) {
+      int32_t q = p;
+      while (r >= 0 && r != q) {
+        q = r;
+        r = ld(P + q);
+      }
+      if (r >= 0) r = q;  // a real root; else the walk ended at -1
+    }
+    if (r < p) {
+      amin(P + v, r);
+      any = true;
+    }
+  }
+  wave_flag(any, flag);
+}
+
+template <typename I, int CONN>
+static cc_status lt_rounds_nonroot(StaticArgs& a) {
+  DevScalars* sc = a.ctx->dev;
+  const uint32_t rules = a.v->lt_rules;
+  const bool full = rules & CC_LT_FULL_SHORTCUT;
+  const bool alter = rules & CC_LT_ALTER;
+  int32_t* Q = a.count;
+  int32_t* eu = nullptr;
+  int32_t* ev = nullptr;
+  unsigned long long* ecnt = (unsigned long long*)&sc->frontier_edges;
+  const unsigned g = grid_for(a.n, kFBlock, 4096);
+  hipLaunchKernelGGL(k_lp_mark, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, (const DevScalars*)sc);
+  if (alter) {
+    eu = (int32_t*)(a.ws + a.L.edges);
+    ev = (int32_t*)(a.ws + a.L.edges + align256((size_t)a.m * 4));
+    hipLaunchKernelGGL(k_lt_emit_base, dim3(1), dim3(1), 0, a.s, (const long long*)a.hp, (const DevScalars*)sc, ecnt);
+    hipLaunchKernelGGL(k_lt_emit_heavy<I>, dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
+                       (const DevScalars*)sc, (const long long*)a.hp, (const I*)a.off, a.adj, eu, ev);
+    hipLaunchKernelGGL(k_lt_emit<I>, dim3(grid_for(a.n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, a.n,
+                       (const int32_t*)a.cand, (const int32_t*)a.big, (const DevScalars*)sc, (const I*)a.off, a.adj,
+                       eu, ev, ecnt);
+    hipLaunchKernelGGL(k_mark_dead, dim3(grid_for(a.m, kFBlock, 8192)), dim3(kFBlock), 0, a.s, eu,
+                       (const unsigned long long*)ecnt);
+  }
+  for (int round = 0;; ++round) {
+    if (round >= kRoundCap) return fail(CC_ELIVELOCK, "Liu-Tarjan exceeded %d rounds", kRoundCap);
+    if (a.ctx->round_limit > 0 && round >= a.ctx->round_limit)
+      return fail(CC_ELIVELOCK, "Liu-Tarjan reached the context's round limit (%d)", a.ctx->round_limit);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->changed, 0u);
+    hipLaunchKernelGGL(k_copy_i32, dim3(g), dim3(kFBlock), 0, a.s, a.n, (const int32_t*)a.P, Q);
+    const LtConnectAny<CONN> op{a.P, Q};
+    if (alter)
+      hipLaunchKernelGGL(k_edge_list_v<LtConnectAny<CONN>>, dim3(grid_for(a.m, kFBlock, 8192)), dim3(kFBlock), 0,
+                         a.s, (const int32_t*)eu, (const int32_t*)ev, (const unsigned long long*)ecnt, op,
+                         &sc->changed);
+    else
+      visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, op, &sc->changed);
+    hipLaunchKernelGGL(k_shortcut_v, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, full ? 1 : 0, &sc->changed);
+    if (alter)
+      hipLaunchKernelGGL(k_lt_alter_v, dim3(grid_for(a.m, kFBlock, 8192)), dim3(kFBlock), 0, a.s, eu, ev,
+                         (const unsigned long long*)ecnt, (const int32_t*)a.P, &sc->changed);
+    CC_LAUNCH_CHECK();
+    ++a.finish_rounds;
+    uint32_t changed = 0;
+    cc_status st = read_flag(a, &changed);
+    if (st != CC_OK) return st;
+    if (!changed) break;
+  }
+  // the virtual vertex's class takes its smallest member (minima of the
+  // count array's blocks first; the snapshot is no longer needed)
+  const unsigned gm = grid_for(a.n, kFBlock, 1024);
+  hipLaunchKernelGGL(k_lp_min, dim3(gm), dim3(kFBlock), 0, a.s, a.n, (const int32_t*)a.P, a.count);
+  hipLaunchKernelGGL(k_lp_fix, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, (const int32_t*)a.count, (int)gm);
+  CC_LAUNCH_CHECK();
+  return CC_OK;
+}
+
+template <typename I>
+cc_status finish_lt(StaticArgs& a) {
+  const uint32_t conn = a.v->lt_rules & 3u;
+  if (!(a.v->lt_rules & CC_LT_ROOTUP)) {
+    if (conn == CC_LT_PARENT_CONNECT) return lt_rounds_nonroot<I, 1>(a);
+    if (conn == CC_LT_EXTENDED_CONNECT) return lt_rounds_nonroot<I, 2>(a);
+    return lt_rounds_nonroot<I, 0>(a);
+  }
+  if (conn == CC_LT_PARENT_CONNECT) return lt_rounds<I, true>(a);
+  return lt_rounds<I, false>(a);
 }
 
 template cc_status finish_sv<int32_t>(StaticArgs&);

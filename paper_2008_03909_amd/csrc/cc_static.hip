@@ -132,10 +132,16 @@ cc_status check_variant(const cc_variant* v, bool for_stream) {
       break;
     case CC_FIN_LT: {
       uint32_t r = v->lt_rules;
-      const uint32_t ok[] = {CC_LT_CRSA, CC_LT_PRSA, CC_LT_PRS, CC_LT_CRFA, CC_LT_PRFA, CC_LT_PRF};
-      bool found = false;
-      for (uint32_t x : ok) found |= (r == x);
-      if (!found) return fail(CC_EUNSUPPORTED, "only the root-based Liu-Tarjan variants are built (rules=%u)", r);
+      const uint32_t root[] = {CC_LT_CRSA, CC_LT_PRSA, CC_LT_PRS, CC_LT_CRFA, CC_LT_PRFA, CC_LT_PRF};
+      const uint32_t nonroot[] = {CC_LT_CUSA, CC_LT_PUSA, CC_LT_PUS, CC_LT_EUSA, CC_LT_EUS,
+                                  CC_LT_CUFA, CC_LT_PUFA, CC_LT_PUF, CC_LT_EUFA, CC_LT_EUF};
+      bool is_root = false, is_nonroot = false;
+      for (uint32_t x : root) is_root |= (r == x);
+      for (uint32_t x : nonroot) is_nonroot |= (r == x);
+      if (!is_root && !is_nonroot)
+        return fail(CC_EUNSUPPORTED, "rules=%u is not one of the 16 Liu-Tarjan variants of the appendix", r);
+      if (for_stream && !is_root)
+        return fail(CC_EUNSUPPORTED, "stream finishes use the root-based Liu-Tarjan variants only");
       break;
     }
     default:

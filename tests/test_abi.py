@@ -52,8 +52,8 @@ def test_extended_variants_are_accepted():
     """UF-Early / UF-Hooks (any find) and label propagation, under every
     sampler, follow the 80 main variants; k-out's max-degree edge choice."""
     vs = b.all_variants(extended=True)
-    assert len(vs) == 116 and [v.name() for v in vs[:80]] == [v.name() for v in b.all_variants()]
-    assert len({v.name() for v in vs}) == 116
+    assert len(vs) == 156 and [v.name() for v in vs[:80]] == [v.name() for v in b.all_variants()]
+    assert len({v.name() for v in vs}) == 156
     for v in vs:
         assert b.check_variant(v) == b.CC_OK, v
     assert b.check_variant(b.default_variant(kout_mode=b.KOUT_MAXDEG)) == b.CC_OK
@@ -80,11 +80,15 @@ def test_bad_variant_fields(field, value, code):
     assert b.check_variant(v) == code
 
 
-def test_non_root_liu_tarjan_is_unsupported():
-    v = b.default_variant(finish=b.FIN_LT, lt_rules=b.LT_CONNECT | b.LT_ALTER)   # CUSA: not root-based
-    assert b.check_variant(v) == b.CC_EUNSUPPORTED
+def test_liu_tarjan_rule_sets():
+    """The appendix's 16 combinations are accepted; other rule sets (e.g.
+    Connect without Alter, which the appendix notes is incorrect) are not."""
+    v = b.default_variant(finish=b.FIN_LT)
+    assert len(b.LT_NAMES) == 16
     for r in b.LT_NAMES:
         assert b.check_variant(v.copy(lt_rules=r)) == b.CC_OK
+    for r in (b.LT_CONNECT, b.LT_CONNECT | b.LT_FULL_SHORTCUT, b.LT_EXTENDED_CONNECT | b.LT_ROOTUP, 3):
+        assert b.check_variant(v.copy(lt_rules=r)) == b.CC_EUNSUPPORTED
 
 
 def test_workspace_sizes_grow_with_the_variant():

@@ -56,15 +56,18 @@ def test_rmat_2_24(ctx):
 
 
 def test_rmat_2_24_further_finishes(ctx):
-    """UF-Early, UF-Hooks and label propagation (with k-out and without
-    sampling) and k-out's max-degree edge choice."""
+    """UF-Early, UF-Hooks, label propagation and non-root-based Liu-Tarjan
+    (with k-out and without sampling) and k-out's max-degree edge choice."""
     g = inputs.workload_rmat(24, 8, seed=2)
     base = b.default_variant()
     _check(ctx, g, [base.copy(finish=b.FIN_UF_EARLY, find=b.FIND_NAIVE),
                     base.copy(finish=b.FIN_UF_HOOKS, find=b.FIND_ATOMIC_SPLIT),
                     base.copy(finish=b.FIN_LP), base.copy(sample=b.SAMPLE_NONE, finish=b.FIN_LP),
                     base.copy(sample=b.SAMPLE_NONE, finish=b.FIN_UF_EARLY, find=b.FIND_COMPRESS),
-                    base.copy(kout_mode=b.KOUT_MAXDEG)])
+                    base.copy(kout_mode=b.KOUT_MAXDEG),
+                    base.copy(finish=b.FIN_LT, lt_rules=b.LT_NONROOT["CUSA"]),
+                    base.copy(finish=b.FIN_LT, lt_rules=b.LT_NONROOT["EUF"]),
+                    base.copy(sample=b.SAMPLE_NONE, finish=b.FIN_LT, lt_rules=b.LT_NONROOT["PUSA"])])
 
 
 def test_grid_256_cubed(ctx):

@@ -118,10 +118,10 @@ def test_pair_list_entry_matches_oracle(ctx, vi):
         assert np.array_equal(lab.cpu().numpy(), want), (v, g)
 
 
-@pytest.mark.parametrize("vi", range(116))
+@pytest.mark.parametrize("vi", range(156))
 def test_every_variant_on_the_suite(ctx, vi):
-    """The 80 main variants and the 36 with the further finishes (UF-Early,
-    UF-Hooks, label propagation)."""
+    """The 80 main variants and the 76 with the further finishes (UF-Early,
+    UF-Hooks, label propagation, non-root-based Liu-Tarjan)."""
     v = b.all_variants(extended=True)[vi]
     for g in SUITE:
         want, wc = oracle.labels(g)
@@ -216,7 +216,7 @@ def _stream_variants():
     vs += [b.default_variant(finish=b.FIN_UF_EARLY, find=3), b.default_variant(finish=b.FIN_UF_HOOKS, find=1)]
     # type-2 streams: inserts in rounds (Shiloach-Vishkin, root-based Liu-Tarjan)
     vs += [b.default_variant(finish=b.FIN_SV)]
-    vs += [b.default_variant(finish=b.FIN_LT, lt_rules=r) for r in sorted(b.LT_NAMES)]
+    vs += [b.default_variant(finish=b.FIN_LT, lt_rules=r) for r in (b.LT_CRSA, b.LT_PRSA, b.LT_PRS, b.LT_CRFA, b.LT_PRFA, b.LT_PRF)]
     return vs
 
 

@@ -29,7 +29,7 @@ def _variants():
           for f in range(4)]
     vs += [b.default_variant(finish=b.FIN_UF_REM_CAS, splice=s, find=f) for s in range(3) for f in range(3)]
     vs += [b.default_variant(finish=b.FIN_SV)]
-    vs += [b.default_variant(finish=b.FIN_LT, lt_rules=r) for r in sorted(b.LT_NAMES)]
+    vs += [b.default_variant(finish=b.FIN_LT, lt_rules=r) for r in (b.LT_CRSA, b.LT_PRSA, b.LT_PRS, b.LT_CRFA, b.LT_PRFA, b.LT_PRF)]
     return vs
 
 
@@ -147,6 +147,7 @@ def test_type2_stream_initialize_then_batches(ctx):
         st.close()
 
 
-def test_label_propagation_is_not_a_stream(ctx):
-    with pytest.raises(b.CCError):
-        b.Stream(ctx, 10, b.default_variant(finish=b.FIN_LP))
+def test_non_streaming_finishes_are_refused(ctx):
+    for v in (b.default_variant(finish=b.FIN_LP), b.default_variant(finish=b.FIN_LT, lt_rules=b.LT_NONROOT["PUS"])):
+        with pytest.raises(b.CCError):
+            b.Stream(ctx, 10, v)
