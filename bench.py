@@ -586,6 +586,12 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                 "traffic": traffic, "kernel": dom_kernel, "phase": dom,
                 "alg_bytes_per_launch": ph_out[dom]["alg_bytes"], "avg_launch_ms": ph_out[dom]["avg_ms"]}
+    if traffic:
+        # the measured HBM bytes per launch over this run's launch time: the
+        # rate the memory system actually delivered (line-granular traffic)
+        tg = traffic / (ph_out[dom]["avg_ms"] / 1e3) / 1e9
+        roofline["traffic_gbs"] = round(tg, 1)
+        roofline["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
 
     out = {
         "metric": "static CC edges/s + HBM GB/s; incremental updates/s with p50/p99 latency",
