@@ -160,6 +160,11 @@ cc_status cc_last_stats(cc_ctx* ctx, cc_stats* out);
  * names are stable strings ("init", "sample", "compress_count", "frequent",
  * "compact", "finish", "output", ...). */
 cc_status cc_ctx_set_timing(cc_ctx* ctx, int enable);
+/* Restricts the recording to the phase named `name` (NULL or "": every
+ * phase).  Each recorded event makes the stream wait for the work enqueued
+ * before it (about 10 us per event pair here), so timing one phase perturbs
+ * a call far less than timing all of them. */
+cc_status cc_ctx_set_timing_phase(cc_ctx* ctx, const char* name);
 /* Caps the rounds of every round-based phase (BFS levels per try, SV and LT
  * rounds) at `limit` (0 = only the built-in caps); a call that reaches it
  * returns CC_ELIVELOCK, its labels undefined.  A measurement aid for timing

@@ -122,6 +122,7 @@ def lib():
             "cc_last_stats": (_int, [_vp, ctypes.POINTER(cc_stats)]),
             "cc_ctx_set_timing": (_int, [_vp, _int]),
             "cc_ctx_set_round_limit": (_int, [_vp, ctypes.c_int32]),
+            "cc_ctx_set_timing_phase": (_int, [_vp, ctypes.c_char_p]),
             "cc_phase_times": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
             "cc_phase_times_reset": (None, [_vp]),
@@ -292,7 +293,9 @@ class Context:
         _check(lib().cc_last_stats(self.h, ctypes.byref(s)), "cc_last_stats")
         return s.as_dict()
 
-    def set_timing(self, on: bool):
+    def set_timing(self, on: bool, only: str | None = None):
+        """Phase events on (every phase, or only the phase named `only`)."""
+        _check(lib().cc_ctx_set_timing_phase(self.h, (only or "").encode()), "cc_ctx_set_timing_phase")
         _check(lib().cc_ctx_set_timing(self.h, int(on)), "cc_ctx_set_timing")
 
     def set_round_limit(self, limit: int):

@@ -56,6 +56,7 @@ struct cc_ctx {
   int round_limit = 0;  // 0: the built-in caps only
   // phase timing
   int timing = 0;
+  std::string timing_only;                  // non-empty: record only the phase of this name
   std::vector<cc::PhaseRec> pending;        // events of calls not yet harvested
   std::vector<hipEvent_t> event_pool;
   std::vector<std::string> phase_names;

@@ -61,7 +61,9 @@ static hipEvent_t get_event(cc_ctx* ctx) {
 }
 
 PhaseScope::PhaseScope(cc_ctx* c, hipStream_t st, const char* nm) : ctx(c), s(st), name(nm) {
-  if (ctx && ctx->timing) {
+  // each recorded event makes the stream wait for the work before it, so a
+  // measurement of one phase records only that phase's pair
+  if (ctx && ctx->timing && (ctx->timing_only.empty() || ctx->timing_only == nm)) {
     a = get_event(ctx);
     if (a) hipEventRecord(a, s);
   }
@@ -1150,6 +1152,12 @@ cc_status cc_ctx_set_round_limit(cc_ctx* ctx, int32_t limit) {
 cc_status cc_ctx_set_timing(cc_ctx* ctx, int enable) {
   if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
   ctx->timing = enable;
+  return CC_OK;
+}
+
+cc_status cc_ctx_set_timing_phase(cc_ctx* ctx, const char* name) {
+  if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+  ctx->timing_only = name ? name : "";
   return CC_OK;
 }
 
