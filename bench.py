@@ -603,7 +603,9 @@ def main():
     if args.phases:
         for k_, x in ph_out.items():
             log(f"  {k_:16s} {x}")
-    dom_kernel = {"sample": "k_kout", "compress_count": "k_compress_count", "init": "k_init",
+    sampler_kernel = {b.SAMPLE_KOUT: "k_kout", b.SAMPLE_BFS: "bfs levels (k_bfs_*)",
+                      b.SAMPLE_LDD: "ldd rounds (k_ldd_wake, k_expand*)"}.get(v.sample, "none")
+    dom_kernel = {"sample": sampler_kernel, "compress_count": "k_compress_count", "init": "k_init",
                   "frequent": "k_argmax", "compact": "k_compact", "finish": "k_fin", "output": "k_output"}.get(dom, dom)
     achieved = ph_out[dom]["alg_gbs"]
     traffic = read_traffic(dom_kernel, args.workload)

@@ -107,7 +107,8 @@ enum {
  *  - bfs_tries >= 1 BFS attempts (paper text: 3), success iff the reached
  *    component holds more than n/10 vertices;
  *  - ldd_beta in (0, 1) (paper default 0.2); ldd_permute must be 0 (the
- *    paper's default ordering; vertex 0 wakes first);
+ *    paper's default ordering; vertex 0 wakes first); LDD takes graphs
+ *    with m < 2^36 adjacency entries (CC_EINVAL above);
  *  - find/splice: for UF-Rem-CAS any splice with find in {NAIVE,
  *    ATOMIC_SPLIT, ATOMIC_HALVE}; for UF-Async any find; FIND_COMPRESS with
  *    Rem-CAS (which includes the SpliceAtomic + FindCompress combination of

@@ -447,11 +447,21 @@ void list_prefix(StaticArgs& a, const int32_t* list, const int32_t* count_ptr) {
 // search over the 64 row starts in LDS.  Rows above kHeavyFrontier are
 // deferred to the grid kernel.  Claimed vertices go through a wave-private
 // LDS buffer, so the output queue's counter is bumped once per flush.
+// Heavy rows are listed with their edge offsets reserved at the same time:
+// one 64-bit atomic per wave adds (rows << 36 | edges) to `pack`, so slot i
+// gets hp[i] = the edges listed before it and the offsets come out sorted
+// by slot -- the prefix the grid kernel searches, with no separate scan.
+// A round lists at most m / 256 + 2 rows holding at most m entries, so both
+// fields fit while m < 2^36 (the sampler refuses larger graphs).
+constexpr int kPackShift = 36;
+constexpr unsigned long long kPackEdges = (1ull << kPackShift) - 1;
+
 template <bool LDD, typename I>
 __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ qin, const uint32_t* cnt_in,
                                                     int32_t* qout, uint32_t* cnt_out, const I* __restrict__ off,
                                                     const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
-                                                    int32_t* P, int32_t* heavy, int32_t* hcount, int2* tree) {
+                                                    int32_t* P, int32_t* heavy, long long* hp,
+                                                    unsigned long long* pack, int2* tree) {
   constexpr int W = kFBlock / kWave;
   __shared__ int32_t qbuf[W][kWaveQCap];
   __shared__ int32_t tpre[W][kWave + 1];
@@ -474,7 +484,26 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
       d = (int64_t)off[u + 1] - b;
     }
     const bool heavy_row = d > kHeavyFrontier;
-    wave_append(heavy_row, u, heavy, (uint32_t*)hcount);  // rare: one atomic per wave with a heavy row
+    const uint64_t mh = __ballot(heavy_row);
+    if (mh) {  // rare: one atomic per wave with a heavy row
+      long long hd = heavy_row ? d : 0;
+      for (int o = 1; o < kWave; o <<= 1) {
+        const long long y = __shfl_up(hd, o, kWave);
+        if (lane >= o) hd += y;
+      }
+      const long long hsum = __shfl(hd, kWave - 1, kWave);
+      const int leader = __ffsll((unsigned long long)mh) - 1;
+      unsigned long long old = 0;
+      if (lane == leader)
+        old = __hip_atomic_fetch_add(pack, ((unsigned long long)__popcll(mh) << kPackShift) | (unsigned long long)hsum,
+                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      old = __shfl(old, leader, kWave);
+      if (heavy_row) {
+        const long long slot = (long long)(old >> kPackShift) + __popcll(mh & lanemask_lt());
+        heavy[slot] = u;
+        hp[slot] = (long long)(old & kPackEdges) + hd - d;
+      }
+    }
     if (heavy_row) d = 0;
     // exclusive scan of the row lengths across the wave
     int32_t inc = (int32_t)d;
@@ -521,16 +550,18 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
 
 // Rows of heavy frontier vertices, spread evenly over the whole grid.
 template <bool LDD, typename I>
-__global__ void __launch_bounds__(kFBlock) k_expand_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount,
+__global__ void __launch_bounds__(kFBlock) k_expand_heavy(const int32_t* __restrict__ heavy,
+                                                          const unsigned long long* pack,
                                                           const long long* __restrict__ hp, const I* __restrict__ off,
                                                           const int32_t* __restrict__ adj, uint32_t* vis,
                                                           uint32_t* fn, int32_t* P, int32_t* qout,
                                                           uint32_t* cnt_out, int2* tree) {
   __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
   WaveQ q{qbuf[threadIdx.x / kWave], 0};
-  const int64_t c = *hcount;
+  const unsigned long long pk = *pack;
+  const int64_t c = (int64_t)(pk >> kPackShift);
   if (c == 0) return;
-  const long long T = hp[c];
+  const long long T = (long long)(pk & kPackEdges);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
     const long long e = base + threadIdx.x;
@@ -786,6 +817,7 @@ __global__ void __launch_bounds__(kFBlock) k_ldd_wake(int64_t lo, int64_t hi, co
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->qcount[nxt] = 0;
     sc->hcount = 0;
+    sc->heavy_pack = 0ull;
   }
   const int lane = lane_id();
   const int64_t lo32 = lo & ~(int64_t)31;
@@ -841,6 +873,8 @@ cc_status sample_ldd(StaticArgs& a) {
   DevScalars* sc = a.ctx->dev;
   const uint64_t key = sm_out(a.v->seed, kTagLdd);
   const float beta = a.v->ldd_beta;
+  if (a.m >= (int64_t(1) << kPackShift))
+    return fail(CC_EINVAL, "LDD sampling takes m < 2^%d adjacency entries (m=%lld)", kPackShift, (long long)a.m);
 
   cc_status st = count_heavy<I>(a);
   if (st != CC_OK) return st;
@@ -872,13 +906,11 @@ cc_status sample_ldd(StaticArgs& a) {
     lo = hi > lo ? hi : lo;
     hipLaunchKernelGGL((k_expand<true, I>), dim3(grid_for(n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, q[cur],
                        &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, (uint32_t*)nullptr, a.P,
-                       a.heavy, &sc->hcount, a.tree_e);
-    if (heavy) {
-      list_prefix<I>(a, a.heavy, (const int32_t*)&sc->hcount);
+                       a.heavy, a.hp, &sc->heavy_pack, a.tree_e);
+    if (heavy)
       hipLaunchKernelGGL((k_expand_heavy<true, I>), dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
-                         (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, (uint32_t*)nullptr,
-                         a.P, q[nxt], &sc->qcount[nxt], a.tree_e);
-    }
+                         (const unsigned long long*)&sc->heavy_pack, (const long long*)a.hp, off, a.adj, vis,
+                         (uint32_t*)nullptr, a.P, q[nxt], &sc->qcount[nxt], a.tree_e);
     CC_LAUNCH_CHECK();
     cur = nxt;
     ++a.sample_rounds;
