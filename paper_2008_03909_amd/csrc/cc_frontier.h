@@ -214,16 +214,18 @@ __device__ __forceinline__ int64_t heavy_owner_tile(const long long* hp, int64_t
 
 // Edge visitors over the degree-binned candidate lists written by the
 // compaction: op(u, w, j) for every candidate u and every entry j of row(u),
-// w = adj[j].  Thread
-// bin: cand front; wave bin: big front; block bin: big back; grid bin: the
-// heavy list, whose edges are spread evenly over the whole grid.
+// w = adj[j].  Thread bin: cand front; wave bin: big front; block bin: big
+// back; grid bin: the heavy list, whose edges are spread evenly over all of
+// the bin's blocks.  Each part runs as block `bid` of `nb` blocks, so the
+// four can share one launch (k_visit_all) or run as kernels of their own.
 template <class Op, typename I>
-__global__ void k_visit_thread(const int32_t* __restrict__ cand, const DevScalars* sc, const I* __restrict__ off,
-                               const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+__device__ __forceinline__ void visit_thread_part(int64_t bid, int64_t nb, const int32_t* __restrict__ cand,
+                                                  const DevScalars* sc, const I* __restrict__ off,
+                                                  const int32_t* __restrict__ adj, const Op& op, uint32_t* flag) {
   const int64_t cnt = sc->bin_count[0];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = nb * blockDim.x;
   bool any = false;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
+  for (int64_t i = bid * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
     const int32_t u = cand[i];
     const int64_t e = (int64_t)off[u + 1];
     for (int64_t j = (int64_t)off[u]; j < e; ++j) any |= op(u, adj[j], j);
@@ -232,13 +234,14 @@ __global__ void k_visit_thread(const int32_t* __restrict__ cand, const DevScalar
 }
 
 template <class Op, typename I>
-__global__ void k_visit_wave(const int32_t* __restrict__ big, const DevScalars* sc, const I* __restrict__ off,
-                             const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+__device__ __forceinline__ void visit_wave_part(int64_t bid, int64_t nb, const int32_t* __restrict__ big,
+                                                const DevScalars* sc, const I* __restrict__ off,
+                                                const int32_t* __restrict__ adj, const Op& op, uint32_t* flag) {
   const int64_t cnt = sc->bin_count[1];
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t waves = nb * (blockDim.x / kWave);
   const int lane = lane_id();
   bool any = false;
-  for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < cnt; i += waves) {
+  for (int64_t i = bid * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < cnt; i += waves) {
     const int32_t u = big[i];
     const int64_t e = (int64_t)off[u + 1];
     for (int64_t j = (int64_t)off[u] + lane; j < e; j += kWave) any |= op(u, adj[j], j);
@@ -247,11 +250,12 @@ __global__ void k_visit_wave(const int32_t* __restrict__ big, const DevScalars* 
 }
 
 template <class Op, typename I>
-__global__ void k_visit_block(int64_t n, const int32_t* __restrict__ big, const DevScalars* sc,
-                              const I* __restrict__ off, const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+__device__ __forceinline__ void visit_block_part(int64_t bid, int64_t nb, int64_t n, const int32_t* __restrict__ big,
+                                                 const DevScalars* sc, const I* __restrict__ off,
+                                                 const int32_t* __restrict__ adj, const Op& op, uint32_t* flag) {
   const int64_t cnt = sc->bin_count[2];
   bool any = false;
-  for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+  for (int64_t i = bid; i < cnt; i += nb) {
     const int32_t u = big[n - 1 - i];
     const int64_t e = (int64_t)off[u + 1];
     for (int64_t j = (int64_t)off[u] + threadIdx.x; j < e; j += blockDim.x) any |= op(u, adj[j], j);
@@ -260,15 +264,16 @@ __global__ void k_visit_block(int64_t n, const int32_t* __restrict__ big, const 
 }
 
 template <class Op, typename I>
-__global__ void k_visit_heavy(const int32_t* __restrict__ hlist, const int32_t* count_ptr,
-                              const long long* __restrict__ hp, const I* __restrict__ off,
-                              const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+__device__ __forceinline__ void visit_heavy_part(int64_t bid, int64_t nb, const int32_t* __restrict__ hlist,
+                                                 const int32_t* count_ptr, const long long* __restrict__ hp,
+                                                 const I* __restrict__ off, const int32_t* __restrict__ adj,
+                                                 const Op& op, uint32_t* flag) {
   const int64_t c = *count_ptr;
   bool any = false;
   if (c > 0) {
-    const long long T = hp[c];  // written by heavy_prefix
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
+    const long long T = hp[c];  // the list's edge total
+    const int64_t stride = nb * blockDim.x;
+    for (long long base = bid * (int64_t)blockDim.x; base < T; base += stride) {
       const long long e0 = base + (threadIdx.x / kWave) * kWave;
       const long long e = base + threadIdx.x;
       if (e0 >= T) continue;
@@ -281,6 +286,48 @@ __global__ void k_visit_heavy(const int32_t* __restrict__ hlist, const int32_t* 
     }
   }
   if (flag) wave_flag(any, flag);
+}
+
+template <class Op, typename I>
+__global__ void k_visit_thread(const int32_t* __restrict__ cand, const DevScalars* sc, const I* __restrict__ off,
+                               const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+  visit_thread_part<Op, I>(blockIdx.x, gridDim.x, cand, sc, off, adj, op, flag);
+}
+
+template <class Op, typename I>
+__global__ void k_visit_wave(const int32_t* __restrict__ big, const DevScalars* sc, const I* __restrict__ off,
+                             const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+  visit_wave_part<Op, I>(blockIdx.x, gridDim.x, big, sc, off, adj, op, flag);
+}
+
+template <class Op, typename I>
+__global__ void k_visit_block(int64_t n, const int32_t* __restrict__ big, const DevScalars* sc,
+                              const I* __restrict__ off, const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+  visit_block_part<Op, I>(blockIdx.x, gridDim.x, n, big, sc, off, adj, op, flag);
+}
+
+template <class Op, typename I>
+__global__ void k_visit_heavy(const int32_t* __restrict__ hlist, const int32_t* count_ptr,
+                              const long long* __restrict__ hp, const I* __restrict__ off,
+                              const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+  visit_heavy_part<Op, I>(blockIdx.x, gridDim.x, hlist, count_ptr, hp, off, adj, op, flag);
+}
+
+// All four bins in one launch: blocks [0, g0) take the thread bin, the next
+// g1 the wave bin, the next g2 the block bin, the rest the grid bin.
+template <class Op, typename I>
+__global__ void k_visit_all(int64_t n, int64_t g0, int64_t g1, int64_t g2, const int32_t* __restrict__ cand,
+                            const int32_t* __restrict__ big, const int32_t* __restrict__ heavy,
+                            const long long* __restrict__ hp, const DevScalars* sc, const I* __restrict__ off,
+                            const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
+  int64_t b = blockIdx.x;
+  if (b < g0) return visit_thread_part<Op, I>(b, g0, cand, sc, off, adj, op, flag);
+  b -= g0;
+  if (b < g1) return visit_wave_part<Op, I>(b, g1, big, sc, off, adj, op, flag);
+  b -= g1;
+  if (b < g2) return visit_block_part<Op, I>(b, g2, n, big, sc, off, adj, op, flag);
+  b -= g2;
+  visit_heavy_part<Op, I>(b, (int64_t)gridDim.x - g0 - g1 - g2, heavy, &sc->bin_count[3], hp, off, adj, op, flag);
 }
 
 // Candidate lists of one static call.
@@ -296,13 +343,9 @@ struct CandLists {
 template <class Op, typename I>
 inline void visit_candidates(hipStream_t s, const CandLists& L, const I* off, const int32_t* adj, Op op,
                              uint32_t* flag) {
-  hipLaunchKernelGGL((k_visit_thread<Op, I>), dim3(grid_for(L.n, kFBlock, 4096)), dim3(kFBlock), 0, s, L.cand, L.sc,
-                     off, adj, op, flag);
-  hipLaunchKernelGGL((k_visit_wave<Op, I>), dim3(grid_for(L.n * kWave, kFBlock, 2048)), dim3(kFBlock), 0, s, L.big,
-                     L.sc, off, adj, op, flag);
-  hipLaunchKernelGGL((k_visit_block<Op, I>), dim3(1024), dim3(kFBlock), 0, s, L.n, L.big, L.sc, off, adj, op, flag);
-  hipLaunchKernelGGL((k_visit_heavy<Op, I>), dim3(2048), dim3(kFBlock), 0, s, L.heavy, &L.sc->bin_count[3], L.hp,
-                     off, adj, op, flag);
+  const int64_t g0 = grid_for(L.n, kFBlock, 4096), g1 = grid_for(L.n * kWave, kFBlock, 2048), g2 = 1024, g3 = 2048;
+  hipLaunchKernelGGL((k_visit_all<Op, I>), dim3((unsigned)(g0 + g1 + g2 + g3)), dim3(kFBlock), 0, s, L.n, g0, g1, g2,
+                     L.cand, L.big, L.heavy, L.hp, L.sc, off, adj, op, flag);
 }
 
 static __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }

@@ -29,7 +29,7 @@ struct DevScalars {
   long long reached;       // vertices reached by the current BFS (follows bfs_mode/bfs_level: read together)
   long long seen_edges;    // BFS: degree sum of every frontier so far
   unsigned long long heavy_count;  // vertices with degree above the frontier threshold
-  unsigned long long heavy_pack;   // LDD: heavy frontier rows (high 24 bits) and their edges (low 40)
+  unsigned long long heavy_pack;   // LDD: heavy frontier rows (high 28 bits) and their edges (low 36)
   uint32_t flag2;          // spare flag for sub-rounds (full shortcut)
   int32_t hcount;          // heavy frontier vertices deferred to the grid kernel
   uint32_t pad[12];        // pad[0]: LDD minimum draw

@@ -167,7 +167,7 @@ WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v) {
   L.hist = off, off += align256(4096 * 4);
   L.mlp = off, off += 65536;   // selector: feature partials, label stats, one MLP row
   if (v->finish == CC_FIN_LT && (v->lt_rules & CC_LT_ALTER)) L.edges = off, off += 2 * align256((size_t)m * 4);
-  L.seg = off, off += align256((size_t)kSegMaxHost * 16) + align256((size_t)kSegMaxHost * 8);
+  L.seg = off, off += align256((size_t)kSegMaxHost * 16) + 2 * align256((size_t)kSegMaxHost * 8);
   {
     const size_t hcap = heavy_cap(m);  // vertices with degree above the frontier threshold
     L.heavy = off, off += align256(hcap * 4) + align256((hcap + 1) * 8) + align256((hcap / kHpTile + 3) * 8);
@@ -188,7 +188,8 @@ __device__ __forceinline__ uint64_t lanemask_lt_dev() {
 }
 
 
-__global__ void k_reset_scalars(DevScalars* sc, long long* ncomp_user) {
+// Per-call device scalars back to their starting values.
+__device__ __forceinline__ void reset_scalars(DevScalars* sc, long long* ncomp_user) {
   sc->changed = 0;
   sc->lmax_key = 0ull;
   sc->lmax = -1;
@@ -204,8 +205,12 @@ __global__ void k_reset_scalars(DevScalars* sc, long long* ncomp_user) {
   if (ncomp_user) *ncomp_user = 0;
 }
 
-// P[v] = v and count[v] = 0, four vertices per lane with 16-byte stores.
-__global__ void k_init(int64_t n, int32_t* __restrict__ P, int32_t* __restrict__ count, int aligned) {
+
+// P[v] = v and count[v] = 0, four vertices per lane with 16-byte stores;
+// the first thread also resets the call's device scalars.
+__global__ void k_init(int64_t n, int32_t* __restrict__ P, int32_t* __restrict__ count, int aligned, DevScalars* sc,
+                       long long* ncomp_user) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) reset_scalars(sc, ncomp_user);
   const int64_t groups = div_up_dev(n, 4);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups; g += stride) {
@@ -495,9 +500,32 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
   return x;
 }
 
+__device__ __forceinline__ int32_t lmax_of(unsigned long long key) {
+  return key ? (int32_t)(~(uint32_t)(key & 0xffffffffull)) : -1;
+}
+
+// Reduces nparts block maxima (nparts 0: no frequent label) and publishes
+// lmax and its class size (one block).
+__device__ __forceinline__ void resolve_lmax(DevScalars* sc, const unsigned long long* part, int nparts) {
+  __shared__ unsigned long long red[kBlock / kWave];
+  unsigned long long best = 0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) best = part[i] > best ? part[i] : best;
+  best = wave_max_u64(best);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) best = red[w] > best ? red[w] : best;
+    sc->lmax_key = best;
+    sc->lmax = lmax_of(best);
+    sc->lmax_size = (long long)(best >> 32);
+  }
+}
+
 // IdentifyFrequent: max over (count << 32 | ~label); ties go to the smaller
 // label.  Each block writes its maximum to part[blockIdx]; one block
-// reduces them (no address takes an atomic per block).
+// reduces them (no address takes an atomic per block).  A last-block
+// reduction inside this kernel was measured slower: the agent-scope fence
+// each block needs before its ticket writes back its XCD's L2.
 __global__ void __launch_bounds__(kBlock) k_argmax(int64_t n, const int32_t* __restrict__ count,
                                                    unsigned long long* __restrict__ part, int aligned) {
   __shared__ unsigned long long red[kBlock / kWave];
@@ -524,26 +552,9 @@ __global__ void __launch_bounds__(kBlock) k_argmax(int64_t n, const int32_t* __r
   }
 }
 
-__device__ __forceinline__ int32_t lmax_of(unsigned long long key) {
-  return key ? (int32_t)(~(uint32_t)(key & 0xffffffffull)) : -1;
-}
-
-// Reduces nparts block maxima (nparts 0: no frequent label) and publishes
-// lmax and its class size.
 __global__ void __launch_bounds__(kBlock) k_resolve_lmax(DevScalars* sc, const unsigned long long* __restrict__ part,
                                                          int nparts) {
-  __shared__ unsigned long long red[kBlock / kWave];
-  unsigned long long best = 0;
-  for (int i = threadIdx.x; i < nparts; i += kBlock) best = part[i] > best ? part[i] : best;
-  best = wave_max_u64(best);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = best;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kBlock / kWave; ++w) best = red[w] > best ? red[w] : best;
-    sc->lmax_key = best;
-    sc->lmax = lmax_of(best);
-    sc->lmax_size = (long long)(best >> 32);
-  }
+  resolve_lmax(sc, part, nparts);
 }
 
 // Candidate compaction with degree binning, in three launches and without
@@ -554,14 +565,18 @@ __global__ void __launch_bounds__(kBlock) k_resolve_lmax(DevScalars* sc, const u
 // gather copies every segment into the final lists (thread bin: cand; wave
 // bin: big front; block bin: big back; grid bin: heavy), classifying the
 // back entries by degree.  The lists come out in a fixed order, so the finish
-// does the same work every run.
+// does the same work every run.  The grid bin's degree prefix (the offsets
+// its edge-balanced visitor searches) is built along the way: per-segment
+// sums of the grid-bin degrees, scanned with the counts, then a wave scan in
+// the gather.
 constexpr int kSegMax = 8448;  // upper bound on the number of segments
 
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, const I* __restrict__ off,
                                                         const int32_t* __restrict__ P, const DevScalars* sc,
                                                         int32_t* __restrict__ scratch, int32_t* __restrict__ segcnt,
-                                                        long long* __restrict__ segedges, int aligned) {
+                                                        long long* __restrict__ segedges,
+                                                        long long* __restrict__ segheavy, int aligned) {
   const int32_t L = sc->lmax;
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt_dev();
@@ -571,7 +586,7 @@ __global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, co
     const int64_t lo = w * S;
     const int64_t hi = (lo + S < n) ? lo + S : n;
     int32_t c0 = 0, cb = 0, c2 = 0, c3 = 0;
-    long long edges = 0;
+    long long edges = 0, hedges = 0;
     for (int64_t base = lo; base < hi; base += 4 * kWave) {
       const int64_t v0 = base + 4 * lane;
       const bool act = v0 < hi;
@@ -598,23 +613,22 @@ __global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, co
         cb += __popcll(ml);
         c2 += __popcll(__ballot(large && deg > kThrBlock && deg <= kThrGrid));
         c3 += __popcll(__ballot(large && deg > kThrGrid));
+        if (large && deg > kThrGrid) hedges += deg;
       }
     }
     edges = wave_sum(edges);
+    hedges = wave_sum(hedges);
     if (lane == 0) {
       segcnt[4 * w + 0] = c0;
       segcnt[4 * w + 1] = cb - c2 - c3;
       segcnt[4 * w + 2] = c2;
       segcnt[4 * w + 3] = c3;
       segedges[w] = edges;
+      segheavy[w] = hedges;
     }
   }
 }
 
-// One block: exclusive scan of the per-segment counts (four bins), totals
-// into the context scalars.  Each thread sums a run of segments; the runs
-// are scanned with wave shuffles and a second-level scan of the 16 wave
-// totals.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T x) {
   const int lane = lane_id();
@@ -625,59 +639,106 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
   return x;
 }
 
+// One block: exclusive scan of the per-segment counts (four bins) and of the
+// grid-bin degree sums, in place; bin totals and the candidates' edge total
+// into the context scalars, the grid bin's edge total into hp[count].
+// Thread t owns a run of at most kScanRun consecutive segments, loaded all
+// at once; the run totals go through one block scan (wave scans, then one
+// wave scans the wave totals), and each thread writes its run back.
+// (Slices of 1024 segments with coalesced loads and a block scan per slice
+// were measured slower: the chained wave scans of eight slices cost more
+// than the strided loads they save.)
+constexpr int kScanRun = (kSegMax + 1023) / 1024;
+
 __global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* segcnt, const long long* segedges,
-                                                       DevScalars* sc) {
+                                                       long long* segheavy, long long* hp, DevScalars* sc) {
   constexpr int kWaves = 1024 / kWave;
-  __shared__ int32_t wtot[4][kWaves];
-  __shared__ long long etot[kWaves];
+  __shared__ int32_t wc[4][kWaves];
+  __shared__ long long wh[kWaves];
+  __shared__ long long we[kWaves];
+  __shared__ int32_t tot[4];
+  __shared__ long long htot;
   const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
   const int64_t per = div_up_dev(nseg, 1024);
-  const int64_t lo = t * per < nseg ? t * per : nseg;
-  const int64_t hi = (lo + per < nseg) ? lo + per : nseg;
-  int32_t s[4] = {0, 0, 0, 0};
-  long long e = 0;
-  for (int64_t i = lo; i < hi; ++i) {
-    for (int q = 0; q < 4; ++q) s[q] += segcnt[4 * i + q];
-    e += segedges[i];
+  const int64_t lo = t * per;
+  int4 c[kScanRun];
+  long long h[kScanRun];
+  int32_t sum[4] = {0, 0, 0, 0};
+  long long hs = 0, e = 0;
+#pragma unroll
+  for (int j = 0; j < kScanRun; ++j) {
+    const int64_t i = lo + j;
+    c[j] = make_int4(0, 0, 0, 0);
+    h[j] = 0;
+    if (j < per && i < nseg) {
+      c[j] = *(const int4*)(segcnt + 4 * i);
+      h[j] = segheavy[i];
+      e += segedges[i];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kScanRun; ++j) {
+    sum[0] += c[j].x, sum[1] += c[j].y, sum[2] += c[j].z, sum[3] += c[j].w;
+    hs += h[j];
   }
   int32_t inc[4];
-  for (int q = 0; q < 4; ++q) {
-    inc[q] = wave_incl_scan(s[q]);
-    if (lane == kWave - 1) wtot[q][w] = inc[q];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) inc[q] = wave_incl_scan(sum[q]);
+  const long long hinc = wave_incl_scan(hs);
+  e = wave_sum(e);
+  if (lane == kWave - 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wc[q][w] = inc[q];
+    wh[w] = hinc;
   }
-  const long long einc = wave_incl_scan(e);
-  if (lane == kWave - 1) etot[w] = einc;
+  if (lane == 0) we[w] = e;
   __syncthreads();
-  if (t < 4) {  // exclusive scan of the 16 wave totals of bin t
-    int32_t run = 0;
-    for (int i = 0; i < kWaves; ++i) {
-      const int32_t x = wtot[t][i];
-      wtot[t][i] = run;
-      run += x;
+  if (w == 0) {  // exclusive scan of the wave totals by one wave
+    const bool in = lane < kWaves;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int32_t x = in ? wc[q][lane] : 0;
+      const int32_t y = wave_incl_scan(x);
+      if (in) wc[q][lane] = y - x;
+      if (lane == kWaves - 1) tot[q] = y;
     }
-    sc->bin_count[t] = run;
-  } else if (t == 4) {
-    long long tot = 0;
-    for (int i = 0; i < kWaves; ++i) tot += etot[i];
-    sc->cand_edges = tot;
+    const long long x = in ? wh[lane] : 0;
+    const long long y = wave_incl_scan(x);
+    if (in) wh[lane] = y - x;
+    if (lane == kWaves - 1) htot = y;
   }
   __syncthreads();
   int32_t r[4];
-  for (int q = 0; q < 4; ++q) r[q] = wtot[q][w] + inc[q] - s[q];
-  for (int64_t i = lo; i < hi; ++i)
-    for (int q = 0; q < 4; ++q) {
-      const int32_t x = segcnt[4 * i + q];
-      segcnt[4 * i + q] = r[q];
-      r[q] += x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) r[q] = wc[q][w] + inc[q] - sum[q];
+  long long hr = wh[w] + hinc - hs;
+#pragma unroll
+  for (int j = 0; j < kScanRun; ++j) {
+    const int64_t i = lo + j;
+    if (j < per && i < nseg) {
+      *(int4*)(segcnt + 4 * i) = make_int4(r[0], r[1], r[2], r[3]);
+      segheavy[i] = hr;
+      r[0] += c[j].x, r[1] += c[j].y, r[2] += c[j].z, r[3] += c[j].w;
+      hr += h[j];
     }
+  }
+  if (t == 0) {
+    long long et = 0;
+    for (int k = 0; k < kWaves; ++k) et += we[k];
+    sc->cand_edges = et;
+    for (int q = 0; q < 4; ++q) sc->bin_count[q] = tot[q];
+    hp[tot[3]] = htot;  // the grid bin's edge total closes its prefix
+  }
 }
 
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_compact_gather(int64_t n, int64_t S, const I* __restrict__ off,
                                                            const int32_t* __restrict__ scratch,
                                                            const int32_t* __restrict__ segoff,
+                                                           const long long* __restrict__ segheavy,
                                                            int32_t* __restrict__ cand, int32_t* __restrict__ big,
-                                                           int32_t* __restrict__ heavy, const DevScalars* sc) {
+                                                           int32_t* __restrict__ heavy, long long* __restrict__ hp,
+                                                           const DevScalars* sc) {
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt_dev();
   const int64_t nseg = div_up_dev(n, S);
@@ -695,6 +756,7 @@ __global__ void __launch_bounds__(kBlock) k_compact_gather(int64_t n, int64_t S,
     for (int32_t i = lane; i < c[0]; i += kWave) cand[o[0] + i] = scratch[lo + i];
     const int32_t cb = c[1] + c[2] + c[3];
     int32_t r1 = o[1], r2 = o[2], r3 = o[3];
+    long long hb = segheavy[w];
     for (int32_t i0 = 0; i0 < cb; i0 += kWave) {
       const int32_t i = i0 + lane;
       int32_t x = 0;
@@ -709,7 +771,15 @@ __global__ void __launch_bounds__(kBlock) k_compact_gather(int64_t n, int64_t S,
       const uint64_t m1 = __ballot(b1), m2 = __ballot(b2), m3 = __ballot(b3);
       if (b1) big[r1 + __popcll(m1 & lt)] = x;
       if (b2) big[n - 1 - (r2 + __popcll(m2 & lt))] = x;
-      if (b3) heavy[r3 + __popcll(m3 & lt)] = x;
+      if (m3) {  // grid bin: row and its degree prefix
+        const long long hd = b3 ? deg : 0;
+        const long long hinc = wave_incl_scan(hd);
+        if (b3) {
+          heavy[r3 + __popcll(m3 & lt)] = x;
+          hp[r3 + __popcll(m3 & lt)] = hb + hinc - hd;
+        }
+        hb += __shfl(hinc, kWave - 1, kWave);
+      }
       r1 += __popcll(m1);
       r2 += __popcll(m2);
       r3 += __popcll(m3);
@@ -730,7 +800,8 @@ struct UnionOp {
 };
 
 // Final compression and component count: label = root (the component's
-// minimum, since every link points to a smaller id).
+// minimum, since every link points to a smaller id).  Per-block root counts
+// go to part[].
 __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, long long* __restrict__ part,
                                                    int aligned) {
   __shared__ long long red[kBlock / kWave];
@@ -929,9 +1000,9 @@ template <typename I>
 static cc_status run_static(StaticArgs& a, bool sample_only) {
   if (!a.skip_init) {
     PhaseScope ps(a.ctx, a.s, "init");
-    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, a.s, a.ctx->dev, (long long*)a.ncomp_user);
     hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P,
-                       a.v->sample == CC_SAMPLE_NONE ? (int32_t*)nullptr : a.count, vec_ok(a));
+                       a.v->sample == CC_SAMPLE_NONE ? (int32_t*)nullptr : a.count, vec_ok(a), a.ctx->dev,
+                       (long long*)a.ncomp_user);
     CC_LAUNCH_CHECK();
   }
   cc_status st = run_sample<I>(a);
@@ -949,15 +1020,16 @@ cc_status compact_candidates(StaticArgs& a) {
   const int64_t nseg = div_up(a.n, S);
   int32_t* segcnt = (int32_t*)(a.ws + a.L.seg);
   long long* segedges = (long long*)(a.ws + a.L.seg + align256((size_t)kSegMax * 16));
+  long long* segheavy = segedges + align256((size_t)kSegMax * 8) / 8;
   const unsigned gw = grid_for(nseg * kWave, kBlock, 2048);
   hipLaunchKernelGGL(k_compact_seg<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
-                     (const int32_t*)a.P, (const DevScalars*)a.ctx->dev, a.count, segcnt, segedges, vec_ok(a));
+                     (const int32_t*)a.P, (const DevScalars*)a.ctx->dev, a.count, segcnt, segedges, segheavy,
+                     vec_ok(a));
   hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, a.s, nseg, segcnt, (const long long*)segedges,
-                     a.ctx->dev);
+                     segheavy, a.hp, a.ctx->dev);
   hipLaunchKernelGGL(k_compact_gather<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
-                     (const int32_t*)a.count, (const int32_t*)segcnt, a.cand, a.big, a.heavy,
-                     (const DevScalars*)a.ctx->dev);
-  heavy_prefix<I>(a.s, a.heavy, (const int32_t*)&a.ctx->dev->bin_count[3], a.hcap, (const I*)a.off, a.tsum, a.hp);
+                     (const int32_t*)a.count, (const int32_t*)segcnt, (const long long*)segheavy, a.cand, a.big,
+                     a.heavy, a.hp, (const DevScalars*)a.ctx->dev);
   CC_LAUNCH_CHECK();
   return CC_OK;
 }
@@ -1008,8 +1080,8 @@ static void record_stats_host(StaticArgs& a);
 
 cc_status static_init(StaticArgs& a) {
   PhaseScope ps(a.ctx, a.s, "init");
-  hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, a.s, a.ctx->dev, (long long*)a.ncomp_user);
-  hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P, a.count, vec_ok(a));
+  hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P, a.count, vec_ok(a), a.ctx->dev,
+                     (long long*)a.ncomp_user);
   CC_LAUNCH_CHECK();
   return CC_OK;
 }
