@@ -61,6 +61,19 @@ def _suite():
     l2 = np.arange(40100, 76100, dtype=np.int32)
     gs.append(inputs.Graph(100000, np.concatenate([h1, h2, [40099]]).astype(np.int32),
                            np.concatenate([l1, l2, [40100]]).astype(np.int32), "two-heavy-hubs"))
+    # twelve rows above the grid-bin threshold, several in one compaction
+    # segment and in one wave, spread over eight components
+    hubs = [5, 6, 7, 300, 301, 5000, 5001, 5002, 5003, 60000, 60001, 119999]
+    free = np.concatenate([np.arange(10000, 60000), np.arange(60002, 119999)]).astype(np.int32)
+    hu, hv, at = [], [], 0
+    for i, h in enumerate(hubs):
+        d = 4100 + 150 * i
+        hu.append(np.full(d, h, np.int32))
+        hv.append(free[at:at + d])
+        at += d
+    hu.append(np.array([5, 300, 60000, 7], np.int32))
+    hv.append(np.array([6, 5000, 119999, 5003], np.int32))
+    gs.append(inputs.Graph(120000, np.concatenate(hu), np.concatenate(hv), "twelve-heavy-rows"))
     # self-loops and duplicates
     u = np.array([0, 0, 1, 1, 2, 3, 3, 5], np.int32)
     v = np.array([0, 1, 0, 1, 2, 4, 4, 5], np.int32)
