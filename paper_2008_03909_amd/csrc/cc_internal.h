@@ -32,7 +32,9 @@ struct DevScalars {
   unsigned long long heavy_pack;   // LDD: heavy frontier rows (high 28 bits) and their edges (low 36)
   uint32_t flag2;          // spare flag for sub-rounds (full shortcut)
   int32_t hcount;          // heavy frontier vertices deferred to the grid kernel
-  uint32_t pad[12];        // pad[0]: LDD minimum draw
+  long long ldd_fe[2];     // LDD: degree sum of the frontier being built in queue 0 / 1
+  long long ldd_seen;      // LDD: degree sum of every frontier expanded so far
+  uint32_t pad[6];         // pad[0]: LDD minimum draw
 };
 
 enum : uint32_t { kErrBadId = 1u, kErrRoundCap = 2u, kErrBadCsr = 4u };

@@ -456,12 +456,52 @@ void list_prefix(StaticArgs& a, const int32_t* list, const int32_t* count_ptr) {
 constexpr int kPackShift = 36;
 constexpr unsigned long long kPackEdges = (1ull << kPackShift) - 1;
 
+// LDD round direction, after the direction-optimizing rule of BFS: bottom-up
+// when the frontier's edges exceed 1/kLddAlpha of the edges not yet
+// expanded and n/kLddGamma (a bottom-up round visits every vertex, so a
+// frontier with fewer edges than that is cheaper top-down).  Every kernel
+// of a round evaluates it from the same scalars (final once the round's
+// wake has run), so they all agree without a host round trip.
+constexpr long long kLddAlpha = 14, kLddGamma = 4;
+
+__device__ __forceinline__ bool ldd_bottom_up(const DevScalars* sc, int cur, int64_t n, int64_t m) {
+  const long long fe = sc->ldd_fe[cur];
+  const long long mu = (long long)m - sc->ldd_seen - fe;
+  return fe * kLddAlpha > mu && fe * kLddGamma > (long long)n;
+}
+
+// Adds the block's degree sums to an LDD frontier accumulator: one atomic
+// per block (same-address atomics from every wave serialize at one L2
+// channel and cost a late grid round hundreds of microseconds).  Called by
+// every thread of the block.
+__device__ __forceinline__ void ldd_add_edges(long long x, long long* acc) {
+  __shared__ long long red[kFBlock / kWave];
+  x = wave_sum(x);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int w = 0; w < kFBlock / kWave; ++w) t += red[w];
+    if (t) atomicAdd((unsigned long long*)acc, (unsigned long long)t);
+  }
+}
+
+// One LDD round (LDD = true) or frontier expansion.  Top-down: the frontier
+// queue's rows, wave-balanced, rows above kHeavyFrontier left to the grid
+// kernel; a claimed vertex joins its claimer's cluster.  Bottom-up (LDD,
+// when ldd_bottom_up holds): every unvisited vertex scans its row for a
+// neighbour stamped with this round (a member of the frontier) and joins
+// that neighbour's cluster; lanes map to consecutive vertices, so each
+// half-wave owns one bitmap word and writes it without atomics.  Claimed
+// vertices get stamp round + 1 and go to the next queue; their degrees are
+// added to the next frontier's edge count.
 template <bool LDD, typename I>
 __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ qin, const uint32_t* cnt_in,
                                                     int32_t* qout, uint32_t* cnt_out, const I* __restrict__ off,
                                                     const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
                                                     int32_t* P, int32_t* heavy, long long* hp,
-                                                    unsigned long long* pack, int2* tree) {
+                                                    unsigned long long* pack, int2* tree, int32_t* stamp,
+                                                    int32_t round, int64_t n, int64_t m, DevScalars* sc, int cur) {
   constexpr int W = kFBlock / kWave;
   __shared__ int32_t qbuf[W][kWaveQCap];
   __shared__ int32_t tpre[W][kWave + 1];
@@ -471,6 +511,39 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   WaveQ q{qbuf[wv], 0};
+  long long added = 0;
+  if (LDD && ldd_bottom_up(sc, cur, n, m)) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+      const int64_t v = base + threadIdx.x;
+      bool found = false;
+      if (v < n && !bit_get(vis, v)) {
+        const int64_t b = (int64_t)off[v];
+        const int64_t e = (int64_t)off[v + 1];
+        for (int64_t j = b; j < e; ++j) {
+          const int32_t x = adj[j];
+          if (stamp[x] == round) {
+            found = true;
+            P[v] = P[x];
+            stamp[v] = round + 1;
+            if (tree) tree[v] = make_int2(x, (int32_t)v);
+            added += e - b;
+            break;
+          }
+        }
+      }
+      // base is a multiple of 256: lanes 0-31 and 32-63 each cover one word
+      const uint64_t bits = __ballot(found);
+      if ((lane & 31) == 0 && v < n) {
+        const uint32_t wbits = (uint32_t)(bits >> (lane & 32));
+        if (wbits) vis[v >> 5] |= wbits;
+      }
+      wq_push(q, found, (int32_t)v, qout, cnt_out);
+    }
+    wq_flush(q, qout, cnt_out);
+    ldd_add_edges(added, &sc->ldd_fe[cur ^ 1]);
+    return;
+  }
   const int64_t cnt = *cnt_in;
   const int64_t tiles = (cnt + kWave - 1) / kWave;
   const int64_t waves = (int64_t)gridDim.x * W;
@@ -534,8 +607,13 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
         w = adj[tbeg[wv][lo] + (e - tpre[wv][lo])];
         got = bit_claim(vis, w);
         if (got) {
-          if (LDD) P[w] = tlab[wv][lo];
-          else aor(fn + (w >> 5), 1u << (w & 31));
+          if (LDD) {
+            P[w] = tlab[wv][lo];
+            stamp[w] = round + 1;
+            added += (long long)off[w + 1] - (long long)off[w];
+          } else {
+            aor(fn + (w >> 5), 1u << (w & 31));
+          }
           if (tree) tree[w] = make_int2(tu[wv][lo], w);
         }
       }
@@ -546,6 +624,7 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   wq_flush(q, qout, cnt_out);
+  if (LDD) ldd_add_edges(added, &sc->ldd_fe[cur ^ 1]);
 }
 
 // Rows of heavy frontier vertices, spread evenly over the whole grid.
@@ -555,9 +634,13 @@ __global__ void __launch_bounds__(kFBlock) k_expand_heavy(const int32_t* __restr
                                                           const long long* __restrict__ hp, const I* __restrict__ off,
                                                           const int32_t* __restrict__ adj, uint32_t* vis,
                                                           uint32_t* fn, int32_t* P, int32_t* qout,
-                                                          uint32_t* cnt_out, int2* tree) {
+                                                          uint32_t* cnt_out, int2* tree, int32_t* stamp,
+                                                          int32_t round, int64_t n, int64_t m, DevScalars* sc,
+                                                          int cur) {
   __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
   WaveQ q{qbuf[threadIdx.x / kWave], 0};
+  if (LDD && ldd_bottom_up(sc, cur, n, m)) return;  // the round runs bottom-up
+  long long added = 0;
   const unsigned long long pk = *pack;
   const int64_t c = (int64_t)(pk >> kPackShift);
   if (c == 0) return;
@@ -574,14 +657,20 @@ __global__ void __launch_bounds__(kFBlock) k_expand_heavy(const int32_t* __restr
       w = adj[(int64_t)off[u] + (e - hp[i])];
       got = bit_claim(vis, w);
       if (got) {
-        if (LDD) P[w] = P[u];
-        else aor(fn + (w >> 5), 1u << (w & 31));
+        if (LDD) {
+          P[w] = P[u];
+          stamp[w] = round + 1;
+          added += (long long)off[w + 1] - (long long)off[w];
+        } else {
+          aor(fn + (w >> 5), 1u << (w & 31));
+        }
         if (tree) tree[w] = make_int2(u, w);
       }
     }
     wq_push(q, got, w, qout, cnt_out);
   }
   wq_flush(q, qout, cnt_out);
+  if (LDD) ldd_add_edges(added, &sc->ldd_fe[cur ^ 1]);
 }
 
 __global__ void k_round_reset(DevScalars* sc, int nxt) {
@@ -779,6 +868,7 @@ __global__ void __launch_bounds__(kFBlock) k_ldd_prep(int64_t n, uint64_t key, i
   if (threadIdx.x == 0) {
     for (int w = 1; w < kFBlock / kWave; ++w) best = red[w] < best ? red[w] : best;
     atomicMin(&sc->pad[0], best);
+    if (blockIdx.x == 0) sc->ldd_fe[0] = sc->ldd_fe[1] = sc->ldd_seen = 0;
   }
 }
 
@@ -802,39 +892,49 @@ __global__ void k_ldd_hist(int64_t n, uint64_t key, float beta, const DevScalars
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-// Vertices [lo, hi) wake: the unvisited ones become cluster centres.  Lanes
-// map to consecutive vertices from a 32-aligned start, so each half-wave
-// owns one bitmap word and writes it without atomics.  Only centres with an
-// edge join the frontier (an isolated centre has nothing to expand).  Block
-// 0 also resets the counters of the round's output queue (queue `nxt`) and
+// Vertices [lo, hi) wake: the unvisited ones become cluster centres
+// (stamped with the round).  Lanes map to consecutive vertices from a
+// 32-aligned start, so each half-wave owns one bitmap word and writes it
+// without atomics.  Only centres with an edge join the frontier (an
+// isolated centre has nothing to expand); their degrees join its edge
+// count.  Block 0 also resets the round's output queue (queue `nxt`), its
+// edge count (after adding the last frontier's to the expanded total) and
 // the heavy list.
 template <typename I>
 __global__ void __launch_bounds__(kFBlock) k_ldd_wake(int64_t lo, int64_t hi, const I* __restrict__ off,
                                                       uint32_t* vis, int32_t* P, int32_t* q, uint32_t* cnt,
-                                                      DevScalars* sc, int nxt) {
+                                                      DevScalars* sc, int nxt, int32_t* stamp, int32_t round) {
   __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
   WaveQ wq{qbuf[threadIdx.x / kWave], 0};
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->qcount[nxt] = 0;
     sc->hcount = 0;
     sc->heavy_pack = 0ull;
+    sc->ldd_seen += sc->ldd_fe[nxt];
+    sc->ldd_fe[nxt] = 0;
   }
+  long long added = 0;
   const int lane = lane_id();
   const int64_t lo32 = lo & ~(int64_t)31;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = lo32 + blockIdx.x * (int64_t)blockDim.x; base < hi; base += stride) {
     const int64_t v = base + threadIdx.x;
     const bool got = v >= lo && v < hi && !bit_get(vis, v);
-    if (got) P[v] = (int32_t)v;
+    if (got) {
+      P[v] = (int32_t)v;
+      stamp[v] = round;
+    }
     const uint64_t bits = __ballot(got);
     if ((lane & 31) == 0) {
       const uint32_t wbits = (uint32_t)(bits >> (lane & 32));
       if (wbits) vis[v >> 5] |= wbits;
     }
-    const bool push = got && (int64_t)off[v + 1] > (int64_t)off[v];
-    wq_push(wq, push, (int32_t)v, q, cnt);
+    const int64_t d = got ? (int64_t)off[v + 1] - (int64_t)off[v] : 0;
+    added += d;
+    wq_push(wq, d > 0, (int32_t)v, q, cnt);
   }
   wq_flush(wq, q, cnt);
+  ldd_add_edges(added, &sc->ldd_fe[nxt ^ 1]);
 }
 
 // Minimum member of every cluster.  mn[c] starts at c, so only members with
@@ -882,6 +982,11 @@ cc_status sample_ldd(StaticArgs& a) {
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->pad[0], 0xffffffffu);
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words, kFBlock, 4096)), dim3(kFBlock), 0, a.s, vis, words, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(kFBlock), 0, a.s, hist, (int64_t)kLddMaxRounds, 0u);
+  // the round each vertex entered a frontier (-1: not yet); the wave-bin
+  // candidate array is free until the compaction
+  int32_t* stamp = a.big;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, (uint32_t*)stamp, n,
+                     0xffffffffu);
   hipLaunchKernelGGL(k_ldd_prep, dim3(grid_for(n, kFBlock, kLddGrid)), dim3(kFBlock), 0, a.s, n, key, mn, sc);
   hipLaunchKernelGGL(k_ldd_hist, dim3(grid_for(n, kFBlock, kLddGrid)), dim3(kFBlock), 0, a.s, n, key, beta,
                      (const DevScalars*)sc, hist);
@@ -901,16 +1006,16 @@ cc_status sample_ldd(StaticArgs& a) {
     S += h[r];
     const int64_t hi = (r == last) ? n : S;
     const int nxt = cur ^ 1;
-    hipLaunchKernelGGL(k_ldd_wake<I>, dim3(grid_for(hi > lo ? hi - (lo & ~(int64_t)31) : 1, kFBlock, 4096)),
-                       dim3(kFBlock), 0, a.s, lo, hi, off, vis, a.P, q[cur], &sc->qcount[cur], sc, nxt);
+    hipLaunchKernelGGL(k_ldd_wake<I>, dim3(grid_for(hi > lo ? hi - (lo & ~(int64_t)31) : 1, kFBlock, 1024)),
+                       dim3(kFBlock), 0, a.s, lo, hi, off, vis, a.P, q[cur], &sc->qcount[cur], sc, nxt, stamp, r);
     lo = hi > lo ? hi : lo;
     hipLaunchKernelGGL((k_expand<true, I>), dim3(grid_for(n, kFBlock, 2048)), dim3(kFBlock), 0, a.s, q[cur],
                        &sc->qcount[cur], q[nxt], &sc->qcount[nxt], off, a.adj, vis, (uint32_t*)nullptr, a.P,
-                       a.heavy, a.hp, &sc->heavy_pack, a.tree_e);
+                       a.heavy, a.hp, &sc->heavy_pack, a.tree_e, stamp, r, n, a.m, sc, cur);
     if (heavy)
       hipLaunchKernelGGL((k_expand_heavy<true, I>), dim3(2048), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
                          (const unsigned long long*)&sc->heavy_pack, (const long long*)a.hp, off, a.adj, vis,
-                         (uint32_t*)nullptr, a.P, q[nxt], &sc->qcount[nxt], a.tree_e);
+                         (uint32_t*)nullptr, a.P, q[nxt], &sc->qcount[nxt], a.tree_e, stamp, r, n, a.m, sc, cur);
     CC_LAUNCH_CHECK();
     cur = nxt;
     ++a.sample_rounds;
