@@ -140,6 +140,8 @@ typedef struct {
   int32_t sample_rounds;     /* BFS levels / LDD rounds (0 for k-out) */
   int32_t finish_rounds;     /* SV / LT rounds (0 for union-find) */
   int64_t num_components;
+  int32_t sample_bottom_up;  /* of sample_rounds, those run bottom-up (speed only) */
+  int32_t reserved;
 } cc_stats;
 
 typedef struct cc_ctx cc_ctx;

@@ -96,6 +96,7 @@ class cc_stats(ctypes.Structure):
         ("candidate_edges", ctypes.c_int64),
         ("sample_rounds", ctypes.c_int32), ("finish_rounds", ctypes.c_int32),
         ("num_components", ctypes.c_int64),
+        ("sample_bottom_up", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):

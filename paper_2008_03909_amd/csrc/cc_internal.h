@@ -34,7 +34,8 @@ struct DevScalars {
   int32_t hcount;          // heavy frontier vertices deferred to the grid kernel
   long long ldd_fe[2];     // LDD: degree sum of the frontier being built in queue 0 / 1
   long long ldd_seen;      // LDD: degree sum of every frontier expanded so far
-  uint32_t pad[6];         // pad[0]: LDD minimum draw
+  int32_t bu_rounds;       // BFS levels / LDD rounds run bottom-up in this call
+  uint32_t pad[5];         // pad[0]: LDD minimum draw
 };
 
 enum : uint32_t { kErrBadId = 1u, kErrRoundCap = 2u, kErrBadCsr = 4u };

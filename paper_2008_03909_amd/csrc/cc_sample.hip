@@ -297,6 +297,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   } else if (mode == kBfsBottomUp) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ++sc->bu_rounds;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
       const int64_t v = base + threadIdx.x;
@@ -513,6 +514,7 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
   WaveQ q{qbuf[wv], 0};
   long long added = 0;
   if (LDD && ldd_bottom_up(sc, cur, n, m)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ++sc->bu_rounds;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
       const int64_t v = base + threadIdx.x;

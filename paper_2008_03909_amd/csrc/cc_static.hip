@@ -198,6 +198,7 @@ __device__ __forceinline__ void reset_scalars(DevScalars* sc, long long* ncomp_u
   sc->cand_edges = 0;
   sc->num_components = 0;
   sc->lmax_size = 0;
+  sc->bu_rounds = 0;
   sc->qcount[0] = sc->qcount[1] = 0;
   sc->frontier_edges = 0;
   sc->reached = 0;
@@ -1211,6 +1212,8 @@ cc_status cc_last_stats(cc_ctx* ctx, cc_stats* out) {
   s.candidates = (int64_t)ctx->host->bin_count[0] + ctx->host->bin_count[1] + ctx->host->bin_count[2];
   s.candidate_edges = ctx->host->cand_edges;
   s.num_components = ctx->host->num_components;
+  s.sample_bottom_up = ctx->host->bu_rounds;
+  s.reserved = 0;
   *out = s;
   return CC_OK;
 }

@@ -202,14 +202,21 @@ def test_bfs_sample_matches_oracle_partition(ctx):
         off, adj = oracle.csr_build(g.n, g.u, g.v, True)
         want, t = oracle.bfs_sample(g.n, off, adj, 3, 99)
         assert np.array_equal(lab.cpu().numpy(), want), g
-        assert ctx.last_stats()["sample_success"] == t
+        st = ctx.last_stats()
+        assert st["sample_success"] == t
+        assert 0 <= st["sample_bottom_up"] <= st["sample_rounds"], g
 
 
 def test_ldd_sample_is_a_partial_labelling_of_stars(ctx):
+    bottom_up = top_down = 0
     for g in SUITE:
         d = _csr(ctx, g)
         v = b.default_variant(sample=b.SAMPLE_LDD, seed=5)
         lab, lmax = b.sample_csr(ctx, d, v)
+        st = ctx.last_stats()
+        assert 0 <= st["sample_bottom_up"] <= st["sample_rounds"], g
+        bottom_up += st["sample_bottom_up"]
+        top_down += st["sample_rounds"] - st["sample_bottom_up"]
         lab = lab.cpu().numpy()
         true, _ = oracle.labels(g)
         idx = np.arange(g.n)
@@ -219,6 +226,8 @@ def test_ldd_sample_is_a_partial_labelling_of_stars(ctx):
         keep = lab[g.u] == lab[g.v]
         sub, _ = oracle.uf_cc(g.n, g.u[keep], g.v[keep])
         assert np.array_equal(sub, lab), g
+    # the suite runs rounds in both directions (a hub's round goes bottom-up)
+    assert bottom_up > 0 and top_down > 0, (bottom_up, top_down)
 
 
 # ---- incremental -----------------------------------------------------------------------
