@@ -105,7 +105,8 @@ enum {
 /* One sampling x finish combination (Algorithm 1's sample_opt/finish_opt).
  *  - kout_k >= 1 edges per vertex (paper default 2);
  *  - bfs_tries >= 1 BFS attempts (paper text: 3), success iff the reached
- *    component holds more than n/10 vertices;
+ *    component holds more than n/10 vertices; BFS takes graphs with
+ *    m < 2^36 adjacency entries (CC_EINVAL above);
  *  - ldd_beta in (0, 1) (paper default 0.2); ldd_permute must be 0 (the
  *    paper's default ordering; vertex 0 wakes first); LDD takes graphs
  *    with m < 2^36 adjacency entries (CC_EINVAL above);

@@ -65,6 +65,41 @@ __global__ void k_bfs_start(int32_t s, const I* off, uint32_t* vis, uint32_t* fc
   sc->bfs_level = 0;
   sc->reached = 1;
   sc->hcount = 0;
+  sc->heavy_pack = 0ull;
+}
+
+// Heavy frontier rows are listed with their edge offsets reserved at the
+// same time: one 64-bit atomic per wave adds (rows << 36 | edges) to `pack`,
+// so slot i gets hp[i] = the edges listed before it and the offsets come out
+// sorted by slot -- the prefix the grid kernel searches, with no separate
+// scan.  A level lists at most m / 256 + 2 rows holding at most m entries,
+// so both fields fit while m < 2^36 (BFS and LDD refuse larger graphs).
+constexpr int kPackShift = 36;
+constexpr unsigned long long kPackEdges = (1ull << kPackShift) - 1;
+
+// Lists lane's row u (degree d) if heavy_row; called by the whole wave.
+__device__ __forceinline__ void heavy_reserve(bool heavy_row, int32_t u, int64_t d, int32_t* heavy, long long* hp,
+                                              unsigned long long* pack) {
+  const uint64_t mh = __ballot(heavy_row);
+  if (!mh) return;  // rare: one atomic per wave with a heavy row
+  const int lane = lane_id();
+  long long hd = heavy_row ? d : 0;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const long long y = __shfl_up(hd, o, kWave);
+    if (lane >= o) hd += y;
+  }
+  const long long hsum = __shfl(hd, kWave - 1, kWave);
+  const int leader = __ffsll((unsigned long long)mh) - 1;
+  unsigned long long old = 0;
+  if (lane == leader)
+    old = __hip_atomic_fetch_add(pack, ((unsigned long long)__popcll(mh) << kPackShift) | (unsigned long long)hsum,
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  old = __shfl(old, leader, kWave);
+  if (heavy_row) {
+    const long long slot = (long long)(old >> kPackShift) + __popcll(mh & lanemask_lt());
+    heavy[slot] = u;
+    hp[slot] = (long long)(old & kPackEdges) + hd - d;
+  }
 }
 
 __device__ __forceinline__ long long block_sum_ll(long long x, long long* red) {
@@ -113,6 +148,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_begin(int64_t words, uint32_t* 
       sc->bfs_mode = mode;
       sc->qcount[cur ^ 1] = 0;
       sc->hcount = 0;
+      sc->heavy_pack = 0ull;
       if (mode != kBfsDone) sc->bfs_level += 1;
     }
   }
@@ -227,7 +263,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
                                                       const uint32_t* __restrict__ fc, uint32_t* fn,
                                                       const int32_t* __restrict__ qin, const uint32_t* cnt_in,
                                                       int32_t* qout, uint32_t* cnt_out, int32_t* heavy,
-                                                      int32_t* hcount, DevScalars* sc,
+                                                      long long* hp, DevScalars* sc,
                                                       long long* __restrict__ fpart, int2* tree) {
   constexpr int W = kFBlock / kWave;
   __shared__ int32_t qbuf[W][kWaveQCap];
@@ -256,7 +292,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
         d = (int64_t)off[u + 1] - b;
       }
       const bool heavy_row = d > kHeavyFrontier;
-      wave_append(heavy_row, u, heavy, (uint32_t*)hcount);
+      heavy_reserve(heavy_row, u, d, heavy, hp, &sc->heavy_pack);
       if (heavy_row) d = 0;
       int32_t inc = (int32_t)d;
       for (int o = 1; o < kWave; o <<= 1) {
@@ -342,7 +378,7 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_step(int64_t n, const I* __rest
 // Heavy frontier rows (top-down levels only), spread evenly over the grid;
 // degree sums of the added vertices to fpart[kBfsStepBlocks + blockIdx].
 template <typename I>
-__global__ void __launch_bounds__(kFBlock) k_bfs_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount,
+__global__ void __launch_bounds__(kFBlock) k_bfs_heavy(const int32_t* __restrict__ heavy,
                                                        const long long* __restrict__ hp, const I* __restrict__ off,
                                                        const int32_t* __restrict__ adj, uint32_t* vis, uint32_t* fn,
                                                        int32_t* qout, uint32_t* cnt_out, const DevScalars* sc,
@@ -350,10 +386,11 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_heavy(const int32_t* __restrict
   __shared__ int32_t qbuf[kFBlock / kWave][kWaveQCap];
   __shared__ long long red[kFBlock / kWave];
   WaveQ q{qbuf[threadIdx.x / kWave], 0};
-  const int64_t c = sc->bfs_mode == kBfsTopDown ? (int64_t)*hcount : 0;
+  const unsigned long long pk = sc->bfs_mode == kBfsTopDown ? sc->heavy_pack : 0ull;
+  const int64_t c = (int64_t)(pk >> kPackShift);
   long long added = 0;
   if (c > 0) {
-    const long long T = hp[c];
+    const long long T = (long long)(pk & kPackEdges);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (long long base = blockIdx.x * (int64_t)blockDim.x; base < T; base += stride) {
       const long long e = base + threadIdx.x;
@@ -385,23 +422,6 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_heavy(const int32_t* __restrict
   }
 }
 
-// One-block exclusive degree prefix of a device-counted list (any length;
-// meant for short lists): hp[i] for i < c, hp[c] = total.
-template <typename I>
-__global__ void __launch_bounds__(kHpTile) k_hp_single(const int32_t* __restrict__ list, const int32_t* count_ptr,
-                                                       const I* __restrict__ off, long long* __restrict__ hp) {
-  const int64_t c = *count_ptr;
-  long long carry = 0;
-  for (int64_t base = 0; base < c; base += kHpTile) {
-    const int64_t i = base + threadIdx.x;
-    long long total;
-    const long long ex = block_excl_scan_ll(list_deg(list, i, c, off), &total);
-    if (i < c) hp[i] = carry + ex;
-    carry += total;
-  }
-  if (threadIdx.x == 0) hp[c] = carry;
-}
-
 template <typename I>
 __global__ void __launch_bounds__(kFBlock) k_count_heavy(int64_t n, const I* __restrict__ off,
                                                          unsigned long long* out) {
@@ -431,16 +451,6 @@ cc_status count_heavy(StaticArgs& a) {
   return CC_OK;
 }
 
-constexpr int64_t kHpSingleMax = 65536;   // heavy lists up to this length use the one-block prefix
-
-template <typename I>
-void list_prefix(StaticArgs& a, const int32_t* list, const int32_t* count_ptr) {
-  if (a.heavy_vertices >= 0 && a.heavy_vertices <= kHpSingleMax)
-    hipLaunchKernelGGL(k_hp_single<I>, dim3(1), dim3(kHpTile), 0, a.s, list, count_ptr, (const I*)a.off, a.hp);
-  else
-    heavy_prefix<I>(a.s, list, count_ptr, a.hcap, (const I*)a.off, a.tsum, a.hp);
-}
-
 // Frontier expansion (BFS top-down step, LDD cluster growth), load-balanced
 // within each wave: a wave takes 64 frontier vertices, concatenates their
 // rows (exclusive scan of the degrees across lanes) and walks the joint edge
@@ -448,14 +458,6 @@ void list_prefix(StaticArgs& a, const int32_t* list, const int32_t* count_ptr) {
 // search over the 64 row starts in LDS.  Rows above kHeavyFrontier are
 // deferred to the grid kernel.  Claimed vertices go through a wave-private
 // LDS buffer, so the output queue's counter is bumped once per flush.
-// Heavy rows are listed with their edge offsets reserved at the same time:
-// one 64-bit atomic per wave adds (rows << 36 | edges) to `pack`, so slot i
-// gets hp[i] = the edges listed before it and the offsets come out sorted
-// by slot -- the prefix the grid kernel searches, with no separate scan.
-// A round lists at most m / 256 + 2 rows holding at most m entries, so both
-// fields fit while m < 2^36 (the sampler refuses larger graphs).
-constexpr int kPackShift = 36;
-constexpr unsigned long long kPackEdges = (1ull << kPackShift) - 1;
 
 // LDD round direction, after the direction-optimizing rule of BFS: bottom-up
 // when the frontier's edges exceed 1/kLddAlpha of the edges not yet
@@ -559,26 +561,7 @@ __global__ void __launch_bounds__(kFBlock) k_expand(const int32_t* __restrict__ 
       d = (int64_t)off[u + 1] - b;
     }
     const bool heavy_row = d > kHeavyFrontier;
-    const uint64_t mh = __ballot(heavy_row);
-    if (mh) {  // rare: one atomic per wave with a heavy row
-      long long hd = heavy_row ? d : 0;
-      for (int o = 1; o < kWave; o <<= 1) {
-        const long long y = __shfl_up(hd, o, kWave);
-        if (lane >= o) hd += y;
-      }
-      const long long hsum = __shfl(hd, kWave - 1, kWave);
-      const int leader = __ffsll((unsigned long long)mh) - 1;
-      unsigned long long old = 0;
-      if (lane == leader)
-        old = __hip_atomic_fetch_add(pack, ((unsigned long long)__popcll(mh) << kPackShift) | (unsigned long long)hsum,
-                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      old = __shfl(old, leader, kWave);
-      if (heavy_row) {
-        const long long slot = (long long)(old >> kPackShift) + __popcll(mh & lanemask_lt());
-        heavy[slot] = u;
-        hp[slot] = (long long)(old & kPackEdges) + hd - d;
-      }
-    }
+    heavy_reserve(heavy_row, u, d, heavy, hp, pack);
     if (heavy_row) d = 0;
     // exclusive scan of the row lengths across the wave
     int32_t inc = (int32_t)d;
@@ -726,6 +709,8 @@ cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reach
   long long* fpart = (long long*)(a.ws + a.L.hist);   // kBfsParts entries (the LDD histogram area)
   const I* off = (const I*)a.off;
   DevScalars* sc = a.ctx->dev;
+  if (m >= (int64_t(1) << kPackShift))
+    return fail(CC_EINVAL, "BFS sampling takes m < 2^%d adjacency entries (m=%lld)", kPackShift, (long long)m);
   cc_status st = count_heavy<I>(a);
   if (st != CC_OK) return st;
   const bool heavy = a.heavy_vertices > 0;
@@ -761,13 +746,11 @@ cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reach
                          m, level_cap);
       hipLaunchKernelGGL(k_bfs_step<I>, dim3(gs), dim3(kFBlock), 0, a.s, n, off, a.adj, vis, (const uint32_t*)fc, fn,
                          (const int32_t*)q[cur], &sc->qcount[cur], q[cur ^ 1], &sc->qcount[cur ^ 1], a.heavy,
-                         &sc->hcount, sc, fpart, a.tree_e);
-      if (heavy) {
-        list_prefix<I>(a, a.heavy, (const int32_t*)&sc->hcount);
+                         a.hp, sc, fpart, a.tree_e);
+      if (heavy)
         hipLaunchKernelGGL(k_bfs_heavy<I>, dim3(gh), dim3(kFBlock), 0, a.s, (const int32_t*)a.heavy,
-                           (const int32_t*)&sc->hcount, (const long long*)a.hp, off, a.adj, vis, fn, q[cur ^ 1],
-                           &sc->qcount[cur ^ 1], (const DevScalars*)sc, fpart, a.tree_e);
-      }
+                           (const long long*)a.hp, off, a.adj, vis, fn, q[cur ^ 1], &sc->qcount[cur ^ 1],
+                           (const DevScalars*)sc, fpart, a.tree_e);
       uint32_t* t2 = fc;
       fc = fn;
       fn = t2;

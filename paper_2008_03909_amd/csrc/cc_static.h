@@ -76,6 +76,5 @@ template <typename I> cc_status bfs_probe(StaticArgs& a, int32_t source, int lev
 template <typename I> cc_status count_heavy(StaticArgs& a);
 // Degree prefix of a device-counted vertex list: one block when the list is
 // known to be short, else the three-launch version.
-template <typename I> void list_prefix(StaticArgs& a, const int32_t* list, const int32_t* count_ptr);
 
 }  // namespace cc
