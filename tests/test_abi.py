@@ -129,3 +129,30 @@ def test_pair_list_workspace_sizing():
     assert L.cc_coo_workspace_bytes(10, -1, ctypes.byref(v), ctypes.byref(sz)) == b.CC_EINVAL
     bad = v.copy(find=b.FIND_COMPRESS)
     assert L.cc_coo_workspace_bytes(10, 10, ctypes.byref(bad), ctypes.byref(sz)) == b.CC_EINVAL
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C layout: gcc
+    compiles the header and prints every field's offset and each size."""
+    structs = {"cc_variant": b.cc_variant, "cc_amsf_options": b.cc_amsf_options, "cc_stats": b.cc_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "connectit_hip.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            name, field, val = line.split()
+            got[(name, field)] = int(val)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
