@@ -30,6 +30,8 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,
     "-I", CSRC,
+    "-Wall",
+    "-Wextra",
     "-Wno-unused-result",
 ]
 

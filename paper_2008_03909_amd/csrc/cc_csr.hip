@@ -89,7 +89,6 @@ __global__ void k_radix_scatter(const unsigned long long* __restrict__ keys, uns
   __shared__ uint32_t wcnt[kWavesPerSortBlock][256];
   const int t = threadIdx.x;
   const int w = t / kWave;
-  const int lane = lane_id();
   gofs[t] = hist_scan[(int64_t)t * nblocks + blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   const uint64_t lt = lanemask_lt();

@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kHpTile) k_hp_tiles(const int32_t* __restrict_
   if (threadIdx.x == 0) tsum[blockIdx.x] = total;
 }
 
-static __global__ void __launch_bounds__(kHpTile) k_hp_top(const int32_t* count_ptr, long long* tsum) {
+[[maybe_unused]] static __global__ void __launch_bounds__(kHpTile) k_hp_top(const int32_t* count_ptr, long long* tsum) {
   const int64_t c = *count_ptr;
   const int64_t tiles = (c + kHpTile - 1) / kHpTile;
   long long carry = 0;
@@ -348,9 +348,9 @@ inline void visit_candidates(hipStream_t s, const CandLists& L, const I* off, co
                      L.cand, L.big, L.heavy, L.hp, L.sc, off, adj, op, flag);
 }
 
-static __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+[[maybe_unused]] static __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
-static __global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v) {
+[[maybe_unused]] static __global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
 }

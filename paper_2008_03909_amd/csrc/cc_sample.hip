@@ -784,8 +784,8 @@ cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reach
   }
   // the batch queued after the finishing snapshot does nothing; wait for it
   CC_HIP(hipStreamSynchronize(a.s));
-  hipEventDestroy(ev[0]);
-  hipEventDestroy(ev[1]);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
   if (result != CC_OK) return result;
   *reached_out = fin.reached;
   *levels_out = fin.level;

@@ -233,12 +233,12 @@ cc_status cc_server_create(cc_ctx* ctx, int64_t n, const cc_variant* v, int64_t 
 
 void cc_server_destroy(cc_server* s) {
   if (!s) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   for (auto* r : s->all) delete r;
-  for (auto e : s->events) hipEventDestroy(e);
-  for (auto x : s->streams) hipStreamDestroy(x);
-  if (s->barrier_stream) hipStreamDestroy(s->barrier_stream);
-  if (s->dpool) hipFree(s->dpool);
+  for (auto e : s->events) (void)hipEventDestroy(e);
+  for (auto x : s->streams) (void)hipStreamDestroy(x);
+  if (s->barrier_stream) (void)hipStreamDestroy(s->barrier_stream);
+  if (s->dpool) (void)hipFree(s->dpool);
   cc_stream_destroy(s->st);
   delete s;
 }

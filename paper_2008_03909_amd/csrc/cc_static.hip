@@ -65,7 +65,7 @@ PhaseScope::PhaseScope(cc_ctx* c, hipStream_t st, const char* nm) : ctx(c), s(st
   // measurement of one phase records only that phase's pair
   if (ctx && ctx->timing && (ctx->timing_only.empty() || ctx->timing_only == nm)) {
     a = get_event(ctx);
-    if (a) hipEventRecord(a, s);
+    if (a) (void)hipEventRecord(a, s);
   }
 }
 
@@ -73,15 +73,15 @@ PhaseScope::~PhaseScope() {
   if (!a) return;
   hipEvent_t b = get_event(ctx);
   if (!b) return;
-  hipEventRecord(b, s);
+  (void)hipEventRecord(b, s);
   ctx->pending.push_back({name, a, b});
 }
 
 static void harvest(cc_ctx* ctx) {
   for (auto& r : ctx->pending) {
-    hipEventSynchronize(r.b);
+    (void)hipEventSynchronize(r.b);
     float ms = 0.f;
-    hipEventElapsedTime(&ms, r.a, r.b);
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
     size_t i = 0;
     for (; i < ctx->phase_names.size(); ++i)
       if (ctx->phase_names[i] == r.name) break;
@@ -1158,9 +1158,9 @@ cc_status cc_ctx_create(int device, cc_ctx** out) {
       hipHostMalloc((void**)&c->sel_host, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void**)&c->sel_dev, c->sel_host, 0) != hipSuccess ||
       hipHostMalloc((void**)&c->ring_host, 256, hipHostMallocDefault) != hipSuccess) {
-    if (c->dev) hipFree(c->dev);
-    if (c->host) hipHostFree(c->host);
-    if (c->sel_host) hipHostFree(c->sel_host);
+    if (c->dev) (void)hipFree(c->dev);
+    if (c->host) (void)hipHostFree(c->host);
+    if (c->sel_host) (void)hipHostFree(c->sel_host);
     delete c;
     return fail(CC_ENOMEM, "cannot allocate context state");
   }
@@ -1173,18 +1173,18 @@ cc_status cc_ctx_create(int device, cc_ctx** out) {
 
 void cc_ctx_destroy(cc_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
   for (auto& r : ctx->pending) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
-  for (auto e : ctx->event_pool) hipEventDestroy(e);
-  if (ctx->dev) hipFree(ctx->dev);
-  if (ctx->host) hipHostFree(ctx->host);
-  if (ctx->sel_host) hipHostFree(ctx->sel_host);
-  if (ctx->ring_host) hipHostFree(ctx->ring_host);
-  if (ctx->amsf_host) hipHostFree(ctx->amsf_host);
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->dev) (void)hipFree(ctx->dev);
+  if (ctx->host) (void)hipHostFree(ctx->host);
+  if (ctx->sel_host) (void)hipHostFree(ctx->sel_host);
+  if (ctx->ring_host) (void)hipHostFree(ctx->ring_host);
+  if (ctx->amsf_host) (void)hipHostFree(ctx->amsf_host);
   delete ctx;
 }
 

@@ -259,17 +259,16 @@ cc_status cc_stream_create(cc_ctx* ctx, int64_t n, const cc_variant* v, cc_strea
          hipMalloc((void**)&s->ecnt, 256) == hipSuccess;
   if (ok && v->finish == CC_FIN_UF_HOOKS) {
     ok = hipMalloc((void**)&s->H, (size_t)n * 4) == hipSuccess;
-    if (ok) hipMemset(s->H, 0xff, (size_t)n * 4);
+    if (ok) ok = hipMemset(s->H, 0xff, (size_t)n * 4) == hipSuccess;
   }
   if (!ok) {
     for (void* p : {(void*)s->P, (void*)s->err, (void*)s->H, (void*)s->Q, (void*)s->ecnt})
-      if (p) hipFree(p);
+      if (p) (void)hipFree(p);
     delete s;
     return fail(CC_ENOMEM, "cannot allocate the stream state (%lld vertices)", (long long)n);
   }
   hipLaunchKernelGGL(k_stream_init, dim3(grid_for(n, 256, 4096)), dim3(256), 0, (hipStream_t)0, n, s->P);
-  hipMemset(s->err, 0, 256);
-  if (hipDeviceSynchronize() != hipSuccess) {
+  if (hipMemset(s->err, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     cc_stream_destroy(s);
     return fail(CC_EDEVICE, "stream initialisation failed");
   }
@@ -279,9 +278,9 @@ cc_status cc_stream_create(cc_ctx* ctx, int64_t n, const cc_variant* v, cc_strea
 
 void cc_stream_destroy(cc_stream* s) {
   if (!s) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();  // teardown: errors have nowhere to go
   for (void* p : {(void*)s->P, (void*)s->err, (void*)s->H, (void*)s->Q, (void*)s->eu, (void*)s->ev, (void*)s->ecnt})
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   delete s;
 }
 
