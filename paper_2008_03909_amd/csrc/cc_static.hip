@@ -167,7 +167,8 @@ WsLayout ws_layout(int64_t n, int64_t m, const cc_variant* v) {
   L.hist = off, off += align256(4096 * 4);
   L.mlp = off, off += 65536;   // selector: feature partials, label stats, one MLP row
   if (v->finish == CC_FIN_LT && (v->lt_rules & CC_LT_ALTER)) L.edges = off, off += 2 * align256((size_t)m * 4);
-  L.seg = off, off += align256((size_t)kSegMaxHost * 16) + 2 * align256((size_t)kSegMaxHost * 8);
+  L.seg = off, off += align256((size_t)kSegMaxHost * 16) + 2 * align256((size_t)kSegMaxHost * 8) +
+                     align256((size_t)kSegMaxHost / 4 * 16) + 2 * align256((size_t)kSegMaxHost / 4 * 8);
   {
     const size_t hcap = heavy_cap(m);  // vertices with degree above the frontier threshold
     L.heavy = off, off += align256(hcap * 4) + align256((hcap + 1) * 8) + align256((hcap / kHpTile + 3) * 8);
@@ -566,10 +567,13 @@ __global__ void __launch_bounds__(kBlock) k_resolve_lmax(DevScalars* sc, const u
 // gather copies every segment into the final lists (thread bin: cand; wave
 // bin: big front; block bin: big back; grid bin: heavy), classifying the
 // back entries by degree.  The lists come out in a fixed order, so the finish
-// does the same work every run.  The grid bin's degree prefix (the offsets
-// its edge-balanced visitor searches) is built along the way: per-segment
-// sums of the grid-bin degrees, scanned with the counts, then a wave scan in
-// the gather.
+// does the same work every run.  The scan is two-level: each block of the
+// segment kernel (four waves, four consecutive segments) also writes its
+// group's totals, the one-block scan runs over groups only, and the gather
+// adds the counts of the at most three earlier segments of its group.  The
+// grid bin's degree prefix (the offsets its edge-balanced visitor searches)
+// is built along the way: per-segment sums of the grid-bin degrees, scanned
+// with the counts, then a wave scan in the gather.
 constexpr int kSegMax = 8448;  // upper bound on the number of segments
 
 template <typename I>
@@ -577,17 +581,23 @@ __global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, co
                                                         const int32_t* __restrict__ P, const DevScalars* sc,
                                                         int32_t* __restrict__ scratch, int32_t* __restrict__ segcnt,
                                                         long long* __restrict__ segedges,
-                                                        long long* __restrict__ segheavy, int aligned) {
+                                                        long long* __restrict__ segheavy,
+                                                        int4* __restrict__ grpcnt, long long* __restrict__ grpedges,
+                                                        long long* __restrict__ grpheavy, int aligned) {
+  static_assert(kBlock / kWave == 4, "a block is one group of four segments");
+  __shared__ int32_t gc[4][4];
+  __shared__ long long ge[4], gh[4];
   const int32_t L = sc->lmax;
   const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
   const uint64_t lt = lanemask_lt_dev();
   const int64_t nseg = div_up_dev(n, S);
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; w < nseg; w += waves) {
+  const int64_t w = blockIdx.x * (int64_t)(blockDim.x / kWave) + wv;  // one segment per wave
+  int32_t c0 = 0, cb = 0, c2 = 0, c3 = 0;
+  long long edges = 0, hedges = 0;
+  if (w < nseg) {
     const int64_t lo = w * S;
     const int64_t hi = (lo + S < n) ? lo + S : n;
-    int32_t c0 = 0, cb = 0, c2 = 0, c3 = 0;
-    long long edges = 0, hedges = 0;
     for (int64_t base = lo; base < hi; base += 4 * kWave) {
       const int64_t v0 = base + 4 * lane;
       const bool act = v0 < hi;
@@ -617,16 +627,31 @@ __global__ void __launch_bounds__(kBlock) k_compact_seg(int64_t n, int64_t S, co
         if (large && deg > kThrGrid) hedges += deg;
       }
     }
-    edges = wave_sum(edges);
-    hedges = wave_sum(hedges);
-    if (lane == 0) {
-      segcnt[4 * w + 0] = c0;
-      segcnt[4 * w + 1] = cb - c2 - c3;
-      segcnt[4 * w + 2] = c2;
-      segcnt[4 * w + 3] = c3;
+  }
+  edges = wave_sum(edges);
+  hedges = wave_sum(hedges);
+  if (lane == 0) {
+    if (w < nseg) {
+      *(int4*)(segcnt + 4 * w) = make_int4(c0, cb - c2 - c3, c2, c3);
       segedges[w] = edges;
       segheavy[w] = hedges;
     }
+    gc[wv][0] = c0, gc[wv][1] = cb - c2 - c3, gc[wv][2] = c2, gc[wv][3] = c3;
+    ge[wv] = edges;
+    gh[wv] = hedges;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int4 t = make_int4(0, 0, 0, 0);
+    long long e = 0, h = 0;
+    for (int k = 0; k < 4; ++k) {
+      t.x += gc[k][0], t.y += gc[k][1], t.z += gc[k][2], t.w += gc[k][3];
+      e += ge[k];
+      h += gh[k];
+    }
+    grpcnt[blockIdx.x] = t;
+    grpedges[blockIdx.x] = e;
+    grpheavy[blockIdx.x] = h;
   }
 }
 
@@ -640,19 +665,17 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
   return x;
 }
 
-// One block: exclusive scan of the per-segment counts (four bins) and of the
-// grid-bin degree sums, in place; bin totals and the candidates' edge total
+// One block: exclusive scan of the group totals (four bin counts and the
+// grid-bin degree sums), in place; bin totals and the candidates' edge total
 // into the context scalars, the grid bin's edge total into hp[count].
-// Thread t owns a run of at most kScanRun consecutive segments, loaded all
-// at once; the run totals go through one block scan (wave scans, then one
-// wave scans the wave totals), and each thread writes its run back.
-// (Slices of 1024 segments with coalesced loads and a block scan per slice
-// were measured slower: the chained wave scans of eight slices cost more
-// than the strided loads they save.)
-constexpr int kScanRun = (kSegMax + 1023) / 1024;
+// Thread t owns a run of at most kScanRun consecutive groups, loaded all at
+// once; the run totals go through one block scan (wave scans, then one wave
+// scans the wave totals), and each thread writes its run back.
+constexpr int kGrpMax = kSegMax / 4;
+constexpr int kScanRun = (kGrpMax + 1023) / 1024;
 
-__global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* segcnt, const long long* segedges,
-                                                       long long* segheavy, long long* hp, DevScalars* sc) {
+__global__ void __launch_bounds__(1024) k_compact_scan(int64_t ngrp, int4* grpcnt, const long long* grpedges,
+                                                       long long* grpheavy, long long* hp, DevScalars* sc) {
   constexpr int kWaves = 1024 / kWave;
   __shared__ int32_t wc[4][kWaves];
   __shared__ long long wh[kWaves];
@@ -660,7 +683,7 @@ __global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* se
   __shared__ int32_t tot[4];
   __shared__ long long htot;
   const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
-  const int64_t per = div_up_dev(nseg, 1024);
+  const int64_t per = div_up_dev(ngrp, 1024);
   const int64_t lo = t * per;
   int4 c[kScanRun];
   long long h[kScanRun];
@@ -671,10 +694,10 @@ __global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* se
     const int64_t i = lo + j;
     c[j] = make_int4(0, 0, 0, 0);
     h[j] = 0;
-    if (j < per && i < nseg) {
-      c[j] = *(const int4*)(segcnt + 4 * i);
-      h[j] = segheavy[i];
-      e += segedges[i];
+    if (j < per && i < ngrp) {
+      c[j] = grpcnt[i];
+      h[j] = grpheavy[i];
+      e += grpedges[i];
     }
   }
 #pragma unroll
@@ -716,9 +739,9 @@ __global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* se
 #pragma unroll
   for (int j = 0; j < kScanRun; ++j) {
     const int64_t i = lo + j;
-    if (j < per && i < nseg) {
-      *(int4*)(segcnt + 4 * i) = make_int4(r[0], r[1], r[2], r[3]);
-      segheavy[i] = hr;
+    if (j < per && i < ngrp) {
+      grpcnt[i] = make_int4(r[0], r[1], r[2], r[3]);
+      grpheavy[i] = hr;
       r[0] += c[j].x, r[1] += c[j].y, r[2] += c[j].z, r[3] += c[j].w;
       hr += h[j];
     }
@@ -735,29 +758,35 @@ __global__ void __launch_bounds__(1024) k_compact_scan(int64_t nseg, int32_t* se
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_compact_gather(int64_t n, int64_t S, const I* __restrict__ off,
                                                            const int32_t* __restrict__ scratch,
-                                                           const int32_t* __restrict__ segoff,
+                                                           const int4* __restrict__ segcnt,
                                                            const long long* __restrict__ segheavy,
+                                                           const int4* __restrict__ grpoff,
+                                                           const long long* __restrict__ grpheavy,
                                                            int32_t* __restrict__ cand, int32_t* __restrict__ big,
-                                                           int32_t* __restrict__ heavy, long long* __restrict__ hp,
-                                                           const DevScalars* sc) {
+                                                           int32_t* __restrict__ heavy, long long* __restrict__ hp) {
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt_dev();
   const int64_t nseg = div_up_dev(n, S);
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  int32_t tot[4];
-  for (int q = 0; q < 4; ++q) tot[q] = sc->bin_count[q];
   for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; w < nseg; w += waves) {
     const int64_t lo = w * S;
     const int64_t hi = (lo + S < n) ? lo + S : n;
-    int32_t o[4], c[4];
-    for (int q = 0; q < 4; ++q) {
-      o[q] = segoff[4 * w + q];
-      c[q] = ((w + 1 < nseg) ? segoff[4 * (w + 1) + q] : tot[q]) - o[q];
+    // this segment's list offsets: its group's offsets plus the counts of
+    // the group's earlier segments
+    const int64_t g = w / 4;
+    int4 ov = grpoff[g];
+    long long hb = grpheavy[g];
+    for (int64_t s2 = 4 * g; s2 < w; ++s2) {
+      const int4 x = segcnt[s2];
+      ov.x += x.x, ov.y += x.y, ov.z += x.z, ov.w += x.w;
+      hb += segheavy[s2];
     }
+    const int4 cv = segcnt[w];
+    const int32_t o[4] = {ov.x, ov.y, ov.z, ov.w};
+    const int32_t c[4] = {cv.x, cv.y, cv.z, cv.w};
     for (int32_t i = lane; i < c[0]; i += kWave) cand[o[0] + i] = scratch[lo + i];
     const int32_t cb = c[1] + c[2] + c[3];
     int32_t r1 = o[1], r2 = o[2], r3 = o[3];
-    long long hb = segheavy[w];
     for (int32_t i0 = 0; i0 < cb; i0 += kWave) {
       const int32_t i = i0 + lane;
       int32_t x = 0;
@@ -1022,15 +1051,20 @@ cc_status compact_candidates(StaticArgs& a) {
   int32_t* segcnt = (int32_t*)(a.ws + a.L.seg);
   long long* segedges = (long long*)(a.ws + a.L.seg + align256((size_t)kSegMax * 16));
   long long* segheavy = segedges + align256((size_t)kSegMax * 8) / 8;
-  const unsigned gw = grid_for(nseg * kWave, kBlock, 2048);
+  int4* grpcnt = (int4*)(segheavy + align256((size_t)kSegMax * 8) / 8);
+  long long* grpedges = (long long*)(grpcnt + align256((size_t)kGrpMax * 16) / 16);
+  long long* grpheavy = grpedges + align256((size_t)kGrpMax * 8) / 8;
+  // one block per group of four segments; the gather walks the segments
+  const int64_t ngrp = div_up(nseg, 4);
+  const unsigned gw = (unsigned)ngrp;
   hipLaunchKernelGGL(k_compact_seg<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
                      (const int32_t*)a.P, (const DevScalars*)a.ctx->dev, a.count, segcnt, segedges, segheavy,
-                     vec_ok(a));
-  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, a.s, nseg, segcnt, (const long long*)segedges,
-                     segheavy, a.hp, a.ctx->dev);
+                     grpcnt, grpedges, grpheavy, vec_ok(a));
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, a.s, ngrp, grpcnt, (const long long*)grpedges,
+                     grpheavy, a.hp, a.ctx->dev);
   hipLaunchKernelGGL(k_compact_gather<I>, dim3(gw), dim3(kBlock), 0, a.s, a.n, S, (const I*)a.off,
-                     (const int32_t*)a.count, (const int32_t*)segcnt, (const long long*)segheavy, a.cand, a.big,
-                     a.heavy, a.hp, (const DevScalars*)a.ctx->dev);
+                     (const int32_t*)a.count, (const int4*)segcnt, (const long long*)segheavy,
+                     (const int4*)grpcnt, (const long long*)grpheavy, a.cand, a.big, a.heavy, a.hp);
   CC_LAUNCH_CHECK();
   return CC_OK;
 }
