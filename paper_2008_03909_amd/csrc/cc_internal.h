@@ -31,7 +31,7 @@ struct DevScalars {
   unsigned long long heavy_count;  // vertices with degree above the frontier threshold
   unsigned long long heavy_pack;   // LDD: heavy frontier rows (high 28 bits) and their edges (low 36)
   uint32_t flag2;          // spare flag for sub-rounds (full shortcut)
-  int32_t hcount;          // heavy frontier vertices deferred to the grid kernel
+  int32_t hcount;          // k-out max-degree: rows long enough for a wave each
   long long ldd_fe[2];     // LDD: degree sum of the frontier being built in queue 0 / 1
   long long ldd_seen;      // LDD: degree sum of every frontier expanded so far
   int32_t bu_rounds;       // BFS levels / LDD rounds run bottom-up in this call

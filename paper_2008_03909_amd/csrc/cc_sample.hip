@@ -64,7 +64,6 @@ __global__ void k_bfs_start(int32_t s, const I* off, uint32_t* vis, uint32_t* fc
   sc->bfs_mode = kBfsTopDown;
   sc->bfs_level = 0;
   sc->reached = 1;
-  sc->hcount = 0;
   sc->heavy_pack = 0ull;
 }
 
@@ -147,7 +146,6 @@ __global__ void __launch_bounds__(kFBlock) k_bfs_begin(int64_t words, uint32_t* 
       if (mode == kBfsTopDown && mf <= kSmallEdges && (level_cap <= 0)) mode = kBfsSmall;
       sc->bfs_mode = mode;
       sc->qcount[cur ^ 1] = 0;
-      sc->hcount = 0;
       sc->heavy_pack = 0ull;
       if (mode != kBfsDone) sc->bfs_level += 1;
     }
@@ -658,11 +656,6 @@ __global__ void __launch_bounds__(kFBlock) k_expand_heavy(const int32_t* __restr
   if (LDD) ldd_add_edges(added, &sc->ldd_fe[cur ^ 1]);
 }
 
-__global__ void k_round_reset(DevScalars* sc, int nxt) {
-  sc->qcount[nxt] = 0;
-  sc->hcount = 0;
-}
-
 // Minimum reached vertex = lowest set bit of the visited bitmap (one atomic
 // per block; the grid is kept small).
 __global__ void __launch_bounds__(kFBlock) k_bitmap_min(const uint32_t* __restrict__ vis, int64_t words,
@@ -893,7 +886,6 @@ __global__ void __launch_bounds__(kFBlock) k_ldd_wake(int64_t lo, int64_t hi, co
   WaveQ wq{qbuf[threadIdx.x / kWave], 0};
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->qcount[nxt] = 0;
-    sc->hcount = 0;
     sc->heavy_pack = 0ull;
     sc->ldd_seen += sc->ldd_fe[nxt];
     sc->ldd_fe[nxt] = 0;
