@@ -148,3 +148,30 @@ def test_training_lowers_the_loss(ctx):
     Y = np.maximum(X @ W, 0).astype(np.float32) * 0.3
     _, _, hist = selector.train(ctx, X, Y, epochs=60, batch=32, lr=3e-3)
     assert hist[-1] < 0.5 * hist[0]
+
+
+def test_decision_matches_oracle_forward_with_the_trained_model(ctx):
+    """The device decision (forward pass and argmin on the returned features)
+    equals the oracle's forward pass on the same features, unless the two
+    best outputs are within rounding of each other."""
+    import os
+    z = np.load(os.path.join(os.path.dirname(selector.__file__), "selector_data", "model.npz"), allow_pickle=False)
+    K, norm = int(z["K"]), z["norm"].astype(np.float32)
+    params = b.mlp_pack_bf16(torch.from_numpy(z["master"].astype(np.float32)).to(ctx.torch_device))
+    arms = selector.arms()
+    sd = np.where(norm[16:] > 0, norm[16:], 1.0).astype(np.float32)
+    checked = 0
+    for s in (1000, 1010, 1020, 1030, 1040, 1050, 1060, 1070):
+        fam, g = selector.corpus_graph(s, 12, 16)
+        d = b.build_csr(ctx, g.n, g.u, g.v)
+        _, chosen, feats = b.select_variant(ctx, d, params, arms, norm)
+        x = (np.array(feats, np.float32) - norm[:16]) / sd
+        y, _ = omlp.forward(omlp.bf16_round(z["master"]), x[None, :].astype(np.float64), K)
+        y = y[0]
+        order = np.argsort(y, kind="stable")
+        if y[order[1]] - y[order[0]] > 1e-3 * max(1.0, abs(y[order[0]])):
+            assert chosen == int(order[0]), (fam, s, chosen, order[:2])
+            checked += 1
+        else:
+            assert chosen in (int(order[0]), int(order[1])), (fam, s)
+    assert checked >= 4
