@@ -619,3 +619,103 @@ def test_kout_pure_and_afforest_are_partial_labellings():
         # afforest with k >= every degree picks every edge: the exact labelling
         lab, c = oracle.kout_sample(g.n, off, adj, int(np.diff(off).max()) + 1, seed=seed, mode=1)
         assert np.array_equal(lab, true)
+
+
+# ---- selector degree features: closed forms of the population moments ----------
+
+def _offsets(degrees):
+    return np.concatenate([[0], np.cumsum(np.asarray(degrees, np.int64))])
+
+
+def test_degree_features_star_closed_form():
+    # star with 4 leaves: degrees (4,1,1,1,1), mean 8/5, variance 4 - 64/25 = 36/25,
+    # sd 6/5, third central moment (2.4^3 - 4*0.6^3)/5 = 2.592 = 1.5 * sd^3
+    f = oracle.degree_features(_offsets([4, 1, 1, 1, 1]))
+    exp = {0: np.log2(5), 1: np.log2(9), 2: 8 / 5, 3: 0.75, 4: 2.5, 5: 0.0, 6: 0.8, 7: 0.8,
+           8: 1.5, 14: 1.0, 15: np.log2(5)}
+    for i, e in exp.items():
+        assert abs(f[i] - e) < 1e-12, (i, f[i], e)
+
+
+def test_degree_features_path_closed_form():
+    # path on 4 vertices: degrees (1,2,2,1), mean 3/2, sd 1/2, symmetric -> skew 0
+    f = oracle.degree_features(_offsets([1, 2, 2, 1]))
+    exp = {0: 2.0, 1: np.log2(7), 2: 1.5, 3: 1 / 3, 4: 4 / 3, 5: 0.0, 6: 0.5, 7: 1.0,
+           8: 0.0, 14: 1.0, 15: np.log2(3)}
+    for i, e in exp.items():
+        assert abs(f[i] - e) < 1e-12, (i, f[i], e)
+
+
+def test_degree_features_regular_and_empty_branches():
+    # K_5: every degree 4 -> sd = 0 (CV and skew take their zero branch), m/n = 4 >= 3
+    f = oracle.degree_features(_offsets([4] * 5))
+    exp = {0: np.log2(5), 1: np.log2(21), 2: 4.0, 3: 0.0, 4: 1.0, 5: 0.0, 6: 0.0, 7: 0.0,
+           8: 0.0, 14: 0.0, 15: np.log2(5)}
+    for i, e in exp.items():
+        assert abs(f[i] - e) < 1e-12, (i, f[i], e)
+    # K_4: m/n = 3 exactly, and the flag is strict (m/n < 3)
+    assert oracle.degree_features(_offsets([3] * 4))[14] == 0.0
+    # no edges: mean 0 -> CV and max/mean take their zero branch; every degree is 0 (<= 2)
+    f = oracle.degree_features(_offsets([0] * 6))
+    exp = {0: np.log2(6), 1: 0.0, 2: 0.0, 3: 0.0, 4: 0.0, 5: 1.0, 6: 0.0, 7: 1.0,
+           8: 0.0, 14: 1.0, 15: 0.0}
+    for i, e in exp.items():
+        assert abs(f[i] - e) < 1e-12, (i, f[i], e)
+
+
+def test_degree_features_skew_sign_and_library_moments():
+    # one hub among many degree-2 vertices: right-skewed; a single low vertex
+    # among many degree-5 ones: left-skewed; magnitudes against scipy's
+    # population (biased) moments, an independent implementation
+    from scipy import stats
+    for degs, sign in (([9, 2, 2, 2, 2, 2, 3], 1), ([0, 5, 5, 5, 5, 4], -1)):
+        f = oracle.degree_features(_offsets(degs))
+        d = np.asarray(degs, np.float64)
+        assert np.sign(f[8]) == sign
+        assert abs(f[8] - stats.skew(d, bias=True)) < 1e-12
+        assert abs(f[3] - stats.variation(d)) < 1e-12
+        # fractions by counting
+        assert f[5] == sum(x == 0 for x in degs) / len(degs)
+        assert f[6] == sum(x == 1 for x in degs) / len(degs)
+        assert f[7] == sum(x <= 2 for x in degs) / len(degs)
+        assert f[14] == float(sum(degs) < 3 * len(degs))
+
+
+# ---- partial labelling checker: planted violations must be caught ----------------
+
+def _partial_by_pairs(s, t):
+    """Definition by brute force over all pairs: s[i] == s[j] implies t[i] == t[j]."""
+    k = len(s)
+    return all(t[i] == t[j] for i in range(k) for j in range(k) if s[i] == s[j])
+
+
+def test_partial_labelling_accepts_refinements():
+    true = np.array([0, 0, 0, 3, 3, 5])
+    assert oracle.partial_labelling_ok(true, true)                       # the labelling itself
+    assert oracle.partial_labelling_ok(np.arange(6), true)               # identity (nothing sampled)
+    assert oracle.partial_labelling_ok(np.array([0, 1, 0, 3, 4, 5]), true)
+    assert oracle.partial_labelling_ok(np.array([], np.int64), np.array([], np.int64))
+
+
+def test_partial_labelling_rejects_planted_violations():
+    true = np.array([0, 0, 2, 2, 4])
+    # a sample class spanning two true components, with the stray member first,
+    # in the middle and last in the class
+    for s in ([0, 0, 0, 2, 4], [2, 0, 2, 2, 4], [0, 2, 2, 2, 4], [0, 0, 2, 2, 0]):
+        assert not oracle.partial_labelling_ok(np.array(s), true), s
+    # one class merges everything
+    assert not oracle.partial_labelling_ok(np.zeros(5, np.int64), true)
+    # one violating vertex among many correct ones
+    t = np.repeat(np.arange(50) * 10, 10)
+    s = t.copy()
+    s[257] = s[100]
+    assert not oracle.partial_labelling_ok(s, t)
+
+
+def test_partial_labelling_against_pairwise_brute_force():
+    rng = np.random.default_rng(7)
+    for _ in range(400):
+        k = int(rng.integers(1, 9))
+        t = rng.integers(0, 3, k)
+        s = rng.integers(0, 4, k)
+        assert oracle.partial_labelling_ok(s, t) == _partial_by_pairs(s, t), (s, t)
