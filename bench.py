@@ -127,18 +127,25 @@ def read_traffic(kernel: str, workload_name: str):
         return None
 
 
-def cpu_baseline(g, m: int):
+def cpu_baseline(g, m: int, timed_labels=None, timed_ncomp=None):
     """The CPU oracle (sequential union-find over the pair list) on the same
-    workload, one host core, median of 3 runs."""
+    workload, one host core, median of 3 runs.  Its labels are also compared
+    element by element with the labels of the timed GPU steps."""
+    import numpy as np
+
     import oracle
 
     if not os.path.exists(oracle._SO):
         oracle.build()
     ts = []
+    want = wc = None
     for _ in range(3):
         t = time.perf_counter()
-        oracle.uf_cc(g.n, g.u, g.v)
+        want, wc = oracle.uf_cc(g.n, g.u, g.v)
         ts.append(time.perf_counter() - t)
+    match = None
+    if timed_labels is not None:
+        match = bool(np.array_equal(timed_labels, want)) and int(timed_ncomp) == int(wc)
     t = statistics.median(ts)
     cpu = "unknown"
     try:
@@ -150,7 +157,8 @@ def cpu_baseline(g, m: int):
         pass
     return {"value": m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"full workload ({g.num_pairs} pairs), sequential union-find oracle, median of 3 runs "
-                      f"({t:.2f} s each); host {cpu}, {os.cpu_count()} logical cpus"}
+                      f"({t:.2f} s each); host {cpu}, {os.cpu_count()} logical cpus",
+            "labels_match_oracle": match}
 
 
 def incremental(ctx, g, seed: int = 5, max_pairs: int | None = None):
@@ -577,6 +585,8 @@ def main():
     ctx.sync_status()
     timed = ctx.phase_times()
     st = ctx.last_stats()
+    timed_labels = labels.cpu().numpy()      # the last timed step's output, checked by the CPU leg
+    timed_ncomp = int(ncomp.item())
     # per-phase breakdown from a separate pass with every phase timed; the
     # dominant phase keeps the timed region's own measurement
     ctx.set_timing(True)
@@ -686,8 +696,10 @@ def main():
                 f"p99 {r['p99_ms']:.3f} ms")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(g, m)
-        log(f"cpu baseline: {out['cpu_baseline']['value']:.3e} edges/s")
+        out["cpu_baseline"] = cpu_baseline(g, m, timed_labels, timed_ncomp)
+        out["labels_match_oracle"] = out["cpu_baseline"]["labels_match_oracle"]
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3e} edges/s, "
+            f"timed labels match the oracle: {out['labels_match_oracle']}")
     out["host"] = platform.node()
     ctx.close()
     print(json.dumps(out), flush=True)

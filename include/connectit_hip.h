@@ -193,7 +193,10 @@ cc_status cc_workspace_bytes(int64_t n, int64_t m, const cc_variant* v, size_t* 
  * must be symmetric (the skip of the frequent component relies on it);
  * rows need not be sorted, but the k-out "first edge" is adj[offsets[v]].
  * Self-loops and duplicates are allowed.  m must fit int32 offsets unless
- * offsets_are_64bit.  workspace: device buffer of >= cc_workspace_bytes.
+ * offsets_are_64bit.  The kernels do not range-check offsets or ids: a
+ * malformed CSR faults the device instead of returning an error (check
+ * untrusted input with cc_validate_csr first).
+ * workspace: device buffer of >= cc_workspace_bytes.
  * num_components_dev (nullable): one int64 written on the device.
  * Round-based variants (BFS, LDD, SV, LT) read a 4-byte flag per round and
  * so synchronise hip_stream internally; k-out/none + union-find does not. */
@@ -297,6 +300,48 @@ cc_status cc_csr_workspace_bytes(int64_t n, int64_t num_pairs, size_t* bytes);
 cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v, int dedup,
                        void* workspace, size_t ws_bytes, void* offsets_out, int offsets_64bit, int32_t* adj_out,
                        int64_t* m_dev, void* hip_stream);
+
+/* ---- CSR validator (debug aid) ----------------------------------------------
+ * The static calls trust their CSR: they index the parent array with
+ * adjacency ids and the adjacency with offsets without range checks, so a
+ * malformed CSR is a GPU memory fault there, not an error code; and the skip
+ * of the most frequent sampled component (Section 3.1) is only correct on a
+ * symmetric graph (appendix "Correctness for Sampling Algorithms").
+ * cc_validate_csr checks a CSR before use:
+ *   CC_CSR_OFFSET0     offsets[0] != 0;
+ *   CC_CSR_OFFSETN     offsets[n] != m;
+ *   CC_CSR_MONOTONE    some row has offsets[v] > offsets[v+1], or a bound
+ *                      outside [0, m] (its entries are then not read);
+ *   CC_CSR_ID_RANGE    some adjacency id outside [0, n);
+ *   CC_CSR_ASYMMETRIC  (check_symmetric != 0, only run when the checks above
+ *                      pass) some entry (v, w) has no entry (w, v).  With
+ *                      every row ascending this is exact (a binary search in
+ *                      row w per entry; bad_entries counts the entries
+ *                      without a reverse); otherwise the multisets {(v, w)}
+ *                      and {(w, v)} are compared by a 64-bit hash sum, so a
+ *                      symmetric CSR always passes, an asymmetric one fails
+ *                      but for a 64-bit hash coincidence, and a pair stored
+ *                      more often in one direction than the other counts as
+ *                      asymmetric.
+ * Inputs as for cc_connectivity_csr (device offsets and adj); report is a
+ * host struct.  Returns CC_OK for a valid CSR and CC_EDEVICE when a check
+ * failed (report says which); host-checkable argument errors give
+ * CC_EINVAL.  The device-side checks set the context's error word (bad id,
+ * malformed CSR) and the call clears it again after reading it; an error
+ * word left by an earlier call is returned first, without validating.
+ * Synchronises the device (once) and hip_stream (twice or three times);
+ * allocates nothing. */
+enum { CC_CSR_OFFSET0 = 1, CC_CSR_OFFSETN = 2, CC_CSR_MONOTONE = 4, CC_CSR_ID_RANGE = 8, CC_CSR_ASYMMETRIC = 16 };
+typedef struct {
+  uint32_t failed;          /* CC_CSR_* bits of the checks that failed (0: valid) */
+  int32_t rows_sorted;      /* 1 iff every well-formed row is ascending */
+  int32_t symmetry_checked; /* 0 not checked, 1 exact (ascending rows), 2 hash of multisets */
+  int32_t reserved;
+  int64_t bad_entries;      /* ids out of range, or (exact check) entries without a reverse */
+  int64_t first_bad_row;    /* smallest row where a check failed, -1 if none or unknown */
+} cc_csr_report;
+cc_status cc_validate_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                          const int32_t* adj, int check_symmetric, cc_csr_report* report, void* hip_stream);
 
 /* ---- batch-incremental connectivity (Section 3.4 "Streaming") ---------------
  * A cc_stream owns an n x int32 parent array on the device (allocated by

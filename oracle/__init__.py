@@ -369,3 +369,66 @@ def partial_labelling_ok(sample_labels, true_labels) -> bool:
     rev = order[::-1]
     first[s[rev]] = t[rev]
     return bool(np.all(first[s] == t))
+
+
+# CSR preconditions (Section 2's CSR format: offsets of n + 1 entries with
+# offsets[n] = m; Section 3.1's skip of the frequent component needs an
+# undirected, i.e. symmetric, adjacency).  Bits: 1 offsets[0] != 0,
+# 2 offsets[n] != m, 4 a row with decreasing offsets or a bound outside
+# [0, m], 8 an id outside [0, n), 16 an entry (v, w) without (w, v).
+CSR_OFFSET0, CSR_OFFSETN, CSR_MONOTONE, CSR_ID_RANGE, CSR_ASYMMETRIC = 1, 2, 4, 8, 16
+
+
+def csr_validate(n: int, offsets, adj, check_symmetric: bool = True) -> dict:
+    """Checks a CSR against those preconditions, row by row, with plain
+    Python sets and counters.  Symmetry is checked only when the structure
+    and ids are sound: as set membership when every row is ascending (the
+    count and first row of the entries without a reverse are reported), else
+    as equality of the multisets {(v, w)} and {(w, v)} (row unknown: -1)."""
+    off = [int(x) for x in np.asarray(offsets).ravel()]
+    a = [int(x) for x in np.asarray(adj).ravel()]
+    m = len(a)
+    failed, bad, first = 0, 0, None
+
+    def flag(bit, row):
+        nonlocal failed, first
+        failed |= bit
+        first = row if first is None else min(first, row)
+
+    if off[0] != 0:
+        flag(CSR_OFFSET0, 0)
+    if off[n] != m:
+        flag(CSR_OFFSETN, n - 1)
+    rows_sorted = True
+    good = []
+    for v in range(n):
+        b, e = off[v], off[v + 1]
+        if b < 0 or e < b or e > m:
+            flag(CSR_MONOTONE, v)
+            continue
+        good.append(v)
+        row = a[b:e]
+        for w in row:
+            if w < 0 or w >= n:
+                flag(CSR_ID_RANGE, v)
+                bad += 1
+        if any(row[i + 1] < row[i] for i in range(len(row) - 1)):
+            rows_sorted = False
+    checked = 0
+    if check_symmetric and failed == 0:
+        checked = 1 if (rows_sorted or m == 0) else 2
+        if m > 0 and rows_sorted:
+            rowsets = [set(a[off[v]:off[v + 1]]) for v in range(n)]
+            for v in range(n):
+                for w in a[off[v]:off[v + 1]]:
+                    if v not in rowsets[w]:
+                        flag(CSR_ASYMMETRIC, v)
+                        bad += 1
+        elif m > 0:
+            from collections import Counter
+            fwd = Counter((v, w) for v in range(n) for w in a[off[v]:off[v + 1]])
+            rev = Counter((w, v) for (v, w), c in fwd.items() for _ in range(c))
+            if fwd != rev:
+                failed |= CSR_ASYMMETRIC
+    return {"failed": failed, "rows_sorted": int(rows_sorted), "symmetry_checked": checked,
+            "bad_entries": bad, "first_bad_row": -1 if (failed == 0 or first is None) else first}

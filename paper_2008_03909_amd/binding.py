@@ -103,6 +103,19 @@ class cc_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class cc_csr_report(ctypes.Structure):
+    _fields_ = [
+        ("failed", ctypes.c_uint32), ("rows_sorted", ctypes.c_int32),
+        ("symmetry_checked", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("bad_entries", ctypes.c_int64), ("first_bad_row", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+CSR_OFFSET0, CSR_OFFSETN, CSR_MONOTONE, CSR_ID_RANGE, CSR_ASYMMETRIC = 1, 2, 4, 8, 16
+
 _lib = None
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -147,6 +160,7 @@ def lib():
                                                ctypes.POINTER(ctypes.c_size_t)]),
             "cc_amsf_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, ctypes.POINTER(cc_amsf_options), _vp,
                                    ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "cc_validate_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _int, ctypes.POINTER(cc_csr_report), _vp]),
             "cc_csr_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
             "cc_build_csr": (_int, [_vp, _i64, _i64, _vp, _vp, _int, _vp, ctypes.c_size_t, _vp, _int, _vp, _vp,
                                     _vp]),
@@ -349,6 +363,18 @@ def build_csr(ctx: Context, n: int, u, v, dedup: bool = True, offsets_64bit: boo
     m = int(m_dev.item())
     del ws
     return CSR(n, offsets, adj[:m])
+
+
+def validate_csr(ctx: Context, g: CSR, check_symmetric: bool = True, stream=None):
+    """cc_validate_csr.  Returns (status, report dict): status CC_OK for a
+    valid CSR, CC_EDEVICE when a check failed (report["failed"] holds the
+    CSR_* bits).  Argument errors raise."""
+    r = cc_csr_report()
+    st = lib().cc_validate_csr(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj) if g.m else ctypes.c_void_p(0),
+                               int(check_symmetric), ctypes.byref(r), _stream_handle(stream))
+    if st not in (CC_OK, CC_EDEVICE) or (st == CC_EDEVICE and r.failed == 0):
+        raise CCError(st, "cc_validate_csr")
+    return st, r.as_dict()
 
 
 def connectivity_csr(ctx: Context, g: CSR, variant: cc_variant | None = None, labels: torch.Tensor | None = None,

@@ -36,6 +36,13 @@ struct DevScalars {
   long long ldd_seen;      // LDD: degree sum of every frontier expanded so far
   int32_t bu_rounds;       // BFS levels / LDD rounds run bottom-up in this call
   uint32_t pad[5];         // pad[0]: LDD minimum draw
+  // CSR validator (cc_validate_csr): failed checks (CC_CSR_* bits), bad
+  // entries, smallest failing row, unsorted-row flag, symmetry fingerprint
+  uint32_t csr_failed;
+  uint32_t csr_unsorted;
+  long long csr_bad;
+  long long csr_first;
+  unsigned long long csr_fp;
 };
 
 enum : uint32_t { kErrBadId = 1u, kErrRoundCap = 2u, kErrBadCsr = 4u };

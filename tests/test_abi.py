@@ -134,7 +134,8 @@ def test_pair_list_workspace_sizing():
 def test_binding_structs_match_the_header(tmp_path):
     """The ctypes mirrors of the header's structs have the C layout: gcc
     compiles the header and prints every field's offset and each size."""
-    structs = {"cc_variant": b.cc_variant, "cc_amsf_options": b.cc_amsf_options, "cc_stats": b.cc_stats}
+    structs = {"cc_variant": b.cc_variant, "cc_amsf_options": b.cc_amsf_options, "cc_stats": b.cc_stats,
+               "cc_csr_report": b.cc_csr_report}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "connectit_hip.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')

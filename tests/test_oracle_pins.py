@@ -719,3 +719,52 @@ def test_partial_labelling_against_pairwise_brute_force():
         t = rng.integers(0, 3, k)
         s = rng.integers(0, 4, k)
         assert oracle.partial_labelling_ok(s, t) == _partial_by_pairs(s, t), (s, t)
+
+
+# ---- CSR preconditions -------------------------------------------------------
+# Section 2 fixes the CSR format (offsets[n] = m) and Section 3.1's skip
+# needs a symmetric adjacency.  Each case plants one defect (or none) and
+# records which check it breaks; the oracle's checker must report exactly
+# that, so a checker that accepts everything, or flags the wrong row, fails.
+
+def test_csr_validate_reports_each_planted_defect():
+    import csr_cases
+    for c in csr_cases.cases():
+        r = oracle.csr_validate(c.n, c.off, c.adj, c.sym)
+        assert r["failed"] == c.bits, c
+        if c.first is not None:
+            assert r["first_bad_row"] == c.first, c
+        if c.bits == 0:
+            assert r["first_bad_row"] == -1 and r["bad_entries"] == 0, c
+        if c.bad is not None:
+            assert r["bad_entries"] == c.bad, c
+        if c.sorted_rows is not None:
+            assert r["rows_sorted"] == c.sorted_rows, c
+
+
+def test_csr_validate_symmetry_mode_and_pairwise_definition():
+    """Exact symmetry agrees with the plain pairwise definition (each entry's
+    reverse is somewhere in the other row) on random small adjacency lists;
+    the multiset mode runs only for unsorted rows."""
+    rng = np.random.default_rng(5)
+    for trial in range(60):
+        n = int(rng.integers(1, 9))
+        rows = [sorted(set(rng.integers(0, n, size=int(rng.integers(0, 4))).tolist())) for _ in range(n)]
+        if trial % 2 == 0:          # make it symmetric
+            for v in range(n):
+                for w in list(rows[v]):
+                    if v not in rows[w]:
+                        rows[w] = sorted(rows[w] + [v])
+        off = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+        adj = np.array([w for r in rows for w in r], np.int32)
+        want = all(v in rows[w] for v in range(n) for w in rows[v])
+        r = oracle.csr_validate(n, off, adj)
+        assert (r["failed"] == 0) == want, (rows, r)
+        assert r["symmetry_checked"] == 1
+        rev = adj.copy()
+        for v in range(n):
+            rev[off[v]:off[v + 1]] = adj[off[v]:off[v + 1]][::-1]
+        r2 = oracle.csr_validate(n, off, rev)
+        assert (r2["failed"] == 0) == want
+        if any(len(x) > 1 for x in rows):
+            assert r2["symmetry_checked"] == 2 and r2["rows_sorted"] == 0
