@@ -350,8 +350,9 @@ cc_status cc_validate_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets
  * 3.4): type 1 = UF-Async (any find) and UF-Rem-CAS with SplitAtomicOne or
  * HalveAtomicOne (inserts and queries may run concurrently); type 2 = SV
  * and the root-based LT variants (inserts in synchronous rounds over the
- * batch; these streams also own an n x int32 snapshot and an edge list
- * that grows, with hipMalloc, to the largest batch seen); type 3 =
+ * batch; these streams also own an n x int32 snapshot and an edge list of
+ * 2^22 pairs, allocated here, and insert a larger batch as consecutive
+ * parts of that size, so no insert allocates); type 3 =
  * UF-Rem-CAS with SpliceAtomic (phase-concurrent).  NULL v: UF-Async with
  * FindNaive.  On one cc_stream, every batch reflects exactly the batches
  * enqueued before it in stream order.  Type-2 inserts synchronise

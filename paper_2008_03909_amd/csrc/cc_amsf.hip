@@ -793,13 +793,13 @@ static cc_status amsf_run(StaticArgs& a, const AmsfLayout& L, const float* w, co
                            (const float*)thr, b, a.P, hsc.lmax, a.hook_e, hookw);
       if (hsc.bin_count[1] > 0)
         hipLaunchKernelGGL((k_visit_wave<AmsfRoundOp, I>), dim3(grid_for((int64_t)hsc.bin_count[1] * kWave, kFBlock, 2048)),
-                           dim3(kFBlock), 0, a.s, cl.big, cl.sc, offI, a.adj, op, (uint32_t*)nullptr);
+                           dim3(kFBlock), 0, a.s, cl.big, cl.bins, offI, a.adj, op, (uint32_t*)nullptr);
       if (hsc.bin_count[2] > 0)
-        hipLaunchKernelGGL((k_visit_block<AmsfRoundOp, I>), dim3(1024), dim3(kFBlock), 0, a.s, cl.n, cl.big, cl.sc,
+        hipLaunchKernelGGL((k_visit_block<AmsfRoundOp, I>), dim3(1024), dim3(kFBlock), 0, a.s, cl.n, cl.big, cl.bins,
                            offI, a.adj, op, (uint32_t*)nullptr);
       if (hsc.bin_count[3] > 0)
         hipLaunchKernelGGL((k_visit_heavy<AmsfRoundOp, I>), dim3(2048), dim3(kFBlock), 0, a.s, cl.heavy,
-                           &cl.sc->bin_count[3], cl.hp, offI, a.adj, op, (uint32_t*)nullptr);
+                           &cl.bins[3], cl.hp, offI, a.adj, op, (uint32_t*)nullptr);
       CC_LAUNCH_CHECK();
       ++a.finish_rounds;
     }

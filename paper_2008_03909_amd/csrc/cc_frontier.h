@@ -220,9 +220,9 @@ __device__ __forceinline__ int64_t heavy_owner_tile(const long long* hp, int64_t
 // four can share one launch (k_visit_all) or run as kernels of their own.
 template <class Op, typename I>
 __device__ __forceinline__ void visit_thread_part(int64_t bid, int64_t nb, const int32_t* __restrict__ cand,
-                                                  const DevScalars* sc, const I* __restrict__ off,
+                                                  const int32_t* bins, const I* __restrict__ off,
                                                   const int32_t* __restrict__ adj, const Op& op, uint32_t* flag) {
-  const int64_t cnt = sc->bin_count[0];
+  const int64_t cnt = bins[0];
   const int64_t stride = nb * blockDim.x;
   bool any = false;
   for (int64_t i = bid * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
@@ -235,9 +235,9 @@ __device__ __forceinline__ void visit_thread_part(int64_t bid, int64_t nb, const
 
 template <class Op, typename I>
 __device__ __forceinline__ void visit_wave_part(int64_t bid, int64_t nb, const int32_t* __restrict__ big,
-                                                const DevScalars* sc, const I* __restrict__ off,
+                                                const int32_t* bins, const I* __restrict__ off,
                                                 const int32_t* __restrict__ adj, const Op& op, uint32_t* flag) {
-  const int64_t cnt = sc->bin_count[1];
+  const int64_t cnt = bins[1];
   const int64_t waves = nb * (blockDim.x / kWave);
   const int lane = lane_id();
   bool any = false;
@@ -251,9 +251,9 @@ __device__ __forceinline__ void visit_wave_part(int64_t bid, int64_t nb, const i
 
 template <class Op, typename I>
 __device__ __forceinline__ void visit_block_part(int64_t bid, int64_t nb, int64_t n, const int32_t* __restrict__ big,
-                                                 const DevScalars* sc, const I* __restrict__ off,
+                                                 const int32_t* bins, const I* __restrict__ off,
                                                  const int32_t* __restrict__ adj, const Op& op, uint32_t* flag) {
-  const int64_t cnt = sc->bin_count[2];
+  const int64_t cnt = bins[2];
   bool any = false;
   for (int64_t i = bid; i < cnt; i += nb) {
     const int32_t u = big[n - 1 - i];
@@ -289,21 +289,21 @@ __device__ __forceinline__ void visit_heavy_part(int64_t bid, int64_t nb, const 
 }
 
 template <class Op, typename I>
-__global__ void k_visit_thread(const int32_t* __restrict__ cand, const DevScalars* sc, const I* __restrict__ off,
+__global__ void k_visit_thread(const int32_t* __restrict__ cand, const int32_t* bins, const I* __restrict__ off,
                                const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
-  visit_thread_part<Op, I>(blockIdx.x, gridDim.x, cand, sc, off, adj, op, flag);
+  visit_thread_part<Op, I>(blockIdx.x, gridDim.x, cand, bins, off, adj, op, flag);
 }
 
 template <class Op, typename I>
-__global__ void k_visit_wave(const int32_t* __restrict__ big, const DevScalars* sc, const I* __restrict__ off,
+__global__ void k_visit_wave(const int32_t* __restrict__ big, const int32_t* bins, const I* __restrict__ off,
                              const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
-  visit_wave_part<Op, I>(blockIdx.x, gridDim.x, big, sc, off, adj, op, flag);
+  visit_wave_part<Op, I>(blockIdx.x, gridDim.x, big, bins, off, adj, op, flag);
 }
 
 template <class Op, typename I>
-__global__ void k_visit_block(int64_t n, const int32_t* __restrict__ big, const DevScalars* sc,
+__global__ void k_visit_block(int64_t n, const int32_t* __restrict__ big, const int32_t* bins,
                               const I* __restrict__ off, const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
-  visit_block_part<Op, I>(blockIdx.x, gridDim.x, n, big, sc, off, adj, op, flag);
+  visit_block_part<Op, I>(blockIdx.x, gridDim.x, n, big, bins, off, adj, op, flag);
 }
 
 template <class Op, typename I>
@@ -318,26 +318,27 @@ __global__ void k_visit_heavy(const int32_t* __restrict__ hlist, const int32_t* 
 template <class Op, typename I>
 __global__ void k_visit_all(int64_t n, int64_t g0, int64_t g1, int64_t g2, const int32_t* __restrict__ cand,
                             const int32_t* __restrict__ big, const int32_t* __restrict__ heavy,
-                            const long long* __restrict__ hp, const DevScalars* sc, const I* __restrict__ off,
+                            const long long* __restrict__ hp, const int32_t* bins, const I* __restrict__ off,
                             const int32_t* __restrict__ adj, Op op, uint32_t* flag) {
   int64_t b = blockIdx.x;
-  if (b < g0) return visit_thread_part<Op, I>(b, g0, cand, sc, off, adj, op, flag);
+  if (b < g0) return visit_thread_part<Op, I>(b, g0, cand, bins, off, adj, op, flag);
   b -= g0;
-  if (b < g1) return visit_wave_part<Op, I>(b, g1, big, sc, off, adj, op, flag);
+  if (b < g1) return visit_wave_part<Op, I>(b, g1, big, bins, off, adj, op, flag);
   b -= g1;
-  if (b < g2) return visit_block_part<Op, I>(b, g2, n, big, sc, off, adj, op, flag);
+  if (b < g2) return visit_block_part<Op, I>(b, g2, n, big, bins, off, adj, op, flag);
   b -= g2;
-  visit_heavy_part<Op, I>(b, (int64_t)gridDim.x - g0 - g1 - g2, heavy, &sc->bin_count[3], hp, off, adj, op, flag);
+  visit_heavy_part<Op, I>(b, (int64_t)gridDim.x - g0 - g1 - g2, heavy, &bins[3], hp, off, adj, op, flag);
 }
 
-// Candidate lists of one static call.
+// Degree-binned vertex lists: the candidates of one static call, or a
+// frontier in the same layout.
 struct CandLists {
   int64_t n;
   const int32_t* cand;    // thread bin
   const int32_t* big;     // wave bin (front), block bin (back)
   const int32_t* heavy;   // grid bin
   const long long* hp;    // degree prefix of the grid bin
-  const DevScalars* sc;
+  const int32_t* bins;    // the four bins' lengths (device)
 };
 
 template <class Op, typename I>
@@ -345,7 +346,7 @@ inline void visit_candidates(hipStream_t s, const CandLists& L, const I* off, co
                              uint32_t* flag) {
   const int64_t g0 = grid_for(L.n, kFBlock, 4096), g1 = grid_for(L.n * kWave, kFBlock, 2048), g2 = 1024, g3 = 2048;
   hipLaunchKernelGGL((k_visit_all<Op, I>), dim3((unsigned)(g0 + g1 + g2 + g3)), dim3(kFBlock), 0, s, L.n, g0, g1, g2,
-                     L.cand, L.big, L.heavy, L.hp, L.sc, off, adj, op, flag);
+                     L.cand, L.big, L.heavy, L.hp, L.bins, off, adj, op, flag);
 }
 
 [[maybe_unused]] static __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }

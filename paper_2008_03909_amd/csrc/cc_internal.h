@@ -43,6 +43,7 @@ struct DevScalars {
   long long csr_bad;
   long long csr_first;
   unsigned long long csr_fp;
+  int32_t fbin[2][4];      // label propagation: bin lengths of the frontier lists (double-buffered)
 };
 
 enum : uint32_t { kErrBadId = 1u, kErrRoundCap = 2u, kErrBadCsr = 4u };
@@ -62,6 +63,7 @@ struct cc_ctx {
   float* sel_dev = nullptr;          // the same memory as the device addresses it
   uint32_t sel_seq = 0;              // sequence number of the last selector call
   unsigned char* ring_host = nullptr;  // pinned: BFS progress snapshots (2 x 16 bytes)
+  hipEvent_t ring_ev[2] = {nullptr, nullptr};  // marks each snapshot's copy (created with the context)
   void* amsf_host = nullptr;         // pinned: bucket histogram of the last AMSF call (allocated on first use)
   cc_stats last{};
   int round_limit = 0;  // 0: the built-in caps only

@@ -366,20 +366,86 @@ cc_status edge_list_rounds(cc_ctx* ctx, hipStream_t s, const cc_variant& v, int6
 // Labels are the parent array read as labels.  The frequent sampled class
 // is first relabelled to -1, below every id, so its vertices never change
 // and their label spreads to every vertex connected to them (the paper's
-// way of composing label propagation with sampling).  A round applies every
-// candidate edge both ways with writeMin; rounds repeat until nothing
-// changes.  Then the -1 class takes its smallest member as its label; every
-// other class already carries its minimum (the sampled labels are class
-// minima), so the result is the canonical labelling and a star forest.
+// way of composing label propagation with sampling).  Rounds follow the
+// appendix's frontier: round 0 applies every candidate edge both ways with
+// writeMin (the frontier is every vertex); afterwards a round visits only
+// the edges of the vertices whose label dropped in the round before.  The
+// lane whose writeMin lowers a label sets that vertex's bit in a bitmap; the
+// next round's frontier is built from the bitmap (bits cleared as they are
+// read) into the same four degree bins as the candidate lists, so the same
+// edge visitors balance its rows.  A vertex that keeps its label has already
+// pushed it to every neighbour, and a neighbour in the frequent class hands
+// its -1 over in round 0, so visiting only the frontier leaves the fixed
+// point unchanged.  Rounds stop when no label changes.  Then the -1 class
+// takes its smallest member as its label; every other class already carries
+// its minimum (the sampled labels are class minima), so the result is the
+// canonical labelling and a star forest.
 struct LpOp {
   int32_t* P;
+  uint32_t* chg;  // bit per vertex: its label dropped in this round
   __device__ __forceinline__ bool operator()(int32_t u, int32_t w, int64_t) const {
     const int32_t a = ld(P + u), c = ld(P + w);
-    if (a < c) return amin(P + w, a) > a;
-    if (c < a) return amin(P + u, c) > c;
+    if (a < c) {
+      if (amin(P + w, a) <= a) return false;
+      bit_claim(chg, w);
+      return true;
+    }
+    if (c < a) {
+      if (amin(P + u, c) <= c) return false;
+      bit_claim(chg, u);
+      return true;
+    }
     return false;
   }
 };
+
+// Next frontier from the change bitmap: every set bit is cleared and its
+// vertex appended to the bin of its degree (thread bin to q0, wave bin to
+// the front of q1, block bin to the back of q1, grid bin to `heavy`), with
+// one counter add per wave and bin.  Also zeroes the other round's bin
+// counters and the change flag for the visit that follows.
+template <typename I>
+__global__ void __launch_bounds__(kFBlock) k_lp_frontier(int64_t n, uint32_t* __restrict__ chg,
+                                                         const I* __restrict__ off, int32_t* __restrict__ q0,
+                                                         int32_t* __restrict__ q1, int32_t* __restrict__ heavy,
+                                                         int32_t* bins, int32_t* other_bins, uint32_t* changed) {
+  if (blockIdx.x == 0 && threadIdx.x < 4) other_bins[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *changed = 0u;
+  const int64_t words = (n + 31) >> 5;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += stride) {
+    uint32_t w = chg[i];
+    if (w) chg[i] = 0u;
+    while (__ballot(w != 0u)) {
+      const bool has = w != 0u;
+      int64_t v = 0, deg = 0;
+      if (has) {
+        v = (i << 5) + (__ffs((int)w) - 1);
+        w &= w - 1u;
+        deg = (int64_t)off[v + 1] - (int64_t)off[v];
+      }
+      const int bin = !has ? -1 : deg <= kThrWave ? 0 : deg <= kThrBlock ? 1 : deg <= kThrGrid ? 2 : 3;
+      wave_append(bin == 0, (int32_t)v, q0, (uint32_t*)&bins[0]);
+      wave_append(bin == 1, (int32_t)v, q1, (uint32_t*)&bins[1]);
+      wave_append(bin == 3, (int32_t)v, heavy, (uint32_t*)&bins[3]);
+      const uint64_t mb = __ballot(bin == 2);
+      if (mb) {
+        const int leader = __ffsll((unsigned long long)mb) - 1;
+        uint32_t base = 0;
+        if (lane_id() == leader)
+          base = __hip_atomic_fetch_add((uint32_t*)&bins[2], (uint32_t)__popcll(mb), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        base = __shfl(base, leader, kWave);
+        if (bin == 2) q1[n - 1 - (int64_t)(base + (uint32_t)__popcll(mb & lanemask_lt()))] = (int32_t)v;
+      }
+    }
+  }
+}
+
+__global__ void k_lp_begin(int32_t* bins1, uint32_t* changed) {
+  if (threadIdx.x < 4) bins1[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *changed = 0u;
+}
 
 __global__ void k_lp_mark(int64_t n, int32_t* P, const DevScalars* sc) {
   const int32_t L = sc->lmax;
@@ -426,14 +492,38 @@ __global__ void k_lp_fix(int64_t n, int32_t* P, const int32_t* __restrict__ part
 template <typename I>
 cc_status finish_lp(StaticArgs& a) {
   DevScalars* sc = a.ctx->dev;
-  const unsigned g = grid_for(a.n, kFBlock, 4096);
-  hipLaunchKernelGGL(k_lp_mark, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, (const DevScalars*)sc);
+  const int64_t n = a.n;
+  const unsigned g = grid_for(n, kFBlock, 4096);
+  // frontier state: the change bitmap, the thread bin and the wave/block
+  // bins in the frontier queues (free after sampling), the grid bin in the
+  // candidates' heavy list (free once round 0 has visited it)
+  uint32_t* chg = (uint32_t*)(a.ws + a.L.bits);
+  int32_t* q0 = (int32_t*)(a.ws + a.L.queue);
+  int32_t* q1 = (int32_t*)(a.ws + a.L.queue + align256((size_t)n * 4));
+  const int64_t words = (n + 31) >> 5;
+  // whether any candidate row is long enough for the grid bin (then each
+  // frontier needs that bin's degree prefix)
+  CC_HIP(hipMemcpyAsync(a.ctx->host->bin_count, sc->bin_count, sizeof(sc->bin_count), hipMemcpyDeviceToHost, a.s));
+  CC_HIP(hipStreamSynchronize(a.s));
+  const bool grid_bin = a.ctx->host->bin_count[3] > 0;
+  hipLaunchKernelGGL(k_lp_mark, dim3(g), dim3(kFBlock), 0, a.s, n, a.P, (const DevScalars*)sc);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words, kFBlock, 4096)), dim3(kFBlock), 0, a.s, chg, words, 0u);
+  hipLaunchKernelGGL(k_lp_begin, dim3(1), dim3(64), 0, a.s, sc->fbin[1], &sc->changed);
+  const unsigned gf = grid_for(words, kFBlock, 2048);
   for (int round = 0;; ++round) {
     if (round >= kRoundCap) return fail(CC_ELIVELOCK, "label propagation exceeded %d rounds", kRoundCap);
     if (a.ctx->round_limit > 0 && round >= a.ctx->round_limit)
       return fail(CC_ELIVELOCK, "label propagation reached the context's round limit (%d)", a.ctx->round_limit);
-    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, a.s, &sc->changed, 0u);
-    visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, LpOp{a.P}, &sc->changed);
+    if (round == 0) {
+      visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, LpOp{a.P, chg}, &sc->changed);
+    } else {
+      int32_t* bins = sc->fbin[round & 1];
+      hipLaunchKernelGGL(k_lp_frontier<I>, dim3(gf), dim3(kFBlock), 0, a.s, n, chg, (const I*)a.off, q0, q1,
+                         a.heavy, bins, sc->fbin[(round + 1) & 1], &sc->changed);
+      if (grid_bin) heavy_prefix<I>(a.s, a.heavy, &bins[3], a.hcap, (const I*)a.off, a.tsum, a.hp);
+      const CandLists fl{n, q0, q1, a.heavy, a.hp, bins};
+      visit_candidates(a.s, fl, (const I*)a.off, a.adj, LpOp{a.P, chg}, &sc->changed);
+    }
     CC_LAUNCH_CHECK();
     ++a.finish_rounds;
     uint32_t changed = 0;
@@ -442,9 +532,9 @@ cc_status finish_lp(StaticArgs& a) {
     if (!changed) break;
   }
   // per-block minima in the count array (free after the compaction)
-  const unsigned gm = grid_for(a.n, kFBlock, 1024);
-  hipLaunchKernelGGL(k_lp_min, dim3(gm), dim3(kFBlock), 0, a.s, a.n, (const int32_t*)a.P, a.count);
-  hipLaunchKernelGGL(k_lp_fix, dim3(g), dim3(kFBlock), 0, a.s, a.n, a.P, (const int32_t*)a.count, (int)gm);
+  const unsigned gm = grid_for(n, kFBlock, 1024);
+  hipLaunchKernelGGL(k_lp_min, dim3(gm), dim3(kFBlock), 0, a.s, n, (const int32_t*)a.P, a.count);
+  hipLaunchKernelGGL(k_lp_fix, dim3(g), dim3(kFBlock), 0, a.s, n, a.P, (const int32_t*)a.count, (int)gm);
   CC_LAUNCH_CHECK();
   return CC_OK;
 }

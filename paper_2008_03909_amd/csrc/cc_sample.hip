@@ -722,9 +722,7 @@ cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reach
   int batch = 2;
   int slot = 0;
   bool have_prev = false;
-  hipEvent_t ev[2];
-  CC_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  CC_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  hipEvent_t* ev = a.ctx->ring_ev;
   struct Snap {
     uint32_t mode;
     int32_t level;
@@ -777,8 +775,6 @@ cc_status bfs_probe(StaticArgs& a, int32_t source, int level_cap, int64_t* reach
   }
   // the batch queued after the finishing snapshot does nothing; wait for it
   CC_HIP(hipStreamSynchronize(a.s));
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
   if (result != CC_OK) return result;
   *reached_out = fin.reached;
   *levels_out = fin.level;

@@ -31,7 +31,7 @@ struct StaticArgs {
   int32_t sample_success = 1;
   int32_t sample_rounds = 0;
   int32_t finish_rounds = 0;
-  CandLists lists() const { return CandLists{n, cand, big, heavy, hp, ctx->dev}; }
+  CandLists lists() const { return CandLists{n, cand, big, heavy, hp, ctx->dev->bin_count}; }
 };
 
 template <typename I> cc_status sample_bfs(StaticArgs& a);

@@ -208,24 +208,27 @@ static int stream_type(const cc_variant& v) {
 }
 
 // Type 2: the batch's inserts as an edge list, then rounds until no change.
+// The edge list has a fixed capacity, allocated with the stream; a larger
+// batch is inserted as consecutive parts of that size, each run to its
+// fixed point (the connectivity after all parts is that of the whole batch,
+// union being associative), so an insert never allocates or waits for
+// memory.
+constexpr int64_t kType2EdgeCap = (int64_t)1 << 22;
+
 static cc_status round_inserts(cc_stream* s, int64_t k, const uint8_t* kind, const int32_t* u, const int32_t* v,
                                uint8_t* out, hipStream_t st) {
-  if (k > s->ecap) {
-    const int64_t cap = std::max<int64_t>(k, 2 * s->ecap);
-    CC_HIP(hipStreamSynchronize(st));
-    if (s->eu) CC_HIP(hipFree(s->eu));
-    if (s->ev) CC_HIP(hipFree(s->ev));
-    s->eu = s->ev = nullptr;
-    s->ecap = 0;
-    if (hipMalloc((void**)&s->eu, (size_t)cap * 4) != hipSuccess ||
-        hipMalloc((void**)&s->ev, (size_t)cap * 4) != hipSuccess)
-      return fail(CC_ENOMEM, "cannot allocate the edge list of a %lld-pair batch", (long long)k);
-    s->ecap = cap;
+  for (int64_t c0 = 0; c0 < k; c0 += s->ecap) {
+    const int64_t kc = std::min<int64_t>(s->ecap, k - c0);
+    hipLaunchKernelGGL(k_stream_edges, dim3(grid_for(kc, 256, 8192)), dim3(256), 0, st, kc,
+                       kind ? kind + c0 : nullptr, u + c0, v + c0, s->eu, s->ev, s->ecnt, s->n, s->err,
+                       out ? out + c0 : nullptr);
+    CC_LAUNCH_CHECK();
+    int32_t rounds = 0;
+    cc_status r = edge_list_rounds(s->ctx, st, s->v, s->n, s->P, s->Q, s->eu, s->ev, s->ecnt, kc, &rounds);
+    if (r != CC_OK) return r;
+    s->last_rounds = c0 == 0 ? rounds : s->last_rounds + rounds;
   }
-  hipLaunchKernelGGL(k_stream_edges, dim3(grid_for(k, 256, 8192)), dim3(256), 0, st, k, kind, u, v, s->eu, s->ev,
-                     s->ecnt, s->n, s->err, out);
-  CC_LAUNCH_CHECK();
-  return edge_list_rounds(s->ctx, st, s->v, s->n, s->P, s->Q, s->eu, s->ev, s->ecnt, k, &s->last_rounds);
+  return CC_OK;
 }
 
 }  // namespace cc
@@ -254,15 +257,18 @@ cc_status cc_stream_create(cc_ctx* ctx, int64_t n, const cc_variant* v, cc_strea
   s->v = *v;
   s->type = stream_type(*v);
   bool ok = hipMalloc((void**)&s->P, (size_t)n * 4) == hipSuccess && hipMalloc((void**)&s->err, 256) == hipSuccess;
-  if (ok && s->type == 2)
-    ok = hipMalloc((void**)&s->Q, (size_t)n * 4) == hipSuccess &&
-         hipMalloc((void**)&s->ecnt, 256) == hipSuccess;
+  if (ok && s->type == 2) {
+    ok = hipMalloc((void**)&s->Q, (size_t)n * 4) == hipSuccess && hipMalloc((void**)&s->ecnt, 256) == hipSuccess &&
+         hipMalloc((void**)&s->eu, (size_t)kType2EdgeCap * 4) == hipSuccess &&
+         hipMalloc((void**)&s->ev, (size_t)kType2EdgeCap * 4) == hipSuccess;
+    s->ecap = kType2EdgeCap;
+  }
   if (ok && v->finish == CC_FIN_UF_HOOKS) {
     ok = hipMalloc((void**)&s->H, (size_t)n * 4) == hipSuccess;
     if (ok) ok = hipMemset(s->H, 0xff, (size_t)n * 4) == hipSuccess;
   }
   if (!ok) {
-    for (void* p : {(void*)s->P, (void*)s->err, (void*)s->H, (void*)s->Q, (void*)s->ecnt})
+    for (void* p : {(void*)s->P, (void*)s->err, (void*)s->H, (void*)s->Q, (void*)s->ecnt, (void*)s->eu, (void*)s->ev})
       if (p) (void)hipFree(p);
     delete s;
     return fail(CC_ENOMEM, "cannot allocate the stream state (%lld vertices)", (long long)n);

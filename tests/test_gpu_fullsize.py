@@ -137,3 +137,4 @@ def test_amsf_rmat_2_24(ctx, rmat24):
         fb = np.searchsorted(t, fw, side="right") - 1
         assert np.array_equal(np.bincount(fb, minlength=len(cnt)), cnt), lf
         assert abs(float(tw.item()) - float(np.sum(fw, dtype=np.float64))) < 1e-6 * float(tw.item())
+

@@ -151,3 +151,38 @@ def test_non_streaming_finishes_are_refused(ctx):
     for v in (b.default_variant(finish=b.FIN_LP), b.default_variant(finish=b.FIN_LT, lt_rules=b.LT_NONROOT["PUS"])):
         with pytest.raises(b.CCError):
             b.Stream(ctx, 10, v)
+
+
+@pytest.mark.parametrize("fin,rules", [(b.FIN_SV, 0), (b.FIN_LT, b.LT_CRSA), (b.FIN_LT, b.LT_PRF)])
+def test_type2_batch_larger_than_the_edge_list(ctx, fin, rules):
+    """A type-2 stream keeps a fixed edge list of 2^22 pairs and inserts a
+    larger batch as consecutive parts: one insert batch of 5,000,000 pairs
+    (plus a mixed batch of 4,500,000 operations) gives the oracle's labels,
+    and the mixed batch's queries see all of its inserts."""
+    n = 1 << 20
+    rng = np.random.default_rng(31)
+    u = rng.integers(0, n, 5_000_000).astype(np.int32)
+    v = rng.integers(0, n, 5_000_000).astype(np.int32)
+    u[:1000] = v[:1000]                       # self-loops are no-ops
+    st = b.Stream(ctx, n, b.default_variant(finish=fin, lt_rules=rules or b.LT_PRF))
+    assert st.type == 2
+    dev = ctx.torch_device
+    st.insert(torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev))
+    lab, nc = st.labels()
+    torch.cuda.synchronize()
+    want, wc = oracle.uf_cc(n, u, v)
+    assert np.array_equal(lab.cpu().numpy(), want) and int(nc.item()) == wc
+    k = 4_500_000
+    kind = (rng.random(k) < 0.5).astype(np.uint8)
+    a = rng.integers(0, n, k).astype(np.int32)
+    c = rng.integers(0, n, k).astype(np.int32)
+    out = st.process(kind, a, c).cpu().numpy()
+    st.sync_status()
+    ins = kind == 0
+    want2, _ = oracle.uf_cc(n, np.concatenate([u, a[ins]]), np.concatenate([v, c[ins]]))
+    q = ~ins
+    assert np.array_equal(out[q], (want2[a[q]] == want2[c[q]]).astype(np.uint8))
+    assert not out[ins].any()
+    lab2, _ = st.labels()
+    assert np.array_equal(lab2.cpu().numpy(), want2)
+    st.close()
