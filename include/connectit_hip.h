@@ -204,6 +204,26 @@ cc_status cc_connectivity_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* off
                               const int32_t* adj, const cc_variant* v, void* workspace, size_t ws_bytes,
                               int32_t* labels_out, int64_t* num_components_dev, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as cc_connectivity_csr, with the workspace taken from a fixed device
+ * array of cc_noalloc_scratch_bytes() (64 MiB) that the library holds on
+ * each device it runs on until the process ends (its address is looked up
+ * when a context is created on the device).  The caller still passes the
+ * CSR, labels_out and num_components_dev.  A graph whose
+ * cc_workspace_bytes exceeds the array returns CC_ENOMEM (with the default
+ * variant that is n above about 3 million vertices); nothing is enqueued
+ * then.  The call allocates nothing and records no phase events, whatever
+ * cc_ctx_set_timing says.  Every call on one device shares that device's
+ * array and leaves its contents behind (each call initialises what it
+ * reads), so calls that overlap in time on one device -- on different
+ * streams, contexts or host threads -- race and must be serialised by the
+ * caller. */
+size_t cc_noalloc_scratch_bytes(void);
+cc_status cc_connectivity_csr_noalloc(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                                      const int32_t* adj, const cc_variant* v, int32_t* labels_out,
+                                      int64_t* num_components_dev, void* hip_stream);
+
 /* Sampling step alone (for inspection/tests): writes the sampled partial
  * labelling, each sampled class relabelled to its minimum member, and the
  * frequent label chosen by IdentifyFrequent (or -1).  Same arguments as

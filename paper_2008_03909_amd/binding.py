@@ -145,6 +145,9 @@ def lib():
             "cc_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_variant), ctypes.POINTER(ctypes.c_size_t)]),
             "cc_connectivity_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
                                            ctypes.c_size_t, _vp, _vp, _vp]),
+            "cc_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+            "cc_connectivity_csr_noalloc": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
+                                                   _vp, _vp]),
             "cc_sample_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
                                      ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_int32), _vp]),
             "cc_coo_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_variant),
@@ -390,6 +393,26 @@ def connectivity_csr(ctx: Context, g: CSR, variant: cc_variant | None = None, la
     _check(lib().cc_connectivity_csr(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), ctypes.byref(v),
                                      _ptr(ws), ws.numel(), _ptr(labels), _ptr(ncomp), _stream_handle(stream)),
            "cc_connectivity_csr")
+    return labels, ncomp
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().cc_noalloc_scratch_bytes())
+
+
+def connectivity_csr_noalloc(ctx: Context, g: CSR, variant: cc_variant | None = None,
+                             labels: torch.Tensor | None = None, ncomp: torch.Tensor | None = None, stream=None):
+    """cc_connectivity_csr_noalloc: as connectivity_csr, with the library's
+    fixed per-device workspace (pass labels/ncomp to allocate nothing here)."""
+    v = variant if variant is not None else default_variant()
+    dev = ctx.torch_device
+    if labels is None:
+        labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    if ncomp is None:
+        ncomp = torch.empty(1, dtype=torch.int64, device=dev)
+    _check(lib().cc_connectivity_csr_noalloc(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj),
+                                             ctypes.byref(v), _ptr(labels), _ptr(ncomp), _stream_handle(stream)),
+           "cc_connectivity_csr_noalloc")
     return labels, ncomp
 
 

@@ -65,6 +65,7 @@ struct cc_ctx {
   unsigned char* ring_host = nullptr;  // pinned: BFS progress snapshots (2 x 16 bytes)
   hipEvent_t ring_ev[2] = {nullptr, nullptr};  // marks each snapshot's copy (created with the context)
   void* amsf_host = nullptr;         // pinned: bucket histogram of the last AMSF call (allocated on first use)
+  void* noalloc_scratch = nullptr;   // device address of this device's no-allocation workspace array
   cc_stats last{};
   int round_limit = 0;  // 0: the built-in caps only
   // phase timing

@@ -20,6 +20,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "cc_device.h"
 #include "cc_frontier.h"
@@ -1167,6 +1168,34 @@ cc_status setup_args(StaticArgs& a, cc_ctx* ctx, int64_t n, int64_t m, const voi
   return CC_OK;
 }
 
+// Workspace of cc_connectivity_csr_noalloc: a fixed device array, one copy
+// per device, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// device symbol): it takes the device address from hipGetSymbolAddress,
+// once per device with that device current, when a context is created.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the caller has made the
+// device current); looked up on the first request per device.
+static cc_status noalloc_scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(CC_EDEVICE, "device %d beyond the %d supported", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CC_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return CC_OK;
+}
+
 static void record_stats_host(StaticArgs& a) {
   cc_stats& s = a.ctx->last;
   s.n = a.n;
@@ -1210,6 +1239,11 @@ cc_status cc_ctx_create(int device, cc_ctx** out) {
   CC_HIP(hipMemset(c->dev, 0, sizeof(DevScalars)));
   memset(c->host, 0, sizeof(DevScalars));
   CC_HIP(hipDeviceSynchronize());
+  if (noalloc_scratch_address(device, &c->noalloc_scratch) != CC_OK) {
+    const std::string msg = cc_last_error();
+    cc_ctx_destroy(c);
+    return fail(CC_EDEVICE, "%s", msg.c_str());
+  }
   *out = c;
   return CC_OK;
 }
@@ -1336,6 +1370,32 @@ cc_status cc_connectivity_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* off
                             num_components_dev, hip_stream);
   if (st != CC_OK) return st;
   st = a.o64 ? run_static<int64_t>(a, false) : run_static<int32_t>(a, false);
+  record_stats_host(a);
+  return st;
+}
+
+size_t cc_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+cc_status cc_connectivity_csr_noalloc(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                                      const int32_t* adj, const cc_variant* v, int32_t* labels_out,
+                                      int64_t* num_components_dev, void* hip_stream) {
+  if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+  if (!ctx->noalloc_scratch) return fail(CC_EDEVICE, "the context has no scratch array");
+  size_t need = 0;
+  cc_status st = cc_workspace_bytes(n, m, v, &need);
+  if (st != CC_OK) return st;
+  if (need > kNoallocScratchBytes)
+    return fail(CC_ENOMEM, "n=%lld, m=%lld needs %zu bytes of workspace; the no-allocation entry point holds %zu",
+                (long long)n, (long long)m, need, kNoallocScratchBytes);
+  StaticArgs a;
+  st = setup_args(a, ctx, n, m, offsets, offsets_are_64bit, adj, v, ctx->noalloc_scratch, kNoallocScratchBytes,
+                  labels_out, num_components_dev, hip_stream);
+  if (st != CC_OK) return st;
+  // phase events would create HIP events on first use: none in this call
+  const int timing = ctx->timing;
+  ctx->timing = 0;
+  st = a.o64 ? run_static<int64_t>(a, false) : run_static<int32_t>(a, false);
+  ctx->timing = timing;
   record_stats_host(a);
   return st;
 }
