@@ -291,8 +291,8 @@ def mixed(ctx, g, seed: int = 7, total_ops: int = 20_000_000):
     return res
 
 
-def serving(ctx, g, capacity_pairs_per_s: float | None = None, loads=(0.0, 0.5, 0.9), requests: int = 300,
-            seed: int = 5):
+def serving(ctx, g, capacity_pairs_per_s: float | None = None, loads=(0.0, 0.3, 0.6, 0.9, 1.2), requests: int = 300,
+            seed: int = 5, variant=None):
     """Poisson arrivals through the serving loop (continuous batching): insert
     requests of log-uniform size in [1e3, 1e7] pairs (the workload's pairs,
     shuffled) and query requests in [1e3, 1e6] random pairs, 50/50, at an
@@ -339,7 +339,8 @@ def serving(ctx, g, capacity_pairs_per_s: float | None = None, loads=(0.0, 0.5, 
         pa = torch.from_numpy(np.concatenate(A).astype(np.int32)).pin_memory()
         pb = torch.from_numpy(np.concatenate(B).astype(np.int32)).pin_memory()
         po = torch.zeros(pa.numel(), dtype=torch.uint8).pin_memory()
-        srv = b.Server(ctx, g.n, budget_bytes=2 << 30, num_streams=4, max_inflight=64)
+        srv = b.Server(ctx, g.n, variant=variant, budget_bytes=2 << 30, num_streams=4, max_inflight=64)
+        mode = "stamped" if srv.stamped else "barrier"
         t0 = time.perf_counter()
         _, lat = srv.run_trace(np.array(types), arrivals, np.array(starts), np.array(lens),
                                pa.numpy(), pb.numpy(), po.numpy())
@@ -350,12 +351,14 @@ def serving(ctx, g, capacity_pairs_per_s: float | None = None, loads=(0.0, 0.5, 
         if load <= 0.0:
             capacity_pairs_per_s = float(lens_a.sum()) / wall
         res.append({
-            "offered_load": load, "requests": len(types), "inserted_pairs": int(ins_pairs),
+            "mode": mode, "offered_load": load, "requests": len(types), "inserted_pairs": int(ins_pairs),
             "queried_pairs": int(lens_a[ty == 1].sum()), "wall_s": round(wall, 4),
             "updates_per_s": ins_pairs / wall, "pairs_per_s": float(lens_a.sum()) / wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "insert_p50_ms": float(np.percentile(lat[ty == 0], 50) * 1e3) if np.any(ty == 0) else None,
             "query_p50_ms": float(np.percentile(lat[ty == 1], 50) * 1e3) if np.any(ty == 1) else None,
+            "insert_p99_ms": float(np.percentile(lat[ty == 0], 99) * 1e3) if np.any(ty == 0) else None,
+            "query_p99_ms": float(np.percentile(lat[ty == 1], 99) * 1e3) if np.any(ty == 1) else None,
         })
     return res
 
@@ -691,9 +694,13 @@ def main():
             f"p50 {out['incremental']['p50_ms']:.3f} ms, p99 {out['incremental']['p99_ms']:.3f} ms")
         log("serving loop (Poisson arrivals) ...")
         out["serving"] = serving(ctx, g)
-        for r in out["serving"]:
-            log(f"serving load {r['offered_load']}: {r['pairs_per_s']:.3e} pairs/s, p50 {r['p50_ms']:.3f} ms, "
-                f"p99 {r['p99_ms']:.3f} ms")
+        # the same traces with the barrier between insert and query phases
+        # (Rem-CAS / SplitAtomicOne, whose splices rewrite links)
+        out["serving_barrier_mode"] = serving(ctx, g, loads=(0.0, 0.9), variant=b.default_variant(
+            finish=b.FIN_UF_REM_CAS, splice=b.SPLICE_SPLIT_ONE, find=b.FIND_NAIVE))
+        for r in out["serving"] + out["serving_barrier_mode"]:
+            log(f"serving {r['mode']} load {r['offered_load']}: {r['pairs_per_s']:.3e} pairs/s, "
+                f"p50 {r['p50_ms']:.3f} ms, p99 {r['p99_ms']:.3f} ms")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, m, timed_labels, timed_ncomp)

@@ -406,32 +406,52 @@ cc_status cc_stream_labels(cc_stream* s, int32_t* labels_out, int64_t* num_compo
 /* Synchronises and reports (then clears) the stream's device error word. */
 cc_status cc_stream_sync_status(cc_stream* s);
 
-/* ---- serving loop (continuous batching over one stream state) -----------------
- * A cc_server owns a cc_stream (created from v; NULL = UF-Async + FindNaive),
- * a device request pool of budget_bytes, num_streams HIP streams (1..16) and
- * at most max_inflight requests on the device.  Requests are admitted in arrival order when their bytes
- * (8 per pair, plus 1 per query pair) fit in the pool; consecutive requests
- * of one type run concurrently, and a change between inserts and queries is
- * ordered by a barrier event, so every query answers against exactly the
- * inserts that arrived before it (the batch-incremental semantics of the
- * streaming appendix, arrival order = batch order).  Single host thread.
- * Zero copy: the server DMAs from the caller's host arrays and writes query
- * answers (0/1 bytes) straight into out, so every array must stay valid and
- * unmodified until its request completes (pinned memory, e.g. hipHostMalloc,
- * makes the transfers asynchronous).  A request larger than the
- * budget returns CC_EBUSY.  Times are seconds on the server's steady clock
+/* ---- serving loop (continuous batching over one device state) -------------------
+ * A cc_server owns a device union-find state for n vertices, a device request
+ * pool of budget_bytes, num_streams HIP streams (1..16) and at most
+ * max_inflight requests on the device.  Requests are admitted in arrival
+ * order when their bytes (8 per pair, plus 1 per query pair) fit in the pool,
+ * and every query answers against exactly the inserts that arrived before it
+ * (the batch-incremental semantics of the streaming appendix, arrival order =
+ * batch order; Section 3.4).  Two modes:
+ *   - v NULL or UF-Async with FindNaive (stamped mode, the type-1 setting of
+ *     Section 3.4): consecutive insert requests with no query between them
+ *     form a numbered insert phase and run concurrently; each link records
+ *     its phase number (the state is n 64-bit words); a phase starts after
+ *     the previous one completed.  A query runs once the inserts that arrived
+ *     before it have completed and reads only links of those phases, so it
+ *     overlaps the insert requests that arrive after it;
+ *   - any other variant (barrier mode): the server owns a cc_stream of that
+ *     variant; consecutive requests of one type run concurrently and each
+ *     change between inserts and queries is ordered by a barrier event.
+ * The server's host state is bounded: completed requests are freed, HIP
+ * events are reused, and cc_server_request_info keeps the outcome of the
+ * 65,536 most recent completions (older ids return CC_EINVAL).  Single host
+ * thread.  Zero copy: the server DMAs from the caller's host arrays and
+ * writes query answers (0/1 bytes) straight into out, so every array must
+ * stay valid and unmodified until its request completes (pinned memory,
+ * e.g. hipHostMalloc, makes the transfers asynchronous).  A request larger
+ * than the budget returns CC_EBUSY.  Ids outside [0, n) set the state's
+ * error word (reported by cc_server_poll with wait_all) and are skipped
+ * (queries answer 0).  Times are seconds on the server's steady clock
  * (cc_server_clock); arrival < 0 means "now". */
 typedef struct cc_server cc_server;
 cc_status cc_server_create(cc_ctx* ctx, int64_t n, const cc_variant* v, int64_t budget_bytes, int num_streams,
                            int max_inflight, cc_server** out);
 void cc_server_destroy(cc_server* s);
 double cc_server_clock(cc_server* s);
+/* 1 if the server runs in stamped mode (queries overlap later inserts). */
+int32_t cc_server_stamped(const cc_server* s);
+/* HIP events the server has created so far (they are reused; bounded by the
+ * requests in flight, not by the requests served). */
+int64_t cc_server_event_count(const cc_server* s);
 cc_status cc_server_submit_insert(cc_server* s, int64_t k, const int32_t* u_host, const int32_t* v_host,
                                   double arrival, int64_t* id);
 cc_status cc_server_submit_query(cc_server* s, int64_t q, const int32_t* a_host, const int32_t* b_host,
                                  uint8_t* out_host, double arrival, int64_t* id);
 /* Retires finished requests and admits pending ones; wait_all != 0 blocks
- * until every submitted request has completed. */
+ * until every submitted request has completed, then reports (and clears) the
+ * state's device error word. */
 cc_status cc_server_poll(cc_server* s, int wait_all);
 /* Replays a trace in real time: request i (type 0 insert / 1 query) arrives
  * arrival_s[i] seconds after the call and carries pairs [start[i],
@@ -492,6 +512,13 @@ cc_status cc_select_variant(cc_ctx* ctx, int64_t n, int64_t m, const void* offse
                             const int32_t* adj, const uint16_t* params_dev, int32_t K, const cc_variant* arms,
                             const float* norm_host, void* workspace, size_t ws_bytes, cc_variant* out_host,
                             int32_t* chosen_host, float* features_host, void* hip_stream);
+/* Small-graph gate of cc_connectivity_auto: with a model, graphs of fewer
+ * than min_vertices vertices skip the features and the forward pass and run
+ * arms[arm] (a choice learned from the training corpus), because the
+ * selector's fixed cost there exceeds what choosing saves; chosen_host then
+ * reports `arm` and features_host NaN.  min_vertices = 0 turns the gate off
+ * (the default).  Applies to calls on this context. */
+cc_status cc_ctx_set_selector_gate(cc_ctx* ctx, int64_t min_vertices, int32_t arm);
 /* Static connectivity with the arm the model predicts fastest: the 16
  * features, x = (f - norm_host[0:16]) / norm_host[16:32], the forward pass
  * and the argmin over the K arms (host array of variants) all run on the

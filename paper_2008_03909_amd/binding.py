@@ -186,6 +186,8 @@ def lib():
             "cc_server_request_info": (_int, [_vp, _i64, ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]),
             "cc_server_labels": (_int, [_vp, _vp, _vp, _vp]),
             "cc_server_pool_used": (_i64, [_vp]),
+            "cc_server_stamped": (ctypes.c_int32, [_vp]),
+            "cc_server_event_count": (_i64, [_vp]),
             "cc_mlp_param_count": (_i64, [ctypes.c_int32]),
             "cc_mlp_forward": (_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp]),
             "cc_mlp_backward": (_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -202,6 +204,7 @@ def lib():
                                          ctypes.POINTER(cc_variant), ctypes.POINTER(ctypes.c_float), _vp,
                                          ctypes.c_size_t, ctypes.POINTER(cc_variant),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float), _vp]),
+            "cc_ctx_set_selector_gate": (_int, [_vp, _i64, ctypes.c_int32]),
             "cc_calib_copy": (_int, [_vp, _vp, ctypes.c_size_t, _vp]),
             "cc_calib_workspace_bytes": (_int, [_i64, ctypes.POINTER(ctypes.c_size_t)]),
             "cc_calib_edges": (_int, [_i64, _i64, _vp, _int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -685,6 +688,14 @@ class Server:
     def pool_used(self) -> int:
         return int(lib().cc_server_pool_used(self.h))
 
+    @property
+    def stamped(self) -> bool:
+        """True when queries overlap later inserts (UF-Async + FindNaive)."""
+        return bool(lib().cc_server_stamped(self.h))
+
+    def event_count(self) -> int:
+        return int(lib().cc_server_event_count(self.h))
+
 
 # ---- selector ---------------------------------------------------------------------
 
@@ -739,8 +750,12 @@ class Selector:
     that a call costs one C call (features, forward pass and argmin on the
     device, then the chosen arm)."""
 
-    def __init__(self, ctx: Context, params_bf16: torch.Tensor | None, arms, norm):
+    def __init__(self, ctx: Context, params_bf16: torch.Tensor | None, arms, norm, gate=None):
+        """gate: (min_vertices, arm) -- smaller graphs run that arm without the
+        model (cc_ctx_set_selector_gate); None leaves the gate off."""
         self.ctx = ctx
+        gv, ga = gate if gate is not None else (0, -1)
+        _check(lib().cc_ctx_set_selector_gate(ctx.h, int(gv), int(ga)), "cc_ctx_set_selector_gate")
         self.params = params_bf16
         self.arms = list(arms) if arms is not None else []
         self.K = len(self.arms) if params_bf16 is not None else 0

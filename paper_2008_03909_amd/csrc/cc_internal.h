@@ -68,6 +68,8 @@ struct cc_ctx {
   void* noalloc_scratch = nullptr;   // device address of this device's no-allocation workspace array
   cc_stats last{};
   int round_limit = 0;  // 0: the built-in caps only
+  int64_t gate_vertices = 0;  // selector: graphs below this many vertices skip the model (0: never)
+  int32_t gate_arm = -1;      // the arm they run instead
   // phase timing
   int timing = 0;
   std::string timing_only;                  // non-empty: record only the phase of this name

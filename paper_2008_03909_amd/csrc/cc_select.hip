@@ -786,16 +786,39 @@ cc_status cc_select_variant(cc_ctx* ctx, int64_t n, int64_t m, const void* offse
   return CC_OK;
 }
 
+cc_status cc_ctx_set_selector_gate(cc_ctx* ctx, int64_t min_vertices, int32_t arm) {
+  if (!ctx || min_vertices < 0 || (min_vertices > 0 && arm < 0)) return fail(CC_EINVAL, "bad gate");
+  ctx->gate_vertices = min_vertices;
+  ctx->gate_arm = min_vertices > 0 ? arm : -1;
+  return CC_OK;
+}
+
 cc_status cc_connectivity_auto(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
                                const int32_t* adj, const uint16_t* params_dev, int32_t K, const cc_variant* arms,
                                const float* norm_host, void* workspace, size_t ws_bytes, int32_t* labels_out,
                                int64_t* num_components_dev, int32_t* chosen_host, float* features_host,
                                void* hip_stream) {
   if (!labels_out) return fail(CC_EINVAL, "labels_out is NULL");
+  if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
   float feat[kIn];
   int chosen;
   cc_variant use, def;
   cc_default_variant(&def);
+  if (params_dev && ctx->gate_vertices > 0 && n < ctx->gate_vertices) {
+    // below the gate the model's fixed cost exceeds what it saves: run the
+    // gate's arm without features
+    if (ctx->gate_arm >= K) return fail(CC_EINVAL, "gate arm %d of %d", ctx->gate_arm, K);
+    cc_status st = check_selector_args(n, m, params_dev, K, arms, norm_host, &def, ws_bytes, workspace);
+    if (st != CC_OK) return st;
+    if (chosen_host) *chosen_host = ctx->gate_arm;
+    if (features_host)
+      for (int i = 0; i < kIn; ++i) features_host[i] = NAN;
+    StaticArgs a;
+    st = setup_args(a, ctx, n, m, offsets, offsets_are_64bit, adj, &arms[ctx->gate_arm], workspace, ws_bytes,
+                    labels_out, num_components_dev, hip_stream);
+    if (st != CC_OK) return st;
+    return static_run(a);
+  }
   // Algorithm 1's init is the same for every arm: it is enqueued behind the
   // selector's kernels and runs while the host waits for the choice.  (The
   // count array sits at the start of every variant's workspace layout.)

@@ -3,13 +3,35 @@
 //
 // Semantics (the batch-incremental correctness of ConnectIt's streaming
 // appendix, with arrival order as the batch order): a query request sees
-// exactly the insert requests that arrived before it.  Inserts commute with
-// inserts and queries with queries, so consecutive requests of one type form
-// a phase whose requests run concurrently on several HIP streams; at a change
-// of type a barrier event (recorded after every request of the previous
-// phase) orders the new phase after the old one.  Requests are admitted in
-// arrival order when their device bytes fit in the memory budget and a
-// stream slot is free, so new work starts while older work is still running.
+// exactly the insert requests that arrived before it.
+//
+// Two modes, by the server's union-find variant:
+//
+//  * Stamped (UF-Async with FindNaive, the default).  The parent array holds
+//    64-bit words (insert stamp << 32 | parent).  Consecutive insert requests
+//    with no query between them form an insert phase; phases are numbered
+//    1, 2, ... in arrival order and every link a phase creates carries its
+//    number.  Requests of one phase run concurrently on several HIP streams;
+//    a phase starts after the previous one has completed.  A query that
+//    arrives after phase t waits for phase t to complete and then follows
+//    only links stamped <= t, so it runs concurrently with later insert
+//    phases and still answers against exactly the inserts that arrived
+//    before it: FindNaive never rewrites a link and a root's word changes
+//    once, from "root" to a link stamped with a later phase, so the links
+//    stamped <= t are exactly the forest that phases 1..t build when run
+//    alone (each of them ran after the previous one and saw no later link).
+//  * Barrier (every other variant, whose finds or splices rewrite links).
+//    Consecutive requests of one type form a phase whose requests run
+//    concurrently; at a change of type a barrier event orders the new phase
+//    after the old one.
+//
+// Requests are admitted in arrival order when their device bytes fit in the
+// memory budget and a slot is free, so new work starts while older work is
+// still running.  The loop's state is bounded: a request is freed when it
+// completes (its latency goes to a ring of recent completions, and to the
+// caller's array for a trace replay), HIP events are recycled, and a phase
+// only tracks its requests still in flight (a completed request needs no
+// wait).
 //
 // Host side: zero copy -- request payloads are DMA'd straight from the
 // caller's buffers (which must stay valid until the request completes; pinned
@@ -22,6 +44,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <unordered_map>
 #include <vector>
 
 #include "cc_device.h"
@@ -87,22 +110,121 @@ struct Request {
   int type = 0;  // 0 insert, 1 query
   int64_t k = 0;
   double arrival = 0.0;   // seconds on the server clock
-  double admitted = 0.0;
-  double done_at = -1.0;
   size_t bytes = 0, off = 0;
   int stream = -1;
   hipEvent_t ev = nullptr;
   uint8_t* out_host = nullptr;  // caller's result buffer (queries)
   const int32_t* a = nullptr;   // caller's payload (valid until completion)
   const int32_t* b = nullptr;
-  int state = 0;                // 0 pending, 1 in flight, 2 done
+  double* latency_out = nullptr;  // trace replay: where the latency goes
 };
+
+// Completions kept for cc_server_request_info (the most recent ones).
+constexpr int64_t kInfoRing = (int64_t)1 << 16;
+struct Done {
+  int64_t id = -1;
+  double latency = 0.0;
+};
+
+// ---- stamped union-find (UF-Async, FindNaive) ------------------------------
+// Word of vertex x: (stamp << 32) | parent; a root is (0 << 32) | x.
+__device__ __forceinline__ uint64_t ldw(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x in the forest of the links stamped <= t (t = ~0u: every link).
+__device__ __forceinline__ int32_t find_stamped(const uint64_t* W, int32_t x, uint32_t t) {
+  while (true) {
+    const uint64_t w = ldw(W + x);
+    const int32_t p = (int32_t)(uint32_t)w;
+    if (p == x || (uint32_t)(w >> 32) > t) return x;
+    x = p;
+  }
+}
+
+__global__ void k_stamped_init(int64_t n, uint64_t* W) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) W[i] = (uint64_t)i;
+}
+
+// UF-Async: find both roots; CAS the larger root's word from "root" to a link
+// under the smaller one, stamped with the insert phase; retry on failure.
+__global__ void k_stamped_insert(int64_t k, const int32_t* __restrict__ u, const int32_t* __restrict__ v,
+                                 uint64_t* W, uint32_t stamp, int64_t n, uint32_t* err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += stride) {
+    const int32_t a = u[i], b = v[i];
+    if (a < 0 || b < 0 || (int64_t)a >= n || (int64_t)b >= n) {
+      bad = true;
+      continue;
+    }
+    if (a == b) continue;
+    while (true) {
+      int32_t ra = find_stamped(W, a, ~0u), rb = find_stamped(W, b, ~0u);
+      if (ra == rb) break;
+      if (ra < rb) {
+        const int32_t x = ra;
+        ra = rb;
+        rb = x;
+      }
+      uint64_t expect = (uint64_t)(uint32_t)ra;
+      if (__hip_atomic_compare_exchange_strong(W + ra, &expect, ((uint64_t)stamp << 32) | (uint32_t)rb,
+                                               __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        break;
+    }
+  }
+  if (bad) atomicOr(err, kErrBadId);
+}
+
+__global__ void k_stamped_query(int64_t q, const int32_t* __restrict__ a, const int32_t* __restrict__ b,
+                                uint8_t* __restrict__ out, const uint64_t* W, uint32_t stamp, int64_t n,
+                                uint32_t* err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q; i += stride) {
+    const int32_t x = a[i], y = b[i];
+    if (x < 0 || y < 0 || (int64_t)x >= n || (int64_t)y >= n) {
+      bad = true;
+      out[i] = 0;
+      continue;
+    }
+    out[i] = (x == y || find_stamped(W, x, stamp) == find_stamped(W, y, stamp)) ? 1 : 0;
+  }
+  if (bad) atomicOr(err, kErrBadId);
+}
+
+// Canonical labels of the whole forest (roots are tree minima: a link always
+// goes from a larger root to a smaller one) and the number of components.
+__global__ void k_stamped_labels(int64_t n, const uint64_t* W, int32_t* labels, long long* ncomp) {
+  __shared__ long long red[256 / kWave];
+  long long roots = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int32_t r = find_stamped(W, (int32_t)v, ~0u);
+    labels[v] = r;
+    roots += (r == (int32_t)v);
+  }
+  roots = wave_sum(roots);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = roots;
+  __syncthreads();
+  if (threadIdx.x == 0 && ncomp) {
+    long long t = 0;
+    for (int i = 0; i < 256 / kWave; ++i) t += red[i];
+    if (t) atomicAdd((unsigned long long*)ncomp, (unsigned long long)t);
+  }
+}
+
+__global__ void k_server_zero(long long* p) { *p = 0; }
 
 }  // namespace cc
 
 struct cc_server {
   cc_ctx* ctx = nullptr;
-  cc_stream* st = nullptr;
+  cc_stream* st = nullptr;      // barrier mode: the union-find state
+  uint64_t* W = nullptr;        // stamped mode: stamped parent words
+  uint32_t* err = nullptr;      // stamped mode: device error word
+  bool stamped = false;
   int64_t n = 0;
   size_t budget = 0;
   int nstreams = 0;
@@ -112,17 +234,20 @@ struct cc_server {
   std::vector<hipStream_t> streams;
   std::vector<int> stream_busy;  // requests in flight per stream
   hipStream_t barrier_stream = nullptr;
-  std::vector<hipEvent_t> events;      // every event created; destroyed with the server
-  std::deque<cc::Request*> pending;   // arrival order, not yet admitted
+  std::vector<hipEvent_t> events_all;   // every event created; destroyed with the server
+  std::vector<hipEvent_t> events_free;  // recycled, ready for a new record
+  std::vector<hipEvent_t> barriers_old; // superseded barriers, recycled once complete
+  std::deque<cc::Request*> pending;     // arrival order, not yet admitted
   std::vector<cc::Request*> inflight;
-  std::vector<cc::Request*> all;
-  // phase bookkeeping
-  int phase_type = -1;
-  hipEvent_t phase_barrier = nullptr;       // previous phases complete
-  std::vector<hipEvent_t> phase_events;     // completion events of the current phase
+  std::unordered_map<int64_t, cc::Request*> live;  // submitted, not completed
+  std::vector<cc::Done> done_ring;
+  // phases
+  int last_type = -1;                   // type of the last admitted request
+  hipEvent_t barrier = nullptr;         // everything the next phase must wait for
+  std::vector<cc::Request*> phase_open; // in-flight requests of the current phase (that a barrier must cover)
+  uint32_t ins_phase = 0;               // stamped mode: insert phases started
   std::chrono::steady_clock::time_point t0;
   int64_t next_id = 0;
-  uint32_t device_error = 0;
 };
 
 namespace cc {
@@ -132,21 +257,43 @@ static double now_s(const cc_server* s) {
 }
 
 static hipEvent_t take_event(cc_server* s) {
+  if (!s->events_free.empty()) {
+    hipEvent_t e = s->events_free.back();
+    s->events_free.pop_back();
+    return e;
+  }
   hipEvent_t e = nullptr;
   if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
-  s->events.push_back(e);
+  s->events_all.push_back(e);
   return e;
 }
 
-// Closes the current phase: a barrier event on the barrier stream after every
-// completion event of the phase.
+// Superseded barriers are reused once they have completed: every wait that
+// referred to them was enqueued before they were superseded.
+static void recycle_barriers(cc_server* s) {
+  for (size_t i = 0; i < s->barriers_old.size();) {
+    if (hipEventQuery(s->barriers_old[i]) == hipSuccess) {
+      s->events_free.push_back(s->barriers_old[i]);
+      s->barriers_old[i] = s->barriers_old.back();
+      s->barriers_old.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+// Closes the current phase: a barrier event on the barrier stream after the
+// previous barrier and every request of the phase still in flight (a
+// completed request is already ordered before anything launched later).
 static cc_status close_phase(cc_server* s) {
-  for (hipEvent_t e : s->phase_events) CC_HIP(hipStreamWaitEvent(s->barrier_stream, e, 0));
+  if (s->barrier) CC_HIP(hipStreamWaitEvent(s->barrier_stream, s->barrier, 0));
+  for (Request* r : s->phase_open) CC_HIP(hipStreamWaitEvent(s->barrier_stream, r->ev, 0));
   hipEvent_t b = take_event(s);
   if (!b) return fail(CC_EDEVICE, "cannot create an event");
   CC_HIP(hipEventRecord(b, s->barrier_stream));
-  s->phase_barrier = b;
-  s->phase_events.clear();
+  if (s->barrier) s->barriers_old.push_back(s->barrier);
+  s->barrier = b;
+  s->phase_open.clear();
   return CC_OK;
 }
 
@@ -161,35 +308,70 @@ static cc_status launch(cc_server* s, Request* r) {
   char* d = s->dpool + r->off;
   const size_t half = (size_t)r->k * 4;
   const size_t pair_bytes = 2 * half;
-  if (r->type != s->phase_type) {
-    if (s->phase_type != -1) {
+  // Phase bookkeeping.  Barrier mode: every change of type closes the phase.
+  // Stamped mode: only an insert phase is ever waited for, so only the change
+  // insert -> query closes one, and a new insert phase opens after a query.
+  bool track = true;
+  if (s->stamped) {
+    if (r->type == 1 && s->last_type == 0) {
       cc_status st = close_phase(s);
       if (st != CC_OK) return st;
     }
-    s->phase_type = r->type;
+    if (r->type == 0 && s->last_type != 0) ++s->ins_phase;
+    track = r->type == 0;
+  } else if (r->type != s->last_type && s->last_type != -1) {
+    cc_status st = close_phase(s);
+    if (st != CC_OK) return st;
   }
+  s->last_type = r->type;
   CC_HIP(hipMemcpyAsync(d, r->a, half, hipMemcpyHostToDevice, hs));
   CC_HIP(hipMemcpyAsync(d + half, r->b, half, hipMemcpyHostToDevice, hs));
-  if (s->phase_barrier) CC_HIP(hipStreamWaitEvent(hs, s->phase_barrier, 0));
+  if (s->barrier) CC_HIP(hipStreamWaitEvent(hs, s->barrier, 0));
   const int32_t* a = (const int32_t*)d;
-  const int32_t* b = (const int32_t*)(d + (size_t)r->k * 4);
-  cc_status st;
-  if (r->type == 0) {
+  const int32_t* b = (const int32_t*)(d + half);
+  uint8_t* out = (uint8_t*)(d + pair_bytes);
+  cc_status st = CC_OK;
+  if (s->stamped) {
+    const unsigned g = grid_for(r->k, 256, 8192);
+    if (r->type == 0)
+      hipLaunchKernelGGL(k_stamped_insert, dim3(g), dim3(256), 0, hs, r->k, a, b, s->W, s->ins_phase, s->n, s->err);
+    else
+      hipLaunchKernelGGL(k_stamped_query, dim3(g), dim3(256), 0, hs, r->k, a, b, out, (const uint64_t*)s->W,
+                         s->ins_phase, s->n, s->err);
+    CC_LAUNCH_CHECK();
+  } else if (r->type == 0) {
     st = cc_insert_batch(s->st, r->k, a, b, hs);
   } else {
-    uint8_t* out = (uint8_t*)(d + pair_bytes);
     st = cc_query_batch(s->st, r->k, a, b, out, hs);
-    if (st == CC_OK) CC_HIP(hipMemcpyAsync(r->out_host, out, (size_t)r->k, hipMemcpyDeviceToHost, hs));
   }
   if (st != CC_OK) return st;
+  if (r->type == 1) CC_HIP(hipMemcpyAsync(r->out_host, out, (size_t)r->k, hipMemcpyDeviceToHost, hs));
   r->ev = take_event(s);
   if (!r->ev) return fail(CC_EDEVICE, "cannot create an event");
   CC_HIP(hipEventRecord(r->ev, hs));
-  s->phase_events.push_back(r->ev);
-  r->state = 1;
-  r->admitted = now_s(s);
+  if (track) s->phase_open.push_back(r);
   s->inflight.push_back(r);
   return CC_OK;
+}
+
+// A request has completed: its memory, stream slot and event go back, its
+// latency is recorded, and it is freed.
+static void retire(cc_server* s, Request* r, double now) {
+  const double lat = now - r->arrival;
+  s->pool.release(r->off, r->bytes);
+  s->stream_busy[r->stream]--;
+  auto it = std::find(s->phase_open.begin(), s->phase_open.end(), r);
+  if (it != s->phase_open.end()) {
+    *it = s->phase_open.back();
+    s->phase_open.pop_back();
+  }
+  s->events_free.push_back(r->ev);
+  if (r->latency_out) *r->latency_out = lat;
+  Done& d = s->done_ring[(size_t)(r->id % kInfoRing)];
+  d.id = r->id;
+  d.latency = lat;
+  s->live.erase(r->id);
+  delete r;
 }
 
 }  // namespace cc
@@ -202,30 +384,49 @@ cc_status cc_server_create(cc_ctx* ctx, int64_t n, const cc_variant* v, int64_t 
                            int max_inflight, cc_server** out) {
   if (!ctx || !out) return fail(CC_EINVAL, "NULL argument");
   *out = nullptr;
+  if (n < 1 || n > 0x7fffffffLL) return fail(CC_EINVAL, "n=%lld outside [1, 2^31-1]", (long long)n);
   if (budget_bytes < 4096) return fail(CC_EINVAL, "budget below 4 KiB");
   if (num_streams < 1 || num_streams > 16) return fail(CC_EINVAL, "num_streams must be in [1, 16]");
   if (max_inflight < 1 || max_inflight > 1024) return fail(CC_EINVAL, "max_inflight must be in [1, 1024]");
+  if (v) {
+    cc_status vs = check_variant(v, true);
+    if (vs != CC_OK) return vs;
+  }
+  CC_HIP(hipSetDevice(ctx->device));
   cc_server* s = new cc_server();
   s->ctx = ctx;
   s->n = n;
-  cc_status st = cc_stream_create(ctx, n, v, &s->st);
+  s->stamped = !v || (v->finish == CC_FIN_UF_ASYNC && v->find == CC_FIND_NAIVE);
+  cc_status st = CC_OK;
+  if (s->stamped) {
+    if (hipMalloc((void**)&s->W, (size_t)n * 8) != hipSuccess || hipMalloc((void**)&s->err, 256) != hipSuccess)
+      st = fail(CC_ENOMEM, "cannot allocate the stamped union-find state (%lld vertices)", (long long)n);
+  } else {
+    st = cc_stream_create(ctx, n, v, &s->st);
+  }
+  if (st == CC_OK && hipMalloc((void**)&s->dpool, (size_t)budget_bytes) != hipSuccess)
+    st = fail(CC_ENOMEM, "cannot allocate a %lld-byte request pool", (long long)budget_bytes);
   if (st != CC_OK) {
+    if (s->W) (void)hipFree(s->W);
+    if (s->err) (void)hipFree(s->err);
+    if (s->st) cc_stream_destroy(s->st);
     delete s;
     return st;
   }
   s->budget = (size_t)budget_bytes;
   s->nstreams = num_streams;
   s->max_inflight = max_inflight;
-  if (hipMalloc((void**)&s->dpool, s->budget) != hipSuccess) {
-    cc_stream_destroy(s->st);
-    delete s;
-    return fail(CC_ENOMEM, "cannot allocate a %lld-byte request pool", (long long)budget_bytes);
-  }
   s->pool.reset(s->budget);
-  s->streams.resize(num_streams);
+  s->done_ring.assign((size_t)kInfoRing, Done{});
+  s->streams.assign(num_streams, nullptr);
   s->stream_busy.assign(num_streams, 0);
   for (auto& x : s->streams) CC_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
   CC_HIP(hipStreamCreateWithFlags(&s->barrier_stream, hipStreamNonBlocking));
+  if (s->stamped) {
+    hipLaunchKernelGGL(k_stamped_init, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s->barrier_stream, n, s->W);
+    CC_HIP(hipMemsetAsync(s->err, 0, 256, s->barrier_stream));
+    CC_HIP(hipStreamSynchronize(s->barrier_stream));
+  }
   s->t0 = std::chrono::steady_clock::now();
   *out = s;
   return CC_OK;
@@ -234,19 +435,30 @@ cc_status cc_server_create(cc_ctx* ctx, int64_t n, const cc_variant* v, int64_t 
 void cc_server_destroy(cc_server* s) {
   if (!s) return;
   (void)hipDeviceSynchronize();
-  for (auto* r : s->all) delete r;
-  for (auto e : s->events) (void)hipEventDestroy(e);
+  for (auto* r : s->pending) delete r;
+  for (auto* r : s->inflight) delete r;
+  for (auto e : s->events_all) (void)hipEventDestroy(e);
   for (auto x : s->streams) (void)hipStreamDestroy(x);
   if (s->barrier_stream) (void)hipStreamDestroy(s->barrier_stream);
   if (s->dpool) (void)hipFree(s->dpool);
-  cc_stream_destroy(s->st);
+  if (s->W) (void)hipFree(s->W);
+  if (s->err) (void)hipFree(s->err);
+  if (s->st) cc_stream_destroy(s->st);
   delete s;
 }
 
 double cc_server_clock(cc_server* s) { return s ? now_s(s) : 0.0; }
 
+int32_t cc_server_stamped(const cc_server* s) { return s && s->stamped ? 1 : 0; }
+
+int64_t cc_server_event_count(const cc_server* s) { return s ? (int64_t)s->events_all.size() : -1; }
+
+}  // extern "C"
+
+namespace cc {
+
 static cc_status submit(cc_server* s, int type, int64_t k, const int32_t* a, const int32_t* b, uint8_t* out,
-                        double arrival, int64_t* id) {
+                        double arrival, int64_t* id, double* latency_out = nullptr) {
   if (!s) return fail(CC_EINVAL, "server is NULL");
   if (k < 1) return fail(CC_EINVAL, "a request needs at least one pair");
   if (!a || !b || (type == 1 && !out)) return fail(CC_EINVAL, "NULL array");
@@ -260,27 +472,15 @@ static cc_status submit(cc_server* s, int type, int64_t k, const int32_t* a, con
   r->arrival = arrival >= 0 ? arrival : now_s(s);
   r->bytes = bytes;
   r->out_host = out;
-  s->all.push_back(r);
   r->a = a;
   r->b = b;
+  r->latency_out = latency_out;
+  s->live[r->id] = r;
   s->pending.push_back(r);
   if (id) *id = r->id;
   return CC_OK;
 }
 
-cc_status cc_server_submit_insert(cc_server* s, int64_t k, const int32_t* u, const int32_t* v, double arrival,
-                                  int64_t* id) {
-  return submit(s, 0, k, u, v, nullptr, arrival, id);
-}
-
-cc_status cc_server_submit_query(cc_server* s, int64_t q, const int32_t* a, const int32_t* b, uint8_t* out,
-                                 double arrival, int64_t* id) {
-  return submit(s, 1, q, a, b, out, arrival, id);
-}
-
-}  // extern "C"
-
-namespace cc {
 // Retires finished requests, then admits pending ones in arrival order while
 // memory and stream slots allow.
 static cc_status progress_staged(cc_server* s) {
@@ -288,18 +488,16 @@ static cc_status progress_staged(cc_server* s) {
     Request* r = s->inflight[i];
     hipError_t q = hipEventQuery(r->ev);
     if (q == hipSuccess) {
-      r->done_at = now_s(s);
-      r->state = 2;
-      s->pool.release(r->off, r->bytes);
-      s->stream_busy[r->stream]--;
       s->inflight[i] = s->inflight.back();
       s->inflight.pop_back();
+      retire(s, r, now_s(s));
     } else if (q == hipErrorNotReady) {
       ++i;
     } else {
       return fail(CC_EDEVICE, "request event failed: %s", hipGetErrorString(q));
     }
   }
+  recycle_barriers(s);
   while (!s->pending.empty() && (int)s->inflight.size() < s->max_inflight) {
     Request* r = s->pending.front();
     size_t off = 0;
@@ -311,9 +509,33 @@ static cc_status progress_staged(cc_server* s) {
   }
   return CC_OK;
 }
+
+// Device error word of the server's state (reported once, then cleared).
+static cc_status server_sync_status(cc_server* s) {
+  if (!s->stamped) return cc_stream_sync_status(s->st);
+  CC_HIP(hipDeviceSynchronize());
+  uint32_t e = 0;
+  CC_HIP(hipMemcpy(&e, s->err, 4, hipMemcpyDeviceToHost));
+  if (e) {
+    CC_HIP(hipMemset(s->err, 0, 4));
+    return fail(CC_EDEVICE, "device error word 0x%x (1: id out of range)", e);
+  }
+  return CC_OK;
+}
+
 }  // namespace cc
 
 extern "C" {
+
+cc_status cc_server_submit_insert(cc_server* s, int64_t k, const int32_t* u, const int32_t* v, double arrival,
+                                  int64_t* id) {
+  return submit(s, 0, k, u, v, nullptr, arrival, id);
+}
+
+cc_status cc_server_submit_query(cc_server* s, int64_t q, const int32_t* a, const int32_t* b, uint8_t* out,
+                                 double arrival, int64_t* id) {
+  return submit(s, 1, q, a, b, out, arrival, id);
+}
 
 cc_status cc_server_poll(cc_server* s, int wait_all) {
   if (!s) return fail(CC_EINVAL, "server is NULL");
@@ -321,10 +543,7 @@ cc_status cc_server_poll(cc_server* s, int wait_all) {
     cc_status st = progress_staged(s);
     if (st != CC_OK) return st;
   } while (wait_all && (!s->pending.empty() || !s->inflight.empty()));
-  if (wait_all) {
-    cc_status st = cc_stream_sync_status(s->st);
-    if (st != CC_OK) return st;
-  }
+  if (wait_all) return server_sync_status(s);
   return CC_OK;
 }
 
@@ -339,40 +558,47 @@ cc_status cc_server_run_trace(cc_server* s, int64_t count, const int32_t* type, 
   if (!s || count < 0 || (count && (!type || !arrival_s || !start || !len || !a || !b || !latency_s)))
     return fail(CC_EINVAL, "bad trace arguments");
   const double base = now_s(s);
-  std::vector<int64_t> ids(count);
   for (int64_t i = 0; i < count; ++i) {
     while (now_s(s) - base < arrival_s[i]) {
       cc_status st = progress_staged(s);
       if (st != CC_OK) return st;
     }
+    latency_s[i] = -1.0;
     cc_status st = submit(s, type[i] ? 1 : 0, len[i], a + start[i], b + start[i], type[i] ? out + start[i] : nullptr,
-                          base + arrival_s[i], &ids[i]);
+                          base + arrival_s[i], nullptr, &latency_s[i]);
     if (st != CC_OK) return st;
     st = progress_staged(s);
     if (st != CC_OK) return st;
   }
-  cc_status st = cc_server_poll(s, 1);
-  if (st != CC_OK) return st;
-  for (int64_t i = 0; i < count; ++i) {
-    const Request* r = s->all[(size_t)ids[i]];
-    latency_s[i] = r->done_at - r->arrival;
-  }
-  return CC_OK;
+  return cc_server_poll(s, 1);
 }
 
 cc_status cc_server_request_info(cc_server* s, int64_t id, int* done, double* latency_s) {
-  if (!s || id < 0 || id >= (int64_t)s->all.size()) return fail(CC_EINVAL, "unknown request");
-  const Request* r = s->all[(size_t)id];
-  if (done) *done = r->state == 2;
-  if (latency_s) *latency_s = r->state == 2 ? r->done_at - r->arrival : -1.0;
+  if (!s || id < 0 || id >= s->next_id) return fail(CC_EINVAL, "unknown request");
+  if (s->live.count(id)) {
+    if (done) *done = 0;
+    if (latency_s) *latency_s = -1.0;
+    return CC_OK;
+  }
+  const Done& d = s->done_ring[(size_t)(id % kInfoRing)];
+  if (d.id != id) return fail(CC_EINVAL, "request %lld completed too long ago to be kept", (long long)id);
+  if (done) *done = 1;
+  if (latency_s) *latency_s = d.latency;
   return CC_OK;
 }
 
 cc_status cc_server_labels(cc_server* s, int32_t* labels_out, int64_t* num_components_dev, void* hip_stream) {
   if (!s) return fail(CC_EINVAL, "server is NULL");
+  if (!labels_out) return fail(CC_EINVAL, "labels_out is NULL");
   cc_status st = cc_server_poll(s, 1);
   if (st != CC_OK) return st;
-  return cc_stream_labels(s->st, labels_out, num_components_dev, hip_stream);
+  if (!s->stamped) return cc_stream_labels(s->st, labels_out, num_components_dev, hip_stream);
+  hipStream_t hs = (hipStream_t)hip_stream;
+  if (num_components_dev) hipLaunchKernelGGL(k_server_zero, dim3(1), dim3(1), 0, hs, (long long*)num_components_dev);
+  hipLaunchKernelGGL(k_stamped_labels, dim3(grid_for(s->n, 256, 4096)), dim3(256), 0, hs, s->n,
+                     (const uint64_t*)s->W, labels_out, (long long*)num_components_dev);
+  CC_LAUNCH_CHECK();
+  return CC_OK;
 }
 
 int64_t cc_server_pool_used(cc_server* s) { return s ? (int64_t)s->pool.used() : -1; }

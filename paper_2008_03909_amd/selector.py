@@ -57,6 +57,34 @@ def arms():
     return out
 
 
+# End-to-end cost of the features, the forward pass and the host's wait for
+# the choice, measured on held-out graphs as the selector's time minus its
+# chosen arm's time (about 25 us); used to decide where the model pays.
+SELECTOR_OVERHEAD_MS = 0.025
+GATE_CANDIDATES = (0, 1 << 12, 1 << 13, 1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
+
+
+def choose_gate(times, n, picks, overhead_ms=SELECTOR_OVERHEAD_MS):
+    """The small-graph gate (min_vertices, arm) that minimises the mean time
+    over training graphs when graphs below min_vertices run one fixed arm
+    (no selector cost) and the rest run the model's pick plus its overhead.
+    min_vertices = 0 means no gate."""
+    times = np.asarray(times, np.float64)
+    n = np.asarray(n)
+    rows = np.arange(times.shape[0])
+    model_cost = times[rows, picks] + overhead_ms
+    best = (float(model_cost.mean()), 0, -1)
+    for th in GATE_CANDIDATES[1:]:
+        below = n < th
+        if not below.any():
+            continue
+        arm = int(np.argmin(times[below].mean(0)))
+        cost = float(np.where(below, times[:, arm], model_cost).mean())
+        if cost < best[0]:
+            best = (cost, int(th), arm)
+    return best[1], best[2]
+
+
 def default_arm_index() -> int:
     return 4   # k-out + Rem-CAS/SplitAtomicOne/FindNaive: the paper's default
 
@@ -232,25 +260,31 @@ def predict(ctx, params, K, Xn):
     return b.mlp_forward(params, K, Xd).cpu().numpy()
 
 
-def save(path, master, norm, K, meta=None):
-    np.savez(path, master=master, norm=norm, K=np.int32(K), **(meta or {}))
+def save(path, master, norm, K, gate=(0, -1), meta=None):
+    np.savez(path, master=master, norm=norm, K=np.int32(K), gate_vertices=np.int64(gate[0]),
+             gate_arm=np.int32(gate[1]), **(meta or {}))
 
 
 def load(ctx, path):
+    """(params_bf16 on the device, norm, K, gate)."""
     z = np.load(path, allow_pickle=False)
     master = torch.from_numpy(z["master"].astype(np.float32)).to(ctx.torch_device)
-    return b.mlp_pack_bf16(master), z["norm"].astype(np.float32), int(z["K"])
+    gate = (int(z["gate_vertices"]), int(z["gate_arm"])) if "gate_vertices" in z.files else (0, -1)
+    return b.mlp_pack_bf16(master), z["norm"].astype(np.float32), int(z["K"]), gate
 
 
-def evaluate(ctx, params, norm, seeds, lo=12, hi=22, reps=3, log=None):
-    """Held-out evaluation: time the selector (features + model + chosen arm,
-    end to end), the per-graph best arm re-timed independently, the fixed
-    default and the decision-tree rules; labels of the selector are checked
-    against the default's."""
+def evaluate(ctx, params, norm, seeds, lo=12, hi=22, reps=3, log=None, gate=(0, -1), all80=True):
+    """Held-out evaluation: time the selector (gate, features, model and
+    chosen arm, end to end), the per-graph best arm re-timed independently,
+    the fixed default and the decision-tree rules; with all80 also every one
+    of the 80 sampling x finish variants of the main table, and the best of
+    them re-timed.  Labels of the selector are checked against the
+    default's."""
     arm_list = arms()
+    main80 = b.all_variants()
     dev = ctx.torch_device
     rows = []
-    sel = b.Selector(ctx, params, arm_list, norm)
+    sel = b.Selector(ctx, params, arm_list, norm, gate=gate)
     ctx.set_round_limit(2000)
     for i, s in enumerate(seeds):
         fam, g = corpus_graph(s, lo, hi)
@@ -274,8 +308,15 @@ def evaluate(ctx, params, norm, seeds, lo=12, hi=22, reps=3, log=None):
         t_best, _ = time_arm(ctx, csr, arm_list[best], labels, ncomp, reps)        # re-timed
         t_def = times[default_arm_index()]
         t_tree = times[decision_tree_arm(feats)]
-        rows.append(dict(seed=s, family=fam, n=g.n, chosen=chosen, best=best, t_selector=t_sel, t_best=t_best,
-                         t_default=t_def, t_tree=t_tree, t_chosen_arm=times[chosen], labels_equal=same))
+        row = dict(seed=s, family=fam, n=g.n, chosen=chosen, best=best, t_selector=t_sel, t_best=t_best,
+                   t_default=t_def, t_tree=t_tree, t_chosen_arm=times[chosen], labels_equal=same,
+                   gated=bool(gate[0] > 0 and g.n < gate[0]))
+        if all80:
+            t80 = [time_arm(ctx, csr, v, labels, ncomp, reps)[0] for v in main80]
+            b80 = int(np.argmin(t80))
+            row["best80"] = b80
+            row["t_best80"], _ = time_arm(ctx, csr, main80[b80], labels, ncomp, reps)    # re-timed
+        rows.append(row)
         if log and (i % 10 == 0 or i + 1 == len(seeds)):
             log(f"eval {i + 1}/{len(seeds)} {fam} n={g.n} chosen={chosen} best={best} sel={t_sel:.3f} "
                 f"best={t_best:.3f} default={t_def:.3f}")
@@ -289,7 +330,13 @@ def summarize(rows):
     de = np.array([r["t_default"] for r in rows])
     tree = np.array([r["t_tree"] for r in rows])
     arm = np.array([r["t_chosen_arm"] for r in rows])
+    out80 = {}
+    if rows and "t_best80" in rows[0]:
+        b80 = np.array([r["t_best80"] for r in rows])
+        out80 = {"best_of_80_variants_ms": float(b80.mean()), "selector_over_best80": float(sel.mean() / b80.mean())}
     return {
+        **out80,
+        "gated_graphs": int(sum(1 for r in rows if r.get("gated"))),
         "graphs": len(rows),
         "mean_ms": {"selector": float(sel.mean()), "best": float(best.mean()), "default": float(de.mean()),
                     "decision_tree": float(tree.mean()), "chosen_arm_only": float(arm.mean())},
@@ -344,6 +391,10 @@ def main(argv=None):
     e.add_argument("--out", required=True)
     e.add_argument("--lo", type=int, default=12)
     e.add_argument("--hi", type=int, default=22)
+    e.add_argument("--no-all80", action="store_true", help="skip timing the 80 main variants per graph")
+    g2 = sub.add_parser("gate", help="fit the small-graph gate of an existing model from corpus files")
+    g2.add_argument("--model", required=True)
+    g2.add_argument("--corpus", nargs="+", required=True)
     a = ap.parse_args(argv)
     ctx = b.Context(0)
     if a.cmd == "corpus":
@@ -359,7 +410,10 @@ def main(argv=None):
         Y = targets(C["times"][train_mask])
         params, master, hist = train(ctx, Xn, Y, epochs=a.epochs, log=_log)
         K = Y.shape[1]
-        save(a.out, master, norm, K, {"loss": np.array(hist, np.float32)})
+        picks_tr = predict(ctx, params, K, Xn).argmin(1)
+        gate = choose_gate(C["times"][train_mask], C["n"][train_mask], picks_tr)
+        _log(f"gate: graphs below {gate[0]} vertices run arm {gate[1]} without the model")
+        save(a.out, master, norm, K, gate, {"loss": np.array(hist, np.float32)})
         # selection quality on the held-out corpus rows (recorded times)
         hm = ~train_mask
         if hm.any():
@@ -369,11 +423,22 @@ def main(argv=None):
             sel = th[np.arange(th.shape[0]), pick].mean()
             _log(f"held-out rows={hm.sum()} selected/best={sel / th.min(1).mean():.3f} "
                  f"selected/default={sel / th[:, default_arm_index()].mean():.3f}")
+    elif a.cmd == "gate":
+        C = load_corpus(a.corpus)
+        tm = C["seeds"] % 10 != 0
+        params, norm, K, _ = load(ctx, a.model)
+        Xn = (C["features"][tm] - norm[:16]) / norm[16:]
+        picks_tr = predict(ctx, params, K, Xn).argmin(1)
+        gate = choose_gate(C["times"][tm], C["n"][tm], picks_tr)
+        z = dict(np.load(a.model, allow_pickle=False))
+        z["gate_vertices"], z["gate_arm"] = np.int64(gate[0]), np.int32(gate[1])
+        np.savez(a.model, **z)
+        _log(f"gate: graphs below {gate[0]} vertices run arm {gate[1]} without the model")
     else:
-        params, norm, K = load(ctx, a.model)
+        params, norm, K, gate = load(ctx, a.model)
         lo, hi = (int(x) for x in a.seeds.split(":"))
         seeds = [s for s in range(lo, hi) if s % 10 == 0]
-        rows = evaluate(ctx, params, norm, seeds, a.lo, a.hi, log=_log)
+        rows = evaluate(ctx, params, norm, seeds, a.lo, a.hi, log=_log, gate=gate, all80=not a.no_all80)
         out = {"summary": summarize(rows), "rows": rows}
         with open(a.out, "w") as f:
             json.dump(out, f, indent=1)

@@ -138,3 +138,70 @@ def test_amsf_rmat_2_24(ctx, rmat24):
         assert np.array_equal(np.bincount(fb, minlength=len(cnt)), cnt), lf
         assert abs(float(tw.item()) - float(np.sum(fw, dtype=np.float64))) < 1e-6 * float(tw.item())
 
+
+def test_map_and_gather_edges_rmat_2_24(ctx, rmat24):
+    """The calibration primitives at full size (hub rows far above a
+    wave's 4096-entry limit): MapEdges gives every degree, GatherEdges the
+    sum of a value over each row, as numpy computes them from the CSR."""
+    d = rmat24.csr
+    off = d.offsets.cpu().numpy().astype(np.int64)
+    deg = np.diff(off)
+    got = b.calib_edges(d).cpu().numpy()
+    assert np.array_equal(got, deg.astype(np.int32))
+    vals = ((np.arange(d.n, dtype=np.int64) * 7 + 3) % 1000).astype(np.int32)
+    gv = b.calib_edges(d, torch.from_numpy(vals).to(ctx.torch_device)).cpu().numpy()
+    adj = d.adj.cpu().numpy()
+    csum = np.concatenate([[0], np.cumsum(vals[adj].astype(np.int64))])
+    want = csum[off[1:]] - csum[off[:-1]]
+    assert np.array_equal(gv.astype(np.int64), want)
+
+
+def test_serving_trace_rmat_2_24_every_answer(ctx, rmat24):
+    """The serving loop at full size (the R-MAT 2^24 pairs, shuffled, as insert
+    requests of log-uniform size in [1e3, 1e7] between query requests of
+    [1e3, 1e6] uniform pairs, Poisson arrivals faster than the device drains
+    them, so queries overlap the inserts that arrive after them): every query
+    answer equals the oracle's answer against exactly the earlier inserts."""
+    g = rmat24.g
+    su, sv = inputs.shuffle_pairs(g.u, g.v, 5)
+    rng = np.random.default_rng(41)
+    types, starts, lens, A, B = [], [], [], [], []
+    pe = pos = 0
+    for i in range(80):
+        t = int(rng.random() < 0.5)
+        if t == 0 and pe < su.size:
+            k = min(inputs.log_uniform_int(1e3, 1e7, rng.random()), su.size - pe)
+            A.append(su[pe:pe + k])
+            B.append(sv[pe:pe + k])
+            pe += k
+        else:
+            t = 1
+            k = inputs.log_uniform_int(1e3, 1e6, rng.random())
+            qa, qb = inputs.query_pairs(g.n, k, seed=4000 + i)
+            A.append(qa)
+            B.append(qb)
+        types.append(t)
+        starts.append(pos)
+        lens.append(k)
+        pos += k
+    types, starts, lens = np.array(types, np.int32), np.array(starts, np.int64), np.array(lens, np.int64)
+    A = np.concatenate(A).astype(np.int32)
+    B = np.concatenate(B).astype(np.int32)
+    arrivals = np.cumsum(rng.exponential(50e-6, types.size))
+    srv = b.Server(ctx, g.n, budget_bytes=1 << 30, num_streams=4, max_inflight=32)
+    assert srv.stamped
+    _note(f"serving trace: {types.size} requests, {int(lens[types == 0].sum())} inserts, "
+          f"{int(lens[types == 1].sum())} queries")
+    got, lat = srv.run_trace(types, arrivals, starts, lens, A, B)
+    inc = oracle.Incremental(g.n)
+    for t, s, k in zip(types, starts, lens):
+        sl = slice(s, s + k)
+        if t == 0:
+            inc.insert(A[sl], B[sl])
+        else:
+            assert np.array_equal(got[sl], inc.query(A[sl], B[sl])), (s, k)
+    assert np.all(lat > 0)
+    lab, nc = srv.labels()
+    want, wc = inc.labels()
+    assert np.array_equal(lab.cpu().numpy(), want)
+    srv.close()

@@ -61,11 +61,16 @@ def _alone(n, types, starts, lens, A, B):
     return out
 
 
-@pytest.mark.parametrize("streams,budget", [(1, 1 << 24), (4, 1 << 24), (8, 1 << 20)])
-def test_server_submit_matches_alone(ctx, streams, budget):
+BARRIER_VARIANT = b.default_variant(finish=b.FIN_UF_REM_CAS, splice=b.SPLICE_SPLIT_ONE, find=b.FIND_NAIVE)
+
+
+@pytest.mark.parametrize("streams,budget,variant", [(1, 1 << 24, None), (4, 1 << 24, None), (8, 1 << 20, None),
+                                                    (4, 1 << 24, BARRIER_VARIANT)])
+def test_server_submit_matches_alone(ctx, streams, budget, variant):
     n = 1 << 15
     types, starts, lens, A, B = _trace(n, 120, seed=streams)
-    srv = b.Server(ctx, n, budget_bytes=budget, num_streams=streams, max_inflight=32)
+    srv = b.Server(ctx, n, variant=variant, budget_bytes=budget, num_streams=streams, max_inflight=32)
+    assert srv.stamped == (variant is None)
     outs = []
     for t, s, k in zip(types, starts, lens):
         sl = slice(s, s + k)
@@ -88,13 +93,15 @@ def test_server_submit_matches_alone(ctx, streams, budget):
     srv.close()
 
 
-def test_server_trace_in_the_mix_equals_alone(ctx):
-    """Poisson arrivals fast enough that requests overlap on the device."""
+@pytest.mark.parametrize("variant", [None, BARRIER_VARIANT])
+def test_server_trace_in_the_mix_equals_alone(ctx, variant):
+    """Poisson arrivals fast enough that requests overlap on the device (in
+    stamped mode queries also overlap the inserts that arrive after them)."""
     n = 1 << 16
     types, starts, lens, A, B = _trace(n, 300, seed=7, max_insert=200000, max_query=50000)
     rng = np.random.default_rng(3)
     arrivals = np.cumsum(rng.exponential(20e-6, types.size))
-    srv = b.Server(ctx, n, budget_bytes=1 << 26, num_streams=4, max_inflight=16)
+    srv = b.Server(ctx, n, variant=variant, budget_bytes=1 << 26, num_streams=4, max_inflight=16)
     got, lat = srv.run_trace(types, arrivals, starts, lens, A, B)
     want = _alone(n, types, starts, lens, A, B)
     q = np.zeros(A.size, bool)
@@ -120,4 +127,49 @@ def test_server_rejects_requests_over_budget(ctx):
     srv.poll(wait_all=True)
     assert out.tolist() == [1, 0, 0]
     assert srv.info(rid)[0]
+    srv.close()
+
+
+def test_server_state_stays_bounded_and_answers_stay_exact(ctx):
+    """3,000 small requests that alternate between inserts and queries (a
+    phase change at almost every request): every answer equals the alone
+    answer, the HIP events the server holds stay bounded by the requests in
+    flight, and the outcome of recent requests is still reported."""
+    n = 1 << 14
+    types, starts, lens, A, B = _trace(n, 3000, seed=11, max_insert=300, max_query=300)
+    srv = b.Server(ctx, n, budget_bytes=1 << 22, num_streams=4, max_inflight=8)
+    rng = np.random.default_rng(5)
+    arrivals = np.cumsum(rng.exponential(2e-6, types.size))
+    got, lat = srv.run_trace(types, arrivals, starts, lens, A, B)
+    want = _alone(n, types, starts, lens, A, B)
+    q = np.zeros(A.size, bool)
+    for t, s0, k in zip(types, starts, lens):
+        if t == 1:
+            q[s0:s0 + k] = True
+    assert np.array_equal(got[q], want[q])
+    assert np.all(lat > 0)
+    assert srv.event_count() <= 2 * 8 + 8, srv.event_count()
+    rid = srv.insert(np.array([1], np.int32), np.array([2], np.int32))
+    srv.poll(wait_all=True)
+    done, l1 = srv.info(rid)
+    assert done and l1 > 0
+    assert srv.pool_used() == 0
+    srv.close()
+
+
+def test_server_labels_after_stamped_inserts(ctx):
+    """The stamped state's labels (every link, whatever its phase) equal the
+    oracle's labels of all inserts, and bad ids are reported."""
+    n = 5000
+    g = inputs.er(n, 4000, seed=12)
+    srv = b.Server(ctx, n, budget_bytes=1 << 20, num_streams=2, max_inflight=4)
+    for i in range(0, g.u.size, 700):
+        srv.insert(g.u[i:i + 700], g.v[i:i + 700])
+        srv.query(g.u[:50], g.v[::-1][:50])
+    lab, nc = srv.labels()
+    want, wc = oracle.uf_cc(n, g.u, g.v)
+    assert np.array_equal(lab.cpu().numpy(), want) and int(nc.item()) == wc
+    srv.insert(np.array([3, n + 5], np.int32), np.array([4, 1], np.int32))
+    with pytest.raises(b.CCError):
+        srv.poll(wait_all=True)
     srv.close()
