@@ -344,7 +344,9 @@ struct CandLists {
 template <class Op, typename I>
 inline void visit_candidates(hipStream_t s, const CandLists& L, const I* off, const int32_t* adj, Op op,
                              uint32_t* flag) {
-  const int64_t g0 = grid_for(L.n, kFBlock, 4096), g1 = grid_for(L.n * kWave, kFBlock, 2048), g2 = 1024, g3 = 2048;
+  // grid-stride parts: enough blocks to fill the device, few enough that an
+  // almost empty list (k-out leaves a few thousand candidates) costs little
+  const int64_t g0 = grid_for(L.n, kFBlock, 2048), g1 = grid_for(L.n * kWave, kFBlock, 1024), g2 = 512, g3 = 1024;
   hipLaunchKernelGGL((k_visit_all<Op, I>), dim3((unsigned)(g0 + g1 + g2 + g3)), dim3(kFBlock), 0, s, L.n, g0, g1, g2,
                      L.cand, L.big, L.heavy, L.hp, L.bins, off, adj, op, flag);
 }

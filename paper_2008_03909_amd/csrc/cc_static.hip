@@ -337,10 +337,11 @@ __global__ void k_zero_one_i32(int32_t* p) { *p = 0; }
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ adj,
                                                  int32_t* P, int k, int mode, uint64_t key, int2* hook,
-                                                 const int32_t* __restrict__ pick0) {
+                                                 const int32_t* __restrict__ pick0, int32_t* __restrict__ count) {
   constexpr int kMaxPreload = 4;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    if (count) count[v] = 0;  // IdentifyFrequent's histogram, cleared here instead of by the init
     const int64_t b = (int64_t)off[v];
     const int64_t deg = (int64_t)off[v + 1] - b;
     if (deg <= 0) continue;
@@ -999,7 +1000,8 @@ static cc_status run_sample(StaticArgs& a) {
       // they free up, which balances rows of different cost better than a
       // grid-stride loop (measured 0.53 -> 0.49 ms on R-MAT 2^24)
       hipLaunchKernelGGL(k_kout<I>, dim3(grid_for(a.n, kBlock, kVertexGridCap)), dim3(kBlock), 0, a.s, a.n,
-                         (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key, a.hook_e, (const int32_t*)pick0);
+                         (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key, a.hook_e, (const int32_t*)pick0,
+                         a.count);
       CC_LAUNCH_CHECK();
       use_lmax = true;
       break;
@@ -1035,9 +1037,10 @@ template <typename I>
 static cc_status run_static(StaticArgs& a, bool sample_only) {
   if (!a.skip_init) {
     PhaseScope ps(a.ctx, a.s, "init");
+    // no sampling needs no histogram; k-out clears it in its own sweep
+    const bool no_count = a.v->sample == CC_SAMPLE_NONE || a.v->sample == CC_SAMPLE_KOUT;
     hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P,
-                       a.v->sample == CC_SAMPLE_NONE ? (int32_t*)nullptr : a.count, vec_ok(a), a.ctx->dev,
-                       (long long*)a.ncomp_user);
+                       no_count ? (int32_t*)nullptr : a.count, vec_ok(a), a.ctx->dev, (long long*)a.ncomp_user);
     CC_LAUNCH_CHECK();
   }
   cc_status st = run_sample<I>(a);
