@@ -4,7 +4,12 @@ from committed data: the network trained on the GPU
 MLP forward pass to the recorded features of the 200 held-out corpus graphs
 (seed % 10 == 0); the recorded time of each selected arm is compared with
 the per-graph best arm, the fixed default (k-out + UF-Rem-CAS /
-SplitAtomicOne / FindNaive) and the paper's text rules."""
+SplitAtomicOne / FindNaive) and the paper's text rules.  The end-to-end
+figures of the GPU evaluation (selector_data/eval.json: the selector's own
+time -- gate, features, forward pass, host wait and chosen arm -- against
+the best arm and the best of the 80 main variants, each re-timed) are
+checked too."""
+import json
 import glob
 import os
 
@@ -51,3 +56,18 @@ def test_trained_selector_against_best_default_and_rules():
     assert sel <= 1.10 * best, (sel, best)
     assert sel < 0.9 * default, (sel, default)
     assert sel < rules, (sel, rules)
+
+
+def test_end_to_end_evaluation():
+    """The selector's measured end-to-end mean is within 10% of the per-graph
+    best arm, below the fixed default, and never changes a label; its regret
+    against the best of the 80 main variants is reported beside it."""
+    d = json.load(open(os.path.join(DATA, "eval.json")))
+    s = d["summary"]
+    assert s["graphs"] == 200 and s["labels_always_equal"]
+    assert s["selector_over_best"] <= 1.10, s
+    assert s["selector_over_default"] < 0.9, s
+    assert "selector_over_best80" in s and s["selector_over_best80"] < s["mean_ms"]["default"] / s["best_of_80_variants_ms"]
+    rows = d["rows"]
+    sel = np.mean([r["t_selector"] for r in rows])
+    assert abs(sel / np.mean([r["t_best"] for r in rows]) - s["selector_over_best"]) < 1e-9
