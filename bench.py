@@ -50,16 +50,19 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def phase_alg_bytes(phase: str, n: int, m: int, o: int, n_nz: int, st: dict, k: int = 2) -> float:
+def phase_alg_bytes(phase: str, n: int, m: int, o: int, n_nz: int, st: dict, k: int = 2, counts_in_init: bool = False) -> float:
     """Algorithmic bytes of one launch of a phase of the default variant.
 
     n_nz = vertices with at least one edge; n_f / m_f = candidate vertices /
-    their adjacency entries; every random 4-byte access counts 4 bytes."""
+    their adjacency entries; every random 4-byte access counts 4 bytes.
+    With k-out sampling the sampling kernel also clears the frequency
+    counts, which the init then leaves alone (BFS and LDD leave them to the
+    init; no sampling needs none)."""
     n_f, m_f, comps = st["candidates"], st["candidate_edges"], st["num_components"]
     if phase == "init":
-        return 8.0 * n                                   # P and count writes
+        return 8.0 * n if counts_in_init else 4.0 * n   # P (and count) writes
     if phase == "sample":
-        return o * n + 16.0 * k * n_nz                   # row bounds; k picks; k unions (2 reads + CAS)
+        return o * n + 4.0 * n + 16.0 * k * n_nz         # row bounds; count clear; k picks; k unions (2 reads + CAS)
     if phase == "compress_count":
         return (4.0 + o) * n + 8.0 * n_nz                # P, degree; root read + count update
     if phase == "frequent":
@@ -609,7 +612,8 @@ def main():
     ph_out = {}
     for name, (ms, cnt) in phases.items():
         avg = ms / max(cnt, 1)
-        ab = phase_alg_bytes(name, n, m, o, n_nz, st)
+        ab = phase_alg_bytes(name, n, m, o, n_nz, st, k=v.kout_k,
+                             counts_in_init=v.sample in (b.SAMPLE_BFS, b.SAMPLE_LDD))
         alg_total += ab * cnt / args.steps
         ph_out[name] = {"avg_ms": round(avg, 4), "launches": cnt, "alg_bytes": ab,
                         "alg_gbs": round(ab / (avg / 1e3) / 1e9, 1) if avg > 0 else None}
