@@ -9,8 +9,10 @@
 //                 bound for any connectivity algorithm that always answers
 //                 correctly, appendix "Comparison with MapEdges and
 //                 GatherEdges")
-// Short rows are reduced by a wave over 64 rows at a time, long rows in
-// edge chunks spread over the grid.
+// Rows are binned by length, the same way the connectivity kernels bin
+// their candidate vertices: a lane reduces a row of up to 32 entries, a wave
+// one of up to 4096, and longer rows are cut into edge chunks spread over
+// the whole grid.
 #include "cc_frontier.h"
 #include "cc_static.h"
 
@@ -21,20 +23,13 @@ __global__ void k_copy16(const int4* __restrict__ src, int4* __restrict__ dst, i
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = src[i];
 }
 
-// Rows of up to kCalibWaveRow entries: a wave takes 64 consecutive rows.
-// When none of them is longer, their entries are one contiguous run of the
-// adjacency; the wave walks it in windows of kCalibWindow entries: every
-// lane loads 16 entries of the window (coalesced, all in flight together)
-// and stores their values (1 for MapEdges, vals[w] for GatherEdges) in LDS;
-// then each lane adds up 16 consecutive values of the window, stepping
-// through the row ends it passes and adding each row's part into that
-// row's LDS slot.  A wave that holds a longer row (listed for
-// k_edges_heavy) walks each of its other rows with the whole wave, or with
-// one lane when the row is shorter than a wave.
+// First sweep, one lane per vertex: rows of at most kCalibLaneRow entries
+// are reduced by their lane (value 1 per entry for MapEdges, vals[w] for
+// GatherEdges); longer rows are appended, a wave at a time, to the medium
+// list (up to kCalibWaveRow entries) or the heavy list.
+constexpr int kCalibLaneRow = 32;
 constexpr int kCalibWaveRow = 4096;
 constexpr int kCalibBlock = 256;
-constexpr int kCalibPer = 16;
-constexpr int kCalibWindow = kCalibPer * 64;
 
 template <bool GATHER>
 __device__ __forceinline__ int32_t edge_value(const int32_t* __restrict__ vals, int32_t w) {
@@ -47,94 +42,23 @@ __global__ void __launch_bounds__(kCalibBlock) k_edges_reduce(int64_t n, const I
                                                               const int32_t* __restrict__ vals,
                                                               int32_t* __restrict__ out, int32_t* heavy,
                                                               int32_t* hcount, int32_t* medium, int32_t* mcount) {
-  // one padding word after every 16 values, so that the 64 chunks of 16 a
-  // lane each reads start in different LDS banks
-  __shared__ int32_t win_s[kCalibBlock / kWave][kCalibWindow + kCalibWindow / kCalibPer];
-  __shared__ long long end_s[kCalibBlock / kWave][kWave];
-  __shared__ int32_t acc_s[kCalibBlock / kWave][kWave];
-  const int lane = lane_id();
-  const int wv = threadIdx.x / kWave;
-  int32_t* win = win_s[wv];
-  long long* re = end_s[wv];
-  int32_t* acc = acc_s[wv];
-  const int64_t nwaves = (int64_t)gridDim.x * (kCalibBlock / kWave);
-  for (int64_t wb = blockIdx.x * (int64_t)(kCalibBlock / kWave) + wv; wb * kWave < n; wb += nwaves) {
-    const int64_t v = wb * kWave + lane;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+    const int64_t v = base + threadIdx.x;
     int64_t b = 0, e = 0;
-    if (v < n) {
-      b = (int64_t)off[v];
-      e = (int64_t)off[v + 1];
-    }
-    const bool heavy_row = (e - b) > kCalibWaveRow;
-    wave_append(heavy_row, (int32_t)v, heavy, (uint32_t*)hcount);
-    int32_t mine = 0;
-    if (__ballot(heavy_row)) {
-      // rare: the light rows of this wave are not one run (these waves hold
-      // the graph's hubs and many long rows); rows longer than a wave go to
-      // k_edges_medium, one wave each, shorter ones are walked by their lane
-      const bool wide = !heavy_row && (e - b) > kWave;
-      wave_append(wide, (int32_t)v, medium, (uint32_t*)mcount);
-      if (!heavy_row && !wide)
-        for (int64_t j = b; j < e; ++j) mine += edge_value<GATHER>(vals, adj[j]);
-    } else {
-      const int last = (int)((n - wb * kWave) < kWave ? (n - wb * kWave) : kWave) - 1;
-      const int64_t B = __shfl(b, 0, kWave);
-      const int64_t E = __shfl(e, last, kWave);
-      re[lane] = lane <= last ? e : E;   // row ends, ascending
-      acc[lane] = 0;
-      for (int64_t W = B; W < E; W += kCalibWindow) {
-        int32_t x[kCalibPer];
-#pragma unroll
-        for (int r = 0; r < kCalibPer; ++r) {
-          const int64_t j = W + lane + (int64_t)r * kWave;
-          x[r] = j < E ? adj[j] : 0;
-        }
-#pragma unroll
-        for (int r = 0; r < kCalibPer; ++r) {
-          const int64_t j = W + lane + (int64_t)r * kWave;
-          const int i = lane + r * kWave;
-          win[i + i / kCalibPer] = j < E ? edge_value<GATHER>(vals, x[r]) : 0;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int64_t c0 = W + (int64_t)kCalibPer * lane;          // this lane's 16 consecutive entries
-        const int64_t c1 = (c0 + kCalibPer < E) ? c0 + kCalibPer : E;
-        if (c0 < c1) {
-          int lo = 0, hi = kWave - 1;  // first row whose end is past c0
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (re[mid] > c0) hi = mid;
-            else lo = mid + 1;
-          }
-          int row = lo;
-          int32_t part = 0;
-          for (int64_t j = c0; j < c1; ++j) {
-            while (j >= re[row]) {
-              if (part) atomicAdd(acc + row, part);
-              part = 0;
-              ++row;
-            }
-            const int i = (int)(j - W);
-            part += win[i + i / kCalibPer];
-          }
-          if (part) atomicAdd(acc + row, part);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-      mine = acc[lane];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    if (v < n) out[v] = mine;  // heavy rows start at 0 (k_edges_heavy adds their sums); medium rows are overwritten
+    if (v < n) { b = (int64_t)off[v]; e = (int64_t)off[v + 1]; }
+    const int64_t d = e - b;
+    wave_append(d > kCalibWaveRow, (int32_t)v, heavy, (uint32_t*)hcount);
+    wave_append(d > kCalibLaneRow && d <= kCalibWaveRow, (int32_t)v, medium, (uint32_t*)mcount);
+    int32_t acc = 0;
+    if (d <= kCalibLaneRow)
+      for (int64_t j = b; j < e; ++j) acc += edge_value<GATHER>(vals, adj[j]);
+    if (v < n) out[v] = acc;
   }
 }
 
-// Rows of (64, kCalibWaveRow] entries that share a wave with a longer row:
-// one wave per row, four loads in flight per lane.
+// Medium rows, (kCalibLaneRow, kCalibWaveRow] entries: one wave per row,
+// four loads in flight per lane.
 template <bool GATHER, typename I>
 __global__ void __launch_bounds__(kCalibBlock) k_edges_medium(const int32_t* __restrict__ medium,
                                                               const int32_t* mcount, const I* __restrict__ off,
@@ -240,7 +164,7 @@ static void launch_edges(int64_t n, const I* off, const int32_t* adj, const int3
   long long* tsum = (long long*)(w + 256 + align256(hcap * 4) + align256((hcap + 1) * 8));
   int32_t* medium = (int32_t*)((char*)tsum + align256((hcap / kHpTile + 3) * 8));
   hipLaunchKernelGGL(k_zero_two_i32, dim3(1), dim3(1), 0, s, hcount);
-  hipLaunchKernelGGL((k_edges_reduce<GATHER, I>), dim3(grid_for(div_up(n, kWave), kCalibBlock / kWave, 1 << 16)),
+  hipLaunchKernelGGL((k_edges_reduce<GATHER, I>), dim3(grid_for(n, kCalibBlock, 1 << 16)),
                      dim3(kCalibBlock), 0, s, n, off, adj, vals, out, heavy, hcount, medium, mcount);
   hipLaunchKernelGGL((k_edges_medium<GATHER, I>), dim3(2048), dim3(kCalibBlock), 0, s, (const int32_t*)medium,
                      (const int32_t*)mcount, off, adj, vals, out);
@@ -271,9 +195,9 @@ cc_status cc_calib_workspace_bytes(int64_t m, size_t* bytes) {
   if (!bytes || m < 0) return fail(CC_EINVAL, "bad argument");
   const size_t hcap = heavy_cap(m);
   // heavy list, its degree prefix and tile sums, then the medium list (rows
-  // of more than 64 entries: at most m / 64 of them)
+  // of more than 32 entries: at most m / 32 of them)
   *bytes = 256 + align256(hcap * 4) + align256((hcap + 1) * 8) + align256((hcap / kHpTile + 3) * 8) +
-           align256(((size_t)m / kWave + 2) * 4);
+           align256(((size_t)m / 32 + 2) * 4);
   return CC_OK;
 }
 

@@ -341,14 +341,23 @@ struct CandLists {
   const int32_t* bins;    // the four bins' lengths (device)
 };
 
+// Blocks of each bin's part in a combined launch over lists of n vertices:
+// grid-stride parts, enough blocks to fill the device, few enough that an
+// almost empty list (k-out leaves a few thousand candidates) costs little.
+inline void visit_grids(int64_t n, int64_t g[4]) {
+  g[0] = grid_for(n, kFBlock, 2048);
+  g[1] = grid_for(n * kWave, kFBlock, 1024);
+  g[2] = 512;
+  g[3] = 1024;
+}
+
 template <class Op, typename I>
 inline void visit_candidates(hipStream_t s, const CandLists& L, const I* off, const int32_t* adj, Op op,
                              uint32_t* flag) {
-  // grid-stride parts: enough blocks to fill the device, few enough that an
-  // almost empty list (k-out leaves a few thousand candidates) costs little
-  const int64_t g0 = grid_for(L.n, kFBlock, 2048), g1 = grid_for(L.n * kWave, kFBlock, 1024), g2 = 512, g3 = 1024;
-  hipLaunchKernelGGL((k_visit_all<Op, I>), dim3((unsigned)(g0 + g1 + g2 + g3)), dim3(kFBlock), 0, s, L.n, g0, g1, g2,
-                     L.cand, L.big, L.heavy, L.hp, L.bins, off, adj, op, flag);
+  int64_t g[4];
+  visit_grids(L.n, g);
+  hipLaunchKernelGGL((k_visit_all<Op, I>), dim3((unsigned)(g[0] + g[1] + g[2] + g[3])), dim3(kFBlock), 0, s, L.n,
+                     g[0], g[1], g[2], L.cand, L.big, L.heavy, L.hp, L.bins, off, adj, op, flag);
 }
 
 [[maybe_unused]] static __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }

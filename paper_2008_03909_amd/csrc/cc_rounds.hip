@@ -373,16 +373,25 @@ cc_status edge_list_rounds(cc_ctx* ctx, hipStream_t s, const cc_variant& v, int6
 // lane whose writeMin lowers a label sets that vertex's bit in a bitmap; the
 // next round's frontier is built from the bitmap (bits cleared as they are
 // read) into the same four degree bins as the candidate lists, so the same
-// edge visitors balance its rows.  A vertex that keeps its label has already
-// pushed it to every neighbour, and a neighbour in the frequent class hands
-// its -1 over in round 0, so visiting only the frontier leaves the fixed
-// point unchanged.  Rounds stop when no label changes.  Then the -1 class
-// takes its smallest member as its label; every other class already carries
-// its minimum (the sampled labels are class minima), so the result is the
-// canonical labelling and a star forest.
+// edge visitors balance its rows.  Rounds stop when no bit was set.  Then
+// the -1 class takes its smallest member as its label; every other class
+// already carries its minimum (the sampled labels are class minima), so the
+// result is the canonical labelling and a star forest.
+//
+// One change of schedule against the appendix: a lane that walks a row of
+// the thread bin and lowers the label of a neighbour whose own row is also
+// short pushes that neighbour onto a small stack in LDS and walks its row
+// next (depth first, at most kLpChase rows per frontier vertex), instead of
+// leaving it to the next round; only what does not fit gets a bit.  With
+// rounds alone a label moves one edge per round, and on a graph whose ids
+// follow its geometry (a lattice) every vertex then takes a new, slightly
+// smaller label in almost every round, so the work grows with n times the
+// diameter.  The fixed point is the same: every vertex whose label drops
+// has its row walked afterwards, with a label read after the drop, either
+// by the lane that lowered it or in the next round.
 struct LpOp {
   int32_t* P;
-  uint32_t* chg;  // bit per vertex: its label dropped in this round
+  uint32_t* chg;  // bit per vertex: its label dropped and its row is still to walk
   __device__ __forceinline__ bool operator()(int32_t u, int32_t w, int64_t) const {
     const int32_t a = ld(P + u), c = ld(P + w);
     if (a < c) {
@@ -398,6 +407,89 @@ struct LpOp {
     return false;
   }
 };
+
+constexpr int kLpStack = 16;  // rows a lane keeps waiting in LDS
+constexpr int kLpChase = 64;  // rows a lane walks per frontier vertex beyond its own
+
+// Thread-bin part of a label propagation round: one lane per frontier
+// vertex, with the depth-first push described above.
+template <typename I>
+__device__ __forceinline__ void lp_thread_part(int64_t bid, int64_t nb, const int32_t* __restrict__ list,
+                                               const int32_t* bins, const I* __restrict__ off,
+                                               const int32_t* __restrict__ adj, int32_t* P, uint32_t* chg,
+                                               int32_t (*stk)[kFBlock], uint32_t* flag) {
+  const int64_t cnt = bins[0];
+  const int t = threadIdx.x;
+  const int64_t stride = nb * blockDim.x;
+  bool any = false;
+  for (int64_t i = bid * (int64_t)blockDim.x + t; i < cnt; i += stride) {
+    int32_t x = list[i];
+    int sp = 0, budget = kLpChase;
+    for (;;) {
+      int32_t a = ld(P + x);
+      const int64_t e = (int64_t)off[x + 1];
+      for (int64_t j = (int64_t)off[x]; j < e; ++j) {
+        const int32_t w = adj[j];
+        const int32_t c = ld(P + w);
+        if (a < c) {
+          if (amin(P + w, a) > a) {
+            bool walk = false;
+            if (sp < kLpStack && budget > 0) walk = (int64_t)off[w + 1] - (int64_t)off[w] <= kThrWave;
+            if (walk) {
+              stk[sp++][t] = w;
+              --budget;
+            } else {
+              bit_claim(chg, w);
+              any = true;
+            }
+          }
+        } else if (c < a) {
+          const int32_t old = amin(P + x, c);
+          if (old > c) {
+            // the entries before j got the larger label: walk the row again
+            bit_claim(chg, x);
+            any = true;
+          }
+          a = old < c ? old : c;
+        }
+      }
+      if (sp == 0) break;
+      x = stk[--sp][t];
+    }
+  }
+  if (flag) wave_flag(any, flag);
+}
+
+// One label propagation round over degree-binned lists (the candidates in
+// round 0, a frontier afterwards); the block layout of k_visit_all.
+template <typename I>
+__global__ void __launch_bounds__(kFBlock) k_lp_visit(int64_t n, int64_t g0, int64_t g1, int64_t g2,
+                                                      const int32_t* __restrict__ cand,
+                                                      const int32_t* __restrict__ big,
+                                                      const int32_t* __restrict__ heavy,
+                                                      const long long* __restrict__ hp, const int32_t* bins,
+                                                      const I* __restrict__ off, const int32_t* __restrict__ adj,
+                                                      int32_t* P, uint32_t* chg, uint32_t* flag) {
+  __shared__ int32_t stk[kLpStack][kFBlock];
+  int64_t b = blockIdx.x;
+  if (b < g0) return lp_thread_part<I>(b, g0, cand, bins, off, adj, P, chg, stk, flag);
+  b -= g0;
+  const LpOp op{P, chg};
+  if (b < g1) return visit_wave_part<LpOp, I>(b, g1, big, bins, off, adj, op, flag);
+  b -= g1;
+  if (b < g2) return visit_block_part<LpOp, I>(b, g2, n, big, bins, off, adj, op, flag);
+  b -= g2;
+  visit_heavy_part<LpOp, I>(b, (int64_t)gridDim.x - g0 - g1 - g2, heavy, &bins[3], hp, off, adj, op, flag);
+}
+
+template <typename I>
+static void lp_round(hipStream_t s, const CandLists& L, const I* off, const int32_t* adj, int32_t* P, uint32_t* chg,
+                     uint32_t* flag) {
+  int64_t g[4];
+  visit_grids(L.n, g);
+  hipLaunchKernelGGL(k_lp_visit<I>, dim3((unsigned)(g[0] + g[1] + g[2] + g[3])), dim3(kFBlock), 0, s, L.n, g[0],
+                     g[1], g[2], L.cand, L.big, L.heavy, L.hp, L.bins, off, adj, P, chg, flag);
+}
 
 // Next frontier from the change bitmap: every set bit is cleared and its
 // vertex appended to the bin of its degree (thread bin to q0, wave bin to
@@ -515,14 +607,14 @@ cc_status finish_lp(StaticArgs& a) {
     if (a.ctx->round_limit > 0 && round >= a.ctx->round_limit)
       return fail(CC_ELIVELOCK, "label propagation reached the context's round limit (%d)", a.ctx->round_limit);
     if (round == 0) {
-      visit_candidates(a.s, a.lists(), (const I*)a.off, a.adj, LpOp{a.P, chg}, &sc->changed);
+      lp_round<I>(a.s, a.lists(), (const I*)a.off, a.adj, a.P, chg, &sc->changed);
     } else {
       int32_t* bins = sc->fbin[round & 1];
       hipLaunchKernelGGL(k_lp_frontier<I>, dim3(gf), dim3(kFBlock), 0, a.s, n, chg, (const I*)a.off, q0, q1,
                          a.heavy, bins, sc->fbin[(round + 1) & 1], &sc->changed);
       if (grid_bin) heavy_prefix<I>(a.s, a.heavy, &bins[3], a.hcap, (const I*)a.off, a.tsum, a.hp);
       const CandLists fl{n, q0, q1, a.heavy, a.hp, bins};
-      visit_candidates(a.s, fl, (const I*)a.off, a.adj, LpOp{a.P, chg}, &sc->changed);
+      lp_round<I>(a.s, fl, (const I*)a.off, a.adj, a.P, chg, &sc->changed);
     }
     CC_LAUNCH_CHECK();
     ++a.finish_rounds;
