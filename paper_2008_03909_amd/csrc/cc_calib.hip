@@ -9,10 +9,10 @@
 //                 bound for any connectivity algorithm that always answers
 //                 correctly, appendix "Comparison with MapEdges and
 //                 GatherEdges")
-// Rows are binned by length, the same way the connectivity kernels bin
-// their candidate vertices: a lane reduces a row of up to 32 entries, a wave
-// one of up to 4096, and longer rows are cut into edge chunks spread over
-// the whole grid.
+// The adjacency array is cut into chunks of kCalibChunk consecutive
+// entries, one block each, whatever rows they belong to, so every load is
+// coalesced and every block has the same work (the CSR-stream scheme for
+// sparse matrix-vector products).
 #include "cc_frontier.h"
 #include "cc_static.h"
 
@@ -23,154 +23,149 @@ __global__ void k_copy16(const int4* __restrict__ src, int4* __restrict__ dst, i
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = src[i];
 }
 
-// First sweep, one lane per vertex: rows of at most kCalibLaneRow entries
-// are reduced by their lane (value 1 per entry for MapEdges, vals[w] for
-// GatherEdges); longer rows are appended, a wave at a time, to the medium
-// list (up to kCalibWaveRow entries) or the heavy list.
-constexpr int kCalibLaneRow = 32;
-constexpr int kCalibWaveRow = 4096;
 constexpr int kCalibBlock = 256;
+constexpr int kCalibPer = 8;                             // entries per lane
+constexpr int64_t kCalibChunk = kCalibBlock * kCalibPer;  // entries per block
+constexpr int kCalibRows = 2048;  // rows a chunk may span with its offsets staged in LDS
 
 template <bool GATHER>
 __device__ __forceinline__ int32_t edge_value(const int32_t* __restrict__ vals, int32_t w) {
   return GATHER ? vals[w] : (w >= 0 ? 1 : 0);
 }
 
-template <bool GATHER, typename I>
-__global__ void __launch_bounds__(kCalibBlock) k_edges_reduce(int64_t n, const I* __restrict__ off,
-                                                              const int32_t* __restrict__ adj,
-                                                              const int32_t* __restrict__ vals,
-                                                              int32_t* __restrict__ out, int32_t* heavy,
-                                                              int32_t* hcount, int32_t* medium, int32_t* mcount) {
+// One lane per row: crow[k] = the row holding entry k * kCalibChunk, for
+// every chunk boundary inside the row, and crow[K] = the row holding the
+// last entry; empty rows get their (zero) result here.
+template <typename I>
+__global__ void __launch_bounds__(kCalibBlock) k_edges_rows(int64_t n, int64_t m, const I* __restrict__ off,
+                                                            int32_t* __restrict__ crow, int32_t* __restrict__ out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
-    const int64_t v = base + threadIdx.x;
-    int64_t b = 0, e = 0;
-    if (v < n) { b = (int64_t)off[v]; e = (int64_t)off[v + 1]; }
-    const int64_t d = e - b;
-    wave_append(d > kCalibWaveRow, (int32_t)v, heavy, (uint32_t*)hcount);
-    wave_append(d > kCalibLaneRow && d <= kCalibWaveRow, (int32_t)v, medium, (uint32_t*)mcount);
-    int32_t acc = 0;
-    if (d <= kCalibLaneRow)
-      for (int64_t j = b; j < e; ++j) acc += edge_value<GATHER>(vals, adj[j]);
-    if (v < n) out[v] = acc;
-  }
-}
-
-// Medium rows, (kCalibLaneRow, kCalibWaveRow] entries: one wave per row,
-// four loads in flight per lane.
-template <bool GATHER, typename I>
-__global__ void __launch_bounds__(kCalibBlock) k_edges_medium(const int32_t* __restrict__ medium,
-                                                              const int32_t* mcount, const I* __restrict__ off,
-                                                              const int32_t* __restrict__ adj,
-                                                              const int32_t* __restrict__ vals,
-                                                              int32_t* __restrict__ out) {
-  const int64_t c = *mcount;
-  const int lane = lane_id();
-  const int64_t nwaves = (int64_t)gridDim.x * (kCalibBlock / kWave);
-  for (int64_t i = blockIdx.x * (int64_t)(kCalibBlock / kWave) + threadIdx.x / kWave; i < c; i += nwaves) {
-    const int32_t u = medium[i];
-    const int64_t b = (int64_t)off[u], e = (int64_t)off[u + 1];
-    int32_t part = 0;
-    for (int64_t j0 = b; j0 < e; j0 += 4 * kWave) {
-      int32_t x[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t j = j0 + lane + r * kWave;
-        x[r] = j < e ? adj[j] : -1;
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (j0 + lane + r * kWave < e) part += edge_value<GATHER>(vals, x[r]);
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += stride) {
+    const int64_t b = (int64_t)off[r], e = (int64_t)off[r + 1];
+    if (b == e) {
+      out[r] = 0;
+      continue;
     }
-    part = wave_sum(part);
-    if (lane == 0) out[u] = part;
+    for (int64_t k = (b + kCalibChunk - 1) / kCalibChunk; k * kCalibChunk < e; ++k) crow[k] = (int32_t)r;
+    if (e == m) crow[(m + kCalibChunk - 1) / kCalibChunk] = (int32_t)r;
   }
 }
 
-// Rows longer than kCalibWaveRow: each wave takes chunks of kCalibChunk
-// consecutive entries of the heavy rows' concatenation (hp = degree prefix
-// of the heavy list); a lane keeps a running sum while the row of its
-// entries stays the same, and whenever some lane reaches a new row the wave
-// adds its sums row by row (one atomic per row run), so a row costs one
-// atomic per chunk it meets instead of one per 64 entries.
-constexpr int64_t kCalibChunk = 4096;
-
-// Adds each lane's `sum` into out[r] for every distinct r >= 0 held by the
-// wave's lanes, one atomic per distinct r, and zeroes the sums it added.
-__device__ __forceinline__ void wave_add_runs(int32_t r, int32_t& sum, int32_t* out) {
-  uint64_t act = __ballot(r >= 0);
-  while (act) {
-    const int leader = __ffsll((unsigned long long)act) - 1;
-    const int32_t lr = __shfl(r, leader, kWave);
-    const bool mine = r == lr && r >= 0;
-    const int32_t part = wave_sum(mine ? sum : 0);
-    if (lane_id() == leader) atomicAdd(out + lr, part);
-    act &= ~__ballot(mine);
-    if (mine) {
-      r = -1;
-      sum = 0;
-    }
-  }
-}
-
-template <bool GATHER, typename I>
-__global__ void __launch_bounds__(kCalibBlock) k_edges_heavy(const int32_t* __restrict__ heavy, const int32_t* hcount,
-                                                             const long long* __restrict__ hp,
-                                                             const I* __restrict__ off,
+// Block k reduces entries [k C, k C + C) (C = kCalibChunk): lane t loads
+// entries 8t .. 8t + 7 of the chunk (two 16-byte loads when the array is
+// aligned), finds the row of its first entry by binary search in the rows'
+// offsets staged in LDS, and adds its values row by row into per-row LDS
+// sums (one LDS atomic per row run).  The chunk then writes the rows that
+// start in it; a row that started in an earlier chunk leaves its share in
+// cont[k] for k_edges_carry.  A chunk that spans more than kCalibRows rows
+// (runs of empty rows) walks them one lane per row instead.
+template <bool GATHER, bool VEC, typename I>
+__global__ void __launch_bounds__(kCalibBlock) k_edges_chunk(int64_t m, const I* __restrict__ off,
                                                              const int32_t* __restrict__ adj,
                                                              const int32_t* __restrict__ vals,
-                                                             int32_t* __restrict__ out) {
-  const int64_t c = *hcount;
-  if (c == 0) return;
-  const long long T = hp[c];
-  const int lane = lane_id();
-  const int64_t nwaves = (int64_t)gridDim.x * (kCalibBlock / kWave);
-  for (int64_t ch = blockIdx.x * (int64_t)(kCalibBlock / kWave) + threadIdx.x / kWave; ch * kCalibChunk < T;
-       ch += nwaves) {
-    const long long e0 = ch * kCalibChunk;
-    const long long e1 = (e0 + kCalibChunk < T) ? e0 + kCalibChunk : T;
-    int64_t i = heavy_owner(hp, c, e0);  // the same for every lane
-    int32_t cur = -1, sum = 0;
-    for (long long e = e0 + lane; __ballot(e < e1); e += kWave) {
-      int32_t u = -1, x = 0;
-      if (e < e1) {
-        while (i + 1 < c && hp[i + 1] <= e) ++i;
-        u = heavy[i];
-        const int32_t w = adj[(int64_t)off[u] + (e - hp[i])];
-        x = GATHER ? vals[w] : (w >= 0 ? 1 : 0);
-      }
-      const bool moved = cur >= 0 && u != cur;
-      if (__ballot(moved)) wave_add_runs(moved ? cur : -1, sum, out);  // zeroes the sums it added
-      if (u != cur) {
-        cur = u;
-        sum = 0;
-      }
-      sum += x;
+                                                             const int32_t* __restrict__ crow,
+                                                             int32_t* __restrict__ out, int32_t* __restrict__ cont) {
+  __shared__ int32_t rel[kCalibRows + 1];  // row offsets minus the chunk start, clamped to [-1, C + 1]
+  __shared__ int32_t acc[kCalibRows];
+  const int64_t k = blockIdx.x;
+  const int64_t c0 = k * kCalibChunk;
+  const int64_t len = (m - c0) < kCalibChunk ? (m - c0) : kCalibChunk;
+  const int32_t r0 = crow[k];
+  const int64_t nr = (int64_t)crow[k + 1] - r0 + 1;
+  const int t = threadIdx.x;
+  if (nr > kCalibRows) {
+    for (int64_t i = t; i < nr; i += kCalibBlock) {
+      const int64_t r = r0 + i;
+      const int64_t b = (int64_t)off[r], e = (int64_t)off[r + 1];
+      const int64_t lo = b > c0 ? b : c0, hi = e < c0 + len ? e : c0 + len;
+      int32_t s = 0;
+      for (int64_t j = lo; j < hi; ++j) s += edge_value<GATHER>(vals, adj[j]);
+      if (b < e && b >= c0 && b < c0 + len) out[r] = s;
+      else if (i == 0 && b < c0) cont[k] = s;
     }
-    wave_add_runs(cur, sum, out);
+    return;
+  }
+  for (int64_t i = t; i <= nr; i += kCalibBlock) {
+    const int64_t x = (int64_t)off[r0 + i] - c0;
+    rel[i] = (int32_t)(x < -1 ? -1 : x > kCalibChunk + 1 ? kCalibChunk + 1 : x);
+    if (i < nr) acc[i] = 0;
+  }
+  __syncthreads();
+  const int e0 = t * kCalibPer;
+  if (e0 < len) {
+    int32_t x[kCalibPer];
+    if (VEC && e0 + kCalibPer <= len) {
+      const int4 a = *(const int4*)(adj + c0 + e0);
+      const int4 b = *(const int4*)(adj + c0 + e0 + 4);
+      x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w, x[4] = b.x, x[5] = b.y, x[6] = b.z, x[7] = b.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kCalibPer; ++j) x[j] = e0 + j < len ? adj[c0 + e0 + j] : 0;
+    }
+    int32_t v[kCalibPer];
+#pragma unroll
+    for (int j = 0; j < kCalibPer; ++j) v[j] = e0 + j < len ? edge_value<GATHER>(vals, x[j]) : 0;
+    // row of entry e0: the last i with rel[i] <= e0 (rows before it that
+    // are empty share its offset and come first)
+    int lo = 0, hi = (int)nr - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rel[mid] <= e0) lo = mid;
+      else hi = mid - 1;
+    }
+    int i = lo;
+    int next = rel[i + 1];
+    int32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kCalibPer; ++j) {
+      if (e0 + j >= len) break;
+      while (e0 + j >= next) {
+        if (s) atomicAdd(acc + i, s);
+        s = 0;
+        ++i;
+        next = rel[i + 1];
+      }
+      s += v[j];
+    }
+    if (s) atomicAdd(acc + i, s);
+  }
+  __syncthreads();
+  for (int64_t i = t; i < nr; i += kCalibBlock) {
+    const int32_t b = rel[i], e = rel[i + 1];
+    if (b < e && b >= 0 && b < len) out[r0 + i] = acc[i];
+    else if (i == 0 && b < 0) cont[k] = acc[0];
   }
 }
 
-__global__ void k_zero_two_i32(int32_t* p) { p[0] = p[1] = 0; }
+// Adds the share of every row that continues across a chunk boundary.
+template <typename I>
+__global__ void k_edges_carry(int64_t K, const I* __restrict__ off, const int32_t* __restrict__ crow,
+                              const int32_t* __restrict__ cont, int32_t* out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < K; k += stride) {
+    const int32_t r = crow[k];
+    if ((int64_t)off[r] < k * kCalibChunk) atomicAdd(out + r, cont[k]);
+  }
+}
 
 template <bool GATHER, typename I>
-static void launch_edges(int64_t n, const I* off, const int32_t* adj, const int32_t* vals, int32_t* out, char* w,
-                         size_t hcap, hipStream_t s) {
-  int32_t* hcount = (int32_t*)w;
-  int32_t* mcount = (int32_t*)w + 1;
-  int32_t* heavy = (int32_t*)(w + 256);
-  long long* hp = (long long*)(w + 256 + align256(hcap * 4));
-  long long* tsum = (long long*)(w + 256 + align256(hcap * 4) + align256((hcap + 1) * 8));
-  int32_t* medium = (int32_t*)((char*)tsum + align256((hcap / kHpTile + 3) * 8));
-  hipLaunchKernelGGL(k_zero_two_i32, dim3(1), dim3(1), 0, s, hcount);
-  hipLaunchKernelGGL((k_edges_reduce<GATHER, I>), dim3(grid_for(n, kCalibBlock, 1 << 16)),
-                     dim3(kCalibBlock), 0, s, n, off, adj, vals, out, heavy, hcount, medium, mcount);
-  hipLaunchKernelGGL((k_edges_medium<GATHER, I>), dim3(2048), dim3(kCalibBlock), 0, s, (const int32_t*)medium,
-                     (const int32_t*)mcount, off, adj, vals, out);
-  heavy_prefix<I>(s, heavy, (const int32_t*)hcount, (int64_t)hcap, off, tsum, hp);
-  hipLaunchKernelGGL((k_edges_heavy<GATHER, I>), dim3(2048), dim3(kCalibBlock), 0, s, (const int32_t*)heavy,
-                     (const int32_t*)hcount, (const long long*)hp, off, adj, vals, out);
+static void launch_edges(int64_t n, int64_t m, const I* off, const int32_t* adj, const int32_t* vals, int32_t* out,
+                         char* w, hipStream_t s) {
+  const int64_t K = (m + kCalibChunk - 1) / kCalibChunk;
+  int32_t* crow = (int32_t*)w;
+  int32_t* cont = (int32_t*)(w + align256((size_t)(K + 1) * 4));
+  hipLaunchKernelGGL((k_edges_rows<I>), dim3(grid_for(n, kCalibBlock, 1 << 16)), dim3(kCalibBlock), 0, s, n, m, off,
+                     crow, out);
+  if (K == 0) return;
+  if (((uintptr_t)adj & 15u) == 0)
+    hipLaunchKernelGGL((k_edges_chunk<GATHER, true, I>), dim3((unsigned)K), dim3(kCalibBlock), 0, s, m, off, adj,
+                       vals, (const int32_t*)crow, out, cont);
+  else
+    hipLaunchKernelGGL((k_edges_chunk<GATHER, false, I>), dim3((unsigned)K), dim3(kCalibBlock), 0, s, m, off, adj,
+                       vals, (const int32_t*)crow, out, cont);
+  if (K > 1)
+    hipLaunchKernelGGL((k_edges_carry<I>), dim3(grid_for(K, kCalibBlock, 1024)), dim3(kCalibBlock), 0, s, K, off,
+                       (const int32_t*)crow, (const int32_t*)cont, out);
 }
 
 }  // namespace cc
@@ -193,11 +188,10 @@ cc_status cc_calib_copy(const void* src, void* dst, size_t bytes, void* hip_stre
 
 cc_status cc_calib_workspace_bytes(int64_t m, size_t* bytes) {
   if (!bytes || m < 0) return fail(CC_EINVAL, "bad argument");
-  const size_t hcap = heavy_cap(m);
-  // heavy list, its degree prefix and tile sums, then the medium list (rows
-  // of more than 32 entries: at most m / 32 of them)
-  *bytes = 256 + align256(hcap * 4) + align256((hcap + 1) * 8) + align256((hcap / kHpTile + 3) * 8) +
-           align256(((size_t)m / 32 + 2) * 4);
+  // the row of every chunk boundary (and of the last entry), then each
+  // chunk's share of a row that started before it
+  const size_t K = (size_t)((m + kCalibChunk - 1) / kCalibChunk);
+  *bytes = align256((K + 1) * 4) + align256((K + 1) * 4);
   return CC_OK;
 }
 
@@ -209,14 +203,13 @@ cc_status cc_calib_edges(int64_t n, int64_t m, const void* offsets, int offsets_
   cc_calib_workspace_bytes(m, &need);
   if (!workspace || ws_bytes < need) return fail(CC_ENOMEM, "workspace smaller than %zu bytes", need);
   hipStream_t s = (hipStream_t)hip_stream;
-  const size_t hcap = heavy_cap(m);
   char* w = (char*)workspace;
   if (offsets_are_64bit) {
-    if (vals) launch_edges<true>(n, (const int64_t*)offsets, adj, vals, out, w, hcap, s);
-    else launch_edges<false>(n, (const int64_t*)offsets, adj, vals, out, w, hcap, s);
+    if (vals) launch_edges<true>(n, m, (const int64_t*)offsets, adj, vals, out, w, s);
+    else launch_edges<false>(n, m, (const int64_t*)offsets, adj, vals, out, w, s);
   } else {
-    if (vals) launch_edges<true>(n, (const int32_t*)offsets, adj, vals, out, w, hcap, s);
-    else launch_edges<false>(n, (const int32_t*)offsets, adj, vals, out, w, hcap, s);
+    if (vals) launch_edges<true>(n, m, (const int32_t*)offsets, adj, vals, out, w, s);
+    else launch_edges<false>(n, m, (const int32_t*)offsets, adj, vals, out, w, s);
   }
   CC_LAUNCH_CHECK();
   return CC_OK;

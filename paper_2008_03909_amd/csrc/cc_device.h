@@ -16,6 +16,21 @@ namespace cc {
 
 constexpr int kWave = 64;
 
+// This block's share of a sweep over [0, n) (see xcd_grid): items
+// base + threadIdx.x, then steps of `step` while below `end`; `base` is the
+// same for the whole block, so loops over it keep block-uniform control.
+struct XcdSweep {
+  int64_t base, end, step;
+};
+__device__ __forceinline__ XcdSweep xcd_sweep(int64_t n) {
+  const int64_t G = gridDim.x, B = blockDim.x;
+  if (G < 8 || G % 8) return XcdSweep{blockIdx.x * B, n, G * B};
+  const int64_t x = blockIdx.x % 8, i = blockIdx.x / 8;
+  const int64_t span = ((n + 7) / 8 + B - 1) / B * B;
+  const int64_t lo = x * span < n ? x * span : n, hi = lo + span < n ? lo + span : n;
+  return XcdSweep{lo + i * B, hi, G / 8 * B};
+}
+
 __device__ __forceinline__ int32_t ld(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

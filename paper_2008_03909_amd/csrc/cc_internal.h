@@ -119,6 +119,19 @@ inline unsigned grid_for(int64_t work, int block, int64_t cap = (int64_t)1 << 20
 }
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// XCD-aware vertex sweeps.  The device hands consecutive blocks of a launch
+// to its 8 XCDs in turn (block b to XCD b mod 8), and each XCD has its own
+// L2.  In a launch whose block count is a multiple of 8, xcd_sweep lets the
+// blocks of XCD x walk the x-th eighth of [0, n) in order, so the vertices
+// one XCD works on at a time are neighbours in id order and share that
+// XCD's cache lines; any other block count gets a plain grid-stride sweep.
+// A different dispatch order only costs speed.
+constexpr int kXcds = 8;
+inline unsigned xcd_grid(int64_t work, int block, int64_t cap) {
+  const int64_t g = grid_for(work, block, cap);
+  return (unsigned)(g >= kXcds ? g / kXcds * kXcds : g);
+}
+
 // Workspace layout of a static call.
 struct WsLayout {
   size_t count = 0;       // n int32: IdentifyFrequent counts / SV prev / LT snapshot

@@ -339,8 +339,8 @@ __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict_
                                                  int32_t* P, int k, int mode, uint64_t key, int2* hook,
                                                  const int32_t* __restrict__ pick0, int32_t* __restrict__ count) {
   constexpr int kMaxPreload = 4;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+  const XcdSweep sw = xcd_sweep(n);
+  for (int64_t v = sw.base + threadIdx.x; v < sw.end; v += sw.step) {
     if (count) count[v] = 0;  // IdentifyFrequent's histogram, cleared here instead of by the init
     const int64_t b = (int64_t)off[v];
     const int64_t deg = (int64_t)off[v + 1] - b;
@@ -996,10 +996,12 @@ static cc_status run_sample(StaticArgs& a) {
         hipLaunchKernelGGL(k_maxdeg_long<I>, dim3(2048), dim3(kBlock), 0, a.s, (const I*)a.off, a.adj,
                            (const int32_t*)a.big, (const int32_t*)nlong, pick0);
       }
-      // one vertex per thread: the hardware spreads the blocks over the CUs as
-      // they free up, which balances rows of different cost better than a
-      // grid-stride loop (measured 0.53 -> 0.49 ms on R-MAT 2^24)
-      hipLaunchKernelGGL(k_kout<I>, dim3(grid_for(a.n, kBlock, kVertexGridCap)), dim3(kBlock), 0, a.s, a.n,
+      // one vertex per thread, each XCD on its own eighth of the ids: the
+      // hardware spreads the blocks over the CUs as they free up, balancing
+      // rows of different cost, and the unions of one XCD stay within its
+      // range (R-MAT 2^24: grid-stride 0.53, one per thread 0.49, by XCD
+      // 0.47 ms; 256^3 grid: 1.00, 1.38, 1.07 ms)
+      hipLaunchKernelGGL(k_kout<I>, dim3(xcd_grid(a.n, kBlock, kVertexGridCap)), dim3(kBlock), 0, a.s, a.n,
                          (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key, a.hook_e, (const int32_t*)pick0,
                          a.count);
       CC_LAUNCH_CHECK();

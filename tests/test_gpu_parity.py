@@ -328,6 +328,46 @@ def test_map_and_gather_edges(ctx):
         assert np.array_equal(gv, want.astype(np.int32)), g
 
 
+def _sym_csr(n, u, v):
+    off, adj = oracle.csr_build(n, np.asarray(u, np.int32), np.asarray(v, np.int32), True)
+    return np.asarray(off, np.int64), np.asarray(adj, np.int32)
+
+
+def _calib_cases():
+    """CSRs whose rows meet the edge-chunk boundaries in every way: a hub row
+    over several chunks, a chunk spanning tens of thousands of rows (mostly
+    empty), the last row the longest, no edges at all."""
+    n = 10000
+    yield "star", n, *_sym_csr(n, np.zeros(n - 1), np.arange(1, n))
+    ids = np.arange(0, 200000, 97)
+    yield "sparse path", 200000, *_sym_csr(200000, ids[:-1], ids[1:])
+    yield "last hub", n, *_sym_csr(n, np.full(n - 1, n - 1), np.arange(n - 1))
+    g = inputs.rmat(14, 8 << 14, 0.57, 0.19, 0.19, seed=5)
+    yield "rmat", g.n + 3000, *_sym_csr(g.n + 3000, g.u, g.v)
+    yield "empty", 10, np.zeros(11, np.int64), np.zeros(0, np.int32)
+
+
+@pytest.mark.parametrize("o64", [False, True])
+@pytest.mark.parametrize("shift", [0, 1])
+def test_map_and_gather_edges_chunk_boundaries(ctx, o64, shift):
+    """MapEdges / GatherEdges against their definitions on rows that cross
+    the kernels' work boundaries; shift = 1 places the adjacency 4 bytes off
+    16-byte alignment."""
+    dev = ctx.torch_device
+    for name, n, off, adj in _calib_cases():
+        offs = torch.from_numpy(off.astype(np.int64 if o64 else np.int32)).to(dev)
+        base = torch.zeros(adj.size + shift + 1, dtype=torch.int32, device=dev)
+        base[shift:shift + adj.size] = torch.from_numpy(adj).to(dev)
+        d = b.CSR(n, offs, base[shift:shift + adj.size])
+        deg = np.diff(off)
+        assert np.array_equal(b.calib_edges(d).cpu().numpy(), deg.astype(np.int32)), name
+        vals = (np.arange(n, dtype=np.int64) * 7 + 3) % 1000
+        want = np.zeros(n, np.int64)
+        np.add.at(want, np.repeat(np.arange(n), deg), vals[adj])
+        got = b.calib_edges(d, torch.from_numpy(vals.astype(np.int32)).to(dev)).cpu().numpy()
+        assert np.array_equal(got, want.astype(np.int32)), name
+
+
 def test_calib_copy(ctx):
     src = torch.randint(0, 255, (1 << 20,), dtype=torch.uint8, device=ctx.torch_device)
     dst = torch.zeros_like(src)
