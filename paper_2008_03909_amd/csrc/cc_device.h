@@ -192,6 +192,35 @@ __device__ __forceinline__ int32_t union_rem_from(int32_t* P, int32_t u, int32_t
   }
 }
 
+// UF-Rem-CAS with FindNaive whose SplitAtomicOne step can be switched off
+// per call: without it the walk only reads parents, and the only writes are
+// the hooking CASes at roots (used by k-out sampling, see k_kout).
+__device__ __forceinline__ int32_t union_rem_opt_split(int32_t* P, int32_t u, int32_t v, bool split) {
+  int32_t ru = u, rv = v;
+  while (true) {
+    int32_t pu = ld(P + ru);
+    int32_t pv = ld(P + rv);
+    if (pu == pv) return -1;
+    if (pu < pv) {
+      int32_t t = ru;
+      ru = rv;
+      rv = t;
+      t = pu;
+      pu = pv;
+      pv = t;
+    }
+    if (pu == ru) {
+      if (cas(P + ru, ru, pv)) return ru;
+      continue;
+    }
+    if (split) {
+      const int32_t w = ld(P + pu);
+      if (pu != w) cas(P + ru, pu, w);
+    }
+    ru = pu;
+  }
+}
+
 template <int SPLICE, int FIND>
 __device__ __forceinline__ int32_t union_rem(int32_t* P, int32_t u, int32_t v) {
   return union_rem_from<SPLICE, FIND>(P, u, v, ld(P + u), ld(P + v));

@@ -334,10 +334,22 @@ __global__ void __launch_bounds__(kBlock) k_maxdeg_long(const I* __restrict__ of
 
 __global__ void k_zero_one_i32(int32_t* p) { *p = 0; }
 
+// k-out's unions are UF-Rem-CAS with FindNaive and, by default,
+// SplitAtomicOne.  When the whole graph is in flight at once (small n) and
+// dense, splitting costs more than it saves: every split is a CAS on a
+// parent slot near the top of a shared tree, which every other walk is
+// reading, so those lines bounce between the CUs.  Then (dense_rule) a
+// vertex of degree above kSplitDegree hooks without splitting; vertices of
+// lower degree, which on lattices and chains hang in long paths, still
+// split.  Both choices give the same partition.
+constexpr int64_t kDenseRuleMaxN = (int64_t)1 << 20;
+constexpr int64_t kSplitDegree = 4;
+
 template <typename I>
 __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ adj,
                                                  int32_t* P, int k, int mode, uint64_t key, int2* hook,
-                                                 const int32_t* __restrict__ pick0, int32_t* __restrict__ count) {
+                                                 const int32_t* __restrict__ pick0, int32_t* __restrict__ count,
+                                                 int dense_rule) {
   constexpr int kMaxPreload = 4;
   const XcdSweep sw = xcd_sweep(n);
   for (int64_t v = sw.base + threadIdx.x; v < sw.end; v += sw.step) {
@@ -345,6 +357,7 @@ __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict_
     const int64_t b = (int64_t)off[v];
     const int64_t deg = (int64_t)off[v + 1] - b;
     if (deg <= 0) continue;
+    const bool split = !dense_rule || deg <= kSplitDegree;
     int32_t w[kMaxPreload];
     const int kk = k < kMaxPreload ? k : kMaxPreload;
     int got = 0;
@@ -363,7 +376,7 @@ __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict_
       w[j] = adj[b + idx];
       got = j + 1;
     }
-    for (int j = 0; j < got; ++j) forest_record(hook, union_rem<kSplitOne, kFindNaive>(P, (int32_t)v, w[j]), (int32_t)v, w[j]);
+    for (int j = 0; j < got; ++j) forest_record(hook, union_rem_opt_split(P, (int32_t)v, w[j], split), (int32_t)v, w[j]);
     for (int j = kMaxPreload; j < k; ++j) {
       int64_t idx;
       if (mode == CC_KOUT_AFFOREST) {
@@ -373,7 +386,7 @@ __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict_
         idx = (int64_t)(sm_out(key, (uint64_t)v * (uint64_t)k + (uint64_t)j) % (uint64_t)deg);
       }
       const int32_t w2 = adj[b + idx];
-      forest_record(hook, union_rem<kSplitOne, kFindNaive>(P, (int32_t)v, w2), (int32_t)v, w2);
+      forest_record(hook, union_rem_opt_split(P, (int32_t)v, w2, split), (int32_t)v, w2);
     }
   }
 }
@@ -1003,7 +1016,7 @@ static cc_status run_sample(StaticArgs& a) {
       // 0.47 ms; 256^3 grid: 1.00, 1.38, 1.07 ms)
       hipLaunchKernelGGL(k_kout<I>, dim3(xcd_grid(a.n, kBlock, kVertexGridCap)), dim3(kBlock), 0, a.s, a.n,
                          (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key, a.hook_e, (const int32_t*)pick0,
-                         a.count);
+                         a.count, (int)(a.n <= kDenseRuleMaxN && a.m >= 3 * a.n));
       CC_LAUNCH_CHECK();
       use_lmax = true;
       break;
