@@ -420,7 +420,10 @@ cc_status cc_stream_sync_status(cc_stream* s);
  *     its phase number (the state is n 64-bit words); a phase starts after
  *     the previous one completed.  A query runs once the inserts that arrived
  *     before it have completed and reads only links of those phases, so it
- *     overlaps the insert requests that arrive after it;
+ *     overlaps the insert requests that arrive after it.  Inserts shorten
+ *     paths (path splitting) only where no query in flight can tell: two
+ *     consecutive links of one phase, or of phases that no such query
+ *     separates;
  *   - any other variant (barrier mode): the server owns a cc_stream of that
  *     variant; consecutive requests of one type run concurrently and each
  *     change between inserts and queries is ordered by a barrier event.

@@ -95,9 +95,11 @@ __global__ void __launch_bounds__(kCalibBlock) k_edges_chunk(int64_t m, const I*
   if (e0 < len) {
     int32_t x[kCalibPer];
     if (VEC && e0 + kCalibPer <= len) {
-      const int4 a = *(const int4*)(adj + c0 + e0);
-      const int4 b = *(const int4*)(adj + c0 + e0 + 4);
-      x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w, x[4] = b.x, x[5] = b.y, x[6] = b.z, x[7] = b.w;
+#pragma unroll
+      for (int q = 0; q < kCalibPer / 4; ++q) {
+        const int4 a = *(const int4*)(adj + c0 + e0 + 4 * q);
+        x[4 * q] = a.x, x[4 * q + 1] = a.y, x[4 * q + 2] = a.z, x[4 * q + 3] = a.w;
+      }
     } else {
 #pragma unroll
       for (int j = 0; j < kCalibPer; ++j) x[j] = e0 + j < len ? adj[c0 + e0 + j] : 0;

@@ -117,6 +117,7 @@ struct Request {
   const int32_t* a = nullptr;   // caller's payload (valid until completion)
   const int32_t* b = nullptr;
   double* latency_out = nullptr;  // trace replay: where the latency goes
+  uint32_t phase = 0;             // stamped mode: the insert phases a query sees
 };
 
 // Completions kept for cc_server_request_info (the most recent ones).
@@ -142,6 +143,35 @@ __device__ __forceinline__ int32_t find_stamped(const uint64_t* W, int32_t x, ui
   }
 }
 
+// Root of x over every link, for inserts, with path splitting where no
+// query that can still run tells the difference.  A query of phase t
+// follows exactly the links stamped <= t, so replacing x -> p (stamp s1)
+// and p -> g (stamp s2) by x -> g stamped max(s1, s2) changes its answer
+// only if min(s1, s2) <= t < max(s1, s2).  [qlo, qhi] spans the phases of
+// the queries in flight when the insert was launched (qlo > qhi: none);
+// queries launched later wait for this insert and see every link it can
+// touch.  So x is re-linked when s1 == s2, or both stamps are <= qlo, or
+// both are > qhi.
+__device__ __forceinline__ int32_t find_stamped_split(uint64_t* W, int32_t x, uint32_t qlo, uint32_t qhi) {
+  while (true) {
+    const uint64_t w = ldw(W + x);
+    const int32_t p = (int32_t)(uint32_t)w;
+    if (p == x) return x;
+    const uint64_t wp = ldw(W + p);
+    const int32_t g = (int32_t)(uint32_t)wp;
+    if (g != p) {
+      const uint32_t s1 = (uint32_t)(w >> 32), s2 = (uint32_t)(wp >> 32);
+      const uint32_t lo = s1 < s2 ? s1 : s2, hi = s1 < s2 ? s2 : s1;
+      if (lo == hi || hi <= qlo || lo > qhi) {
+        uint64_t expect = w;
+        __hip_atomic_compare_exchange_strong(W + x, &expect, ((uint64_t)hi << 32) | (uint32_t)g, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    x = p;
+  }
+}
+
 __global__ void k_stamped_init(int64_t n, uint64_t* W) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) W[i] = (uint64_t)i;
@@ -150,7 +180,7 @@ __global__ void k_stamped_init(int64_t n, uint64_t* W) {
 // UF-Async: find both roots; CAS the larger root's word from "root" to a link
 // under the smaller one, stamped with the insert phase; retry on failure.
 __global__ void k_stamped_insert(int64_t k, const int32_t* __restrict__ u, const int32_t* __restrict__ v,
-                                 uint64_t* W, uint32_t stamp, int64_t n, uint32_t* err) {
+                                 uint64_t* W, uint32_t stamp, uint32_t qlo, uint32_t qhi, int64_t n, uint32_t* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool bad = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += stride) {
@@ -161,7 +191,7 @@ __global__ void k_stamped_insert(int64_t k, const int32_t* __restrict__ u, const
     }
     if (a == b) continue;
     while (true) {
-      int32_t ra = find_stamped(W, a, ~0u), rb = find_stamped(W, b, ~0u);
+      int32_t ra = find_stamped_split(W, a, qlo, qhi), rb = find_stamped_split(W, b, qlo, qhi);
       if (ra == rb) break;
       if (ra < rb) {
         const int32_t x = ra;
@@ -333,9 +363,18 @@ static cc_status launch(cc_server* s, Request* r) {
   cc_status st = CC_OK;
   if (s->stamped) {
     const unsigned g = grid_for(r->k, 256, 8192);
-    if (r->type == 0)
-      hipLaunchKernelGGL(k_stamped_insert, dim3(g), dim3(256), 0, hs, r->k, a, b, s->W, s->ins_phase, s->n, s->err);
-    else
+    r->phase = s->ins_phase;
+    if (r->type == 0) {
+      // the phases of the queries in flight bound which links may be split
+      uint32_t qlo = 0xffffffffu, qhi = 0;
+      for (const Request* q : s->inflight)
+        if (q->type == 1) {
+          qlo = q->phase < qlo ? q->phase : qlo;
+          qhi = q->phase > qhi ? q->phase : qhi;
+        }
+      hipLaunchKernelGGL(k_stamped_insert, dim3(g), dim3(256), 0, hs, r->k, a, b, s->W, s->ins_phase, qlo, qhi, s->n,
+                         s->err);
+    } else
       hipLaunchKernelGGL(k_stamped_query, dim3(g), dim3(256), 0, hs, r->k, a, b, out, (const uint64_t*)s->W,
                          s->ins_phase, s->n, s->err);
     CC_LAUNCH_CHECK();
