@@ -85,6 +85,50 @@ def choose_gate(times, n, picks, overhead_ms=SELECTOR_OVERHEAD_MS):
     return best[1], best[2]
 
 
+# Output bias given to a pruned arm: far above any predicted log-time
+# ratio, so the decision's argmin never lands on it (BF16 holds it as 9984).
+PRUNED_BIAS = 1.0e4
+
+
+def prune_arms(pred, times, clip=20.0):
+    """Backward elimination of arms on training rows: repeatedly drop the arm
+    whose removal most lowers the mean time of the model's pick (argmin of
+    pred over the arms kept), while some removal lowers it.  An arm that the
+    model over-rates (picked where it is rarely good) goes; an arm it picks
+    well stays.  Times are clipped at clip x the row's median so that one
+    disturbed measurement cannot decide.  Returns the boolean keep mask."""
+    pred = np.asarray(pred, np.float64)
+    T = np.asarray(times, np.float64)
+    T = np.minimum(T, clip * np.median(T, axis=1, keepdims=True))
+    rows = np.arange(T.shape[0])
+
+    def cost(keep):
+        return T[rows, np.where(keep[None, :], pred, np.inf).argmin(1)].mean()
+
+    keep = np.ones(T.shape[1], bool)
+    cur = cost(keep)
+    while keep.sum() > 2:
+        trials = []
+        for a in np.flatnonzero(keep):
+            k2 = keep.copy()
+            k2[a] = False
+            trials.append((cost(k2), a))
+        c, a = min(trials)
+        if c >= cur * (1.0 - 1e-4):
+            break
+        keep[a] = False
+        cur = c
+    return keep
+
+
+def apply_pruning(master, K, keep):
+    """Sets the output bias of every arm not kept to PRUNED_BIAS (the last K
+    entries of the FP32 master parameters are the output biases)."""
+    m = np.array(master, np.float32, copy=True)
+    m[len(m) - K:][~np.asarray(keep, bool)] = PRUNED_BIAS
+    return m
+
+
 def default_arm_index() -> int:
     return 4   # k-out + Rem-CAS/SplitAtomicOne/FindNaive: the paper's default
 
@@ -410,6 +454,10 @@ def main(argv=None):
         Y = targets(C["times"][train_mask])
         params, master, hist = train(ctx, Xn, Y, epochs=a.epochs, log=_log)
         K = Y.shape[1]
+        keep = prune_arms(predict(ctx, params, K, Xn), C["times"][train_mask])
+        master = apply_pruning(master, K, keep)
+        params = b.mlp_pack_bf16(torch.from_numpy(master).to(ctx.torch_device))
+        _log(f"arms kept: {np.flatnonzero(keep).tolist()}")
         picks_tr = predict(ctx, params, K, Xn).argmin(1)
         gate = choose_gate(C["times"][train_mask], C["n"][train_mask], picks_tr)
         _log(f"gate: graphs below {gate[0]} vertices run arm {gate[1]} without the model")
