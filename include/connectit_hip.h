@@ -204,6 +204,25 @@ cc_status cc_connectivity_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* off
                               const int32_t* adj, const cc_variant* v, void* workspace, size_t ws_bytes,
                               int32_t* labels_out, int64_t* num_components_dev, void* hip_stream);
 
+/* cc_connectivity_csr on a CSR whose vertices were renumbered (vertex x of
+ * the CSR is original vertex orig_of[x]; new_of is the inverse permutation;
+ * both device int32[n], e.g. from cc_build_csr_degree_order), with the
+ * result in the original numbering: labels_out[o] = the smallest original
+ * id in original vertex o's component (the canonical labelling of the
+ * original graph, Section 2).  The algorithm runs in the CSR's numbering
+ * (k-out's blocks in id order rather than by XCD range), then each
+ * component's smallest original id is found (one atomicMin per non-root
+ * vertex, aggregated per wave; the frequent component per block) and
+ * gathered to the original vertices.  orig_of and new_of must be inverse
+ * permutations of [0, n); they are not checked.  Workspace: device, >=
+ * cc_mapped_workspace_bytes (cc_workspace_bytes plus 4n bytes for the
+ * labels in the CSR's numbering). */
+cc_status cc_mapped_workspace_bytes(int64_t n, int64_t m, const cc_variant* v, size_t* bytes);
+cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                                     const int32_t* adj, const int32_t* orig_of, const int32_t* new_of,
+                                     const cc_variant* v, void* workspace, size_t ws_bytes, int32_t* labels_out,
+                                     int64_t* num_components_dev, void* hip_stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * call as cc_connectivity_csr, with the workspace taken from a fixed device
@@ -320,6 +339,23 @@ cc_status cc_csr_workspace_bytes(int64_t n, int64_t num_pairs, size_t* bytes);
 cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v, int dedup,
                        void* workspace, size_t ws_bytes, void* offsets_out, int offsets_64bit, int32_t* adj_out,
                        int64_t* m_dev, void* hip_stream);
+
+/* The same CSR with its vertices renumbered by decreasing degree (the
+ * degree of cc_build_csr's output, ties by smaller id; a degree above
+ * 2^b - 1, b = bits of n - 1, counts as 2^b - 1): vertex x of the output is
+ * original vertex orig_of[x], and new_of[o] is the new number of original
+ * vertex o (both device int32[n], written by the call).  A layout choice
+ * made at ingest: on power-law graphs the hubs' parent entries then share
+ * a few cache lines and the k-out picks of low-degree vertices land on them.
+ * Use the result with cc_connectivity_csr_mapped to get labels in the
+ * original numbering.  Ids outside [0, n) are reported as by cc_build_csr.
+ * Workspace: device, 256-byte aligned, >= cc_csr_degree_order_workspace_bytes.
+ * Synchronises hip_stream twice. */
+cc_status cc_csr_degree_order_workspace_bytes(int64_t n, int64_t num_pairs, size_t* bytes);
+cc_status cc_build_csr_degree_order(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v,
+                                    int dedup, void* workspace, size_t ws_bytes, void* offsets_out, int offsets_64bit,
+                                    int32_t* adj_out, int64_t* m_dev, int32_t* orig_of, int32_t* new_of,
+                                    void* hip_stream);
 
 /* ---- CSR validator (debug aid) ----------------------------------------------
  * The static calls trust their CSR: they index the parent array with

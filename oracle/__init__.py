@@ -346,6 +346,23 @@ def degree_features(offsets):
             8: skew, 14: float(m / n < 3), 15: np.log2(d.max() + 1)}
 
 
+def degree_order(n: int, offsets):
+    """The renumbering of the degree-ordered ingest (a layout choice, not a
+    step of the paper's method): original vertex ids sorted by decreasing
+    degree, ties by smaller id, where a degree above 2^b - 1 (b = the bits of
+    n - 1, at least 1) counts as 2^b - 1.  Returns orig_of (position ->
+    original id) and new_of (its inverse)."""
+    d = np.diff(np.asarray(offsets, np.int64))
+    bits = 1
+    while bits < 31 and (1 << bits) < n:
+        bits += 1
+    d = np.minimum(d, (1 << bits) - 1)
+    orig_of = np.lexsort((np.arange(n), -d)).astype(np.int32)
+    new_of = np.empty(n, np.int32)
+    new_of[orig_of] = np.arange(n, dtype=np.int32)
+    return orig_of, new_of
+
+
 def identify_frequent(labels_arr) -> int:
     """Most frequent label (Algorithm 1, IdentifyFrequent); ties go to the
     smallest label.  ``np.argmax`` returns the first maximum, i.e. the

@@ -145,6 +145,10 @@ def lib():
             "cc_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_variant), ctypes.POINTER(ctypes.c_size_t)]),
             "cc_connectivity_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
                                            ctypes.c_size_t, _vp, _vp, _vp]),
+            "cc_mapped_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_variant),
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+            "cc_connectivity_csr_mapped": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, _vp,
+                                                  ctypes.POINTER(cc_variant), _vp, ctypes.c_size_t, _vp, _vp, _vp]),
             "cc_noalloc_scratch_bytes": (ctypes.c_size_t, []),
             "cc_connectivity_csr_noalloc": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
                                                    _vp, _vp]),
@@ -167,6 +171,9 @@ def lib():
             "cc_csr_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
             "cc_build_csr": (_int, [_vp, _i64, _i64, _vp, _vp, _int, _vp, ctypes.c_size_t, _vp, _int, _vp, _vp,
                                     _vp]),
+            "cc_csr_degree_order_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+            "cc_build_csr_degree_order": (_int, [_vp, _i64, _i64, _vp, _vp, _int, _vp, ctypes.c_size_t, _vp, _int,
+                                                 _vp, _vp, _vp, _vp, _vp]),
             "cc_stream_create": (_int, [_vp, _i64, ctypes.POINTER(cc_variant), ctypes.POINTER(_vp)]),
             "cc_stream_destroy": (None, [_vp]),
             "cc_stream_init_csr": (_int, [_vp, _i64, _vp, _int, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -369,6 +376,66 @@ def build_csr(ctx: Context, n: int, u, v, dedup: bool = True, offsets_64bit: boo
     m = int(m_dev.item())
     del ws
     return CSR(n, offsets, adj[:m])
+
+
+class RenumberedCSR(CSR):
+    """A device CSR of the graph with its vertices renumbered by decreasing
+    degree (cc_build_csr_degree_order): orig_of[x] is the original id of
+    vertex x, new_of its inverse (both int32[n] on the device)."""
+
+    def __init__(self, n: int, offsets: torch.Tensor, adj: torch.Tensor, orig_of: torch.Tensor,
+                 new_of: torch.Tensor):
+        super().__init__(n, offsets, adj)
+        self.orig_of = orig_of
+        self.new_of = new_of
+
+
+def build_csr_degree_order(ctx: Context, n: int, u, v, dedup: bool = True, offsets_64bit: bool | None = None,
+                           stream=None) -> RenumberedCSR:
+    """cc_build_csr_degree_order: the CSR of the pair list with vertices
+    renumbered by decreasing degree (ties by id), and the permutation."""
+    dev = ctx.torch_device
+    ut = _dev_tensor(u, torch.int32, dev)
+    vt = _dev_tensor(v, torch.int32, dev)
+    k = int(ut.numel())
+    if offsets_64bit is None:
+        offsets_64bit = 2 * k > 0x7FFFFFFF
+    wsb = ctypes.c_size_t()
+    _check(lib().cc_csr_degree_order_workspace_bytes(n, k, ctypes.byref(wsb)), "cc_csr_degree_order_workspace_bytes")
+    ws = torch.empty(max(int(wsb.value), 256), dtype=torch.uint8, device=dev)
+    offsets = torch.empty(n + 1, dtype=torch.int64 if offsets_64bit else torch.int32, device=dev)
+    adj = torch.empty(max(2 * k, 1), dtype=torch.int32, device=dev)
+    m_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+    orig_of = torch.empty(n, dtype=torch.int32, device=dev)
+    new_of = torch.empty(n, dtype=torch.int32, device=dev)
+    _check(lib().cc_build_csr_degree_order(ctx.h, n, k, _ptr(ut), _ptr(vt), int(dedup), _ptr(ws), ws.numel(),
+                                           _ptr(offsets), int(offsets_64bit), _ptr(adj), _ptr(m_dev), _ptr(orig_of),
+                                           _ptr(new_of), _stream_handle(stream)),
+           "cc_build_csr_degree_order")
+    m = int(m_dev.item())
+    del ws
+    return RenumberedCSR(n, offsets, adj[:m], orig_of, new_of)
+
+
+def connectivity_csr_mapped(ctx: Context, g: RenumberedCSR, variant: cc_variant | None = None,
+                            labels: torch.Tensor | None = None, ncomp: torch.Tensor | None = None, stream=None):
+    """cc_connectivity_csr_mapped on a renumbered CSR: labels (int32[n], in
+    the original numbering: each vertex's smallest original id in its
+    component) and the component count."""
+    v = variant if variant is not None else default_variant()
+    dev = ctx.torch_device
+    if labels is None:
+        labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    if ncomp is None:
+        ncomp = torch.empty(1, dtype=torch.int64, device=dev)
+    b = ctypes.c_size_t()
+    _check(lib().cc_mapped_workspace_bytes(g.n, g.m, ctypes.byref(v), ctypes.byref(b)), "cc_mapped_workspace_bytes")
+    ws = ctx.workspace(int(b.value))
+    _check(lib().cc_connectivity_csr_mapped(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(g.orig_of),
+                                            _ptr(g.new_of), ctypes.byref(v), _ptr(ws), ws.numel(), _ptr(labels),
+                                            _ptr(ncomp), _stream_handle(stream)),
+           "cc_connectivity_csr_mapped")
+    return labels, ncomp
 
 
 def validate_csr(ctx: Context, g: CSR, check_symmetric: bool = True, stream=None):

@@ -231,16 +231,90 @@ __global__ void k_emit_csr(const unsigned long long* __restrict__ keys, const un
                            O* __restrict__ offsets, int32_t* __restrict__ adj, long long* m_user) {
   const int64_t m = (int64_t)*m_ptr;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= m; i += stride) {
-    const int64_t src = (i < m) ? (int64_t)(keys[i] >> 32) : n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
+    const int64_t src = (int64_t)(keys[i] >> 32);
     const int64_t prev = (i == 0) ? -1 : (int64_t)(keys[i - 1] >> 32);
     for (int64_t x = prev + 1; x <= src; ++x) offsets[x] = (O)i;
-    if (i < m) adj[i] = (int32_t)(uint32_t)(keys[i] & 0xffffffffull);
+    adj[i] = (int32_t)(uint32_t)(keys[i] & 0xffffffffull);
   }
+  // the rows after the last entry's row (all of them when m = 0), spread
+  // over the grid: with vertices in decreasing-degree order they are every
+  // isolated vertex
+  const int64_t last = m > 0 ? (int64_t)(keys[m - 1] >> 32) : -1;
+  for (int64_t x = last + 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x <= n; x += stride) offsets[x] = (O)m;
   if (blockIdx.x == 0 && threadIdx.x == 0 && m_user) *m_user = (long long)m;
 }
 
 __global__ void k_copy_u64(const unsigned long long* a, unsigned long long* b) { *b = *a; }
+
+// Bits of a vertex id in [0, n).
+static int id_bits(int64_t n) {
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < n) ++bits;
+  return bits;
+}
+
+// Stable LSD radix sort of `sorted` 64-bit keys on the low `bits` bits of
+// both 32-bit halves (low half first, so the order is by high half, then low
+// half); *src holds the result afterwards and *dst the other buffer.
+static void radix_sort(hipStream_t s, unsigned long long** src, unsigned long long** dst, int64_t sorted, int bits,
+                       uint32_t* hist, uint32_t* sums) {
+  std::vector<int> shifts;
+  for (int b = 0; b < bits; b += 8) shifts.push_back(b);
+  for (int b = 0; b < bits; b += 8) shifts.push_back(32 + b);
+  const int64_t tiles = div_up(sorted > 0 ? sorted : 1, kSortTile);
+  for (int sh : shifts) {
+    const int lowbit = sh >= 32 ? sh - 32 : sh;
+    const int width = (bits - lowbit) < 8 ? (bits - lowbit) : 8;
+    const uint32_t dmask = (1u << width) - 1u;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)tiles), dim3(kSortThreads), 0, s,
+                       (const unsigned long long*)*src, sorted, sh, dmask, hist, tiles);
+    exclusive_scan(s, hist, 256 * tiles, sums);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kSortThreads), 0, s,
+                       (const unsigned long long*)*src, *dst, sorted, sh, dmask, (const uint32_t*)hist, tiles);
+    unsigned long long* t = *src;
+    *src = *dst;
+    *dst = t;
+  }
+}
+
+// ---- degree order ----------------------------------------------------------------
+// Sort key of vertex x: (D - min(deg x, D)) in the high half, x in the low
+// half, D = 2^bits - 1; ascending keys = decreasing degree, then id.
+template <typename O>
+__global__ void k_degree_keys(int64_t n, const O* __restrict__ off, int bits, unsigned long long* __restrict__ keys) {
+  const int64_t D = ((int64_t)1 << bits) - 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += stride) {
+    int64_t d = (int64_t)off[x + 1] - (int64_t)off[x];
+    d = d < D ? d : D;
+    keys[x] = ((unsigned long long)(D - d) << 32) | (uint32_t)x;
+  }
+}
+
+// orig_of[i] = the vertex in sorted position i; new_of is its inverse.
+__global__ void k_order_maps(int64_t n, const unsigned long long* __restrict__ keys, int32_t* __restrict__ orig_of,
+                             int32_t* __restrict__ new_of) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int32_t x = (int32_t)(uint32_t)keys[i];
+    orig_of[i] = x;
+    new_of[x] = (int32_t)i;
+  }
+}
+
+// Pairs renumbered by new_of; ids outside [0, n) are kept as they are, so
+// the CSR build still reports them.
+__global__ void k_renumber_pairs(int64_t n, int64_t k, const int32_t* __restrict__ u, const int32_t* __restrict__ v,
+                                 const int32_t* __restrict__ new_of, int32_t* __restrict__ u2,
+                                 int32_t* __restrict__ v2) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += stride) {
+    const int32_t a = u[i], b = v[i];
+    u2[i] = (a >= 0 && (int64_t)a < n) ? new_of[a] : a;
+    v2[i] = (b >= 0 && (int64_t)b < n) ? new_of[b] : b;
+  }
+}
 
 struct CsrWs {
   size_t keys = 0, alt = 0, flags = 0, hist = 0, sums = 0, scal = 0, total = 0;
@@ -306,32 +380,13 @@ cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t*
   CC_HIP(hipMemcpyAsync(&E, scal, 8, hipMemcpyDeviceToHost, s));
   CC_HIP(hipStreamSynchronize(s));
 
-  int bits = 1;
-  while (bits < 31 && ((int64_t)1 << bits) < n) ++bits;
-  std::vector<int> shifts;
-  for (int b = 0; b < bits; b += 8) shifts.push_back(b);
-  for (int b = 0; b < bits; b += 8) shifts.push_back(32 + b);
+  const int bits = id_bits(n);
   const int64_t count = (int64_t)E;          // real keys; they sort ahead of the sentinels
   const int64_t sorted = 2 * num_pairs;       // keys the radix passes move
-  const int64_t tiles = div_up(sorted > 0 ? sorted : 1, kSortTile);
   unsigned long long* src = keys;
   unsigned long long* dst = alt;
-  if (count > 0) {
-    for (int sh : shifts) {
-      const int lowbit = sh >= 32 ? sh - 32 : sh;
-      const int width = (bits - lowbit) < 8 ? (bits - lowbit) : 8;
-      const uint32_t dmask = (1u << width) - 1u;
-      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)tiles), dim3(kSortThreads), 0, s,
-                         (const unsigned long long*)src, sorted, sh, dmask, hist, tiles);
-      exclusive_scan(s, hist, 256 * tiles, sums);
-      hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kSortThreads), 0, s,
-                         (const unsigned long long*)src, dst, sorted, sh, dmask, (const uint32_t*)hist, tiles);
-      CC_LAUNCH_CHECK();
-      unsigned long long* t = src;
-      src = dst;
-      dst = t;
-    }
-  }
+  if (count > 0) radix_sort(s, &src, &dst, sorted, bits, hist, sums);
+  CC_LAUNCH_CHECK();
   const unsigned long long* final_keys = src;
   if (count > 0 && dedup) {
     hipLaunchKernelGGL(k_dup_flags, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s,
@@ -351,6 +406,69 @@ cc_status cc_build_csr(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t*
                        (const unsigned long long*)(scal + 1), n, (int32_t*)offsets_out, adj_out, (long long*)m_dev);
   CC_LAUNCH_CHECK();
   return CC_OK;
+}
+
+// Workspace of cc_build_csr_degree_order: one CSR build's workspace sized
+// for max(num_pairs, ceil(n / 2)) pairs (its sort buffers also sort the n
+// vertex keys), then the renumbered pair list.
+static size_t degree_order_ws(int64_t n, int64_t num_pairs, size_t* csr_part) {
+  const int64_t big = num_pairs > (n + 1) / 2 ? num_pairs : (n + 1) / 2;
+  *csr_part = csr_ws(big).total;
+  return *csr_part + 2 * align256((size_t)(num_pairs > 0 ? num_pairs : 1) * 4);
+}
+
+cc_status cc_csr_degree_order_workspace_bytes(int64_t n, int64_t num_pairs, size_t* bytes) {
+  if (!bytes) return fail(CC_EINVAL, "bytes is NULL");
+  if (n < 1 || n > 0x7fffffffLL || num_pairs < 0) return fail(CC_EINVAL, "bad n or num_pairs");
+  if (2 * num_pairs >= 0xffffffffLL) return fail(CC_EINVAL, "more than 2^32-1 directed edges");
+  size_t part = 0;
+  *bytes = degree_order_ws(n, num_pairs, &part);
+  return CC_OK;
+}
+
+cc_status cc_build_csr_degree_order(cc_ctx* ctx, int64_t n, int64_t num_pairs, const int32_t* u, const int32_t* v,
+                                    int dedup, void* workspace, size_t ws_bytes, void* offsets_out, int offsets_64bit,
+                                    int32_t* adj_out, int64_t* m_dev, int32_t* orig_of, int32_t* new_of,
+                                    void* hip_stream) {
+  if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+  if (n < 1 || n > 0x7fffffffLL || num_pairs < 0) return fail(CC_EINVAL, "bad n or num_pairs");
+  if (!orig_of || !new_of) return fail(CC_EINVAL, "NULL permutation argument");
+  size_t part = 0;
+  const size_t need = degree_order_ws(n, num_pairs, &part);
+  if (!workspace || ws_bytes < need)
+    return fail(CC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+  if (((uintptr_t)workspace & 255u) != 0) return fail(CC_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)hip_stream;
+  // 1. the CSR in the given numbering, for the degrees
+  cc_status st = cc_build_csr(ctx, n, num_pairs, u, v, dedup, workspace, part, offsets_out, offsets_64bit, adj_out,
+                              m_dev, hip_stream);
+  if (st != CC_OK) return st;
+  // 2. vertices sorted by decreasing degree, then id (the build's sort buffers)
+  const int64_t big = num_pairs > (n + 1) / 2 ? num_pairs : (n + 1) / 2;
+  const CsrWs W = csr_ws(big);
+  char* w = (char*)workspace;
+  unsigned long long* src = (unsigned long long*)(w + W.keys);
+  unsigned long long* dst = (unsigned long long*)(w + W.alt);
+  const int bits = id_bits(n);
+  if (offsets_64bit)
+    hipLaunchKernelGGL(k_degree_keys<int64_t>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n,
+                       (const int64_t*)offsets_out, bits, src);
+  else
+    hipLaunchKernelGGL(k_degree_keys<int32_t>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n,
+                       (const int32_t*)offsets_out, bits, src);
+  radix_sort(s, &src, &dst, n, bits, (uint32_t*)(w + W.hist), (uint32_t*)(w + W.sums));
+  hipLaunchKernelGGL(k_order_maps, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n,
+                     (const unsigned long long*)src, orig_of, new_of);
+  CC_LAUNCH_CHECK();
+  if (num_pairs == 0) return CC_OK;  // no edges: every vertex has degree 0, the CSR is the same
+  // 3. the pairs renumbered, and the CSR built again from them
+  int32_t* u2 = (int32_t*)(w + part);
+  int32_t* v2 = (int32_t*)(w + part + align256((size_t)num_pairs * 4));
+  hipLaunchKernelGGL(k_renumber_pairs, dim3(grid_for(num_pairs, 256, 8192)), dim3(256), 0, s, n, num_pairs, u, v,
+                     (const int32_t*)new_of, u2, v2);
+  CC_LAUNCH_CHECK();
+  return cc_build_csr(ctx, n, num_pairs, u2, v2, dedup, workspace, part, offsets_out, offsets_64bit, adj_out, m_dev,
+                      hip_stream);
 }
 
 }  // extern "C"

@@ -28,6 +28,9 @@ struct StaticArgs {
   int2* hook_e = nullptr;    // spanning forest: union-find edge per hooked root (nullable)
   int64_t* ncomp_user = nullptr;
   bool skip_init = false;    // init (P = identity, counts and scalars cleared) already enqueued
+  bool kout_by_xcd = true;   // k-out: each XCD takes its own eighth of the ids (else blocks in id order)
+  const int32_t* map_orig = nullptr;  // renumbered CSR: original id of each vertex (output copies it to map_rmin)
+  int32_t* map_rmin = nullptr;
   int32_t sample_success = 1;
   int32_t sample_rounds = 0;
   int32_t finish_rounds = 0;

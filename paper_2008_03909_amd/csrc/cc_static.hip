@@ -349,9 +349,10 @@ template <typename I>
 __global__ void __launch_bounds__(kBlock) k_kout(int64_t n, const I* __restrict__ off, const int32_t* __restrict__ adj,
                                                  int32_t* P, int k, int mode, uint64_t key, int2* hook,
                                                  const int32_t* __restrict__ pick0, int32_t* __restrict__ count,
-                                                 int dense_rule) {
+                                                 int dense_rule, int by_xcd) {
   constexpr int kMaxPreload = 4;
-  const XcdSweep sw = xcd_sweep(n);
+  const XcdSweep sw = by_xcd ? xcd_sweep(n)
+                             : XcdSweep{(int64_t)blockIdx.x * blockDim.x, n, (int64_t)gridDim.x * blockDim.x};
   for (int64_t v = sw.base + threadIdx.x; v < sw.end; v += sw.step) {
     if (count) count[v] = 0;  // IdentifyFrequent's histogram, cleared here instead of by the init
     const int64_t b = (int64_t)off[v];
@@ -848,8 +849,11 @@ struct UnionOp {
 // Final compression and component count: label = root (the component's
 // minimum, since every link points to a smaller id).  Per-block root counts
 // go to part[].
+// With orig_of (a renumbered CSR), the sweep also copies orig_of into rmin,
+// the start of every root's minimum original id (see k_map_min).
 __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, long long* __restrict__ part,
-                                                   int aligned) {
+                                                   int aligned, const int32_t* __restrict__ orig_of,
+                                                   int32_t* __restrict__ rmin) {
   __shared__ long long red[kBlock / kWave];
   long long roots = 0;
   const int64_t groups = div_up_dev(n, 4);
@@ -859,6 +863,14 @@ __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, long l
     const bool vec = aligned && v0 + 3 < n;
     int32_t p[4], r[4];
     load4(P, v0, vec, n, p);
+    if (orig_of) {
+      if (vec) {
+        *(int4*)(rmin + v0) = *(const int4*)(orig_of + v0);
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (v0 + j < n) rmin[v0 + j] = orig_of[v0 + j];
+      }
+    }
     bool moved = false;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -888,6 +900,91 @@ __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, long l
     for (int w = 1; w < kBlock / kWave; ++w) roots += red[w];
     part[blockIdx.x] = roots;
   }
+}
+
+// ---- labels in the original numbering -----------------------------------
+// For a CSR whose vertices were renumbered (orig_of[x] = the original id of
+// vertex x, new_of its inverse), the labels come out in the new numbering
+// (each component's smallest new id); the caller wants each original vertex
+// labelled with its component's smallest original id.  rmin[r] collects
+// that minimum for every root r: it starts as the root's own original id
+// (copied by the output sweep), every other vertex adds its own with
+// atomicMin, and the vertices of the
+// frequent class's component (root P[lmax]; most of a power-law graph) fold
+// theirs into one partial per block instead, so that no address takes one
+// atomic per vertex.  A gather then labels the original vertices.
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const int32_t y = __shfl_xor(v, o, kWave);
+    v = y < v ? y : v;
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_map_min(int64_t n, const int32_t* __restrict__ P,
+                                                    const int32_t* __restrict__ orig_of, int32_t* rmin,
+                                                    const DevScalars* sc, int32_t* __restrict__ part) {
+  __shared__ int32_t red[kBlock / kWave];
+  const int32_t L = sc->lmax;
+  const int32_t Rg = L >= 0 ? P[L] : -1;
+  int32_t bmin = 0x7fffffff;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+    const int64_t x = base + threadIdx.x;
+    int32_t r = -1, o = 0x7fffffff;
+    if (x < n) {
+      r = P[x];
+      if (r != (int32_t)x) o = orig_of[x];
+    }
+    const bool giant = x < n && r != (int32_t)x && r == Rg;
+    if (giant) bmin = o < bmin ? o : bmin;
+    bool act = x < n && r != (int32_t)x && r != Rg;
+    // lanes with equal roots add one minimum per root and wave
+    uint64_t mask = __ballot(act);
+    while (mask) {
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      const int32_t lr = __shfl(r, leader, kWave);
+      const bool mine = act && r == lr;
+      const int32_t mn = wave_min_i32(mine ? o : 0x7fffffff);
+      if (lane_id() == leader) atomicMin(rmin + lr, mn);
+      mask &= ~__ballot(mine);
+      if (mine) act = false;
+    }
+  }
+  bmin = wave_min_i32(bmin);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = bmin;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) bmin = red[w] < bmin ? red[w] : bmin;
+    part[blockIdx.x] = bmin;
+  }
+}
+
+// One block: the frequent component's minimum from the block partials.
+__global__ void __launch_bounds__(kBlock) k_map_giant(const int32_t* __restrict__ P, const DevScalars* sc,
+                                                      const int32_t* __restrict__ part, int nparts, int32_t* rmin) {
+  __shared__ int32_t red[kBlock / kWave];
+  const int32_t L = sc->lmax;
+  if (L < 0) return;
+  int32_t m = 0x7fffffff;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) m = part[i] < m ? part[i] : m;
+  m = wave_min_i32(m);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) m = red[w] < m ? red[w] : m;
+    const int32_t Rg = P[L];
+    if (m < rmin[Rg]) rmin[Rg] = m;
+  }
+}
+
+// Each original vertex takes its root's minimum (one random read of P and
+// one of rmin per vertex: the gather is the map-back's floor, about the
+// cost of reading a random permutation).
+__global__ void k_map_gather(int64_t n, const int32_t* __restrict__ P, const int32_t* __restrict__ new_of,
+                             const int32_t* __restrict__ rmin, int32_t* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += stride) out[o] = rmin[P[new_of[o]]];
 }
 
 // Component count from the per-block root counts (one block).
@@ -1014,9 +1111,15 @@ static cc_status run_sample(StaticArgs& a) {
       // rows of different cost, and the unions of one XCD stay within its
       // range (R-MAT 2^24: grid-stride 0.53, one per thread 0.49, by XCD
       // 0.47 ms; 256^3 grid: 1.00, 1.38, 1.07 ms)
-      hipLaunchKernelGGL(k_kout<I>, dim3(xcd_grid(a.n, kBlock, kVertexGridCap)), dim3(kBlock), 0, a.s, a.n,
-                         (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key, a.hook_e, (const int32_t*)pick0,
-                         a.count, (int)(a.n <= kDenseRuleMaxN && a.m >= 3 * a.n));
+      // (A CSR renumbered by decreasing degree runs its blocks in id order
+      // instead: there the ranges would be unequal work, the hubs in the
+      // first and the isolated vertices in the last.)
+      hipLaunchKernelGGL(k_kout<I>,
+                         dim3(a.kout_by_xcd ? xcd_grid(a.n, kBlock, kVertexGridCap)
+                                            : grid_for(a.n, kBlock, kVertexGridCap)),
+                         dim3(kBlock), 0, a.s, a.n, (const I*)a.off, a.adj, a.P, v->kout_k, v->kout_mode, key,
+                         a.hook_e, (const int32_t*)pick0, a.count, (int)(a.n <= kDenseRuleMaxN && a.m >= 3 * a.n),
+                         (int)a.kout_by_xcd);
       CC_LAUNCH_CHECK();
       use_lmax = true;
       break;
@@ -1108,7 +1211,8 @@ cc_status output_labels(StaticArgs& a) {
   // per-block root counts in the compaction area (free once the finish ran)
   long long* part = (long long*)(a.ws + a.L.seg);
   const unsigned nb = grid4(a.n);
-  hipLaunchKernelGGL(k_output, dim3(nb), dim3(kBlock), 0, a.s, a.n, a.P, part, vec_ok(a));
+  const int vec = vec_ok(a) && (!a.map_orig || (al16(a.map_orig) && al16(a.map_rmin)));
+  hipLaunchKernelGGL(k_output, dim3(nb), dim3(kBlock), 0, a.s, a.n, a.P, part, vec, a.map_orig, a.map_rmin);
   hipLaunchKernelGGL(k_output_sum, dim3(1), dim3(kBlock), 0, a.s, (const long long*)part, (int)nb, a.ctx->dev,
                      (long long*)a.ncomp_user);
   CC_LAUNCH_CHECK();
@@ -1388,6 +1492,55 @@ cc_status cc_connectivity_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* off
                             num_components_dev, hip_stream);
   if (st != CC_OK) return st;
   st = a.o64 ? run_static<int64_t>(a, false) : run_static<int32_t>(a, false);
+  record_stats_host(a);
+  return st;
+}
+
+cc_status cc_mapped_workspace_bytes(int64_t n, int64_t m, const cc_variant* v, size_t* bytes) {
+  size_t base = 0;
+  cc_status st = cc_workspace_bytes(n, m, v, &base);
+  if (st != CC_OK) return st;
+  *bytes = base + align256((size_t)n * 4);  // the labels in the CSR's numbering
+  return CC_OK;
+}
+
+cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
+                                     const int32_t* adj, const int32_t* orig_of, const int32_t* new_of,
+                                     const cc_variant* v, void* workspace, size_t ws_bytes, int32_t* labels_out,
+                                     int64_t* num_components_dev, void* hip_stream) {
+  if (!orig_of || !new_of) return fail(CC_EINVAL, "NULL permutation argument");
+  size_t base = 0;
+  cc_status st = cc_workspace_bytes(n, m, v, &base);
+  if (st != CC_OK) return st;
+  if (!workspace || ws_bytes < base + align256((size_t)n * 4))
+    return fail(CC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                base + align256((size_t)n * 4));
+  if (!labels_out) return fail(CC_EINVAL, "labels_out is NULL");
+  int32_t* Pnew = (int32_t*)((char*)workspace + base);
+  StaticArgs a;
+  st = setup_args(a, ctx, n, m, offsets, offsets_are_64bit, adj, v, workspace, base, Pnew, num_components_dev,
+                  hip_stream);
+  if (st != CC_OK) return st;
+  a.kout_by_xcd = false;
+  // the count array is free once the finish has run: the output sweep
+  // starts each root's minimum original id there
+  int32_t* rmin = a.count;
+  a.map_orig = orig_of;
+  a.map_rmin = rmin;
+  st = a.o64 ? run_static<int64_t>(a, false) : run_static<int32_t>(a, false);
+  if (st == CC_OK) {
+    PhaseScope ps(a.ctx, a.s, "mapback");
+    // the compaction area is free once the labels are out
+    int32_t* part = (int32_t*)(a.ws + a.L.seg);
+    const unsigned g = grid_for(n, kBlock, 2048);
+    hipLaunchKernelGGL(k_map_min, dim3(g), dim3(kBlock), 0, a.s, n, (const int32_t*)Pnew, orig_of, rmin,
+                       (const DevScalars*)a.ctx->dev, part);
+    hipLaunchKernelGGL(k_map_giant, dim3(1), dim3(kBlock), 0, a.s, (const int32_t*)Pnew,
+                       (const DevScalars*)a.ctx->dev, (const int32_t*)part, (int)g, rmin);
+    hipLaunchKernelGGL(k_map_gather, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
+                       (const int32_t*)Pnew, new_of, (const int32_t*)rmin, labels_out);
+    CC_LAUNCH_CHECK();
+  }
   record_stats_host(a);
   return st;
 }

@@ -89,6 +89,25 @@ def test_rmat_2_24_every_variant(ctx, rmat24):
     rmat24.check(ctx, b.all_variants(extended=True) + _edge_choice_rows())
 
 
+def test_rmat_2_24_degree_ordered_mapped(ctx, rmat24):
+    """The degree-ordered CSR of the same pairs (as bench.py times it), every
+    variant of the main table and the edge-choice rows: labels in the
+    original numbering equal the oracle's."""
+    dev = ctx.torch_device
+    g = rmat24.g
+    d = b.build_csr_degree_order(ctx, g.n, torch.from_numpy(g.u).to(dev), torch.from_numpy(g.v).to(dev))
+    assert d.m == rmat24.csr.m
+    for v in b.all_variants() + _edge_choice_rows():
+        _note(f"{g} mapped {v.name()} kout_mode={v.kout_mode} k={v.kout_k}")
+        rmat24.labels.fill_(-1)
+        b.connectivity_csr_mapped(ctx, d, v, labels=rmat24.labels, ncomp=rmat24.ncomp)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        assert int(rmat24.ncomp.item()) == rmat24.wc, v.name()
+        assert torch.equal(rmat24.labels, rmat24.want_dev), v.name()
+    del d
+
+
 def test_grid_256_cubed_every_variant(ctx, grid):
     grid.check(ctx, [b.default_variant()] + b.all_variants(extended=True) + _edge_choice_rows())
 

@@ -107,6 +107,53 @@ def test_build_csr_flags_out_of_range_ids(ctx):
     assert np.array_equal(d.adj.cpu().numpy(), adj)
 
 
+@pytest.mark.parametrize("dedup", [True, False])
+@pytest.mark.parametrize("o64", [False, True])
+def test_build_csr_degree_order_matches_oracle(ctx, dedup, o64):
+    """The degree-ordered ingest: the permutation equals the oracle's degree
+    order of the CSR in the given numbering, and the CSR equals the oracle's
+    CSR of the renumbered pairs."""
+    for g in SUITE + [inputs.workload_er_2_16()]:
+        d = b.build_csr_degree_order(ctx, g.n, g.u, g.v, dedup=dedup, offsets_64bit=o64)
+        off0, _ = oracle.csr_build(g.n, g.u, g.v, dedup)
+        orig, new = oracle.degree_order(g.n, off0)
+        assert np.array_equal(d.orig_of.cpu().numpy(), orig), g
+        assert np.array_equal(d.new_of.cpu().numpy(), new), g
+        off, adj = oracle.csr_build(g.n, new[g.u], new[g.v], dedup)
+        assert np.array_equal(d.offsets.cpu().numpy().astype(np.int64), off), g
+        assert np.array_equal(d.adj.cpu().numpy(), adj), g
+
+
+@pytest.mark.parametrize("vi", range(0, 156, 5))
+def test_mapped_connectivity_on_the_suite(ctx, vi):
+    """Labels in the original numbering from a degree-ordered CSR equal the
+    oracle's labels of the original graph (every fifth variant of the 156:
+    each sampler and finish family is among them)."""
+    v = b.all_variants(extended=True)[vi]
+    for g in SUITE:
+        want, wc = oracle.labels(g)
+        d = b.build_csr_degree_order(ctx, g.n, g.u, g.v)
+        lab, nc = b.connectivity_csr_mapped(ctx, d, v)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        assert int(nc.item()) == wc, (v, g)
+        assert np.array_equal(lab.cpu().numpy(), want), (v, g)
+
+
+def test_mapped_connectivity_with_a_random_permutation(ctx):
+    """The mapped entry takes any permutation, not only the degree order."""
+    for g in SUITE[8:12]:
+        want, wc = oracle.labels(g)
+        perm = inputs.permutation(g.n, 11).astype(np.int32)      # new id of original vertex o
+        orig = np.empty(g.n, np.int32)
+        orig[perm] = np.arange(g.n, dtype=np.int32)
+        d0 = _csr(ctx, inputs.Graph(g.n, perm[g.u], perm[g.v]))
+        dev = ctx.torch_device
+        d = b.RenumberedCSR(g.n, d0.offsets, d0.adj, torch.from_numpy(orig).to(dev), torch.from_numpy(perm).to(dev))
+        lab, nc = b.connectivity_csr_mapped(ctx, d)
+        assert int(nc.item()) == wc and np.array_equal(lab.cpu().numpy(), want), g
+
+
 # ---- default variant and the full variant space ----------------------------------
 
 def test_default_variant_er_workload(ctx):

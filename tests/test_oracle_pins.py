@@ -768,3 +768,49 @@ def test_csr_validate_symmetry_mode_and_pairwise_definition():
         assert (r2["failed"] == 0) == want
         if any(len(x) > 1 for x in rows):
             assert r2["symmetry_checked"] == 2 and r2["rows_sorted"] == 0
+
+
+# ---- degree-ordered ingest (layout) -------------------------------------------
+
+def test_degree_order_hand_cases():
+    """Star: the centre first, then the leaves by id; path 0-1-2-3-4: the
+    interior vertices (degree 2) by id, then the ends; isolated vertices
+    last; equal degrees keep id order."""
+    off, _ = oracle.csr_build(6, np.array([3, 3, 3, 3, 3], np.int32), np.array([0, 1, 2, 4, 5], np.int32))
+    orig, new = oracle.degree_order(6, off)
+    assert orig.tolist() == [3, 0, 1, 2, 4, 5]
+    assert new.tolist() == [1, 2, 3, 0, 4, 5]
+    off, _ = oracle.csr_build(7, np.array([0, 1, 2, 3], np.int32), np.array([1, 2, 3, 4], np.int32))
+    orig, new = oracle.degree_order(7, off)
+    assert orig.tolist() == [1, 2, 3, 0, 4, 5, 6]
+    assert np.array_equal(new[orig], np.arange(7))
+
+
+def test_degree_order_is_a_sort_by_degree_then_id():
+    """On random graphs: a permutation, degrees non-increasing along it,
+    ids increasing within a degree; brute-force comparison with Python's
+    sorted on the (-degree, id) key."""
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 17, 300):
+        k = int(rng.integers(0, 4 * n + 1))
+        u = rng.integers(0, n, k).astype(np.int32)
+        v = rng.integers(0, n, k).astype(np.int32)
+        off, _ = oracle.csr_build(n, u, v)
+        deg = np.diff(np.asarray(off, np.int64))
+        orig, new = oracle.degree_order(n, off)
+        assert sorted(orig.tolist()) == list(range(n))
+        assert orig.tolist() == sorted(range(n), key=lambda x: (-int(deg[x]), x))
+        assert np.array_equal(new[orig], np.arange(n))
+
+
+def test_degree_order_caps_degrees_at_the_id_width():
+    """Without deduplication a degree can exceed n - 1; it counts as 2^b - 1
+    (b = bits of n - 1), so two such vertices tie and keep id order."""
+    n = 4   # b = 2, cap 3
+    u = np.array([1, 1, 1, 1, 1, 2, 2, 2, 2], np.int32)
+    v = np.array([0, 0, 0, 0, 3, 0, 0, 0, 3], np.int32)
+    off, _ = oracle.csr_build(n, u, v, False)
+    deg = np.diff(np.asarray(off, np.int64))
+    assert deg.tolist() == [7, 5, 4, 2]
+    orig, _ = oracle.degree_order(n, off)
+    assert orig.tolist() == [0, 1, 2, 3]   # 7, 5 and 4 all count as 3
