@@ -44,6 +44,7 @@ struct DevScalars {
   long long csr_first;
   unsigned long long csr_fp;
   int32_t fbin[2][4];      // label propagation: bin lengths of the frontier lists (double-buffered)
+  long long map_tail;      // renumbered CSR: first vertex from which every row is empty
 };
 
 enum : uint32_t { kErrBadId = 1u, kErrRoundCap = 2u, kErrBadCsr = 4u };

@@ -923,11 +923,13 @@ __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
 
 __global__ void __launch_bounds__(kBlock) k_map_min(int64_t n, const int32_t* __restrict__ P,
                                                     const int32_t* __restrict__ orig_of, int32_t* rmin,
-                                                    const DevScalars* sc, int32_t* __restrict__ part) {
+                                                    const DevScalars* sc, int32_t* __restrict__ part,
+                                                    uint32_t* __restrict__ in_giant) {
   __shared__ int32_t red[kBlock / kWave];
   const int32_t L = sc->lmax;
   const int32_t Rg = L >= 0 ? P[L] : -1;
   int32_t bmin = 0x7fffffff;
+  const int lane = lane_id();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
     const int64_t x = base + threadIdx.x;
@@ -936,6 +938,12 @@ __global__ void __launch_bounds__(kBlock) k_map_min(int64_t n, const int32_t* __
       r = P[x];
       if (r != (int32_t)x) o = orig_of[x];
     }
+    // membership of the frequent component, one bit per vertex (lanes 0 and
+    // 32 write the wave's two words)
+    const uint64_t gm = __ballot(x < n && r == Rg);
+    const int64_t w0 = (base + (threadIdx.x & ~(kWave - 1))) >> 5;
+    if (lane == 0 && (w0 << 5) < n) in_giant[w0] = (uint32_t)gm;
+    if (lane == 32 && ((w0 + 1) << 5) < n) in_giant[w0 + 1] = (uint32_t)(gm >> 32);
     const bool giant = x < n && r != (int32_t)x && r == Rg;
     if (giant) bmin = o < bmin ? o : bmin;
     bool act = x < n && r != (int32_t)x && r != Rg;
@@ -946,13 +954,13 @@ __global__ void __launch_bounds__(kBlock) k_map_min(int64_t n, const int32_t* __
       const int32_t lr = __shfl(r, leader, kWave);
       const bool mine = act && r == lr;
       const int32_t mn = wave_min_i32(mine ? o : 0x7fffffff);
-      if (lane_id() == leader) atomicMin(rmin + lr, mn);
+      if (lane == leader) atomicMin(rmin + lr, mn);
       mask &= ~__ballot(mine);
       if (mine) act = false;
     }
   }
   bmin = wave_min_i32(bmin);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = bmin;
+  if (lane == 0) red[threadIdx.x / kWave] = bmin;
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kBlock / kWave; ++w) bmin = red[w] < bmin ? red[w] : bmin;
@@ -960,10 +968,25 @@ __global__ void __launch_bounds__(kBlock) k_map_min(int64_t n, const int32_t* __
   }
 }
 
-// One block: the frequent component's minimum from the block partials.
-__global__ void __launch_bounds__(kBlock) k_map_giant(const int32_t* __restrict__ P, const DevScalars* sc,
+// One block: the frequent component's minimum from the block partials, and
+// the first vertex of the CSR's run of trailing empty rows (each of those
+// vertices is alone in its component; a CSR in decreasing-degree order keeps
+// every isolated vertex there).
+template <typename I>
+__global__ void __launch_bounds__(kBlock) k_map_giant(int64_t n, const I* __restrict__ off,
+                                                      const int32_t* __restrict__ P, DevScalars* sc,
                                                       const int32_t* __restrict__ part, int nparts, int32_t* rmin) {
   __shared__ int32_t red[kBlock / kWave];
+  if (threadIdx.x == 0) {
+    const I m = off[n];
+    int64_t lo = 0, hi = n;  // first x with off[x] == m (off[n] == m)
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (off[mid] == m) hi = mid;
+      else lo = mid + 1;
+    }
+    sc->map_tail = lo;
+  }
   const int32_t L = sc->lmax;
   if (L < 0) return;
   int32_t m = 0x7fffffff;
@@ -978,13 +1001,26 @@ __global__ void __launch_bounds__(kBlock) k_map_giant(const int32_t* __restrict_
   }
 }
 
-// Each original vertex takes its root's minimum (one random read of P and
-// one of rmin per vertex: the gather is the map-back's floor, about the
-// cost of reading a random permutation).
+// Original vertex o: its own id when its row lies in the empty tail, the
+// frequent component's minimum when its bit is set, else its root's minimum.
+// The bitmap (n/8 bytes) stays in cache, so only the vertices of the other
+// non-trivial components read the parent array, whose random reads cost
+// more once it outgrows the device's caches (R-MAT 2^27).
 __global__ void k_map_gather(int64_t n, const int32_t* __restrict__ P, const int32_t* __restrict__ new_of,
-                             const int32_t* __restrict__ rmin, int32_t* __restrict__ out) {
+                             const int32_t* __restrict__ rmin, const DevScalars* sc,
+                             const uint32_t* __restrict__ in_giant, int32_t* __restrict__ out) {
+  const int32_t L = sc->lmax;
+  const int32_t gmin = L >= 0 ? rmin[P[L]] : 0;
+  const int64_t tail = sc->map_tail;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += stride) out[o] = rmin[P[new_of[o]]];
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += stride) {
+    const int32_t x = new_of[o];
+    int32_t lab;
+    if (x >= tail) lab = (int32_t)o;
+    else if ((in_giant[x >> 5] >> (x & 31)) & 1u) lab = gmin;
+    else lab = rmin[P[x]];
+    out[o] = lab;
+  }
 }
 
 // Component count from the per-block root counts (one block).
@@ -1533,12 +1569,18 @@ cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t m, const vo
     // the compaction area is free once the labels are out
     int32_t* part = (int32_t*)(a.ws + a.L.seg);
     const unsigned g = grid_for(n, kBlock, 2048);
+    uint32_t* in_giant = (uint32_t*)(a.ws + a.L.bits);  // the bitmap area is free too
     hipLaunchKernelGGL(k_map_min, dim3(g), dim3(kBlock), 0, a.s, n, (const int32_t*)Pnew, orig_of, rmin,
-                       (const DevScalars*)a.ctx->dev, part);
-    hipLaunchKernelGGL(k_map_giant, dim3(1), dim3(kBlock), 0, a.s, (const int32_t*)Pnew,
-                       (const DevScalars*)a.ctx->dev, (const int32_t*)part, (int)g, rmin);
+                       (const DevScalars*)a.ctx->dev, part, in_giant);
+    if (a.o64)
+      hipLaunchKernelGGL(k_map_giant<int64_t>, dim3(1), dim3(kBlock), 0, a.s, n, (const int64_t*)offsets,
+                         (const int32_t*)Pnew, a.ctx->dev, (const int32_t*)part, (int)g, rmin);
+    else
+      hipLaunchKernelGGL(k_map_giant<int32_t>, dim3(1), dim3(kBlock), 0, a.s, n, (const int32_t*)offsets,
+                         (const int32_t*)Pnew, a.ctx->dev, (const int32_t*)part, (int)g, rmin);
     hipLaunchKernelGGL(k_map_gather, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
-                       (const int32_t*)Pnew, new_of, (const int32_t*)rmin, labels_out);
+                       (const int32_t*)Pnew, new_of, (const int32_t*)rmin, (const DevScalars*)a.ctx->dev,
+                       (const uint32_t*)in_giant, labels_out);
     CC_LAUNCH_CHECK();
   }
   record_stats_host(a);
