@@ -64,7 +64,7 @@ def phase_alg_bytes(phase: str, n: int, m: int, o: int, n_nz: int, st: dict, k: 
     if phase == "sample":
         return o * n + 4.0 * n + 16.0 * k * n_nz         # row bounds; count clear; k picks; k unions (2 reads + CAS)
     if phase == "mapback":
-        return 32.0 * n                                  # copy of orig_of, P + orig_of, new_of + P + rmin + labels
+        return 16.0 * n + 4.0 * comps                    # roots' original ids copied; P + non-roots' orig_of; new_of + labels
     if phase == "compress_count":
         return (4.0 + o) * n + 8.0 * n_nz                # P, degree; root read + count update
     if phase == "frequent":

@@ -849,8 +849,9 @@ struct UnionOp {
 // Final compression and component count: label = root (the component's
 // minimum, since every link points to a smaller id).  Per-block root counts
 // go to part[].
-// With orig_of (a renumbered CSR), the sweep also copies orig_of into rmin,
-// the start of every root's minimum original id (see k_map_min).
+// With orig_of (a renumbered CSR), the sweep also copies each root's
+// original id into rmin, the start of its minimum original id (see
+// k_map_min).
 __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, long long* __restrict__ part,
                                                    int aligned, const int32_t* __restrict__ orig_of,
                                                    int32_t* __restrict__ rmin) {
@@ -864,11 +865,15 @@ __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, long l
     int32_t p[4], r[4];
     load4(P, v0, vec, n, p);
     if (orig_of) {
+      // only a root's slot is ever read, so groups without one skip the copy
+      // (most of them, where the non-isolated vertices come first)
       if (vec) {
-        *(int4*)(rmin + v0) = *(const int4*)(orig_of + v0);
+        if (p[0] == (int32_t)v0 || p[1] == (int32_t)(v0 + 1) || p[2] == (int32_t)(v0 + 2) ||
+            p[3] == (int32_t)(v0 + 3))
+          *(int4*)(rmin + v0) = *(const int4*)(orig_of + v0);
       } else {
         for (int j = 0; j < 4; ++j)
-          if (v0 + j < n) rmin[v0 + j] = orig_of[v0 + j];
+          if (v0 + j < n && p[j] == (int32_t)(v0 + j)) rmin[v0 + j] = orig_of[v0 + j];
       }
     }
     bool moved = false;
@@ -912,7 +917,9 @@ __global__ void __launch_bounds__(kBlock) k_output(int64_t n, int32_t* P, long l
 // atomicMin, and the vertices of the
 // frequent class's component (root P[lmax]; most of a power-law graph) fold
 // theirs into one partial per block instead, so that no address takes one
-// atomic per vertex.  A gather then labels the original vertices.
+// atomic per vertex.  A gather then labels the original vertices from the
+// tail and the frequent component, and a pass over the frequent component's
+// bitmap corrects the rest.
 __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
   for (int o = 32; o > 0; o >>= 1) {
     const int32_t y = __shfl_xor(v, o, kWave);
@@ -924,39 +931,60 @@ __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
 __global__ void __launch_bounds__(kBlock) k_map_min(int64_t n, const int32_t* __restrict__ P,
                                                     const int32_t* __restrict__ orig_of, int32_t* rmin,
                                                     const DevScalars* sc, int32_t* __restrict__ part,
-                                                    uint32_t* __restrict__ in_giant) {
+                                                    uint32_t* __restrict__ in_giant, int aligned) {
   __shared__ int32_t red[kBlock / kWave];
   const int32_t L = sc->lmax;
   const int32_t Rg = L >= 0 ? P[L] : -1;
   int32_t bmin = 0x7fffffff;
   const int lane = lane_id();
+  const int64_t groups = div_up_dev(n, 4);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
-    const int64_t x = base + threadIdx.x;
-    int32_t r = -1, o = 0x7fffffff;
-    if (x < n) {
-      r = P[x];
-      if (r != (int32_t)x) o = orig_of[x];
+  // four consecutive vertices per lane, so a wave covers 256 vertices: eight
+  // bitmap words, word j of the wave holding the nibbles of lanes 8j .. 8j + 7
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < groups; base += stride) {
+    const int64_t g = base + threadIdx.x;
+    const int64_t v0 = 4 * g;
+    const bool vec = aligned && v0 + 3 < n;
+    int32_t r[4], o[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+    bool nonroot[4];
+    if (g < groups) {
+      load4(P, v0, vec, n, r);
+    } else {
+      r[0] = r[1] = r[2] = r[3] = -1;
     }
-    // membership of the frequent component, one bit per vertex (lanes 0 and
-    // 32 write the wave's two words)
-    const uint64_t gm = __ballot(x < n && r == Rg);
-    const int64_t w0 = (base + (threadIdx.x & ~(kWave - 1))) >> 5;
-    if (lane == 0 && (w0 << 5) < n) in_giant[w0] = (uint32_t)gm;
-    if (lane == 32 && ((w0 + 1) << 5) < n) in_giant[w0 + 1] = (uint32_t)(gm >> 32);
-    const bool giant = x < n && r != (int32_t)x && r == Rg;
-    if (giant) bmin = o < bmin ? o : bmin;
-    bool act = x < n && r != (int32_t)x && r != Rg;
-    // lanes with equal roots add one minimum per root and wave
-    uint64_t mask = __ballot(act);
-    while (mask) {
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      const int32_t lr = __shfl(r, leader, kWave);
-      const bool mine = act && r == lr;
-      const int32_t mn = wave_min_i32(mine ? o : 0x7fffffff);
-      if (lane == leader) atomicMin(rmin + lr, mn);
-      mask &= ~__ballot(mine);
-      if (mine) act = false;
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      nonroot[j] = v0 + j < n && r[j] != (int32_t)(v0 + j);
+      any |= nonroot[j];
+    }
+    if (any) load4(orig_of, v0, vec, n, o);
+    uint32_t word = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (v0 + j < n && r[j] == Rg) word |= 1u << (4 * (lane & 7) + j);
+      if (nonroot[j] && r[j] == Rg) bmin = o[j] < bmin ? o[j] : bmin;
+    }
+    word |= __shfl_xor(word, 1, kWave);
+    word |= __shfl_xor(word, 2, kWave);
+    word |= __shfl_xor(word, 4, kWave);
+    const int64_t w = (base + (threadIdx.x & ~(kWave - 1))) / 8 + (lane >> 3);
+    if ((lane & 7) == 0 && (w << 5) < n) in_giant[w] = word;
+    // the other components: lanes with equal roots add one minimum per root
+    // and wave
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bool act = nonroot[j] && r[j] != Rg;
+      uint64_t mask = __ballot(act);
+      while (mask) {
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        const int32_t lr = __shfl(r[j], leader, kWave);
+        const bool mine = act && r[j] == lr;
+        const int32_t mn = wave_min_i32(mine ? o[j] : 0x7fffffff);
+        if (lane == leader) atomicMin(rmin + lr, mn);
+        mask &= ~__ballot(mine);
+        if (mine) act = false;
+      }
     }
   }
   bmin = wave_min_i32(bmin);
@@ -1001,25 +1029,54 @@ __global__ void __launch_bounds__(kBlock) k_map_giant(int64_t n, const I* __rest
   }
 }
 
-// Original vertex o: its own id when its row lies in the empty tail, the
-// frequent component's minimum when its bit is set, else its root's minimum.
-// The bitmap (n/8 bytes) stays in cache, so only the vertices of the other
-// non-trivial components read the parent array, whose random reads cost
-// more once it outgrows the device's caches (R-MAT 2^27).
-__global__ void k_map_gather(int64_t n, const int32_t* __restrict__ P, const int32_t* __restrict__ new_of,
-                             const int32_t* __restrict__ rmin, const DevScalars* sc,
-                             const uint32_t* __restrict__ in_giant, int32_t* __restrict__ out) {
+// Original vertex o: its own id when its row lies in the trailing run of
+// empty rows, else the frequent component's minimum.  Sequential reads and
+// writes only; the vertices before the tail that are not in the frequent
+// component are corrected by k_map_fix afterwards.
+__global__ void __launch_bounds__(kBlock) k_map_gather(int64_t n, const int32_t* __restrict__ P,
+                                                       const int32_t* __restrict__ new_of,
+                                                       const int32_t* __restrict__ rmin, const DevScalars* sc,
+                                                       int32_t* __restrict__ out, int aligned) {
   const int32_t L = sc->lmax;
   const int32_t gmin = L >= 0 ? rmin[P[L]] : 0;
   const int64_t tail = sc->map_tail;
+  const int64_t groups = div_up_dev(n, 4);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += stride) {
-    const int32_t x = new_of[o];
-    int32_t lab;
-    if (x >= tail) lab = (int32_t)o;
-    else if ((in_giant[x >> 5] >> (x & 31)) & 1u) lab = gmin;
-    else lab = rmin[P[x]];
-    out[o] = lab;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups; g += stride) {
+    const int64_t o0 = 4 * g;
+    if (aligned && o0 + 3 < n) {
+      const int4 x = *(const int4*)(new_of + o0);
+      *(int4*)(out + o0) = make_int4(x.x >= tail ? (int32_t)o0 : gmin, x.y >= tail ? (int32_t)(o0 + 1) : gmin,
+                                     x.z >= tail ? (int32_t)(o0 + 2) : gmin, x.w >= tail ? (int32_t)(o0 + 3) : gmin);
+    } else {
+      for (int64_t o = o0; o < n && o < o0 + 4; ++o) out[o] = new_of[o] >= tail ? (int32_t)o : gmin;
+    }
+  }
+}
+
+// Vertices x before the tail whose bit is clear (not in the frequent
+// component, or an isolated vertex when the numbering leaves empty rows
+// before the tail): their original vertex takes its root's minimum, which
+// for an isolated root is its own original id.  One lane per bitmap word;
+// when almost every vertex with an edge is in the frequent component (R-MAT)
+// this touches a few thousand vertices, so the per-vertex random reads of
+// the parent array leave the gather.
+__global__ void __launch_bounds__(kBlock) k_map_fix(int64_t n, const int32_t* __restrict__ P,
+                                                    const int32_t* __restrict__ orig_of,
+                                                    const int32_t* __restrict__ rmin, const DevScalars* sc,
+                                                    const uint32_t* __restrict__ in_giant, int32_t* out) {
+  const int64_t tail = sc->map_tail < n ? sc->map_tail : n;
+  const int64_t words = (tail + 31) >> 5;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < words; w += stride) {
+    uint32_t need = ~in_giant[w];
+    const int64_t x0 = w << 5;
+    if (tail - x0 < 32) need &= (1u << (tail - x0)) - 1u;
+    while (need) {
+      const int64_t x = x0 + __builtin_ctz(need);
+      need &= need - 1u;
+      out[orig_of[x]] = rmin[P[x]];
+    }
   }
 }
 
@@ -1572,18 +1629,22 @@ cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t m, const vo
     PhaseScope ps(a.ctx, a.s, "mapback");
     // the compaction area is free once the labels are out
     int32_t* part = (int32_t*)(a.ws + a.L.seg);
-    const unsigned g = grid_for(n, kBlock, 2048);
+    const unsigned g = grid_for((n + 3) / 4, kBlock, 2048);
     uint32_t* in_giant = (uint32_t*)(a.ws + a.L.bits);  // the bitmap area is free too
+    const int aligned = (((uintptr_t)Pnew | (uintptr_t)orig_of | (uintptr_t)new_of | (uintptr_t)labels_out) & 15u) == 0;
     hipLaunchKernelGGL(k_map_min, dim3(g), dim3(kBlock), 0, a.s, n, (const int32_t*)Pnew, orig_of, rmin,
-                       (const DevScalars*)a.ctx->dev, part, in_giant);
+                       (const DevScalars*)a.ctx->dev, part, in_giant, aligned);
     if (a.o64)
       hipLaunchKernelGGL(k_map_giant<int64_t>, dim3(1), dim3(kBlock), 0, a.s, n, (const int64_t*)offsets,
                          (const int32_t*)Pnew, a.ctx->dev, (const int32_t*)part, (int)g, rmin);
     else
       hipLaunchKernelGGL(k_map_giant<int32_t>, dim3(1), dim3(kBlock), 0, a.s, n, (const int32_t*)offsets,
                          (const int32_t*)Pnew, a.ctx->dev, (const int32_t*)part, (int)g, rmin);
-    hipLaunchKernelGGL(k_map_gather, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
+    hipLaunchKernelGGL(k_map_gather, dim3(grid_for((n + 3) / 4, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
                        (const int32_t*)Pnew, new_of, (const int32_t*)rmin, (const DevScalars*)a.ctx->dev,
+                       labels_out, aligned);
+    hipLaunchKernelGGL(k_map_fix, dim3(grid_for((n + 31) / 32, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
+                       (const int32_t*)Pnew, orig_of, (const int32_t*)rmin, (const DevScalars*)a.ctx->dev,
                        (const uint32_t*)in_giant, labels_out);
     CC_LAUNCH_CHECK();
   }
