@@ -446,8 +446,9 @@ cc_status cc_stream_sync_status(cc_stream* s);
  * A cc_server owns a device union-find state for n vertices, a device request
  * pool of budget_bytes, num_streams HIP streams (1..16) and at most
  * max_inflight requests on the device.  Requests are admitted in arrival
- * order when their bytes (8 per pair, plus 1 per query pair) fit in the pool,
- * and every query answers against exactly the inserts that arrived before it
+ * order when a slot is free and, for requests that are copied (below), their
+ * bytes (8 per pair, plus 1 per query pair) fit in the pool; every query
+ * answers against exactly the inserts that arrived before it
  * (the batch-incremental semantics of the streaming appendix, arrival order =
  * batch order; Section 3.4).  Two modes:
  *   - v NULL or UF-Async with FindNaive (stamped mode, the type-1 setting of
@@ -466,11 +467,15 @@ cc_status cc_stream_sync_status(cc_stream* s);
  * The server's host state is bounded: completed requests are freed, HIP
  * events are reused, and cc_server_request_info keeps the outcome of the
  * 65,536 most recent completions (older ids return CC_EINVAL).  Single host
- * thread.  Zero copy: the server DMAs from the caller's host arrays and
- * writes query answers (0/1 bytes) straight into out, so every array must
- * stay valid and unmodified until its request completes (pinned memory,
- * e.g. hipHostMalloc, makes the transfers asynchronous).  A request larger
- * than the budget returns CC_EBUSY.  Ids outside [0, n) set the state's
+ * thread.  Payloads: when a request's arrays (and out, for a query) are
+ * host memory mapped into the device's address space (pinned, e.g.
+ * hipHostMalloc or a pinned torch tensor; checked with
+ * hipPointerGetAttributes over each whole range), the kernels read the pairs
+ * and write the 0/1 answers in place and the request takes no pool bytes;
+ * otherwise the server copies the pairs into the pool on a copy stream of its
+ * own and copies the answers back.  Either way every array must stay valid
+ * and unmodified until its request completes.  A copied request larger than
+ * the budget returns CC_EBUSY.  Ids outside [0, n) set the state's
  * error word (reported by cc_server_poll with wait_all) and are skipped
  * (queries answer 0).  Times are seconds on the server's steady clock
  * (cc_server_clock); arrival < 0 means "now". */

@@ -35,8 +35,9 @@
 //
 // Host side: zero copy -- request payloads are DMA'd straight from the
 // caller's buffers (which must stay valid until the request completes; pinned
-// memory makes the copies asynchronous) and query answers land directly in
-// the caller's output buffer.  Device side: a first-fit pool of the budget.
+// memory makes the copies asynchronous) on a copy stream of their own that
+// no phase barrier holds up, and query answers land directly in the caller's
+// output buffer.  Device side: a first-fit pool of the budget.
 // Latency = completion (observed by polling the request's event) minus
 // arrival, on the host's steady clock.
 #include <algorithm>
@@ -112,11 +113,18 @@ struct Request {
   double arrival = 0.0;   // seconds on the server clock
   size_t bytes = 0, off = 0;
   int stream = -1;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev = nullptr;       // completion, on the request's stream
+  hipEvent_t ev_copy = nullptr;  // payload on the device, on the copy stream
   uint8_t* out_host = nullptr;  // caller's result buffer (queries)
   const int32_t* a = nullptr;   // caller's payload (valid until completion)
   const int32_t* b = nullptr;
   double* latency_out = nullptr;  // trace replay: where the latency goes
+  // mapped host memory: the kernels read the payload and write the answers
+  // in place through these device addresses (no pool bytes, no copies)
+  bool in_place = false;
+  const int32_t* da = nullptr;
+  const int32_t* db = nullptr;
+  uint8_t* dout = nullptr;
   uint32_t phase = 0;             // stamped mode: the insert phases a query sees
 };
 
@@ -263,6 +271,7 @@ struct cc_server {
   cc::RangePool pool;
   std::vector<hipStream_t> streams;
   std::vector<int> stream_busy;  // requests in flight per stream
+  hipStream_t copy_stream = nullptr;     // payload copies, in admission order
   hipStream_t barrier_stream = nullptr;
   std::vector<hipEvent_t> events_all;   // every event created; destroyed with the server
   std::vector<hipEvent_t> events_free;  // recycled, ready for a new record
@@ -354,12 +363,24 @@ static cc_status launch(cc_server* s, Request* r) {
     if (st != CC_OK) return st;
   }
   s->last_type = r->type;
-  CC_HIP(hipMemcpyAsync(d, r->a, half, hipMemcpyHostToDevice, hs));
-  CC_HIP(hipMemcpyAsync(d + half, r->b, half, hipMemcpyHostToDevice, hs));
+  const int32_t* a = r->da;
+  const int32_t* b = r->db;
+  uint8_t* out = r->dout;
+  if (!r->in_place) {
+    // The payload goes over on the copy stream, which never waits for a
+    // phase, so copies keep the link busy while earlier phases compute; the
+    // request's stream waits for its copy and for the barrier.
+    CC_HIP(hipMemcpyAsync(d, r->a, half, hipMemcpyHostToDevice, s->copy_stream));
+    CC_HIP(hipMemcpyAsync(d + half, r->b, half, hipMemcpyHostToDevice, s->copy_stream));
+    r->ev_copy = take_event(s);
+    if (!r->ev_copy) return fail(CC_EDEVICE, "cannot create an event");
+    CC_HIP(hipEventRecord(r->ev_copy, s->copy_stream));
+    CC_HIP(hipStreamWaitEvent(hs, r->ev_copy, 0));
+    a = (const int32_t*)d;
+    b = (const int32_t*)(d + half);
+    out = (uint8_t*)(d + pair_bytes);
+  }
   if (s->barrier) CC_HIP(hipStreamWaitEvent(hs, s->barrier, 0));
-  const int32_t* a = (const int32_t*)d;
-  const int32_t* b = (const int32_t*)(d + half);
-  uint8_t* out = (uint8_t*)(d + pair_bytes);
   cc_status st = CC_OK;
   if (s->stamped) {
     const unsigned g = grid_for(r->k, 256, 8192);
@@ -384,7 +405,8 @@ static cc_status launch(cc_server* s, Request* r) {
     st = cc_query_batch(s->st, r->k, a, b, out, hs);
   }
   if (st != CC_OK) return st;
-  if (r->type == 1) CC_HIP(hipMemcpyAsync(r->out_host, out, (size_t)r->k, hipMemcpyDeviceToHost, hs));
+  if (r->type == 1 && !r->in_place)
+    CC_HIP(hipMemcpyAsync(r->out_host, out, (size_t)r->k, hipMemcpyDeviceToHost, hs));
   r->ev = take_event(s);
   if (!r->ev) return fail(CC_EDEVICE, "cannot create an event");
   CC_HIP(hipEventRecord(r->ev, hs));
@@ -397,7 +419,7 @@ static cc_status launch(cc_server* s, Request* r) {
 // latency is recorded, and it is freed.
 static void retire(cc_server* s, Request* r, double now) {
   const double lat = now - r->arrival;
-  s->pool.release(r->off, r->bytes);
+  if (!r->in_place) s->pool.release(r->off, r->bytes);
   s->stream_busy[r->stream]--;
   auto it = std::find(s->phase_open.begin(), s->phase_open.end(), r);
   if (it != s->phase_open.end()) {
@@ -405,6 +427,7 @@ static void retire(cc_server* s, Request* r, double now) {
     s->phase_open.pop_back();
   }
   s->events_free.push_back(r->ev);
+  if (r->ev_copy) s->events_free.push_back(r->ev_copy);  // complete: the request's stream waited for it
   if (r->latency_out) *r->latency_out = lat;
   Done& d = s->done_ring[(size_t)(r->id % kInfoRing)];
   d.id = r->id;
@@ -460,6 +483,7 @@ cc_status cc_server_create(cc_ctx* ctx, int64_t n, const cc_variant* v, int64_t 
   s->streams.assign(num_streams, nullptr);
   s->stream_busy.assign(num_streams, 0);
   for (auto& x : s->streams) CC_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+  CC_HIP(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking));
   CC_HIP(hipStreamCreateWithFlags(&s->barrier_stream, hipStreamNonBlocking));
   if (s->stamped) {
     hipLaunchKernelGGL(k_stamped_init, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s->barrier_stream, n, s->W);
@@ -478,6 +502,7 @@ void cc_server_destroy(cc_server* s) {
   for (auto* r : s->inflight) delete r;
   for (auto e : s->events_all) (void)hipEventDestroy(e);
   for (auto x : s->streams) (void)hipStreamDestroy(x);
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   if (s->barrier_stream) (void)hipStreamDestroy(s->barrier_stream);
   if (s->dpool) (void)hipFree(s->dpool);
   if (s->W) (void)hipFree(s->W);
@@ -496,12 +521,38 @@ int64_t cc_server_event_count(const cc_server* s) { return s ? (int64_t)s->event
 
 namespace cc {
 
+// Device address of a host range the GPU can read and write in place (host
+// memory pinned and mapped into the device's address space, such as
+// hipHostMalloc's), or nullptr.  Both ends of the range must map to the same
+// allocation at the same distance, so the kernels never reach past it.
+static void* mapped_host(const void* p, size_t bytes) {
+  hipPointerAttribute_t a0{}, a1{};
+  if (hipPointerGetAttributes(&a0, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (a0.type != hipMemoryTypeHost || !a0.devicePointer) return nullptr;
+  const char* last = (const char*)p + bytes - 1;
+  if (hipPointerGetAttributes(&a1, last) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (a1.type != hipMemoryTypeHost || !a1.devicePointer ||
+      (const char*)a1.devicePointer - (const char*)a0.devicePointer != (ptrdiff_t)(bytes - 1))
+    return nullptr;
+  return a0.devicePointer;
+}
+
 static cc_status submit(cc_server* s, int type, int64_t k, const int32_t* a, const int32_t* b, uint8_t* out,
                         double arrival, int64_t* id, double* latency_out = nullptr) {
   if (!s) return fail(CC_EINVAL, "server is NULL");
   if (k < 1) return fail(CC_EINVAL, "a request needs at least one pair");
   if (!a || !b || (type == 1 && !out)) return fail(CC_EINVAL, "NULL array");
-  const size_t bytes = (size_t)k * 8 + (type == 1 ? (size_t)k : 0);
+  const int32_t* da = (const int32_t*)mapped_host(a, (size_t)k * 4);
+  const int32_t* db = da ? (const int32_t*)mapped_host(b, (size_t)k * 4) : nullptr;
+  uint8_t* dout = (db && type == 1) ? (uint8_t*)mapped_host(out, (size_t)k) : nullptr;
+  const bool in_place = db && (type == 0 || dout);
+  const size_t bytes = in_place ? 0 : (size_t)k * 8 + (type == 1 ? (size_t)k : 0);
   if (align256(bytes) > s->budget)
     return fail(CC_EBUSY, "request of %zu bytes can never fit the %zu-byte budget", bytes, s->budget);
   Request* r = new Request();
@@ -514,6 +565,10 @@ static cc_status submit(cc_server* s, int type, int64_t k, const int32_t* a, con
   r->a = a;
   r->b = b;
   r->latency_out = latency_out;
+  r->in_place = in_place;
+  r->da = da;
+  r->db = db;
+  r->dout = dout;
   s->live[r->id] = r;
   s->pending.push_back(r);
   if (id) *id = r->id;
@@ -540,7 +595,7 @@ static cc_status progress_staged(cc_server* s) {
   while (!s->pending.empty() && (int)s->inflight.size() < s->max_inflight) {
     Request* r = s->pending.front();
     size_t off = 0;
-    if (!s->pool.alloc(r->bytes, &off)) break;
+    if (!r->in_place && !s->pool.alloc(r->bytes, &off)) break;
     r->off = off;
     s->pending.pop_front();
     cc_status st = launch(s, r);

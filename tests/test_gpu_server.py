@@ -93,16 +93,33 @@ def test_server_submit_matches_alone(ctx, streams, budget, variant):
     srv.close()
 
 
-@pytest.mark.parametrize("variant", [None, BARRIER_VARIANT])
-def test_server_trace_in_the_mix_equals_alone(ctx, variant):
+def _pinned(x):
+    """A numpy view of a pinned (device-mapped) host copy of x."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x)).pin_memory()
+    return t.numpy(), t
+
+
+@pytest.mark.parametrize("variant,pinned", [(None, False), (BARRIER_VARIANT, False), (None, True),
+                                            (BARRIER_VARIANT, True)])
+def test_server_trace_in_the_mix_equals_alone(ctx, variant, pinned):
     """Poisson arrivals fast enough that requests overlap on the device (in
-    stamped mode queries also overlap the inserts that arrive after them)."""
+    stamped mode queries also overlap the inserts that arrive after them).
+    Pageable payloads are copied through the pool; pinned ones are read and
+    answered in place by the kernels."""
     n = 1 << 16
     types, starts, lens, A, B = _trace(n, 300, seed=7, max_insert=200000, max_query=50000)
     rng = np.random.default_rng(3)
     arrivals = np.cumsum(rng.exponential(20e-6, types.size))
-    srv = b.Server(ctx, n, variant=variant, budget_bytes=1 << 26, num_streams=4, max_inflight=16)
-    got, lat = srv.run_trace(types, arrivals, starts, lens, A, B)
+    # in place, requests need no pool: a 64 KiB budget would refuse most of
+    # them as copies (up to 200,000 pairs, 1.6 MB)
+    srv = b.Server(ctx, n, variant=variant, budget_bytes=(1 << 16) if pinned else (1 << 26), num_streams=2,
+                   max_inflight=16)
+    if pinned:
+        (pa, ta), (pb, tb), (po, to) = _pinned(A), _pinned(B), _pinned(np.zeros(A.size, np.uint8))
+        got, lat = srv.run_trace(types, arrivals, starts, lens, pa, pb, po)
+    else:
+        got, lat = srv.run_trace(types, arrivals, starts, lens, A, B)
     want = _alone(n, types, starts, lens, A, B)
     q = np.zeros(A.size, bool)
     for t, s, k in zip(types, starts, lens):
@@ -148,7 +165,9 @@ def test_server_state_stays_bounded_and_answers_stay_exact(ctx):
             q[s0:s0 + k] = True
     assert np.array_equal(got[q], want[q])
     assert np.all(lat > 0)
-    assert srv.event_count() <= 2 * 8 + 8, srv.event_count()
+    # two per request in flight (completion, payload copy) and the barriers
+    # of the phases those requests belong to
+    assert srv.event_count() <= 3 * 8 + 1, srv.event_count()
     rid = srv.insert(np.array([1], np.int32), np.array([2], np.int32))
     srv.poll(wait_all=True)
     done, l1 = srv.info(rid)
