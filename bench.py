@@ -50,31 +50,36 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def phase_alg_bytes(phase: str, n: int, m: int, o: int, n_nz: int, st: dict, k: int = 2, counts_in_init: bool = False) -> float:
+def phase_alg_bytes(phase: str, n: int, m: int, o: int, n_nz: int, st: dict, k: int = 2, counts_in_init: bool = False,
+                    na: int | None = None) -> float:
     """Algorithmic bytes of one launch of a phase of the default variant.
 
     n_nz = vertices with at least one edge; n_f / m_f = candidate vertices /
     their adjacency entries; every random 4-byte access counts 4 bytes.
-    With k-out sampling the sampling kernel also clears the frequency
-    counts, which the init then leaves alone (BFS and LDD leave them to the
-    init; no sampling needs none)."""
+    na = the vertices the per-vertex phases sweep (a renumbered CSR whose
+    rows from na on are empty runs the algorithm on [0, na) only; n
+    otherwise).  With k-out sampling the sampling kernel also clears the
+    frequency counts, which the init then leaves alone (BFS and LDD leave
+    them to the init; no sampling needs none)."""
     n_f, m_f, comps = st["candidates"], st["candidate_edges"], st["num_components"]
+    na = n if na is None else na
+    ca = comps - (n - na)                                # components among the swept vertices
     if phase == "init":
-        return 8.0 * n if counts_in_init else 4.0 * n   # P (and count) writes
+        return 4.0 * n + (4.0 * na if counts_in_init else 0.0)   # P (and count) writes
     if phase == "sample":
-        return o * n + 4.0 * n + 16.0 * k * n_nz         # row bounds; count clear; k picks; k unions (2 reads + CAS)
+        return o * na + 4.0 * na + 16.0 * k * n_nz       # row bounds; count clear; k picks; k unions (2 reads + CAS)
     if phase == "mapback":
-        return 16.0 * n + 4.0 * comps                    # roots' original ids copied; P + non-roots' orig_of; new_of + labels
+        return 8.0 * n + 8.0 * na + 4.0 * ca             # roots' original ids copied; P + non-roots' orig_of; new_of + labels
     if phase == "compress_count":
-        return (4.0 + o) * n + 8.0 * n_nz                # P, degree; root read + count update
+        return (4.0 + o) * na + 8.0 * n_nz               # P, degree; root read + count update
     if phase == "frequent":
-        return 4.0 * n
+        return 4.0 * na
     if phase == "compact":
-        return (4.0 + o) * n + 4.0 * n_f
+        return (4.0 + o) * na + 4.0 * n_f
     if phase == "finish":
         return 2.0 * o * n_f + 12.0 * m_f                # row bounds; adjacency + 2 parent reads per edge
     if phase == "output":
-        return 4.0 * n + 8.0 * (n - comps)               # P read; root read + write for non-roots
+        return 4.0 * na + 8.0 * (na - ca)                # P read; root read + write for non-roots
     return 0.0
 
 
@@ -646,7 +651,8 @@ def main():
     for name, (ms, cnt) in phases.items():
         avg = ms / max(cnt, 1)
         ab = phase_alg_bytes(name, n, m, o, n_nz, st, k=v.kout_k,
-                             counts_in_init=v.sample in (b.SAMPLE_BFS, b.SAMPLE_LDD))
+                             counts_in_init=v.sample in (b.SAMPLE_BFS, b.SAMPLE_LDD),
+                             na=rcsr.n_active if rcsr is not None else n)
         alg_total += ab * cnt / args.steps
         ph_out[name] = {"avg_ms": round(avg, 4), "launches": cnt, "alg_bytes": ab,
                         "alg_gbs": round(ab / (avg / 1e3) / 1e9, 1) if avg > 0 else None}

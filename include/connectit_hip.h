@@ -213,15 +213,29 @@ cc_status cc_connectivity_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* off
  * (k-out's blocks in id order rather than by XCD range), then each
  * component's smallest original id is found (one atomicMin per non-root
  * vertex, aggregated per wave; the frequent component per block) and
- * gathered to the original vertices.  orig_of and new_of must be inverse
+ * gathered to the original vertices.  n_active (0..n): the caller's promise
+ * that rows n_active .. n-1 are empty (a CSR in decreasing-degree order
+ * keeps every isolated vertex there; cc_csr_active_prefix finds the
+ * smallest such value; pass n when unknown).  The algorithm then runs on
+ * vertices [0, n_active) only, every other vertex being a component of its
+ * own; all n labels and the count cover the whole graph.  A broken promise
+ * (a non-empty row at or after n_active) sets the bad-CSR bit of the
+ * context's error word, and its labels are then not defined; adjacency ids
+ * below n stay safe to read.  orig_of and new_of must be inverse
  * permutations of [0, n); they are not checked.  Workspace: device, >=
  * cc_mapped_workspace_bytes (cc_workspace_bytes plus 4n bytes for the
  * labels in the CSR's numbering). */
 cc_status cc_mapped_workspace_bytes(int64_t n, int64_t m, const cc_variant* v, size_t* bytes);
-cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
-                                     const int32_t* adj, const int32_t* orig_of, const int32_t* new_of,
-                                     const cc_variant* v, void* workspace, size_t ws_bytes, int32_t* labels_out,
-                                     int64_t* num_components_dev, void* hip_stream);
+cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t n_active, int64_t m, const void* offsets,
+                                     int offsets_are_64bit, const int32_t* adj, const int32_t* orig_of,
+                                     const int32_t* new_of, const cc_variant* v, void* workspace, size_t ws_bytes,
+                                     int32_t* labels_out, int64_t* num_components_dev, void* hip_stream);
+/* *active_dev (device int64) = the smallest x such that rows x .. n-1 of
+ * the CSR are all empty (offsets ascending; one lane's binary search on
+ * hip_stream).  For a CSR from cc_build_csr_degree_order this is the number
+ * of vertices with at least one adjacency entry. */
+cc_status cc_csr_active_prefix(int64_t n, const void* offsets, int offsets_are_64bit, int64_t* active_dev,
+                               void* hip_stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -147,8 +147,9 @@ def lib():
                                            ctypes.c_size_t, _vp, _vp, _vp]),
             "cc_mapped_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_variant),
                                                  ctypes.POINTER(ctypes.c_size_t)]),
-            "cc_connectivity_csr_mapped": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, _vp,
+            "cc_connectivity_csr_mapped": (_int, [_vp, _i64, _i64, _i64, _vp, _int, _vp, _vp, _vp,
                                                   ctypes.POINTER(cc_variant), _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+            "cc_csr_active_prefix": (_int, [_i64, _vp, _int, _vp, _vp]),
             "cc_noalloc_scratch_bytes": (ctypes.c_size_t, []),
             "cc_connectivity_csr_noalloc": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
                                                    _vp, _vp]),
@@ -381,13 +382,15 @@ def build_csr(ctx: Context, n: int, u, v, dedup: bool = True, offsets_64bit: boo
 class RenumberedCSR(CSR):
     """A device CSR of the graph with its vertices renumbered by decreasing
     degree (cc_build_csr_degree_order): orig_of[x] is the original id of
-    vertex x, new_of its inverse (both int32[n] on the device)."""
+    vertex x, new_of its inverse (both int32[n] on the device).  n_active:
+    rows n_active .. n-1 are empty (n when unknown)."""
 
     def __init__(self, n: int, offsets: torch.Tensor, adj: torch.Tensor, orig_of: torch.Tensor,
-                 new_of: torch.Tensor):
+                 new_of: torch.Tensor, n_active: int | None = None):
         super().__init__(n, offsets, adj)
         self.orig_of = orig_of
         self.new_of = new_of
+        self.n_active = n if n_active is None else int(n_active)
 
 
 def build_csr_degree_order(ctx: Context, n: int, u, v, dedup: bool = True, offsets_64bit: bool | None = None,
@@ -414,7 +417,18 @@ def build_csr_degree_order(ctx: Context, n: int, u, v, dedup: bool = True, offse
            "cc_build_csr_degree_order")
     m = int(m_dev.item())
     del ws
-    return RenumberedCSR(n, offsets, adj[:m], orig_of, new_of)
+    act = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib().cc_csr_active_prefix(n, _ptr(offsets), int(offsets_64bit), _ptr(act), _stream_handle(stream)),
+           "cc_csr_active_prefix")
+    return RenumberedCSR(n, offsets, adj[:m], orig_of, new_of, int(act.item()))
+
+
+def csr_active_prefix(g: CSR, stream=None) -> int:
+    """cc_csr_active_prefix: the smallest x with rows x .. n-1 empty."""
+    act = torch.zeros(1, dtype=torch.int64, device=g.offsets.device)
+    _check(lib().cc_csr_active_prefix(g.n, _ptr(g.offsets), g.o64, _ptr(act), _stream_handle(stream)),
+           "cc_csr_active_prefix")
+    return int(act.item())
 
 
 def connectivity_csr_mapped(ctx: Context, g: RenumberedCSR, variant: cc_variant | None = None,
@@ -431,9 +445,9 @@ def connectivity_csr_mapped(ctx: Context, g: RenumberedCSR, variant: cc_variant 
     b = ctypes.c_size_t()
     _check(lib().cc_mapped_workspace_bytes(g.n, g.m, ctypes.byref(v), ctypes.byref(b)), "cc_mapped_workspace_bytes")
     ws = ctx.workspace(int(b.value))
-    _check(lib().cc_connectivity_csr_mapped(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(g.orig_of),
-                                            _ptr(g.new_of), ctypes.byref(v), _ptr(ws), ws.numel(), _ptr(labels),
-                                            _ptr(ncomp), _stream_handle(stream)),
+    _check(lib().cc_connectivity_csr_mapped(ctx.h, g.n, g.n_active, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj),
+                                            _ptr(g.orig_of), _ptr(g.new_of), ctypes.byref(v), _ptr(ws), ws.numel(),
+                                            _ptr(labels), _ptr(ncomp), _stream_handle(stream)),
            "cc_connectivity_csr_mapped")
     return labels, ncomp
 

@@ -292,6 +292,21 @@ __global__ void k_degree_keys(int64_t n, const O* __restrict__ off, int bits, un
   }
 }
 
+// The first x from which every row is empty (offsets ascending): one lane
+// searches.
+template <typename O>
+__global__ void k_active_prefix(int64_t n, const O* __restrict__ off, long long* out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const O m = off[n];
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] == m) hi = mid;
+    else lo = mid + 1;
+  }
+  *out = lo;
+}
+
 // orig_of[i] = the vertex in sorted position i; new_of is its inverse.
 __global__ void k_order_maps(int64_t n, const unsigned long long* __restrict__ keys, int32_t* __restrict__ orig_of,
                              int32_t* __restrict__ new_of) {
@@ -469,6 +484,21 @@ cc_status cc_build_csr_degree_order(cc_ctx* ctx, int64_t n, int64_t num_pairs, c
   CC_LAUNCH_CHECK();
   return cc_build_csr(ctx, n, num_pairs, u2, v2, dedup, workspace, part, offsets_out, offsets_64bit, adj_out, m_dev,
                       hip_stream);
+}
+
+cc_status cc_csr_active_prefix(int64_t n, const void* offsets, int offsets_are_64bit, int64_t* active_dev,
+                               void* hip_stream) {
+  if (n < 1 || n > 0x7fffffffLL) return fail(CC_EINVAL, "bad n");
+  if (!offsets || !active_dev) return fail(CC_EINVAL, "NULL pointer");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (offsets_are_64bit)
+    hipLaunchKernelGGL(k_active_prefix<int64_t>, dim3(1), dim3(64), 0, s, n, (const int64_t*)offsets,
+                       (long long*)active_dev);
+  else
+    hipLaunchKernelGGL(k_active_prefix<int32_t>, dim3(1), dim3(64), 0, s, n, (const int32_t*)offsets,
+                       (long long*)active_dev);
+  CC_LAUNCH_CHECK();
+  return CC_OK;
 }
 
 }  // extern "C"

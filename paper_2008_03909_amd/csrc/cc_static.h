@@ -31,6 +31,10 @@ struct StaticArgs {
   bool kout_by_xcd = true;   // k-out: each XCD takes its own eighth of the ids (else blocks in id order)
   const int32_t* map_orig = nullptr;  // renumbered CSR: original id of each vertex (output copies it to map_rmin)
   int32_t* map_rmin = nullptr;
+  // a call on the first n vertices of a larger graph whose other vertices
+  // have no edges: the init still gives all n_parents entries of P a valid
+  // parent, and the component count includes the n_parents - n others
+  int64_t n_parents = 0;
   int32_t sample_success = 1;
   int32_t sample_rounds = 0;
   int32_t finish_rounds = 0;

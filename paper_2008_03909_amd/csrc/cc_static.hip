@@ -212,22 +212,29 @@ __device__ __forceinline__ void reset_scalars(DevScalars* sc, long long* ncomp_u
 
 // P[v] = v and count[v] = 0, four vertices per lane with 16-byte stores;
 // the first thread also resets the call's device scalars.
-__global__ void k_init(int64_t n, int32_t* __restrict__ P, int32_t* __restrict__ count, int aligned, DevScalars* sc,
-                       long long* ncomp_user) {
+// P[v] = v for v < np (np >= n: a call restricted to the first n vertices
+// still gives every vertex of the array a valid parent) and count[v] = 0 for
+// v < n.
+__global__ void k_init(int64_t n, int64_t np, int32_t* __restrict__ P, int32_t* __restrict__ count, int aligned,
+                       DevScalars* sc, long long* ncomp_user) {
   if (blockIdx.x == 0 && threadIdx.x == 0) reset_scalars(sc, ncomp_user);
-  const int64_t groups = div_up_dev(n, 4);
+  const int64_t groups = div_up_dev(np, 4);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups; g += stride) {
     const int64_t v0 = 4 * g;
-    if (aligned && v0 + 3 < n) {
+    if (aligned && v0 + 3 < np) {
       *(int4*)(P + v0) = make_int4((int)v0, (int)v0 + 1, (int)v0 + 2, (int)v0 + 3);
-      if (count) *(int4*)(count + v0) = make_int4(0, 0, 0, 0);
     } else {
       for (int j = 0; j < 4; ++j)
-        if (v0 + j < n) {
-          P[v0 + j] = (int32_t)(v0 + j);
-          if (count) count[v0 + j] = 0;
-        }
+        if (v0 + j < np) P[v0 + j] = (int32_t)(v0 + j);
+    }
+    if (count && v0 < n) {
+      if (aligned && v0 + 3 < n) {
+        *(int4*)(count + v0) = make_int4(0, 0, 0, 0);
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (v0 + j < n) count[v0 + j] = 0;
+      }
     }
   }
 }
@@ -999,21 +1006,30 @@ __global__ void __launch_bounds__(kBlock) k_map_min(int64_t n, const int32_t* __
 // One block: the frequent component's minimum from the block partials, and
 // the first vertex of the CSR's run of trailing empty rows (each of those
 // vertices is alone in its component; a CSR in decreasing-degree order keeps
-// every isolated vertex there).
+// every isolated vertex there).  The caller promised that rows na .. n-1
+// are empty: the run starts at na unless row na-1 is empty too (then a
+// binary search below na finds it); a broken promise sets the bad-CSR bit.
 template <typename I>
-__global__ void __launch_bounds__(kBlock) k_map_giant(int64_t n, const I* __restrict__ off,
+__global__ void __launch_bounds__(kBlock) k_map_giant(int64_t n, int64_t na, const I* __restrict__ off,
                                                       const int32_t* __restrict__ P, DevScalars* sc,
                                                       const int32_t* __restrict__ part, int nparts, int32_t* rmin) {
   __shared__ int32_t red[kBlock / kWave];
   if (threadIdx.x == 0) {
     const I m = off[n];
-    int64_t lo = 0, hi = n;  // first x with off[x] == m (off[n] == m)
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (off[mid] == m) hi = mid;
-      else lo = mid + 1;
+    if (off[na] != m) {
+      atomicOr(&sc->error, kErrBadCsr);
+      sc->map_tail = na;
+    } else if (na > 0 && off[na - 1] != m) {
+      sc->map_tail = na;
+    } else {
+      int64_t lo = 0, hi = na;  // first x with off[x] == m (off[na] == m)
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (off[mid] == m) hi = mid;
+        else lo = mid + 1;
+      }
+      sc->map_tail = lo;
     }
-    sc->map_tail = lo;
   }
   const int32_t L = sc->lmax;
   if (L < 0) return;
@@ -1080,8 +1096,9 @@ __global__ void __launch_bounds__(kBlock) k_map_fix(int64_t n, const int32_t* __
   }
 }
 
-// Component count from the per-block root counts (one block).
-__global__ void __launch_bounds__(kBlock) k_output_sum(const long long* __restrict__ part, int nparts,
+// Component count from the per-block root counts (one block), plus `extra`
+// isolated vertices outside the swept range.
+__global__ void __launch_bounds__(kBlock) k_output_sum(const long long* __restrict__ part, int nparts, long long extra,
                                                        DevScalars* sc, long long* ncomp_user) {
   __shared__ long long red[kBlock / kWave];
   long long s = 0;
@@ -1091,6 +1108,7 @@ __global__ void __launch_bounds__(kBlock) k_output_sum(const long long* __restri
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kBlock / kWave; ++w) s += red[w];
+    s += extra;
     sc->num_components = s;
     if (ncomp_user) *ncomp_user = s;
   }
@@ -1254,7 +1272,8 @@ static cc_status run_static(StaticArgs& a, bool sample_only) {
     PhaseScope ps(a.ctx, a.s, "init");
     // no sampling needs no histogram; k-out clears it in its own sweep
     const bool no_count = a.v->sample == CC_SAMPLE_NONE || a.v->sample == CC_SAMPLE_KOUT;
-    hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P,
+    const int64_t np = a.n_parents > a.n ? a.n_parents : a.n;
+    hipLaunchKernelGGL(k_init, dim3(grid4(np)), dim3(kBlock), 0, a.s, a.n, np, a.P,
                        no_count ? (int32_t*)nullptr : a.count, vec_ok(a), a.ctx->dev, (long long*)a.ncomp_user);
     CC_LAUNCH_CHECK();
   }
@@ -1310,8 +1329,9 @@ cc_status output_labels(StaticArgs& a) {
   const unsigned nb = grid4(a.n);
   const int vec = vec_ok(a) && (!a.map_orig || (al16(a.map_orig) && al16(a.map_rmin)));
   hipLaunchKernelGGL(k_output, dim3(nb), dim3(kBlock), 0, a.s, a.n, a.P, part, vec, a.map_orig, a.map_rmin);
-  hipLaunchKernelGGL(k_output_sum, dim3(1), dim3(kBlock), 0, a.s, (const long long*)part, (int)nb, a.ctx->dev,
-                     (long long*)a.ncomp_user);
+  const long long extra = a.n_parents > a.n ? (long long)(a.n_parents - a.n) : 0;
+  hipLaunchKernelGGL(k_output_sum, dim3(1), dim3(kBlock), 0, a.s, (const long long*)part, (int)nb, extra,
+                     a.ctx->dev, (long long*)a.ncomp_user);
   CC_LAUNCH_CHECK();
   return CC_OK;
 }
@@ -1339,7 +1359,7 @@ static void record_stats_host(StaticArgs& a);
 
 cc_status static_init(StaticArgs& a) {
   PhaseScope ps(a.ctx, a.s, "init");
-  hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.P, a.count, vec_ok(a), a.ctx->dev,
+  hipLaunchKernelGGL(k_init, dim3(grid4(a.n)), dim3(kBlock), 0, a.s, a.n, a.n, a.P, a.count, vec_ok(a), a.ctx->dev,
                      (long long*)a.ncomp_user);
   CC_LAUNCH_CHECK();
   return CC_OK;
@@ -1601,11 +1621,12 @@ cc_status cc_mapped_workspace_bytes(int64_t n, int64_t m, const cc_variant* v, s
   return CC_OK;
 }
 
-cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, int offsets_are_64bit,
-                                     const int32_t* adj, const int32_t* orig_of, const int32_t* new_of,
-                                     const cc_variant* v, void* workspace, size_t ws_bytes, int32_t* labels_out,
-                                     int64_t* num_components_dev, void* hip_stream) {
+cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t n_active, int64_t m, const void* offsets,
+                                     int offsets_are_64bit, const int32_t* adj, const int32_t* orig_of,
+                                     const int32_t* new_of, const cc_variant* v, void* workspace, size_t ws_bytes,
+                                     int32_t* labels_out, int64_t* num_components_dev, void* hip_stream) {
   if (!orig_of || !new_of) return fail(CC_EINVAL, "NULL permutation argument");
+  if (n_active < 0 || n_active > n) return fail(CC_EINVAL, "n_active=%lld outside [0, n]", (long long)n_active);
   size_t base = 0;
   cc_status st = cc_workspace_bytes(n, m, v, &base);
   if (st != CC_OK) return st;
@@ -1613,11 +1634,16 @@ cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t m, const vo
     return fail(CC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
                 base + align256((size_t)n * 4));
   if (!labels_out) return fail(CC_EINVAL, "labels_out is NULL");
+  // The algorithm runs on the first na vertices only: the others have no
+  // edges, so each is a component of its own, labelled by the gather below
+  // (one vertex at least, so that a graph without edges is a call too).
+  const int64_t na = n_active > 0 ? n_active : 1;
   int32_t* Pnew = (int32_t*)((char*)workspace + base);
   StaticArgs a;
-  st = setup_args(a, ctx, n, m, offsets, offsets_are_64bit, adj, v, workspace, base, Pnew, num_components_dev,
+  st = setup_args(a, ctx, na, m, offsets, offsets_are_64bit, adj, v, workspace, base, Pnew, num_components_dev,
                   hip_stream);
   if (st != CC_OK) return st;
+  a.n_parents = n;
   a.kout_by_xcd = false;
   // the count array is free once the finish has run: the output sweep
   // starts each root's minimum original id there
@@ -1629,21 +1655,21 @@ cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t m, const vo
     PhaseScope ps(a.ctx, a.s, "mapback");
     // the compaction area is free once the labels are out
     int32_t* part = (int32_t*)(a.ws + a.L.seg);
-    const unsigned g = grid_for((n + 3) / 4, kBlock, 2048);
+    const unsigned g = grid_for((na + 3) / 4, kBlock, 2048);
     uint32_t* in_giant = (uint32_t*)(a.ws + a.L.bits);  // the bitmap area is free too
     const int aligned = (((uintptr_t)Pnew | (uintptr_t)orig_of | (uintptr_t)new_of | (uintptr_t)labels_out) & 15u) == 0;
-    hipLaunchKernelGGL(k_map_min, dim3(g), dim3(kBlock), 0, a.s, n, (const int32_t*)Pnew, orig_of, rmin,
+    hipLaunchKernelGGL(k_map_min, dim3(g), dim3(kBlock), 0, a.s, na, (const int32_t*)Pnew, orig_of, rmin,
                        (const DevScalars*)a.ctx->dev, part, in_giant, aligned);
     if (a.o64)
-      hipLaunchKernelGGL(k_map_giant<int64_t>, dim3(1), dim3(kBlock), 0, a.s, n, (const int64_t*)offsets,
+      hipLaunchKernelGGL(k_map_giant<int64_t>, dim3(1), dim3(kBlock), 0, a.s, n, na, (const int64_t*)offsets,
                          (const int32_t*)Pnew, a.ctx->dev, (const int32_t*)part, (int)g, rmin);
     else
-      hipLaunchKernelGGL(k_map_giant<int32_t>, dim3(1), dim3(kBlock), 0, a.s, n, (const int32_t*)offsets,
+      hipLaunchKernelGGL(k_map_giant<int32_t>, dim3(1), dim3(kBlock), 0, a.s, n, na, (const int32_t*)offsets,
                          (const int32_t*)Pnew, a.ctx->dev, (const int32_t*)part, (int)g, rmin);
     hipLaunchKernelGGL(k_map_gather, dim3(grid_for((n + 3) / 4, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
                        (const int32_t*)Pnew, new_of, (const int32_t*)rmin, (const DevScalars*)a.ctx->dev,
                        labels_out, aligned);
-    hipLaunchKernelGGL(k_map_fix, dim3(grid_for((n + 31) / 32, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
+    hipLaunchKernelGGL(k_map_fix, dim3(grid_for((na + 31) / 32, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
                        (const int32_t*)Pnew, orig_of, (const int32_t*)rmin, (const DevScalars*)a.ctx->dev,
                        (const uint32_t*)in_giant, labels_out);
     CC_LAUNCH_CHECK();

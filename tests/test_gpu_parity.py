@@ -154,6 +154,60 @@ def test_mapped_connectivity_with_a_random_permutation(ctx):
         assert int(nc.item()) == wc and np.array_equal(lab.cpu().numpy(), want), g
 
 
+def test_csr_active_prefix(ctx):
+    """The smallest x from which every row is empty, for CSRs as built and
+    renumbered by degree (there it is the number of vertices with an entry:
+    isolated vertices come last)."""
+    for g in SUITE:
+        for o64 in (False, True):
+            d = _csr(ctx, g, o64=o64)
+            off = d.offsets.cpu().numpy().astype(np.int64)
+            want = int(np.argmax(off == off[-1]))
+            assert b.csr_active_prefix(d) == want, g
+            r = b.build_csr_degree_order(ctx, g.n, g.u, g.v, offsets_64bit=o64)
+            roff = r.offsets.cpu().numpy().astype(np.int64)
+            assert r.n_active == int(np.count_nonzero(np.diff(roff))), g
+            assert r.n_active == int(np.argmax(roff == roff[-1])), g
+
+
+@pytest.mark.parametrize("vi", [0, 20, 40, 60])
+def test_mapped_connectivity_with_and_without_the_active_prefix(ctx, vi):
+    """The call restricted to the vertices with edges and the call told
+    nothing (n_active = n) give the same labels and count, both the
+    oracle's."""
+    v = b.all_variants()[vi]
+    for g in SUITE:
+        want, wc = oracle.labels(g)
+        d = b.build_csr_degree_order(ctx, g.n, g.u, g.v)
+        full = b.RenumberedCSR(g.n, d.offsets, d.adj, d.orig_of, d.new_of)
+        for r in (d, full):
+            lab, nc = b.connectivity_csr_mapped(ctx, r, v)
+            torch.cuda.synchronize()
+            ctx.sync_status()
+            assert int(nc.item()) == wc, (v, g, r.n_active)
+            assert np.array_equal(lab.cpu().numpy(), want), (v, g, r.n_active)
+
+
+def test_mapped_connectivity_reports_a_broken_active_prefix(ctx):
+    """n_active below the last non-empty row is reported through the
+    context's error word (the parent array covers every vertex, so the call
+    itself reads only valid entries)."""
+    g = SUITE[8]  # many small components and isolated vertices
+    d = b.build_csr_degree_order(ctx, g.n, g.u, g.v)
+    assert d.n_active >= 2
+    bad = b.RenumberedCSR(g.n, d.offsets, d.adj, d.orig_of, d.new_of, d.n_active - 1)
+    b.connectivity_csr_mapped(ctx, bad)
+    torch.cuda.synchronize()
+    with pytest.raises(b.CCError):
+        ctx.sync_status()
+    # the context works again afterwards
+    lab, nc = b.connectivity_csr_mapped(ctx, d)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    want, wc = oracle.labels(g)
+    assert int(nc.item()) == wc and np.array_equal(lab.cpu().numpy(), want)
+
+
 # ---- default variant and the full variant space ----------------------------------
 
 def test_default_variant_er_workload(ctx):
