@@ -1437,7 +1437,7 @@ static cc_status noalloc_scratch_address(int device, void** out) {
 
 static void record_stats_host(StaticArgs& a) {
   cc_stats& s = a.ctx->last;
-  s.n = a.n;
+  s.n = a.n_parents > a.n ? a.n_parents : a.n;  // the graph's vertices, swept or not
   s.m = a.m;
   s.sample_success = a.sample_success;
   s.sample_rounds = a.sample_rounds;
