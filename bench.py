@@ -700,22 +700,31 @@ def main():
         "ingest": {"ms": ingest_ms, "pairs": g.num_pairs, "pairs_per_s": g.num_pairs / (ingest_ms / 1e3),
                    "degree_order_ms": relabel_ms},
     }
-    del rcsr
     del ws
     forest_ok = v.finish == b.FIN_UF_ASYNC or (v.finish == b.FIN_UF_REM_CAS and v.splice != b.SPLICE_ATOMIC)
     if not args.no_forest and forest_ok:
-        # spanning forest with the default variant on the same CSR (outside the timed region above)
+        # spanning forest with the default variant on the layout the static
+        # call used (outside the timed region above); on a renumbered CSR its
+        # edges and labels come back in the original numbering
+        if rcsr is not None:
+            def forest_call():
+                return b.spanning_forest_csr_mapped(ctx, rcsr, v)
+        else:
+            def forest_call():
+                return b.spanning_forest_csr(ctx, csr, v)
         for _ in range(2):
-            b.spanning_forest_csr(ctx, csr, v)
+            forest_call()
         torch.cuda.synchronize()
         t0f = time.perf_counter()
         for _ in range(args.steps):
-            _, _, _, ne = b.spanning_forest_csr(ctx, csr, v)
+            _, _, _, ne = forest_call()
         torch.cuda.synchronize()
         ms_f = (time.perf_counter() - t0f) * 1e3 / args.steps
         out["spanning_forest"] = {"ms": ms_f, "edges_per_s": m / (ms_f / 1e3),
-                                  "forest_edges": int(ne.item()), "vs_connectivity": ms_f / ms_step}
+                                  "forest_edges": int(ne.item()), "vs_connectivity": ms_f / ms_step,
+                                  "layout": layout}
         log(f"spanning forest: {ms_f:.3f} ms ({ms_f / ms_step:.2f}x connectivity), {int(ne.item())} edges")
+    del rcsr
     if not args.no_amsf:
         out["amsf"] = amsf_leg(ctx, csr, n, m, ms_step, args.steps)
     if args.sweep:

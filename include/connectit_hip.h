@@ -297,6 +297,21 @@ cc_status cc_spanning_forest_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* 
                                  const int32_t* adj, const cc_variant* v, void* workspace, size_t ws_bytes,
                                  int32_t* labels_out, int32_t* edges_u, int32_t* edges_v, int64_t* num_edges_dev,
                                  void* hip_stream);
+/* The spanning forest of a renumbered CSR (orig_of / new_of and n_active as
+ * for cc_connectivity_csr_mapped), reported in the original numbering: each
+ * forest edge (edges_u[i], edges_v[i]) is a pair of original ids, and
+ * labels_out[o] is the smallest original id in original vertex o's
+ * component.  The algorithm runs on vertices [0, n_active); the others have
+ * no edges and add none.  Variants as for cc_spanning_forest_csr.
+ * workspace: device buffer of >= cc_forest_mapped_workspace_bytes
+ * (cc_forest_workspace_bytes plus 4n bytes for the labels in the CSR's
+ * numbering). */
+cc_status cc_forest_mapped_workspace_bytes(int64_t n, int64_t m, const cc_variant* v, size_t* bytes);
+cc_status cc_spanning_forest_csr_mapped(cc_ctx* ctx, int64_t n, int64_t n_active, int64_t m, const void* offsets,
+                                        int offsets_are_64bit, const int32_t* adj, const int32_t* orig_of,
+                                        const int32_t* new_of, const cc_variant* v, void* workspace, size_t ws_bytes,
+                                        int32_t* labels_out, int32_t* edges_u, int32_t* edges_v,
+                                        int64_t* num_edges_dev, void* hip_stream);
 
 /* ---- approximate minimum spanning forest (Section 5.1, AMSF) -------------------
  * weights[j] > 0 is the weight of adjacency entry j of the symmetric CSR

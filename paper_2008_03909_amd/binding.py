@@ -163,6 +163,11 @@ def lib():
                                                  ctypes.POINTER(ctypes.c_size_t)]),
             "cc_spanning_forest_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, ctypes.POINTER(cc_variant), _vp,
                                               ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]),
+            "cc_forest_mapped_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_variant),
+                                                        ctypes.POINTER(ctypes.c_size_t)]),
+            "cc_spanning_forest_csr_mapped": (_int, [_vp, _i64, _i64, _i64, _vp, _int, _vp, _vp, _vp,
+                                                     ctypes.POINTER(cc_variant), _vp, ctypes.c_size_t, _vp, _vp, _vp,
+                                                     _vp, _vp]),
             "cc_amsf_default_options": (_int, [ctypes.POINTER(cc_amsf_options)]),
             "cc_amsf_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_amsf_options),
                                                ctypes.POINTER(ctypes.c_size_t)]),
@@ -537,6 +542,26 @@ def spanning_forest_csr(ctx: Context, g: CSR, variant: cc_variant | None = None,
     _check(lib().cc_spanning_forest_csr(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), ctypes.byref(v),
                                         _ptr(ws), ws.numel(), _ptr(labels), _ptr(eu), _ptr(ev), _ptr(ne),
                                         _stream_handle(stream)), "cc_spanning_forest_csr")
+    return labels, eu, ev, ne
+
+
+def spanning_forest_csr_mapped(ctx: Context, g: RenumberedCSR, variant: cc_variant | None = None, stream=None):
+    """cc_spanning_forest_csr_mapped.  Returns (labels int32[n], edges_u,
+    edges_v, num_edges int64[1]) in the original numbering."""
+    v = variant if variant is not None else default_variant()
+    dev = ctx.torch_device
+    labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    eu = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    ev = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    ne = torch.zeros(1, dtype=torch.int64, device=dev)
+    wsb = ctypes.c_size_t()
+    _check(lib().cc_forest_mapped_workspace_bytes(g.n, g.m, ctypes.byref(v), ctypes.byref(wsb)),
+           "cc_forest_mapped_workspace_bytes")
+    ws = ctx.workspace(int(wsb.value))
+    _check(lib().cc_spanning_forest_csr_mapped(ctx.h, g.n, g.n_active, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj),
+                                               _ptr(g.orig_of), _ptr(g.new_of), ctypes.byref(v), _ptr(ws),
+                                               ws.numel(), _ptr(labels), _ptr(eu), _ptr(ev), _ptr(ne),
+                                               _stream_handle(stream)), "cc_spanning_forest_csr_mapped")
     return labels, eu, ev, ne
 
 

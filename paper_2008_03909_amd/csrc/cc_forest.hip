@@ -80,7 +80,8 @@ __global__ void __launch_bounds__(kFBlock) k_forest_write(int64_t len, const int
                                                           const float* __restrict__ hook_w, int64_t n,
                                                           const int32_t* __restrict__ base_of,
                                                           int32_t* __restrict__ out_u, int32_t* __restrict__ out_v,
-                                                          float* __restrict__ out_w) {
+                                                          float* __restrict__ out_w,
+                                                          const int32_t* __restrict__ orig_of) {
   __shared__ int32_t wcnt[kFBlock / kWave];
   const int lane = lane_id(), w = threadIdx.x / kWave;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -101,8 +102,8 @@ __global__ void __launch_bounds__(kFBlock) k_forest_write(int64_t len, const int
     }
     if (keep) {
       const int32_t p = pos + before + __popcll(m & lt);
-      out_u[p] = e.x;
-      out_v[p] = e.y;
+      out_u[p] = orig_of ? orig_of[e.x] : e.x;
+      out_v[p] = orig_of ? orig_of[e.y] : e.y;
       if (out_w) out_w[p] = hook_w[tree ? i - n : i];
     }
     pos += all;
@@ -113,14 +114,15 @@ __global__ void __launch_bounds__(kFBlock) k_forest_write(int64_t len, const int
 int64_t forest_tiles(int64_t len) { return (len + kForestTile - 1) / kForestTile; }
 
 cc_status forest_filter(hipStream_t s, int64_t n, const int2* tree, const int2* hook, const float* hook_w,
-                        int32_t* cnt, int32_t* out_u, int32_t* out_v, float* out_w, int64_t* num_edges) {
+                        int32_t* cnt, int32_t* out_u, int32_t* out_v, float* out_w, int64_t* num_edges,
+                        const int32_t* orig_of) {
   const int64_t len = tree ? 2 * n : n;
   const int64_t tiles = forest_tiles(len);
   hipLaunchKernelGGL(k_forest_count, dim3((unsigned)tiles), dim3(kFBlock), 0, s, len, tree, hook, n, cnt);
   hipLaunchKernelGGL(k_forest_scan, dim3(1), dim3(1024), 0, s, tiles, cnt, (long long*)num_edges);
   hipLaunchKernelGGL(k_forest_write, dim3((unsigned)tiles), dim3(kFBlock), 0, s, len, tree, hook,
                      (hook_w && out_w) ? hook_w : (const float*)nullptr, n, (const int32_t*)cnt, out_u, out_v,
-                     (hook_w && out_w) ? out_w : (float*)nullptr);
+                     (hook_w && out_w) ? out_w : (float*)nullptr, orig_of);
   CC_LAUNCH_CHECK();
   return CC_OK;
 }
@@ -178,6 +180,67 @@ cc_status cc_spanning_forest_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* 
   st = static_run(a);
   if (st != CC_OK) return st;
   return forest_filter(a.s, n, a.tree_e, a.hook_e, nullptr, cnt, edges_u, edges_v, nullptr, num_edges_dev);
+}
+
+cc_status cc_forest_mapped_workspace_bytes(int64_t n, int64_t m, const cc_variant* v, size_t* bytes) {
+  if (!bytes) return fail(CC_EINVAL, "bytes is NULL");
+  size_t f = 0;
+  cc_status st = cc_forest_workspace_bytes(n, m, v, &f);
+  if (st != CC_OK) return st;
+  *bytes = f + align256((size_t)n * 4);  // the labels in the CSR's numbering
+  return CC_OK;
+}
+
+cc_status cc_spanning_forest_csr_mapped(cc_ctx* ctx, int64_t n, int64_t n_active, int64_t m, const void* offsets,
+                                        int offsets_are_64bit, const int32_t* adj, const int32_t* orig_of,
+                                        const int32_t* new_of, const cc_variant* v, void* workspace, size_t ws_bytes,
+                                        int32_t* labels_out, int32_t* edges_u, int32_t* edges_v,
+                                        int64_t* num_edges_dev, void* hip_stream) {
+  if (!v) return fail(CC_EINVAL, "variant is NULL");
+  if (v->finish != CC_FIN_UF_REM_CAS && v->finish != CC_FIN_UF_ASYNC && v->finish != CC_FIN_UF_EARLY &&
+      v->finish != CC_FIN_UF_HOOKS)
+    return fail(CC_EUNSUPPORTED, "spanning forest needs a union-find finish (Rem-CAS, Async, Early or Hooks)");
+  if (v->finish == CC_FIN_UF_REM_CAS && v->splice == CC_SPLICE_ATOMIC)
+    return fail(CC_EUNSUPPORTED, "spanning forest: SpliceAtomic moves non-roots between trees without a hook");
+  if (!edges_u || !edges_v || !num_edges_dev || !labels_out) return fail(CC_EINVAL, "NULL output");
+  if (!orig_of || !new_of) return fail(CC_EINVAL, "NULL permutation argument");
+  if (n_active < 0 || n_active > n) return fail(CC_EINVAL, "n_active=%lld outside [0, n]", (long long)n_active);
+  size_t need = 0;
+  cc_status st = cc_forest_mapped_workspace_bytes(n, m, v, &need);
+  if (st != CC_OK) return st;
+  if (!workspace || ws_bytes < need)
+    return fail(CC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+  size_t base = 0;
+  cc_workspace_bytes(n, m, v, &base);
+  base = align256(base);
+  // as cc_connectivity_csr_mapped: the algorithm on the first na vertices,
+  // the others (empty rows) alone in their components and without edges
+  const int64_t na = n_active > 0 ? n_active : 1;
+  char* w = (char*)workspace + base;
+  int32_t* Pnew = (int32_t*)(w + forest_extra(n));
+  StaticArgs a;
+  st = setup_args(a, ctx, na, m, offsets, offsets_are_64bit, adj, v, workspace, base, Pnew, nullptr, hip_stream);
+  if (st != CC_OK) return st;
+  a.n_parents = n;
+  a.kout_by_xcd = false;
+  a.map_orig = orig_of;
+  a.map_rmin = a.count;
+  // slot arrays sized for all n vertices (a hook or claim beyond na, which
+  // only a broken n_active makes, lands in a slot the filter never reads);
+  // the filter reads the first na of each
+  a.tree_e = (int2*)w;
+  a.hook_e = (int2*)(w + align256((size_t)n * 8));
+  int32_t* cnt = (int32_t*)(w + 2 * align256((size_t)n * 8));
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(4 * na, kFBlock, 4096)), dim3(kFBlock), 0, a.s, (uint32_t*)a.tree_e,
+                     2 * na, 0xffffffffu);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(4 * na, kFBlock, 4096)), dim3(kFBlock), 0, a.s, (uint32_t*)a.hook_e,
+                     2 * na, 0xffffffffu);
+  CC_LAUNCH_CHECK();
+  st = static_run(a);
+  if (st != CC_OK) return st;
+  st = forest_filter(a.s, na, a.tree_e, a.hook_e, nullptr, cnt, edges_u, edges_v, nullptr, num_edges_dev, orig_of);
+  if (st != CC_OK) return st;
+  return map_back_labels(a, n, orig_of, new_of, Pnew, labels_out);
 }
 
 }  // extern "C"

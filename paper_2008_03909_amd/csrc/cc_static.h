@@ -60,9 +60,18 @@ cc_status output_labels(StaticArgs& a);
 // Writes the recorded forest edges (tree_e when given, then hook_e) densely
 // to out_u/out_v (and the hook weights to out_w when both are given);
 // *num_edges (device) receives the count.  `cnt` holds forest_tiles(len)
-// int32.
+// int32.  With orig_of, each endpoint x is written as orig_of[x] (a CSR
+// whose vertices were renumbered).
 cc_status forest_filter(hipStream_t s, int64_t n, const int2* tree, const int2* hook, const float* hook_w,
-                        int32_t* cnt, int32_t* out_u, int32_t* out_v, float* out_w, int64_t* num_edges);
+                        int32_t* cnt, int32_t* out_u, int32_t* out_v, float* out_w, int64_t* num_edges,
+                        const int32_t* orig_of = nullptr);
+// After a static run on the first a.n vertices of a renumbered CSR of n
+// vertices (a.map_orig set, so the output sweep started each root's
+// minimum original id in a.count): labels_out[o] = the smallest original
+// id in original vertex o's component, from the labels P in the CSR's
+// numbering.  Vertices a.n .. n-1 have empty rows.
+cc_status map_back_labels(StaticArgs& a, int64_t n, const int32_t* orig_of, const int32_t* new_of,
+                          const int32_t* P, int32_t* labels_out);
 int64_t forest_tiles(int64_t len);
 // SV / root-based LT rounds over an explicit edge list until nothing changes
 // (stream batch inserts with a round-based finish).

@@ -1435,6 +1435,32 @@ static cc_status noalloc_scratch_address(int device, void** out) {
   return CC_OK;
 }
 
+cc_status map_back_labels(StaticArgs& a, int64_t n, const int32_t* orig_of, const int32_t* new_of,
+                          const int32_t* P, int32_t* labels_out) {
+  PhaseScope ps(a.ctx, a.s, "mapback");
+  const int64_t na = a.n;
+  int32_t* rmin = a.map_rmin;
+  // the compaction area is free once the labels are out
+  int32_t* part = (int32_t*)(a.ws + a.L.seg);
+  const unsigned g = grid_for((na + 3) / 4, kBlock, 2048);
+  uint32_t* in_giant = (uint32_t*)(a.ws + a.L.bits);  // the bitmap area is free too
+  const int aligned = (((uintptr_t)P | (uintptr_t)orig_of | (uintptr_t)new_of | (uintptr_t)labels_out) & 15u) == 0;
+  hipLaunchKernelGGL(k_map_min, dim3(g), dim3(kBlock), 0, a.s, na, P, orig_of, rmin, (const DevScalars*)a.ctx->dev,
+                     part, in_giant, aligned);
+  if (a.o64)
+    hipLaunchKernelGGL(k_map_giant<int64_t>, dim3(1), dim3(kBlock), 0, a.s, n, na, (const int64_t*)a.off, P,
+                       a.ctx->dev, (const int32_t*)part, (int)g, rmin);
+  else
+    hipLaunchKernelGGL(k_map_giant<int32_t>, dim3(1), dim3(kBlock), 0, a.s, n, na, (const int32_t*)a.off, P,
+                       a.ctx->dev, (const int32_t*)part, (int)g, rmin);
+  hipLaunchKernelGGL(k_map_gather, dim3(grid_for((n + 3) / 4, kBlock, 4096)), dim3(kBlock), 0, a.s, n, P, new_of,
+                     (const int32_t*)rmin, (const DevScalars*)a.ctx->dev, labels_out, aligned);
+  hipLaunchKernelGGL(k_map_fix, dim3(grid_for((na + 31) / 32, kBlock, 4096)), dim3(kBlock), 0, a.s, n, P, orig_of,
+                     (const int32_t*)rmin, (const DevScalars*)a.ctx->dev, (const uint32_t*)in_giant, labels_out);
+  CC_LAUNCH_CHECK();
+  return CC_OK;
+}
+
 static void record_stats_host(StaticArgs& a) {
   cc_stats& s = a.ctx->last;
   s.n = a.n_parents > a.n ? a.n_parents : a.n;  // the graph's vertices, swept or not
@@ -1647,33 +1673,10 @@ cc_status cc_connectivity_csr_mapped(cc_ctx* ctx, int64_t n, int64_t n_active, i
   a.kout_by_xcd = false;
   // the count array is free once the finish has run: the output sweep
   // starts each root's minimum original id there
-  int32_t* rmin = a.count;
   a.map_orig = orig_of;
-  a.map_rmin = rmin;
+  a.map_rmin = a.count;
   st = a.o64 ? run_static<int64_t>(a, false) : run_static<int32_t>(a, false);
-  if (st == CC_OK) {
-    PhaseScope ps(a.ctx, a.s, "mapback");
-    // the compaction area is free once the labels are out
-    int32_t* part = (int32_t*)(a.ws + a.L.seg);
-    const unsigned g = grid_for((na + 3) / 4, kBlock, 2048);
-    uint32_t* in_giant = (uint32_t*)(a.ws + a.L.bits);  // the bitmap area is free too
-    const int aligned = (((uintptr_t)Pnew | (uintptr_t)orig_of | (uintptr_t)new_of | (uintptr_t)labels_out) & 15u) == 0;
-    hipLaunchKernelGGL(k_map_min, dim3(g), dim3(kBlock), 0, a.s, na, (const int32_t*)Pnew, orig_of, rmin,
-                       (const DevScalars*)a.ctx->dev, part, in_giant, aligned);
-    if (a.o64)
-      hipLaunchKernelGGL(k_map_giant<int64_t>, dim3(1), dim3(kBlock), 0, a.s, n, na, (const int64_t*)offsets,
-                         (const int32_t*)Pnew, a.ctx->dev, (const int32_t*)part, (int)g, rmin);
-    else
-      hipLaunchKernelGGL(k_map_giant<int32_t>, dim3(1), dim3(kBlock), 0, a.s, n, na, (const int32_t*)offsets,
-                         (const int32_t*)Pnew, a.ctx->dev, (const int32_t*)part, (int)g, rmin);
-    hipLaunchKernelGGL(k_map_gather, dim3(grid_for((n + 3) / 4, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
-                       (const int32_t*)Pnew, new_of, (const int32_t*)rmin, (const DevScalars*)a.ctx->dev,
-                       labels_out, aligned);
-    hipLaunchKernelGGL(k_map_fix, dim3(grid_for((na + 31) / 32, kBlock, 4096)), dim3(kBlock), 0, a.s, n,
-                       (const int32_t*)Pnew, orig_of, (const int32_t*)rmin, (const DevScalars*)a.ctx->dev,
-                       (const uint32_t*)in_giant, labels_out);
-    CC_LAUNCH_CHECK();
-  }
+  if (st == CC_OK) st = map_back_labels(a, n, orig_of, new_of, Pnew, labels_out);
   record_stats_host(a);
   return st;
 }

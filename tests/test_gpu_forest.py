@@ -79,3 +79,41 @@ def test_forest_rejects_unsupported_finishes(ctx):
         with pytest.raises(b.CCError) as e:
             b.spanning_forest_csr(ctx, d, v)
         assert e.value.status == b.CC_EUNSUPPORTED
+
+
+def _check_mapped(ctx, g, v):
+    d = b.build_csr_degree_order(ctx, g.n, g.u, g.v)
+    lab, eu, ev, ne = b.spanning_forest_csr_mapped(ctx, d, v)
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    want, wc = oracle.labels(g)
+    k = int(ne.item())
+    assert np.array_equal(lab.cpu().numpy(), want), (v.name(), g)
+    assert k == g.n - wc, (v.name(), g, k, g.n - wc)
+    code = oracle.forest_check(g, eu[:k].cpu().numpy(), ev[:k].cpu().numpy())
+    assert code == oracle.FOREST_OK, (v.name(), g, code)
+
+
+@pytest.mark.parametrize("vi", range(0, 72, 3))
+def test_forest_mapped_on_the_suite(ctx, vi):
+    """The forest of the degree-ordered CSR, run on the vertices with edges
+    and reported in the original numbering (every third union-find variant:
+    each sampler and each finish family is among them)."""
+    v = _uf_variants()[vi]
+    for g in SUITE:
+        _check_mapped(ctx, g, v)
+
+
+def test_forest_mapped_rmat_2_24_default(ctx):
+    g = inputs.workload_rmat(24, 8, seed=2)
+    off, adj = oracle.csr_build(g.n, g.u, g.v, True)
+    want, wc = oracle.uf_cc(g.n, g.u, g.v)
+    dev = ctx.torch_device
+    d = b.build_csr_degree_order(ctx, g.n, torch.from_numpy(g.u).to(dev), torch.from_numpy(g.v).to(dev))
+    lab, eu, ev, ne = b.spanning_forest_csr_mapped(ctx, d, b.default_variant())
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    k = int(ne.item())
+    assert np.array_equal(lab.cpu().numpy(), want) and k == g.n - wc
+    assert oracle.forest_check_csr(g.n, off, adj, want, eu[:k].cpu().numpy(), ev[:k].cpu().numpy()) == 0
+
