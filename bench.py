@@ -472,10 +472,12 @@ def sweep(ctx, csr, g, workload_name: str, reps: int = 5, check: bool = True):
     return rows
 
 
-def amsf_leg(ctx, csr, n: int, m: int, ms_conn: float, steps: int) -> dict:
-    """Approximate MSF (Section 5.1) on the same CSR with exponential weights
-    of mean 1 (the paper's weighting), eps = 0.25.  Timed outside the main
-    region; per-phase times from the call's own events."""
+def amsf_leg(ctx, csr, n: int, m: int, ms_conn: float, steps: int, rcsr=None) -> dict:
+    """Approximate MSF (Section 5.1) with exponential weights of mean 1 (the
+    paper's weighting, a function of the pair of original vertices), eps =
+    0.25, on the layout of the static call (the renumbered CSR rcsr when
+    given).  Timed outside the main region; per-phase times from the call's
+    own events."""
     import numpy as np
     import torch
 
@@ -483,28 +485,38 @@ def amsf_leg(ctx, csr, n: int, m: int, ms_conn: float, steps: int) -> dict:
     from paper_2008_03909_amd import inputs
 
     t = time.perf_counter()
-    off_h = csr.offsets.cpu().numpy()
-    adj_h = csr.adj.cpu().numpy()
+    g = rcsr if rcsr is not None else csr
+    off_h = g.offsets.cpu().numpy()
+    adj_h = g.adj.cpu().numpy()
     rows = np.repeat(np.arange(n, dtype=np.int32), np.diff(off_h))
+    if rcsr is not None:
+        orig = rcsr.orig_of.cpu().numpy()
+        rows, adj_h = orig[rows], orig[adj_h]
     w = inputs.pair_weights(n, rows, adj_h, seed=77, mean=1.0)
     del rows, adj_h, off_h
     wt = torch.from_numpy(w).to(ctx.torch_device)
     del w
     log(f"amsf weights in {time.perf_counter() - t:.1f}s")
     opt = b.amsf_options()
+    if rcsr is not None:
+        def call():
+            return b.amsf_csr_mapped(ctx, rcsr, wt, opt)
+    else:
+        def call():
+            return b.amsf_csr(ctx, csr, wt, opt)
     for _ in range(2):
-        b.amsf_csr(ctx, csr, wt, opt)
+        call()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        _, _, _, _, ne, tw = b.amsf_csr(ctx, csr, wt, opt)
+        _, _, _, _, ne, tw = call()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     # phase breakdown from a separate pass (phase events slow the calls down)
     ctx.set_timing(True)
     ctx.phase_times_reset()
     for _ in range(steps):
-        b.amsf_csr(ctx, csr, wt, opt)
+        call()
     torch.cuda.synchronize()
     ctx.set_timing(False)
     ph = {k: round(v[0] / steps, 4) for k, v in ctx.phase_times().items()}
@@ -724,9 +736,10 @@ def main():
                                   "forest_edges": int(ne.item()), "vs_connectivity": ms_f / ms_step,
                                   "layout": layout}
         log(f"spanning forest: {ms_f:.3f} ms ({ms_f / ms_step:.2f}x connectivity), {int(ne.item())} edges")
-    del rcsr
     if not args.no_amsf:
-        out["amsf"] = amsf_leg(ctx, csr, n, m, ms_step, args.steps)
+        out["amsf"] = amsf_leg(ctx, csr, n, m, ms_step, args.steps, rcsr=rcsr)
+        out["amsf"]["layout"] = layout
+    del rcsr
     if args.sweep:
         log("variant sweep ...")
         rows = sweep(ctx, csr, g, args.workload)

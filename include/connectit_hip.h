@@ -355,6 +355,20 @@ cc_status cc_amsf_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, in
                       const int32_t* adj, const float* weights, const cc_amsf_options* opt, void* workspace,
                       size_t ws_bytes, int32_t* labels_out, int32_t* edges_u, int32_t* edges_v, float* edges_w,
                       int64_t* num_edges_dev, double* weight_dev, void* hip_stream);
+/* cc_amsf_csr on a renumbered CSR (orig_of / new_of and n_active as for
+ * cc_connectivity_csr_mapped; weights[j] is the weight of the CSR's
+ * adjacency entry j), reported in the original numbering: forest edges as
+ * pairs of original ids, labels_out[o] the smallest original id in o's
+ * component.  The unions run on vertices [0, n_active); every row of the
+ * CSR is still scanned once to cut the adjacency into tiles.  workspace: >=
+ * cc_amsf_mapped_workspace_bytes (cc_amsf_workspace_bytes plus 4n bytes for
+ * the labels in the CSR's numbering). */
+cc_status cc_amsf_mapped_workspace_bytes(int64_t n, int64_t m, const cc_amsf_options* opt, size_t* bytes);
+cc_status cc_amsf_csr_mapped(cc_ctx* ctx, int64_t n, int64_t n_active, int64_t m, const void* offsets,
+                             int offsets_are_64bit, const int32_t* adj, const int32_t* orig_of, const int32_t* new_of,
+                             const float* weights, const cc_amsf_options* opt, void* workspace, size_t ws_bytes,
+                             int32_t* labels_out, int32_t* edges_u, int32_t* edges_v, float* edges_w,
+                             int64_t* num_edges_dev, double* weight_dev, void* hip_stream);
 
 /* ---- ingest: undirected pair list -> symmetric CSR (Section 2 formats) -------
  * Output: both orientations of every pair with u != v, rows sorted

@@ -173,6 +173,11 @@ def lib():
                                                ctypes.POINTER(ctypes.c_size_t)]),
             "cc_amsf_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _vp, ctypes.POINTER(cc_amsf_options), _vp,
                                    ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "cc_amsf_mapped_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(cc_amsf_options),
+                                                      ctypes.POINTER(ctypes.c_size_t)]),
+            "cc_amsf_csr_mapped": (_int, [_vp, _i64, _i64, _i64, _vp, _int, _vp, _vp, _vp, _vp,
+                                          ctypes.POINTER(cc_amsf_options), _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp,
+                                          _vp, _vp, _vp]),
             "cc_validate_csr": (_int, [_vp, _i64, _i64, _vp, _int, _vp, _int, ctypes.POINTER(cc_csr_report), _vp]),
             "cc_csr_workspace_bytes": (_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
             "cc_build_csr": (_int, [_vp, _i64, _i64, _vp, _vp, _int, _vp, ctypes.c_size_t, _vp, _int, _vp, _vp,
@@ -601,6 +606,31 @@ def amsf_csr(ctx: Context, g: CSR, weights, options: cc_amsf_options | None = No
     _check(lib().cc_amsf_csr(ctx.h, g.n, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), wp, ctypes.byref(o), _ptr(ws),
                              ws.numel(), _ptr(labels), _ptr(eu), _ptr(ev), _ptr(ew), _ptr(ne), _ptr(tw),
                              _stream_handle(stream)), "cc_amsf_csr")
+    return labels, eu, ev, ew, ne, tw
+
+
+def amsf_csr_mapped(ctx: Context, g: RenumberedCSR, weights, options: cc_amsf_options | None = None, stream=None):
+    """cc_amsf_csr_mapped: as amsf_csr on a renumbered CSR (weights per
+    adjacency entry of that CSR), edges and labels in the original numbering."""
+    o = options if options is not None else amsf_options()
+    dev = ctx.torch_device
+    labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    eu = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    ev = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    ew = torch.empty(max(g.n, 1), dtype=torch.float32, device=dev)
+    ne = torch.zeros(1, dtype=torch.int64, device=dev)
+    tw = torch.zeros(1, dtype=torch.float64, device=dev)
+    if weights.dtype != torch.float32 or weights.numel() != g.m:
+        raise ValueError(f"weights must be float32 with {g.m} entries")
+    wsb = ctypes.c_size_t()
+    _check(lib().cc_amsf_mapped_workspace_bytes(g.n, g.m, ctypes.byref(o), ctypes.byref(wsb)),
+           "cc_amsf_mapped_workspace_bytes")
+    ws = ctx.workspace(int(wsb.value))
+    wp = _ptr(weights) if g.m > 0 else None
+    _check(lib().cc_amsf_csr_mapped(ctx.h, g.n, g.n_active, g.m, _ptr(g.offsets), g.o64, _ptr(g.adj), _ptr(g.orig_of),
+                                    _ptr(g.new_of), wp, ctypes.byref(o), _ptr(ws), ws.numel(), _ptr(labels),
+                                    _ptr(eu), _ptr(ev), _ptr(ew), _ptr(ne), _ptr(tw), _stream_handle(stream)),
+           "cc_amsf_csr_mapped")
     return labels, eu, ev, ew, ne, tw
 
 

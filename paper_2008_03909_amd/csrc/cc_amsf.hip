@@ -689,9 +689,11 @@ static cc_status check_amsf_options(const cc_amsf_options* opt) {
 }
 
 template <typename I>
+// orig_of (nullable): the CSR's vertices were renumbered; forest edges are
+// written in the original numbering.
 static cc_status amsf_run(StaticArgs& a, const AmsfLayout& L, const float* w, const cc_amsf_options* opt,
                           AmsfHostBlock* hb_host, int32_t* edges_u, int32_t* edges_v, float* edges_w,
-                          int64_t* num_edges, double* weight_dev) {
+                          int64_t* num_edges, double* weight_dev, const int32_t* orig_of) {
   char* ws = a.ws;
   float* thr = (float*)(ws + L.thr);
   AmsfHostBlock* hb = (AmsfHostBlock*)(ws + L.hostblk);
@@ -706,7 +708,10 @@ static cc_status amsf_run(StaticArgs& a, const AmsfLayout& L, const float* w, co
   const int aligned = (((uintptr_t)w | (uintptr_t)a.adj) & 15u) == 0;
   {
     PhaseScope ps(a.ctx, a.s, "init");
-    hipLaunchKernelGGL(k_amsf_iota, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n, a.P);
+    // every parent of the array gets a valid value, also beyond the swept
+    // vertices of a restricted call
+    const int64_t np = a.n_parents > n ? a.n_parents : n;
+    hipLaunchKernelGGL(k_amsf_iota, dim3(grid_for(np, kFBlock, 4096)), dim3(kFBlock), 0, a.s, np, a.P);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 * n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, (uint32_t*)a.hook_e,
                        2 * n, 0xffffffffu);
     CC_LAUNCH_CHECK();
@@ -719,7 +724,12 @@ static cc_status amsf_run(StaticArgs& a, const AmsfLayout& L, const float* w, co
     hipLaunchKernelGGL(k_amsf_setup, dim3(1), dim3(1024), 0, a.s, (const RangePart*)part, (int)gr,
                        (double)opt->epsilon, opt->light_fraction, sm_out(opt->seed, kTagAmsf), m, w, thr, as,
                        hb->shist);
-    hipLaunchKernelGGL(k_amsf_tile_rows<I>, dim3(grid_for(n, kFBlock, 4096)), dim3(kFBlock), 0, a.s, n,
+    // every row of the CSR, also beyond the swept vertices of a restricted
+    // call: then each tile's first row is right even if rows after the
+    // swept ones were not empty, and the pass reads only rows and offsets
+    // inside the arrays
+    const int64_t nt = a.n_parents > n ? a.n_parents : n;
+    hipLaunchKernelGGL(k_amsf_tile_rows<I>, dim3(grid_for(nt, kFBlock, 4096)), dim3(kFBlock), 0, a.s, nt,
                        (const I*)a.off, tile_row);
     hipLaunchKernelGGL((k_amsf_pass<I, false>), dim3(G), dim3(kAmsfThreads), 0, a.s, n, m, (const I*)a.off, a.adj,
                        w, (const float*)thr, (const AmsfScalars*)as, (const int32_t*)tile_row, L.ntiles, -1, lpart,
@@ -807,7 +817,7 @@ static cc_status amsf_run(StaticArgs& a, const AmsfLayout& L, const float* w, co
   cc_status st = output_labels(a);
   if (st != CC_OK) return st;
   st = forest_filter(a.s, n, nullptr, a.hook_e, hookw, (int32_t*)(ws + L.fcnt), edges_u, edges_v, edges_w,
-                     num_edges);
+                     num_edges, orig_of);
   if (st != CC_OK) return st;
   if (weight_dev) {  // edges_w is non-NULL (checked at entry)
     double* wpart = (double*)(ws + L.wpart);
@@ -867,9 +877,61 @@ cc_status cc_amsf_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* offsets, in
   a.hook_e = (int2*)((char*)workspace + L.hook);
   if (!ctx->amsf_host) CC_HIP(hipHostMalloc((void**)&ctx->amsf_host, sizeof(AmsfHostBlock), hipHostMallocDefault));
   st = offsets_are_64bit ? amsf_run<int64_t>(a, L, weights, opt, (AmsfHostBlock*)ctx->amsf_host, edges_u, edges_v,
-                                             edges_w, num_edges_dev, weight_dev)
+                                             edges_w, num_edges_dev, weight_dev, nullptr)
                          : amsf_run<int32_t>(a, L, weights, opt, (AmsfHostBlock*)ctx->amsf_host, edges_u, edges_v,
-                                             edges_w, num_edges_dev, weight_dev);
+                                             edges_w, num_edges_dev, weight_dev, nullptr);
+  cc_stats& s = ctx->last;
+  s.n = n;
+  s.m = m;
+  s.sample_rounds = a.sample_rounds;
+  s.finish_rounds = a.finish_rounds;
+  return st;
+}
+
+cc_status cc_amsf_mapped_workspace_bytes(int64_t n, int64_t m, const cc_amsf_options* opt, size_t* bytes) {
+  cc_status st = cc_amsf_workspace_bytes(n, m, opt, bytes);
+  if (st != CC_OK) return st;
+  *bytes += align256((size_t)n * 4);  // the labels in the CSR's numbering
+  return CC_OK;
+}
+
+cc_status cc_amsf_csr_mapped(cc_ctx* ctx, int64_t n, int64_t n_active, int64_t m, const void* offsets,
+                             int offsets_are_64bit, const int32_t* adj, const int32_t* orig_of, const int32_t* new_of,
+                             const float* weights, const cc_amsf_options* opt, void* workspace, size_t ws_bytes,
+                             int32_t* labels_out, int32_t* edges_u, int32_t* edges_v, float* edges_w,
+                             int64_t* num_edges_dev, double* weight_dev, void* hip_stream) {
+  cc_status st = check_amsf_options(opt);
+  if (st != CC_OK) return st;
+  if (!edges_u || !edges_v || !num_edges_dev || !labels_out) return fail(CC_EINVAL, "NULL output");
+  if (!orig_of || !new_of) return fail(CC_EINVAL, "NULL permutation argument");
+  if (n_active < 0 || n_active > n) return fail(CC_EINVAL, "n_active=%lld outside [0, n]", (long long)n_active);
+  if (m > 0 && !weights) return fail(CC_EINVAL, "weights are NULL");
+  if (weight_dev && !edges_w) return fail(CC_EINVAL, "weight_dev needs edges_w");
+  size_t need = 0;
+  st = cc_amsf_mapped_workspace_bytes(n, m, opt, &need);
+  if (st != CC_OK) return st;
+  if (!workspace || ws_bytes < need)
+    return fail(CC_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+  // the layout of the whole graph; the algorithm runs on the first na
+  // vertices (the others have empty rows: alone in their components, no
+  // forest edges), with the labels in the CSR's numbering after the layout
+  const AmsfLayout L = amsf_layout(n, m, opt->light_fraction);
+  const int64_t na = n_active > 0 ? n_active : 1;
+  int32_t* Pnew = (int32_t*)((char*)workspace + L.total);
+  const cc_variant v = amsf_variant();
+  StaticArgs a;
+  st = setup_args(a, ctx, na, m, offsets, offsets_are_64bit, adj, &v, workspace, L.hook, Pnew, nullptr, hip_stream);
+  if (st != CC_OK) return st;
+  a.n_parents = n;
+  a.map_orig = orig_of;
+  a.map_rmin = a.count;
+  a.hook_e = (int2*)((char*)workspace + L.hook);
+  if (!ctx->amsf_host) CC_HIP(hipHostMalloc((void**)&ctx->amsf_host, sizeof(AmsfHostBlock), hipHostMallocDefault));
+  st = offsets_are_64bit ? amsf_run<int64_t>(a, L, weights, opt, (AmsfHostBlock*)ctx->amsf_host, edges_u, edges_v,
+                                             edges_w, num_edges_dev, weight_dev, orig_of)
+                         : amsf_run<int32_t>(a, L, weights, opt, (AmsfHostBlock*)ctx->amsf_host, edges_u, edges_v,
+                                             edges_w, num_edges_dev, weight_dev, orig_of);
+  if (st == CC_OK) st = map_back_labels(a, n, orig_of, new_of, Pnew, labels_out);
   cc_stats& s = ctx->last;
   s.n = n;
   s.m = m;

@@ -47,29 +47,36 @@ def _check(ctx, d, w, opt, name, want=None, rows_adj=None):
     off, adj, rows = rows_adj if rows_adj is not None else _host_csr(d)
     dev = ctx.torch_device
     wt = torch.from_numpy(w).to(dev)
-    lab, eu, ev, ew, ne, tw = b.amsf_csr(ctx, d, wt, opt)
+    out = b.amsf_csr(ctx, d, wt, opt)
     torch.cuda.synchronize()
     ctx.sync_status()
+    _verify(d.n, d.m, off, adj, rows, w, opt, name, out, want)
+
+
+def _verify(n, m, off, adj, rows, w, opt, name, out, want=None):
+    """The oracle's checks of one result on the host CSR (off, adj, rows)
+    with entry weights w."""
+    lab, eu, ev, ew, ne, tw = out
     k = int(ne.item())
     fu, fv, fw = eu[:k].cpu().numpy(), ev[:k].cpu().numpy(), ew[:k].cpu().numpy()
     if want is None:
-        want = oracle.uf_cc(d.n, rows, adj)
+        want = oracle.uf_cc(n, rows, adj)
     wl, wc = want
     assert np.array_equal(lab.cpu().numpy(), wl), name
-    assert k == d.n - wc, (name, k, d.n - wc)
-    assert oracle.forest_check_csr(d.n, off, adj, wl, fu, fv) == oracle.FOREST_OK, name
+    assert k == n - wc, (name, k, n - wc)
+    assert oracle.forest_check_csr(n, off, adj, wl, fu, fv) == oracle.FOREST_OK, name
     # each returned weight is its edge's weight (entry weights are a function of the pair)
-    key = rows.astype(np.int64) * d.n + adj
+    key = rows.astype(np.int64) * n + adj
     order = np.argsort(key, kind="stable")
-    pos = np.searchsorted(key[order], fu.astype(np.int64) * d.n + fv)
+    pos = np.searchsorted(key[order], fu.astype(np.int64) * n + fv)
     assert np.array_equal(fw, w[order][pos]), name
-    if d.m == 0:
+    if m == 0:
         assert k == 0 and float(tw.item()) == 0.0
         return
-    t, cnt = oracle.amsf_buckets(d.n, rows, adj, w, opt.epsilon)
+    t, cnt = oracle.amsf_buckets(n, rows, adj, w, opt.epsilon)
     fb = np.searchsorted(t, fw, side="right") - 1
     assert np.array_equal(np.bincount(fb, minlength=len(cnt)), cnt), name
-    exact, ek = oracle.msf_weight(d.n, rows, adj, w.astype(np.float64))
+    exact, ek = oracle.msf_weight(n, rows, adj, w.astype(np.float64))
     assert ek == k
     total = float(tw.item())
     assert abs(total - float(np.sum(fw, dtype=np.float64))) <= 1e-9 * max(total, 1.0), name
@@ -171,3 +178,24 @@ def test_amsf_rejects_bad_input(ctx):
         b.amsf_csr(ctx, d, torch.from_numpy(x).to(dev), b.amsf_options(epsilon=0.01))
     # the context still works afterwards
     _check(ctx, d, w, b.amsf_options(), "after errors")
+
+
+@pytest.mark.parametrize("lf", [0.0, 0.5])
+def test_amsf_mapped_suite(ctx, lf):
+    """On the degree-ordered CSR, with each entry weighted as the same pair of
+    original vertices: edges, weights and labels come back in the original
+    numbering and pass the checks on the original CSR."""
+    opt = b.amsf_options(light_fraction=lf)
+    for i, g in enumerate(SUITE):
+        d0 = b.build_csr(ctx, g.n, g.u, g.v)
+        w0, ra = _weights_for(d0, seed=100 + i)
+        r = b.build_csr_degree_order(ctx, g.n, g.u, g.v)
+        off_r, adj_r, rows_r = _host_csr(r)
+        orig = r.orig_of.cpu().numpy()
+        wr = inputs.pair_weights(g.n, orig[rows_r], orig[adj_r], 100 + i, 1.0)
+        _note(f"{g} mapped lf={lf}")
+        out = b.amsf_csr_mapped(ctx, r, torch.from_numpy(wr).to(ctx.torch_device), opt)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        _verify(g.n, d0.m, ra[0], ra[1], ra[2], w0, opt, f"{g} mapped lf={lf}", out)
+
