@@ -703,8 +703,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "m": m, "nonisolated": n_nz, "variant": v.name(),
                    "num_components": st["num_components"], "parallelism": "single-gpu",
-                   "layout": ("CSR renumbered by decreasing degree at ingest; labels mapped back to the original "
-                              "numbering inside the timed call" if rcsr is not None else "CSR as built")},
+                   "layout": ("CSR renumbered by decreasing degree at ingest; the algorithm runs on the "
+                              f"{rcsr.n_active} vertices with edges (the isolated ones come last); labels of all "
+                              "vertices mapped back to the original numbering inside the timed call"
+                              if rcsr is not None else "CSR as built")},
         "hbm_gbs_alg": round(alg_total / (ms_step / 1e3) / 1e9, 1),
         "roofline": roofline,
         "phases": ph_out,
