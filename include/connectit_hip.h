@@ -219,9 +219,14 @@ cc_status cc_connectivity_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* off
  * smallest such value; pass n when unknown).  The algorithm then runs on
  * vertices [0, n_active) only, every other vertex being a component of its
  * own; all n labels and the count cover the whole graph.  A broken promise
- * (a non-empty row at or after n_active) sets the bad-CSR bit of the
- * context's error word, and its labels are then not defined; adjacency ids
- * below n stay safe to read.  orig_of and new_of must be inverse
+ * (a non-empty row at or after n_active) is a malformed CSR: the labels are
+ * then not defined and the bad-CSR bit of the context's error word is set.
+ * With k-out sampling and a union-find finish every access still stays
+ * inside the arrays (the parent array covers all n vertices); the BFS, LDD,
+ * SV, LT and label-propagation variants size their frontier and round
+ * arrays by n_active and trust the promise as the static calls trust their
+ * CSR (cc_validate_csr on the first n_active rows checks it: every id below
+ * n_active).  orig_of and new_of must be inverse
  * permutations of [0, n); they are not checked.  Workspace: device, >=
  * cc_mapped_workspace_bytes (cc_workspace_bytes plus 4n bytes for the
  * labels in the CSR's numbering). */
