@@ -222,7 +222,9 @@ cc_status cc_connectivity_csr(cc_ctx* ctx, int64_t n, int64_t m, const void* off
  * (a non-empty row at or after n_active) is a malformed CSR: the labels are
  * then not defined and the bad-CSR bit of the context's error word is set.
  * With k-out sampling and a union-find finish every access still stays
- * inside the arrays (the parent array covers all n vertices); the BFS, LDD,
+ * inside the workspace and the caller's arrays (the parent array covers all
+ * n vertices, and the arrays sized by n_active lie inside a workspace sized
+ * for n); the BFS, LDD,
  * SV, LT and label-propagation variants size their frontier and round
  * arrays by n_active and trust the promise as the static calls trust their
  * CSR (cc_validate_csr on the first n_active rows checks it: every id below
