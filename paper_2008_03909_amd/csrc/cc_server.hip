@@ -33,11 +33,12 @@
 // only tracks its requests still in flight (a completed request needs no
 // wait).
 //
-// Host side: zero copy -- request payloads are DMA'd straight from the
-// caller's buffers (which must stay valid until the request completes; pinned
-// memory makes the copies asynchronous) on a copy stream of their own that
-// no phase barrier holds up, and query answers land directly in the caller's
-// output buffer.  Device side: a first-fit pool of the budget.
+// Host side: the caller's buffers must stay valid until the request
+// completes.  When they are pinned host memory mapped into the device's
+// address space, the kernels read the pairs and write the answers in place
+// (no pool bytes, no copies).  Otherwise the pairs are DMA'd into the pool
+// on a copy stream of their own that no phase barrier holds up, and the
+// answers are copied back.  Device side: a first-fit pool of the budget.
 // Latency = completion (observed by polling the request's event) minus
 // arrival, on the host's steady clock.
 #include <algorithm>
