@@ -554,8 +554,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
-              f"DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the graph over several GPUs "
+              f"is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
