@@ -425,10 +425,12 @@ def calibration(ctx, csr, n: int, m: int, o: int):
     }
 
 
-def sweep(ctx, csr, g, workload_name: str, reps: int = 5, check: bool = True):
+def sweep(ctx, csr, g, workload_name: str, reps: int = 5, check: bool = True, rcsr=None):
     """Time every sampling x finish variant (median of `reps` after one warm-up)
     and check every labelling against the CPU oracle.  Extra rows vary the
-    k-out edge choice and k under the default finish."""
+    k-out edge choice and k under the default finish.  With rcsr (a
+    renumbered CSR of the same graph) the calls are the mapped ones, on the
+    layout the static call of the benchmark uses."""
     import numpy as np
     import torch
 
@@ -449,8 +451,14 @@ def sweep(ctx, csr, g, workload_name: str, reps: int = 5, check: bool = True):
     dev = ctx.torch_device
     labels = torch.empty(csr.n, dtype=torch.int32, device=dev)
     ncomp = torch.empty(1, dtype=torch.int64, device=dev)
+    def call(v):
+        if rcsr is not None:
+            b.connectivity_csr_mapped(ctx, rcsr, v, labels=labels, ncomp=ncomp)
+        else:
+            b.connectivity_csr(ctx, csr, v, labels=labels, ncomp=ncomp)
+
     for i, v in enumerate(vs + extra):
-        b.connectivity_csr(ctx, csr, v, labels=labels, ncomp=ncomp)
+        call(v)
         torch.cuda.synchronize()
         ok = True
         if want is not None:
@@ -459,7 +467,7 @@ def sweep(ctx, csr, g, workload_name: str, reps: int = 5, check: bool = True):
         for _ in range(reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            b.connectivity_csr(ctx, csr, v, labels=labels, ncomp=ncomp)
+            call(v)
             e1.record()
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1))
@@ -744,10 +752,9 @@ def main():
     if not args.no_amsf:
         out["amsf"] = amsf_leg(ctx, csr, n, m, ms_step, args.steps, rcsr=rcsr)
         out["amsf"]["layout"] = layout
-    del rcsr
     if args.sweep:
         log("variant sweep ...")
-        rows = sweep(ctx, csr, g, args.workload)
+        rows = sweep(ctx, csr, g, args.workload, rcsr=rcsr)
         with open(args.sweep, "w") as f:
             json.dump({"workload": desc, "n": n, "m": m, "rows": rows}, f, indent=1)
         best = min(rows[:80], key=lambda r: r["ms"])
@@ -755,7 +762,8 @@ def main():
         out["sweep"] = {"variants": len(rows), "all_match_oracle": all(r["labels_match_oracle"] for r in rows),
                         "best": best["variant"], "best_ms": best["ms"], "best_edges_per_s": best["edges_per_s"],
                         "best_any_row": best_all["variant"], "best_any_row_ms": best_all["ms"],
-                        "file": os.path.basename(args.sweep)}
+                        "file": os.path.basename(args.sweep), "layout": layout}
+    del rcsr
     out["calibration"] = calibration(ctx, csr, n, m, o)
     log(f"calibration: {out['calibration']}")
     if not args.no_incremental:
