@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(kBlock) k_compress_count(int64_t n, const I* _
     for (int j = 0; j < 4; ++j) {
       r[j] = p[j];
       if (act && v0 + j < n && p[j] != (int32_t)(v0 + j)) {
-        r[j] = find_naive(P, p[j]);
+        r[j] = find_sweep(P, p[j]);
         moved |= r[j] != p[j];
       }
     }

@@ -154,6 +154,20 @@ def test_mapped_connectivity_with_a_random_permutation(ctx):
         assert int(nc.item()) == wc and np.array_equal(lab.cpu().numpy(), want), g
 
 
+def test_long_id_ordered_path(ctx):
+    """A path of 2^20 vertices numbered along it: k-out links each vertex to
+    its predecessor, one tree as deep as the path; every sampler and the
+    compression after it still give one component labelled 0."""
+    g = inputs.path(1 << 20)
+    d = _csr(ctx, g)
+    base = b.default_variant()
+    for v in (base, base.copy(sample=b.SAMPLE_BFS), base.copy(sample=b.SAMPLE_LDD), base.copy(sample=b.SAMPLE_NONE)):
+        lab, nc = b.connectivity_csr(ctx, d, v)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        assert int(nc.item()) == 1, v.name()
+        assert int(lab.max().item()) == 0 and int(lab.min().item()) == 0, v.name()
+
 def test_csr_active_prefix(ctx):
     """The smallest x from which every row is empty, for CSRs as built and
     renumbered by degree (there it is the number of vertices with an entry:
