@@ -84,30 +84,6 @@ __device__ __forceinline__ int32_t find_naive(int32_t* P, int32_t u) {
   return u;
 }
 
-// Root of u in a forest that no union changes meanwhile (the compression
-// sweep after the sampling).  The walk is naive for
-// kSweepWalk steps, deeper than the trees of nearly every graph; past them
-// it halves: each further node is pointed at its grandparent with a CAS (an
-// ancestor either way, and a slot another lane has already changed is left
-// alone), so lanes walking one long path (an id-ordered path graph) shorten
-// it for each other instead of each walking all of it.
-constexpr int kSweepWalk = 64;
-__device__ __forceinline__ int32_t find_sweep(int32_t* P, int32_t u) {
-  int32_t p = ld(P + u);
-  for (int i = 0; i < kSweepWalk; ++i) {
-    if (p == u) return u;
-    u = p;
-    p = ld(P + u);
-  }
-  while (p != u) {
-    const int32_t g = ld(P + p);
-    if (g != p) cas(P + u, p, g);
-    u = g;
-    p = ld(P + u);
-  }
-  return u;
-}
-
 // FindAtomicSplit: point each visited node at its grandparent, then step to
 // the old parent.  FindAtomicHalve: same CAS, then step to the node's
 // (possibly new) parent.  Both re-read v and w every iteration.
